@@ -1,0 +1,208 @@
+/*
+ * pisco.h -- C ABI of the MI355X (gfx950) implementation of PISCO subspace
+ * sensitivity-map estimation (Lobos, Chan, Haldar: "New Theory and Faster
+ * Computations for Subspace-Based Sensitivity Map Estimation in Multichannel
+ * MRI", extended version).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - All array arguments except those marked "host" are DEVICE pointers owned
+ *    by the caller.  The library never allocates device memory inside a
+ *    call; scratch space comes from the caller's workspace, whose size is
+ *    given by pisco_workspace_size().  Workspace pointers must be 256-byte
+ *    aligned.
+ *  - Calls enqueue kernels on the handle's stream and return without
+ *    synchronising, except where stated.  Results are valid once the stream
+ *    has been synchronised.  No call issues hipMemsetAsync or host<->device
+ *    copies, so a sequence of calls can be captured into a HIP graph.
+ *  - Complex data are interleaved single-precision pairs (float2, re then im)
+ *    unless marked double2.
+ *  - Spatial arrays are stored [z][y][x] with x fastest.  For D = 2 the z
+ *    extent is 1.  Along a dimension of length L, index a corresponds to the
+ *    integer frequency k = a - floor(L/2) (k-space) and to the position
+ *    x = (a - floor(L/2)) / L (image space), i.e. the field of view is
+ *    [-1/2, 1/2)^D with unit k-space spacing (Sec. III-A, Eqs. 2-4).
+ *  - The kernel support Lambda = { n in Z^D : ||n||_2 <= radius } (Sec. IV-B)
+ *    is ordered lexicographically, z slowest and x fastest; |Lambda| is
+ *    returned by pisco_support().  n = Q |Lambda| is the Gram dimension and
+ *    filter vectors are indexed q |Lambda| + i (the column order of
+ *    C = [C_1 ... C_Q], Eq. 14).
+ *  - Return codes: PISCO_OK, or an error detected on the host before any
+ *    launch (bad argument, workspace too small, unsupported size) or reported
+ *    by the HIP runtime on launch.  Numerical conditions found on the device
+ *    (non-finite input, nullspace iteration not converged) are recorded in
+ *    the handle's device status word and read with pisco_get_status().
+ *    pisco_last_error() gives a message for the last failing call.
+ *  - No C++ exception or abort crosses this interface.
+ */
+#ifndef PISCO_H
+#define PISCO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  PISCO_OK = 0,
+  PISCO_ERR_ARG = 1,         /* invalid argument (null pointer, bad size) */
+  PISCO_ERR_WORKSPACE = 2,   /* workspace smaller than pisco_workspace_size */
+  PISCO_ERR_HIP = 3,         /* HIP runtime error (launch, device) */
+  PISCO_ERR_UNSUPPORTED = 4, /* size outside what the kernels support */
+  PISCO_ERR_NUMERIC = 5      /* numeric failure reported by the device */
+} pisco_status_t;
+
+/* Device status flags (bits of the word returned by pisco_get_status). */
+#define PISCO_FLAG_NONFINITE      0x1u  /* NaN/Inf met in an input or result */
+#define PISCO_FLAG_NOT_CONVERGED  0x2u  /* nullspace iteration hit its cap    */
+#define PISCO_FLAG_BLOCK_TOO_SMALL 0x4u /* signal rank reached the block size */
+#define PISCO_FLAG_ZERO_DATA      0x8u  /* all-zero calibration data          */
+
+typedef struct pisco_handle_s* pisco_handle_t;
+
+/* Problem description (Sec. III-A, IV-B, IV-D). */
+typedef struct {
+  int32_t D;            /* 2 or 3 */
+  int32_t Q;            /* number of channels, 2..32 */
+  int32_t acs[3];       /* calibration (ACS) extent z, y, x; acs[0] = 1 for D = 2 */
+  float radius;         /* kernel radius tau of the ellipsoidal support (Sec. IV-B) */
+  int32_t grid_lr[3];   /* low-resolution estimation grid z, y, x (Sec. IV-D) */
+  int32_t grid_out[3];  /* output grid z, y, x; each >= grid_lr */
+  float thresh;         /* nullspace rule sigma_n < thresh * sigma_1; 0.05 in the
+                           paper (Sec. III-B footnote) */
+} pisco_problem_t;
+
+/* Options of the per-voxel solve and the nullspace iteration. */
+typedef struct {
+  int32_t power_iters;  /* power-iteration steps (10 in the paper, Sec. IV-E);
+                           in tolerance mode the cap on steps */
+  float tol;            /* 0: fixed step count; > 0: stop a voxel once
+                           ||G c - lambda c||_2 <= tol * |Lambda| */
+  int32_t phase_rule;   /* 0: cancel the phase of the coil-combined apodized
+                           low-resolution image (Sec. IV-D); 1: reference to
+                           channel 0 (Sec. V) */
+  int32_t block;        /* nullspace block size (multiple of 32, 0 = automatic) */
+  int32_t max_subspace_iters; /* cap on nullspace iterations (0 = 60) */
+} pisco_opts_t;
+
+/* Stage identifiers for pisco_workspace_size. */
+#define PISCO_STAGE_GRAM      1
+#define PISCO_STAGE_NULLSPACE 2
+#define PISCO_STAGE_GX        3
+#define PISCO_STAGE_EIG       4
+#define PISCO_STAGE_MAPS      5
+#define PISCO_STAGE_ALL       0   /* pisco_estimate, intermediates included */
+
+/* Handle creation.  `stream` is a hipStream_t (NULL = default stream).  The
+ * handle owns only host state and one small device status word allocated
+ * here (the one allocation the library makes; freed by pisco_destroy).  A
+ * handle must not be used from two threads at once. */
+pisco_status_t pisco_create(pisco_handle_t* handle, void* stream);
+pisco_status_t pisco_destroy(pisco_handle_t handle);
+pisco_status_t pisco_set_stream(pisco_handle_t handle, void* stream);
+const char* pisco_status_string(pisco_status_t status);
+const char* pisco_last_error(pisco_handle_t handle);
+
+/* Synchronises the handle's stream, then returns the device status flags
+ * accumulated since the last call and clears them (host pointer `flags`). */
+pisco_status_t pisco_get_status(pisco_handle_t handle, uint32_t* flags);
+
+/* Kernel support (Sec. IV-B).  Host-only.  Writes |Lambda| to *count and,
+ * when `offsets` (host, int32[3 * count], z y x per point) is non-null, the
+ * offsets in the library's order.  Needs D in {2,3}, radius in [1, 12]. */
+pisco_status_t pisco_support(int32_t D, float radius, int32_t* count,
+                             int32_t* offsets);
+
+/* Bytes of workspace needed by one stage (or by pisco_estimate when stage is
+ * PISCO_STAGE_ALL).  `opts` may be NULL (defaults).  Host-only. */
+pisco_status_t pisco_workspace_size(const pisco_problem_t* prob,
+                                    const pisco_opts_t* opts, int32_t stage,
+                                    size_t* bytes);
+
+/* Calibration Gram C^H C by zero-padded FFT correlation (Sec. IV-A).
+ *   acs  : float2 [Q][acs z][acs y][acs x], the Nyquist-sampled ACS block
+ *   gram : float2 [n][n], n = Q |Lambda|, row-major; entry ((p,i),(q,j)) is
+ *          R_pq[n_i - n_j] with R_pq[d] = sum_k conj(s_p[k]) s_q[k+d]
+ *          (samples outside the ACS are zero: the unmasked form the paper
+ *          uses, equal to C^H C over every row the data touch).  Exactly
+ *          Hermitian (the lower triangle is written as the conjugate of the
+ *          upper). */
+pisco_status_t pisco_gram(pisco_handle_t handle, const pisco_problem_t* prob,
+                          const void* acs, void* gram, void* workspace,
+                          size_t workspace_bytes);
+
+/* Signal/null split of the Gram (Sec. III-A/B; threshold from the footnote
+ * of Sec. III-B).  FP64 block subspace iteration with Rayleigh-Ritz on the
+ * FP32 Gram widened exactly to FP64.  The filters h_r of the paper are the
+ * eigenvectors with lambda < thresh^2 lambda_1; their complement, the signal
+ * eigenvectors, is returned because the nullspace projector is
+ * I - V_s V_s^H (the route of Eq. 20).
+ *   gram    : float2 [n][n] from pisco_gram (only the Hermitian part is used)
+ *   eigvals : double [block], Ritz values, descending; the first counts[0]
+ *             are the signal eigenvalues lambda_k >= thresh^2 lambda_1
+ *   basis   : double2 [block][n], Ritz vectors, one contiguous vector per
+ *             row, orthonormal; the first counts[0] span the signal space
+ *   counts  : int32 [4] written on the device: {r_signal, block,
+ *             iterations used, 1 if converged else 0}
+ * `block` is opts->block or the automatic size (pisco_nullspace_block). */
+pisco_status_t pisco_nullspace(pisco_handle_t handle,
+                               const pisco_problem_t* prob,
+                               const pisco_opts_t* opts, const void* gram,
+                               double* eigvals, void* basis, int32_t* counts,
+                               void* workspace, size_t workspace_bytes);
+
+/* Block size pisco_nullspace uses for this problem (host-only). */
+pisco_status_t pisco_nullspace_block(const pisco_problem_t* prob,
+                                     const pisco_opts_t* opts, int32_t* block);
+
+/* Per-voxel G(x) = H(x)^H H(x) on the low-resolution grid (Sec. IV-C,
+ * Eqs. 23-26), from the lag sums of the nullspace filters' correlations.
+ *   basis, counts : outputs of pisco_nullspace (counts read on the device)
+ *   G : float2 [Q(Q+1)/2][N_lr], packed upper triangle, entry (p,q) with
+ *       p <= q at index p*Q - p*(p-1)/2 + (q - p); each entry is a
+ *       contiguous plane over the voxels of grid_lr. */
+pisco_status_t pisco_gx(pisco_handle_t handle, const pisco_problem_t* prob,
+                        const pisco_opts_t* opts, const void* basis,
+                        const int32_t* counts, void* G, void* workspace,
+                        size_t workspace_bytes);
+
+/* Per-voxel eigenvector of G(x) for its smallest eigenvalue by power
+ * iteration on |Lambda| I - G(x) (Sec. III-D step 4, Sec. IV-E).  The start
+ * vector is e_q with q the smallest diagonal entry of G(x) (lowest index on
+ * ties).
+ *   G        : float2 packed as produced by pisco_gx, N voxels
+ *   bound    : |Lambda| (the spectrum of G lies in [0, bound])
+ *   maps     : float2 [Q][N], unit-norm eigenvector per voxel
+ *   lam_min  : float [N], c^H G c (may be NULL)
+ *   iters    : int32 [N], steps taken (may be NULL) */
+pisco_status_t pisco_eig(pisco_handle_t handle, int32_t Q, int64_t N,
+                         float bound, const pisco_opts_t* opts, const void* G,
+                         void* maps, float* lam_min, int32_t* iters,
+                         void* workspace, size_t workspace_bytes);
+
+/* Phase reference, periodic sinc interpolation and sum-of-squares
+ * normalisation (Sec. IV-D, Sec. V).
+ *   acs      : float2 [Q][acs], used for the apodized low-resolution image
+ *   maps_lr  : float2 [Q][grid_lr] from pisco_eig
+ *   maps_out : float2 [Q][grid_out], unit root-sum-of-squares per voxel */
+pisco_status_t pisco_maps(pisco_handle_t handle, const pisco_problem_t* prob,
+                          const pisco_opts_t* opts, const void* acs,
+                          const void* maps_lr, void* maps_out, void* workspace,
+                          size_t workspace_bytes);
+
+/* The whole path: pisco_gram, pisco_nullspace, pisco_gx, pisco_eig and
+ * pisco_maps chained, intermediates in the workspace.
+ *   lam_min : float [N_lr] (may be NULL) */
+pisco_status_t pisco_estimate(pisco_handle_t handle,
+                              const pisco_problem_t* prob,
+                              const pisco_opts_t* opts, const void* acs,
+                              void* maps_out, float* lam_min, void* workspace,
+                              size_t workspace_bytes);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PISCO_H */

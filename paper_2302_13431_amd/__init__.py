@@ -1,0 +1,11 @@
+"""PISCO subspace sensitivity-map estimation on MI355X (gfx950).
+
+The computation lives in libpisco.so (HIP kernels behind the C ABI of
+include/pisco.h); this package is its Python binding plus a small pipeline
+helper that allocates device buffers with torch.
+"""
+from ._lib import (  # noqa: F401
+    Handle, Opts, PiscoError, Problem, lib, make_opts, make_problem, pisco_eig, pisco_estimate,
+    pisco_gram, pisco_gx, pisco_maps, pisco_nullspace, pisco_nullspace_block, pisco_support,
+    pisco_status_string, pisco_workspace_size)
+from .pipeline import Estimator  # noqa: F401

@@ -1,0 +1,222 @@
+"""ctypes binding of libpisco (the C ABI declared in include/pisco.h).
+
+Argument marshalling only: every computation runs in the HIP kernels of
+libpisco.so.  Functions keep the C names; device arrays are passed as torch
+tensors (their data pointers) and the stream is torch's current stream unless
+given.  There is no CPU fallback: if the library is missing the import of the
+functions raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpisco.so")
+
+PISCO_OK = 0
+STATUS_NAMES = {0: "ok", 1: "invalid argument", 2: "workspace too small", 3: "HIP error",
+                4: "unsupported", 5: "numeric failure"}
+
+FLAG_NONFINITE = 0x1
+FLAG_NOT_CONVERGED = 0x2
+FLAG_BLOCK_TOO_SMALL = 0x4
+FLAG_ZERO_DATA = 0x8
+
+STAGE_ALL, STAGE_GRAM, STAGE_NULLSPACE, STAGE_GX, STAGE_EIG, STAGE_MAPS = 0, 1, 2, 3, 4, 5
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [("D", ctypes.c_int32), ("Q", ctypes.c_int32), ("acs", ctypes.c_int32 * 3),
+                ("radius", ctypes.c_float), ("grid_lr", ctypes.c_int32 * 3),
+                ("grid_out", ctypes.c_int32 * 3), ("thresh", ctypes.c_float)]
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("power_iters", ctypes.c_int32), ("tol", ctypes.c_float),
+                ("phase_rule", ctypes.c_int32), ("block", ctypes.c_int32),
+                ("max_subspace_iters", ctypes.c_int32)]
+
+
+class PiscoError(RuntimeError):
+    def __init__(self, status: int, where: str, msg: str = ""):
+        super().__init__(f"{where}: {STATUS_NAMES.get(status, status)} {msg}".strip())
+        self.status = status
+
+
+_lib = None
+
+_P = ctypes.c_void_p
+_SIGS = {
+    "pisco_create": ([ctypes.POINTER(_P), _P], ctypes.c_int),
+    "pisco_destroy": ([_P], ctypes.c_int),
+    "pisco_set_stream": ([_P, _P], ctypes.c_int),
+    "pisco_status_string": ([ctypes.c_int], ctypes.c_char_p),
+    "pisco_last_error": ([_P], ctypes.c_char_p),
+    "pisco_get_status": ([_P, ctypes.POINTER(ctypes.c_uint32)], ctypes.c_int),
+    "pisco_support": ([ctypes.c_int32, ctypes.c_float, ctypes.POINTER(ctypes.c_int32), _P],
+                      ctypes.c_int),
+    "pisco_workspace_size": ([ctypes.POINTER(Problem), ctypes.POINTER(Opts), ctypes.c_int32,
+                              ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+    "pisco_nullspace_block": ([ctypes.POINTER(Problem), ctypes.POINTER(Opts),
+                               ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
+    "pisco_gram": ([_P, ctypes.POINTER(Problem), _P, _P, _P, ctypes.c_size_t], ctypes.c_int),
+    "pisco_nullspace": ([_P, ctypes.POINTER(Problem), ctypes.POINTER(Opts), _P, _P, _P, _P, _P,
+                         ctypes.c_size_t], ctypes.c_int),
+    "pisco_gx": ([_P, ctypes.POINTER(Problem), ctypes.POINTER(Opts), _P, _P, _P, _P,
+                  ctypes.c_size_t], ctypes.c_int),
+    "pisco_eig": ([_P, ctypes.c_int32, ctypes.c_int64, ctypes.c_float, ctypes.POINTER(Opts), _P,
+                   _P, _P, _P, _P, ctypes.c_size_t], ctypes.c_int),
+    "pisco_maps": ([_P, ctypes.POINTER(Problem), ctypes.POINTER(Opts), _P, _P, _P, _P,
+                    ctypes.c_size_t], ctypes.c_int),
+    "pisco_estimate": ([_P, ctypes.POINTER(Problem), ctypes.POINTER(Opts), _P, _P, _P, _P,
+                        ctypes.c_size_t], ctypes.c_int),
+}
+
+
+def lib():
+    """Load libpisco.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} not built; run python -m paper_2302_13431_amd.build")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (args, res) in _SIGS.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+    return _lib
+
+
+def make_problem(D: int, Q: int, acs: Sequence[int], radius: float, grid_lr: Sequence[int],
+                 grid_out: Sequence[int], thresh: float = 0.05) -> Problem:
+    """Problem with extents given slowest-first; 2D shapes get z = 1."""
+    def pad(v):
+        v = list(v)
+        return ([1] * (3 - len(v))) + v
+    p = Problem()
+    p.D, p.Q, p.radius, p.thresh = int(D), int(Q), float(radius), float(thresh)
+    for name, val in (("acs", acs), ("grid_lr", grid_lr), ("grid_out", grid_out)):
+        arr = getattr(p, name)
+        for i, x in enumerate(pad(val)):
+            arr[i] = int(x)
+    return p
+
+
+def make_opts(power_iters: int = 10, tol: float = 0.0, phase_rule: int = 0, block: int = 0,
+              max_subspace_iters: int = 60) -> Opts:
+    o = Opts()
+    o.power_iters, o.tol, o.phase_rule = int(power_iters), float(tol), int(phase_rule)
+    o.block, o.max_subspace_iters = int(block), int(max_subspace_iters)
+    return o
+
+
+def _check(st: int, where: str, handle=None):
+    if st != PISCO_OK:
+        msg = ""
+        if handle is not None:
+            m = lib().pisco_last_error(handle)
+            msg = m.decode() if m else ""
+        raise PiscoError(st, where, msg)
+
+
+def _ptr(t) -> Optional[int]:
+    if t is None:
+        return None
+    return ctypes.c_void_p(t.data_ptr())
+
+
+# ---------------------------------------------------------------- host-only calls
+
+
+def pisco_support(D: int, radius: float):
+    """Support offsets as a list of (z, y, x) tuples in the library's order."""
+    n = ctypes.c_int32()
+    _check(lib().pisco_support(D, radius, ctypes.byref(n), None), "pisco_support")
+    buf = (ctypes.c_int32 * (3 * n.value))()
+    _check(lib().pisco_support(D, radius, ctypes.byref(n), ctypes.cast(buf, _P)), "pisco_support")
+    return [tuple(buf[3 * i:3 * i + 3]) for i in range(n.value)]
+
+
+def pisco_workspace_size(prob: Problem, opts: Optional[Opts], stage: int) -> int:
+    out = ctypes.c_size_t()
+    _check(lib().pisco_workspace_size(ctypes.byref(prob), ctypes.byref(opts) if opts else None,
+                                      stage, ctypes.byref(out)), "pisco_workspace_size")
+    return out.value
+
+
+def pisco_nullspace_block(prob: Problem, opts: Optional[Opts]) -> int:
+    out = ctypes.c_int32()
+    _check(lib().pisco_nullspace_block(ctypes.byref(prob), ctypes.byref(opts) if opts else None,
+                                       ctypes.byref(out)), "pisco_nullspace_block")
+    return out.value
+
+
+def pisco_status_string(st: int) -> str:
+    return lib().pisco_status_string(st).decode()
+
+
+# ---------------------------------------------------------------- handle and device calls
+
+
+class Handle:
+    """Owns a pisco handle bound to a HIP stream (torch's current by default)."""
+
+    def __init__(self, stream=None):
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        self.h = _P()
+        _check(lib().pisco_create(ctypes.byref(self.h), _P(stream.cuda_stream)), "pisco_create")
+
+    def close(self):
+        if self.h:
+            lib().pisco_destroy(self.h)
+            self.h = _P()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def status(self) -> int:
+        f = ctypes.c_uint32()
+        _check(lib().pisco_get_status(self.h, ctypes.byref(f)), "pisco_get_status", self.h)
+        return f.value
+
+
+def pisco_gram(h: Handle, prob: Problem, acs, gram, ws):
+    _check(lib().pisco_gram(h.h, ctypes.byref(prob), _ptr(acs), _ptr(gram), _ptr(ws),
+                            ws.numel() * ws.element_size()), "pisco_gram", h.h)
+
+
+def pisco_nullspace(h: Handle, prob: Problem, opts: Opts, gram, eigvals, basis, counts, ws):
+    _check(lib().pisco_nullspace(h.h, ctypes.byref(prob), ctypes.byref(opts), _ptr(gram),
+                                 _ptr(eigvals), _ptr(basis), _ptr(counts), _ptr(ws),
+                                 ws.numel() * ws.element_size()), "pisco_nullspace", h.h)
+
+
+def pisco_gx(h: Handle, prob: Problem, opts: Opts, basis, counts, G, ws):
+    _check(lib().pisco_gx(h.h, ctypes.byref(prob), ctypes.byref(opts), _ptr(basis), _ptr(counts),
+                          _ptr(G), _ptr(ws), ws.numel() * ws.element_size()), "pisco_gx", h.h)
+
+
+def pisco_eig(h: Handle, Q: int, N: int, bound: float, opts: Opts, G, maps, lam=None, iters=None):
+    _check(lib().pisco_eig(h.h, Q, N, bound, ctypes.byref(opts), _ptr(G), _ptr(maps), _ptr(lam),
+                           _ptr(iters), None, 0), "pisco_eig", h.h)
+
+
+def pisco_maps(h: Handle, prob: Problem, opts: Opts, acs, maps_lr, maps_out, ws):
+    _check(lib().pisco_maps(h.h, ctypes.byref(prob), ctypes.byref(opts), _ptr(acs), _ptr(maps_lr),
+                            _ptr(maps_out), _ptr(ws), ws.numel() * ws.element_size()),
+           "pisco_maps", h.h)
+
+
+def pisco_estimate(h: Handle, prob: Problem, opts: Opts, acs, maps_out, lam, ws):
+    _check(lib().pisco_estimate(h.h, ctypes.byref(prob), ctypes.byref(opts), _ptr(acs),
+                                _ptr(maps_out), _ptr(lam), _ptr(ws),
+                                ws.numel() * ws.element_size()), "pisco_estimate", h.h)

@@ -1,0 +1,206 @@
+// Internal definitions shared by the HIP translation units of libpisco.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+
+#include "pisco.h"
+
+namespace pisco {
+
+// ------------------------------------------------------------------ complex
+
+__host__ __device__ inline float2 cmul(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__host__ __device__ inline float2 cmulc(float2 a, float2 b) {  // conj(a) * b
+  return make_float2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
+}
+__host__ __device__ inline float2 cadd(float2 a, float2 b) {
+  return make_float2(a.x + b.x, a.y + b.y);
+}
+__host__ __device__ inline float2 csub(float2 a, float2 b) {
+  return make_float2(a.x - b.x, a.y - b.y);
+}
+__host__ __device__ inline float2 cconj(float2 a) { return make_float2(a.x, -a.y); }
+__host__ __device__ inline float2 cscale(float2 a, float s) {
+  return make_float2(a.x * s, a.y * s);
+}
+__host__ __device__ inline float cabs2(float2 a) { return a.x * a.x + a.y * a.y; }
+
+__host__ __device__ inline double2 zmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__host__ __device__ inline double2 zmulc(double2 a, double2 b) {  // conj(a) * b
+  return make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
+}
+__host__ __device__ inline double2 zadd(double2 a, double2 b) {
+  return make_double2(a.x + b.x, a.y + b.y);
+}
+__host__ __device__ inline double2 zsub(double2 a, double2 b) {
+  return make_double2(a.x - b.x, a.y - b.y);
+}
+__host__ __device__ inline double2 zconj(double2 a) { return make_double2(a.x, -a.y); }
+__host__ __device__ inline double2 zscale(double2 a, double s) {
+  return make_double2(a.x * s, a.y * s);
+}
+__host__ __device__ inline double zabs2(double2 a) { return a.x * a.x + a.y * a.y; }
+
+// ------------------------------------------------------------------ handle
+
+struct Handle {
+  hipStream_t stream = nullptr;
+  uint32_t* status_dev = nullptr;   // device status word (PISCO_FLAG_*)
+  uint32_t* host_pinned = nullptr;  // pinned host mirror for status/flags
+  std::string last_error;
+};
+
+// ------------------------------------------------------------------ plan
+
+constexpr int kMaxQ = 32;
+constexpr int kMaxSupport = 4096;
+
+// Sizes derived from a problem description; everything a stage needs on the
+// host to size launches and to lay out its workspace.
+struct Plan {
+  int D = 2, Q = 0;
+  int acs[3] = {1, 1, 1};
+  int tau = 0;            // floor(radius): half-width of the support box
+  float radius = 0.f;
+  int L = 0;              // |Lambda|
+  int n = 0;              // Q |Lambda|
+  int P = 0;              // Q (Q + 1) / 2 channel pairs
+  int B[3] = {1, 1, 1};   // lag box extent per dim: 4 tau + 1 (1 for unused z)
+  int nlag = 0;           // B0 * B1 * B2
+  int F[3] = {1, 1, 1};   // FFT size per dim for the Gram correlation
+  int nF = 0;
+  int K[3] = {1, 1, 1};   // frequency grid of the filter correlations (= B)
+  int nK = 0;
+  int lr[3] = {1, 1, 1};
+  int out[3] = {1, 1, 1};
+  long long Nlr = 0, Nout = 0;
+  float thresh = 0.05f;
+};
+
+// Fills `plan` from `prob`; returns PISCO_OK or an argument error with a
+// message in `err`.
+pisco_status_t make_plan(const pisco_problem_t* prob, Plan* plan, std::string* err);
+
+// Enumerates the support in the library's order (host).
+int enumerate_support(int D, float radius, int32_t* offsets /* 3 per point */,
+                      int cap);
+
+// ------------------------------------------------------------------ workspace carving
+
+struct Carver {
+  char* base;
+  size_t used = 0;
+  explicit Carver(void* b) : base(static_cast<char*>(b)) {}
+  template <class T>
+  T* take(size_t count) {
+    size_t off = (used + 255) & ~size_t(255);
+    used = off + count * sizeof(T);
+    return reinterpret_cast<T*>(base ? base + off : nullptr);
+  }
+};
+
+// Workspace layouts; each `layout_*` fills pointers when `ws` is non-null and
+// returns the bytes used.
+struct GramWs {
+  int4* support;   // [L] (z, y, x, 0)
+  float2* S;       // [Q][F0][F1][F2] coil spectra (plus the stage buffers)
+  float2* T1;      // pair intermediates
+  float2* T2;
+  float2* R;       // [P][nlag] correlation lags
+};
+size_t layout_gram(const Plan& p, void* ws, GramWs* out);
+
+struct NullWs {
+  double2* X;      // [b][n] current orthonormal block (column-major n x b)
+  double2* Z;      // [b][n] A X
+  double2* H;      // [b][b] X^H Z
+  double2* S;      // [b][b] Z^H Z
+  double2* U;      // [b][b] Ritz vectors of H
+  double2* T;      // [b][b] scratch
+  double2* V;      // [b][b] scratch
+  double2* M;      // [b][b] combined update
+  double* theta;   // [b]
+  double* lam;     // [b]
+  double* resid;   // [b]
+  double2* part;   // split-K partials
+  int* ctl;        // [8] control words
+  double* jac;     // Jacobi scratch (global-memory fallback) [b*b*2]
+};
+size_t layout_null(const Plan& p, int b, void* ws, NullWs* out);
+
+struct GxWs {
+  int4* support;   // [L]
+  float2* Fh;      // [b][Q][nK] filter spectra
+  float2* Tmp;     // separable-transform scratch, two halves of tmp_half
+  size_t tmp_half;
+  float2* Kh;      // [P][nK] K^(f)
+  float2* Klag;    // [P][nlag]
+  float2* Mx;      // DFT matrices (3 dims, forward and lag)
+};
+size_t layout_gx(const Plan& p, int b, void* ws, GxWs* out);
+
+struct MapsWs {
+  float2* rho;     // [Q][Nlr] apodized low-res images
+  float2* tmpA;    // separable-transform scratch
+  float2* tmpB;
+  float2* cref;    // [Q][Nlr] phase-referenced maps
+  float2* Mx;      // transform matrices
+};
+size_t layout_maps(const Plan& p, void* ws, MapsWs* out);
+
+// ------------------------------------------------------------------ stage launchers
+
+pisco_status_t run_gram(Handle* h, const Plan& p, const float2* acs, float2* gram,
+                        void* ws);
+pisco_status_t run_nullspace(Handle* h, const Plan& p, int b, int max_iters,
+                             const float2* gram, double* eigvals, double2* basis,
+                             int32_t* counts, void* ws);
+pisco_status_t run_gx(Handle* h, const Plan& p, int b, const double2* basis,
+                      const int32_t* counts, float2* G, void* ws);
+pisco_status_t run_eig(Handle* h, int Q, long long N, float bound, int iters,
+                       float tol, const float2* G, float2* maps, float* lam,
+                       int32_t* it_out);
+pisco_status_t run_maps(Handle* h, const Plan& p, int phase_rule, const float2* acs,
+                        const float2* maps_lr, float2* maps_out, void* ws);
+
+// Separable transform along one axis of a batched 3D array:
+//   out[b][..o..] = sum_i M[o][i] * in[b][..i..]
+// shape_in = {batch, d0, d1, d2}; axis in {1,2,3}; M is [nout][nin] float2.
+pisco_status_t axis_transform(hipStream_t s, const float2* in, float2* out,
+                              const int shape_in[4], int axis, int nout,
+                              const float2* M);
+
+// Matrix builders (float2, row-major [nout][nin]) for axis_transform:
+//   build_dft : M[o][i] = scale * g(i) * exp(i sign 2 pi (i - ci)(o - co) / period),
+//               g(i) = exp(-(i - ci)^2 / (2 sigma^2)) if sigma > 0 else 1
+//   build_sinc: periodic sinc interpolation n_in -> n_out centred samples
+pisco_status_t build_dft(hipStream_t s, float2* M, int nout, int nin, int co, int ci,
+                         double period, double sign, double scale, double sigma);
+pisco_status_t build_sinc(hipStream_t s, float2* M, int nout, int nin);
+
+// Writes the support offsets (z, y, x, 0) into `out` on the device.
+pisco_status_t launch_support(hipStream_t s, int4* out, int D, float radius);
+
+inline pisco_status_t hip_check(Handle* h, hipError_t e, const char* what) {
+  if (e == hipSuccess) return PISCO_OK;
+  if (h) h->last_error = std::string(what) + ": " + hipGetErrorString(e);
+  return PISCO_ERR_HIP;
+}
+
+#define PISCO_LAUNCH_CHECK(h, what)                                   \
+  do {                                                                \
+    hipError_t e_ = hipGetLastError();                                \
+    if (e_ != hipSuccess) return ::pisco::hip_check((h), e_, (what)); \
+  } while (0)
+
+inline unsigned ceil_div(long long a, long long b) { return unsigned((a + b - 1) / b); }
+
+}  // namespace pisco

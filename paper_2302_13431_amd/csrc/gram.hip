@@ -1,0 +1,356 @@
+// Calibration Gram C^H C by zero-padded FFT correlation (Sec. IV-A).
+//
+// Column i of C_p^H C_q is a shift of the single correlation
+//   R_pq[d] = sum_k conj(s_p[k]) s_q[k + d]
+// so the whole Gram follows from Q forward FFTs of the zero-padded channels,
+// one cross-spectrum and one inverse FFT per channel pair, and a gather.  The
+// pad F >= A + 2 tau per dimension makes the circular correlation equal the
+// linear one at every lag |d| <= 2 tau that the gather needs.
+//
+// Only the Q(Q+1)/2 pairs p <= q are transformed; the lower blocks are the
+// conjugate transpose of the upper ones, which also makes the result exactly
+// Hermitian.  Transforms are separable passes of radix-2 Stockham FFTs held in
+// LDS; the forward passes skip the zero padding on input and the inverse passes
+// keep only the 4 tau + 1 lags per dimension on output.
+#include "common.hpp"
+
+namespace pisco {
+
+// In-LDS radix-2 Stockham FFT of LPB lines of length L, stored line-major in
+// `a` (scratch `b` of the same size).  Thread t handles butterfly `bt` of line
+// `ln`.  sign = -1: e^{-i 2 pi f k / L}; sign = +1: e^{+i ...} (unnormalised).
+// Every thread of the block must call this (it synchronises the block).
+__device__ float2* lds_fft(float2* a, float2* b, int L, int ln, int bt, bool active,
+                           float sign) {
+  const int half = L >> 1;
+  for (int ns = 1; ns < L; ns <<= 1) {
+    if (active) {
+      float2* x = a + ln * L;
+      float2* y = b + ln * L;
+      for (int j = bt; j < half; j += 128) {
+        const int k = j & (ns - 1);
+        float sn, cs;
+        sincospif(sign * float(k) / float(ns), &sn, &cs);
+        const float2 u = x[j];
+        const float2 v = cmul(x[j + half], make_float2(cs, sn));
+        const int o = ((j - k) << 1) + k;
+        y[o] = cadd(u, v);
+        y[o + ns] = csub(u, v);
+      }
+    }
+    __syncthreads();
+    float2* t = a;
+    a = b;
+    b = t;
+  }
+  return a;
+}
+
+// Maps FFT position j (0..F-1) of a zero-padded, centred sequence of A samples
+// to the array index a (k = a - floor(A/2), j = k mod F); -1 if padding.
+__device__ inline int pad_source(int j, int A, int F) {
+  const int h = A / 2;
+  int k = (j <= A - 1 - h) ? j : j - F;
+  if (k < -h || k > A - 1 - h) return -1;
+  return k + h;
+}
+
+// Lag kept at output slot m (0..B-1) of an inverse pass: d = m - (B-1)/2,
+// found at FFT position d mod F.
+__device__ inline int lag_position(int m, int B, int F) {
+  int d = m - (B - 1) / 2;
+  return d < 0 ? d + F : d;
+}
+
+__device__ inline void pair_decode(int pair, int Q, int* p, int* q) {
+  int base = 0;
+  for (int pp = 0; pp < Q; ++pp) {
+    const int cnt = Q - pp;
+    if (pair < base + cnt) {
+      *p = pp;
+      *q = pp + (pair - base);
+      return;
+    }
+    base += cnt;
+  }
+  *p = Q - 1;
+  *q = Q - 1;
+}
+
+struct PassGeom {
+  int L;        // FFT length
+  int nlines;
+  int lpb;      // lines per block
+  int thr;      // threads per line (= min(L/2, 128))
+};
+
+static PassGeom geom(int L, long long nlines) {
+  PassGeom g;
+  g.L = L;
+  g.thr = L / 2 < 128 ? (L / 2 > 0 ? L / 2 : 1) : 128;
+  g.lpb = 256 / g.thr;
+  g.nlines = int(nlines);
+  return g;
+}
+
+// Thread-to-(line, butterfly) mapping.  When the lines are contiguous in
+// memory (the x passes), consecutive threads walk along a line; otherwise
+// consecutive threads take consecutive lines so global accesses coalesce.
+template <bool kAlongLine>
+__device__ inline void map_thread(const PassGeom& g, int* ln, int* bt) {
+  const int t = threadIdx.x;
+  if (kAlongLine) {
+    *ln = t / g.thr;
+    *bt = t % g.thr;
+  } else {
+    *ln = t % g.lpb;
+    *bt = t / g.lpb;
+  }
+}
+
+__global__ void k_support(int4* out, int D, float radius) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const int t = int(floorf(radius));
+  const double r2 = double(radius) * double(radius);
+  const int zlo = (D == 3) ? -t : 0, zhi = (D == 3) ? t : 0;
+  int c = 0;
+  for (int z = zlo; z <= zhi; ++z)
+    for (int y = -t; y <= t; ++y)
+      for (int x = -t; x <= t; ++x)
+        if (double(z) * z + double(y) * y + double(x) * x <= r2)
+          out[c++] = make_int4(z, y, x, 0);
+}
+
+// ---------------------------------------------------------------- forward passes
+
+// x pass: lines (q, az, ay) of the ACS, zero-padded to F2 -> S1[q][az][ay][F2]
+__global__ void __launch_bounds__(256) k_fwd_x(const float2* __restrict__ acs,
+                                               float2* __restrict__ out, PassGeom g,
+                                               int A2, int F2, unsigned* status) {
+  __shared__ float2 sa[2 * 256 * 2];
+  float2* a = sa;
+  float2* b = sa + 2 * 256;
+  int ln, bt;
+  map_thread<true>(g, &ln, &bt);
+  const int line = blockIdx.x * g.lpb + ln;
+  const bool active = line < g.nlines && ln < g.lpb;
+  if (active) {
+    for (int j = bt; j < g.L; j += g.thr) {
+      const int src = pad_source(j, A2, F2);
+      float2 v = make_float2(0.f, 0.f);
+      if (src >= 0) {
+        v = acs[size_t(line) * A2 + src];
+        if (!isfinite(v.x) || !isfinite(v.y)) {
+          atomicOr(status, PISCO_FLAG_NONFINITE);
+          v = make_float2(0.f, 0.f);
+        }
+      }
+      a[ln * g.L + j] = v;
+    }
+  }
+  __syncthreads();
+  float2* r = lds_fft(a, b, g.L, ln, bt, active, -1.f);
+  if (active)
+    for (int j = bt; j < g.L; j += g.thr) out[size_t(line) * F2 + j] = r[ln * g.L + j];
+}
+
+// y or z pass over a [outer][A][inner] array: lines (outer, inner), the A
+// samples along the middle axis are zero-padded to F -> [outer][F][inner]
+__global__ void __launch_bounds__(256) k_fwd_mid(const float2* __restrict__ in,
+                                                 float2* __restrict__ out, PassGeom g,
+                                                 int A, int F, int inner) {
+  __shared__ float2 sa[2 * 256 * 2];
+  float2* a = sa;
+  float2* b = sa + 2 * 256;
+  int ln, bt;
+  map_thread<false>(g, &ln, &bt);
+  const int line = blockIdx.x * g.lpb + ln;
+  const bool active = line < g.nlines;
+  const int outer = active ? line / inner : 0, in_i = active ? line % inner : 0;
+  if (active) {
+    for (int j = bt; j < g.L; j += g.thr) {
+      const int src = pad_source(j, A, F);
+      a[ln * g.L + j] = src >= 0 ? in[(size_t(outer) * A + src) * inner + in_i]
+                                 : make_float2(0.f, 0.f);
+    }
+  }
+  __syncthreads();
+  float2* r = lds_fft(a, b, g.L, ln, bt, active, -1.f);
+  if (active)
+    for (int j = bt; j < g.L; j += g.thr)
+      out[(size_t(outer) * F + j) * inner + in_i] = r[ln * g.L + j];
+}
+
+// ---------------------------------------------------------------- inverse passes
+
+// First inverse pass along the slowest used axis (length F, extent of the
+// axis in S), with the cross-spectrum conj(S_p) S_q formed on load.
+//   S : [Q][Fa][inner];  out: [P][B][inner]; lines (pair, inner)
+__global__ void __launch_bounds__(256) k_inv_first(const float2* __restrict__ S,
+                                                   float2* __restrict__ out, PassGeom g,
+                                                   int Q, int F, int inner, int B) {
+  __shared__ float2 sa[2 * 256 * 2];
+  float2* a = sa;
+  float2* b = sa + 2 * 256;
+  int ln, bt;
+  map_thread<false>(g, &ln, &bt);
+  const int line = blockIdx.x * g.lpb + ln;
+  const bool active = line < g.nlines;
+  int pair = 0, in_i = 0, p = 0, q = 0;
+  if (active) {
+    pair = line / inner;
+    in_i = line % inner;
+    pair_decode(pair, Q, &p, &q);
+    const float2* Sp = S + size_t(p) * F * inner;
+    const float2* Sq = S + size_t(q) * F * inner;
+    for (int j = bt; j < g.L; j += g.thr) {
+      const size_t o = size_t(j) * inner + in_i;
+      a[ln * g.L + j] = cmulc(Sp[o], Sq[o]);
+    }
+  }
+  __syncthreads();
+  float2* r = lds_fft(a, b, g.L, ln, bt, active, +1.f);
+  if (active)
+    for (int m = bt; m < B; m += g.thr)
+      out[(size_t(pair) * B + m) * inner + in_i] = r[ln * g.L + lag_position(m, B, F)];
+}
+
+// Middle inverse pass: in [outer][F][inner] -> out [outer][B][inner]
+__global__ void __launch_bounds__(256) k_inv_mid(const float2* __restrict__ in,
+                                                 float2* __restrict__ out, PassGeom g,
+                                                 int F, int inner, int B) {
+  __shared__ float2 sa[2 * 256 * 2];
+  float2* a = sa;
+  float2* b = sa + 2 * 256;
+  int ln, bt;
+  map_thread<false>(g, &ln, &bt);
+  const int line = blockIdx.x * g.lpb + ln;
+  const bool active = line < g.nlines;
+  const int outer = active ? line / inner : 0, in_i = active ? line % inner : 0;
+  if (active)
+    for (int j = bt; j < g.L; j += g.thr)
+      a[ln * g.L + j] = in[(size_t(outer) * F + j) * inner + in_i];
+  __syncthreads();
+  float2* r = lds_fft(a, b, g.L, ln, bt, active, +1.f);
+  if (active)
+    for (int m = bt; m < B; m += g.thr)
+      out[(size_t(outer) * B + m) * inner + in_i] = r[ln * g.L + lag_position(m, B, F)];
+}
+
+// Last inverse pass along x (contiguous lines): in [lines][F] -> R [lines][B]
+// scaled by 1 / (F0 F1 F2).
+__global__ void __launch_bounds__(256) k_inv_x(const float2* __restrict__ in,
+                                               float2* __restrict__ out, PassGeom g, int F,
+                                               int B, float scale) {
+  __shared__ float2 sa[2 * 256 * 2];
+  float2* a = sa;
+  float2* b = sa + 2 * 256;
+  int ln, bt;
+  map_thread<true>(g, &ln, &bt);
+  const int line = blockIdx.x * g.lpb + ln;
+  const bool active = line < g.nlines && ln < g.lpb;
+  if (active)
+    for (int j = bt; j < g.L; j += g.thr) a[ln * g.L + j] = in[size_t(line) * F + j];
+  __syncthreads();
+  float2* r = lds_fft(a, b, g.L, ln, bt, active, +1.f);
+  if (active)
+    for (int m = bt; m < B; m += g.thr)
+      out[size_t(line) * B + m] = cscale(r[ln * g.L + lag_position(m, B, F)], scale);
+}
+
+// ---------------------------------------------------------------- gather
+
+// gram[(p,i),(q,j)] = R_pq[n_i - n_j] for row <= col; the lower triangle is
+// the conjugate of the upper one and the diagonal is real.
+__global__ void __launch_bounds__(256) k_gather(const float2* __restrict__ R,
+                                                const int4* __restrict__ sup,
+                                                float2* __restrict__ gram, int Q, int L,
+                                                int B0, int B1, int B2, int nlag) {
+  const int n = Q * L;
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  const int r = blockIdx.y;
+  if (c >= n) return;
+  const int lo = r <= c ? r : c, hi = r <= c ? c : r;
+  const int p = lo / L, i = lo - p * L, q = hi / L, j = hi - q * L;
+  const int4 ni = sup[i], nj = sup[j];
+  const int dz = ni.x - nj.x + (B0 - 1) / 2;
+  const int dy = ni.y - nj.y + (B1 - 1) / 2;
+  const int dx = ni.z - nj.z + (B2 - 1) / 2;
+  const int pair = p * Q - p * (p - 1) / 2 + (q - p);
+  float2 v = R[size_t(pair) * nlag + (dz * B1 + dy) * B2 + dx];
+  if (r > c) v = cconj(v);
+  if (r == c) v.y = 0.f;
+  gram[size_t(r) * n + c] = v;
+}
+
+pisco_status_t launch_support(hipStream_t s, int4* out, int D, float radius) {
+  hipLaunchKernelGGL(k_support, dim3(1), dim3(64), 0, s, out, D, radius);
+  return hipGetLastError() == hipSuccess ? PISCO_OK : PISCO_ERR_HIP;
+}
+
+static unsigned blocks_for(const PassGeom& g) { return ceil_div(g.nlines, g.lpb); }
+
+pisco_status_t run_gram(Handle* h, const Plan& p, const float2* acs, float2* gram,
+                        void* ws) {
+  GramWs w;
+  layout_gram(p, ws, &w);
+  hipStream_t s = h->stream;
+  const int Q = p.Q, P = p.P;
+  const int A0 = p.acs[0], A1 = p.acs[1], A2 = p.acs[2];
+  const int F0 = p.F[0], F1 = p.F[1], F2 = p.F[2];
+  const int B0 = p.B[0], B1 = p.B[1], B2 = p.B[2];
+
+  hipLaunchKernelGGL(k_support, dim3(1), dim3(64), 0, s, w.support, p.D, p.radius);
+  PISCO_LAUNCH_CHECK(h, "gram support");
+
+  // forward: x, y, (z)
+  float2* S1 = w.S;                                   // [Q][A0][A1][F2]
+  float2* S2 = w.S + size_t(Q) * F0 * F1 * F2;        // second half
+  PassGeom gx = geom(F2, 1LL * Q * A0 * A1);
+  hipLaunchKernelGGL(k_fwd_x, dim3(blocks_for(gx)), dim3(256), 0, s, acs, S1, gx, A2, F2,
+                     h->status_dev);
+  PISCO_LAUNCH_CHECK(h, "gram fwd x");
+  PassGeom gy = geom(F1, 1LL * Q * A0 * F2);
+  // 2D: S = S2 is [Q][1][F1][F2];  3D: S2 is [Q][A0][F1][F2]
+  hipLaunchKernelGGL(k_fwd_mid, dim3(blocks_for(gy)), dim3(256), 0, s, S1, S2, gy, A1, F1,
+                     F2);
+  PISCO_LAUNCH_CHECK(h, "gram fwd y");
+  const float2* Sfull = S2;
+  if (p.D == 3) {
+    PassGeom gz = geom(F0, 1LL * Q * F1 * F2);
+    hipLaunchKernelGGL(k_fwd_mid, dim3(blocks_for(gz)), dim3(256), 0, s, S2, S1, gz, A0,
+                       F0, F1 * F2);
+    PISCO_LAUNCH_CHECK(h, "gram fwd z");
+    Sfull = S1;  // [Q][F0][F1][F2]
+  }
+
+  // inverse per pair: (z), y, x
+  const float scale = 1.0f / float(p.nF);
+  if (p.D == 3) {
+    PassGeom iz = geom(F0, 1LL * P * F1 * F2);
+    hipLaunchKernelGGL(k_inv_first, dim3(blocks_for(iz)), dim3(256), 0, s, Sfull, w.T1, iz,
+                       Q, F0, F1 * F2, B0);
+    PISCO_LAUNCH_CHECK(h, "gram inv z");
+    PassGeom iy = geom(F1, 1LL * P * B0 * F2);
+    hipLaunchKernelGGL(k_inv_mid, dim3(blocks_for(iy)), dim3(256), 0, s, w.T1, w.T2, iy, F1,
+                       F2, B1);
+    PISCO_LAUNCH_CHECK(h, "gram inv y");
+  } else {
+    PassGeom iy = geom(F1, 1LL * P * F2);
+    hipLaunchKernelGGL(k_inv_first, dim3(blocks_for(iy)), dim3(256), 0, s, Sfull, w.T2, iy,
+                       Q, F1, F2, B1);
+    PISCO_LAUNCH_CHECK(h, "gram inv y");
+  }
+  PassGeom ix = geom(F2, 1LL * P * B0 * B1);
+  hipLaunchKernelGGL(k_inv_x, dim3(blocks_for(ix)), dim3(256), 0, s, w.T2, w.R, ix, F2, B2,
+                     scale);
+  PISCO_LAUNCH_CHECK(h, "gram inv x");
+
+  dim3 gg(ceil_div(p.n, 256), p.n);
+  hipLaunchKernelGGL(k_gather, gg, dim3(256), 0, s, w.R, w.support, gram, Q, p.L, B0, B1,
+                     B2, p.nlag);
+  PISCO_LAUNCH_CHECK(h, "gram gather");
+  return PISCO_OK;
+}
+
+}  // namespace pisco

@@ -1,0 +1,215 @@
+// Per-voxel G(x) on the low-resolution grid (Sec. IV-C, Eqs. 23-26).
+//
+// The paper forms W = sum_r h_r h_r^H over the null filters, sums its block
+// diagonals into the lag kernel K_pq[m] (Eq. 26) and evaluates
+// G_pq(x) = sum_m K_pq[m] e^{-i 2 pi m.x} with a zero-padded FFT.  Here the
+// same K is obtained from the signal vectors v_r (complement route, Eq. 20):
+//   K_pq = |Lambda| delta_pq delta[m] - K^s_pq,
+//   K^s_pq[m] = sum_r sum_s conj(v_r[n_s + m, p]) v_r[n_s, q],
+// and the correlation over s is done in the frequency domain, as the paper
+// does for C^H C (Sec. IV-A):
+//   1. filter spectra  F_r(f, q) = sum_{n in Lambda} v_r[n, q] e^{+i 2 pi n.f/Lk}
+//      on a grid of Lk = 4 tau + 1 points per dimension (separable passes);
+//   2. K^s_hat(f)_pq = sum_r conj(F_r(f, p)) F_r(f, q)   (contraction over r);
+//   3. K^s[m] = (1/Lk^D) sum_f K^s_hat(f) e^{+i 2 pi m.f/Lk}, |m_d| <= 2 tau;
+//   4. G^s(x) = sum_m K^s[m] e^{-i 2 pi m.x} on the low-res grid and
+//      G = |Lambda| I - G^s.
+// Lk = 4 tau + 1 is the smallest grid that holds every lag without aliasing.
+#include "common.hpp"
+
+namespace pisco {
+
+// dense map from support-box cell to support index (-1 outside Lambda)
+__global__ void k_box_map(const int4* __restrict__ sup, int L, int* __restrict__ map,
+                          int tz, int tau, int By, int Bx, int ncell) {
+  const int c = blockIdx.x * 256 + threadIdx.x;
+  if (c >= ncell) return;
+  const int bz = c / (By * Bx), rem = c - bz * By * Bx, by = rem / Bx, bx = rem - by * Bx;
+  int found = -1;
+  for (int i = 0; i < L; ++i) {
+    const int4 n = sup[i];
+    if (n.x + tz == bz && n.y + tau == by && n.z + tau == bx) {
+      found = i;
+      break;
+    }
+  }
+  map[c] = found;
+}
+
+// box[r][q][cell] = v_r[q|Lambda| + i(cell)] for r < r_s, else 0 (FP64 -> FP32)
+__global__ void k_scatter_box(const double2* __restrict__ basis,
+                              const int32_t* __restrict__ counts, const int* __restrict__ map,
+                              float2* __restrict__ box, int n, int L, int Q, int b,
+                              int ncell) {
+  const long long idx = blockIdx.x * 256LL + threadIdx.x;
+  if (idx >= 1LL * b * Q * ncell) return;
+  const int cell = int(idx % ncell);
+  const long long rq = idx / ncell;
+  const int q = int(rq % Q), r = int(rq / Q);
+  const int rs = counts[0];
+  const int i = map[cell];
+  float2 v = make_float2(0.f, 0.f);
+  if (i >= 0 && r < rs) {
+    const double2 d = basis[size_t(r) * n + size_t(q) * L + i];
+    v = make_float2(float(d.x), float(d.y));
+  }
+  box[idx] = v;
+}
+
+// Kh[pair(p,q)][f] = sum_{r < r_s} conj(F[r][p][f]) F[r][q][f]
+// Block: FT frequencies x Q channels; r staged through LDS in chunks of 8.
+__global__ void __launch_bounds__(256) k_herk(const float2* __restrict__ F,
+                                              const int32_t* __restrict__ counts,
+                                              float2* __restrict__ Kh, int Q, int nK, int FT) {
+  __shared__ float2 tile[8 * 256];
+  const int t = threadIdx.x;
+  const int fl = t % FT, q = t / FT;
+  const int f = blockIdx.x * FT + fl;
+  const bool active = q < Q && f < nK;
+  const int rs = counts[0];
+  float2 acc[kMaxQ];
+#pragma unroll
+  for (int p = 0; p < kMaxQ; ++p) acc[p] = make_float2(0.f, 0.f);
+  for (int r0 = 0; r0 < rs; r0 += 8) {
+    const int rc = rs - r0 < 8 ? rs - r0 : 8;
+    for (int e = t; e < rc * Q * FT; e += 256) {
+      const int rr = e / (Q * FT), rem = e - rr * Q * FT, qq = rem / FT, ff = rem - qq * FT;
+      const int gf = blockIdx.x * FT + ff;
+      tile[e] = gf < nK ? F[(size_t(r0 + rr) * Q + qq) * nK + gf] : make_float2(0.f, 0.f);
+    }
+    __syncthreads();
+    if (active) {
+      for (int rr = 0; rr < rc; ++rr) {
+        const float2* row = tile + rr * Q * FT;
+        const float2 x = row[q * FT + fl];
+#pragma unroll
+        for (int p = 0; p < kMaxQ; ++p)
+          if (p <= q) {
+            const float2 y = row[p * FT + fl];
+            acc[p].x = fmaf(y.x, x.x, fmaf(y.y, x.y, acc[p].x));
+            acc[p].y = fmaf(y.x, x.y, fmaf(-y.y, x.x, acc[p].y));
+          }
+      }
+    }
+    __syncthreads();
+  }
+  if (!active) return;
+#pragma unroll
+  for (int p = 0; p < kMaxQ; ++p)
+    if (p <= q) {
+      const int pair = p * Q - p * (p - 1) / 2 + (q - p);
+      Kh[size_t(pair) * nK + f] = acc[p];
+    }
+}
+
+// G = |Lambda| I - G^s on the packed planes; diagonal entries real.
+__global__ void k_gx_finish(float2* __restrict__ G, int Q, long long N, float bound) {
+  const long long idx = blockIdx.x * 256LL + threadIdx.x;
+  const int P = Q * (Q + 1) / 2;
+  if (idx >= 1LL * P * N) return;
+  const int pair = int(idx / N);
+  // pair is diagonal when it is the first entry of its row block
+  int p = 0, base = 0;
+  while (pair >= base + (Q - p)) {
+    base += Q - p;
+    ++p;
+  }
+  const bool diag = pair == base;
+  const float2 g = G[idx];
+  G[idx] = diag ? make_float2(bound - g.x, 0.f) : make_float2(-g.x, -g.y);
+}
+
+static pisco_status_t chain(hipStream_t s, const float2* in, float2* out, int shape[4],
+                            int axis, int nout, const float2* M) {
+  pisco_status_t st = axis_transform(s, in, out, shape, axis, nout, M);
+  shape[axis] = nout;
+  return st;
+}
+
+pisco_status_t run_gx(Handle* h, const Plan& p, int b, const double2* basis,
+                      const int32_t* counts, float2* G, void* ws) {
+  GxWs w;
+  layout_gx(p, b, ws, &w);
+  hipStream_t s = h->stream;
+  const int Q = p.Q, tau = p.tau, P = p.P;
+  const int box = 2 * tau + 1;
+  const int Bz = p.D == 3 ? box : 1, tz = p.D == 3 ? tau : 0;
+  const int ncell = Bz * box * box;
+  pisco_status_t st;
+  if ((st = launch_support(s, w.support, p.D, p.radius))) return st;
+
+  // transform matrices
+  float2* m = w.Mx;
+  float2* M1[3];
+  float2* M3[3];
+  float2* M4[3];
+  for (int d = 0; d < 3; ++d) {
+    const bool used = d > 0 || p.D == 3;
+    const int Lk = p.K[d], bd = used ? box : 1, Bd = p.B[d], lr = p.lr[d];
+    M1[d] = m;
+    m += size_t(Lk) * bd;
+    M3[d] = m;
+    m += size_t(Bd) * Lk;
+    M4[d] = m;
+    m += size_t(lr) * Bd;
+    if (!used) continue;
+    // filter spectra: e^{+i 2 pi n f / Lk}, n = box index - tau
+    if ((st = build_dft(s, M1[d], Lk, bd, 0, tau, Lk, +1.0, 1.0, 0.0))) return st;
+    // lags from spectra: (1/Lk) e^{+i 2 pi m f / Lk}, m = out index - 2 tau
+    if ((st = build_dft(s, M3[d], Bd, Lk, 2 * tau, 0, Lk, +1.0, 1.0 / Lk, 0.0))) return st;
+    // low-res evaluation: e^{-i 2 pi m x}, x = (a - floor(N/2)) / N
+    if ((st = build_dft(s, M4[d], lr, Bd, lr / 2, 2 * tau, lr, -1.0, 1.0, 0.0))) return st;
+  }
+
+  int* map = reinterpret_cast<int*>(w.Kh);  // Kh is free until step 2
+  hipLaunchKernelGGL(k_box_map, dim3(ceil_div(ncell, 256)), dim3(256), 0, s, w.support, p.L,
+                     map, tz, tau, box, box, ncell);
+  PISCO_LAUNCH_CHECK(h, "gx box map");
+  float2* bufA = w.Tmp;
+  float2* bufB = w.Tmp + w.tmp_half;
+  hipLaunchKernelGGL(k_scatter_box, dim3(ceil_div(1LL * b * Q * ncell, 256)), dim3(256), 0, s,
+                     basis, counts, map, bufA, p.n, p.L, Q, b, ncell);
+  PISCO_LAUNCH_CHECK(h, "gx scatter");
+
+  // 1. filter spectra: [bQ][Bz][box][box] -> [bQ][Kz][Ky][Kx] (ends in Fh)
+  int shp[4] = {b * Q, Bz, box, box};
+  if (p.D == 3) {
+    if ((st = chain(s, bufA, bufB, shp, 3, p.K[2], M1[2]))) return st;
+    if ((st = chain(s, bufB, bufA, shp, 2, p.K[1], M1[1]))) return st;
+    if ((st = chain(s, bufA, w.Fh, shp, 1, p.K[0], M1[0]))) return st;
+  } else {
+    if ((st = chain(s, bufA, bufB, shp, 3, p.K[2], M1[2]))) return st;
+    if ((st = chain(s, bufB, w.Fh, shp, 2, p.K[1], M1[1]))) return st;
+  }
+  // 2. contraction over the signal vectors
+  const int FT = 256 / Q;
+  hipLaunchKernelGGL(k_herk, dim3(ceil_div(p.nK, FT)), dim3(256), 0, s, w.Fh, counts, w.Kh, Q,
+                     p.nK, FT);
+  PISCO_LAUNCH_CHECK(h, "gx herk");
+  // 3. lags: [P][Kz][Ky][Kx] -> [P][Bz'][By][Bx]
+  int shk[4] = {P, p.K[0], p.K[1], p.K[2]};
+  if (p.D == 3) {
+    if ((st = chain(s, w.Kh, bufA, shk, 3, p.B[2], M3[2]))) return st;
+    if ((st = chain(s, bufA, bufB, shk, 2, p.B[1], M3[1]))) return st;
+    if ((st = chain(s, bufB, w.Klag, shk, 1, p.B[0], M3[0]))) return st;
+  } else {
+    if ((st = chain(s, w.Kh, bufA, shk, 3, p.B[2], M3[2]))) return st;
+    if ((st = chain(s, bufA, w.Klag, shk, 2, p.B[1], M3[1]))) return st;
+  }
+  // 4. evaluate on the low-res grid: [P][Bz][By][Bx] -> [P][lr0][lr1][lr2]
+  int shl[4] = {P, p.B[0], p.B[1], p.B[2]};
+  if (p.D == 3) {
+    if ((st = chain(s, w.Klag, bufA, shl, 3, p.lr[2], M4[2]))) return st;
+    if ((st = chain(s, bufA, bufB, shl, 2, p.lr[1], M4[1]))) return st;
+    if ((st = chain(s, bufB, G, shl, 1, p.lr[0], M4[0]))) return st;
+  } else {
+    if ((st = chain(s, w.Klag, bufA, shl, 3, p.lr[2], M4[2]))) return st;
+    if ((st = chain(s, bufA, G, shl, 2, p.lr[1], M4[1]))) return st;
+  }
+  hipLaunchKernelGGL(k_gx_finish, dim3(ceil_div(1LL * P * p.Nlr, 256)), dim3(256), 0, s, G, Q,
+                     p.Nlr, float(p.L));
+  PISCO_LAUNCH_CHECK(h, "gx finish");
+  return PISCO_OK;
+}
+
+}  // namespace pisco

@@ -1,0 +1,525 @@
+// Signal/null split of the calibration Gram in FP64 (Sec. III-A/B, Eq. 20).
+//
+// The paper takes the SVD of C and keeps as filters h_r the right singular
+// vectors with sigma_n < 0.05 sigma_1.  Because only a few percent of the
+// spectrum lies above that level for calibration data, the complement (the
+// signal eigenvectors, lambda_n >= 0.05^2 lambda_1 of C^H C) is computed
+// instead and the nullspace projector is I - V_s V_s^H, which is the ESPIRiT
+// form of Eq. (20).
+//
+// Method: block subspace iteration with Rayleigh-Ritz on a block of b >= r_s
+// columns, all in FP64 on the GPU.  Each iteration
+//   Z = A X                        (A = FP32 Gram widened exactly to FP64)
+//   H = X^H Z, eig(H) = U diag(theta) U^H     (one-sided Jacobi, PSD)
+//   W = X U (Ritz vectors), Y = Z U, residual_k = ||Y_k - theta_k W_k||
+//   X <- orth(Y) by SVQB: S = Y^H Y, D = diag(S)^-1/2, eig(D S D) = V L V^H,
+//        X = Y D V L^-1/2
+// stops when every Ritz pair up to the first one below the threshold has a
+// residual below 1e-10 theta_1.  The per-iteration rate is
+// lambda_{b+1} / lambda_{r_s}, small because the spectrum falls steeply past
+// the threshold.
+#include <cmath>
+
+#include "common.hpp"
+
+namespace pisco {
+
+// ------------------------------------------------------------------ init
+
+__device__ inline uint64_t mix64(uint64_t z) {
+  z += 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+__global__ void k_init_block(double2* X, int n, int b) {
+  const long long idx = blockIdx.x * 256LL + threadIdx.x;
+  if (idx >= 1LL * n * b) return;
+  const uint64_t h = mix64(uint64_t(idx) * 2654435761ull + 12345u);
+  const double re = double(h >> 11) * (1.0 / 9007199254740992.0) - 0.5;
+  const double im = double(mix64(h) >> 11) * (1.0 / 9007199254740992.0) - 0.5;
+  X[idx] = make_double2(re, im);
+}
+
+// ------------------------------------------------------------------ GEMMs
+
+// Z_part[ks] = A[:, kslice] X[kslice, :], A float2 row-major n x n (widened to
+// FP64), X and Z column-major n x b (double2).  32 x 32 output tile per block,
+// 2 x 2 complex micro-tile per thread, K in steps of 32 staged in LDS.
+__global__ void __launch_bounds__(256) k_gemm_ax(const float2* __restrict__ A,
+                                                 const double2* __restrict__ X,
+                                                 double2* __restrict__ Zp, int n, int b,
+                                                 int kchunk) {
+  __shared__ double2 As[32][33];
+  __shared__ double2 Xs[32][33];
+  const int t = threadIdx.x;
+  const int tr = t >> 4, tc = t & 15;
+  const int row0 = blockIdx.x * 32, col0 = blockIdx.y * 32;
+  const int kbeg = blockIdx.z * kchunk;
+  const int kend = min(n, kbeg + kchunk);
+  double2 acc[2][2];
+  for (int a = 0; a < 2; ++a)
+    for (int c = 0; c < 2; ++c) acc[a][c] = make_double2(0.0, 0.0);
+  for (int k0 = kbeg; k0 < kend; k0 += 32) {
+    for (int e = t; e < 1024; e += 256) {
+      const int rr = e >> 5, kk = e & 31;
+      const int gr = row0 + rr, gk = k0 + kk;
+      double2 v = make_double2(0.0, 0.0);
+      if (gr < n && gk < kend) {
+        const float2 f = A[size_t(gr) * n + gk];
+        v = make_double2(double(f.x), double(f.y));
+      }
+      As[rr][kk] = v;
+      const int cc = e >> 5;  // column of X
+      const int gc = col0 + cc;
+      double2 x = make_double2(0.0, 0.0);
+      if (gc < b && gk < kend) x = X[size_t(gc) * n + gk];
+      Xs[kk][cc] = x;
+    }
+    __syncthreads();
+#pragma unroll 8
+    for (int kk = 0; kk < 32; ++kk) {
+      const double2 a0 = As[tr * 2][kk], a1 = As[tr * 2 + 1][kk];
+      const double2 x0 = Xs[kk][tc * 2], x1 = Xs[kk][tc * 2 + 1];
+      acc[0][0] = zadd(acc[0][0], zmul(a0, x0));
+      acc[0][1] = zadd(acc[0][1], zmul(a0, x1));
+      acc[1][0] = zadd(acc[1][0], zmul(a1, x0));
+      acc[1][1] = zadd(acc[1][1], zmul(a1, x1));
+    }
+    __syncthreads();
+  }
+  double2* out = Zp + size_t(blockIdx.z) * n * b;
+  for (int a = 0; a < 2; ++a)
+    for (int c = 0; c < 2; ++c) {
+      const int gr = row0 + tr * 2 + a, gc = col0 + tc * 2 + c;
+      if (gr < n && gc < b) out[size_t(gc) * n + gr] = acc[a][c];
+    }
+}
+
+// out = sum over `parts` slabs of size `len` (fixed order: deterministic)
+__global__ void k_sum_parts(const double2* __restrict__ parts, double2* __restrict__ out,
+                            long long len, int nparts) {
+  const long long i = blockIdx.x * 256LL + threadIdx.x;
+  if (i >= len) return;
+  double2 s = parts[i];
+  for (int k = 1; k < nparts; ++k) s = zadd(s, parts[size_t(k) * len + i]);
+  out[i] = s;
+}
+
+// part[chunk] = P[rows of chunk, :]^H Q[rows of chunk, :]; P, Q column-major
+// n x b; part is column-major b x b.  Rows are split in chunks of 256.
+__global__ void __launch_bounds__(256) k_gemm_tn(const double2* __restrict__ P,
+                                                 const double2* __restrict__ Qm,
+                                                 double2* __restrict__ part, int n, int b) {
+  __shared__ double2 Ps[32][33];
+  __shared__ double2 Qs[32][33];
+  const int t = threadIdx.x;
+  const int ti = t >> 4, tj = t & 15;
+  const int i0 = blockIdx.x * 32, j0 = blockIdx.y * 32;
+  const int rbeg = blockIdx.z * 256, rend = min(n, rbeg + 256);
+  double2 acc[2][2];
+  for (int a = 0; a < 2; ++a)
+    for (int c = 0; c < 2; ++c) acc[a][c] = make_double2(0.0, 0.0);
+  for (int r0 = rbeg; r0 < rend; r0 += 32) {
+    for (int e = t; e < 1024; e += 256) {
+      const int cc = e >> 5, rr = e & 31;
+      const int gr = r0 + rr;
+      double2 pv = make_double2(0.0, 0.0), qv = make_double2(0.0, 0.0);
+      if (gr < rend) {
+        if (i0 + cc < b) pv = P[size_t(i0 + cc) * n + gr];
+        if (j0 + cc < b) qv = Qm[size_t(j0 + cc) * n + gr];
+      }
+      Ps[rr][cc] = pv;
+      Qs[rr][cc] = qv;
+    }
+    __syncthreads();
+#pragma unroll 8
+    for (int rr = 0; rr < 32; ++rr) {
+      const double2 p0 = Ps[rr][ti * 2], p1 = Ps[rr][ti * 2 + 1];
+      const double2 q0 = Qs[rr][tj * 2], q1 = Qs[rr][tj * 2 + 1];
+      acc[0][0] = zadd(acc[0][0], zmulc(p0, q0));
+      acc[0][1] = zadd(acc[0][1], zmulc(p0, q1));
+      acc[1][0] = zadd(acc[1][0], zmulc(p1, q0));
+      acc[1][1] = zadd(acc[1][1], zmulc(p1, q1));
+    }
+    __syncthreads();
+  }
+  double2* out = part + size_t(blockIdx.z) * b * b;
+  for (int a = 0; a < 2; ++a)
+    for (int c = 0; c < 2; ++c) {
+      const int gi = i0 + ti * 2 + a, gj = j0 + tj * 2 + c;
+      if (gi < b && gj < b) out[size_t(gj) * b + gi] = acc[a][c];
+    }
+}
+
+// Y = P M; P column-major m x k, M column-major k x b, Y column-major m x b.
+__global__ void __launch_bounds__(256) k_gemm_nn(const double2* __restrict__ Pm,
+                                                 const double2* __restrict__ M,
+                                                 double2* __restrict__ Y, int m, int k,
+                                                 int b) {
+  __shared__ double2 Ps[32][33];
+  __shared__ double2 Ms[32][33];
+  const int t = threadIdx.x;
+  const int tr = t >> 4, tc = t & 15;
+  const int r0 = blockIdx.x * 32, c0 = blockIdx.y * 32;
+  double2 acc[2][2];
+  for (int a = 0; a < 2; ++a)
+    for (int c = 0; c < 2; ++c) acc[a][c] = make_double2(0.0, 0.0);
+  for (int k0 = 0; k0 < k; k0 += 32) {
+    for (int e = t; e < 1024; e += 256) {
+      const int cc = e >> 5, rr = e & 31;
+      double2 pv = make_double2(0.0, 0.0), mv = make_double2(0.0, 0.0);
+      if (r0 + rr < m && k0 + cc < k) pv = Pm[size_t(k0 + cc) * m + r0 + rr];
+      if (k0 + rr < k && c0 + cc < b) mv = M[size_t(c0 + cc) * k + k0 + rr];
+      Ps[rr][cc] = pv;   // [row][kk]
+      Ms[rr][cc] = mv;   // [kk][col]
+    }
+    __syncthreads();
+#pragma unroll 8
+    for (int kk = 0; kk < 32; ++kk) {
+      const double2 p0 = Ps[tr * 2][kk], p1 = Ps[tr * 2 + 1][kk];
+      const double2 m0 = Ms[kk][tc * 2], m1 = Ms[kk][tc * 2 + 1];
+      acc[0][0] = zadd(acc[0][0], zmul(p0, m0));
+      acc[0][1] = zadd(acc[0][1], zmul(p0, m1));
+      acc[1][0] = zadd(acc[1][0], zmul(p1, m0));
+      acc[1][1] = zadd(acc[1][1], zmul(p1, m1));
+    }
+    __syncthreads();
+  }
+  for (int a = 0; a < 2; ++a)
+    for (int c = 0; c < 2; ++c) {
+      const int gr = r0 + tr * 2 + a, gc = c0 + tc * 2 + c;
+      if (gr < m && gc < b) Y[size_t(gc) * m + gr] = acc[a][c];
+    }
+}
+
+// ------------------------------------------------------------------ Jacobi
+
+// One-sided (Hestenes) Jacobi on a Hermitian positive semidefinite b x b
+// matrix A (column-major).  Column pairs are rotated until all columns are
+// orthogonal: A V = U diag(s); for PSD A the s_k are its eigenvalues and the
+// normalised columns u_k its eigenvectors.  Output sorted by decreasing
+// eigenvalue.  One block of up to 1024 threads; the working copy lives in LDS
+// when kLds (b <= 96) and in `gwork` otherwise.  Pairs follow the round-robin
+// tournament ordering, so the b/2 rotations of a round touch disjoint columns.
+constexpr int kJacLdsMax = 96;
+
+template <bool kLds>
+__global__ void __launch_bounds__(1024) k_jacobi(const double2* __restrict__ Ain, int b,
+                                                 double2* __restrict__ vec_out,
+                                                 double* __restrict__ val_out,
+                                                 double2* __restrict__ gwork,
+                                                 int max_sweeps) {
+  __shared__ double2 lds_mat[kLds ? kJacLdsMax * kJacLdsMax : 1];
+  __shared__ double norms[1024];
+  __shared__ int rotated;
+  double2* M = kLds ? lds_mat : gwork;
+  const int t = threadIdx.x, nt = blockDim.x;
+  const int bb = b * b;
+  for (int e = t; e < bb; e += nt) M[e] = Ain[e];
+  __syncthreads();
+  const int npairs = b / 2;
+  int G = 64;
+  while (G > 1 && G * npairs > nt) G >>= 1;
+  const int pair = t / G, lane = t % G;
+  const bool active = pair < npairs;
+  const double tol = 1e-14;
+  for (int sweep = 0; sweep < max_sweeps; ++sweep) {
+    if (t == 0) rotated = 0;
+    __syncthreads();
+    for (int round = 0; round < b - 1; ++round) {
+      if (active) {
+        // tournament positions (pair, b-1-pair); position 0 is fixed
+        auto col_at = [&](int pos) { return pos == 0 ? 0 : ((pos - 1 + round) % (b - 1)) + 1; };
+        const int ci = col_at(pair), cj = col_at(b - 1 - pair);
+        const int i = ci < cj ? ci : cj, j = ci < cj ? cj : ci;
+        double2* hi = M + size_t(i) * b;
+        double2* hj = M + size_t(j) * b;
+        double al = 0.0, be = 0.0, gr = 0.0, gim = 0.0;
+        for (int r = lane; r < b; r += G) {
+          const double2 x = hi[r], y = hj[r];
+          al += zabs2(x);
+          be += zabs2(y);
+          gr += x.x * y.x + x.y * y.y;
+          gim += x.x * y.y - x.y * y.x;
+        }
+        for (int off = G >> 1; off > 0; off >>= 1) {
+          al += __shfl_xor(al, off, G);
+          be += __shfl_xor(be, off, G);
+          gr += __shfl_xor(gr, off, G);
+          gim += __shfl_xor(gim, off, G);
+        }
+        const double gabs = sqrt(gr * gr + gim * gim);
+        if (gabs > tol * sqrt(al * be) && gabs > 0.0) {
+          const double zeta = (be - al) / (2.0 * gabs);
+          const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+          const double c = 1.0 / sqrt(1.0 + tt * tt);
+          const double s = tt * c;
+          const double er = gr / gabs, ei = gim / gabs;  // e^{i phi}
+          for (int r = lane; r < b; r += G) {
+            const double2 x = hi[r], y = hj[r];
+            // x' = c x - s e^{-i phi} y ;  y' = s e^{i phi} x + c y
+            const double2 emy = make_double2(er * y.x + ei * y.y, er * y.y - ei * y.x);
+            const double2 epx = make_double2(er * x.x - ei * x.y, er * x.y + ei * x.x);
+            hi[r] = make_double2(c * x.x - s * emy.x, c * x.y - s * emy.y);
+            hj[r] = make_double2(s * epx.x + c * y.x, s * epx.y + c * y.y);
+          }
+          if (lane == 0) rotated = 1;
+        }
+      }
+      __syncthreads();
+    }
+    const int any = rotated;
+    __syncthreads();
+    if (!any) break;
+  }
+  // eigenvalues = column norms; rank-sort descending (ties: lower index first)
+  for (int k = t; k < b; k += nt) {
+    double s = 0.0;
+    for (int r = 0; r < b; ++r) s += zabs2(M[size_t(k) * b + r]);
+    norms[k] = sqrt(s);
+  }
+  __syncthreads();
+  for (int k = t; k < b; k += nt) {
+    const double sk = norms[k];
+    int rank = 0;
+    for (int l = 0; l < b; ++l) {
+      const double sl = norms[l];
+      rank += (sl > sk) || (sl == sk && l < k);
+    }
+    val_out[rank] = sk;
+    const double inv = sk > 0.0 ? 1.0 / sk : 0.0;
+    for (int r = 0; r < b; ++r) {
+      double2 v = zscale(M[size_t(k) * b + r], inv);
+      if (sk == 0.0) v = make_double2(r == k ? 1.0 : 0.0, 0.0);
+      vec_out[size_t(rank) * b + r] = v;
+    }
+  }
+}
+
+// ------------------------------------------------------------------ small kernels
+
+// T = D S D with D = diag(S)^{-1/2}; d stored in dvec.
+__global__ void k_svqb_scale(const double2* __restrict__ S, double2* __restrict__ T,
+                             double* __restrict__ dvec, int b) {
+  const int idx = blockIdx.x * 256 + threadIdx.x;
+  if (idx >= b * b) return;
+  const int i = idx % b, j = idx / b;
+  const double si = S[size_t(i) * b + i].x, sj = S[size_t(j) * b + j].x;
+  const double di = si > 0.0 ? 1.0 / sqrt(si) : 0.0, dj = sj > 0.0 ? 1.0 / sqrt(sj) : 0.0;
+  T[idx] = zscale(S[idx], di * dj);
+  if (j == 0) dvec[i] = di;
+}
+
+// M[i][k] = d_i V[i][k] / sqrt(l_k)   (column-major)
+__global__ void k_svqb_build(const double2* __restrict__ V, const double* __restrict__ l,
+                             const double* __restrict__ dvec, double2* __restrict__ M,
+                             int b) {
+  const int idx = blockIdx.x * 256 + threadIdx.x;
+  if (idx >= b * b) return;
+  const int i = idx % b, k = idx / b;
+  const double lk = l[k] > 1e-300 ? l[k] : 1e-300;
+  M[idx] = zscale(V[idx], dvec[i] / sqrt(lk));
+}
+
+// part[chunk][k] = sum over rows of chunk of |Y_k - theta_k W_k|^2
+__global__ void __launch_bounds__(256) k_colresid(const double2* __restrict__ Y,
+                                                  const double2* __restrict__ W,
+                                                  const double* __restrict__ theta,
+                                                  double* __restrict__ part, int n, int b) {
+  __shared__ double red[256];
+  const int k = blockIdx.y;
+  const int rbeg = blockIdx.x * 1024;
+  const double th = theta[k];
+  double s = 0.0;
+  for (int r = rbeg + threadIdx.x; r < min(n, rbeg + 1024); r += 256) {
+    const double2 y = Y[size_t(k) * n + r], w = W[size_t(k) * n + r];
+    s += zabs2(make_double2(y.x - th * w.x, y.y - th * w.y));
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[size_t(blockIdx.x) * b + k] = red[0];
+}
+
+// Control: count signal Ritz values, test convergence.
+//   ctl[0] = r_signal, ctl[1] = converged, ctl[2] = iterations,
+//   ctl[3] = block too small, ctl[4] = all-zero data
+__global__ void k_control(const double* __restrict__ theta, const double* __restrict__ rpart,
+                          int nchunks, int b, double thr2, double tol, int margin, int iter,
+                          int* ctl, unsigned* status) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const double t0 = theta[0];
+  int rs = 0;
+  for (int k = 0; k < b; ++k) rs += theta[k] >= thr2 * t0;
+  const int upto = rs + 1 < b ? rs + 1 : b;
+  double worst = 0.0;
+  bool finite = isfinite(t0);
+  for (int k = 0; k < upto; ++k) {
+    double s = 0.0;
+    for (int c = 0; c < nchunks; ++c) s += rpart[size_t(c) * b + k];
+    const double r = sqrt(s);
+    if (!isfinite(r)) finite = false;
+    worst = r > worst ? r : worst;
+  }
+  const int too_small = rs > b - margin;
+  const int zero = !(t0 > 0.0);
+  ctl[0] = rs;
+  ctl[1] = (finite && !zero && worst <= tol * t0 && !too_small) ? 1 : 0;
+  ctl[2] = iter + 1;
+  ctl[3] = too_small;
+  ctl[4] = zero;
+  if (!finite) atomicOr(status, PISCO_FLAG_NONFINITE);
+}
+
+__global__ void k_finalize(const double2* __restrict__ W, const double* __restrict__ theta,
+                           const int* __restrict__ ctl, double2* __restrict__ basis,
+                           double* __restrict__ eigvals, int32_t* __restrict__ counts,
+                           long long nb, int b, unsigned* status) {
+  const long long i = blockIdx.x * 256LL + threadIdx.x;
+  if (i < nb) basis[i] = W[i];
+  if (i < b) eigvals[i] = theta[i];
+  if (i == 0) {
+    counts[0] = ctl[0];
+    counts[1] = b;
+    counts[2] = ctl[2];
+    counts[3] = ctl[1];
+    unsigned f = 0;
+    if (!ctl[1]) f |= PISCO_FLAG_NOT_CONVERGED;
+    if (ctl[3]) f |= PISCO_FLAG_BLOCK_TOO_SMALL;
+    if (ctl[4]) f |= PISCO_FLAG_ZERO_DATA;
+    if (f) atomicOr(status, f);
+  }
+}
+
+// ------------------------------------------------------------------ driver
+
+namespace {
+
+struct NullCtx {
+  Handle* h;
+  const Plan* p;
+  int b;
+  NullWs w;
+};
+
+pisco_status_t gemm_tn(NullCtx& c, const double2* P, const double2* Qm, double2* out, int rows) {
+  const int b = c.b;
+  const int chunks = int(ceil_div(rows, 256));
+  dim3 g(ceil_div(b, 32), ceil_div(b, 32), chunks);
+  hipLaunchKernelGGL(k_gemm_tn, g, dim3(256), 0, c.h->stream, P, Qm, c.w.part, rows, b);
+  PISCO_LAUNCH_CHECK(c.h, "nullspace gemm_tn");
+  const long long len = 1LL * b * b;
+  hipLaunchKernelGGL(k_sum_parts, dim3(ceil_div(len, 256)), dim3(256), 0, c.h->stream,
+                     c.w.part, out, len, chunks);
+  PISCO_LAUNCH_CHECK(c.h, "nullspace reduce");
+  return PISCO_OK;
+}
+
+pisco_status_t gemm_nn(NullCtx& c, const double2* P, const double2* M, double2* Y, int m,
+                       int k) {
+  dim3 g(ceil_div(m, 32), ceil_div(c.b, 32));
+  hipLaunchKernelGGL(k_gemm_nn, g, dim3(256), 0, c.h->stream, P, M, Y, m, k, c.b);
+  PISCO_LAUNCH_CHECK(c.h, "nullspace gemm_nn");
+  return PISCO_OK;
+}
+
+pisco_status_t jacobi(NullCtx& c, const double2* A, double2* vecs, double* vals) {
+  const int b = c.b;
+  if (b <= kJacLdsMax)
+    hipLaunchKernelGGL(k_jacobi<true>, dim3(1), dim3(1024), 0, c.h->stream, A, b, vecs, vals,
+                       c.w.jac ? reinterpret_cast<double2*>(c.w.jac) : nullptr, 40);
+  else
+    hipLaunchKernelGGL(k_jacobi<false>, dim3(1), dim3(1024), 0, c.h->stream, A, b, vecs, vals,
+                       reinterpret_cast<double2*>(c.w.jac), 40);
+  PISCO_LAUNCH_CHECK(c.h, "nullspace jacobi");
+  return PISCO_OK;
+}
+
+// X <- orth(Y) by SVQB (Y, X column-major n x b)
+pisco_status_t svqb(NullCtx& c, const double2* Y, double2* X) {
+  const int b = c.b, n = c.p->n;
+  pisco_status_t st = gemm_tn(c, Y, Y, c.w.S, n);
+  if (st) return st;
+  double* dvec = c.w.resid;  // reused as scratch
+  hipLaunchKernelGGL(k_svqb_scale, dim3(ceil_div(b * b, 256)), dim3(256), 0, c.h->stream,
+                     c.w.S, c.w.T, dvec, b);
+  PISCO_LAUNCH_CHECK(c.h, "nullspace svqb scale");
+  if ((st = jacobi(c, c.w.T, c.w.V, c.w.lam))) return st;
+  hipLaunchKernelGGL(k_svqb_build, dim3(ceil_div(b * b, 256)), dim3(256), 0, c.h->stream,
+                     c.w.V, c.w.lam, dvec, c.w.M, b);
+  PISCO_LAUNCH_CHECK(c.h, "nullspace svqb build");
+  return gemm_nn(c, Y, c.w.M, X, n, b);
+}
+
+}  // namespace
+
+pisco_status_t run_nullspace(Handle* h, const Plan& p, int b, int max_iters,
+                             const float2* gram, double* eigvals, double2* basis,
+                             int32_t* counts, void* ws) {
+  NullCtx c{h, &p, b, {}};
+  layout_null(p, b, ws, &c.w);
+  hipStream_t s = h->stream;
+  const int n = p.n;
+  const long long nb = 1LL * n * b;
+
+  hipLaunchKernelGGL(k_init_block, dim3(ceil_div(nb, 256)), dim3(256), 0, s, c.w.Z, n, b);
+  PISCO_LAUNCH_CHECK(h, "nullspace init");
+  pisco_status_t st = svqb(c, c.w.Z, c.w.X);
+  if (st) return st;
+
+  const double thr2 = double(p.thresh) * double(p.thresh);
+  const int margin = b / 8 > 4 ? b / 8 : 4;
+  const int kchunk = 256 * int(ceil_div(ceil_div(n, 4), 256));
+  const int ksplit = int(ceil_div(n, kchunk));
+  const int rchunks = int(ceil_div(n, 1024));
+  double2* W = basis;  // Ritz vectors are formed directly in the output buffer
+  double2* X = c.w.X;  // current orthonormal block
+  double2* Z = c.w.Z;  // A X, then the next block's input
+  int it = 0;
+  for (; it < max_iters; ++it) {
+    // Z = A X (split-K partials in `part`, summed in fixed order)
+    dim3 g(ceil_div(n, 32), ceil_div(b, 32), ksplit);
+    hipLaunchKernelGGL(k_gemm_ax, g, dim3(256), 0, s, gram, X, c.w.part, n, b, kchunk);
+    PISCO_LAUNCH_CHECK(h, "nullspace gemm_ax");
+    hipLaunchKernelGGL(k_sum_parts, dim3(ceil_div(nb, 256)), dim3(256), 0, s, c.w.part, Z,
+                       nb, ksplit);
+    PISCO_LAUNCH_CHECK(h, "nullspace reduce ax");
+    // Rayleigh-Ritz
+    if ((st = gemm_tn(c, X, Z, c.w.H, n))) return st;
+    if ((st = jacobi(c, c.w.H, c.w.U, c.w.theta))) return st;
+    if ((st = gemm_nn(c, X, c.w.U, W, n, b))) return st;  // Ritz vectors
+    // Y = Z U overwrites X (X is no longer needed this iteration)
+    if ((st = gemm_nn(c, Z, c.w.U, X, n, b))) return st;
+    double* rpart = reinterpret_cast<double*>(c.w.part);
+    hipLaunchKernelGGL(k_colresid, dim3(rchunks, b), dim3(256), 0, s, X, W, c.w.theta, rpart,
+                       n, b);
+    PISCO_LAUNCH_CHECK(h, "nullspace resid");
+    hipLaunchKernelGGL(k_control, dim3(1), dim3(64), 0, s, c.w.theta, rpart, rchunks, b, thr2,
+                       1e-10, margin, it, c.w.ctl, h->status_dev);
+    PISCO_LAUNCH_CHECK(h, "nullspace control");
+    hipError_t e = hipMemcpyAsync(h->host_pinned, c.w.ctl, 5 * sizeof(int),
+                                  hipMemcpyDeviceToHost, s);
+    if (e != hipSuccess) return hip_check(h, e, "nullspace ctl copy");
+    e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_check(h, e, "nullspace sync");
+    const int* hc = reinterpret_cast<const int*>(h->host_pinned);
+    if (hc[1] || hc[3] || hc[4]) break;
+    if (it + 1 == max_iters) break;
+    // next block: orth(Y) with Y held in X; the result goes to Z, then swap
+    if ((st = svqb(c, X, Z))) return st;
+    double2* tmp = X;
+    X = Z;
+    Z = tmp;
+  }
+  hipLaunchKernelGGL(k_finalize, dim3(ceil_div(nb > b ? nb : b, 256)), dim3(256), 0, s, W,
+                     c.w.theta, c.w.ctl, basis, eigvals, counts, nb, b, h->status_dev);
+  PISCO_LAUNCH_CHECK(h, "nullspace finalize");
+  return PISCO_OK;
+}
+
+}  // namespace pisco

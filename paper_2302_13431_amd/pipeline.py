@@ -1,0 +1,116 @@
+"""Stage-by-stage and end-to-end calls with torch-allocated device buffers.
+
+torch provides device memory and the stream; every stage is one call into
+libpisco (see include/pisco.h for the layouts).
+"""
+from __future__ import annotations
+
+from typing import Optional, Sequence
+
+from . import _lib as L
+
+
+def _prod(v):
+    out = 1
+    for x in v:
+        out *= int(x)
+    return out
+
+
+class Estimator:
+    """Buffers and calls for one problem size."""
+
+    def __init__(self, Q: int, acs_shape: Sequence[int], radius: float,
+                 grid_lr: Sequence[int], grid_out: Sequence[int], thresh: float = 0.05,
+                 power_iters: int = 10, tol: float = 0.0, phase_rule: int = 0,
+                 block: int = 0, max_subspace_iters: int = 60, stream=None):
+        import torch
+        self.torch = torch
+        self.D = len(acs_shape)
+        self.Q = int(Q)
+        self.acs_shape = tuple(int(a) for a in acs_shape)
+        self.grid_lr = tuple(int(a) for a in grid_lr)
+        self.grid_out = tuple(int(a) for a in grid_out)
+        self.radius = float(radius)
+        self.prob = L.make_problem(self.D, Q, acs_shape, radius, grid_lr, grid_out, thresh)
+        self.opts = L.make_opts(power_iters, tol, phase_rule, block, max_subspace_iters)
+        self.h = L.Handle(stream)
+        self.support = L.pisco_support(self.D, radius)
+        self.nsup = len(self.support)
+        self.n = self.Q * self.nsup
+        self.P = self.Q * (self.Q + 1) // 2
+        self.block = L.pisco_nullspace_block(self.prob, self.opts)
+        self.Nlr = _prod(self.grid_lr)
+        self.Nout = _prod(self.grid_out)
+        dev = torch.device("cuda")
+        ws_stage = max(L.pisco_workspace_size(self.prob, self.opts, s) for s in range(1, 6))
+        self.ws_stage = torch.empty(ws_stage + 256, dtype=torch.uint8, device=dev)
+        self.ws_all = None
+        self.dev = dev
+
+    # -------------------------------------------------------------- buffers
+    def _alloc(self, shape, dtype):
+        return self.torch.empty(tuple(shape), dtype=dtype, device=self.dev)
+
+    def _ws(self):
+        # 256-byte aligned view of the stage workspace
+        base = self.ws_stage.data_ptr()
+        off = (-base) % 256
+        return self.ws_stage[off:]
+
+    # -------------------------------------------------------------- stages
+    def gram(self, acs):
+        t = self.torch
+        out = self._alloc((self.n, self.n), t.complex64)
+        L.pisco_gram(self.h, self.prob, acs.contiguous(), out, self._ws())
+        return out
+
+    def nullspace(self, gram):
+        t = self.torch
+        b = self.block
+        eig = self._alloc((b,), t.float64)
+        basis = self._alloc((b, self.n), t.complex128)
+        counts = self._alloc((4,), t.int32)
+        L.pisco_nullspace(self.h, self.prob, self.opts, gram.contiguous(), eig, basis, counts,
+                          self._ws())
+        return eig, basis, counts
+
+    def gx(self, basis, counts):
+        t = self.torch
+        G = self._alloc((self.P, self.Nlr), t.complex64)
+        L.pisco_gx(self.h, self.prob, self.opts, basis.contiguous(), counts, G, self._ws())
+        return G
+
+    def eig(self, G, N: Optional[int] = None, opts: Optional[L.Opts] = None):
+        t = self.torch
+        N = self.Nlr if N is None else int(N)
+        maps = self._alloc((self.Q, N), t.complex64)
+        lam = self._alloc((N,), t.float32)
+        it = self._alloc((N,), t.int32)
+        L.pisco_eig(self.h, self.Q, N, float(self.nsup), opts or self.opts, G.contiguous(), maps,
+                    lam, it)
+        return maps, lam, it
+
+    def maps(self, acs, maps_lr):
+        t = self.torch
+        out = self._alloc((self.Q,) + self.grid_out, t.complex64)
+        L.pisco_maps(self.h, self.prob, self.opts, acs.contiguous(), maps_lr.contiguous(), out,
+                     self._ws())
+        return out
+
+    def estimate(self, acs, out=None, lam=None):
+        t = self.torch
+        if self.ws_all is None:
+            size = L.pisco_workspace_size(self.prob, self.opts, L.STAGE_ALL)
+            self.ws_all = t.empty(size + 256, dtype=t.uint8, device=self.dev)
+        base = self.ws_all.data_ptr()
+        ws = self.ws_all[(-base) % 256:]
+        if out is None:
+            out = self._alloc((self.Q,) + self.grid_out, t.complex64)
+        if lam is None:
+            lam = self._alloc((self.Nlr,), t.float32)
+        L.pisco_estimate(self.h, self.prob, self.opts, acs.contiguous(), out, lam, ws)
+        return out, lam
+
+    def status(self) -> int:
+        return self.h.status()
