@@ -1,0 +1,203 @@
+#!/usr/bin/env python3
+"""Throughput of the PISCO sensitivity-map path on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+
+One step is one full pass of the hot path on one synthetic scan whose ACS is
+already resident in HBM: calibration Gram by FFT correlation, FP64 signal /
+null split, G(x) on the low-resolution grid, per-voxel power iteration, phase
+reference, sinc interpolation and RSS normalisation (pisco_estimate).  The
+value is output voxels (maps on the full grid) per second.
+
+Prints one JSON line.  The roofline object describes the kernel that takes
+the most time in the timed steps: its launches are bracketed by HIP events on
+the library's stream (pisco_trace_enable) during the timed region.  The CPU
+baseline times the FP64 oracle on this host's cores after the GPU timing.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Mvoxel maps/s end-to-end, mixed/learned vs plain FP32 at fixed map error"
+
+# nullspace block per workload (a multiple of 32 comfortably above the signal rank)
+BLOCKS = {"2d_64x64_q8_acs24_r3": 64, "2d_256x256_q32_acs32_r5": 96,
+          "3d_96x160x160_q16_acs24_r4": 224}
+
+PEAKS = {  # MI355X datasheet, dense
+    "hbm": (8000.0, "GB/s"),
+    "fp64": (78.6, "TFLOP/s"),
+    "fp32": (157.3, "TFLOP/s"),
+}
+
+
+def kernel_model(name: str, w, est, rs: int):
+    """(bound, algorithmic work per launch, unit) of a kernel, or None.
+
+    Work per unit (the method's own need, not what the kernel happens to do):
+      k_gemm_ax  Gram x block, complex FP64:         8 n^2 b flops
+      k_jacobi   Hermitian eigen-decomposition, order b, with vectors:
+                 36 b^3 flops (9 b^3 real-arithmetic count, x4 for complex)
+      k_chol_inv Cholesky + triangular inverse, order b: 8/3 b^3 + 4/3 b^3 flops
+      k_herk     K^s_hat over r_s signal vectors:     8 nK P r_s flops
+      k_power    power iteration:                     8 Q^2 (iters + 1) N_lr flops
+      k_gather   Gram write:                          8 n^2 bytes
+      k_rss      read + write of the output maps:     16 Q N_out bytes
+    """
+    n, b, Q = est.n, est.block, est.Q
+    if name.startswith("k_gemm_ax"):
+        return "fp64", 8.0 * n * n * b, "flop"
+    if name.startswith("k_jacobi"):
+        return "fp64", 36.0 * b ** 3, "flop"
+    if name.startswith("k_chol_inv"):
+        return "fp64", 4.0 * b ** 3, "flop"
+    if name.startswith("k_herk"):
+        nK = 1
+        tau = int(w.radius)
+        for _ in range(w.D):
+            nK *= 4 * tau + 1
+        return "fp32", 8.0 * nK * est.P * rs, "flop"
+    if name.startswith("k_power"):
+        return "fp32", 8.0 * Q * Q * (est.opts.power_iters + 1) * est.Nlr, "flop"
+    if name.startswith("k_gather"):
+        return "hbm", 8.0 * n * n, "byte"
+    if name.startswith("k_rss"):
+        return "hbm", 16.0 * Q * est.Nout, "byte"
+    return None
+
+
+def cpu_baseline(w, acs, budget_s: float = 25.0):
+    """Oracle (FP64 numpy) on a bounded sample: whole-pipeline runs of the same
+    scan until about `budget_s` seconds have been spent (at least one)."""
+    import numpy as np
+    from oracle import pipeline as opipe
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:  # pragma: no cover
+        threads = len(os.sched_getaffinity(0))
+    a = acs.astype(np.complex128)
+    runs, spent = 0, 0.0
+    while runs == 0 or spent < budget_s * 0.5:
+        t0 = time.perf_counter()
+        opipe.estimate(a, w.radius, w.grid_lr, w.grid)
+        spent += time.perf_counter() - t0
+        runs += 1
+        if spent > budget_s:
+            break
+    nout = 1
+    for g in w.grid:
+        nout *= g
+    return {"value": runs * nout / spent / 1e6, "unit": "Mvoxel/s", "cores": int(threads),
+            "kind": "oracle",
+            "sample": f"{runs} full oracle run(s) of the same scan ({nout} output voxels each), "
+                      f"{spent:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="2d_256x256_q32_acs32_r5")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--breakdown", action="store_true", help="per-kernel times to stderr")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for {args.gpus}); the path does not run "
+              "across GPUs in this build.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    import paper_2302_13431_amd as P
+    from synth import as_device_input, workloads
+
+    w = workloads.ALL[args.workload]
+    scan = w.scan(keep_kspace=False)
+    acs_np = as_device_input(scan.acs)
+    acs = torch.from_numpy(acs_np).cuda()
+    est = P.Estimator(w.Q, w.acs, w.radius, w.grid_lr, w.grid, block=BLOCKS.get(w.name, 0))
+    out = torch.empty((w.Q,) + tuple(w.grid), dtype=torch.complex64, device="cuda")
+    lam = torch.empty((est.Nlr,), dtype=torch.float32, device="cuda")
+
+    for _ in range(args.warmup):
+        est.estimate(acs, out, lam)
+    torch.cuda.synchronize()
+    status = est.status()
+
+    # one traced step (all kernels) to find the dominant kernel
+    P.pisco_trace_enable(est.h, True, None)
+    est.estimate(acs, out, lam)
+    per = P.pisco_trace_read(est.h)
+    P.pisco_trace_enable(est.h, False)
+    dom = max(per.items(), key=lambda kv: kv[1][1])[0]
+    if args.breakdown:
+        tot = sum(v[1] for v in per.values())
+        for k, (cnt, ms) in sorted(per.items(), key=lambda kv: -kv[1][1]):
+            print(f"  {k:28s} {cnt:5d} launches {ms:9.3f} ms {100 * ms / tot:5.1f}%",
+                  file=sys.stderr)
+
+    # timed region: K steps, the dominant kernel traced with events
+    P.pisco_trace_enable(est.h, True, dom)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        est.estimate(acs, out, lam)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    traced = P.pisco_trace_read(est.h).get(dom, (0, 0.0))
+    P.pisco_trace_enable(est.h, False)
+    status |= est.status()
+
+    nout = int(np.prod(w.grid))
+    ms_per_step = elapsed / args.steps * 1e3
+    value = args.steps * nout / elapsed / 1e6
+
+    roof = None
+    rs = 0
+    ev, basis, counts = est.nullspace(est.gram(acs))
+    rs = int(counts[0].item())
+    model = kernel_model(dom, w, est, rs)
+    if model and traced[0] > 0:
+        bound, work, unit = model
+        avg_s = traced[1] / traced[0] / 1e3
+        if bound == "hbm":
+            achieved = work / avg_s / 1e9
+            peak, punit = PEAKS["hbm"]
+        else:
+            achieved = work / avg_s / 1e12
+            peak, punit = PEAKS[bound]
+        roof = {"kernel": dom, "bound": "hbm" if bound == "hbm" else "alu",
+                "dtype": bound if bound != "hbm" else None,
+                "achieved": achieved, "peak": peak, "unit": punit, "frac": achieved / peak,
+                "traffic": None, "launches": traced[0], "avg_us": avg_s * 1e6,
+                "work_per_launch": work, "work_unit": unit}
+
+    line = {"metric": METRIC, "value": value, "unit": "Mvoxel/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+            "data": "synthetic",
+            "config": {"workload": w.name, "grid": list(w.grid), "Q": w.Q, "acs": list(w.acs),
+                       "radius": w.radius, "grid_lr": list(w.grid_lr),
+                       "precision": "fp32 path, fp64 nullspace", "power_iters": 10,
+                       "nullspace_block": est.block, "signal_rank": rs,
+                       "device_status": status},
+            "roofline": roof}
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(w, acs_np)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

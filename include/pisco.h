@@ -201,6 +201,26 @@ pisco_status_t pisco_estimate(pisco_handle_t handle,
                               void* maps_out, float* lam_min, void* workspace,
                               size_t workspace_bytes);
 
+/* Kernel tracing (measurement aid).  While enabled, every kernel launch whose
+ * name contains `filter` (every launch when filter is NULL or empty) is
+ * bracketed by HIP events recorded on the handle's stream.  Adds two event
+ * records per traced launch; off by default. */
+pisco_status_t pisco_trace_enable(pisco_handle_t handle, int32_t enable,
+                                  const char* filter);
+
+typedef struct {
+  char name[64];      /* kernel name as written in the source */
+  int32_t launches;   /* traced launches since the last read */
+  double total_ms;    /* summed event-to-event durations */
+} pisco_trace_entry_t;
+
+/* Synchronises the handle's stream, aggregates the traced launches by kernel
+ * name into `out` (host array of `cap` entries, sorted by name), writes the
+ * number of distinct kernels to *count (which may exceed cap) and clears the
+ * records. */
+pisco_status_t pisco_trace_read(pisco_handle_t handle, pisco_trace_entry_t* out,
+                                int32_t cap, int32_t* count);
+
 #ifdef __cplusplus
 }
 #endif

@@ -31,8 +31,14 @@ def unit(c: np.ndarray, axis: int = 0) -> np.ndarray:
 
 
 def map_error(c_ref: np.ndarray, c: np.ndarray, axis: int = 0) -> np.ndarray:
-    """Per-voxel gauge-invariant distance between the unit-normalised maps."""
+    """Per-voxel gauge-invariant distance between the unit-normalised maps.
+
+    Equal to sqrt(2 - 2 |a^H b|) for unit a, b, evaluated as the norm of the
+    phase-aligned difference ||a - e^{i phi} b|| (e^{i phi} = phase of b^H a),
+    which has no cancellation for nearly equal vectors."""
     a = unit(np.asarray(c_ref, dtype=np.complex128), axis)
     b = unit(np.asarray(c, dtype=np.complex128), axis)
-    ip = np.abs(np.sum(np.conj(a) * b, axis=axis))
-    return np.sqrt(np.maximum(0.0, 2.0 - 2.0 * ip))
+    ip = np.sum(np.conj(b) * a, axis=axis, keepdims=True)
+    mag = np.abs(ip)
+    ph = np.where(mag > 0, ip / np.where(mag > 0, mag, 1), 1)
+    return np.sqrt(np.sum(np.abs(a - ph * b) ** 2, axis=axis))

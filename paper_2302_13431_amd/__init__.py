@@ -7,5 +7,5 @@ helper that allocates device buffers with torch.
 from ._lib import (  # noqa: F401
     Handle, Opts, PiscoError, Problem, lib, make_opts, make_problem, pisco_eig, pisco_estimate,
     pisco_gram, pisco_gx, pisco_maps, pisco_nullspace, pisco_nullspace_block, pisco_support,
-    pisco_status_string, pisco_workspace_size)
+    pisco_status_string, pisco_trace_enable, pisco_trace_read, pisco_workspace_size)
 from .pipeline import Estimator  # noqa: F401

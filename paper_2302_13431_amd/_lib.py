@@ -39,6 +39,11 @@ class Opts(ctypes.Structure):
                 ("max_subspace_iters", ctypes.c_int32)]
 
 
+class TraceEntry(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 64), ("launches", ctypes.c_int32),
+                ("total_ms", ctypes.c_double)]
+
+
 class PiscoError(RuntimeError):
     def __init__(self, status: int, where: str, msg: str = ""):
         super().__init__(f"{where}: {STATUS_NAMES.get(status, status)} {msg}".strip())
@@ -72,6 +77,8 @@ _SIGS = {
                     ctypes.c_size_t], ctypes.c_int),
     "pisco_estimate": ([_P, ctypes.POINTER(Problem), ctypes.POINTER(Opts), _P, _P, _P, _P,
                         ctypes.c_size_t], ctypes.c_int),
+    "pisco_trace_enable": ([_P, ctypes.c_int32, ctypes.c_char_p], ctypes.c_int),
+    "pisco_trace_read": ([_P, _P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
 }
 
 
@@ -220,3 +227,20 @@ def pisco_estimate(h: Handle, prob: Problem, opts: Opts, acs, maps_out, lam, ws)
     _check(lib().pisco_estimate(h.h, ctypes.byref(prob), ctypes.byref(opts), _ptr(acs),
                                 _ptr(maps_out), _ptr(lam), _ptr(ws),
                                 ws.numel() * ws.element_size()), "pisco_estimate", h.h)
+
+
+def pisco_trace_enable(h: Handle, enable: bool, filter: Optional[str] = None):
+    _check(lib().pisco_trace_enable(h.h, 1 if enable else 0,
+                                    filter.encode() if filter else None),
+           "pisco_trace_enable", h.h)
+
+
+def pisco_trace_read(h: Handle):
+    """{kernel name: (launches, total_ms)} since the last read (synchronises)."""
+    cap = 256
+    buf = (TraceEntry * cap)()
+    n = ctypes.c_int32()
+    _check(lib().pisco_trace_read(h.h, ctypes.cast(buf, _P), cap, ctypes.byref(n)),
+           "pisco_trace_read", h.h)
+    return {buf[i].name.decode(): (buf[i].launches, buf[i].total_ms)
+            for i in range(min(n.value, cap))}

@@ -6,6 +6,7 @@
 #include <cstddef>
 #include <cstdint>
 #include <string>
+#include <vector>
 
 #include "pisco.h"
 
@@ -51,12 +52,42 @@ __host__ __device__ inline double zabs2(double2 a) { return a.x * a.x + a.y * a.
 
 // ------------------------------------------------------------------ handle
 
+struct TraceRec {
+  const char* name;
+  hipEvent_t begin, end;
+};
+
 struct Handle {
   hipStream_t stream = nullptr;
   uint32_t* status_dev = nullptr;   // device status word (PISCO_FLAG_*)
   uint32_t* host_pinned = nullptr;  // pinned host mirror for status/flags
   std::string last_error;
+  // kernel tracing (pisco_trace_enable): events bracket matching launches
+  bool trace = false;
+  std::string trace_filter;
+  std::vector<hipEvent_t> event_pool;
+  size_t events_used = 0;
+  std::vector<TraceRec> records;
 };
+
+// Brackets one kernel launch with events when tracing is on and the kernel
+// name contains the filter.
+struct TraceScope {
+  Handle* h;
+  TraceRec rec{nullptr, nullptr, nullptr};
+  TraceScope(Handle* hh, const char* name);
+  ~TraceScope();
+};
+
+// Launch `kernel` on the handle's stream; traced when enabled; a launch error
+// returns PISCO_ERR_HIP from the enclosing function.
+#define PISCO_KERNEL(h, kernel, grid, block, shm, ...)                          \
+  do {                                                                          \
+    ::pisco::TraceScope pisco_ts_((h), #kernel);                                \
+    hipLaunchKernelGGL(kernel, grid, block, shm, (h)->stream, __VA_ARGS__);     \
+    hipError_t pisco_e_ = hipGetLastError();                                    \
+    if (pisco_e_ != hipSuccess) return ::pisco::hip_check((h), pisco_e_, #kernel); \
+  } while (0)
 
 // ------------------------------------------------------------------ plan
 
@@ -148,11 +179,16 @@ struct GxWs {
 size_t layout_gx(const Plan& p, int b, void* ws, GxWs* out);
 
 struct MapsWs {
-  float2* rho;     // [Q][Nlr] apodized low-res images
+  double2* rho;    // [Q][Nlr] apodized low-res images (FP64)
+  double2* rtA;    // FP64 scratch of the apodized passes
+  double2* rtB;
+  double2* m;      // [Nlr] coil combination (FP64)
+  double* pmax;    // per-block maxima of |m|
+  double2* Ma;     // apodized DFT matrices (FP64)
   float2* tmpA;    // separable-transform scratch
   float2* tmpB;
   float2* cref;    // [Q][Nlr] phase-referenced maps
-  float2* Mx;      // transform matrices
+  float2* Mx;      // interpolation matrices
 };
 size_t layout_maps(const Plan& p, void* ws, MapsWs* out);
 
@@ -174,7 +210,7 @@ pisco_status_t run_maps(Handle* h, const Plan& p, int phase_rule, const float2* 
 // Separable transform along one axis of a batched 3D array:
 //   out[b][..o..] = sum_i M[o][i] * in[b][..i..]
 // shape_in = {batch, d0, d1, d2}; axis in {1,2,3}; M is [nout][nin] float2.
-pisco_status_t axis_transform(hipStream_t s, const float2* in, float2* out,
+pisco_status_t axis_transform(Handle* h, const float2* in, float2* out,
                               const int shape_in[4], int axis, int nout,
                               const float2* M);
 
@@ -182,12 +218,19 @@ pisco_status_t axis_transform(hipStream_t s, const float2* in, float2* out,
 //   build_dft : M[o][i] = scale * g(i) * exp(i sign 2 pi (i - ci)(o - co) / period),
 //               g(i) = exp(-(i - ci)^2 / (2 sigma^2)) if sigma > 0 else 1
 //   build_sinc: periodic sinc interpolation n_in -> n_out centred samples
-pisco_status_t build_dft(hipStream_t s, float2* M, int nout, int nin, int co, int ci,
+pisco_status_t build_dft(Handle* h, float2* M, int nout, int nin, int co, int ci,
                          double period, double sign, double scale, double sigma);
-pisco_status_t build_sinc(hipStream_t s, float2* M, int nout, int nin);
+pisco_status_t build_dft(Handle* h, double2* M, int nout, int nin, int co, int ci,
+                         double period, double sign, double scale, double sigma);
+// FP64 variants of axis_transform (input FP32 or FP64, output and matrix FP64)
+pisco_status_t axis_transform64(Handle* h, const float2* in, double2* out,
+                                const int shape_in[4], int axis, int nout, const double2* M);
+pisco_status_t axis_transform64(Handle* h, const double2* in, double2* out,
+                                const int shape_in[4], int axis, int nout, const double2* M);
+pisco_status_t build_sinc(Handle* h, float2* M, int nout, int nin);
 
 // Writes the support offsets (z, y, x, 0) into `out` on the device.
-pisco_status_t launch_support(hipStream_t s, int4* out, int D, float radius);
+pisco_status_t launch_support(Handle* h, int4* out, int D, float radius);
 
 inline pisco_status_t hip_check(Handle* h, hipError_t e, const char* what) {
   if (e == hipSuccess) return PISCO_OK;

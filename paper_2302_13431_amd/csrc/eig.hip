@@ -109,11 +109,10 @@ __global__ void __launch_bounds__(256) k_power(const float2* __restrict__ G, int
 
 pisco_status_t run_eig(Handle* h, int Q, long long N, float bound, int iters, float tol,
                        const float2* G, float2* maps, float* lam, int32_t* it_out) {
-  hipStream_t s = h->stream;
   if (N <= 0) return PISCO_OK;
-#define PISCO_POWER(QG)                                                                     \
-  hipLaunchKernelGGL(k_power<QG>, dim3(ceil_div(N, 256 / QG)), dim3(256), 0, s, G, Q, N,    \
-                     bound, iters, tol, maps, lam, it_out, h->status_dev)
+#define PISCO_POWER(QG)                                                                \
+  PISCO_KERNEL(h, k_power<QG>, dim3(ceil_div(N, 256 / QG)), dim3(256), 0, G, Q, N, bound, \
+               iters, tol, maps, lam, it_out, h->status_dev)
   if (Q <= 4)
     PISCO_POWER(4);
   else if (Q <= 8)
@@ -123,7 +122,6 @@ pisco_status_t run_eig(Handle* h, int Q, long long N, float bound, int iters, fl
   else
     PISCO_POWER(32);
 #undef PISCO_POWER
-  PISCO_LAUNCH_CHECK(h, "eig power");
   return PISCO_OK;
 }
 

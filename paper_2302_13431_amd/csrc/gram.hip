@@ -283,9 +283,9 @@ __global__ void __launch_bounds__(256) k_gather(const float2* __restrict__ R,
   gram[size_t(r) * n + c] = v;
 }
 
-pisco_status_t launch_support(hipStream_t s, int4* out, int D, float radius) {
-  hipLaunchKernelGGL(k_support, dim3(1), dim3(64), 0, s, out, D, radius);
-  return hipGetLastError() == hipSuccess ? PISCO_OK : PISCO_ERR_HIP;
+pisco_status_t launch_support(Handle* h, int4* out, int D, float radius) {
+  PISCO_KERNEL(h, k_support, dim3(1), dim3(64), 0, out, D, radius);
+  return PISCO_OK;
 }
 
 static unsigned blocks_for(const PassGeom& g) { return ceil_div(g.nlines, g.lpb); }
@@ -294,33 +294,25 @@ pisco_status_t run_gram(Handle* h, const Plan& p, const float2* acs, float2* gra
                         void* ws) {
   GramWs w;
   layout_gram(p, ws, &w);
-  hipStream_t s = h->stream;
   const int Q = p.Q, P = p.P;
   const int A0 = p.acs[0], A1 = p.acs[1], A2 = p.acs[2];
   const int F0 = p.F[0], F1 = p.F[1], F2 = p.F[2];
   const int B0 = p.B[0], B1 = p.B[1], B2 = p.B[2];
 
-  hipLaunchKernelGGL(k_support, dim3(1), dim3(64), 0, s, w.support, p.D, p.radius);
-  PISCO_LAUNCH_CHECK(h, "gram support");
+  PISCO_KERNEL(h, k_support, dim3(1), dim3(64), 0, w.support, p.D, p.radius);
 
   // forward: x, y, (z)
   float2* S1 = w.S;                                   // [Q][A0][A1][F2]
   float2* S2 = w.S + size_t(Q) * F0 * F1 * F2;        // second half
   PassGeom gx = geom(F2, 1LL * Q * A0 * A1);
-  hipLaunchKernelGGL(k_fwd_x, dim3(blocks_for(gx)), dim3(256), 0, s, acs, S1, gx, A2, F2,
-                     h->status_dev);
-  PISCO_LAUNCH_CHECK(h, "gram fwd x");
+  PISCO_KERNEL(h, k_fwd_x, dim3(blocks_for(gx)), dim3(256), 0, acs, S1, gx, A2, F2, h->status_dev);
   PassGeom gy = geom(F1, 1LL * Q * A0 * F2);
   // 2D: S = S2 is [Q][1][F1][F2];  3D: S2 is [Q][A0][F1][F2]
-  hipLaunchKernelGGL(k_fwd_mid, dim3(blocks_for(gy)), dim3(256), 0, s, S1, S2, gy, A1, F1,
-                     F2);
-  PISCO_LAUNCH_CHECK(h, "gram fwd y");
+  PISCO_KERNEL(h, k_fwd_mid, dim3(blocks_for(gy)), dim3(256), 0, S1, S2, gy, A1, F1, F2);
   const float2* Sfull = S2;
   if (p.D == 3) {
     PassGeom gz = geom(F0, 1LL * Q * F1 * F2);
-    hipLaunchKernelGGL(k_fwd_mid, dim3(blocks_for(gz)), dim3(256), 0, s, S2, S1, gz, A0,
-                       F0, F1 * F2);
-    PISCO_LAUNCH_CHECK(h, "gram fwd z");
+    PISCO_KERNEL(h, k_fwd_mid, dim3(blocks_for(gz)), dim3(256), 0, S2, S1, gz, A0, F0, F1 * F2);
     Sfull = S1;  // [Q][F0][F1][F2]
   }
 
@@ -328,28 +320,18 @@ pisco_status_t run_gram(Handle* h, const Plan& p, const float2* acs, float2* gra
   const float scale = 1.0f / float(p.nF);
   if (p.D == 3) {
     PassGeom iz = geom(F0, 1LL * P * F1 * F2);
-    hipLaunchKernelGGL(k_inv_first, dim3(blocks_for(iz)), dim3(256), 0, s, Sfull, w.T1, iz,
-                       Q, F0, F1 * F2, B0);
-    PISCO_LAUNCH_CHECK(h, "gram inv z");
+    PISCO_KERNEL(h, k_inv_first, dim3(blocks_for(iz)), dim3(256), 0, Sfull, w.T1, iz, Q, F0, F1 * F2, B0);
     PassGeom iy = geom(F1, 1LL * P * B0 * F2);
-    hipLaunchKernelGGL(k_inv_mid, dim3(blocks_for(iy)), dim3(256), 0, s, w.T1, w.T2, iy, F1,
-                       F2, B1);
-    PISCO_LAUNCH_CHECK(h, "gram inv y");
+    PISCO_KERNEL(h, k_inv_mid, dim3(blocks_for(iy)), dim3(256), 0, w.T1, w.T2, iy, F1, F2, B1);
   } else {
     PassGeom iy = geom(F1, 1LL * P * F2);
-    hipLaunchKernelGGL(k_inv_first, dim3(blocks_for(iy)), dim3(256), 0, s, Sfull, w.T2, iy,
-                       Q, F1, F2, B1);
-    PISCO_LAUNCH_CHECK(h, "gram inv y");
+    PISCO_KERNEL(h, k_inv_first, dim3(blocks_for(iy)), dim3(256), 0, Sfull, w.T2, iy, Q, F1, F2, B1);
   }
   PassGeom ix = geom(F2, 1LL * P * B0 * B1);
-  hipLaunchKernelGGL(k_inv_x, dim3(blocks_for(ix)), dim3(256), 0, s, w.T2, w.R, ix, F2, B2,
-                     scale);
-  PISCO_LAUNCH_CHECK(h, "gram inv x");
+  PISCO_KERNEL(h, k_inv_x, dim3(blocks_for(ix)), dim3(256), 0, w.T2, w.R, ix, F2, B2, scale);
 
   dim3 gg(ceil_div(p.n, 256), p.n);
-  hipLaunchKernelGGL(k_gather, gg, dim3(256), 0, s, w.R, w.support, gram, Q, p.L, B0, B1,
-                     B2, p.nlag);
-  PISCO_LAUNCH_CHECK(h, "gram gather");
+  PISCO_KERNEL(h, k_gather, gg, dim3(256), 0, w.R, w.support, gram, Q, p.L, B0, B1, B2, p.nlag);
   return PISCO_OK;
 }
 

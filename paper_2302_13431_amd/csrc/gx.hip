@@ -119,9 +119,9 @@ __global__ void k_gx_finish(float2* __restrict__ G, int Q, long long N, float bo
   G[idx] = diag ? make_float2(bound - g.x, 0.f) : make_float2(-g.x, -g.y);
 }
 
-static pisco_status_t chain(hipStream_t s, const float2* in, float2* out, int shape[4],
+static pisco_status_t chain(Handle* h, const float2* in, float2* out, int shape[4],
                             int axis, int nout, const float2* M) {
-  pisco_status_t st = axis_transform(s, in, out, shape, axis, nout, M);
+  pisco_status_t st = axis_transform(h, in, out, shape, axis, nout, M);
   shape[axis] = nout;
   return st;
 }
@@ -130,13 +130,12 @@ pisco_status_t run_gx(Handle* h, const Plan& p, int b, const double2* basis,
                       const int32_t* counts, float2* G, void* ws) {
   GxWs w;
   layout_gx(p, b, ws, &w);
-  hipStream_t s = h->stream;
   const int Q = p.Q, tau = p.tau, P = p.P;
   const int box = 2 * tau + 1;
   const int Bz = p.D == 3 ? box : 1, tz = p.D == 3 ? tau : 0;
   const int ncell = Bz * box * box;
   pisco_status_t st;
-  if ((st = launch_support(s, w.support, p.D, p.radius))) return st;
+  if ((st = launch_support(h, w.support, p.D, p.radius))) return st;
 
   // transform matrices
   float2* m = w.Mx;
@@ -154,61 +153,53 @@ pisco_status_t run_gx(Handle* h, const Plan& p, int b, const double2* basis,
     m += size_t(lr) * Bd;
     if (!used) continue;
     // filter spectra: e^{+i 2 pi n f / Lk}, n = box index - tau
-    if ((st = build_dft(s, M1[d], Lk, bd, 0, tau, Lk, +1.0, 1.0, 0.0))) return st;
+    if ((st = build_dft(h, M1[d], Lk, bd, 0, tau, Lk, +1.0, 1.0, 0.0))) return st;
     // lags from spectra: (1/Lk) e^{+i 2 pi m f / Lk}, m = out index - 2 tau
-    if ((st = build_dft(s, M3[d], Bd, Lk, 2 * tau, 0, Lk, +1.0, 1.0 / Lk, 0.0))) return st;
+    if ((st = build_dft(h, M3[d], Bd, Lk, 2 * tau, 0, Lk, +1.0, 1.0 / Lk, 0.0))) return st;
     // low-res evaluation: e^{-i 2 pi m x}, x = (a - floor(N/2)) / N
-    if ((st = build_dft(s, M4[d], lr, Bd, lr / 2, 2 * tau, lr, -1.0, 1.0, 0.0))) return st;
+    if ((st = build_dft(h, M4[d], lr, Bd, lr / 2, 2 * tau, lr, -1.0, 1.0, 0.0))) return st;
   }
 
   int* map = reinterpret_cast<int*>(w.Kh);  // Kh is free until step 2
-  hipLaunchKernelGGL(k_box_map, dim3(ceil_div(ncell, 256)), dim3(256), 0, s, w.support, p.L,
-                     map, tz, tau, box, box, ncell);
-  PISCO_LAUNCH_CHECK(h, "gx box map");
+  PISCO_KERNEL(h, k_box_map, dim3(ceil_div(ncell, 256)), dim3(256), 0, w.support, p.L, map, tz, tau, box, box, ncell);
   float2* bufA = w.Tmp;
   float2* bufB = w.Tmp + w.tmp_half;
-  hipLaunchKernelGGL(k_scatter_box, dim3(ceil_div(1LL * b * Q * ncell, 256)), dim3(256), 0, s,
-                     basis, counts, map, bufA, p.n, p.L, Q, b, ncell);
-  PISCO_LAUNCH_CHECK(h, "gx scatter");
+  PISCO_KERNEL(h, k_scatter_box, dim3(ceil_div(1LL * b * Q * ncell, 256)), dim3(256), 0, basis, counts, map, bufA, p.n, p.L, Q, b, ncell);
 
   // 1. filter spectra: [bQ][Bz][box][box] -> [bQ][Kz][Ky][Kx] (ends in Fh)
   int shp[4] = {b * Q, Bz, box, box};
   if (p.D == 3) {
-    if ((st = chain(s, bufA, bufB, shp, 3, p.K[2], M1[2]))) return st;
-    if ((st = chain(s, bufB, bufA, shp, 2, p.K[1], M1[1]))) return st;
-    if ((st = chain(s, bufA, w.Fh, shp, 1, p.K[0], M1[0]))) return st;
+    if ((st = chain(h, bufA, bufB, shp, 3, p.K[2], M1[2]))) return st;
+    if ((st = chain(h, bufB, bufA, shp, 2, p.K[1], M1[1]))) return st;
+    if ((st = chain(h, bufA, w.Fh, shp, 1, p.K[0], M1[0]))) return st;
   } else {
-    if ((st = chain(s, bufA, bufB, shp, 3, p.K[2], M1[2]))) return st;
-    if ((st = chain(s, bufB, w.Fh, shp, 2, p.K[1], M1[1]))) return st;
+    if ((st = chain(h, bufA, bufB, shp, 3, p.K[2], M1[2]))) return st;
+    if ((st = chain(h, bufB, w.Fh, shp, 2, p.K[1], M1[1]))) return st;
   }
   // 2. contraction over the signal vectors
   const int FT = 256 / Q;
-  hipLaunchKernelGGL(k_herk, dim3(ceil_div(p.nK, FT)), dim3(256), 0, s, w.Fh, counts, w.Kh, Q,
-                     p.nK, FT);
-  PISCO_LAUNCH_CHECK(h, "gx herk");
+  PISCO_KERNEL(h, k_herk, dim3(ceil_div(p.nK, FT)), dim3(256), 0, w.Fh, counts, w.Kh, Q, p.nK, FT);
   // 3. lags: [P][Kz][Ky][Kx] -> [P][Bz'][By][Bx]
   int shk[4] = {P, p.K[0], p.K[1], p.K[2]};
   if (p.D == 3) {
-    if ((st = chain(s, w.Kh, bufA, shk, 3, p.B[2], M3[2]))) return st;
-    if ((st = chain(s, bufA, bufB, shk, 2, p.B[1], M3[1]))) return st;
-    if ((st = chain(s, bufB, w.Klag, shk, 1, p.B[0], M3[0]))) return st;
+    if ((st = chain(h, w.Kh, bufA, shk, 3, p.B[2], M3[2]))) return st;
+    if ((st = chain(h, bufA, bufB, shk, 2, p.B[1], M3[1]))) return st;
+    if ((st = chain(h, bufB, w.Klag, shk, 1, p.B[0], M3[0]))) return st;
   } else {
-    if ((st = chain(s, w.Kh, bufA, shk, 3, p.B[2], M3[2]))) return st;
-    if ((st = chain(s, bufA, w.Klag, shk, 2, p.B[1], M3[1]))) return st;
+    if ((st = chain(h, w.Kh, bufA, shk, 3, p.B[2], M3[2]))) return st;
+    if ((st = chain(h, bufA, w.Klag, shk, 2, p.B[1], M3[1]))) return st;
   }
   // 4. evaluate on the low-res grid: [P][Bz][By][Bx] -> [P][lr0][lr1][lr2]
   int shl[4] = {P, p.B[0], p.B[1], p.B[2]};
   if (p.D == 3) {
-    if ((st = chain(s, w.Klag, bufA, shl, 3, p.lr[2], M4[2]))) return st;
-    if ((st = chain(s, bufA, bufB, shl, 2, p.lr[1], M4[1]))) return st;
-    if ((st = chain(s, bufB, G, shl, 1, p.lr[0], M4[0]))) return st;
+    if ((st = chain(h, w.Klag, bufA, shl, 3, p.lr[2], M4[2]))) return st;
+    if ((st = chain(h, bufA, bufB, shl, 2, p.lr[1], M4[1]))) return st;
+    if ((st = chain(h, bufB, G, shl, 1, p.lr[0], M4[0]))) return st;
   } else {
-    if ((st = chain(s, w.Klag, bufA, shl, 3, p.lr[2], M4[2]))) return st;
-    if ((st = chain(s, bufA, G, shl, 2, p.lr[1], M4[1]))) return st;
+    if ((st = chain(h, w.Klag, bufA, shl, 3, p.lr[2], M4[2]))) return st;
+    if ((st = chain(h, bufA, G, shl, 2, p.lr[1], M4[1]))) return st;
   }
-  hipLaunchKernelGGL(k_gx_finish, dim3(ceil_div(1LL * P * p.Nlr, 256)), dim3(256), 0, s, G, Q,
-                     p.Nlr, float(p.L));
-  PISCO_LAUNCH_CHECK(h, "gx finish");
+  PISCO_KERNEL(h, k_gx_finish, dim3(ceil_div(1LL * P * p.Nlr, 256)), dim3(256), 0, G, Q, p.Nlr, float(p.L));
   return PISCO_OK;
 }
 

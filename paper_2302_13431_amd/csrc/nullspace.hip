@@ -10,12 +10,13 @@
 // Method: block subspace iteration with Rayleigh-Ritz on a block of b >= r_s
 // columns, all in FP64 on the GPU.  Each iteration
 //   Z = A X                        (A = FP32 Gram widened exactly to FP64)
+//   X <- orth(Z)  by Cholesky QR with column scaling
+// and, every few iterations, a Rayleigh-Ritz step
 //   H = X^H Z, eig(H) = U diag(theta) U^H     (one-sided Jacobi, PSD)
-//   W = X U (Ritz vectors), Y = Z U, residual_k = ||Y_k - theta_k W_k||
-//   X <- orth(Y) by SVQB: S = Y^H Y, D = diag(S)^-1/2, eig(D S D) = V L V^H,
-//        X = Y D V L^-1/2
-// stops when every Ritz pair up to the first one below the threshold has a
-// residual below 1e-10 theta_1.  The per-iteration rate is
+//   W = X U (Ritz vectors), residual_k = ||Z U_k - theta_k W_k||
+// that stops the iteration once every Ritz pair up to the first one below
+// the threshold has a residual below 1e-10 theta_1, and otherwise predicts
+// from the Ritz values how many plain steps remain.  The per-iteration rate is
 // lambda_{b+1} / lambda_{r_s}, small because the spectrum falls steeply past
 // the threshold.
 #include <cmath>
@@ -236,13 +237,29 @@ __global__ void __launch_bounds__(1024) k_jacobi(const double2* __restrict__ Ain
         const int i = ci < cj ? ci : cj, j = ci < cj ? cj : ci;
         double2* hi = M + size_t(i) * b;
         double2* hj = M + size_t(j) * b;
+        // the pair's two columns are held in registers for the round
+        constexpr int SL = kLds ? 8 : 1;
+        double2 xr[SL], yr[SL];
         double al = 0.0, be = 0.0, gr = 0.0, gim = 0.0;
-        for (int r = lane; r < b; r += G) {
-          const double2 x = hi[r], y = hj[r];
-          al += zabs2(x);
-          be += zabs2(y);
-          gr += x.x * y.x + x.y * y.y;
-          gim += x.x * y.y - x.y * y.x;
+        if (kLds) {
+#pragma unroll
+          for (int k = 0; k < SL; ++k) {
+            const int r = lane + k * G;
+            xr[k] = r < b ? hi[r] : make_double2(0.0, 0.0);
+            yr[k] = r < b ? hj[r] : make_double2(0.0, 0.0);
+            al += zabs2(xr[k]);
+            be += zabs2(yr[k]);
+            gr += xr[k].x * yr[k].x + xr[k].y * yr[k].y;
+            gim += xr[k].x * yr[k].y - xr[k].y * yr[k].x;
+          }
+        } else {
+          for (int r = lane; r < b; r += G) {
+            const double2 x = hi[r], y = hj[r];
+            al += zabs2(x);
+            be += zabs2(y);
+            gr += x.x * y.x + x.y * y.y;
+            gim += x.x * y.y - x.y * y.x;
+          }
         }
         for (int off = G >> 1; off > 0; off >>= 1) {
           al += __shfl_xor(al, off, G);
@@ -257,13 +274,27 @@ __global__ void __launch_bounds__(1024) k_jacobi(const double2* __restrict__ Ain
           const double c = 1.0 / sqrt(1.0 + tt * tt);
           const double s = tt * c;
           const double er = gr / gabs, ei = gim / gabs;  // e^{i phi}
-          for (int r = lane; r < b; r += G) {
-            const double2 x = hi[r], y = hj[r];
-            // x' = c x - s e^{-i phi} y ;  y' = s e^{i phi} x + c y
-            const double2 emy = make_double2(er * y.x + ei * y.y, er * y.y - ei * y.x);
-            const double2 epx = make_double2(er * x.x - ei * x.y, er * x.y + ei * x.x);
-            hi[r] = make_double2(c * x.x - s * emy.x, c * x.y - s * emy.y);
-            hj[r] = make_double2(s * epx.x + c * y.x, s * epx.y + c * y.y);
+          // x' = c x - s e^{-i phi} y ;  y' = s e^{i phi} x + c y
+          if (kLds) {
+#pragma unroll
+            for (int k = 0; k < SL; ++k) {
+              const int r = lane + k * G;
+              if (r < b) {
+                const double2 x = xr[k], y = yr[k];
+                const double2 emy = make_double2(er * y.x + ei * y.y, er * y.y - ei * y.x);
+                const double2 epx = make_double2(er * x.x - ei * x.y, er * x.y + ei * x.x);
+                hi[r] = make_double2(c * x.x - s * emy.x, c * x.y - s * emy.y);
+                hj[r] = make_double2(s * epx.x + c * y.x, s * epx.y + c * y.y);
+              }
+            }
+          } else {
+            for (int r = lane; r < b; r += G) {
+              const double2 x = hi[r], y = hj[r];
+              const double2 emy = make_double2(er * y.x + ei * y.y, er * y.y - ei * y.x);
+              const double2 epx = make_double2(er * x.x - ei * x.y, er * x.y + ei * x.x);
+              hi[r] = make_double2(c * x.x - s * emy.x, c * x.y - s * emy.y);
+              hj[r] = make_double2(s * epx.x + c * y.x, s * epx.y + c * y.y);
+            }
           }
           if (lane == 0) rotated = 1;
         }
@@ -300,27 +331,163 @@ __global__ void __launch_bounds__(1024) k_jacobi(const double2* __restrict__ Ain
 
 // ------------------------------------------------------------------ small kernels
 
-// T = D S D with D = diag(S)^{-1/2}; d stored in dvec.
-__global__ void k_svqb_scale(const double2* __restrict__ S, double2* __restrict__ T,
-                             double* __restrict__ dvec, int b) {
-  const int idx = blockIdx.x * 256 + threadIdx.x;
-  if (idx >= b * b) return;
-  const int i = idx % b, j = idx / b;
-  const double si = S[size_t(i) * b + i].x, sj = S[size_t(j) * b + j].x;
-  const double di = si > 0.0 ? 1.0 / sqrt(si) : 0.0, dj = sj > 0.0 ? 1.0 / sqrt(sj) : 0.0;
-  T[idx] = zscale(S[idx], di * dj);
-  if (j == 0) dvec[i] = di;
-}
-
-// M[i][k] = d_i V[i][k] / sqrt(l_k)   (column-major)
-__global__ void k_svqb_build(const double2* __restrict__ V, const double* __restrict__ l,
-                             const double* __restrict__ dvec, double2* __restrict__ M,
-                             int b) {
-  const int idx = blockIdx.x * 256 + threadIdx.x;
-  if (idx >= b * b) return;
-  const int i = idx % b, k = idx / b;
-  const double lk = l[k] > 1e-300 ? l[k] : 1e-300;
-  M[idx] = zscale(V[idx], dvec[i] / sqrt(lk));
+// Cholesky QR factor: for a Hermitian positive definite S (b x b,
+// column-major) returns M = D R^{-1} with D = diag(S)^{-1/2} and R the upper
+// Cholesky factor of D S D + shift I, so that Y M has orthonormal columns
+// when S = Y^H Y (up to the shift).  One block; the working matrix is in LDS
+// when kLds (b <= 96) and in `gwork` otherwise.  A pivot that is not positive
+// is replaced by a tiny one and reported through *flag.
+template <bool kLds>
+__global__ void __launch_bounds__(1024) k_chol_inv(const double2* __restrict__ S, int b,
+                                                   double shift, double2* __restrict__ M,
+                                                   double2* __restrict__ gwork,
+                                                   int* __restrict__ flag,
+                                                   double* __restrict__ rdiag) {
+  // T is row-major with a padded leading dimension ld = b + 1, so that rows
+  // are contiguous for the factorisation and the column walks of the inverse
+  // spread over the LDS banks
+  __shared__ double2 lds_mat[kLds ? kJacLdsMax * (kJacLdsMax + 1) : 1];
+  __shared__ double dsc[kLds ? kJacLdsMax : 1024];
+  double2* T = kLds ? lds_mat : gwork;
+  const int ld = b + 1;
+  const int t = threadIdx.x, nt = blockDim.x;
+  for (int k = t; k < b; k += nt) {
+    const double d = S[size_t(k) * b + k].x;
+    dsc[k] = d > 0.0 ? 1.0 / sqrt(d) : 0.0;
+  }
+  __syncthreads();
+  for (int e = t; e < b * b; e += nt) {
+    const int i = e % b, j = e / b;  // S is column-major: e = j b + i
+    double2 v = zscale(S[e], dsc[i] * dsc[j]);
+    if (i == j) v = make_double2(v.x + shift, 0.0);
+    T[size_t(i) * ld + j] = v;
+  }
+  __syncthreads();
+  // blocked right-looking Cholesky on the upper triangle, T = R^H R, with
+  // panels of kPW columns: (a) the first wave factors the diagonal block
+  // (wave-level ordering only), (b) each remaining column solves the panel's
+  // triangular system, (c) all threads apply the rank-kPW trailing update.
+  constexpr int kPW = 16;
+  for (int k0 = 0; k0 < b; k0 += kPW) {
+    const int k1 = k0 + kPW < b ? k0 + kPW : b;
+    if (t < 64) {
+      for (int k = k0; k < k1; ++k) {
+        double2* rk = T + size_t(k) * ld;
+        double dk = rk[k].x;
+        if (!(dk > 1e-300)) {
+          if (t == 0) *flag = 1;
+          dk = 1e-300;
+        }
+        const double r = sqrt(dk), rinv = 1.0 / r;
+        // diagonal of the unscaled factor (R' D^-1): converges to the
+        // eigenvalue magnitudes in orthogonal iteration
+        if (rdiag && t == 0) rdiag[k] = dsc[k] > 0.0 ? r / dsc[k] : 0.0;
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        if (t < k1 - k) rk[k + t] = t == 0 ? make_double2(r, 0.0) : zscale(rk[k + t], rinv);
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        // update the rest of the diagonal block: rows i in (k, k1), j >= i
+        const int m = k1 - k - 1;
+        for (int e = t; e < m * m; e += 64) {
+          const int i = k + 1 + e / m, j = k + 1 + e % m;
+          if (j >= i)
+            T[size_t(i) * ld + j] = zsub(T[size_t(i) * ld + j], zmulc(rk[i], rk[j]));
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+      }
+    }
+    __syncthreads();
+    // (b) R_{k0:k1, j} = R_pp^{-H} T_{k0:k1, j} for every column j >= k1
+    for (int j = k1 + t; j < b; j += nt) {
+      for (int k = k0; k < k1; ++k) {
+        double2 acc = T[size_t(k) * ld + j];
+        for (int l = k0; l < k; ++l)
+          acc = zsub(acc, zmulc(T[size_t(l) * ld + k], T[size_t(l) * ld + j]));
+        T[size_t(k) * ld + j] = zscale(acc, 1.0 / T[size_t(k) * ld + k].x);
+      }
+    }
+    __syncthreads();
+    // (c) T_{i,j} -= sum_{l in panel} conj(R_{l,i}) R_{l,j},  k1 <= i <= j
+    const int m = b - k1;
+    for (int e = t; e < m * m; e += nt) {
+      const int i = k1 + e / m, j = k1 + e % m;
+      if (j < i) continue;
+      double2 acc = T[size_t(i) * ld + j];
+      for (int l = k0; l < k1; ++l)
+        acc = zsub(acc, zmulc(T[size_t(l) * ld + i], T[size_t(l) * ld + j]));
+      T[size_t(i) * ld + j] = acc;
+    }
+    __syncthreads();
+  }
+  if (kLds) {
+    // M(:, j) = D R^{-1} e_j by back substitution, one group of 8 lanes per
+    // column j; entry l of the column lives in register slot l / 8 of lane
+    // l % 8 and each step's dot product is a butterfly over the group.
+    constexpr int G = 8, SL = kJacLdsMax / G;
+    const int j = t / G, lane = t % G;
+    double2 mreg[SL];
+#pragma unroll
+    for (int k = 0; k < SL; ++k) mreg[k] = make_double2(0.0, 0.0);
+    if (j < b) {
+      const double rjj = 1.0 / T[size_t(j) * ld + j].x;
+#pragma unroll
+      for (int k = 0; k < SL; ++k)
+        if (k == j / G && lane == j % G) mreg[k] = make_double2(rjj, 0.0);
+      for (int i = j - 1; i >= 0; --i) {
+        const double2* ri = T + size_t(i) * ld;
+        double ar = 0.0, ai = 0.0;
+#pragma unroll
+        for (int k = 0; k < SL; ++k) {
+          const int l = lane + k * G;
+          if (l > i && l <= j) {
+            const double2 r = ri[l];
+            ar = fma(r.x, mreg[k].x, fma(-r.y, mreg[k].y, ar));
+            ai = fma(r.x, mreg[k].y, fma(r.y, mreg[k].x, ai));
+          }
+        }
+#pragma unroll
+        for (int off = G / 2; off > 0; off >>= 1) {
+          ar += __shfl_xor(ar, off, G);
+          ai += __shfl_xor(ai, off, G);
+        }
+        const double inv = -1.0 / ri[i].x;
+#pragma unroll
+        for (int k = 0; k < SL; ++k)
+          if (k == i / G && lane == i % G) mreg[k] = make_double2(ar * inv, ai * inv);
+      }
+#pragma unroll
+      for (int k = 0; k < SL; ++k) {
+        const int l = lane + k * G;
+        if (l < b)
+          M[size_t(j) * b + l] = l <= j ? zscale(mreg[k], dsc[l]) : make_double2(0.0, 0.0);
+      }
+    }
+    return;
+  }
+  // global-memory variant: in-place inverse of the upper triangle, column by
+  // column (with the leading j x j block already inverted, column j of R^{-1}
+  // is -(R^{-1})_{0:j,0:j} R_{0:j,j} / R_jj, and 1 / R_jj on the diagonal)
+  __shared__ double2 xcol[kLds ? 1 : 1024];
+  for (int j = 0; j < b; ++j) {
+    for (int i = t; i < j; i += nt) xcol[i] = T[size_t(i) * ld + j];
+    __syncthreads();
+    const double inv_jj = 1.0 / T[size_t(j) * ld + j].x;
+    for (int i = t; i < j; i += nt) {
+      double2 acc = make_double2(0.0, 0.0);
+      for (int l = i; l < j; ++l) acc = zadd(acc, zmul(T[size_t(i) * ld + l], xcol[l]));
+      T[size_t(i) * ld + j] = zscale(acc, -inv_jj);
+    }
+    __syncthreads();
+    if (t == 0) T[size_t(j) * ld + j] = make_double2(inv_jj, 0.0);
+  }
+  __syncthreads();
+  // M = D R^{-1} (rows scaled), column-major, zero below the diagonal
+  for (int e = t; e < b * b; e += nt) {
+    const int i = e % b, j = e / b;
+    M[e] = i <= j ? zscale(T[size_t(i) * ld + j], dsc[i]) : make_double2(0.0, 0.0);
+  }
 }
 
 // part[chunk][k] = sum over rows of chunk of |Y_k - theta_k W_k|^2
@@ -346,9 +513,10 @@ __global__ void __launch_bounds__(256) k_colresid(const double2* __restrict__ Y,
   if (threadIdx.x == 0) part[size_t(blockIdx.x) * b + k] = red[0];
 }
 
-// Control: count signal Ritz values, test convergence.
+// Control: count signal Ritz values, test convergence, predict.
 //   ctl[0] = r_signal, ctl[1] = converged, ctl[2] = iterations,
-//   ctl[3] = block too small, ctl[4] = all-zero data
+//   ctl[3] = block too small, ctl[4] = all-zero data,
+//   ctl[5] = plain steps predicted before the next Rayleigh-Ritz
 __global__ void k_control(const double* __restrict__ theta, const double* __restrict__ rpart,
                           int nchunks, int b, double thr2, double tol, int margin, int iter,
                           int* ctl, unsigned* status) {
@@ -366,14 +534,42 @@ __global__ void k_control(const double* __restrict__ theta, const double* __rest
     if (!isfinite(r)) finite = false;
     worst = r > worst ? r : worst;
   }
-  const int too_small = rs > b - margin;
   const int zero = !(t0 > 0.0);
+  if (zero) rs = 0;
+  const int too_small = rs > b - margin;
   ctl[0] = rs;
   ctl[1] = (finite && !zero && worst <= tol * t0 && !too_small) ? 1 : 0;
   ctl[2] = iter + 1;
   ctl[3] = too_small;
   ctl[4] = zero;
+  // iterations predicted to reach the tolerance at rate theta_b / theta_rs
+  int need = 1;
+  if (rs > 0 && worst > tol * t0 && finite && !zero) {
+    double rho = theta[b - 1] / theta[rs - 1];
+    rho = rho < 1e-3 ? 1e-3 : (rho > 0.95 ? 0.95 : rho);
+    const double k = log(tol * t0 / worst) / log(rho);
+    need = int(ceil(k)) + 1;
+    need = need < 1 ? 1 : (need > 20 ? 20 : need);
+  }
+  ctl[5] = need;
   if (!finite) atomicOr(status, PISCO_FLAG_NONFINITE);
+}
+
+// Iterations still needed, predicted from the Cholesky diagonal d_j (about
+// lambda_j): rate d_{b-1} / d_{r}, r the number of d_j >= thr2 d_0, from an
+// error of order one after `done` products.  ctl[6] = prediction.
+__global__ void k_predict(const double* __restrict__ d, int b, double thr2, double tol,
+                          int done, int* ctl) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  int r = 0;
+  for (int k = 0; k < b; ++k) r += d[k] >= thr2 * d[0];
+  int need = 4;
+  if (r > 0 && r < b && d[r - 1] > 0.0) {
+    double rho = d[b - 1] / d[r - 1];
+    rho = rho < 1e-3 ? 1e-3 : (rho > 0.95 ? 0.95 : rho);
+    need = int(ceil(log(tol) / log(rho))) - done + 1;
+  }
+  ctl[6] = need < 1 ? 1 : (need > 40 ? 40 : need);
 }
 
 __global__ void k_finalize(const double2* __restrict__ W, const double* __restrict__ theta,
@@ -411,49 +607,57 @@ pisco_status_t gemm_tn(NullCtx& c, const double2* P, const double2* Qm, double2*
   const int b = c.b;
   const int chunks = int(ceil_div(rows, 256));
   dim3 g(ceil_div(b, 32), ceil_div(b, 32), chunks);
-  hipLaunchKernelGGL(k_gemm_tn, g, dim3(256), 0, c.h->stream, P, Qm, c.w.part, rows, b);
-  PISCO_LAUNCH_CHECK(c.h, "nullspace gemm_tn");
+  PISCO_KERNEL(c.h, k_gemm_tn, g, dim3(256), 0, P, Qm, c.w.part, rows, b);
   const long long len = 1LL * b * b;
-  hipLaunchKernelGGL(k_sum_parts, dim3(ceil_div(len, 256)), dim3(256), 0, c.h->stream,
-                     c.w.part, out, len, chunks);
-  PISCO_LAUNCH_CHECK(c.h, "nullspace reduce");
+  PISCO_KERNEL(c.h, k_sum_parts, dim3(ceil_div(len, 256)), dim3(256), 0, c.w.part, out, len, chunks);
   return PISCO_OK;
 }
 
 pisco_status_t gemm_nn(NullCtx& c, const double2* P, const double2* M, double2* Y, int m,
                        int k) {
   dim3 g(ceil_div(m, 32), ceil_div(c.b, 32));
-  hipLaunchKernelGGL(k_gemm_nn, g, dim3(256), 0, c.h->stream, P, M, Y, m, k, c.b);
-  PISCO_LAUNCH_CHECK(c.h, "nullspace gemm_nn");
+  PISCO_KERNEL(c.h, k_gemm_nn, g, dim3(256), 0, P, M, Y, m, k, c.b);
   return PISCO_OK;
 }
 
 pisco_status_t jacobi(NullCtx& c, const double2* A, double2* vecs, double* vals) {
   const int b = c.b;
   if (b <= kJacLdsMax)
-    hipLaunchKernelGGL(k_jacobi<true>, dim3(1), dim3(1024), 0, c.h->stream, A, b, vecs, vals,
-                       c.w.jac ? reinterpret_cast<double2*>(c.w.jac) : nullptr, 40);
+    PISCO_KERNEL(c.h, k_jacobi<true>, dim3(1), dim3(1024), 0, A, b, vecs, vals, reinterpret_cast<double2*>(c.w.jac), 40);
   else
-    hipLaunchKernelGGL(k_jacobi<false>, dim3(1), dim3(1024), 0, c.h->stream, A, b, vecs, vals,
-                       reinterpret_cast<double2*>(c.w.jac), 40);
-  PISCO_LAUNCH_CHECK(c.h, "nullspace jacobi");
+    PISCO_KERNEL(c.h, k_jacobi<false>, dim3(1), dim3(1024), 0, A, b, vecs, vals, reinterpret_cast<double2*>(c.w.jac), 40);
   return PISCO_OK;
 }
 
-// X <- orth(Y) by SVQB (Y, X column-major n x b)
-pisco_status_t svqb(NullCtx& c, const double2* Y, double2* X) {
-  const int b = c.b, n = c.p->n;
-  pisco_status_t st = gemm_tn(c, Y, Y, c.w.S, n);
-  if (st) return st;
-  double* dvec = c.w.resid;  // reused as scratch
-  hipLaunchKernelGGL(k_svqb_scale, dim3(ceil_div(b * b, 256)), dim3(256), 0, c.h->stream,
-                     c.w.S, c.w.T, dvec, b);
-  PISCO_LAUNCH_CHECK(c.h, "nullspace svqb scale");
-  if ((st = jacobi(c, c.w.T, c.w.V, c.w.lam))) return st;
-  hipLaunchKernelGGL(k_svqb_build, dim3(ceil_div(b * b, 256)), dim3(256), 0, c.h->stream,
-                     c.w.V, c.w.lam, dvec, c.w.M, b);
-  PISCO_LAUNCH_CHECK(c.h, "nullspace svqb build");
-  return gemm_nn(c, Y, c.w.M, X, n, b);
+pisco_status_t chol_inv(NullCtx& c, const double2* S, double shift, double2* M,
+                        double* rdiag = nullptr) {
+  const int b = c.b;
+  int* flag = c.w.ctl + 8;
+  if (b <= kJacLdsMax)
+    PISCO_KERNEL(c.h, k_chol_inv<true>, dim3(1), dim3(1024), 0, S, b, shift, M,
+                 reinterpret_cast<double2*>(c.w.jac), flag, rdiag);
+  else
+    PISCO_KERNEL(c.h, k_chol_inv<false>, dim3(1), dim3(1024), 0, S, b, shift, M,
+                 reinterpret_cast<double2*>(c.w.jac), flag, rdiag);
+  return PISCO_OK;
+}
+
+// Orthonormalise the columns of Y (n x b) by Cholesky QR with column scaling
+// (the first pass with a tiny diagonal shift against breakdown).  Two passes
+// (result back in Y, `tmp` is scratch) while the columns may be nearly
+// dependent; one pass (result in `tmp`) once they are close to orthogonal
+// after scaling, where a single pass is already accurate to rounding.
+pisco_status_t orth(NullCtx& c, double2* Y, double2* tmp, double* rdiag = nullptr,
+                    int passes = 2) {
+  const int n = c.p->n, b = c.b;
+  pisco_status_t st;
+  if ((st = gemm_tn(c, Y, Y, c.w.S, n))) return st;
+  if ((st = chol_inv(c, c.w.S, passes == 2 ? 1e-12 : 0.0, c.w.M, rdiag))) return st;
+  if ((st = gemm_nn(c, Y, c.w.M, tmp, n, b))) return st;
+  if (passes == 1) return PISCO_OK;
+  if ((st = gemm_tn(c, tmp, tmp, c.w.S, n))) return st;
+  if ((st = chol_inv(c, c.w.S, 0.0, c.w.M))) return st;
+  return gemm_nn(c, tmp, c.w.M, Y, n, b);
 }
 
 }  // namespace
@@ -466,43 +670,59 @@ pisco_status_t run_nullspace(Handle* h, const Plan& p, int b, int max_iters,
   hipStream_t s = h->stream;
   const int n = p.n;
   const long long nb = 1LL * n * b;
+  double2* W = basis;  // Ritz vectors are formed directly in the output buffer
+  double2* X = c.w.X;  // current orthonormal block
+  double2* Z = c.w.Z;  // A X
 
-  hipLaunchKernelGGL(k_init_block, dim3(ceil_div(nb, 256)), dim3(256), 0, s, c.w.Z, n, b);
-  PISCO_LAUNCH_CHECK(h, "nullspace init");
-  pisco_status_t st = svqb(c, c.w.Z, c.w.X);
+  PISCO_KERNEL(h, k_init_block, dim3(ceil_div(nb, 256)), dim3(256), 0, X, n, b);
+  pisco_status_t st = orth(c, X, Z);
   if (st) return st;
 
   const double thr2 = double(p.thresh) * double(p.thresh);
+  const double tol = 1e-10;
   const int margin = b / 8 > 4 ? b / 8 : 4;
   const int kchunk = 256 * int(ceil_div(ceil_div(n, 4), 256));
   const int ksplit = int(ceil_div(n, kchunk));
   const int rchunks = int(ceil_div(n, 1024));
-  double2* W = basis;  // Ritz vectors are formed directly in the output buffer
-  double2* X = c.w.X;  // current orthonormal block
-  double2* Z = c.w.Z;  // A X, then the next block's input
-  int it = 0;
-  for (; it < max_iters; ++it) {
+  // the first Rayleigh-Ritz step is scheduled from the Cholesky diagonal seen
+  // after three products; later ones from the Ritz values and residuals
+  constexpr int kUnscheduled = 1 << 30;
+  int next_rr = kUnscheduled;
+  for (int it = 0; it < max_iters; ++it) {
     // Z = A X (split-K partials in `part`, summed in fixed order)
     dim3 g(ceil_div(n, 32), ceil_div(b, 32), ksplit);
-    hipLaunchKernelGGL(k_gemm_ax, g, dim3(256), 0, s, gram, X, c.w.part, n, b, kchunk);
-    PISCO_LAUNCH_CHECK(h, "nullspace gemm_ax");
-    hipLaunchKernelGGL(k_sum_parts, dim3(ceil_div(nb, 256)), dim3(256), 0, s, c.w.part, Z,
-                       nb, ksplit);
-    PISCO_LAUNCH_CHECK(h, "nullspace reduce ax");
-    // Rayleigh-Ritz
+    PISCO_KERNEL(h, k_gemm_ax, g, dim3(256), 0, gram, X, c.w.part, n, b, kchunk);
+    PISCO_KERNEL(h, k_sum_parts, dim3(ceil_div(nb, 256)), dim3(256), 0, c.w.part, Z, nb, ksplit);
+    if (it < next_rr && it + 1 < max_iters) {
+      // plain subspace step: X <- orth(A X)
+      const bool predict = it == 2 && next_rr == kUnscheduled;
+      const int passes = it < 3 ? 2 : 1;
+      if ((st = orth(c, Z, X, predict ? c.w.resid : nullptr, passes))) return st;
+      if (passes == 2) {  // result in Z: swap roles
+        double2* tmp = X;
+        X = Z;
+        Z = tmp;
+      }
+      if (predict) {
+        PISCO_KERNEL(h, k_predict, dim3(1), dim3(64), 0, c.w.resid, b, thr2, tol, it + 1,
+                     c.w.ctl);
+        hipError_t e = hipMemcpyAsync(h->host_pinned, c.w.ctl, 8 * sizeof(int),
+                                      hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return hip_check(h, e, "nullspace predict");
+        next_rr = it + reinterpret_cast<const int*>(h->host_pinned)[6];
+      }
+      continue;
+    }
+    // Rayleigh-Ritz on span(X): H = X^H A X = U diag(theta) U^H
     if ((st = gemm_tn(c, X, Z, c.w.H, n))) return st;
     if ((st = jacobi(c, c.w.H, c.w.U, c.w.theta))) return st;
     if ((st = gemm_nn(c, X, c.w.U, W, n, b))) return st;  // Ritz vectors
-    // Y = Z U overwrites X (X is no longer needed this iteration)
-    if ((st = gemm_nn(c, Z, c.w.U, X, n, b))) return st;
+    if ((st = gemm_nn(c, Z, c.w.U, X, n, b))) return st;  // A * Ritz vectors
     double* rpart = reinterpret_cast<double*>(c.w.part);
-    hipLaunchKernelGGL(k_colresid, dim3(rchunks, b), dim3(256), 0, s, X, W, c.w.theta, rpart,
-                       n, b);
-    PISCO_LAUNCH_CHECK(h, "nullspace resid");
-    hipLaunchKernelGGL(k_control, dim3(1), dim3(64), 0, s, c.w.theta, rpart, rchunks, b, thr2,
-                       1e-10, margin, it, c.w.ctl, h->status_dev);
-    PISCO_LAUNCH_CHECK(h, "nullspace control");
-    hipError_t e = hipMemcpyAsync(h->host_pinned, c.w.ctl, 5 * sizeof(int),
+    PISCO_KERNEL(h, k_colresid, dim3(rchunks, b), dim3(256), 0, X, W, c.w.theta, rpart, n, b);
+    PISCO_KERNEL(h, k_control, dim3(1), dim3(64), 0, c.w.theta, rpart, rchunks, b, thr2, tol, margin, it, c.w.ctl, h->status_dev);
+    hipError_t e = hipMemcpyAsync(h->host_pinned, c.w.ctl, 6 * sizeof(int),
                                   hipMemcpyDeviceToHost, s);
     if (e != hipSuccess) return hip_check(h, e, "nullspace ctl copy");
     e = hipStreamSynchronize(s);
@@ -510,15 +730,14 @@ pisco_status_t run_nullspace(Handle* h, const Plan& p, int b, int max_iters,
     const int* hc = reinterpret_cast<const int*>(h->host_pinned);
     if (hc[1] || hc[3] || hc[4]) break;
     if (it + 1 == max_iters) break;
-    // next block: orth(Y) with Y held in X; the result goes to Z, then swap
-    if ((st = svqb(c, X, Z))) return st;
+    next_rr = it + hc[5];
+    // next block: orth(A * Ritz vectors) (held in X; nearly orthogonal columns)
+    if ((st = orth(c, X, Z, nullptr, 1))) return st;
     double2* tmp = X;
     X = Z;
     Z = tmp;
   }
-  hipLaunchKernelGGL(k_finalize, dim3(ceil_div(nb > b ? nb : b, 256)), dim3(256), 0, s, W,
-                     c.w.theta, c.w.ctl, basis, eigvals, counts, nb, b, h->status_dev);
-  PISCO_LAUNCH_CHECK(h, "nullspace finalize");
+  PISCO_KERNEL(h, k_finalize, dim3(ceil_div(nb > b ? nb : b, 256)), dim3(256), 0, W, c.w.theta, c.w.ctl, basis, eigvals, counts, nb, b, h->status_dev);
   return PISCO_OK;
 }
 

@@ -119,7 +119,7 @@ size_t layout_null(const Plan& p, int b, void* ws, NullWs* o) {
   if (chunks * bb > part) part = chunks * bb;
   w.part = c.take<double2>(part);
   w.ctl = c.take<int>(16);
-  w.jac = c.take<double>(bb * 2);
+  w.jac = c.take<double>((size_t(b) + 1) * b * 2);
   if (o) *o = w;
   return c.used + 256;
 }
@@ -151,20 +151,24 @@ size_t layout_gx(const Plan& p, int b, void* ws, GxWs* o) {
 size_t layout_maps(const Plan& p, void* ws, MapsWs* o) {
   Carver c(ws);
   MapsWs w{};
-  w.rho = c.take<float2>(size_t(p.Q) * p.Nlr);
-  // largest intermediate of the separable passes (lr -> out in x, y, z order)
-  size_t a = size_t(p.Q) * p.lr[0] * p.lr[1] * p.out[2];
-  size_t b = size_t(p.Q) * p.lr[0] * p.out[1] * p.out[2];
-  size_t r1 = size_t(p.Q) * p.acs[0] * p.acs[1] * p.lr[2];
-  size_t r2 = size_t(p.Q) * p.acs[0] * p.lr[1] * p.lr[2];
-  size_t m = a > b ? a : b;
-  if (r1 > m) m = r1;
-  if (r2 > m) m = r2;
-  w.tmpA = c.take<float2>(m);
-  w.tmpB = c.take<float2>(m);
+  w.rho = c.take<double2>(size_t(p.Q) * p.Nlr);
+  const size_t r1 = size_t(p.Q) * p.acs[0] * p.acs[1] * p.lr[2];
+  const size_t r2 = size_t(p.Q) * p.acs[0] * p.lr[1] * p.lr[2];
+  w.rtA = c.take<double2>(r1 > r2 ? r1 : r2);
+  w.rtB = c.take<double2>(r1 > r2 ? r1 : r2);
+  w.m = c.take<double2>(p.Nlr);
+  w.pmax = c.take<double>((p.Nlr + 255) / 256 + 1);
+  size_t ma = 0;
+  for (int d = 0; d < 3; ++d) ma += size_t(p.lr[d]) * p.acs[d];
+  w.Ma = c.take<double2>(ma + 8);
+  // largest intermediate of the interpolation passes (lr -> out in x, y, z order)
+  const size_t a = size_t(p.Q) * p.lr[0] * p.lr[1] * p.out[2];
+  const size_t b = size_t(p.Q) * p.lr[0] * p.out[1] * p.out[2];
+  w.tmpA = c.take<float2>(a > b ? a : b);
+  w.tmpB = c.take<float2>(a > b ? a : b);
   w.cref = c.take<float2>(size_t(p.Q) * p.Nlr);
   size_t msz = 0;
-  for (int d = 0; d < 3; ++d) msz += size_t(p.lr[d]) * p.acs[d] + size_t(p.out[d]) * p.lr[d];
+  for (int d = 0; d < 3; ++d) msz += size_t(p.out[d]) * p.lr[d];
   w.Mx = c.take<float2>(msz + 64);
   if (o) *o = w;
   return c.used + 256;

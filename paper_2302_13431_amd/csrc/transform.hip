@@ -10,89 +10,128 @@
 
 namespace pisco {
 
+// Element helpers: loads widen to the accumulation type T of the output.
+template <class T> struct Acc;
+template <> struct Acc<float2> {
+  using S = float;
+  __device__ static float2 zero() { return make_float2(0.f, 0.f); }
+};
+template <> struct Acc<double2> {
+  using S = double;
+  __device__ static double2 zero() { return make_double2(0.0, 0.0); }
+};
+template <class T, class U> __device__ inline T widen(U v) { return T{v.x, v.y}; }
+
 // out[outer][o][inner] = sum_i M[o][i] in[outer][i][inner]   (inner > 1)
-// One thread per (outer, inner) column; 8 outputs per pass over the inputs.
-__global__ void __launch_bounds__(256) k_axis_mid(const float2* __restrict__ in,
-                                                  float2* __restrict__ out,
-                                                  const float2* __restrict__ M,
-                                                  long long outer, int nin, int nout,
-                                                  int inner) {
+// Block = 256 consecutive (outer, inner) columns x a tile of kOT outputs;
+// the tile's rows of M are staged in LDS and read as broadcasts, each input
+// load feeds kOT complex multiply-adds.
+constexpr int kOT = 16;
+constexpr int kMidMaxIn = 256;
+
+template <class TI, class TO>
+__global__ void __launch_bounds__(256) k_axis_mid(const TI* __restrict__ in,
+                                                  TO* __restrict__ out,
+                                                  const TO* __restrict__ M, long long outer,
+                                                  int nin, int nout, int inner) {
+  __shared__ TO Ms[kOT * kMidMaxIn];
+  const int o0 = blockIdx.y * kOT;
+  const int cnt = nout - o0 < kOT ? nout - o0 : kOT;
+  for (int e = threadIdx.x; e < cnt * nin; e += 256) Ms[e] = M[size_t(o0) * nin + e];
+  __syncthreads();
   const long long col = blockIdx.x * 256LL + threadIdx.x;
   if (col >= outer * inner) return;
   const long long ou = col / inner;
   const int ii = int(col - ou * inner);
-  const float2* src = in + size_t(ou) * nin * inner + ii;
-  float2* dst = out + size_t(ou) * nout * inner + ii;
-  for (int o0 = 0; o0 < nout; o0 += 8) {
-    float2 acc[8];
+  const TI* src = in + size_t(ou) * nin * inner + ii;
+  TO* dst = out + size_t(ou) * nout * inner + ii;
+  TO acc[kOT];
 #pragma unroll
-    for (int k = 0; k < 8; ++k) acc[k] = make_float2(0.f, 0.f);
-    const int cnt = nout - o0 < 8 ? nout - o0 : 8;
-    for (int i = 0; i < nin; ++i) {
-      const float2 x = src[size_t(i) * inner];
+  for (int k = 0; k < kOT; ++k) acc[k] = Acc<TO>::zero();
+  for (int i = 0; i < nin; ++i) {
+    const TO x = widen<TO>(src[size_t(i) * inner]);
 #pragma unroll
-      for (int k = 0; k < 8; ++k)
-        if (k < cnt) {
-          const float2 m = M[size_t(o0 + k) * nin + i];
-          acc[k].x = fmaf(m.x, x.x, fmaf(-m.y, x.y, acc[k].x));
-          acc[k].y = fmaf(m.x, x.y, fmaf(m.y, x.x, acc[k].y));
-        }
+    for (int k = 0; k < kOT; ++k) {
+      const TO m = Ms[k * nin + i];
+      acc[k].x = fma(m.x, x.x, fma(-m.y, x.y, acc[k].x));
+      acc[k].y = fma(m.x, x.y, fma(m.y, x.x, acc[k].y));
     }
-#pragma unroll
-    for (int k = 0; k < 8; ++k)
-      if (k < cnt) dst[size_t(o0 + k) * inner] = acc[k];
   }
+#pragma unroll
+  for (int k = 0; k < kOT; ++k)
+    if (k < cnt) dst[size_t(o0 + k) * inner] = acc[k];
 }
 
 // out[line][o] = sum_i M[o][i] in[line][i]   (contiguous lines)
 // A block stages 16 lines in LDS; thread (line, o) computes one output.
-__global__ void __launch_bounds__(256) k_axis_last(const float2* __restrict__ in,
-                                                   float2* __restrict__ out,
-                                                   const float2* __restrict__ M,
-                                                   long long lines, int nin, int nout) {
-  extern __shared__ float2 sl[];  // [16][nin]
+template <class TI, class TO>
+__global__ void __launch_bounds__(256) k_axis_last(const TI* __restrict__ in,
+                                                   TO* __restrict__ out,
+                                                   const TO* __restrict__ M, long long lines,
+                                                   int nin, int nout) {
+  using S = typename Acc<TO>::S;
+  extern __shared__ unsigned char smem[];
+  TO* sl = reinterpret_cast<TO*>(smem);  // [16][nin]
   const long long l0 = blockIdx.x * 16LL;
   const int nl = lines - l0 < 16 ? int(lines - l0) : 16;
-  for (int e = threadIdx.x; e < nl * nin; e += 256) sl[e] = in[size_t(l0) * nin + e];
+  for (int e = threadIdx.x; e < nl * nin; e += 256) sl[e] = widen<TO>(in[size_t(l0) * nin + e]);
   __syncthreads();
   for (int e = threadIdx.x; e < nl * nout; e += 256) {
     const int ln = e / nout, o = e - ln * nout;
-    const float2* x = sl + ln * nin;
-    const float2* m = M + size_t(o) * nin;
-    float ar = 0.f, ai = 0.f;
+    const TO* x = sl + ln * nin;
+    const TO* m = M + size_t(o) * nin;
+    S ar = 0, ai = 0;
     for (int i = 0; i < nin; ++i) {
-      const float2 mv = m[i], xv = x[i];
-      ar = fmaf(mv.x, xv.x, fmaf(-mv.y, xv.y, ar));
-      ai = fmaf(mv.x, xv.y, fmaf(mv.y, xv.x, ai));
+      const TO mv = m[i], xv = x[i];
+      ar = fma(mv.x, xv.x, fma(-mv.y, xv.y, ar));
+      ai = fma(mv.x, xv.y, fma(mv.y, xv.x, ai));
     }
-    out[size_t(l0 + ln) * nout + o] = make_float2(ar, ai);
+    out[size_t(l0 + ln) * nout + o] = TO{ar, ai};
   }
 }
 
-pisco_status_t axis_transform(hipStream_t s, const float2* in, float2* out,
-                              const int shape_in[4], int axis, int nout, const float2* M) {
+template <class TI, class TO>
+static pisco_status_t axis_impl(Handle* h, const TI* in, TO* out, const int shape_in[4],
+                                int axis, int nout, const TO* M) {
   long long outer = shape_in[0];
   for (int d = 1; d < axis; ++d) outer *= shape_in[d];
   long long inner = 1;
   for (int d = axis + 1; d < 4; ++d) inner *= shape_in[d];
   const int nin = shape_in[axis];
   if (inner == 1) {
-    const size_t lds = size_t(16) * nin * sizeof(float2);
+    const size_t lds = size_t(16) * nin * sizeof(TO);
     if (lds > 64 * 1024) return PISCO_ERR_UNSUPPORTED;
-    hipLaunchKernelGGL(k_axis_last, dim3(ceil_div(outer, 16)), dim3(256), lds, s, in, out, M,
-                       outer, nin, nout);
+    PISCO_KERNEL(h, (k_axis_last<TI, TO>), dim3(ceil_div(outer, 16)), dim3(256), lds, in, out, M,
+                 outer, nin, nout);
   } else {
-    hipLaunchKernelGGL(k_axis_mid, dim3(ceil_div(outer * inner, 256)), dim3(256), 0, s, in,
-                       out, M, outer, nin, nout, int(inner));
+    if (nin > kMidMaxIn) return PISCO_ERR_UNSUPPORTED;
+    PISCO_KERNEL(h, (k_axis_mid<TI, TO>), dim3(ceil_div(outer * inner, 256), ceil_div(nout, kOT)),
+                 dim3(256), 0, in, out, M, outer, nin, nout, int(inner));
   }
-  return hipGetLastError() == hipSuccess ? PISCO_OK : PISCO_ERR_HIP;
+  return PISCO_OK;
+}
+
+pisco_status_t axis_transform(Handle* h, const float2* in, float2* out, const int shape_in[4],
+                              int axis, int nout, const float2* M) {
+  return axis_impl<float2, float2>(h, in, out, shape_in, axis, nout, M);
+}
+
+pisco_status_t axis_transform64(Handle* h, const float2* in, double2* out,
+                                const int shape_in[4], int axis, int nout, const double2* M) {
+  return axis_impl<float2, double2>(h, in, out, shape_in, axis, nout, M);
+}
+
+pisco_status_t axis_transform64(Handle* h, const double2* in, double2* out,
+                                const int shape_in[4], int axis, int nout, const double2* M) {
+  return axis_impl<double2, double2>(h, in, out, shape_in, axis, nout, M);
 }
 
 // ------------------------------------------------------------------ matrix builders
 
 // M[o][i] = scale * w(i) * exp(i * sign * 2 pi * (i - ci) * (o - co) / period)
 // with w(i) = exp(-(i - ci)^2 / (2 sigma^2)) when sigma > 0, else 1.
-__global__ void k_build_dft(float2* M, int nout, int nin, int co, int ci, double period,
+template <class TM>
+__global__ void k_build_dft(TM* M, int nout, int nin, int co, int ci, double period,
                             double sign, double scale, double sigma) {
   const int idx = blockIdx.x * 256 + threadIdx.x;
   if (idx >= nout * nin) return;
@@ -115,7 +154,7 @@ __global__ void k_build_dft(float2* M, int nout, int nin, int co, int ci, double
     const double k = double(i - ci);
     w *= exp(-k * k / (2.0 * sigma * sigma));
   }
-  M[idx] = make_float2(float(w * cs), float(w * sn));
+  M[idx] = TM{static_cast<decltype(TM{}.x)>(w * cs), static_cast<decltype(TM{}.x)>(w * sn)};
 }
 
 // Periodic sinc (Dirichlet) interpolation from n_in to n_out >= n_in centred
@@ -147,17 +186,23 @@ __global__ void k_build_sinc(float2* M, int nout, int nin) {
   M[idx] = make_float2(float(re / nin), float(im / nin));
 }
 
-pisco_status_t build_dft(hipStream_t s, float2* M, int nout, int nin, int co, int ci,
+pisco_status_t build_dft(Handle* h, float2* M, int nout, int nin, int co, int ci,
                          double period, double sign, double scale, double sigma) {
-  hipLaunchKernelGGL(k_build_dft, dim3(ceil_div(nout * nin, 256)), dim3(256), 0, s, M, nout,
-                     nin, co, ci, period, sign, scale, sigma);
-  return hipGetLastError() == hipSuccess ? PISCO_OK : PISCO_ERR_HIP;
+  PISCO_KERNEL(h, k_build_dft<float2>, dim3(ceil_div(nout * nin, 256)), dim3(256), 0, M, nout,
+               nin, co, ci, period, sign, scale, sigma);
+  return PISCO_OK;
 }
 
-pisco_status_t build_sinc(hipStream_t s, float2* M, int nout, int nin) {
-  hipLaunchKernelGGL(k_build_sinc, dim3(ceil_div(nout * nin, 256)), dim3(256), 0, s, M, nout,
-                     nin);
-  return hipGetLastError() == hipSuccess ? PISCO_OK : PISCO_ERR_HIP;
+pisco_status_t build_dft(Handle* h, double2* M, int nout, int nin, int co, int ci,
+                         double period, double sign, double scale, double sigma) {
+  PISCO_KERNEL(h, k_build_dft<double2>, dim3(ceil_div(nout * nin, 256)), dim3(256), 0, M, nout,
+               nin, co, ci, period, sign, scale, sigma);
+  return PISCO_OK;
+}
+
+pisco_status_t build_sinc(Handle* h, float2* M, int nout, int nin) {
+  PISCO_KERNEL(h, k_build_sinc, dim3(ceil_div(nout * nin, 256)), dim3(256), 0, M, nout, nin);
+  return PISCO_OK;
 }
 
 }  // namespace pisco

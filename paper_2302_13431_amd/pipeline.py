@@ -81,14 +81,16 @@ class Estimator:
         L.pisco_gx(self.h, self.prob, self.opts, basis.contiguous(), counts, G, self._ws())
         return G
 
-    def eig(self, G, N: Optional[int] = None, opts: Optional[L.Opts] = None):
+    def eig(self, G, N: Optional[int] = None, opts: Optional[L.Opts] = None,
+            Q: Optional[int] = None, bound: Optional[float] = None):
         t = self.torch
         N = self.Nlr if N is None else int(N)
-        maps = self._alloc((self.Q, N), t.complex64)
+        Q = self.Q if Q is None else int(Q)
+        bound = float(self.nsup) if bound is None else float(bound)
+        maps = self._alloc((Q, N), t.complex64)
         lam = self._alloc((N,), t.float32)
         it = self._alloc((N,), t.int32)
-        L.pisco_eig(self.h, self.Q, N, float(self.nsup), opts or self.opts, G.contiguous(), maps,
-                    lam, it)
+        L.pisco_eig(self.h, Q, N, bound, opts or self.opts, G.contiguous(), maps, lam, it)
         return maps, lam, it
 
     def maps(self, acs, maps_lr):

@@ -429,3 +429,18 @@ def test_generator_properties():
     assert a.acs.shape == (8, 24, 24)
     # ACS index a <-> k = a - floor(A/2): the DC sample is at the centre
     assert np.allclose(a.acs[:, 12, 12], a.kspace[:, 32, 32])
+
+
+def test_map_error_has_no_cancellation_floor():
+    """Unit b = (a cos t + w sin t) e^{i psi} with w orthogonal to a has the
+    closed-form distance 2 sin(t/2); it must be resolved down to 1e-9, far
+    below the sqrt(eps) floor of the 2 - 2|a^H b| form."""
+    rng = np.random.default_rng(3)
+    a = rng.standard_normal((10, 5)) + 1j * rng.standard_normal((10, 5))
+    a = metrics.unit(a)
+    w = rng.standard_normal((10, 5)) + 1j * rng.standard_normal((10, 5))
+    w = metrics.unit(w - a * np.sum(np.conj(a) * w, axis=0, keepdims=True))
+    t = np.array([1e-9, 3e-8, 1e-6, 1e-3, 0.5])
+    b = (a * np.cos(t) + w * np.sin(t)) * np.exp(1j * np.array([0.3, 1.3, 2.0, -1.0, 3.0]))
+    e = metrics.map_error(a, b)
+    assert np.allclose(e, 2 * np.sin(t / 2), rtol=1e-6, atol=0)
