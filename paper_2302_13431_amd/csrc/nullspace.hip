@@ -8,18 +8,23 @@
 // form of Eq. (20).
 //
 // Method: block subspace iteration with Rayleigh-Ritz on a block of b >= r_s
-// columns, all in FP64 on the GPU.  Each iteration
+// columns, all in FP64 on the GPU:
 //   Z = A X                        (A = FP32 Gram widened exactly to FP64)
-//   X <- orth(Z)  by Cholesky QR with column scaling
-// and, every few iterations, a Rayleigh-Ritz step
+//   X <- orth(Z) by Cholesky QR with column scaling; after the third product
+//        up to three products share one orthonormalisation, the scaled
+//        block staying well conditioned;
+// and, when the rate predicted from the Cholesky diagonal (about the
+// eigenvalues in orthogonal iteration) says the block has converged, a
+// Rayleigh-Ritz step
 //   H = X^H Z, eig(H) = U diag(theta) U^H     (one-sided Jacobi, PSD)
 //   W = X U (Ritz vectors), residual_k = ||Z U_k - theta_k W_k||
 // that stops the iteration once every Ritz pair up to the first one below
-// the threshold has a residual below 1e-10 theta_1, and otherwise predicts
-// from the Ritz values how many plain steps remain.  The per-iteration rate is
+// the threshold has a residual below 1e-10 theta_1 (otherwise the Ritz
+// values predict how many more products to run).  The rate per product is
 // lambda_{b+1} / lambda_{r_s}, small because the spectrum falls steeply past
 // the threshold.
 #include <cmath>
+#include <utility>
 
 #include "common.hpp"
 
@@ -211,14 +216,30 @@ __global__ void __launch_bounds__(1024) k_jacobi(const double2* __restrict__ Ain
                                                  double2* __restrict__ vec_out,
                                                  double* __restrict__ val_out,
                                                  double2* __restrict__ gwork,
-                                                 int max_sweeps) {
+                                                 int max_sweeps, double junk_rel) {
   __shared__ double2 lds_mat[kLds ? kJacLdsMax * kJacLdsMax : 1];
   __shared__ double norms[1024];
   __shared__ int rotated;
+  __shared__ double junk_sq;
   double2* M = kLds ? lds_mat : gwork;
   const int t = threadIdx.x, nt = blockDim.x;
   const int bb = b * b;
   for (int e = t; e < bb; e += nt) M[e] = Ain[e];
+  __syncthreads();
+  // squared column norms, tracked through the rotations; a pair whose two
+  // columns are both below junk_rel * max_k H_kk (far under the signal
+  // threshold) is never rotated: such columns only need to stay orthogonal
+  // to the signal ones, which the other pairs ensure
+  for (int k = t; k < b; k += nt) {
+    double s = 0.0;
+    for (int r = 0; r < b; ++r) s += zabs2(M[size_t(k) * b + r]);
+    norms[k] = s;
+  }
+  if (t == 0) {
+    double mx = 0.0;
+    for (int k = 0; k < b; ++k) mx = fmax(mx, M[size_t(k) * b + k].x);
+    junk_sq = (junk_rel * mx) * (junk_rel * mx);
+  }
   __syncthreads();
   const int npairs = b / 2;
   int G = 64;
@@ -237,11 +258,13 @@ __global__ void __launch_bounds__(1024) k_jacobi(const double2* __restrict__ Ain
         const int i = ci < cj ? ci : cj, j = ci < cj ? cj : ci;
         double2* hi = M + size_t(i) * b;
         double2* hj = M + size_t(j) * b;
+        const bool skip = norms[i] < junk_sq && norms[j] < junk_sq;
         // the pair's two columns are held in registers for the round
         constexpr int SL = kLds ? 8 : 1;
         double2 xr[SL], yr[SL];
         double al = 0.0, be = 0.0, gr = 0.0, gim = 0.0;
-        if (kLds) {
+        if (skip) {
+        } else if (kLds) {
 #pragma unroll
           for (int k = 0; k < SL; ++k) {
             const int r = lane + k * G;
@@ -268,7 +291,7 @@ __global__ void __launch_bounds__(1024) k_jacobi(const double2* __restrict__ Ain
           gim += __shfl_xor(gim, off, G);
         }
         const double gabs = sqrt(gr * gr + gim * gim);
-        if (gabs > tol * sqrt(al * be) && gabs > 0.0) {
+        if (!skip && gabs > tol * sqrt(al * be) && gabs > 0.0) {
           const double zeta = (be - al) / (2.0 * gabs);
           const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
           const double c = 1.0 / sqrt(1.0 + tt * tt);
@@ -296,7 +319,14 @@ __global__ void __launch_bounds__(1024) k_jacobi(const double2* __restrict__ Ain
               hj[r] = make_double2(s * epx.x + c * y.x, s * epx.y + c * y.y);
             }
           }
-          if (lane == 0) rotated = 1;
+          if (lane == 0) {
+            rotated = 1;
+            norms[i] = al - tt * gabs;
+            norms[j] = be + tt * gabs;
+          }
+        } else if (!skip && lane == 0) {
+          norms[i] = al;
+          norms[j] = be;
         }
       }
       __syncthreads();
@@ -305,6 +335,7 @@ __global__ void __launch_bounds__(1024) k_jacobi(const double2* __restrict__ Ain
     __syncthreads();
     if (!any) break;
   }
+  __syncthreads();
   // eigenvalues = column norms; rank-sort descending (ties: lower index first)
   for (int k = t; k < b; k += nt) {
     double s = 0.0;
@@ -368,6 +399,7 @@ __global__ void __launch_bounds__(1024) k_chol_inv(const double2* __restrict__ S
   // (wave-level ordering only), (b) each remaining column solves the panel's
   // triangular system, (c) all threads apply the rank-kPW trailing update.
   constexpr int kPW = 16;
+  __shared__ double dinv[kPW];
   for (int k0 = 0; k0 < b; k0 += kPW) {
     const int k1 = k0 + kPW < b ? k0 + kPW : b;
     if (t < 64) {
@@ -399,13 +431,15 @@ __global__ void __launch_bounds__(1024) k_chol_inv(const double2* __restrict__ S
       }
     }
     __syncthreads();
+    for (int k = k0 + t; k < k1; k += nt) dinv[k - k0] = 1.0 / T[size_t(k) * ld + k].x;
+    __syncthreads();
     // (b) R_{k0:k1, j} = R_pp^{-H} T_{k0:k1, j} for every column j >= k1
     for (int j = k1 + t; j < b; j += nt) {
       for (int k = k0; k < k1; ++k) {
         double2 acc = T[size_t(k) * ld + j];
         for (int l = k0; l < k; ++l)
           acc = zsub(acc, zmulc(T[size_t(l) * ld + k], T[size_t(l) * ld + j]));
-        T[size_t(k) * ld + j] = zscale(acc, 1.0 / T[size_t(k) * ld + k].x);
+        T[size_t(k) * ld + j] = zscale(acc, dinv[k - k0]);
       }
     }
     __syncthreads();
@@ -426,36 +460,37 @@ __global__ void __launch_bounds__(1024) k_chol_inv(const double2* __restrict__ S
     // column j; entry l of the column lives in register slot l / 8 of lane
     // l % 8 and each step's dot product is a butterfly over the group.
     constexpr int G = 8, SL = kJacLdsMax / G;
+    __shared__ double rinv[kJacLdsMax];
+    for (int i = t; i < b; i += nt) rinv[i] = 1.0 / T[size_t(i) * ld + i].x;
+    __syncthreads();
+    // column j of R^{-1} by a column-oriented back substitution: start from
+    // e_j, and for i = j, j-1, ..., 0 scale entry i by 1/R_ii, broadcast it
+    // to the group and subtract its multiple of column i of R from the
+    // entries above it.  No reductions; one broadcast per step.
     const int j = t / G, lane = t % G;
     double2 mreg[SL];
 #pragma unroll
-    for (int k = 0; k < SL; ++k) mreg[k] = make_double2(0.0, 0.0);
+    for (int k = 0; k < SL; ++k) {
+      const int l = lane + k * G;
+      mreg[k] = make_double2(l == j ? 1.0 : 0.0, 0.0);
+    }
     if (j < b) {
-      const double rjj = 1.0 / T[size_t(j) * ld + j].x;
+      for (int i = j; i >= 0; --i) {
+        // owner of entry i scales it; everyone reads it
+        double2 mi = make_double2(0.0, 0.0);
 #pragma unroll
-      for (int k = 0; k < SL; ++k)
-        if (k == j / G && lane == j % G) mreg[k] = make_double2(rjj, 0.0);
-      for (int i = j - 1; i >= 0; --i) {
-        const double2* ri = T + size_t(i) * ld;
-        double ar = 0.0, ai = 0.0;
+        for (int k = 0; k < SL; ++k)
+          if (k == i / G) mi = mreg[k];
+        mi = zscale(mi, rinv[i]);
+        const int src = (t & ~(G - 1)) + (i % G);
+        mi.x = __shfl(mi.x, src, 64);
+        mi.y = __shfl(mi.y, src, 64);
 #pragma unroll
         for (int k = 0; k < SL; ++k) {
           const int l = lane + k * G;
-          if (l > i && l <= j) {
-            const double2 r = ri[l];
-            ar = fma(r.x, mreg[k].x, fma(-r.y, mreg[k].y, ar));
-            ai = fma(r.x, mreg[k].y, fma(r.y, mreg[k].x, ai));
-          }
+          if (l == i) mreg[k] = mi;
+          else if (l < i) mreg[k] = zsub(mreg[k], zmul(T[size_t(l) * ld + i], mi));
         }
-#pragma unroll
-        for (int off = G / 2; off > 0; off >>= 1) {
-          ar += __shfl_xor(ar, off, G);
-          ai += __shfl_xor(ai, off, G);
-        }
-        const double inv = -1.0 / ri[i].x;
-#pragma unroll
-        for (int k = 0; k < SL; ++k)
-          if (k == i / G && lane == i % G) mreg[k] = make_double2(ar * inv, ai * inv);
       }
 #pragma unroll
       for (int k = 0; k < SL; ++k) {
@@ -620,12 +655,13 @@ pisco_status_t gemm_nn(NullCtx& c, const double2* P, const double2* M, double2* 
   return PISCO_OK;
 }
 
-pisco_status_t jacobi(NullCtx& c, const double2* A, double2* vecs, double* vals) {
+pisco_status_t jacobi(NullCtx& c, const double2* A, double2* vecs, double* vals,
+                      double junk_rel) {
   const int b = c.b;
   if (b <= kJacLdsMax)
-    PISCO_KERNEL(c.h, k_jacobi<true>, dim3(1), dim3(1024), 0, A, b, vecs, vals, reinterpret_cast<double2*>(c.w.jac), 40);
+    PISCO_KERNEL(c.h, k_jacobi<true>, dim3(1), dim3(1024), 0, A, b, vecs, vals, reinterpret_cast<double2*>(c.w.jac), 40, junk_rel);
   else
-    PISCO_KERNEL(c.h, k_jacobi<false>, dim3(1), dim3(1024), 0, A, b, vecs, vals, reinterpret_cast<double2*>(c.w.jac), 40);
+    PISCO_KERNEL(c.h, k_jacobi<false>, dim3(1), dim3(1024), 0, A, b, vecs, vals, reinterpret_cast<double2*>(c.w.jac), 40, junk_rel);
   return PISCO_OK;
 }
 
@@ -675,8 +711,10 @@ pisco_status_t run_nullspace(Handle* h, const Plan& p, int b, int max_iters,
   double2* Z = c.w.Z;  // A X
 
   PISCO_KERNEL(h, k_init_block, dim3(ceil_div(nb, 256)), dim3(256), 0, X, n, b);
-  pisco_status_t st = orth(c, X, Z);
+  // a random block is well conditioned: one Cholesky QR pass
+  pisco_status_t st = orth(c, X, Z, nullptr, 1);
   if (st) return st;
+  std::swap(X, Z);
 
   const double thr2 = double(p.thresh) * double(p.thresh);
   const double tol = 1e-10;
@@ -684,44 +722,60 @@ pisco_status_t run_nullspace(Handle* h, const Plan& p, int b, int max_iters,
   const int kchunk = 256 * int(ceil_div(ceil_div(n, 4), 256));
   const int ksplit = int(ceil_div(n, kchunk));
   const int rchunks = int(ceil_div(n, 1024));
-  // the first Rayleigh-Ritz step is scheduled from the Cholesky diagonal seen
-  // after three products; later ones from the Ritz values and residuals
-  constexpr int kUnscheduled = 1 << 30;
-  int next_rr = kUnscheduled;
-  for (int it = 0; it < max_iters; ++it) {
-    // Z = A X (split-K partials in `part`, summed in fixed order)
+  // Z = A X (split-K partials in `part`, summed in fixed order)
+  auto product = [&](const double2* in, double2* out) -> pisco_status_t {
     dim3 g(ceil_div(n, 32), ceil_div(b, 32), ksplit);
-    PISCO_KERNEL(h, k_gemm_ax, g, dim3(256), 0, gram, X, c.w.part, n, b, kchunk);
-    PISCO_KERNEL(h, k_sum_parts, dim3(ceil_div(nb, 256)), dim3(256), 0, c.w.part, Z, nb, ksplit);
-    if (it < next_rr && it + 1 < max_iters) {
-      // plain subspace step: X <- orth(A X)
-      const bool predict = it == 2 && next_rr == kUnscheduled;
-      const int passes = it < 3 ? 2 : 1;
-      if ((st = orth(c, Z, X, predict ? c.w.resid : nullptr, passes))) return st;
-      if (passes == 2) {  // result in Z: swap roles
-        double2* tmp = X;
-        X = Z;
-        Z = tmp;
+    PISCO_KERNEL(h, k_gemm_ax, g, dim3(256), 0, gram, in, c.w.part, n, b, kchunk);
+    PISCO_KERNEL(h, k_sum_parts, dim3(ceil_div(nb, 256)), dim3(256), 0, c.w.part, out, nb,
+                 ksplit);
+    return PISCO_OK;
+  };
+  // Products are counted in `done`.  The first Rayleigh-Ritz step is
+  // scheduled from the Cholesky diagonal seen after three products, later
+  // ones from the Ritz values and residuals.  After the third product the
+  // scaled block stays well conditioned (kappa of order 10 for two more
+  // products), so up to three products share one Cholesky QR pass.
+  constexpr int kUnscheduled = 1 << 30;
+  int rr_at = kUnscheduled;  // product count at which to run Rayleigh-Ritz
+  int done = 0;
+  while (true) {
+    if ((st = product(X, Z))) return st;
+    ++done;
+    if (done < rr_at && done < max_iters) {
+      int extra = 0;
+      if (done >= 3 && rr_at != kUnscheduled) {
+        extra = rr_at - done - 1;
+        extra = extra < 0 ? 0 : (extra > 2 ? 2 : extra);
       }
+      for (int e = 0; e < extra; ++e) {
+        if ((st = product(Z, X))) return st;
+        std::swap(X, Z);
+        ++done;
+      }
+      const bool predict = done == 3 && rr_at == kUnscheduled;
+      const int passes = done == 1 ? 2 : 1;
+      if ((st = orth(c, Z, X, predict ? c.w.resid : nullptr, passes))) return st;
+      if (passes == 2) std::swap(X, Z);  // two passes leave the result in Z
       if (predict) {
-        PISCO_KERNEL(h, k_predict, dim3(1), dim3(64), 0, c.w.resid, b, thr2, tol, it + 1,
+        PISCO_KERNEL(h, k_predict, dim3(1), dim3(64), 0, c.w.resid, b, thr2, tol, done,
                      c.w.ctl);
         hipError_t e = hipMemcpyAsync(h->host_pinned, c.w.ctl, 8 * sizeof(int),
                                       hipMemcpyDeviceToHost, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         if (e != hipSuccess) return hip_check(h, e, "nullspace predict");
-        next_rr = it + reinterpret_cast<const int*>(h->host_pinned)[6];
+        rr_at = done + reinterpret_cast<const int*>(h->host_pinned)[6];
       }
       continue;
     }
     // Rayleigh-Ritz on span(X): H = X^H A X = U diag(theta) U^H
     if ((st = gemm_tn(c, X, Z, c.w.H, n))) return st;
-    if ((st = jacobi(c, c.w.H, c.w.U, c.w.theta))) return st;
+    if ((st = jacobi(c, c.w.H, c.w.U, c.w.theta, 0.0))) return st;
     if ((st = gemm_nn(c, X, c.w.U, W, n, b))) return st;  // Ritz vectors
     if ((st = gemm_nn(c, Z, c.w.U, X, n, b))) return st;  // A * Ritz vectors
     double* rpart = reinterpret_cast<double*>(c.w.part);
     PISCO_KERNEL(h, k_colresid, dim3(rchunks, b), dim3(256), 0, X, W, c.w.theta, rpart, n, b);
-    PISCO_KERNEL(h, k_control, dim3(1), dim3(64), 0, c.w.theta, rpart, rchunks, b, thr2, tol, margin, it, c.w.ctl, h->status_dev);
+    PISCO_KERNEL(h, k_control, dim3(1), dim3(64), 0, c.w.theta, rpart, rchunks, b, thr2, tol,
+                 margin, done - 1, c.w.ctl, h->status_dev);
     hipError_t e = hipMemcpyAsync(h->host_pinned, c.w.ctl, 6 * sizeof(int),
                                   hipMemcpyDeviceToHost, s);
     if (e != hipSuccess) return hip_check(h, e, "nullspace ctl copy");
@@ -729,13 +783,11 @@ pisco_status_t run_nullspace(Handle* h, const Plan& p, int b, int max_iters,
     if (e != hipSuccess) return hip_check(h, e, "nullspace sync");
     const int* hc = reinterpret_cast<const int*>(h->host_pinned);
     if (hc[1] || hc[3] || hc[4]) break;
-    if (it + 1 == max_iters) break;
-    next_rr = it + hc[5];
+    if (done >= max_iters) break;
+    rr_at = done + hc[5];
     // next block: orth(A * Ritz vectors) (held in X; nearly orthogonal columns)
     if ((st = orth(c, X, Z, nullptr, 1))) return st;
-    double2* tmp = X;
-    X = Z;
-    Z = tmp;
+    std::swap(X, Z);
   }
   PISCO_KERNEL(h, k_finalize, dim3(ceil_div(nb > b ? nb : b, 256)), dim3(256), 0, W, c.w.theta, c.w.ctl, basis, eigvals, counts, nb, b, h->status_dev);
   return PISCO_OK;
