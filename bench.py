@@ -73,6 +73,32 @@ def kernel_model(name: str, w, est, rs: int):
     return None
 
 
+KERNEL_SOURCES = {"k_gemm_ax": "nullspace.hip", "k_jacobi": "nullspace.hip",
+                  "k_chol_inv": "nullspace.hip", "k_gemm_tn": "nullspace.hip",
+                  "k_gemm_nn": "nullspace.hip", "k_herk": "gx.hip", "k_power": "eig.hip",
+                  "k_gather": "gram.hip", "k_rss": "maps.hip"}
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summaries,
+    or None when there is none or the kernel's source changed since."""
+    import glob
+    import hashlib
+    base = kernel.split("<")[0].strip("()")
+    src = KERNEL_SOURCES.get(base)
+    if not src:
+        return None
+    path = os.path.join(ROOT, "paper_2302_13431_amd", "csrc", src)
+    digest = hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+    for f in glob.glob(os.path.join(ROOT, "profiles", "*.md")):
+        for line in open(f):
+            parts = line.split()
+            if len(parts) == 5 and parts[0] == "traffic" and parts[1] == base \
+                    and parts[3] == src and parts[4] == digest:
+                return float(parts[2])
+    return None
+
+
 def cpu_baseline(w, acs, budget_s: float = 25.0):
     """Oracle (FP64 numpy) on a bounded sample: whole-pipeline runs of the same
     scan until about `budget_s` seconds have been spent (at least one)."""
@@ -109,7 +135,20 @@ def main():
     ap.add_argument("--workload", default="2d_256x256_q32_acs32_r5")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--breakdown", action="store_true", help="per-kernel times to stderr")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run 5 device-to-device copies of MIB MiB (HBM counter "
+                         "calibration under rocprofv3) and exit")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        src = torch.empty(args.copy_calibration * (1 << 20), dtype=torch.uint8, device="cuda")
+        src.fill_(1)
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": src.numel(), "copies": 5}))
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for {args.gpus}); the path does not run "
               "across GPUs in this build.", file=sys.stderr)
@@ -181,7 +220,7 @@ def main():
         roof = {"kernel": dom, "bound": "hbm" if bound == "hbm" else "alu",
                 "dtype": bound if bound != "hbm" else None,
                 "achieved": achieved, "peak": peak, "unit": punit, "frac": achieved / peak,
-                "traffic": None, "launches": traced[0], "avg_us": avg_s * 1e6,
+                "traffic": measured_traffic(dom), "launches": traced[0], "avg_us": avg_s * 1e6,
                 "work_per_launch": work, "work_unit": unit}
 
     line = {"metric": METRIC, "value": value, "unit": "Mvoxel/s", "n_gpus": 1,
