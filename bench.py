@@ -43,8 +43,8 @@ def kernel_model(name: str, w, est, rs: int):
 
     Work per unit (the method's own need, not what the kernel happens to do):
       k_gemm_ax  Gram x block, complex FP64:         8 n^2 b flops
-      k_jacobi   Hermitian eigen-decomposition, order b, with vectors:
-                 36 b^3 flops (9 b^3 real-arithmetic count, x4 for complex)
+      k_hetrd    Householder tridiagonalisation, order b, complex:
+                 16/3 b^3 flops (4/3 b^3 real multiply-adds, x4 for complex)
       k_chol_inv Cholesky + triangular inverse, order b: 8/3 b^3 + 4/3 b^3 flops
       k_herk     K^s_hat over r_s signal vectors:     8 nK P r_s flops
       k_power    power iteration:                     8 Q^2 (iters + 1) N_lr flops
@@ -54,8 +54,8 @@ def kernel_model(name: str, w, est, rs: int):
     n, b, Q = est.n, est.block, est.Q
     if name.startswith("k_gemm_ax"):
         return "fp64", 8.0 * n * n * b, "flop"
-    if name.startswith("k_jacobi"):
-        return "fp64", 36.0 * b ** 3, "flop"
+    if name.startswith("k_hetrd"):
+        return "fp64", 16.0 / 3.0 * b ** 3, "flop"
     if name.startswith("k_chol_inv"):
         return "fp64", 4.0 * b ** 3, "flop"
     if name.startswith("k_herk"):
@@ -73,7 +73,7 @@ def kernel_model(name: str, w, est, rs: int):
     return None
 
 
-KERNEL_SOURCES = {"k_gemm_ax": "nullspace.hip", "k_jacobi": "nullspace.hip",
+KERNEL_SOURCES = {"k_gemm_ax": "nullspace.hip", "k_hetrd": "heev.hip",
                   "k_chol_inv": "nullspace.hip", "k_gemm_tn": "nullspace.hip",
                   "k_gemm_nn": "nullspace.hip", "k_herk": "gx.hip", "k_power": "eig.hip",
                   "k_gather": "gram.hip", "k_rss": "maps.hip"}

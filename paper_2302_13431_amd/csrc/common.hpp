@@ -155,15 +155,14 @@ struct NullWs {
   double2* H;      // [b][b] X^H Z
   double2* S;      // [b][b] Z^H Z
   double2* U;      // [b][b] Ritz vectors of H
-  double2* T;      // [b][b] scratch
-  double2* V;      // [b][b] scratch
   double2* M;      // [b][b] combined update
   double* theta;   // [b]
   double* lam;     // [b]
   double* resid;   // [b]
   double2* part;   // split-K partials
   int* ctl;        // [8] control words
-  double* jac;     // Jacobi scratch (global-memory fallback) [b*b*2]
+  double* jac;     // Cholesky scratch (global-memory fallback) [b*(b+1)*2]
+  double* heev;    // eigen-decomposition scratch [heev_workspace_doubles(b)]
 };
 size_t layout_null(const Plan& p, int b, void* ws, NullWs* out);
 
@@ -206,6 +205,13 @@ pisco_status_t run_eig(Handle* h, int Q, long long N, float bound, int iters,
                        int32_t* it_out);
 pisco_status_t run_maps(Handle* h, const Plan& p, int phase_rule, const float2* acs,
                         const float2* maps_lr, float2* maps_out, void* ws);
+
+// Eigen-decomposition H = U diag(theta) U^H of a b x b Hermitian matrix
+// (column-major, FP64), eigenvalues descending, 1 <= b <= 1024; `ws` holds
+// heev_workspace_doubles(b) doubles (device).
+size_t heev_workspace_doubles(int b);
+pisco_status_t run_heev(Handle* h, const double2* H, int b, double2* U, double* theta,
+                        double* ws);
 
 // Separable transform along one axis of a batched 3D array:
 //   out[b][..o..] = sum_i M[o][i] * in[b][..i..]

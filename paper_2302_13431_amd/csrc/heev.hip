@@ -1,0 +1,407 @@
+// Eigen-decomposition of the small Hermitian Rayleigh-Ritz matrix H = X^H A X
+// (order b, FP64) used by the signal/null split.
+//
+//   k_hetrd       one workgroup: Householder reduction H = Q T Q^H with T real
+//                 symmetric tridiagonal (each reflector H_k = I - tau_k v_k v_k^H
+//                 is chosen so that H_k^H maps the column below the diagonal
+//                 onto a real multiple of the first unit vector); the
+//                 reflectors are kept for the back-transformation.
+//   k_tri_eigval  one workgroup per eigenvalue: multisection on Sturm counts
+//                 (64 points per step), to about eps * ||T||.
+//   k_tri_vector  one workgroup per eigenvalue: the eigenvector of T by the
+//                 twisted factorisation; eigenvalues closer than 1e-12 ||T||
+//                 (and the rare vector whose residual is not small) go to
+//                 inverse iteration with Gram-Schmidt inside the cluster.  The
+//                 vector is then mapped back, u = Q z, by one wave holding its
+//                 rows in registers, and written in descending eigenvalue
+//                 order.
+//
+// Cost for b = 96: b - 1 reduction steps of four barriers each in LDS, then
+// independent per-eigenvalue work spread over b workgroups.  The former
+// one-sided Jacobi needed about seven sweeps of b - 1 barrier rounds for the
+// Rayleigh-Ritz matrices met here (far from diagonal).
+#include <cfloat>
+
+#include "common.hpp"
+#include "tridiag.hpp"
+
+namespace pisco {
+
+namespace {
+
+constexpr int kTrdLdsMax = 96;   // largest b reduced with the matrix in LDS
+constexpr int kTriMax = 1024;    // largest b of the tridiagonal kernels
+
+__device__ inline double wave_sum(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+__device__ inline double wave_max(double v) {
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+  return v;
+}
+__device__ inline double wave_min(double v) {
+  for (int off = 32; off > 0; off >>= 1) v = fmin(v, __shfl_xor(v, off, 64));
+  return v;
+}
+
+// ------------------------------------------------------------------ reduction
+
+// A (column-major b x b, Hermitian part of H) is reduced in place: in LDS for
+// b <= kTrdLdsMax, else in `gwork` (global, b*b).  Step k: wave 0 builds the
+// reflector from column k; the product x = tau A22 v is formed in column
+// slices (partial sums in LDS), wave 0 forms w = x - (tau/2)(x^H v) v, and
+// all threads apply A22 <- A22 - v w^H - w v^H, which equals H_k^H A22 H_k.
+template <bool kLds>
+__global__ void __launch_bounds__(1024) k_hetrd(const double2* __restrict__ H, int b,
+                                                double2* __restrict__ gwork,
+                                                double2* __restrict__ refl,
+                                                double2* __restrict__ tau_out,
+                                                double* __restrict__ d_out,
+                                                double* __restrict__ e_out) {
+  constexpr int kVec = kLds ? 128 : kTriMax;  // vector capacity
+  constexpr int kPR = kLds ? 128 : 256;       // product: row stride
+  constexpr int kPS = 4;                      // product: column slices
+  constexpr int kUR = kLds ? 128 : 256;       // update: row stride
+  constexpr int kUS = 1024 / kUR;             // update: column slices
+  __shared__ double2 lds_mat[kLds ? kTrdLdsMax * kTrdLdsMax : 1];
+  __shared__ double2 part[kPS][kVec];
+  __shared__ double2 vs[kVec], ws[kVec];
+  __shared__ double2 sh_tau;
+  double2* A = kLds ? lds_mat : gwork;
+  const int t = threadIdx.x;
+  for (int e = t; e < b * b; e += 1024) {
+    const int i = e % b, j = e / b;
+    const double2 x = H[e], y = H[size_t(i) * b + j];
+    A[e] = make_double2(0.5 * (x.x + y.x), 0.5 * (x.y - y.y));
+  }
+  __syncthreads();
+  for (int k = 0; k + 1 < b; ++k) {
+    const int m = b - k - 1;
+    const double2* colk = A + size_t(k) * b + (k + 1);
+    if (t < 64) {
+      double s = 0.0;
+      for (int i = 1 + t; i < m; i += 64) s += zabs2(colk[i]);
+      s = wave_sum(s);
+      const double2 al = colk[0];
+      double2 tau = make_double2(0.0, 0.0), scale = make_double2(0.0, 0.0);
+      double beta = al.x;
+      if (s > 0.0 || al.y != 0.0) {
+        const double nrm = sqrt(zabs2(al) + s);
+        beta = al.x >= 0.0 ? -nrm : nrm;
+        tau = make_double2((beta - al.x) / beta, -al.y / beta);
+        const double2 den = make_double2(al.x - beta, al.y);  // |den| >= nrm
+        const double inv = 1.0 / zabs2(den);
+        scale = make_double2(den.x * inv, -den.y * inv);
+      }
+      for (int i = t; i < m; i += 64) {
+        const double2 v = i == 0 ? make_double2(1.0, 0.0) : zmul(colk[i], scale);
+        vs[i] = v;
+        refl[size_t(k) * b + k + 1 + i] = v;
+      }
+      if (t == 0) {
+        sh_tau = tau;
+        tau_out[k] = tau;
+        e_out[k] = beta;
+        d_out[k] = A[size_t(k) * b + k].x;
+      }
+    }
+    __syncthreads();
+    const double2 tau = sh_tau;
+    double2* a22 = A + size_t(k + 1) * b + (k + 1);  // A22(i, j) = a22[j * b + i]
+    {
+      const int i0 = t % kPR, sl = t / kPR;
+      if (sl < kPS) {
+        for (int i = i0; i < m; i += kPR) {
+          double2 acc = make_double2(0.0, 0.0);
+          for (int j = sl; j < m; j += kPS) {
+            const double2 a = a22[size_t(j) * b + i], v = vs[j];
+            acc.x += a.x * v.x - a.y * v.y;
+            acc.y += a.x * v.y + a.y * v.x;
+          }
+          part[sl][i] = acc;
+        }
+      }
+    }
+    __syncthreads();
+    if (t < 64) {
+      double dr = 0.0, di = 0.0;  // x^H v
+      for (int i = t; i < m; i += 64) {
+        double2 x = part[0][i];
+#pragma unroll
+        for (int q = 1; q < kPS; ++q) x = zadd(x, part[q][i]);
+        x = zmul(tau, x);
+        part[0][i] = x;
+        const double2 v = vs[i];
+        dr += x.x * v.x + x.y * v.y;
+        di += x.x * v.y - x.y * v.x;
+      }
+      dr = wave_sum(dr);
+      di = wave_sum(di);
+      const double2 ap = zmul(make_double2(-0.5 * tau.x, -0.5 * tau.y), make_double2(dr, di));
+      for (int i = t; i < m; i += 64) ws[i] = zadd(part[0][i], zmul(ap, vs[i]));
+    }
+    __syncthreads();
+    {
+      const int i0 = t % kUR, sl = t / kUR;
+      for (int i = i0; i < m; i += kUR) {
+        const double2 vi = vs[i], wi = ws[i];
+        for (int j = sl; j < m; j += kUS) {
+          const double2 vj = vs[j], wj = ws[j];
+          double2 a = a22[size_t(j) * b + i];
+          a.x -= vi.x * wj.x + vi.y * wj.y + wi.x * vj.x + wi.y * vj.y;
+          a.y -= vi.y * wj.x - vi.x * wj.y + wi.y * vj.x - wi.x * vj.y;
+          a22[size_t(j) * b + i] = a;
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    d_out[b - 1] = A[size_t(b - 1) * b + (b - 1)].x;
+    if (b >= 1) e_out[b - 1] = 0.0;
+  }
+}
+
+// ------------------------------------------------------------------ eigenvalues
+
+// Eigenvalue j (ascending, 0-based) of T by multisection: each of the 64
+// lanes takes the Sturm count at one of 64 interior points of the bracket.
+__global__ void __launch_bounds__(64) k_tri_eigval(const double* __restrict__ d,
+                                                   const double* __restrict__ e, int b,
+                                                   double* __restrict__ lam) {
+  __shared__ double sd[kTriMax], se2[kTriMax];
+  const int t = threadIdx.x, j = blockIdx.x;
+  double glo = INFINITY, ghi = -INFINITY, emax2 = 0.0;
+  for (int i = t; i < b; i += 64) {
+    const double di = d[i];
+    const double el = i > 0 ? e[i - 1] : 0.0, er = i + 1 < b ? e[i] : 0.0;
+    sd[i] = di;
+    se2[i] = er * er;
+    emax2 = fmax(emax2, er * er);
+    const double r = fabs(el) + fabs(er);
+    glo = fmin(glo, di - r);
+    ghi = fmax(ghi, di + r);
+  }
+  glo = wave_min(glo);
+  ghi = wave_max(ghi);
+  emax2 = wave_max(emax2);
+  __syncthreads();
+  const double pivmin = DBL_MIN * fmax(1.0, emax2);
+  const double wide = 2.0 * DBL_EPSILON * fmax(fabs(glo), fabs(ghi)) + 2.0 * pivmin;
+  double lo = glo - wide, hi = ghi + wide;
+  for (int it = 0; it < 64; ++it) {
+    const double w = hi - lo;
+    if (!(w > 2.0 * DBL_EPSILON * fmax(fabs(lo), fabs(hi)) + 4.0 * pivmin)) break;
+    const double x = lo + w * (double(t + 1) / 65.0);
+    const int c = tri::negcount(sd, se2, b, x, pivmin);
+    const unsigned long long mask = __ballot(c > j);
+    double nlo, nhi;
+    if (mask == 0ull) {
+      nlo = __shfl(x, 63, 64);
+      nhi = hi;
+    } else {
+      const int l = __builtin_ctzll(mask);
+      nhi = __shfl(x, l, 64);
+      const double xl = __shfl(x, l > 0 ? l - 1 : 0, 64);
+      nlo = l > 0 ? xl : lo;
+    }
+    if (nlo == lo && nhi == hi) break;
+    lo = nlo;
+    hi = nhi;
+  }
+  if (t == 0) lam[j] = 0.5 * (lo + hi);
+}
+
+// ------------------------------------------------------------------ eigenvectors
+
+// z <- z / ||z||_2 over the b entries in LDS (wave 0 only), scaled by the
+// largest magnitude first so that no square overflows.
+__device__ void wave_normalize(double* z, int b) {
+  const int t = threadIdx.x;
+  double mx = 0.0;
+  for (int i = t; i < b; i += 64) mx = fmax(mx, fabs(z[i]));
+  mx = wave_max(mx);
+  const double s1 = mx > 0.0 ? 1.0 / mx : 1.0;
+  double ss = 0.0;
+  for (int i = t; i < b; i += 64) {
+    const double v = z[i] * s1;
+    ss += v * v;
+  }
+  ss = wave_sum(ss);
+  const double s2 = ss > 0.0 ? s1 / sqrt(ss) : 0.0;
+  for (int i = t; i < b; i += 64) z[i] *= s2;
+  __syncthreads();
+}
+
+// u = Q z for the real tridiagonal eigenvector z (LDS), written as column
+// `col` of U (b x b column-major).  Lane t keeps rows t + 64 q in registers;
+// the reflectors are applied last to first.
+template <int kPL>
+__device__ void back_transform(const double* z, int b, const double2* __restrict__ refl,
+                               const double2* __restrict__ tau, double2* __restrict__ U,
+                               int col) {
+  const int t = threadIdx.x;
+  double2 u[kPL];
+#pragma unroll
+  for (int q = 0; q < kPL; ++q) {
+    const int r = t + 64 * q;
+    u[q] = make_double2(r < b ? z[r] : 0.0, 0.0);
+  }
+  for (int k = b - 2; k >= 0; --k) {
+    const double2 tk = tau[k];
+    if (tk.x == 0.0 && tk.y == 0.0) continue;
+    const double2* v = refl + size_t(k) * b;
+    double2 vq[kPL];
+    double sr = 0.0, si = 0.0;  // v^H u
+#pragma unroll
+    for (int q = 0; q < kPL; ++q) {
+      const int r = t + 64 * q;
+      vq[q] = (r > k && r < b) ? v[r] : make_double2(0.0, 0.0);
+      sr += vq[q].x * u[q].x + vq[q].y * u[q].y;
+      si += vq[q].x * u[q].y - vq[q].y * u[q].x;
+    }
+    sr = wave_sum(sr);
+    si = wave_sum(si);
+    const double2 ts = zmul(tk, make_double2(sr, si));
+#pragma unroll
+    for (int q = 0; q < kPL; ++q) u[q] = zsub(u[q], zmul(vq[q], ts));
+  }
+#pragma unroll
+  for (int q = 0; q < kPL; ++q) {
+    const int r = t + 64 * q;
+    if (r < b) U[size_t(col) * b + r] = u[q];
+  }
+}
+
+// One workgroup (one wave) per eigenvalue j.  Members of a cluster (gaps
+// below 1e-12 ||T||) are computed together by the cluster's first
+// workgroup; `zwork` (b x b, real) holds the cluster's finished vectors for
+// the Gram-Schmidt steps.  Output column c = b - 1 - j (descending order).
+template <int kPL>
+__global__ void __launch_bounds__(64) k_tri_vector(const double* __restrict__ d,
+                                                   const double* __restrict__ e,
+                                                   const double* __restrict__ lam, int b,
+                                                   const double2* __restrict__ refl,
+                                                   const double2* __restrict__ tau,
+                                                   double* __restrict__ zwork,
+                                                   double2* __restrict__ U,
+                                                   double* __restrict__ theta) {
+  constexpr int kN = 64 * kPL;
+  __shared__ double sd[kN], se[kN], sl[kN], z[kN];
+  __shared__ double w0[kN], w1[kN], w2[kN], w3[kN];
+  __shared__ int sw[kN];
+  __shared__ int bad;
+  const int t = threadIdx.x, j = blockIdx.x;
+  double emax2 = 0.0;
+  for (int i = t; i < b; i += 64) {
+    sd[i] = d[i];
+    const double ei = i + 1 < b ? e[i] : 0.0;
+    se[i] = ei;
+    emax2 = fmax(emax2, ei * ei);
+    sl[i] = lam[i];
+  }
+  emax2 = wave_max(emax2);
+  __syncthreads();
+  const double nrm = fmax(fabs(sl[0]), fabs(sl[b - 1]));
+  const double pivmin = DBL_MIN * fmax(1.0, emax2);
+  const double ctol = 1e-12 * nrm;
+  int cs = j, ce = j;
+  while (cs > 0 && sl[cs] - sl[cs - 1] <= ctol) --cs;
+  while (ce + 1 < b && sl[ce + 1] - sl[ce] <= ctol) ++ce;
+  if (cs != j) return;  // the cluster's first workgroup computes it
+  bool inverse = ce > cs;
+  if (!inverse) {
+    if (t == 0) tri::twisted_vector(sd, se, b, sl[j], pivmin, w0, w1, z);
+    __syncthreads();
+    // residual ||(T - lambda) z||_inf against a few ulps of ||T||
+    const double lj = sl[j];
+    double r = 0.0;
+    for (int i = t; i < b; i += 64) {
+      double v = (sd[i] - lj) * z[i];
+      if (i > 0) v += se[i - 1] * z[i - 1];
+      if (i + 1 < b) v += se[i] * z[i + 1];
+      r = fmax(r, fabs(v));
+    }
+    r = wave_max(r);
+    if (t == 0) bad = !(r <= 1e3 * b * DBL_EPSILON * nrm + pivmin);
+    __syncthreads();
+    inverse = bad != 0;
+    if (!inverse) {
+      if (t == 0) theta[b - 1 - j] = sl[j];
+      back_transform<kPL>(z, b, refl, tau, U, b - 1 - j);
+      return;
+    }
+  }
+  const double tiny = fmax(DBL_EPSILON * nrm, pivmin);
+  for (int q = cs; q <= ce; ++q) {
+    for (int i = t; i < b; i += 64) z[i] = tri::start_value(q, i);
+    if (t == 0) tri::lu_factor(sd, se, b, sl[q], tiny, w0, w1, w2, w3, sw);
+    __syncthreads();
+    for (int it = 0; it < 3; ++it) {
+      if (t == 0) tri::lu_solve(b, w0, w1, w2, w3, sw, z);
+      __syncthreads();
+      // classical Gram-Schmidt against the finished members, twice
+      for (int pass = 0; pass < 2; ++pass) {
+        for (int p = cs; p < q; ++p) {
+          const double* zp = zwork + size_t(p) * b;
+          double s = 0.0;
+          for (int i = t; i < b; i += 64) s += zp[i] * z[i];
+          s = wave_sum(s);
+          for (int i = t; i < b; i += 64) z[i] -= s * zp[i];
+          __syncthreads();
+        }
+      }
+      wave_normalize(z, b);
+    }
+    for (int i = t; i < b; i += 64) zwork[size_t(q) * b + i] = z[i];
+    __threadfence_block();
+    if (t == 0) theta[b - 1 - q] = sl[q];
+    back_transform<kPL>(z, b, refl, tau, U, b - 1 - q);
+    __syncthreads();
+  }
+}
+
+}  // namespace
+
+// Eigen-decomposition H = U diag(theta) U^H of the b x b Hermitian matrix H
+// (column-major), eigenvalues descending.  ws must hold
+// heev_workspace_doubles(b) doubles.
+size_t heev_workspace_doubles(int b) {
+  const size_t bb = size_t(b) * b;
+  // refl (complex b*b), reduction matrix when not in LDS (complex b*b),
+  // zwork (b*b), tau (complex b), d, e, lam (b each)
+  return 2 * bb + 2 * bb + bb + 2 * size_t(b) + 3 * size_t(b) + 64;
+}
+
+pisco_status_t run_heev(Handle* h, const double2* H, int b, double2* U, double* theta,
+                        double* ws) {
+  if (b < 1 || b > kTriMax) {
+    h->last_error = "heev: order out of range";
+    return PISCO_ERR_UNSUPPORTED;
+  }
+  const size_t bb = size_t(b) * b;
+  double2* refl = reinterpret_cast<double2*>(ws);
+  double2* gwork = refl + bb;
+  double* zwork = reinterpret_cast<double*>(gwork + bb);
+  double2* tau = reinterpret_cast<double2*>(zwork + bb);
+  double* d = reinterpret_cast<double*>(tau + b);
+  double* e = d + b;
+  double* lam = e + b;
+  if (b <= kTrdLdsMax)
+    PISCO_KERNEL(h, k_hetrd<true>, dim3(1), dim3(1024), 0, H, b, gwork, refl, tau, d, e);
+  else
+    PISCO_KERNEL(h, k_hetrd<false>, dim3(1), dim3(1024), 0, H, b, gwork, refl, tau, d, e);
+  PISCO_KERNEL(h, k_tri_eigval, dim3(b), dim3(64), 0, d, e, b, lam);
+  if (b <= 128)
+    PISCO_KERNEL(h, k_tri_vector<2>, dim3(b), dim3(64), 0, d, e, lam, b, refl, tau, zwork, U, theta);
+  else if (b <= 256)
+    PISCO_KERNEL(h, k_tri_vector<4>, dim3(b), dim3(64), 0, d, e, lam, b, refl, tau, zwork, U, theta);
+  else if (b <= 512)
+    PISCO_KERNEL(h, k_tri_vector<8>, dim3(b), dim3(64), 0, d, e, lam, b, refl, tau, zwork, U, theta);
+  else
+    PISCO_KERNEL(h, k_tri_vector<16>, dim3(b), dim3(64), 0, d, e, lam, b, refl, tau, zwork, U, theta);
+  return PISCO_OK;
+}
+
+}  // namespace pisco

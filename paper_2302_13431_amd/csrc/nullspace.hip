@@ -16,7 +16,7 @@
 // and, when the rate predicted from the Cholesky diagonal (about the
 // eigenvalues in orthogonal iteration) says the block has converged, a
 // Rayleigh-Ritz step
-//   H = X^H Z, eig(H) = U diag(theta) U^H     (one-sided Jacobi, PSD)
+//   H = X^H Z, eig(H) = U diag(theta) U^H     (tridiagonal route, heev.hip)
 //   W = X U (Ritz vectors), residual_k = ||Z U_k - theta_k W_k||
 // that stops the iteration once every Ritz pair up to the first one below
 // the threshold has a residual below 1e-10 theta_1 (otherwise the Ritz
@@ -200,170 +200,10 @@ __global__ void __launch_bounds__(256) k_gemm_nn(const double2* __restrict__ Pm,
     }
 }
 
-// ------------------------------------------------------------------ Jacobi
+// ------------------------------------------------------------------ Cholesky QR
 
-// One-sided (Hestenes) Jacobi on a Hermitian positive semidefinite b x b
-// matrix A (column-major).  Column pairs are rotated until all columns are
-// orthogonal: A V = U diag(s); for PSD A the s_k are its eigenvalues and the
-// normalised columns u_k its eigenvectors.  Output sorted by decreasing
-// eigenvalue.  One block of up to 1024 threads; the working copy lives in LDS
-// when kLds (b <= 96) and in `gwork` otherwise.  Pairs follow the round-robin
-// tournament ordering, so the b/2 rotations of a round touch disjoint columns.
-constexpr int kJacLdsMax = 96;
+constexpr int kCholLdsMax = 96;  // largest b factored with the matrix in LDS
 
-template <bool kLds>
-__global__ void __launch_bounds__(1024) k_jacobi(const double2* __restrict__ Ain, int b,
-                                                 double2* __restrict__ vec_out,
-                                                 double* __restrict__ val_out,
-                                                 double2* __restrict__ gwork,
-                                                 int max_sweeps, double junk_rel) {
-  __shared__ double2 lds_mat[kLds ? kJacLdsMax * kJacLdsMax : 1];
-  __shared__ double norms[1024];
-  __shared__ int rotated;
-  __shared__ double junk_sq;
-  double2* M = kLds ? lds_mat : gwork;
-  const int t = threadIdx.x, nt = blockDim.x;
-  const int bb = b * b;
-  for (int e = t; e < bb; e += nt) M[e] = Ain[e];
-  __syncthreads();
-  // squared column norms, tracked through the rotations; a pair whose two
-  // columns are both below junk_rel * max_k H_kk (far under the signal
-  // threshold) is never rotated: such columns only need to stay orthogonal
-  // to the signal ones, which the other pairs ensure
-  for (int k = t; k < b; k += nt) {
-    double s = 0.0;
-    for (int r = 0; r < b; ++r) s += zabs2(M[size_t(k) * b + r]);
-    norms[k] = s;
-  }
-  if (t == 0) {
-    double mx = 0.0;
-    for (int k = 0; k < b; ++k) mx = fmax(mx, M[size_t(k) * b + k].x);
-    junk_sq = (junk_rel * mx) * (junk_rel * mx);
-  }
-  __syncthreads();
-  const int npairs = b / 2;
-  int G = 64;
-  while (G > 1 && G * npairs > nt) G >>= 1;
-  const int pair = t / G, lane = t % G;
-  const bool active = pair < npairs;
-  const double tol = 1e-14;
-  for (int sweep = 0; sweep < max_sweeps; ++sweep) {
-    if (t == 0) rotated = 0;
-    __syncthreads();
-    for (int round = 0; round < b - 1; ++round) {
-      if (active) {
-        // tournament positions (pair, b-1-pair); position 0 is fixed
-        auto col_at = [&](int pos) { return pos == 0 ? 0 : ((pos - 1 + round) % (b - 1)) + 1; };
-        const int ci = col_at(pair), cj = col_at(b - 1 - pair);
-        const int i = ci < cj ? ci : cj, j = ci < cj ? cj : ci;
-        double2* hi = M + size_t(i) * b;
-        double2* hj = M + size_t(j) * b;
-        const bool skip = norms[i] < junk_sq && norms[j] < junk_sq;
-        // the pair's two columns are held in registers for the round
-        constexpr int SL = kLds ? 8 : 1;
-        double2 xr[SL], yr[SL];
-        double al = 0.0, be = 0.0, gr = 0.0, gim = 0.0;
-        if (skip) {
-        } else if (kLds) {
-#pragma unroll
-          for (int k = 0; k < SL; ++k) {
-            const int r = lane + k * G;
-            xr[k] = r < b ? hi[r] : make_double2(0.0, 0.0);
-            yr[k] = r < b ? hj[r] : make_double2(0.0, 0.0);
-            al += zabs2(xr[k]);
-            be += zabs2(yr[k]);
-            gr += xr[k].x * yr[k].x + xr[k].y * yr[k].y;
-            gim += xr[k].x * yr[k].y - xr[k].y * yr[k].x;
-          }
-        } else {
-          for (int r = lane; r < b; r += G) {
-            const double2 x = hi[r], y = hj[r];
-            al += zabs2(x);
-            be += zabs2(y);
-            gr += x.x * y.x + x.y * y.y;
-            gim += x.x * y.y - x.y * y.x;
-          }
-        }
-        for (int off = G >> 1; off > 0; off >>= 1) {
-          al += __shfl_xor(al, off, G);
-          be += __shfl_xor(be, off, G);
-          gr += __shfl_xor(gr, off, G);
-          gim += __shfl_xor(gim, off, G);
-        }
-        const double gabs = sqrt(gr * gr + gim * gim);
-        if (!skip && gabs > tol * sqrt(al * be) && gabs > 0.0) {
-          const double zeta = (be - al) / (2.0 * gabs);
-          const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-          const double c = 1.0 / sqrt(1.0 + tt * tt);
-          const double s = tt * c;
-          const double er = gr / gabs, ei = gim / gabs;  // e^{i phi}
-          // x' = c x - s e^{-i phi} y ;  y' = s e^{i phi} x + c y
-          if (kLds) {
-#pragma unroll
-            for (int k = 0; k < SL; ++k) {
-              const int r = lane + k * G;
-              if (r < b) {
-                const double2 x = xr[k], y = yr[k];
-                const double2 emy = make_double2(er * y.x + ei * y.y, er * y.y - ei * y.x);
-                const double2 epx = make_double2(er * x.x - ei * x.y, er * x.y + ei * x.x);
-                hi[r] = make_double2(c * x.x - s * emy.x, c * x.y - s * emy.y);
-                hj[r] = make_double2(s * epx.x + c * y.x, s * epx.y + c * y.y);
-              }
-            }
-          } else {
-            for (int r = lane; r < b; r += G) {
-              const double2 x = hi[r], y = hj[r];
-              const double2 emy = make_double2(er * y.x + ei * y.y, er * y.y - ei * y.x);
-              const double2 epx = make_double2(er * x.x - ei * x.y, er * x.y + ei * x.x);
-              hi[r] = make_double2(c * x.x - s * emy.x, c * x.y - s * emy.y);
-              hj[r] = make_double2(s * epx.x + c * y.x, s * epx.y + c * y.y);
-            }
-          }
-          if (lane == 0) {
-            rotated = 1;
-            norms[i] = al - tt * gabs;
-            norms[j] = be + tt * gabs;
-          }
-        } else if (!skip && lane == 0) {
-          norms[i] = al;
-          norms[j] = be;
-        }
-      }
-      __syncthreads();
-    }
-    const int any = rotated;
-    __syncthreads();
-    if (!any) break;
-  }
-  __syncthreads();
-  // eigenvalues = column norms; rank-sort descending (ties: lower index first)
-  for (int k = t; k < b; k += nt) {
-    double s = 0.0;
-    for (int r = 0; r < b; ++r) s += zabs2(M[size_t(k) * b + r]);
-    norms[k] = sqrt(s);
-  }
-  __syncthreads();
-  for (int k = t; k < b; k += nt) {
-    const double sk = norms[k];
-    int rank = 0;
-    for (int l = 0; l < b; ++l) {
-      const double sl = norms[l];
-      rank += (sl > sk) || (sl == sk && l < k);
-    }
-    val_out[rank] = sk;
-    const double inv = sk > 0.0 ? 1.0 / sk : 0.0;
-    for (int r = 0; r < b; ++r) {
-      double2 v = zscale(M[size_t(k) * b + r], inv);
-      if (sk == 0.0) v = make_double2(r == k ? 1.0 : 0.0, 0.0);
-      vec_out[size_t(rank) * b + r] = v;
-    }
-  }
-}
-
-// ------------------------------------------------------------------ small kernels
-
-// Cholesky QR factor: for a Hermitian positive definite S (b x b,
-// column-major) returns M = D R^{-1} with D = diag(S)^{-1/2} and R the upper
 // Cholesky factor of D S D + shift I, so that Y M has orthonormal columns
 // when S = Y^H Y (up to the shift).  One block; the working matrix is in LDS
 // when kLds (b <= 96) and in `gwork` otherwise.  A pivot that is not positive
@@ -377,8 +217,8 @@ __global__ void __launch_bounds__(1024) k_chol_inv(const double2* __restrict__ S
   // T is row-major with a padded leading dimension ld = b + 1, so that rows
   // are contiguous for the factorisation and the column walks of the inverse
   // spread over the LDS banks
-  __shared__ double2 lds_mat[kLds ? kJacLdsMax * (kJacLdsMax + 1) : 1];
-  __shared__ double dsc[kLds ? kJacLdsMax : 1024];
+  __shared__ double2 lds_mat[kLds ? kCholLdsMax * (kCholLdsMax + 1) : 1];
+  __shared__ double dsc[kLds ? kCholLdsMax : 1024];
   double2* T = kLds ? lds_mat : gwork;
   const int ld = b + 1;
   const int t = threadIdx.x, nt = blockDim.x;
@@ -459,8 +299,8 @@ __global__ void __launch_bounds__(1024) k_chol_inv(const double2* __restrict__ S
     // M(:, j) = D R^{-1} e_j by back substitution, one group of 8 lanes per
     // column j; entry l of the column lives in register slot l / 8 of lane
     // l % 8 and each step's dot product is a butterfly over the group.
-    constexpr int G = 8, SL = kJacLdsMax / G;
-    __shared__ double rinv[kJacLdsMax];
+    constexpr int G = 8, SL = kCholLdsMax / G;
+    __shared__ double rinv[kCholLdsMax];
     for (int i = t; i < b; i += nt) rinv[i] = 1.0 / T[size_t(i) * ld + i].x;
     __syncthreads();
     // column j of R^{-1} by a column-oriented back substitution: start from
@@ -655,21 +495,11 @@ pisco_status_t gemm_nn(NullCtx& c, const double2* P, const double2* M, double2* 
   return PISCO_OK;
 }
 
-pisco_status_t jacobi(NullCtx& c, const double2* A, double2* vecs, double* vals,
-                      double junk_rel) {
-  const int b = c.b;
-  if (b <= kJacLdsMax)
-    PISCO_KERNEL(c.h, k_jacobi<true>, dim3(1), dim3(1024), 0, A, b, vecs, vals, reinterpret_cast<double2*>(c.w.jac), 40, junk_rel);
-  else
-    PISCO_KERNEL(c.h, k_jacobi<false>, dim3(1), dim3(1024), 0, A, b, vecs, vals, reinterpret_cast<double2*>(c.w.jac), 40, junk_rel);
-  return PISCO_OK;
-}
-
 pisco_status_t chol_inv(NullCtx& c, const double2* S, double shift, double2* M,
                         double* rdiag = nullptr) {
   const int b = c.b;
   int* flag = c.w.ctl + 8;
-  if (b <= kJacLdsMax)
+  if (b <= kCholLdsMax)
     PISCO_KERNEL(c.h, k_chol_inv<true>, dim3(1), dim3(1024), 0, S, b, shift, M,
                  reinterpret_cast<double2*>(c.w.jac), flag, rdiag);
   else
@@ -769,7 +599,7 @@ pisco_status_t run_nullspace(Handle* h, const Plan& p, int b, int max_iters,
     }
     // Rayleigh-Ritz on span(X): H = X^H A X = U diag(theta) U^H
     if ((st = gemm_tn(c, X, Z, c.w.H, n))) return st;
-    if ((st = jacobi(c, c.w.H, c.w.U, c.w.theta, 0.0))) return st;
+    if ((st = run_heev(h, c.w.H, b, c.w.U, c.w.theta, c.w.heev))) return st;
     if ((st = gemm_nn(c, X, c.w.U, W, n, b))) return st;  // Ritz vectors
     if ((st = gemm_nn(c, Z, c.w.U, X, n, b))) return st;  // A * Ritz vectors
     double* rpart = reinterpret_cast<double*>(c.w.part);

@@ -106,8 +106,6 @@ size_t layout_null(const Plan& p, int b, void* ws, NullWs* o) {
   w.H = c.take<double2>(bb);
   w.S = c.take<double2>(bb);
   w.U = c.take<double2>(bb);
-  w.T = c.take<double2>(bb);
-  w.V = c.take<double2>(bb);
   w.M = c.take<double2>(bb);
   w.theta = c.take<double>(b);
   w.lam = c.take<double>(b);
@@ -120,6 +118,7 @@ size_t layout_null(const Plan& p, int b, void* ws, NullWs* o) {
   w.part = c.take<double2>(part);
   w.ctl = c.take<int>(16);
   w.jac = c.take<double>((size_t(b) + 1) * b * 2);
+  w.heev = c.take<double>(heev_workspace_doubles(b));
   if (o) *o = w;
   return c.used + 256;
 }

@@ -99,6 +99,41 @@ def test_nullspace(name):
     assert np.all(ev[rs:] < 0.05 ** 2 * ev[0]) and np.all(ev[:rs] >= 0.05 ** 2 * ev[0])
 
 
+def test_nullspace_repeated_eigenvalues():
+    """Gram with exactly repeated eigenvalues (a phase-permutation of a
+    diagonal, exact in FP32): the Rayleigh-Ritz matrices then have clusters
+    of equal eigenvalues, in the signal part and across the whole noise part
+    of the block.  The signal projector is unique and must match; the basis
+    must stay orthonormal."""
+    noise = 2.0 ** -10
+    name = "2d_64x64_q8_acs24_r3"
+    w = workloads.ALL[name]
+    est = estimator(name)
+    n = est.n
+    rng = np.random.default_rng(11)
+    vals = np.full(n, noise)
+    vals[:20] = [100.0] * 10 + [40.0] * 5 + [1.0] * 5
+    perm = rng.permutation(n)
+    phase = np.array([1, -1, 1j, -1j])[rng.integers(0, 4, n)]
+    Umat = np.zeros((n, n), complex)
+    Umat[perm, np.arange(n)] = phase
+    g = (Umat * vals) @ Umat.conj().T
+    g32 = g.astype(np.complex64)
+    assert np.array_equal(g32.astype(complex), g)
+    ev, basis, counts = est.nullspace(cuda(g32))
+    ev, basis, counts = ev.cpu().numpy(), basis.cpu().numpy(), counts.cpu().numpy()
+    rs = int(counts[0])
+    Vs = basis[:rs].T
+    Po = Umat[:, :20] @ Umat[:, :20].conj().T
+    e_proj = float(np.abs(Vs @ Vs.conj().T - Po).max())
+    e_orth = float(np.abs(basis.conj() @ basis.T - np.eye(len(basis))).max())
+    e_eig = float(np.abs(ev[:21] - np.sort(vals)[::-1][:21]).max() / 100.0)
+    report("nullspace repeated", r=rs, iters=int(counts[2]), err_eig=e_eig,
+           err_proj=e_proj, err_orth=e_orth)
+    assert counts[3] == 1 and rs == 20
+    assert e_eig <= 1e-12 and e_proj <= 1e-10 and e_orth <= 1e-10
+
+
 # ------------------------------------------------------------------ G(x)
 
 
