@@ -203,165 +203,180 @@ __global__ void __launch_bounds__(256) k_gemm_nn(const double2* __restrict__ Pm,
 // ------------------------------------------------------------------ Cholesky QR
 
 constexpr int kCholLdsMax = 96;  // largest b factored with the matrix in LDS
+constexpr int kCholThreads = 512;
 
-// Cholesky factor of D S D + shift I, so that Y M has orthonormal columns
-// when S = Y^H Y (up to the shift).  One block; the working matrix is in LDS
-// when kLds (b <= 96) and in `gwork` otherwise.  A pivot that is not positive
-// is replaced by a tiny one and reported through *flag.
+// Cholesky factor of D S D + shift I (D = diag(S)^{-1/2}) and M = D R^{-1},
+// so that Y M has orthonormal columns when S = Y^H Y (up to the shift).  One
+// workgroup; the working matrix T (row-major, ld = b + 1 so that column
+// walks spread over the LDS banks) is in LDS when kLds (b <= 96) and in
+// `gwork` otherwise.  A pivot that is not positive is replaced by a tiny
+// one and reported through *flag.
+//
+// Blocked in panels of kNB = 8 columns (b must be a multiple).  Per panel
+// J: (a) one wave factors the diagonal block, lane j holding column j in
+// registers (pivot rows are broadcast with readlane), then inverts it,
+// X_JJ = R_JJ^{-1}, lane c forming column c, and stores X_JJ in place of
+// R_JJ (R_JJ itself is not needed again); (b) the panel row
+// R_J,j = X_JJ^H T_J,j for all later columns; (c) the trailing update
+// T_ij -= R_Ji^H R_Jj.  Then R^{-1} is formed in place block column by block
+// column: X_IJ = -(sum_K X_IK R_KJ) X_JJ, the partial sums staged in the
+// unused strict lower triangle.  Phase (a) runs on one wave and is bound by
+// its instruction count, which grows with b times the panel width; narrow
+// panels keep it short at the price of more barriers in the other phases.
+__device__ inline double readlane_f64(double v, int lane) {
+  const long long x = __double_as_longlong(v);
+  const unsigned lo = __builtin_amdgcn_readlane(int(x), lane);
+  const unsigned hi = __builtin_amdgcn_readlane(int(x >> 32), lane);
+  return __longlong_as_double((static_cast<long long>(hi) << 32) | lo);
+}
+
 template <bool kLds>
-__global__ void __launch_bounds__(1024) k_chol_inv(const double2* __restrict__ S, int b,
+__global__ void __launch_bounds__(kCholThreads) k_chol_inv(const double2* __restrict__ S, int b,
                                                    double shift, double2* __restrict__ M,
                                                    double2* __restrict__ gwork,
                                                    int* __restrict__ flag,
                                                    double* __restrict__ rdiag) {
-  // T is row-major with a padded leading dimension ld = b + 1, so that rows
-  // are contiguous for the factorisation and the column walks of the inverse
-  // spread over the LDS banks
+  constexpr int kNB = 8;                        // panel width (b is a multiple)
+  constexpr int kNT = kCholThreads;
+  constexpr int kOut = kLds ? 3 : 32;           // panel outputs per thread
   __shared__ double2 lds_mat[kLds ? kCholLdsMax * (kCholLdsMax + 1) : 1];
   __shared__ double dsc[kLds ? kCholLdsMax : 1024];
   double2* T = kLds ? lds_mat : gwork;
   const int ld = b + 1;
-  const int t = threadIdx.x, nt = blockDim.x;
-  for (int k = t; k < b; k += nt) {
+  const int t = threadIdx.x;
+  auto at = [&](int i, int j) -> double2& { return T[i * ld + j]; };
+  for (int k = t; k < b; k += kNT) {
     const double d = S[size_t(k) * b + k].x;
     dsc[k] = d > 0.0 ? 1.0 / sqrt(d) : 0.0;
   }
   __syncthreads();
-  for (int e = t; e < b * b; e += nt) {
+  for (int e = t; e < b * b; e += kNT) {
     const int i = e % b, j = e / b;  // S is column-major: e = j b + i
+    if (j < i) continue;
     double2 v = zscale(S[e], dsc[i] * dsc[j]);
     if (i == j) v = make_double2(v.x + shift, 0.0);
-    T[size_t(i) * ld + j] = v;
+    at(i, j) = v;
   }
   __syncthreads();
-  // blocked right-looking Cholesky on the upper triangle, T = R^H R, with
-  // panels of kPW columns: (a) the first wave factors the diagonal block
-  // (wave-level ordering only), (b) each remaining column solves the panel's
-  // triangular system, (c) all threads apply the rank-kPW trailing update.
-  constexpr int kPW = 16;
-  __shared__ double dinv[kPW];
-  for (int k0 = 0; k0 < b; k0 += kPW) {
-    const int k1 = k0 + kPW < b ? k0 + kPW : b;
+  for (int k0 = 0; k0 < b; k0 += kNB) {
+    const int w = kNB;
+    const int k1 = k0 + w;
+    // (a) wave 0: factor and invert the diagonal block (every loop bound is
+    // a constant).  Lane t keeps column t % kNB in registers; rows below the
+    // diagonal are carried along but never used, which keeps the code free
+    // of per-lane branches.  The pivot row is broadcast with readlane.  Then
+    // lane t forms column t % kNB of X = R^{-1} by back substitution (R_il is
+    // lane l's entry i, again by readlane), and X is stored in place of R.
     if (t < 64) {
-      for (int k = k0; k < k1; ++k) {
-        double2* rk = T + size_t(k) * ld;
-        double dk = rk[k].x;
-        if (!(dk > 1e-300)) {
-          if (t == 0) *flag = 1;
-          dk = 1e-300;
-        }
+      // tc goes through an empty asm statement so that the compiler cannot
+      // hoist per-lane constants of this phase out of the panel loop
+      int tc = t & (kNB - 1);
+      asm volatile("" : "+v"(tc));
+      double2 c[kNB];
+#pragma unroll
+      for (int i = 0; i < kNB; ++i) c[i] = at(k0 + i, k0 + tc);
+#pragma unroll
+      for (int kk = 0; kk < kNB; ++kk) {
+        double dk = readlane_f64(c[kk].x, kk);
+        const bool bad = !(dk > 1e-300);
+        dk = bad ? 1e-300 : dk;
         const double r = sqrt(dk), rinv = 1.0 / r;
-        // diagonal of the unscaled factor (R' D^-1): converges to the
-        // eigenvalue magnitudes in orthogonal iteration
-        if (rdiag && t == 0) rdiag[k] = dsc[k] > 0.0 ? r / dsc[k] : 0.0;
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        if (t < k1 - k) rk[k + t] = t == 0 ? make_double2(r, 0.0) : zscale(rk[k + t], rinv);
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        // update the rest of the diagonal block: rows i in (k, k1), j >= i
-        const int m = k1 - k - 1;
-        for (int e = t; e < m * m; e += 64) {
-          const int i = k + 1 + e / m, j = k + 1 + e % m;
-          if (j >= i)
-            T[size_t(i) * ld + j] = zsub(T[size_t(i) * ld + j], zmulc(rk[i], rk[j]));
+        if (t == 0) {
+          if (bad) *flag = 1;
+          // diagonal of the unscaled factor (R' D^-1): converges to the
+          // eigenvalue magnitudes in orthogonal iteration
+          if (rdiag) rdiag[k0 + kk] = dsc[k0 + kk] > 0.0 ? r / dsc[k0 + kk] : 0.0;
         }
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-      }
-    }
-    __syncthreads();
-    for (int k = k0 + t; k < k1; k += nt) dinv[k - k0] = 1.0 / T[size_t(k) * ld + k].x;
-    __syncthreads();
-    // (b) R_{k0:k1, j} = R_pp^{-H} T_{k0:k1, j} for every column j >= k1
-    for (int j = k1 + t; j < b; j += nt) {
-      for (int k = k0; k < k1; ++k) {
-        double2 acc = T[size_t(k) * ld + j];
-        for (int l = k0; l < k; ++l)
-          acc = zsub(acc, zmulc(T[size_t(l) * ld + k], T[size_t(l) * ld + j]));
-        T[size_t(k) * ld + j] = zscale(acc, dinv[k - k0]);
-      }
-    }
-    __syncthreads();
-    // (c) T_{i,j} -= sum_{l in panel} conj(R_{l,i}) R_{l,j},  k1 <= i <= j
-    const int m = b - k1;
-    for (int e = t; e < m * m; e += nt) {
-      const int i = k1 + e / m, j = k1 + e % m;
-      if (j < i) continue;
-      double2 acc = T[size_t(i) * ld + j];
-      for (int l = k0; l < k1; ++l)
-        acc = zsub(acc, zmulc(T[size_t(l) * ld + i], T[size_t(l) * ld + j]));
-      T[size_t(i) * ld + j] = acc;
-    }
-    __syncthreads();
-  }
-  if (kLds) {
-    // M(:, j) = D R^{-1} e_j by back substitution, one group of 8 lanes per
-    // column j; entry l of the column lives in register slot l / 8 of lane
-    // l % 8 and each step's dot product is a butterfly over the group.
-    constexpr int G = 8, SL = kCholLdsMax / G;
-    __shared__ double rinv[kCholLdsMax];
-    for (int i = t; i < b; i += nt) rinv[i] = 1.0 / T[size_t(i) * ld + i].x;
-    __syncthreads();
-    // column j of R^{-1} by a column-oriented back substitution: start from
-    // e_j, and for i = j, j-1, ..., 0 scale entry i by 1/R_ii, broadcast it
-    // to the group and subtract its multiple of column i of R from the
-    // entries above it.  No reductions; one broadcast per step.
-    const int j = t / G, lane = t % G;
-    double2 mreg[SL];
+        const double2 ck = tc == kk ? make_double2(r, 0.0) : zscale(c[kk], rinv);
+        c[kk] = ck;
 #pragma unroll
-    for (int k = 0; k < SL; ++k) {
-      const int l = lane + k * G;
-      mreg[k] = make_double2(l == j ? 1.0 : 0.0, 0.0);
-    }
-    if (j < b) {
-      for (int i = j; i >= 0; --i) {
-        // owner of entry i scales it; everyone reads it
-        double2 mi = make_double2(0.0, 0.0);
-#pragma unroll
-        for (int k = 0; k < SL; ++k)
-          if (k == i / G) mi = mreg[k];
-        mi = zscale(mi, rinv[i]);
-        const int src = (t & ~(G - 1)) + (i % G);
-        mi.x = __shfl(mi.x, src, 64);
-        mi.y = __shfl(mi.y, src, 64);
-#pragma unroll
-        for (int k = 0; k < SL; ++k) {
-          const int l = lane + k * G;
-          if (l == i) mreg[k] = mi;
-          else if (l < i) mreg[k] = zsub(mreg[k], zmul(T[size_t(l) * ld + i], mi));
+        for (int i = kk + 1; i < kNB; ++i) {
+          const double2 rki = make_double2(readlane_f64(ck.x, i), readlane_f64(ck.y, i));
+          c[i] = zsub(c[i], zmulc(rki, ck));
         }
       }
+      double2 x[kNB];
 #pragma unroll
-      for (int k = 0; k < SL; ++k) {
-        const int l = lane + k * G;
-        if (l < b)
-          M[size_t(j) * b + l] = l <= j ? zscale(mreg[k], dsc[l]) : make_double2(0.0, 0.0);
+      for (int i = kNB - 1; i >= 0; --i) {
+        const double dinv = 1.0 / readlane_f64(c[i].x, i);
+        double2 acc = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int l = i + 1; l < kNB; ++l) {
+          const double2 ril = make_double2(readlane_f64(c[i].x, l), readlane_f64(c[i].y, l));
+          acc = zadd(acc, zmul(ril, x[l]));
+        }
+        const double2 xi = i == tc ? make_double2(dinv, 0.0) : zscale(acc, -dinv);
+        x[i] = i <= tc ? xi : make_double2(0.0, 0.0);
+      }
+      if (t < kNB) {
+#pragma unroll
+        for (int i = 0; i < kNB; ++i)
+          if (i <= t) at(k0 + i, k0 + t) = x[i];
       }
     }
-    return;
-  }
-  // global-memory variant: in-place inverse of the upper triangle, column by
-  // column (with the leading j x j block already inverted, column j of R^{-1}
-  // is -(R^{-1})_{0:j,0:j} R_{0:j,j} / R_jj, and 1 / R_jj on the diagonal)
-  __shared__ double2 xcol[kLds ? 1 : 1024];
-  for (int j = 0; j < b; ++j) {
-    for (int i = t; i < j; i += nt) xcol[i] = T[size_t(i) * ld + j];
     __syncthreads();
-    const double inv_jj = 1.0 / T[size_t(j) * ld + j].x;
-    for (int i = t; i < j; i += nt) {
+    if (k1 < b) {
+      // (b) R[k0+r][j] = sum_{l <= r} conj(X_lr) T[k0+l][j] for j >= k1
+      const int nc = b - k1, nout = w * nc;
+      double2 res[kOut];
+#pragma unroll
+      for (int q = 0; q < kOut; ++q) {
+        const int o = t + kNT * q;
+        res[q] = make_double2(0.0, 0.0);
+        if (o < nout) {
+          const int r = o / nc, j = k1 + o % nc;
+          double2 acc = make_double2(0.0, 0.0);
+          for (int l = 0; l <= r; ++l) acc = zadd(acc, zmulc(at(k0 + l, k0 + r), at(k0 + l, j)));
+          res[q] = acc;
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < kOut; ++q) {
+        const int o = t + kNT * q;
+        if (o < nout) at(k0 + o / nc, k1 + o % nc) = res[q];
+      }
+      __syncthreads();
+      // (c) T_ij -= sum_{l in panel} conj(R_li) R_lj for k1 <= i <= j
+      for (int i = k1 + (t >> 6); i < b; i += kNT / 64) {
+        for (int j = i + (t & 63); j < b; j += 64) {
+          double2 acc = at(i, j);
+          for (int l = k0; l < k1; ++l) acc = zsub(acc, zmulc(at(l, i), at(l, j)));
+          at(i, j) = acc;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  // R^{-1} in place, block column J = [k0, k1) for k0 >= 16: P_i,c =
+  // sum_{l = i .. k0-1} X_il R_l,k0+c (staged at (k0+c, i)), then
+  // X_i,k0+c = -sum_{l <= c} P_i,l (X_JJ)_l,c.
+  for (int k0 = kNB; k0 < b; k0 += kNB) {
+    constexpr int w = kNB;
+    for (int o = t; o < k0 * w; o += kNT) {
+      const int i = o / w, c = o % w;
+      double2 a0 = make_double2(0.0, 0.0), a1 = make_double2(0.0, 0.0);
+      int l = i;
+      for (; l + 1 < k0; l += 2) {
+        a0 = zadd(a0, zmul(at(i, l), at(l, k0 + c)));
+        a1 = zadd(a1, zmul(at(i, l + 1), at(l + 1, k0 + c)));
+      }
+      if (l < k0) a0 = zadd(a0, zmul(at(i, l), at(l, k0 + c)));
+      at(k0 + c, i) = zadd(a0, a1);
+    }
+    __syncthreads();
+    for (int o = t; o < k0 * w; o += kNT) {
+      const int i = o / w, c = o % w;
       double2 acc = make_double2(0.0, 0.0);
-      for (int l = i; l < j; ++l) acc = zadd(acc, zmul(T[size_t(i) * ld + l], xcol[l]));
-      T[size_t(i) * ld + j] = zscale(acc, -inv_jj);
+      for (int l = 0; l <= c; ++l) acc = zadd(acc, zmul(at(k0 + l, i), at(k0 + l, k0 + c)));
+      at(i, k0 + c) = make_double2(-acc.x, -acc.y);
     }
     __syncthreads();
-    if (t == 0) T[size_t(j) * ld + j] = make_double2(inv_jj, 0.0);
   }
-  __syncthreads();
   // M = D R^{-1} (rows scaled), column-major, zero below the diagonal
-  for (int e = t; e < b * b; e += nt) {
+  for (int e = t; e < b * b; e += kNT) {
     const int i = e % b, j = e / b;
-    M[e] = i <= j ? zscale(T[size_t(i) * ld + j], dsc[i]) : make_double2(0.0, 0.0);
+    M[e] = i <= j ? zscale(at(i, j), dsc[i]) : make_double2(0.0, 0.0);
   }
 }
 
@@ -498,32 +513,31 @@ pisco_status_t gemm_nn(NullCtx& c, const double2* P, const double2* M, double2* 
 pisco_status_t chol_inv(NullCtx& c, const double2* S, double shift, double2* M,
                         double* rdiag = nullptr) {
   const int b = c.b;
+  if (b % 8 != 0) {
+    c.h->last_error = "nullspace: block size must be a multiple of 8";
+    return PISCO_ERR_UNSUPPORTED;
+  }
   int* flag = c.w.ctl + 8;
   if (b <= kCholLdsMax)
-    PISCO_KERNEL(c.h, k_chol_inv<true>, dim3(1), dim3(1024), 0, S, b, shift, M,
+    PISCO_KERNEL(c.h, k_chol_inv<true>, dim3(1), dim3(kCholThreads), 0, S, b, shift, M,
                  reinterpret_cast<double2*>(c.w.jac), flag, rdiag);
   else
-    PISCO_KERNEL(c.h, k_chol_inv<false>, dim3(1), dim3(1024), 0, S, b, shift, M,
+    PISCO_KERNEL(c.h, k_chol_inv<false>, dim3(1), dim3(kCholThreads), 0, S, b, shift, M,
                  reinterpret_cast<double2*>(c.w.jac), flag, rdiag);
   return PISCO_OK;
 }
 
-// Orthonormalise the columns of Y (n x b) by Cholesky QR with column scaling
-// (the first pass with a tiny diagonal shift against breakdown).  Two passes
-// (result back in Y, `tmp` is scratch) while the columns may be nearly
-// dependent; one pass (result in `tmp`) once they are close to orthogonal
-// after scaling, where a single pass is already accurate to rounding.
-pisco_status_t orth(NullCtx& c, double2* Y, double2* tmp, double* rdiag = nullptr,
-                    int passes = 2) {
+// Orthonormalise the columns of Y (n x b) by one Cholesky QR pass with
+// column scaling, the result in `tmp`.  `shift` (relative to the scaled
+// diagonal) keeps the factorisation from breaking down on the first
+// product, whose columns may be nearly dependent; a block that is not yet
+// orthonormal to rounding is fine there, the next products correct it.
+pisco_status_t orth(NullCtx& c, const double2* Y, double2* tmp, double* rdiag, double shift) {
   const int n = c.p->n, b = c.b;
   pisco_status_t st;
   if ((st = gemm_tn(c, Y, Y, c.w.S, n))) return st;
-  if ((st = chol_inv(c, c.w.S, passes == 2 ? 1e-12 : 0.0, c.w.M, rdiag))) return st;
-  if ((st = gemm_nn(c, Y, c.w.M, tmp, n, b))) return st;
-  if (passes == 1) return PISCO_OK;
-  if ((st = gemm_tn(c, tmp, tmp, c.w.S, n))) return st;
-  if ((st = chol_inv(c, c.w.S, 0.0, c.w.M))) return st;
-  return gemm_nn(c, tmp, c.w.M, Y, n, b);
+  if ((st = chol_inv(c, c.w.S, shift, c.w.M, rdiag))) return st;
+  return gemm_nn(c, Y, c.w.M, tmp, n, b);
 }
 
 }  // namespace
@@ -540,11 +554,10 @@ pisco_status_t run_nullspace(Handle* h, const Plan& p, int b, int max_iters,
   double2* X = c.w.X;  // current orthonormal block
   double2* Z = c.w.Z;  // A X
 
+  // random start block; its columns need not be orthonormal, since the
+  // first product is orthonormalised before any Rayleigh-Ritz step
   PISCO_KERNEL(h, k_init_block, dim3(ceil_div(nb, 256)), dim3(256), 0, X, n, b);
-  // a random block is well conditioned: one Cholesky QR pass
-  pisco_status_t st = orth(c, X, Z, nullptr, 1);
-  if (st) return st;
-  std::swap(X, Z);
+  pisco_status_t st = PISCO_OK;
 
   const double thr2 = double(p.thresh) * double(p.thresh);
   const double tol = 1e-10;
@@ -583,9 +596,8 @@ pisco_status_t run_nullspace(Handle* h, const Plan& p, int b, int max_iters,
         ++done;
       }
       const bool predict = done == 3 && rr_at == kUnscheduled;
-      const int passes = done == 1 ? 2 : 1;
-      if ((st = orth(c, Z, X, predict ? c.w.resid : nullptr, passes))) return st;
-      if (passes == 2) std::swap(X, Z);  // two passes leave the result in Z
+      if ((st = orth(c, Z, X, predict ? c.w.resid : nullptr, done == 1 ? 1e-12 : 0.0)))
+        return st;
       if (predict) {
         PISCO_KERNEL(h, k_predict, dim3(1), dim3(64), 0, c.w.resid, b, thr2, tol, done,
                      c.w.ctl);
@@ -616,7 +628,7 @@ pisco_status_t run_nullspace(Handle* h, const Plan& p, int b, int max_iters,
     if (done >= max_iters) break;
     rr_at = done + hc[5];
     // next block: orth(A * Ritz vectors) (held in X; nearly orthogonal columns)
-    if ((st = orth(c, X, Z, nullptr, 1))) return st;
+    if ((st = orth(c, X, Z, nullptr, 0.0))) return st;
     std::swap(X, Z);
   }
   PISCO_KERNEL(h, k_finalize, dim3(ceil_div(nb > b ? nb : b, 256)), dim3(256), 0, W, c.w.theta, c.w.ctl, basis, eigvals, counts, nb, b, h->status_dev);
