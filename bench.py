@@ -33,7 +33,8 @@ BLOCKS = {"2d_64x64_q8_acs24_r3": 64, "2d_256x256_q32_acs32_r5": 96,
 
 PEAKS = {  # MI355X datasheet, dense
     "hbm": (8000.0, "GB/s"),
-    "fp64": (78.6, "TFLOP/s"),
+    "fp64": (78.6, "TFLOP/s"),        # vector FP64
+    "mfma_fp64": (78.6, "TFLOP/s"),   # FP64 matrix cores
     "fp32": (157.3, "TFLOP/s"),
 }
 
@@ -42,7 +43,7 @@ def kernel_model(name: str, w, est, rs: int):
     """(bound, algorithmic work per launch, unit) of a kernel, or None.
 
     Work per unit (the method's own need, not what the kernel happens to do):
-      k_gemm_ax  Gram x block, complex FP64:         8 n^2 b flops
+      k_gemm_ax  Gram x block, complex FP64 (matrix cores): 8 n^2 b flops
       k_hetrd    Householder tridiagonalisation, order b, complex:
                  16/3 b^3 flops (4/3 b^3 real multiply-adds, x4 for complex)
       k_chol_inv Cholesky + triangular inverse, order b: 8/3 b^3 + 4/3 b^3 flops
@@ -53,7 +54,7 @@ def kernel_model(name: str, w, est, rs: int):
     """
     n, b, Q = est.n, est.block, est.Q
     if name.startswith("k_gemm_ax"):
-        return "fp64", 8.0 * n * n * b, "flop"
+        return "mfma_fp64", 8.0 * n * n * b, "flop"
     if name.startswith("k_hetrd"):
         return "fp64", 16.0 / 3.0 * b ** 3, "flop"
     if name.startswith("k_chol_inv"):
@@ -217,8 +218,10 @@ def main():
         else:
             achieved = work / avg_s / 1e12
             peak, punit = PEAKS[bound]
-        roof = {"kernel": dom, "bound": "hbm" if bound == "hbm" else "alu",
-                "dtype": bound if bound != "hbm" else None,
+        roof = {"kernel": dom,
+                "bound": "hbm" if bound == "hbm" else ("mfma" if bound.startswith("mfma")
+                                                      else "alu"),
+                "dtype": {"hbm": None, "mfma_fp64": "fp64"}.get(bound, bound),
                 "achieved": achieved, "peak": peak, "unit": punit, "frac": achieved / peak,
                 "traffic": measured_traffic(dom), "launches": traced[0], "avg_us": avg_s * 1e6,
                 "work_per_launch": work, "work_unit": unit}

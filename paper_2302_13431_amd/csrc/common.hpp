@@ -92,6 +92,7 @@ struct TraceScope {
 // ------------------------------------------------------------------ plan
 
 constexpr int kMaxQ = 32;
+constexpr int kAxSplit = 8;  // most K slices of the nullspace product A X
 constexpr int kMaxSupport = 4096;
 
 // Sizes derived from a problem description; everything a stage needs on the

@@ -50,58 +50,93 @@ __global__ void k_init_block(double2* X, int n, int b) {
 
 // ------------------------------------------------------------------ GEMMs
 
-// Z_part[ks] = A[:, kslice] X[kslice, :], A float2 row-major n x n (widened to
-// FP64), X and Z column-major n x b (double2).  32 x 32 output tile per block,
-// 2 x 2 complex micro-tile per thread, K in steps of 32 staged in LDS.
-__global__ void __launch_bounds__(256) k_gemm_ax(const float2* __restrict__ A,
-                                                 const double2* __restrict__ X,
-                                                 double2* __restrict__ Zp, int n, int b,
-                                                 int kchunk) {
-  __shared__ double2 As[32][33];
-  __shared__ double2 Xs[32][33];
-  const int t = threadIdx.x;
-  const int tr = t >> 4, tc = t & 15;
-  const int row0 = blockIdx.x * 32, col0 = blockIdx.y * 32;
+// Z_part[ks] = A[:, kslice] X[kslice, :], A float2 row-major n x n (widened
+// exactly to FP64), X and Z column-major n x b (double2).  One wave per
+// 32 x 32 output tile and K slice, on FP64 matrix cores: each complex
+// 16 x 16 x 4 block step is four real v_mfma_f64_16x16x4f64 products
+// (Re += Ar Xr - Ai Xi, Im += Ar Xi + Ai Xr).  Operand lanes: lane l
+// supplies row (or column) l % 16 at k = k0 + 4 s + l / 16 for step s, so a
+// lane's four k of one chunk are 4 apart and every load instruction reads
+// 4 consecutive elements per row; accumulator element v of lane l is row
+// l / 16 + 4 v, column l % 16.  Operands for the next chunk of 16 k are loaded before the
+// products of the current one.  Every wave reads only its own rows of A, so
+// the three column tiles of a row share A through the caches.
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+struct AxChunk {
+  float2 a[2][4];    // rows r0 + li (+16), k = k0 + 4 q + lk
+  double2 x[2][4];   // columns c0 + li (+16), same k
+};
+
+__device__ inline void ax_load(AxChunk& ch, const float2* Ar0, const float2* Ar1, bool v0,
+                               bool v1, const double2* X0, const double2* X1, int k0, int lk,
+                               int kend) {
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int k = k0 + 4 * q + lk;
+    const bool ok = k < kend;
+    ch.a[0][q] = (ok && v0) ? Ar0[k] : make_float2(0.f, 0.f);
+    ch.a[1][q] = (ok && v1) ? Ar1[k] : make_float2(0.f, 0.f);
+    ch.x[0][q] = ok ? X0[k] : make_double2(0.0, 0.0);
+    ch.x[1][q] = ok ? X1[k] : make_double2(0.0, 0.0);
+  }
+}
+
+__global__ void __launch_bounds__(64) k_gemm_ax(const float2* __restrict__ A,
+                                                const double2* __restrict__ X,
+                                                double2* __restrict__ Zp, int n, int b,
+                                                int kchunk) {
+  const int l = threadIdx.x;
+  const int li = l & 15, lk = l >> 4;
+  const int r0 = blockIdx.x * 32, c0 = blockIdx.y * 32;
   const int kbeg = blockIdx.z * kchunk;
   const int kend = min(n, kbeg + kchunk);
-  double2 acc[2][2];
-  for (int a = 0; a < 2; ++a)
-    for (int c = 0; c < 2; ++c) acc[a][c] = make_double2(0.0, 0.0);
-  for (int k0 = kbeg; k0 < kend; k0 += 32) {
-    for (int e = t; e < 1024; e += 256) {
-      const int rr = e >> 5, kk = e & 31;
-      const int gr = row0 + rr, gk = k0 + kk;
-      double2 v = make_double2(0.0, 0.0);
-      if (gr < n && gk < kend) {
-        const float2 f = A[size_t(gr) * n + gk];
-        v = make_double2(double(f.x), double(f.y));
+  const bool v0 = r0 + li < n, v1 = r0 + 16 + li < n;
+  const float2* Ar0 = A + size_t(v0 ? r0 + li : 0) * n;
+  const float2* Ar1 = A + size_t(v1 ? r0 + 16 + li : 0) * n;
+  const double2* X0 = X + size_t(c0 + li) * n;
+  const double2* X1 = X + size_t(c0 + 16 + li) * n;
+  f64x4 cr[2][2], ci[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      cr[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
+      ci[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
+    }
+  AxChunk cur, nxt;
+  ax_load(cur, Ar0, Ar1, v0, v1, X0, X1, kbeg, lk, kend);
+  for (int k0 = kbeg; k0 < kend; k0 += 16) {
+    if (k0 + 16 < kend) ax_load(nxt, Ar0, Ar1, v0, v1, X0, X1, k0 + 16, lk, kend);
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        const double ar = cur.a[i][s].x, ai = cur.a[i][s].y;
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          const double xr = cur.x[j][s].x, xi = cur.x[j][s].y;
+          cr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, xr, cr[i][j], 0, 0, 0);
+          cr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai, xi, cr[i][j], 0, 0, 0);
+          ci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, xi, ci[i][j], 0, 0, 0);
+          ci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, xr, ci[i][j], 0, 0, 0);
+        }
       }
-      As[rr][kk] = v;
-      const int cc = e >> 5;  // column of X
-      const int gc = col0 + cc;
-      double2 x = make_double2(0.0, 0.0);
-      if (gc < b && gk < kend) x = X[size_t(gc) * n + gk];
-      Xs[kk][cc] = x;
     }
-    __syncthreads();
-#pragma unroll 8
-    for (int kk = 0; kk < 32; ++kk) {
-      const double2 a0 = As[tr * 2][kk], a1 = As[tr * 2 + 1][kk];
-      const double2 x0 = Xs[kk][tc * 2], x1 = Xs[kk][tc * 2 + 1];
-      acc[0][0] = zadd(acc[0][0], zmul(a0, x0));
-      acc[0][1] = zadd(acc[0][1], zmul(a0, x1));
-      acc[1][0] = zadd(acc[1][0], zmul(a1, x0));
-      acc[1][1] = zadd(acc[1][1], zmul(a1, x1));
-    }
-    __syncthreads();
+    cur = nxt;
   }
   double2* out = Zp + size_t(blockIdx.z) * n * b;
-  for (int a = 0; a < 2; ++a)
-    for (int c = 0; c < 2; ++c) {
-      const int gr = row0 + tr * 2 + a, gc = col0 + tc * 2 + c;
-      if (gr < n && gc < b) out[size_t(gc) * n + gr] = acc[a][c];
-    }
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = r0 + 16 * i + lk + 4 * v, col = c0 + 16 * j + li;
+        if (row < n) out[size_t(col) * n + row] = make_double2(cr[i][j][v], ci[i][j][v]);
+      }
 }
+
 
 // out = sum over `parts` slabs of size `len` (fixed order: deterministic)
 __global__ void k_sum_parts(const double2* __restrict__ parts, double2* __restrict__ out,
@@ -562,13 +597,17 @@ pisco_status_t run_nullspace(Handle* h, const Plan& p, int b, int max_iters,
   const double thr2 = double(p.thresh) * double(p.thresh);
   const double tol = 1e-10;
   const int margin = b / 8 > 4 ? b / 8 : 4;
-  const int kchunk = 256 * int(ceil_div(ceil_div(n, 4), 256));
+  // K slices so that the product runs about 2048 waves (at most kAxSplit)
+  const long long tiles = 1LL * ceil_div(n, 32) * ceil_div(b, 32);
+  int want = int(ceil_div(2048, tiles));
+  want = want < 1 ? 1 : (want > kAxSplit ? kAxSplit : want);
+  const int kchunk = 16 * int(ceil_div(ceil_div(n, want), 16));
   const int ksplit = int(ceil_div(n, kchunk));
   const int rchunks = int(ceil_div(n, 1024));
   // Z = A X (split-K partials in `part`, summed in fixed order)
   auto product = [&](const double2* in, double2* out) -> pisco_status_t {
     dim3 g(ceil_div(n, 32), ceil_div(b, 32), ksplit);
-    PISCO_KERNEL(h, k_gemm_ax, g, dim3(256), 0, gram, in, c.w.part, n, b, kchunk);
+    PISCO_KERNEL(h, k_gemm_ax, g, dim3(64), 0, gram, in, c.w.part, n, b, kchunk);
     PISCO_KERNEL(h, k_sum_parts, dim3(ceil_div(nb, 256)), dim3(256), 0, c.w.part, out, nb,
                  ksplit);
     return PISCO_OK;

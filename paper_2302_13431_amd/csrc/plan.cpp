@@ -110,10 +110,10 @@ size_t layout_null(const Plan& p, int b, void* ws, NullWs* o) {
   w.theta = c.take<double>(b);
   w.lam = c.take<double>(b);
   w.resid = c.take<double>(b);
-  // split-K partials of A X (up to 4 slabs of n x b), row-chunk partials of
-  // the b x b products, and residual partials share one buffer
+  // split-K partials of A X (up to kAxSplit slabs of n x b), row-chunk
+  // partials of the b x b products, and residual partials share one buffer
   const size_t chunks = (size_t(p.n) + 255) / 256;
-  size_t part = 4 * nb;
+  size_t part = size_t(kAxSplit) * nb;
   if (chunks * bb > part) part = chunks * bb;
   w.part = c.take<double2>(part);
   w.ctl = c.take<int>(16);
