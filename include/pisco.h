@@ -85,7 +85,17 @@ typedef struct {
                            channel 0 (Sec. V) */
   int32_t block;        /* nullspace block size (multiple of 32, 0 = automatic) */
   int32_t max_subspace_iters; /* cap on nullspace iterations (0 = 60) */
+  int32_t precision;    /* arithmetic of the G(x) contraction over the signal
+                           vectors: PISCO_PREC_FP32, or matrix cores with FP32
+                           accumulation and split operands (PISCO_PREC_SPLIT_*) */
 } pisco_opts_t;
+
+/* Precision choices (pisco_opts_t.precision). */
+#define PISCO_PREC_FP32       0  /* FP32 arithmetic */
+#define PISCO_PREC_SPLIT_F16  1  /* FP16 MFMA, each operand as 2 FP16 parts,
+                                    3 cross products, FP32 accumulation */
+#define PISCO_PREC_SPLIT_BF16 2  /* BF16 MFMA, each operand as 3 BF16 parts,
+                                    6 cross products, FP32 accumulation */
 
 /* Stage identifiers for pisco_workspace_size. */
 #define PISCO_STAGE_GRAM      1

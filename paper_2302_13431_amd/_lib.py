@@ -25,6 +25,7 @@ FLAG_BLOCK_TOO_SMALL = 0x4
 FLAG_ZERO_DATA = 0x8
 
 STAGE_ALL, STAGE_GRAM, STAGE_NULLSPACE, STAGE_GX, STAGE_EIG, STAGE_MAPS = 0, 1, 2, 3, 4, 5
+PREC_FP32, PREC_SPLIT_F16, PREC_SPLIT_BF16 = 0, 1, 2
 
 
 class Problem(ctypes.Structure):
@@ -36,7 +37,7 @@ class Problem(ctypes.Structure):
 class Opts(ctypes.Structure):
     _fields_ = [("power_iters", ctypes.c_int32), ("tol", ctypes.c_float),
                 ("phase_rule", ctypes.c_int32), ("block", ctypes.c_int32),
-                ("max_subspace_iters", ctypes.c_int32)]
+                ("max_subspace_iters", ctypes.c_int32), ("precision", ctypes.c_int32)]
 
 
 class TraceEntry(ctypes.Structure):
@@ -113,10 +114,11 @@ def make_problem(D: int, Q: int, acs: Sequence[int], radius: float, grid_lr: Seq
 
 
 def make_opts(power_iters: int = 10, tol: float = 0.0, phase_rule: int = 0, block: int = 0,
-              max_subspace_iters: int = 60) -> Opts:
+              max_subspace_iters: int = 60, precision: int = PREC_FP32) -> Opts:
     o = Opts()
     o.power_iters, o.tol, o.phase_rule = int(power_iters), float(tol), int(phase_rule)
     o.block, o.max_subspace_iters = int(block), int(max_subspace_iters)
+    o.precision = int(precision)
     return o
 
 

@@ -16,6 +16,7 @@ pisco_opts_t default_opts() {
   o.phase_rule = 0;
   o.block = 0;
   o.max_subspace_iters = 60;
+  o.precision = PISCO_PREC_FP32;
   return o;
 }
 
@@ -286,7 +287,10 @@ pisco_status_t pisco_gx(pisco_handle_t handle, const pisco_problem_t* prob,
     return fail(h, PISCO_ERR_ARG, "null or unaligned pointer");
   if (ws_bytes < layout_gx(p, b, nullptr, nullptr))
     return fail(h, PISCO_ERR_WORKSPACE, "workspace too small for pisco_gx");
-  return run_gx(h, p, b, static_cast<const double2*>(basis), counts, static_cast<float2*>(G), ws);
+  if (o.precision < PISCO_PREC_FP32 || o.precision > PISCO_PREC_SPLIT_BF16)
+    return fail(h, PISCO_ERR_ARG, "unknown precision");
+  return run_gx(h, p, b, o.precision, static_cast<const double2*>(basis), counts,
+                static_cast<float2*>(G), ws);
 }
 
 pisco_status_t pisco_eig(pisco_handle_t handle, int32_t Q, int64_t N, float bound,
@@ -337,6 +341,8 @@ pisco_status_t pisco_estimate(pisco_handle_t handle, const pisco_problem_t* prob
   if ((st = block_of(p, o, &b, &err))) return fail(h, st, err.c_str());
   if (!acs || !maps_out || !ws || !aligned(ws))
     return fail(h, PISCO_ERR_ARG, "null or unaligned pointer");
+  if (o.precision < PISCO_PREC_FP32 || o.precision > PISCO_PREC_SPLIT_BF16)
+    return fail(h, PISCO_ERR_ARG, "unknown precision");
   EstLayout e = est_layout(p, b, ws);
   if (ws_bytes < e.total) return fail(h, PISCO_ERR_WORKSPACE, "workspace too small for pisco_estimate");
   const float2* a = static_cast<const float2*>(acs);
@@ -344,7 +350,7 @@ pisco_status_t pisco_estimate(pisco_handle_t handle, const pisco_problem_t* prob
   if ((st = run_nullspace(h, p, b, o.max_subspace_iters, e.gram, e.eigvals, e.basis, e.counts,
                           e.stage_ws)))
     return st;
-  if ((st = run_gx(h, p, b, e.basis, e.counts, e.G, e.stage_ws))) return st;
+  if ((st = run_gx(h, p, b, o.precision, e.basis, e.counts, e.G, e.stage_ws))) return st;
   float* lam = lam_min ? lam_min : e.lam;
   if ((st = run_eig(h, p.Q, p.Nlr, float(p.L), o.power_iters, o.tol, e.G, e.maps_lr, lam,
                     nullptr)))

@@ -199,7 +199,7 @@ pisco_status_t run_gram(Handle* h, const Plan& p, const float2* acs, float2* gra
 pisco_status_t run_nullspace(Handle* h, const Plan& p, int b, int max_iters,
                              const float2* gram, double* eigvals, double2* basis,
                              int32_t* counts, void* ws);
-pisco_status_t run_gx(Handle* h, const Plan& p, int b, const double2* basis,
+pisco_status_t run_gx(Handle* h, const Plan& p, int b, int precision, const double2* basis,
                       const int32_t* counts, float2* G, void* ws);
 pisco_status_t run_eig(Handle* h, int Q, long long N, float bound, int iters,
                        float tol, const float2* G, float2* maps, float* lam,

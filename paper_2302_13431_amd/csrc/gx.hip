@@ -15,6 +15,8 @@
 //   4. G^s(x) = sum_m K^s[m] e^{-i 2 pi m.x} on the low-res grid and
 //      G = |Lambda| I - G^s.
 // Lk = 4 tau + 1 is the smallest grid that holds every lag without aliasing.
+#include <cmath>
+
 #include "common.hpp"
 
 namespace pisco {
@@ -102,6 +104,171 @@ __global__ void __launch_bounds__(256) k_herk(const float2* __restrict__ F,
     }
 }
 
+// Split-precision variant of k_herk on the matrix cores (FP32 accumulation).
+// kPrec = PISCO_PREC_SPLIT_F16: each FP32 operand x, scaled by 2^e so that
+// FP16's range is used, is split into x_hi = fp16(x) and x_lo = fp16(x -
+// x_hi) and a product is x_hi y_hi + x_hi y_lo + x_lo y_hi (three MFMAs; the
+// dropped x_lo y_lo is below 2^-22 relative).  kPrec = PISCO_PREC_SPLIT_BF16:
+// three BF16 parts hi, mid, lo and the six cross products of total order
+// <= 2.  Workgroup: 16 frequencies, 4 waves of 4 frequencies each; r runs
+// in chunks of 16 staged in LDS as [r][q][f] (f padded to 17 against bank
+// conflicts).  For one frequency the Q x Q result is C = A^H A with A the
+// r x Q matrix F[.][.][f]: Re C = Ar^T Ar + Ai^T Ai, Im C = Ar^T Ai - Ai^T Ar,
+// as 16 x 16 x 16 blocks (upper blocks only).  Operand lanes: lane l holds
+// row (column) l % 16 at k = 4 (l / 16) + j, j < 4; accumulator element v of
+// lane l is row 4 (l / 16) + v, column l % 16.
+typedef _Float16 f16x4 __attribute__((ext_vector_type(4)));
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ inline short bf16_rne(float f) {
+  unsigned u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return short(u >> 16);
+}
+__device__ inline float bf16_to_f32(short h) {
+  return __uint_as_float(static_cast<unsigned>(static_cast<unsigned short>(h)) << 16);
+}
+
+template <int kPrec>
+struct SplitOps;
+
+template <>
+struct SplitOps<PISCO_PREC_SPLIT_F16> {
+  static constexpr int kParts = 2;
+  typedef f16x4 vec;
+  __device__ static void split(const float (&x)[4], float s, vec (&out)[kParts]) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const float v = x[j] * s;
+      const _Float16 hi = static_cast<_Float16>(v);
+      out[0][j] = hi;
+      out[1][j] = static_cast<_Float16>(v - static_cast<float>(hi));
+    }
+  }
+  __device__ static vec neg(vec a) { return -a; }
+  __device__ static f32x4 mma(vec a, vec b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x16f16(a, b, c, 0, 0, 0);
+  }
+  // (part of x, part of y) pairs kept: hi hi, hi lo, lo hi
+  static constexpr int kTerms = 3;
+  __device__ static constexpr int ta(int i) { return i == 2 ? 1 : 0; }
+  __device__ static constexpr int tb(int i) { return i == 1 ? 1 : 0; }
+};
+
+template <>
+struct SplitOps<PISCO_PREC_SPLIT_BF16> {
+  static constexpr int kParts = 3;
+  typedef bf16x4 vec;
+  __device__ static void split(const float (&x)[4], float, vec (&out)[kParts]) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      float v = x[j];
+      const short hi = bf16_rne(v);
+      v -= bf16_to_f32(hi);
+      const short mid = bf16_rne(v);
+      v -= bf16_to_f32(mid);
+      out[0][j] = hi;
+      out[1][j] = mid;
+      out[2][j] = bf16_rne(v);
+    }
+  }
+  __device__ static vec neg(vec a) { return a ^ bf16x4{short(0x8000), short(0x8000), short(0x8000), short(0x8000)}; }
+  __device__ static f32x4 mma(vec a, vec b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+  }
+  // hi hi, hi mid, mid hi, hi lo, lo hi, mid mid
+  static constexpr int kTerms = 6;
+  __device__ static constexpr int ta(int i) { return i == 2 ? 1 : (i == 4 ? 2 : (i == 5 ? 1 : 0)); }
+  __device__ static constexpr int tb(int i) { return i == 1 ? 1 : (i == 3 ? 2 : (i == 5 ? 1 : 0)); }
+};
+
+template <int kPrec>
+__global__ void __launch_bounds__(256) k_herk_mfma(const float2* __restrict__ F,
+                                                   const int32_t* __restrict__ counts,
+                                                   float2* __restrict__ Kh, int Q, int nK,
+                                                   float scale) {
+  using Ops = SplitOps<kPrec>;
+  using vec = typename Ops::vec;
+  constexpr int kFB = 16, kFP = 17, kFW = 4;  // frequencies per block / padded / per wave
+  __shared__ float2 tile[16 * kMaxQ * kFP];
+  const int t = threadIdx.x, wv = t >> 6, l = t & 63;
+  const int li = l & 15, kg = l >> 4;
+  const int f0 = blockIdx.x * kFB;
+  const int rs = counts[0];
+  const int nqb = Q > 16 ? 2 : 1;
+  f32x4 cr[kFW][3], ci[kFW][3];
+#pragma unroll
+  for (int fi = 0; fi < kFW; ++fi)
+#pragma unroll
+    for (int bk = 0; bk < 3; ++bk) {
+      cr[fi][bk] = f32x4{0.f, 0.f, 0.f, 0.f};
+      ci[fi][bk] = f32x4{0.f, 0.f, 0.f, 0.f};
+    }
+  for (int r0 = 0; r0 < rs; r0 += 16) {
+    for (int e = t; e < 16 * Q * kFB; e += 256) {
+      const int ff = e % kFB, rq = e / kFB, rr = rq / Q;
+      const int f = f0 + ff;
+      tile[rq * kFP + ff] = (r0 + rr < rs && f < nK) ? F[size_t(r0 * Q + rq) * nK + f]
+                                                     : make_float2(0.f, 0.f);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int fi = 0; fi < kFW; ++fi) {
+      const int ff = wv * kFW + fi;
+      // parts of Re and Im for the lane's column in channel block 0 and 1
+      vec re[2][Ops::kParts], im[2][Ops::kParts];
+#pragma unroll
+      for (int cb = 0; cb < 2; ++cb) {
+        float xr[4], xi[4];
+        const int q = 16 * cb + li;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const float2 v = q < Q ? tile[((4 * kg + j) * Q + q) * kFP + ff] : make_float2(0.f, 0.f);
+          xr[j] = v.x;
+          xi[j] = v.y;
+        }
+        Ops::split(xr, scale, re[cb]);
+        Ops::split(xi, scale, im[cb]);
+      }
+#pragma unroll
+      for (int bk = 0; bk < 3; ++bk) {
+        const int pb = bk == 2 ? 1 : 0, qb = bk == 0 ? 0 : 1;
+        if (qb >= nqb) continue;
+#pragma unroll
+        for (int term = 0; term < Ops::kTerms; ++term) {
+          const vec arp = re[pb][Ops::ta(term)], aip = im[pb][Ops::ta(term)];
+          const vec brq = re[qb][Ops::tb(term)], biq = im[qb][Ops::tb(term)];
+          cr[fi][bk] = Ops::mma(arp, brq, cr[fi][bk]);
+          cr[fi][bk] = Ops::mma(aip, biq, cr[fi][bk]);
+          ci[fi][bk] = Ops::mma(arp, biq, ci[fi][bk]);
+          ci[fi][bk] = Ops::mma(Ops::neg(aip), brq, ci[fi][bk]);
+        }
+      }
+    }
+    __syncthreads();
+  }
+  const float inv = kPrec == PISCO_PREC_SPLIT_F16 ? 1.f / (scale * scale) : 1.f;
+#pragma unroll
+  for (int fi = 0; fi < kFW; ++fi) {
+    const int f = f0 + wv * kFW + fi;
+    if (f >= nK) continue;
+#pragma unroll
+    for (int bk = 0; bk < 3; ++bk) {
+      const int pb = bk == 2 ? 1 : 0, qb = bk == 0 ? 0 : 1;
+      if (qb >= nqb) continue;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int p = 16 * pb + 4 * kg + v, q = 16 * qb + li;
+        if (p <= q && q < Q) {
+          const int pair = p * Q - p * (p - 1) / 2 + (q - p);
+          Kh[size_t(pair) * nK + f] = make_float2(cr[fi][bk][v] * inv, ci[fi][bk][v] * inv);
+        }
+      }
+    }
+  }
+}
+
 // G = |Lambda| I - G^s on the packed planes; diagonal entries real.
 __global__ void k_gx_finish(float2* __restrict__ G, int Q, long long N, float bound) {
   const long long idx = blockIdx.x * 256LL + threadIdx.x;
@@ -126,7 +293,7 @@ static pisco_status_t chain(Handle* h, const float2* in, float2* out, int shape[
   return st;
 }
 
-pisco_status_t run_gx(Handle* h, const Plan& p, int b, const double2* basis,
+pisco_status_t run_gx(Handle* h, const Plan& p, int b, int precision, const double2* basis,
                       const int32_t* counts, float2* G, void* ws) {
   GxWs w;
   layout_gx(p, b, ws, &w);
@@ -177,8 +344,17 @@ pisco_status_t run_gx(Handle* h, const Plan& p, int b, const double2* basis,
     if ((st = chain(h, bufB, w.Fh, shp, 2, p.K[1], M1[1]))) return st;
   }
   // 2. contraction over the signal vectors
-  const int FT = 256 / Q;
-  PISCO_KERNEL(h, k_herk, dim3(ceil_div(p.nK, FT)), dim3(256), 0, w.Fh, counts, w.Kh, Q, p.nK, FT);
+  if (precision == PISCO_PREC_SPLIT_F16) {
+    // |F_r(f, q)| <= sum_n |v_r[n, q]| <= sqrt(|Lambda|) for unit v_r: scale
+    // so that this bound maps below 2^15 (FP16 holds up to 65504)
+    const float scale = std::ldexp(1.f, int(std::floor(15.0 - 0.5 * std::log2(double(p.L)))));
+    PISCO_KERNEL(h, k_herk_mfma<PISCO_PREC_SPLIT_F16>, dim3(ceil_div(p.nK, 16)), dim3(256), 0, w.Fh, counts, w.Kh, Q, p.nK, scale);
+  } else if (precision == PISCO_PREC_SPLIT_BF16) {
+    PISCO_KERNEL(h, k_herk_mfma<PISCO_PREC_SPLIT_BF16>, dim3(ceil_div(p.nK, 16)), dim3(256), 0, w.Fh, counts, w.Kh, Q, p.nK, 1.f);
+  } else {
+    const int FT = 256 / Q;
+    PISCO_KERNEL(h, k_herk, dim3(ceil_div(p.nK, FT)), dim3(256), 0, w.Fh, counts, w.Kh, Q, p.nK, FT);
+  }
   // 3. lags: [P][Kz][Ky][Kx] -> [P][Bz'][By][Bx]
   int shk[4] = {P, p.K[0], p.K[1], p.K[2]};
   if (p.D == 3) {

@@ -23,7 +23,8 @@ class Estimator:
     def __init__(self, Q: int, acs_shape: Sequence[int], radius: float,
                  grid_lr: Sequence[int], grid_out: Sequence[int], thresh: float = 0.05,
                  power_iters: int = 10, tol: float = 0.0, phase_rule: int = 0,
-                 block: int = 0, max_subspace_iters: int = 60, stream=None):
+                 block: int = 0, max_subspace_iters: int = 60, precision: int = 0,
+                 stream=None):
         import torch
         self.torch = torch
         self.D = len(acs_shape)
@@ -33,7 +34,8 @@ class Estimator:
         self.grid_out = tuple(int(a) for a in grid_out)
         self.radius = float(radius)
         self.prob = L.make_problem(self.D, Q, acs_shape, radius, grid_lr, grid_out, thresh)
-        self.opts = L.make_opts(power_iters, tol, phase_rule, block, max_subspace_iters)
+        self.opts = L.make_opts(power_iters, tol, phase_rule, block, max_subspace_iters,
+                                precision)
         self.h = L.Handle(stream)
         self.support = L.pisco_support(self.D, radius)
         self.nsup = len(self.support)

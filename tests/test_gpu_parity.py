@@ -137,11 +137,18 @@ def test_nullspace_repeated_eigenvalues():
 # ------------------------------------------------------------------ G(x)
 
 
+PRECISIONS = {0: "fp32", 1: "split_f16", 2: "split_bf16"}
+
+
+@pytest.mark.parametrize("prec", list(PRECISIONS))
 @pytest.mark.parametrize("name", WLALL)
-def test_gx(name):
+def test_gx(name, prec):
+    """G(x) against the oracle for each arithmetic of the contraction over
+    the signal vectors (FP32, or FP16 / BF16 matrix cores with split
+    operands and FP32 accumulation); the error vs FP64 is printed."""
     w, _ = scan_inputs(name)
     lam, lags, _, _, sp = oracle_gram_split(name)
-    est = estimator(name)
+    est = estimator(name, precision=prec)
     b = est.block
     basis = np.ascontiguousarray(sp.vectors[:, :b].T)
     counts = np.array([sp.r_signal, b, 0, 1], dtype=np.int32)
@@ -154,7 +161,7 @@ def test_gx(name):
         idx, pts = sampled_points(w.grid_lr, 600, 77)
     Go = packed_upper(ogx.gx_from_lag_kernel(Kn, lags, pts))
     err = float(np.abs(G[:, idx] - Go).max() / len(lam))
-    report("gx " + name, err=err, sampled=len(idx))
+    report(f"gx {name} {PRECISIONS[prec]}", err=err, sampled=len(idx))
     assert err <= 1e-5
 
 
@@ -250,10 +257,11 @@ def test_maps(name, rule):
 
 
 @pytest.mark.parametrize("name", WLALL)
-def test_end_to_end(name):
+@pytest.mark.parametrize("prec", list(PRECISIONS))
+def test_end_to_end(name, prec):
     ref = oracle_full(name)
     w, acs = scan_inputs(name)
-    est = estimator(name)
+    est = estimator(name, precision=prec)
     out, lam = est.estimate(cuda(acs))
     out, lam = out.cpu().numpy(), lam.cpu().numpy()
     bound = float(len(ref.lam))
@@ -261,7 +269,7 @@ def test_end_to_end(name):
     mask_lr = lowres_mask(ref.c_lr, ref.rho_lr, None)
     mo = output_mask(mask_lr, w.grid)
     e = map_error(ref.maps, out)
-    report("e2e " + name, err_lam=e_lam, err_map_mask=float(e[mo].max()),
+    report(f"e2e {name} {PRECISIONS[prec]}", err_lam=e_lam, err_map_mask=float(e[mo].max()),
            err_map_p99=float(np.percentile(e, 99)), err_map_all=float(e.max()))
     assert est.status() == 0
     assert e_lam <= 1e-5
