@@ -7,7 +7,10 @@ One step is one full pass of the hot path on one synthetic scan whose ACS is
 already resident in HBM: calibration Gram by FFT correlation, FP64 signal /
 null split, G(x) on the low-resolution grid, per-voxel power iteration, phase
 reference, sinc interpolation and RSS normalisation (pisco_estimate).  The
-value is output voxels (maps on the full grid) per second.
+value is output voxels (maps on the full grid) per second of the mixed form
+(G(x) contraction on FP16 matrix cores with split operands); the plain FP32
+form is timed the same way and reported beside it, and with the CPU
+baseline both forms' map errors against the FP64 oracle are reported.
 
 Prints one JSON line.  The roofline object describes the kernel that takes
 the most time in the timed steps: its launches are bracketed by HIP events on
@@ -111,10 +114,10 @@ def cpu_baseline(w, acs, budget_s: float = 25.0):
     except Exception:  # pragma: no cover
         threads = len(os.sched_getaffinity(0))
     a = acs.astype(np.complex128)
-    runs, spent = 0, 0.0
+    runs, spent, ref = 0, 0.0, None
     while runs == 0 or spent < budget_s * 0.5:
         t0 = time.perf_counter()
-        opipe.estimate(a, w.radius, w.grid_lr, w.grid)
+        ref = opipe.estimate(a, w.radius, w.grid_lr, w.grid)
         spent += time.perf_counter() - t0
         runs += 1
         if spent > budget_s:
@@ -125,7 +128,22 @@ def cpu_baseline(w, acs, budget_s: float = 25.0):
     return {"value": runs * nout / spent / 1e6, "unit": "Mvoxel/s", "cores": int(threads),
             "kind": "oracle",
             "sample": f"{runs} full oracle run(s) of the same scan ({nout} output voxels each), "
-                      f"{spent:.1f} s"}
+                      f"{spent:.1f} s"}, ref
+
+
+def map_error_defined(w, ref, out):
+    """Largest gauge-invariant map error vs the FP64 oracle where the map is
+    defined (coil-combined apodized low-res image >= 1e-3 of its maximum,
+    eroded by one low-res voxel, carried to the output grid)."""
+    import numpy as np
+    from scipy.ndimage import binary_erosion
+    from oracle import metrics
+    m = np.abs(np.sum(np.conj(ref.c_lr) * ref.rho_lr, axis=0))
+    mask_lr = binary_erosion(m >= 1e-3 * m.max(), iterations=1)
+    idx = [np.round(((np.arange(n) - n // 2) / n) * l + l // 2).astype(int) % l
+           for n, l in zip(w.grid, w.grid_lr)]
+    mask = mask_lr[np.ix_(*idx)]
+    return float(metrics.map_error(ref.maps, out)[mask].max())
 
 
 def main():
@@ -167,46 +185,51 @@ def main():
     scan = w.scan(keep_kspace=False)
     acs_np = as_device_input(scan.acs)
     acs = torch.from_numpy(acs_np).cuda()
-    est = P.Estimator(w.Q, w.acs, w.radius, w.grid_lr, w.grid, block=BLOCKS.get(w.name, 0))
-    out = torch.empty((w.Q,) + tuple(w.grid), dtype=torch.complex64, device="cuda")
-    lam = torch.empty((est.Nlr,), dtype=torch.float32, device="cuda")
-
-    for _ in range(args.warmup):
-        est.estimate(acs, out, lam)
-    torch.cuda.synchronize()
-    status = est.status()
-
-    # one traced step (all kernels) to find the dominant kernel
-    P.pisco_trace_enable(est.h, True, None)
-    est.estimate(acs, out, lam)
-    per = P.pisco_trace_read(est.h)
-    P.pisco_trace_enable(est.h, False)
-    dom = max(per.items(), key=lambda kv: kv[1][1])[0]
-    if args.breakdown:
-        tot = sum(v[1] for v in per.values())
-        for k, (cnt, ms) in sorted(per.items(), key=lambda kv: -kv[1][1]):
-            print(f"  {k:28s} {cnt:5d} launches {ms:9.3f} ms {100 * ms / tot:5.1f}%",
-                  file=sys.stderr)
-
-    # timed region: K steps, the dominant kernel traced with events
-    P.pisco_trace_enable(est.h, True, dom)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        est.estimate(acs, out, lam)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    traced = P.pisco_trace_read(est.h).get(dom, (0, 0.0))
-    P.pisco_trace_enable(est.h, False)
-    status |= est.status()
-
     nout = int(np.prod(w.grid))
-    ms_per_step = elapsed / args.steps * 1e3
-    value = args.steps * nout / elapsed / 1e6
 
+    def run_form(precision, trace_all=False):
+        """Warm up, find the dominant kernel, time `steps` steps (that kernel
+        bracketed by HIP events).  Returns a dict of results."""
+        est = P.Estimator(w.Q, w.acs, w.radius, w.grid_lr, w.grid,
+                          block=BLOCKS.get(w.name, 0), precision=precision)
+        out = torch.empty((w.Q,) + tuple(w.grid), dtype=torch.complex64, device="cuda")
+        lam = torch.empty((est.Nlr,), dtype=torch.float32, device="cuda")
+        for _ in range(args.warmup):
+            est.estimate(acs, out, lam)
+        torch.cuda.synchronize()
+        status = est.status()
+        P.pisco_trace_enable(est.h, True, None)
+        est.estimate(acs, out, lam)
+        per = P.pisco_trace_read(est.h)
+        P.pisco_trace_enable(est.h, False)
+        dom = max(per.items(), key=lambda kv: kv[1][1])[0]
+        P.pisco_trace_enable(est.h, True, dom)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            est.estimate(acs, out, lam)
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
+        traced = P.pisco_trace_read(est.h).get(dom, (0, 0.0))
+        P.pisco_trace_enable(est.h, False)
+        status |= est.status()
+        return {"est": est, "out": out.cpu().numpy(), "status": status, "per": per, "dom": dom,
+                "traced": traced, "ms": elapsed / args.steps * 1e3,
+                "value": args.steps * nout / elapsed / 1e6}
+
+    mixed = run_form(P._lib.PREC_SPLIT_F16)
+    plain = run_form(P._lib.PREC_FP32)
+    if args.breakdown:
+        for tag, r in (("mixed", mixed), ("plain_fp32", plain)):
+            tot = sum(v[1] for v in r["per"].values())
+            print(f"[{tag}] {r['ms']:.3f} ms/step", file=sys.stderr)
+            for k, (cnt, ms) in sorted(r["per"].items(), key=lambda kv: -kv[1][1]):
+                print(f"  {k:28s} {cnt:5d} launches {ms:9.3f} ms {100 * ms / tot:5.1f}%",
+                      file=sys.stderr)
+
+    est, dom, traced = mixed["est"], mixed["dom"], mixed["traced"]
     roof = None
-    rs = 0
-    ev, basis, counts = est.nullspace(est.gram(acs))
+    _, _, counts = est.nullspace(est.gram(acs))
     rs = int(counts[0].item())
     model = kernel_model(dom, w, est, rs)
     if model and traced[0] > 0:
@@ -226,18 +249,24 @@ def main():
                 "traffic": measured_traffic(dom), "launches": traced[0], "avg_us": avg_s * 1e6,
                 "work_per_launch": work, "work_unit": unit}
 
-    line = {"metric": METRIC, "value": value, "unit": "Mvoxel/s", "n_gpus": 1,
-            "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+    line = {"metric": METRIC, "value": mixed["value"], "unit": "Mvoxel/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": mixed["ms"],
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
             "data": "synthetic",
             "config": {"workload": w.name, "grid": list(w.grid), "Q": w.Q, "acs": list(w.acs),
                        "radius": w.radius, "grid_lr": list(w.grid_lr),
-                       "precision": "fp32 path, fp64 nullspace", "power_iters": 10,
-                       "nullspace_block": est.block, "signal_rank": rs,
-                       "device_status": status},
+                       "precision": "G(x) contraction on FP16 matrix cores with split operands "
+                                    "and FP32 accumulation; nullspace FP64; rest FP32",
+                       "power_iters": 10, "nullspace_block": est.block, "signal_rank": rs,
+                       "device_status": mixed["status"] | plain["status"],
+                       "plain_fp32": {"value": plain["value"], "ms_per_step": plain["ms"]}},
             "roofline": roof}
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(w, acs_np)
+        base, ref = cpu_baseline(w, acs_np)
+        line["cpu_baseline"] = base
+        line["config"]["map_error_vs_fp64"] = {"mixed": map_error_defined(w, ref, mixed["out"]),
+                                               "plain_fp32": map_error_defined(w, ref,
+                                                                               plain["out"])}
     print(json.dumps(line), flush=True)
 
 
