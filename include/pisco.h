@@ -202,6 +202,73 @@ pisco_status_t pisco_maps(pisco_handle_t handle, const pisco_problem_t* prob,
                           const void* maps_lr, void* maps_out, void* workspace,
                           size_t workspace_bytes);
 
+/* As pisco_eig, starting each voxel from the caller's vector instead of e_q
+ * (a warm start, e.g. from pisco_ws_forward).
+ *   init : float2 [Q][N]; normalised here; a voxel whose start vector is zero
+ *          or not finite falls back to e_q. */
+pisco_status_t pisco_eig_from(pisco_handle_t handle, int32_t Q, int64_t N,
+                              float bound, const pisco_opts_t* opts,
+                              const void* G, const void* init, void* maps,
+                              float* lam_min, int32_t* iters, void* workspace,
+                              size_t workspace_bytes);
+
+/* ---- Learned warm start (not in the paper) ------------------------------
+ * A network predicts each voxel's start vector for the power iteration from
+ * G(x) / |Lambda| (upper triangle: Q real diagonal entries, then Re and Im of
+ * the entries p < q in row-major order) and a neighbour vector n (Re, Im):
+ * two ReLU layers of 256, output y (2Q reals), start vector n + y.
+ * Parameters, one flat vector (FP32 master and FP16 copy, same layout):
+ *   [W1 (256 x Din, row-major), b1 (256), W2 (256 x 256), b2 (256),
+ *    W3 (2Q x 256), b3 (2Q)],  Din = Q^2 + 2Q.
+ * Products run on FP16 matrix cores with FP32 accumulation.  All pointers
+ * are device pointers owned by the caller; Q in [2, 32]. */
+
+/* Number of parameters (host-only). */
+pisco_status_t pisco_ws_param_count(int32_t Q, int64_t* count);
+
+/* Workspace bytes for pisco_ws_forward / pisco_ws_train_step on N voxels
+ * (host-only). */
+pisco_status_t pisco_ws_workspace_size(int32_t Q, int64_t N, size_t* bytes);
+
+/* Deterministic He-uniform initialisation from `seed` (output layer scaled
+ * by 1e-2, biases zero) of master (float [count]) and weights16 (FP16
+ * [count]). */
+pisco_status_t pisco_ws_init(pisco_handle_t handle, int32_t Q, uint64_t seed,
+                             float* master, void* weights16);
+
+/* Neighbour vectors for the grid grid_lr (z, y, x) from eigenvectors on the
+ * grid coarser by two, ceil(grid_lr / 2) per dimension: voxel i takes the
+ * coarse voxel floor((i - floor(lr/2)) / 2) + floor(lc/2) (the nearest
+ * sample at or below its position), with the largest-magnitude entry
+ * rotated to be real and positive.
+ *   coarse   : float2 [Q][Nc];  neighbor : float2 [Q][N] */
+pisco_status_t pisco_ws_neighbor(pisco_handle_t handle, int32_t Q,
+                                 const int32_t grid_lr[3], const void* coarse,
+                                 void* neighbor);
+
+/* Start vectors init = normalise(n + y) for N voxels.
+ *   G : packed as from pisco_gx;  neighbor, init : float2 [Q][N];
+ *   weights16 : FP16 parameters. */
+pisco_status_t pisco_ws_forward(pisco_handle_t handle, int32_t Q, int64_t N,
+                                float bound, const void* G, const void* neighbor,
+                                const void* weights16, void* init,
+                                void* workspace, size_t workspace_bytes);
+
+/* One training step on a batch of N >= 1 voxels with target eigenvectors
+ * (float2 [Q][N], unit norm): loss 1 - |c_hat^H c|^2 / ||c_hat||^2 averaged
+ * over the batch, its gradient, and, when step >= 1, one Adam update
+ * (beta 0.9 / 0.999, eps 1e-8, bias correction for step `step`) of master,
+ * adam_m, adam_v (float [count]) with the FP16 copy refreshed.
+ *   loss_out : device float[1], the mean loss before the update (nullable)
+ *   grad_out : device float[count], gradient of the SUMMED loss (nullable) */
+pisco_status_t pisco_ws_train_step(pisco_handle_t handle, int32_t Q, int64_t N,
+                                   float bound, const void* G,
+                                   const void* neighbor, const void* target,
+                                   float* master, void* weights16,
+                                   float* adam_m, float* adam_v, int32_t step,
+                                   float lr, float* loss_out, float* grad_out,
+                                   void* workspace, size_t workspace_bytes);
+
 /* The whole path: pisco_gram, pisco_nullspace, pisco_gx, pisco_eig and
  * pisco_maps chained, intermediates in the workspace.
  *   lam_min : float [N_lr] (may be NULL) */

@@ -78,6 +78,19 @@ _SIGS = {
                     ctypes.c_size_t], ctypes.c_int),
     "pisco_estimate": ([_P, ctypes.POINTER(Problem), ctypes.POINTER(Opts), _P, _P, _P, _P,
                         ctypes.c_size_t], ctypes.c_int),
+    "pisco_eig_from": ([_P, ctypes.c_int32, ctypes.c_int64, ctypes.c_float, ctypes.POINTER(Opts),
+                        _P, _P, _P, _P, _P, _P, ctypes.c_size_t], ctypes.c_int),
+    "pisco_ws_param_count": ([ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
+    "pisco_ws_workspace_size": ([ctypes.c_int32, ctypes.c_int64, ctypes.POINTER(ctypes.c_size_t)],
+                                ctypes.c_int),
+    "pisco_ws_init": ([_P, ctypes.c_int32, ctypes.c_uint64, _P, _P], ctypes.c_int),
+    "pisco_ws_neighbor": ([_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), _P, _P],
+                          ctypes.c_int),
+    "pisco_ws_forward": ([_P, ctypes.c_int32, ctypes.c_int64, ctypes.c_float, _P, _P, _P, _P, _P,
+                          ctypes.c_size_t], ctypes.c_int),
+    "pisco_ws_train_step": ([_P, ctypes.c_int32, ctypes.c_int64, ctypes.c_float, _P, _P, _P, _P,
+                             _P, _P, _P, ctypes.c_int32, ctypes.c_float, _P, _P, _P,
+                             ctypes.c_size_t], ctypes.c_int),
     "pisco_trace_enable": ([_P, ctypes.c_int32, ctypes.c_char_p], ctypes.c_int),
     "pisco_trace_read": ([_P, _P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
 }
@@ -217,6 +230,51 @@ def pisco_gx(h: Handle, prob: Problem, opts: Opts, basis, counts, G, ws):
 def pisco_eig(h: Handle, Q: int, N: int, bound: float, opts: Opts, G, maps, lam=None, iters=None):
     _check(lib().pisco_eig(h.h, Q, N, bound, ctypes.byref(opts), _ptr(G), _ptr(maps), _ptr(lam),
                            _ptr(iters), None, 0), "pisco_eig", h.h)
+
+
+def pisco_eig_from(h: Handle, Q: int, N: int, bound: float, opts: Opts, G, init, maps, lam=None,
+                   iters=None):
+    _check(lib().pisco_eig_from(h.h, Q, N, bound, ctypes.byref(opts), _ptr(G), _ptr(init),
+                                _ptr(maps), _ptr(lam), _ptr(iters), None, 0), "pisco_eig_from", h.h)
+
+
+def pisco_ws_param_count(Q: int) -> int:
+    n = ctypes.c_int64()
+    _check(lib().pisco_ws_param_count(Q, ctypes.byref(n)), "pisco_ws_param_count")
+    return n.value
+
+
+def pisco_ws_workspace_size(Q: int, N: int) -> int:
+    n = ctypes.c_size_t()
+    _check(lib().pisco_ws_workspace_size(Q, N, ctypes.byref(n)), "pisco_ws_workspace_size")
+    return n.value
+
+
+def pisco_ws_init(h: Handle, Q: int, seed: int, master, weights16):
+    _check(lib().pisco_ws_init(h.h, Q, seed, _ptr(master), _ptr(weights16)), "pisco_ws_init", h.h)
+
+
+def pisco_ws_neighbor(h: Handle, Q: int, grid_lr, coarse, neighbor):
+    g = list(grid_lr)
+    g = [1] * (3 - len(g)) + g
+    arr = (ctypes.c_int32 * 3)(*g)
+    _check(lib().pisco_ws_neighbor(h.h, Q, arr, _ptr(coarse), _ptr(neighbor)),
+           "pisco_ws_neighbor", h.h)
+
+
+def pisco_ws_forward(h: Handle, Q: int, N: int, bound: float, G, neighbor, weights16, init, ws):
+    _check(lib().pisco_ws_forward(h.h, Q, N, bound, _ptr(G), _ptr(neighbor), _ptr(weights16),
+                                  _ptr(init), _ptr(ws), ws.numel() * ws.element_size()),
+           "pisco_ws_forward", h.h)
+
+
+def pisco_ws_train_step(h: Handle, Q: int, N: int, bound: float, G, neighbor, target, master,
+                        weights16, adam_m, adam_v, step: int, lr: float, loss_out, grad_out, ws):
+    _check(lib().pisco_ws_train_step(h.h, Q, N, bound, _ptr(G), _ptr(neighbor), _ptr(target),
+                                     _ptr(master), _ptr(weights16), _ptr(adam_m), _ptr(adam_v),
+                                     int(step), float(lr), _ptr(loss_out), _ptr(grad_out),
+                                     _ptr(ws), ws.numel() * ws.element_size()),
+           "pisco_ws_train_step", h.h)
 
 
 def pisco_maps(h: Handle, prob: Problem, opts: Opts, acs, maps_lr, maps_out, ws):

@@ -296,6 +296,14 @@ pisco_status_t pisco_gx(pisco_handle_t handle, const pisco_problem_t* prob,
 pisco_status_t pisco_eig(pisco_handle_t handle, int32_t Q, int64_t N, float bound,
                          const pisco_opts_t* opts, const void* G, void* maps, float* lam_min,
                          int32_t* iters, void* ws, size_t ws_bytes) {
+  return pisco_eig_from(handle, Q, N, bound, opts, G, nullptr, maps, lam_min, iters, ws,
+                        ws_bytes);
+}
+
+pisco_status_t pisco_eig_from(pisco_handle_t handle, int32_t Q, int64_t N, float bound,
+                              const pisco_opts_t* opts, const void* G, const void* init,
+                              void* maps, float* lam_min, int32_t* iters, void* ws,
+                              size_t ws_bytes) {
   Handle* h = reinterpret_cast<Handle*>(handle);
   (void)ws;
   (void)ws_bytes;
@@ -308,7 +316,7 @@ pisco_status_t pisco_eig(pisco_handle_t handle, int32_t Q, int64_t N, float boun
   if (o.power_iters < 0 || o.power_iters > 100000 || o.tol < 0.f)
     return fail(h, PISCO_ERR_ARG, "bad power-iteration options");
   return run_eig(h, Q, N, bound, o.power_iters, o.tol, static_cast<const float2*>(G),
-                 static_cast<float2*>(maps), lam_min, iters);
+                 static_cast<const float2*>(init), static_cast<float2*>(maps), lam_min, iters);
 }
 
 pisco_status_t pisco_maps(pisco_handle_t handle, const pisco_problem_t* prob,
@@ -352,7 +360,7 @@ pisco_status_t pisco_estimate(pisco_handle_t handle, const pisco_problem_t* prob
     return st;
   if ((st = run_gx(h, p, b, o.precision, e.basis, e.counts, e.G, e.stage_ws))) return st;
   float* lam = lam_min ? lam_min : e.lam;
-  if ((st = run_eig(h, p.Q, p.Nlr, float(p.L), o.power_iters, o.tol, e.G, e.maps_lr, lam,
+  if ((st = run_eig(h, p.Q, p.Nlr, float(p.L), o.power_iters, o.tol, e.G, nullptr, e.maps_lr, lam,
                     nullptr)))
     return st;
   return run_maps(h, p, o.phase_rule, a, e.maps_lr, static_cast<float2*>(maps_out),

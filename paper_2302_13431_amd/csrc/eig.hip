@@ -6,6 +6,9 @@
 // (0 <= G <= |Lambda| I because G = Phi^H conj(W) Phi with W a projector and
 // Phi^H Phi = |Lambda| I); the top eigenvector of Gs is the bottom one of G.
 //
+// The start vector is e_q* (q* = argmin_q G_qq) or, when given, the caller's
+// per-voxel vector (a warm start, normalised here).
+//
 // Mapping: one voxel per group of QG = next_pow2(Q) lanes; lane q holds row q
 // of Gs in registers and component q of the iterate.  The matrix-vector
 // product gathers the iterate with cross-lane shuffles inside the group and
@@ -28,6 +31,7 @@ __device__ inline float group_sum(float v) {
 template <int QG>
 __global__ void __launch_bounds__(256) k_power(const float2* __restrict__ G, int Q,
                                                long long N, float bound, int iters, float tol,
+                                               const float2* __restrict__ init,
                                                float2* __restrict__ maps,
                                                float* __restrict__ lam,
                                                int32_t* __restrict__ itout,
@@ -66,6 +70,16 @@ __global__ void __launch_bounds__(256) k_power(const float2* __restrict__ G, int
     }
   }
   float2 x = make_float2(lane == bidx ? 1.f : 0.f, 0.f);
+  if (init) {
+    // caller's start vector (a warm start); e_q* stays the fallback when it
+    // is zero or not finite
+    const float2 s0 = row ? init[size_t(lane) * N + v] : make_float2(0.f, 0.f);
+    const float nn = group_sum<QG>(s0.x * s0.x + s0.y * s0.y);
+    if (nn > 0.f && isfinite(nn)) {
+      const float inv = rsqrtf(nn);
+      x = make_float2(s0.x * inv, s0.y * inv);
+    }
+  }
   int done = 0, steps = 0;
   const float stop = tol * bound;
   const int cap = iters;
@@ -108,11 +122,12 @@ __global__ void __launch_bounds__(256) k_power(const float2* __restrict__ G, int
 }
 
 pisco_status_t run_eig(Handle* h, int Q, long long N, float bound, int iters, float tol,
-                       const float2* G, float2* maps, float* lam, int32_t* it_out) {
+                       const float2* G, const float2* init, float2* maps, float* lam,
+                       int32_t* it_out) {
   if (N <= 0) return PISCO_OK;
 #define PISCO_POWER(QG)                                                                \
   PISCO_KERNEL(h, k_power<QG>, dim3(ceil_div(N, 256 / QG)), dim3(256), 0, G, Q, N, bound, \
-               iters, tol, maps, lam, it_out, h->status_dev)
+               iters, tol, init, maps, lam, it_out, h->status_dev)
   if (Q <= 4)
     PISCO_POWER(4);
   else if (Q <= 8)

@@ -95,6 +95,17 @@ class Estimator:
         L.pisco_eig(self.h, Q, N, bound, opts or self.opts, G.contiguous(), maps, lam, it)
         return maps, lam, it
 
+    def eig_from(self, G, init, opts: Optional[L.Opts] = None):
+        """Power iteration from the given start vectors (float2 [Q][N_lr])."""
+        t = self.torch
+        N = self.Nlr
+        maps = self._alloc((self.Q, N), t.complex64)
+        lam = self._alloc((N,), t.float32)
+        it = self._alloc((N,), t.int32)
+        L.pisco_eig_from(self.h, self.Q, N, float(self.nsup), opts or self.opts, G.contiguous(),
+                         init.contiguous(), maps, lam, it)
+        return maps, lam, it
+
     def maps(self, acs, maps_lr):
         t = self.torch
         out = self._alloc((self.Q,) + self.grid_out, t.complex64)
