@@ -146,6 +146,76 @@ def map_error_defined(w, ref, out):
     return float(metrics.map_error(ref.maps, out)[mask].max())
 
 
+def learned_report(w, acs, n_scans: int, tol: float = 1e-4):
+    """Train the warm-start network (library kernels) on the method's own
+    eigenvectors of `n_scans` seeded scans of this workload's family, then
+    on the benchmark scan report the power-iteration steps to reach
+    ||G c - lambda c|| <= tol |Lambda| from the plain, neighbour-only and
+    learned starts, and the time of that eigen stage (for the learned start
+    it includes the coarse-grid field and solve, the neighbour gather and the
+    network)."""
+    import numpy as np
+    import torch
+    import paper_2302_13431_amd as P
+    from paper_2302_13431_amd.warmstart import LearnedSolver
+    from synth import generator
+    blk = BLOCKS.get(w.name, 0)
+    est = P.Estimator(w.Q, w.acs, w.radius, w.grid_lr, w.grid, block=blk)
+    est_c = P.Estimator(w.Q, w.acs, w.radius, P.coarse_grid(w.grid_lr), w.grid, block=blk)
+    ws = P.WarmStart(w.Q, seed=7)
+    solver = LearnedSolver(est, est_c, ws)
+    bound = float(est.nsup)
+    tight = P.make_opts(power_iters=4000, tol=1e-6, block=est.block)
+    t0 = time.perf_counter()
+    data = []
+    for s in range(n_scans):
+        sc = generator.make_scan(30000 + s, w.grid, w.Q, w.acs, 20, w.snr_db, keep_kspace=False)
+        G, Gc = solver.fields(torch.from_numpy(generator.as_device_input(sc.acs)).cuda())
+        target, _, _ = est.eig(G, opts=tight)
+        data.append((G, solver.neighbour(Gc), target))
+    torch.cuda.synchronize()
+    t_data = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    first = last = None
+    for ep in range(20):
+        tot = 0.0
+        for i in np.random.default_rng(ep).permutation(len(data)):
+            G, nb, target = data[i]
+            tot += float(ws.train_step(G, nb, target, bound, 1e-3).item())
+        first = tot / len(data) if first is None else first
+        last = tot / len(data)
+    t_train = time.perf_counter() - t0
+    G, Gc = solver.fields(acs)
+    opts = P.make_opts(power_iters=4000, tol=tol, block=est.block)
+    _, _, ip = est.eig(G, opts=opts)
+    _, _, inb = est.eig_from(G, solver.neighbour(Gc), opts)
+    _, _, il = solver.solve(G, Gc, opts)
+
+    def timed(fn, reps=20):
+        fn()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) / reps * 1e3
+
+    def learned_stage():
+        Gc_ = est_c.gx(*solver_basis)
+        return solver.solve(G, Gc_, opts)
+
+    gram = est.gram(acs)
+    _, basis, counts = est.nullspace(gram)
+    solver_basis = (basis, counts)
+    return {"voxels_trained": int(n_scans * est.Nlr), "train_scans": n_scans, "epochs": 20,
+            "loss_first_epoch": first, "loss_last_epoch": last,
+            "data_s": round(t_data, 2), "train_s": round(t_train, 2), "tol": tol,
+            "iters_mean": {"plain": float(ip.float().mean()), "neighbour": float(inb.float().mean()),
+                           "learned": float(il.float().mean())},
+            "eig_stage_ms": {"plain": timed(lambda: est.eig(G, opts=opts)),
+                             "learned": timed(learned_stage)}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -153,6 +223,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="2d_256x256_q32_acs32_r5")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-learned", action="store_true",
+                    help="skip training and measuring the learned warm start")
+    ap.add_argument("--learned-scans", type=int, default=64,
+                    help="training scans for the learned warm start (64 x 56^2 = 200k voxels)")
     ap.add_argument("--breakdown", action="store_true", help="per-kernel times to stderr")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run 5 device-to-device copies of MIB MiB (HBM counter "
@@ -261,6 +335,8 @@ def main():
                        "device_status": mixed["status"] | plain["status"],
                        "plain_fp32": {"value": plain["value"], "ms_per_step": plain["ms"]}},
             "roofline": roof}
+    if not args.no_learned:
+        line["config"]["learned_warm_start"] = learned_report(w, acs, args.learned_scans)
     if not args.no_cpu_baseline:
         base, ref = cpu_baseline(w, acs_np)
         line["cpu_baseline"] = base

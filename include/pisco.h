@@ -212,6 +212,49 @@ pisco_status_t pisco_eig_from(pisco_handle_t handle, int32_t Q, int64_t N,
                               float* lam_min, int32_t* iters, void* workspace,
                               size_t workspace_bytes);
 
+/* ---- Batches in one graph launch (not in the paper) ---------------------
+ * Many problems (slices or scans of any sizes and channel counts) run as
+ * one captured HIP graph, launched with a single call.  pisco_batch_create
+ *  1. times candidate nullspace block sizes and product-kernel wave counts
+ *     per distinct problem shape (eager runs on the first slice of that
+ *     shape; results cached in the handle) and keeps the fastest that
+ *     converges,
+ *  2. runs each slice once eagerly to fix its number of nullspace products,
+ *  3. captures every slice's whole path with that fixed schedule (no host
+ *     read-back) on up to 4 internal streams forked from one origin stream.
+ * A graph launch recomputes all maps from the ACS buffers' current
+ * contents; a slice whose data need more products than planned is flagged
+ * PISCO_FLAG_NOT_CONVERGED in the handle's status.  The buffers passed at
+ * creation (ACS, outputs, workspace) must stay allocated until
+ * pisco_batch_destroy.  The eager runs of creation already write the outputs. */
+typedef struct pisco_batch_s* pisco_batch_t;
+
+/* Workspace bytes for a batch (host-only); opts may be NULL (defaults) or
+ * an array of B options. */
+pisco_status_t pisco_batch_workspace_size(int32_t B, const pisco_problem_t* probs,
+                                          const pisco_opts_t* opts, size_t* bytes);
+
+/*   acs[i]      : device float2 [Q][acs] of slice i
+ *   maps_out[i] : device float2 [Q][grid_out] of slice i
+ *   lam_min     : NULL, or an array of B device float [N_lr] (entries may be NULL)
+ *   workspace   : 256-byte aligned, pisco_batch_workspace_size bytes */
+pisco_status_t pisco_batch_create(pisco_handle_t handle, int32_t B,
+                                  const pisco_problem_t* probs,
+                                  const pisco_opts_t* opts, const void* const* acs,
+                                  void* const* maps_out, float* const* lam_min,
+                                  void* workspace, size_t workspace_bytes,
+                                  pisco_batch_t* batch);
+
+/* One launch of the whole batch on the handle's stream. */
+pisco_status_t pisco_batch_launch(pisco_batch_t batch);
+
+/* The tuned block size, planned product count and product wave target of
+ * slice i (host-only). */
+pisco_status_t pisco_batch_slice_info(pisco_batch_t batch, int32_t i, int32_t* block,
+                                      int32_t* products, int32_t* ax_waves);
+
+pisco_status_t pisco_batch_destroy(pisco_batch_t batch);
+
 /* ---- Learned warm start (not in the paper) ------------------------------
  * A network predicts each voxel's start vector for the power iteration from
  * G(x) / |Lambda| (upper triangle: Q real diagonal entries, then Re and Im of

@@ -12,3 +12,4 @@ from ._lib import (  # noqa: F401
     pisco_ws_param_count, pisco_ws_train_step, pisco_ws_workspace_size)
 from .pipeline import Estimator  # noqa: F401
 from .warmstart import WarmStart, coarse_grid  # noqa: F401
+from .batch import Batch  # noqa: F401

@@ -91,6 +91,15 @@ _SIGS = {
     "pisco_ws_train_step": ([_P, ctypes.c_int32, ctypes.c_int64, ctypes.c_float, _P, _P, _P, _P,
                              _P, _P, _P, ctypes.c_int32, ctypes.c_float, _P, _P, _P,
                              ctypes.c_size_t], ctypes.c_int),
+    "pisco_batch_workspace_size": ([ctypes.c_int32, _P, _P, ctypes.POINTER(ctypes.c_size_t)],
+                                   ctypes.c_int),
+    "pisco_batch_create": ([_P, ctypes.c_int32, _P, _P, _P, _P, _P, _P, ctypes.c_size_t,
+                            ctypes.POINTER(_P)], ctypes.c_int),
+    "pisco_batch_launch": ([_P], ctypes.c_int),
+    "pisco_batch_slice_info": ([_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                                ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)],
+                               ctypes.c_int),
+    "pisco_batch_destroy": ([_P], ctypes.c_int),
     "pisco_trace_enable": ([_P, ctypes.c_int32, ctypes.c_char_p], ctypes.c_int),
     "pisco_trace_read": ([_P, _P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
 }

@@ -1,5 +1,6 @@
 // extern "C" entry points of libpisco: argument validation, workspace sizing
 // and stage chaining.  Kernels live in the .hip translation units.
+#include <cstdio>
 #include <cstring>
 #include <new>
 
@@ -114,6 +115,30 @@ EstLayout est_layout(const Plan& p, int b, void* ws) {
 }
 
 }  // namespace
+
+namespace pisco {
+
+size_t estimate_ws_size(const Plan& p, int b) { return est_layout(p, b, nullptr).total; }
+
+pisco_status_t estimate_core(Handle* h, const Plan& p, const pisco_opts_t& o, int b,
+                             const float2* acs, float2* maps_out, float* lam_min, void* ws,
+                             int fixed_products, int ax_waves, int32_t** counts_out) {
+  EstLayout e = est_layout(p, b, ws);
+  if (counts_out) *counts_out = e.counts;
+  pisco_status_t st;
+  if ((st = run_gram(h, p, acs, e.gram, e.stage_ws))) return st;
+  if ((st = run_nullspace(h, p, b, o.max_subspace_iters, e.gram, e.eigvals, e.basis, e.counts,
+                          e.stage_ws, fixed_products, ax_waves)))
+    return st;
+  if ((st = run_gx(h, p, b, o.precision, e.basis, e.counts, e.G, e.stage_ws))) return st;
+  float* lam = lam_min ? lam_min : e.lam;
+  if ((st = run_eig(h, p.Q, p.Nlr, float(p.L), o.power_iters, o.tol, e.G, nullptr, e.maps_lr,
+                    lam, nullptr)))
+    return st;
+  return run_maps(h, p, o.phase_rule, acs, e.maps_lr, maps_out, e.stage_ws);
+}
+
+}  // namespace pisco
 
 extern "C" {
 
@@ -351,20 +376,285 @@ pisco_status_t pisco_estimate(pisco_handle_t handle, const pisco_problem_t* prob
     return fail(h, PISCO_ERR_ARG, "null or unaligned pointer");
   if (o.precision < PISCO_PREC_FP32 || o.precision > PISCO_PREC_SPLIT_BF16)
     return fail(h, PISCO_ERR_ARG, "unknown precision");
-  EstLayout e = est_layout(p, b, ws);
-  if (ws_bytes < e.total) return fail(h, PISCO_ERR_WORKSPACE, "workspace too small for pisco_estimate");
-  const float2* a = static_cast<const float2*>(acs);
-  if ((st = run_gram(h, p, a, e.gram, e.stage_ws))) return st;
-  if ((st = run_nullspace(h, p, b, o.max_subspace_iters, e.gram, e.eigvals, e.basis, e.counts,
-                          e.stage_ws)))
-    return st;
-  if ((st = run_gx(h, p, b, o.precision, e.basis, e.counts, e.G, e.stage_ws))) return st;
-  float* lam = lam_min ? lam_min : e.lam;
-  if ((st = run_eig(h, p.Q, p.Nlr, float(p.L), o.power_iters, o.tol, e.G, nullptr, e.maps_lr, lam,
-                    nullptr)))
-    return st;
-  return run_maps(h, p, o.phase_rule, a, e.maps_lr, static_cast<float2*>(maps_out),
-                  e.stage_ws);
+  if (ws_bytes < estimate_ws_size(p, b))
+    return fail(h, PISCO_ERR_WORKSPACE, "workspace too small for pisco_estimate");
+  return estimate_core(h, p, o, b, static_cast<const float2*>(acs),
+                       static_cast<float2*>(maps_out), lam_min, ws, 0, 0);
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- batches
+
+struct BatchSlice {
+  Plan p;
+  pisco_opts_t o;
+  int b = 0, products = 0, ax_waves = 0;
+  const float2* acs = nullptr;
+  float2* out = nullptr;
+  float* lam = nullptr;
+  void* ws = nullptr;
+};
+
+struct pisco_batch_s {
+  Handle* h = nullptr;
+  std::vector<hipStream_t> streams;
+  std::vector<Handle*> sub;
+  std::vector<hipEvent_t> events;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::vector<BatchSlice> slices;
+};
+
+namespace {
+
+std::string shape_key(const Plan& p, const pisco_opts_t& o) {
+  char buf[256];
+  std::snprintf(buf, sizeof(buf), "%d:%d:%d,%d,%d:%.4f:%d,%d,%d:%d,%d,%d:%.5f:%d:%d:%.3g:%d",
+                p.D, p.Q, p.acs[0], p.acs[1], p.acs[2], p.radius, p.lr[0], p.lr[1], p.lr[2],
+                p.out[0], p.out[1], p.out[2], p.thresh, o.precision, o.power_iters, o.tol,
+                o.phase_rule);
+  return buf;
+}
+
+// Device status flags read back and cleared (synchronises the stream).
+pisco_status_t take_flags(Handle* h, uint32_t* flags) {
+  return pisco_get_status(reinterpret_cast<pisco_handle_t>(h), flags);
+}
+
+int max_block(const Plan& p, int b0) {
+  int hi = b0 + 32;
+  const int cap = p.n / 32 * 32 < 1024 ? p.n / 32 * 32 : 1024;
+  return hi <= cap ? hi : b0;
+}
+
+pisco_status_t batch_prepare(Handle* h, int32_t B, const pisco_problem_t* probs,
+                             const pisco_opts_t* opts, std::vector<BatchSlice>* out,
+                             size_t* total) {
+  if (B < 1 || !probs) return fail(h, PISCO_ERR_ARG, "batch: empty or null problem list");
+  size_t sum = 0;
+  out->clear();
+  for (int i = 0; i < B; ++i) {
+    BatchSlice sl;
+    pisco_status_t st = check_common(h, &probs[i], &sl.p);
+    if (st) return st;
+    sl.o = resolve(opts ? &opts[i] : nullptr);
+    std::string err;
+    if ((st = block_of(sl.p, sl.o, &sl.b, &err))) return fail(h, st, err.c_str());
+    if (sl.o.precision < PISCO_PREC_FP32 || sl.o.precision > PISCO_PREC_SPLIT_BF16)
+      return fail(h, PISCO_ERR_ARG, "unknown precision");
+    const int bmax = sl.o.block > 0 ? sl.b : max_block(sl.p, sl.b);
+    sum += (estimate_ws_size(sl.p, bmax) + 255) & ~size_t(255);
+    out->push_back(sl);
+  }
+  *total = sum;
+  return PISCO_OK;
+}
+
+void batch_free(pisco_batch_s* bt) {
+  if (!bt) return;
+  if (bt->exec) (void)hipGraphExecDestroy(bt->exec);
+  if (bt->graph) (void)hipGraphDestroy(bt->graph);
+  for (hipEvent_t e : bt->events) (void)hipEventDestroy(e);
+  for (Handle* s : bt->sub) delete s;  // status word and pinned buffer are borrowed
+  for (hipStream_t s : bt->streams) (void)hipStreamDestroy(s);
+  delete bt;
+}
+
+}  // namespace
+
+extern "C" {
+
+pisco_status_t pisco_batch_workspace_size(int32_t B, const pisco_problem_t* probs,
+                                          const pisco_opts_t* opts, size_t* bytes) {
+  Handle tmp;
+  std::vector<BatchSlice> sl;
+  if (!bytes) return PISCO_ERR_ARG;
+  return batch_prepare(&tmp, B, probs, opts, &sl, bytes);
+}
+
+pisco_status_t pisco_batch_create(pisco_handle_t handle, int32_t B, const pisco_problem_t* probs,
+                                  const pisco_opts_t* opts, const void* const* acs,
+                                  void* const* maps_out, float* const* lam_min, void* ws,
+                                  size_t ws_bytes, pisco_batch_t* batch) {
+  Handle* h = reinterpret_cast<Handle*>(handle);
+  if (!h || !batch) return PISCO_ERR_ARG;
+  *batch = nullptr;
+  std::vector<BatchSlice> sl;
+  size_t need = 0;
+  pisco_status_t st = batch_prepare(h, B, probs, opts, &sl, &need);
+  if (st) return st;
+  if (!acs || !maps_out || !ws || !aligned(ws))
+    return fail(h, PISCO_ERR_ARG, "batch: null or unaligned pointer");
+  if (ws_bytes < need) return fail(h, PISCO_ERR_WORKSPACE, "batch: workspace too small");
+  char* base = static_cast<char*>(ws);
+  for (int i = 0; i < B; ++i) {
+    if (!acs[i] || !maps_out[i]) return fail(h, PISCO_ERR_ARG, "batch: null slice pointer");
+    sl[i].acs = static_cast<const float2*>(acs[i]);
+    sl[i].out = static_cast<float2*>(maps_out[i]);
+    sl[i].lam = lam_min ? lam_min[i] : nullptr;
+    sl[i].ws = base;
+    const int bmax = sl[i].o.block > 0 ? sl[i].b : max_block(sl[i].p, sl[i].b);
+    base += (estimate_ws_size(sl[i].p, bmax) + 255) & ~size_t(255);
+  }
+  uint32_t saved = 0, flags = 0;
+  if ((st = take_flags(h, &saved))) return st;
+  hipEvent_t t0 = nullptr, t1 = nullptr;
+  hipError_t e = hipEventCreate(&t0);
+  if (e == hipSuccess) e = hipEventCreate(&t1);
+  if (e != hipSuccess) return hip_check(h, e, "batch: events");
+  auto cleanup_events = [&]() {
+    (void)hipEventDestroy(t0);
+    (void)hipEventDestroy(t1);
+  };
+  const uint32_t bad = PISCO_FLAG_NONFINITE | PISCO_FLAG_NOT_CONVERGED | PISCO_FLAG_BLOCK_TOO_SMALL;
+  // autotune per shape (timed eager runs), then one eager planning run per
+  // slice that fixes its product count
+  for (int i = 0; i < B; ++i) {
+    BatchSlice& x = sl[i];
+    const std::string key = shape_key(x.p, x.o) + (x.o.block > 0 ? ":b" + std::to_string(x.b) : "");
+    auto it = h->tuned.find(key);
+    if (it == h->tuned.end()) {
+      std::vector<int> blocks{x.b};
+      if (x.o.block <= 0 && max_block(x.p, x.b) != x.b) blocks.push_back(max_block(x.p, x.b));
+      const int waves[3] = {1024, 2048, 4096};
+      float best = 3.0e38f;
+      std::pair<int, int> choice(x.b, 2048);
+      for (int bb : blocks)
+        for (int wv : waves) {
+          float ms = 0.f;
+          for (int rep = 0; rep < 2 && !st; ++rep) {
+            if (rep == 1) e = hipEventRecord(t0, h->stream);
+            st = estimate_core(h, x.p, x.o, bb, x.acs, x.out, x.lam, x.ws, 0, wv);
+            if (rep == 1 && e == hipSuccess) e = hipEventRecord(t1, h->stream);
+          }
+          if (st) {
+            cleanup_events();
+            return st;
+          }
+          if (e == hipSuccess) e = hipEventSynchronize(t1);
+          if (e == hipSuccess) e = hipEventElapsedTime(&ms, t0, t1);
+          if (e != hipSuccess) {
+            cleanup_events();
+            return hip_check(h, e, "batch: tuning");
+          }
+          if ((st = take_flags(h, &flags))) {
+            cleanup_events();
+            return st;
+          }
+          if (!(flags & bad) && ms < best) {
+            best = ms;
+            choice = std::make_pair(bb, wv);
+          }
+        }
+      it = h->tuned.emplace(key, choice).first;
+    }
+    x.b = it->second.first;
+    x.ax_waves = it->second.second;
+    int32_t* counts = nullptr;
+    if ((st = estimate_core(h, x.p, x.o, x.b, x.acs, x.out, x.lam, x.ws, 0, x.ax_waves, &counts))) {
+      cleanup_events();
+      return st;
+    }
+    int32_t hc[4] = {0, 0, 0, 0};
+    e = hipMemcpyAsync(hc, counts, sizeof(hc), hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) {
+      cleanup_events();
+      return hip_check(h, e, "batch: planning");
+    }
+    x.products = hc[2] > 3 ? hc[2] : 3;
+  }
+  cleanup_events();
+  if ((st = take_flags(h, &flags))) return st;
+  // restore the flags the caller had not read yet
+  h->host_pinned[2] = saved | flags;
+  e = hipMemcpyAsync(h->status_dev, h->host_pinned + 2, sizeof(uint32_t), hipMemcpyHostToDevice,
+                     h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return hip_check(h, e, "batch: flags");
+
+  // capture: the slices spread over a few streams (default priority) that
+  // fork from and join back into the first one
+  pisco_batch_s* bt = new (std::nothrow) pisco_batch_s();
+  if (!bt) return fail(h, PISCO_ERR_ARG, "batch: out of host memory");
+  bt->h = h;
+  bt->slices = sl;
+  const int S = B < 4 ? B : 4;
+  for (int k = 0; k < S && e == hipSuccess; ++k) {
+    hipStream_t s = nullptr;
+    e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+    if (e == hipSuccess) {
+      bt->streams.push_back(s);
+      Handle* sh = new Handle();
+      sh->stream = s;
+      sh->status_dev = h->status_dev;
+      sh->host_pinned = h->host_pinned;
+      bt->sub.push_back(sh);
+    }
+  }
+  for (int k = 0; k < S + 1 && e == hipSuccess; ++k) {
+    hipEvent_t ev = nullptr;
+    e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (e == hipSuccess) bt->events.push_back(ev);
+  }
+  if (e != hipSuccess) {
+    batch_free(bt);
+    return hip_check(h, e, "batch: streams");
+  }
+  hipStream_t origin = bt->streams[0];
+  e = hipStreamBeginCapture(origin, hipStreamCaptureModeRelaxed);
+  if (e == hipSuccess) e = hipEventRecord(bt->events[0], origin);
+  for (int k = 1; k < S && e == hipSuccess; ++k) e = hipStreamWaitEvent(bt->streams[k], bt->events[0], 0);
+  for (int i = 0; i < B && e == hipSuccess && !st; ++i) {
+    const BatchSlice& x = bt->slices[i];
+    st = estimate_core(bt->sub[i % S], x.p, x.o, x.b, x.acs, x.out, x.lam, x.ws, x.products,
+                       x.ax_waves);
+  }
+  for (int k = 1; k < S && e == hipSuccess; ++k) {
+    e = hipEventRecord(bt->events[k], bt->streams[k]);
+    if (e == hipSuccess) e = hipStreamWaitEvent(origin, bt->events[k], 0);
+  }
+  hipGraph_t g = nullptr;
+  const hipError_t e_end = hipStreamEndCapture(origin, &g);
+  bt->graph = g;
+  if (e == hipSuccess) e = e_end;
+  if (st || e != hipSuccess) {
+    batch_free(bt);
+    if (st) return st;
+    return hip_check(h, e, "batch: capture");
+  }
+  e = hipGraphInstantiate(&bt->exec, bt->graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    batch_free(bt);
+    return hip_check(h, e, "batch: instantiate");
+  }
+  *batch = bt;
+  return PISCO_OK;
+}
+
+pisco_status_t pisco_batch_launch(pisco_batch_t batch) {
+  if (!batch || !batch->exec) return PISCO_ERR_ARG;
+  const hipError_t e = hipGraphLaunch(batch->exec, batch->h->stream);
+  return hip_check(batch->h, e, "pisco_batch_launch");
+}
+
+pisco_status_t pisco_batch_slice_info(pisco_batch_t batch, int32_t i, int32_t* block,
+                                      int32_t* products, int32_t* ax_waves) {
+  if (!batch || i < 0 || i >= int32_t(batch->slices.size())) return PISCO_ERR_ARG;
+  const BatchSlice& x = batch->slices[i];
+  if (block) *block = x.b;
+  if (products) *products = x.products;
+  if (ax_waves) *ax_waves = x.ax_waves;
+  return PISCO_OK;
+}
+
+pisco_status_t pisco_batch_destroy(pisco_batch_t batch) {
+  if (!batch) return PISCO_ERR_ARG;
+  (void)hipStreamSynchronize(batch->h->stream);
+  for (hipStream_t s : batch->streams) (void)hipStreamSynchronize(s);
+  batch_free(batch);
+  return PISCO_OK;
 }
 
 }  // extern "C"

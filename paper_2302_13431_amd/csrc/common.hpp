@@ -5,6 +5,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -68,6 +69,8 @@ struct Handle {
   std::vector<hipEvent_t> event_pool;
   size_t events_used = 0;
   std::vector<TraceRec> records;
+  // autotuner results per problem shape: nullspace block and product waves
+  std::map<std::string, std::pair<int, int>> tuned;
 };
 
 // Brackets one kernel launch with events when tracing is on and the kernel
@@ -196,9 +199,13 @@ size_t layout_maps(const Plan& p, void* ws, MapsWs* out);
 
 pisco_status_t run_gram(Handle* h, const Plan& p, const float2* acs, float2* gram,
                         void* ws);
+// fixed_products > 0: that many products and one Rayleigh-Ritz step, no host
+// read-back (graph-capturable); 0: adaptive schedule with host reads.
+// ax_waves: wave count targeted by the split-K product (0 = 2048).
 pisco_status_t run_nullspace(Handle* h, const Plan& p, int b, int max_iters,
                              const float2* gram, double* eigvals, double2* basis,
-                             int32_t* counts, void* ws);
+                             int32_t* counts, void* ws, int fixed_products = 0,
+                             int ax_waves = 0);
 pisco_status_t run_gx(Handle* h, const Plan& p, int b, int precision, const double2* basis,
                       const int32_t* counts, float2* G, void* ws);
 pisco_status_t run_eig(Handle* h, int Q, long long N, float bound, int iters,
@@ -206,6 +213,14 @@ pisco_status_t run_eig(Handle* h, int Q, long long N, float bound, int iters,
                        float* lam, int32_t* it_out);
 pisco_status_t run_maps(Handle* h, const Plan& p, int phase_rule, const float2* acs,
                         const float2* maps_lr, float2* maps_out, void* ws);
+
+// The whole path for one problem on h's stream (pisco_estimate's body);
+// fixed_products / ax_waves as for run_nullspace; counts_out (nullable)
+// receives the device address of the nullspace counts in `ws`.
+size_t estimate_ws_size(const Plan& p, int b);
+pisco_status_t estimate_core(Handle* h, const Plan& p, const pisco_opts_t& o, int b,
+                             const float2* acs, float2* maps_out, float* lam_min, void* ws,
+                             int fixed_products, int ax_waves, int32_t** counts_out = nullptr);
 
 // Eigen-decomposition H = U diag(theta) U^H of a b x b Hermitian matrix
 // (column-major, FP64), eigenvalues descending, 1 <= b <= 1024; `ws` holds

@@ -579,7 +579,7 @@ pisco_status_t orth(NullCtx& c, const double2* Y, double2* tmp, double* rdiag, d
 
 pisco_status_t run_nullspace(Handle* h, const Plan& p, int b, int max_iters,
                              const float2* gram, double* eigvals, double2* basis,
-                             int32_t* counts, void* ws) {
+                             int32_t* counts, void* ws, int fixed_products, int ax_waves) {
   NullCtx c{h, &p, b, {}};
   layout_null(p, b, ws, &c.w);
   hipStream_t s = h->stream;
@@ -597,9 +597,9 @@ pisco_status_t run_nullspace(Handle* h, const Plan& p, int b, int max_iters,
   const double thr2 = double(p.thresh) * double(p.thresh);
   const double tol = 1e-10;
   const int margin = b / 8 > 4 ? b / 8 : 4;
-  // K slices so that the product runs about 2048 waves (at most kAxSplit)
+  // K slices so that the product runs about ax_waves waves (at most kAxSplit)
   const long long tiles = 1LL * ceil_div(n, 32) * ceil_div(b, 32);
-  int want = int(ceil_div(2048, tiles));
+  int want = int(ceil_div(ax_waves > 0 ? ax_waves : 2048, tiles));
   want = want < 1 ? 1 : (want > kAxSplit ? kAxSplit : want);
   const int kchunk = 16 * int(ceil_div(ceil_div(n, want), 16));
   const int ksplit = int(ceil_div(n, kchunk));
@@ -617,8 +617,13 @@ pisco_status_t run_nullspace(Handle* h, const Plan& p, int b, int max_iters,
   // ones from the Ritz values and residuals.  After the third product the
   // scaled block stays well conditioned (kappa of order 10 for two more
   // products), so up to three products share one Cholesky QR pass.
+  // With fixed_products > 0 the schedule is set in advance (that many
+  // products, one Rayleigh-Ritz step at the end) and nothing is read back on
+  // the host, so the whole call can be captured in a graph; convergence is
+  // still tested on the device and reported through counts and the status.
   constexpr int kUnscheduled = 1 << 30;
-  int rr_at = kUnscheduled;  // product count at which to run Rayleigh-Ritz
+  const bool fixed = fixed_products > 0;
+  int rr_at = fixed ? (fixed_products < 3 ? 3 : fixed_products) : kUnscheduled;
   int done = 0;
   while (true) {
     if ((st = product(X, Z))) return st;
@@ -634,7 +639,7 @@ pisco_status_t run_nullspace(Handle* h, const Plan& p, int b, int max_iters,
         std::swap(X, Z);
         ++done;
       }
-      const bool predict = done == 3 && rr_at == kUnscheduled;
+      const bool predict = !fixed && done == 3 && rr_at == kUnscheduled;
       if ((st = orth(c, Z, X, predict ? c.w.resid : nullptr, done == 1 ? 1e-12 : 0.0)))
         return st;
       if (predict) {
@@ -657,6 +662,7 @@ pisco_status_t run_nullspace(Handle* h, const Plan& p, int b, int max_iters,
     PISCO_KERNEL(h, k_colresid, dim3(rchunks, b), dim3(256), 0, X, W, c.w.theta, rpart, n, b);
     PISCO_KERNEL(h, k_control, dim3(1), dim3(64), 0, c.w.theta, rpart, rchunks, b, thr2, tol,
                  margin, done - 1, c.w.ctl, h->status_dev);
+    if (fixed) break;
     hipError_t e = hipMemcpyAsync(h->host_pinned, c.w.ctl, 6 * sizeof(int),
                                   hipMemcpyDeviceToHost, s);
     if (e != hipSuccess) return hip_check(h, e, "nullspace ctl copy");
