@@ -173,6 +173,8 @@ def learned_report(w, acs, n_scans: int, tol: float = 1e-4):
         G, Gc = solver.fields(torch.from_numpy(generator.as_device_input(sc.acs)).cuda())
         target, _, _ = est.eig(G, opts=tight)
         data.append((G, solver.neighbour(Gc), target))
+        if s % 16 == 15:
+            print(f"learned: {s + 1} training scans", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t_data = time.perf_counter() - t0
     t0 = time.perf_counter()
@@ -216,6 +218,71 @@ def learned_report(w, acs, n_scans: int, tol: float = 1e-4):
                              "learned": timed(learned_stage)}}
 
 
+def batched_report(steps: int):
+    """64 seeded 2D slices with uneven grids (128^2, 192^2, 256^2, 256x320),
+    Q in {8, 16, 32}, ACS 24-40, radius 3-6, 30 dB: all slices in one graph
+    launch (pisco_batch_*, autotuned, fixed nullspace schedules) against the
+    same slices as one pisco_estimate call each with the same block sizes
+    (adaptive schedules, host reads).  Throughput is output voxels of all
+    slices per second."""
+    import numpy as np
+    import torch
+    import paper_2302_13431_amd as P
+    from synth import as_device_input, workloads
+    slices = workloads.batch_slices()
+    acs = [torch.from_numpy(as_device_input(s.scan(keep_kspace=False).acs)).cuda() for s in slices]
+    print("batched: slices generated", file=sys.stderr, flush=True)
+    nout = sum(int(np.prod(s.grid)) for s in slices)
+    specs = [{"Q": s.Q, "acs": s.acs, "radius": s.radius, "grid_lr": s.grid_lr,
+              "grid_out": s.grid} for s in slices]
+    t = time.perf_counter()
+    b = P.Batch(specs, acs)
+    torch.cuda.synchronize()
+    t_plan = time.perf_counter() - t
+    print(f"batched: planned and captured in {t_plan:.1f} s", file=sys.stderr, flush=True)
+    # per-slice launches with the same (tuned) block sizes
+    ests = [P.Estimator(s.Q, s.acs, s.radius, s.grid_lr, s.grid, block=b.info(i)[0])
+            for i, s in enumerate(slices)]
+    outs = [torch.empty((s.Q,) + tuple(s.grid), dtype=torch.complex64, device="cuda")
+            for s in slices]
+    flags_eager = 0
+    for e, a, o in zip(ests, acs, outs):
+        e.estimate(a, o)
+        flags_eager |= e.status()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    reps = max(1, steps // 4)
+    for _ in range(reps):
+        for e, a, o in zip(ests, acs, outs):
+            e.estimate(a, o)
+    torch.cuda.synchronize()
+    t_eager = (time.perf_counter() - t) / reps
+    print("batched: eager timed", file=sys.stderr, flush=True)
+    b.launch()
+    torch.cuda.synchronize()
+    flags_graph = b.status()
+    t = time.perf_counter()
+    for _ in range(steps):
+        b.launch()
+    torch.cuda.synchronize()
+    t_graph = (time.perf_counter() - t) / steps
+    flags_graph |= b.status()
+    err = 0.0
+    from oracle.metrics import map_error
+    for i in range(len(slices)):
+        e = map_error(outs[i].cpu().numpy(), b.outputs[i].cpu().numpy())
+        err = max(err, float(np.percentile(e, 99)))
+    blocks = sorted({b.info(i)[0] for i in range(len(slices))})
+    b.close()
+    return {"slices": len(slices), "voxels_out": nout,
+            "graph": {"Mvoxel_s": nout / t_graph / 1e6, "ms": t_graph * 1e3,
+                      "device_status": flags_graph},
+            "per_slice_launches": {"Mvoxel_s": nout / t_eager / 1e6, "ms": t_eager * 1e3,
+                                   "device_status": flags_eager},
+            "plan_and_tune_s": round(t_plan, 2), "tuned_blocks": blocks,
+            "graph_vs_eager_map_error_p99_max": err}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -225,6 +292,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-learned", action="store_true",
                     help="skip training and measuring the learned warm start")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the batch of 64 uneven slices in one graph launch")
     ap.add_argument("--learned-scans", type=int, default=64,
                     help="training scans for the learned warm start (64 x 56^2 = 200k voxels)")
     ap.add_argument("--breakdown", action="store_true", help="per-kernel times to stderr")
@@ -337,6 +406,8 @@ def main():
             "roofline": roof}
     if not args.no_learned:
         line["config"]["learned_warm_start"] = learned_report(w, acs, args.learned_scans)
+    if not args.no_batched:
+        line["config"]["batched"] = batched_report(args.steps)
     if not args.no_cpu_baseline:
         base, ref = cpu_baseline(w, acs_np)
         line["cpu_baseline"] = base

@@ -215,11 +215,14 @@ pisco_status_t pisco_eig_from(pisco_handle_t handle, int32_t Q, int64_t N,
 /* ---- Batches in one graph launch (not in the paper) ---------------------
  * Many problems (slices or scans of any sizes and channel counts) run as
  * one captured HIP graph, launched with a single call.  pisco_batch_create
- *  1. times candidate nullspace block sizes and product-kernel wave counts
- *     per distinct problem shape (eager runs on the first slice of that
- *     shape; results cached in the handle) and keeps the fastest that
- *     converges,
- *  2. runs each slice once eagerly to fix its number of nullspace products,
+ *  1. times candidate nullspace block sizes (the automatic one and +32,
+ *     widened by 32 up to +96 while none converges) and product-kernel wave
+ *     counts (1024, 2048, 4096) per distinct problem shape (eager runs on
+ *     the first slice of that shape; results cached in the handle) and
+ *     keeps the fastest that converges,
+ *  2. runs each slice once eagerly to fix its number of nullspace products
+ *     (a slice whose signal rank reaches the tuned block is given a block
+ *     wider by 32 until it fits or the limit is reached),
  *  3. captures every slice's whole path with that fixed schedule (no host
  *     read-back) on up to 4 internal streams forked from one origin stream.
  * A graph launch recomputes all maps from the ACS buffers' current

@@ -422,10 +422,11 @@ pisco_status_t take_flags(Handle* h, uint32_t* flags) {
   return pisco_get_status(reinterpret_cast<pisco_handle_t>(h), flags);
 }
 
+// Largest nullspace block the tuner may try (the workspace is sized for it):
+// the automatic block plus 96, within the Gram dimension and 1024.
 int max_block(const Plan& p, int b0) {
-  int hi = b0 + 32;
   const int cap = p.n / 32 * 32 < 1024 ? p.n / 32 * 32 : 1024;
-  return hi <= cap ? hi : b0;
+  return b0 + 96 <= cap ? b0 + 96 : (cap > b0 ? cap : b0);
 }
 
 pisco_status_t batch_prepare(Handle* h, int32_t B, const pisco_problem_t* probs,
@@ -497,7 +498,7 @@ pisco_status_t pisco_batch_create(pisco_handle_t handle, int32_t B, const pisco_
     const int bmax = sl[i].o.block > 0 ? sl[i].b : max_block(sl[i].p, sl[i].b);
     base += (estimate_ws_size(sl[i].p, bmax) + 255) & ~size_t(255);
   }
-  uint32_t saved = 0, flags = 0;
+  uint32_t saved = 0, flags = 0, tune_flags = 0;
   if ((st = take_flags(h, &saved))) return st;
   hipEvent_t t0 = nullptr, t1 = nullptr;
   hipError_t e = hipEventCreate(&t0);
@@ -516,11 +517,14 @@ pisco_status_t pisco_batch_create(pisco_handle_t handle, int32_t B, const pisco_
     auto it = h->tuned.find(key);
     if (it == h->tuned.end()) {
       std::vector<int> blocks{x.b};
-      if (x.o.block <= 0 && max_block(x.p, x.b) != x.b) blocks.push_back(max_block(x.p, x.b));
+      const int bcap = x.o.block > 0 ? x.b : max_block(x.p, x.b);
+      if (x.b + 32 <= bcap) blocks.push_back(x.b + 32);
       const int waves[3] = {1024, 2048, 4096};
       float best = 3.0e38f;
       std::pair<int, int> choice(x.b, 2048);
-      for (int bb : blocks)
+      bool found = false;
+      for (size_t bi = 0; bi < blocks.size(); ++bi) {
+        const int bb = blocks[bi];
         for (int wv : waves) {
           float ms = 0.f;
           for (int rep = 0; rep < 2 && !st; ++rep) {
@@ -538,36 +542,56 @@ pisco_status_t pisco_batch_create(pisco_handle_t handle, int32_t B, const pisco_
             cleanup_events();
             return hip_check(h, e, "batch: tuning");
           }
-          if ((st = take_flags(h, &flags))) {
+          if ((st = take_flags(h, &tune_flags))) {
             cleanup_events();
             return st;
           }
-          if (!(flags & bad) && ms < best) {
+          if (!(tune_flags & bad) && ms < best) {
             best = ms;
             choice = std::make_pair(bb, wv);
+            found = true;
           }
         }
+        // no candidate converged yet (signal rank at the block size): widen
+        if (!found && bi + 1 == blocks.size() && bb + 32 <= bcap) blocks.push_back(bb + 32);
+      }
       it = h->tuned.emplace(key, choice).first;
     }
     x.b = it->second.first;
     x.ax_waves = it->second.second;
-    int32_t* counts = nullptr;
-    if ((st = estimate_core(h, x.p, x.o, x.b, x.acs, x.out, x.lam, x.ws, 0, x.ax_waves, &counts))) {
-      cleanup_events();
-      return st;
+    // planning run; the signal rank depends on the data, so a slice whose
+    // rank reaches the tuned block gets a wider block of its own
+    const int bcap = x.o.block > 0 ? x.b : max_block(x.p, x.b);
+    uint32_t plan_flags = 0;
+    while (true) {
+      int32_t* counts = nullptr;
+      if ((st = estimate_core(h, x.p, x.o, x.b, x.acs, x.out, x.lam, x.ws, 0, x.ax_waves,
+                              &counts))) {
+        cleanup_events();
+        return st;
+      }
+      int32_t hc[4] = {0, 0, 0, 0};
+      e = hipMemcpyAsync(hc, counts, sizeof(hc), hipMemcpyDeviceToHost, h->stream);
+      if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+      if (e != hipSuccess) {
+        cleanup_events();
+        return hip_check(h, e, "batch: planning");
+      }
+      if ((st = take_flags(h, &plan_flags))) {
+        cleanup_events();
+        return st;
+      }
+      // one product beyond the eager run's count: the fixed schedule has a
+      // single Rayleigh-Ritz step where the eager run may have had two
+      x.products = (hc[2] > 3 ? hc[2] : 3) + 1;
+      if (!(plan_flags & PISCO_FLAG_BLOCK_TOO_SMALL) || x.b + 32 > bcap) break;
+      x.b += 32;
     }
-    int32_t hc[4] = {0, 0, 0, 0};
-    e = hipMemcpyAsync(hc, counts, sizeof(hc), hipMemcpyDeviceToHost, h->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
-    if (e != hipSuccess) {
-      cleanup_events();
-      return hip_check(h, e, "batch: planning");
-    }
-    x.products = hc[2] > 3 ? hc[2] : 3;
+    flags |= plan_flags;
   }
   cleanup_events();
-  if ((st = take_flags(h, &flags))) return st;
-  // restore the flags the caller had not read yet
+  // restore the flags the caller had not read yet, plus those of the
+  // planning runs (the tuning runs' flags only steered the choice)
   h->host_pinned[2] = saved | flags;
   e = hipMemcpyAsync(h->status_dev, h->host_pinned + 2, sizeof(uint32_t), hipMemcpyHostToDevice,
                      h->stream);
