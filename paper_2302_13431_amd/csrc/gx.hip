@@ -110,9 +110,8 @@ __global__ void __launch_bounds__(256) k_herk(const float2* __restrict__ F,
 // x_hi) and a product is x_hi y_hi + x_hi y_lo + x_lo y_hi (three MFMAs; the
 // dropped x_lo y_lo is below 2^-22 relative).  kPrec = PISCO_PREC_SPLIT_BF16:
 // three BF16 parts hi, mid, lo and the six cross products of total order
-// <= 2.  Workgroup: 16 frequencies, 4 waves of 4 frequencies each; r runs
-// in chunks of 16 staged in LDS as [r][q][f] (f padded to 17 against bank
-// conflicts).  For one frequency the Q x Q result is C = A^H A with A the
+// <= 2.  Workgroup: 4 frequencies, one per wave; r runs in chunks of 16
+// staged in LDS as [r][q][f] (f padded to 5 against bank conflicts).  For one frequency the Q x Q result is C = A^H A with A the
 // r x Q matrix F[.][.][f]: Re C = Ar^T Ar + Ai^T Ai, Im C = Ar^T Ai - Ai^T Ar,
 // as 16 x 16 x 16 blocks (upper blocks only).  Operand lanes: lane l holds
 // row (column) l % 16 at k = 4 (l / 16) + j, j < 4; accumulator element v of
@@ -190,7 +189,7 @@ __global__ void __launch_bounds__(256) k_herk_mfma(const float2* __restrict__ F,
                                                    float scale) {
   using Ops = SplitOps<kPrec>;
   using vec = typename Ops::vec;
-  constexpr int kFB = 16, kFP = 17, kFW = 4;  // frequencies per block / padded / per wave
+  constexpr int kFB = 4, kFP = 5, kFW = 1;  // frequencies per block / padded / per wave
   __shared__ float2 tile[16 * kMaxQ * kFP];
   const int t = threadIdx.x, wv = t >> 6, l = t & 63;
   const int li = l & 15, kg = l >> 4;
@@ -348,9 +347,9 @@ pisco_status_t run_gx(Handle* h, const Plan& p, int b, int precision, const doub
     // |F_r(f, q)| <= sum_n |v_r[n, q]| <= sqrt(|Lambda|) for unit v_r: scale
     // so that this bound maps below 2^15 (FP16 holds up to 65504)
     const float scale = std::ldexp(1.f, int(std::floor(15.0 - 0.5 * std::log2(double(p.L)))));
-    PISCO_KERNEL(h, k_herk_mfma<PISCO_PREC_SPLIT_F16>, dim3(ceil_div(p.nK, 16)), dim3(256), 0, w.Fh, counts, w.Kh, Q, p.nK, scale);
+    PISCO_KERNEL(h, k_herk_mfma<PISCO_PREC_SPLIT_F16>, dim3(ceil_div(p.nK, 4)), dim3(256), 0, w.Fh, counts, w.Kh, Q, p.nK, scale);
   } else if (precision == PISCO_PREC_SPLIT_BF16) {
-    PISCO_KERNEL(h, k_herk_mfma<PISCO_PREC_SPLIT_BF16>, dim3(ceil_div(p.nK, 16)), dim3(256), 0, w.Fh, counts, w.Kh, Q, p.nK, 1.f);
+    PISCO_KERNEL(h, k_herk_mfma<PISCO_PREC_SPLIT_BF16>, dim3(ceil_div(p.nK, 4)), dim3(256), 0, w.Fh, counts, w.Kh, Q, p.nK, 1.f);
   } else {
     const int FT = 256 / Q;
     PISCO_KERNEL(h, k_herk, dim3(ceil_div(p.nK, FT)), dim3(256), 0, w.Fh, counts, w.Kh, Q, p.nK, FT);

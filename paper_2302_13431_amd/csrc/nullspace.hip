@@ -108,18 +108,23 @@ __global__ void __launch_bounds__(64) k_gemm_ax(const float2* __restrict__ A,
   ax_load(cur, Ar0, Ar1, v0, v1, X0, X1, kbeg, lk, kend);
   for (int k0 = kbeg; k0 < kend; k0 += 16) {
     if (k0 + 16 < kend) ax_load(nxt, Ar0, Ar1, v0, v1, X0, X1, k0 + 16, lk, kend);
+    // the eight accumulators are updated in turn, so that the two products
+    // into one accumulator are never back to back
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
 #pragma unroll
-      for (int i = 0; i < 2; ++i) {
-        const double ar = cur.a[i][s].x, ai = cur.a[i][s].y;
+      for (int half = 0; half < 2; ++half) {
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
-          const double xr = cur.x[j][s].x, xi = cur.x[j][s].y;
-          cr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, xr, cr[i][j], 0, 0, 0);
-          cr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(-ai, xi, cr[i][j], 0, 0, 0);
-          ci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, xi, ci[i][j], 0, 0, 0);
-          ci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, xr, ci[i][j], 0, 0, 0);
+        for (int i = 0; i < 2; ++i) {
+          const double ar = cur.a[i][s].x, ai = cur.a[i][s].y;
+#pragma unroll
+          for (int j = 0; j < 2; ++j) {
+            const double xr = cur.x[j][s].x, xi = cur.x[j][s].y;
+            cr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(half ? -ai : ar, half ? xi : xr,
+                                                            cr[i][j], 0, 0, 0);
+            ci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(half ? ai : ar, half ? xr : xi,
+                                                            ci[i][j], 0, 0, 0);
+          }
         }
       }
     }
@@ -149,90 +154,120 @@ __global__ void k_sum_parts(const double2* __restrict__ parts, double2* __restri
 }
 
 // part[chunk] = P[rows of chunk, :]^H Q[rows of chunk, :]; P, Q column-major
-// n x b; part is column-major b x b.  Rows are split in chunks of 256.
-__global__ void __launch_bounds__(256) k_gemm_tn(const double2* __restrict__ P,
-                                                 const double2* __restrict__ Qm,
-                                                 double2* __restrict__ part, int n, int b) {
-  __shared__ double2 Ps[32][33];
-  __shared__ double2 Qs[32][33];
-  const int t = threadIdx.x;
-  const int ti = t >> 4, tj = t & 15;
+// n x b (b a multiple of 32); part is column-major b x b.  Rows are split
+// in chunks of kTnRows.  One wave per 32 x 32 block of the result and row
+// chunk, on FP64 matrix cores (operand and accumulator lanes as in
+// k_gemm_ax): Re += Pr Qr + Pi Qi, Im += Pr Qi - Pi Qr.
+__global__ void __launch_bounds__(64) k_gemm_tn(const double2* __restrict__ P,
+                                                const double2* __restrict__ Qm,
+                                                double2* __restrict__ part, int n, int b) {
+  const int l = threadIdx.x, li = l & 15, lk = l >> 4;
   const int i0 = blockIdx.x * 32, j0 = blockIdx.y * 32;
-  const int rbeg = blockIdx.z * 256, rend = min(n, rbeg + 256);
-  double2 acc[2][2];
-  for (int a = 0; a < 2; ++a)
-    for (int c = 0; c < 2; ++c) acc[a][c] = make_double2(0.0, 0.0);
-  for (int r0 = rbeg; r0 < rend; r0 += 32) {
-    for (int e = t; e < 1024; e += 256) {
-      const int cc = e >> 5, rr = e & 31;
-      const int gr = r0 + rr;
-      double2 pv = make_double2(0.0, 0.0), qv = make_double2(0.0, 0.0);
-      if (gr < rend) {
-        if (i0 + cc < b) pv = P[size_t(i0 + cc) * n + gr];
-        if (j0 + cc < b) qv = Qm[size_t(j0 + cc) * n + gr];
+  const int rbeg = blockIdx.z * kTnRows, rend = min(n, rbeg + kTnRows);
+  const double2* Pc[2] = {P + size_t(i0 + li) * n, P + size_t(i0 + 16 + li) * n};
+  const double2* Qc[2] = {Qm + size_t(j0 + li) * n, Qm + size_t(j0 + 16 + li) * n};
+  f64x4 cr[2][2], ci[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      cr[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
+      ci[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
+    }
+  for (int r0 = rbeg; r0 < rend; r0 += 16) {
+    double2 pv[2][4], qv[2][4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int r = r0 + 4 * q + lk;
+      const bool ok = r < rend;
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        pv[c][q] = ok ? Pc[c][r] : make_double2(0.0, 0.0);
+        qv[c][q] = ok ? Qc[c][r] : make_double2(0.0, 0.0);
       }
-      Ps[rr][cc] = pv;
-      Qs[rr][cc] = qv;
     }
-    __syncthreads();
-#pragma unroll 8
-    for (int rr = 0; rr < 32; ++rr) {
-      const double2 p0 = Ps[rr][ti * 2], p1 = Ps[rr][ti * 2 + 1];
-      const double2 q0 = Qs[rr][tj * 2], q1 = Qs[rr][tj * 2 + 1];
-      acc[0][0] = zadd(acc[0][0], zmulc(p0, q0));
-      acc[0][1] = zadd(acc[0][1], zmulc(p0, q1));
-      acc[1][0] = zadd(acc[1][0], zmulc(p1, q0));
-      acc[1][1] = zadd(acc[1][1], zmulc(p1, q1));
-    }
-    __syncthreads();
+#pragma unroll
+    for (int st = 0; st < 4; ++st)
+#pragma unroll
+      for (int half = 0; half < 2; ++half)
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j) {
+            const double2 x = pv[i][st], y = qv[j][st];
+            cr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(half ? x.y : x.x, half ? y.y : y.x,
+                                                            cr[i][j], 0, 0, 0);
+            ci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(half ? -x.y : x.x, half ? y.x : y.y,
+                                                            ci[i][j], 0, 0, 0);
+          }
   }
   double2* out = part + size_t(blockIdx.z) * b * b;
-  for (int a = 0; a < 2; ++a)
-    for (int c = 0; c < 2; ++c) {
-      const int gi = i0 + ti * 2 + a, gj = j0 + tj * 2 + c;
-      if (gi < b && gj < b) out[size_t(gj) * b + gi] = acc[a][c];
-    }
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = i0 + 16 * i + lk + 4 * v, col = j0 + 16 * j + li;
+        out[size_t(col) * b + row] = make_double2(cr[i][j][v], ci[i][j][v]);
+      }
 }
 
-// Y = P M; P column-major m x k, M column-major k x b, Y column-major m x b.
-__global__ void __launch_bounds__(256) k_gemm_nn(const double2* __restrict__ Pm,
-                                                 const double2* __restrict__ M,
-                                                 double2* __restrict__ Y, int m, int k,
-                                                 int b) {
-  __shared__ double2 Ps[32][33];
-  __shared__ double2 Ms[32][33];
-  const int t = threadIdx.x;
-  const int tr = t >> 4, tc = t & 15;
+// Y = P M; P column-major m x k, M column-major k x b, Y column-major m x b
+// (b a multiple of 32).  One wave per 32 x 32 tile on FP64 matrix cores:
+// Re += Pr Mr - Pi Mi, Im += Pr Mi + Pi Mr.
+__global__ void __launch_bounds__(64) k_gemm_nn(const double2* __restrict__ Pm,
+                                                const double2* __restrict__ M,
+                                                double2* __restrict__ Y, int m, int k,
+                                                int b) {
+  const int l = threadIdx.x, li = l & 15, lk = l >> 4;
   const int r0 = blockIdx.x * 32, c0 = blockIdx.y * 32;
-  double2 acc[2][2];
-  for (int a = 0; a < 2; ++a)
-    for (int c = 0; c < 2; ++c) acc[a][c] = make_double2(0.0, 0.0);
-  for (int k0 = 0; k0 < k; k0 += 32) {
-    for (int e = t; e < 1024; e += 256) {
-      const int cc = e >> 5, rr = e & 31;
-      double2 pv = make_double2(0.0, 0.0), mv = make_double2(0.0, 0.0);
-      if (r0 + rr < m && k0 + cc < k) pv = Pm[size_t(k0 + cc) * m + r0 + rr];
-      if (k0 + rr < k && c0 + cc < b) mv = M[size_t(c0 + cc) * k + k0 + rr];
-      Ps[rr][cc] = pv;   // [row][kk]
-      Ms[rr][cc] = mv;   // [kk][col]
+  const bool v0 = r0 + li < m, v1 = r0 + 16 + li < m;
+  const double2* Mc[2] = {M + size_t(c0 + li) * k, M + size_t(c0 + 16 + li) * k};
+  f64x4 cr[2][2], ci[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      cr[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
+      ci[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
     }
-    __syncthreads();
-#pragma unroll 8
-    for (int kk = 0; kk < 32; ++kk) {
-      const double2 p0 = Ps[tr * 2][kk], p1 = Ps[tr * 2 + 1][kk];
-      const double2 m0 = Ms[kk][tc * 2], m1 = Ms[kk][tc * 2 + 1];
-      acc[0][0] = zadd(acc[0][0], zmul(p0, m0));
-      acc[0][1] = zadd(acc[0][1], zmul(p0, m1));
-      acc[1][0] = zadd(acc[1][0], zmul(p1, m0));
-      acc[1][1] = zadd(acc[1][1], zmul(p1, m1));
+  for (int k0 = 0; k0 < k; k0 += 16) {
+    double2 pv[2][4], mv[2][4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int kk = k0 + 4 * q + lk;
+      const bool ok = kk < k;
+      const double2* col = Pm + size_t(ok ? kk : 0) * m;
+      pv[0][q] = (ok && v0) ? col[r0 + li] : make_double2(0.0, 0.0);
+      pv[1][q] = (ok && v1) ? col[r0 + 16 + li] : make_double2(0.0, 0.0);
+      mv[0][q] = ok ? Mc[0][kk] : make_double2(0.0, 0.0);
+      mv[1][q] = ok ? Mc[1][kk] : make_double2(0.0, 0.0);
     }
-    __syncthreads();
+#pragma unroll
+    for (int st = 0; st < 4; ++st)
+#pragma unroll
+      for (int half = 0; half < 2; ++half)
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j) {
+            const double2 x = pv[i][st], y = mv[j][st];
+            cr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(half ? -x.y : x.x, half ? y.y : y.x,
+                                                            cr[i][j], 0, 0, 0);
+            ci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(half ? x.y : x.x, half ? y.x : y.y,
+                                                            ci[i][j], 0, 0, 0);
+          }
   }
-  for (int a = 0; a < 2; ++a)
-    for (int c = 0; c < 2; ++c) {
-      const int gr = r0 + tr * 2 + a, gc = c0 + tc * 2 + c;
-      if (gr < m && gc < b) Y[size_t(gc) * m + gr] = acc[a][c];
-    }
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = r0 + 16 * i + lk + 4 * v, col = c0 + 16 * j + li;
+        if (row < m) Y[size_t(col) * m + row] = make_double2(cr[i][j][v], ci[i][j][v]);
+      }
 }
 
 // ------------------------------------------------------------------ Cholesky QR
@@ -530,9 +565,9 @@ struct NullCtx {
 
 pisco_status_t gemm_tn(NullCtx& c, const double2* P, const double2* Qm, double2* out, int rows) {
   const int b = c.b;
-  const int chunks = int(ceil_div(rows, 256));
+  const int chunks = int(ceil_div(rows, kTnRows));
   dim3 g(ceil_div(b, 32), ceil_div(b, 32), chunks);
-  PISCO_KERNEL(c.h, k_gemm_tn, g, dim3(256), 0, P, Qm, c.w.part, rows, b);
+  PISCO_KERNEL(c.h, k_gemm_tn, g, dim3(64), 0, P, Qm, c.w.part, rows, b);
   const long long len = 1LL * b * b;
   PISCO_KERNEL(c.h, k_sum_parts, dim3(ceil_div(len, 256)), dim3(256), 0, c.w.part, out, len, chunks);
   return PISCO_OK;
@@ -541,7 +576,7 @@ pisco_status_t gemm_tn(NullCtx& c, const double2* P, const double2* Qm, double2*
 pisco_status_t gemm_nn(NullCtx& c, const double2* P, const double2* M, double2* Y, int m,
                        int k) {
   dim3 g(ceil_div(m, 32), ceil_div(c.b, 32));
-  PISCO_KERNEL(c.h, k_gemm_nn, g, dim3(256), 0, P, M, Y, m, k, c.b);
+  PISCO_KERNEL(c.h, k_gemm_nn, g, dim3(64), 0, P, M, Y, m, k, c.b);
   return PISCO_OK;
 }
 
@@ -631,7 +666,9 @@ pisco_status_t run_nullspace(Handle* h, const Plan& p, int b, int max_iters,
     if (done < rr_at && done < max_iters) {
       int extra = 0;
       if (done >= 3 && rr_at != kUnscheduled) {
-        extra = rr_at - done - 1;
+        // in the fixed schedule the last orthonormalisation before the single
+        // Rayleigh-Ritz step follows one product only (best conditioned)
+        extra = rr_at - done - (fixed ? 2 : 1);
         extra = extra < 0 ? 0 : (extra > 2 ? 2 : extra);
       }
       for (int e = 0; e < extra; ++e) {

@@ -112,7 +112,7 @@ size_t layout_null(const Plan& p, int b, void* ws, NullWs* o) {
   w.resid = c.take<double>(b);
   // split-K partials of A X (up to kAxSplit slabs of n x b), row-chunk
   // partials of the b x b products, and residual partials share one buffer
-  const size_t chunks = (size_t(p.n) + 255) / 256;
+  const size_t chunks = (size_t(p.n) + kTnRows - 1) / kTnRows;
   size_t part = size_t(kAxSplit) * nb;
   if (chunks * bb > part) part = chunks * bb;
   w.part = c.take<double2>(part);
