@@ -362,6 +362,21 @@ def main():
 
     mixed = run_form(P._lib.PREC_SPLIT_F16)
     plain = run_form(P._lib.PREC_FP32)
+    # the mixed form as a one-slice graph (fixed nullspace schedule, no host
+    # read-back, one launch)
+    g1 = P.Batch([{"Q": w.Q, "acs": w.acs, "radius": w.radius, "grid_lr": w.grid_lr,
+                   "grid_out": w.grid, "precision": P._lib.PREC_SPLIT_F16,
+                   "block": BLOCKS.get(w.name, 0)}], [acs])
+    g1.launch()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        g1.launch()
+    torch.cuda.synchronize()
+    g1_ms = (time.perf_counter() - t0) / args.steps * 1e3
+    g1_status = g1.status()
+    g1_products = g1.info(0)[1]
+    g1.close()
     if args.breakdown:
         for tag, r in (("mixed", mixed), ("plain_fp32", plain)):
             tot = sum(v[1] for v in r["per"].values())
@@ -402,7 +417,10 @@ def main():
                                     "and FP32 accumulation; nullspace FP64; rest FP32",
                        "power_iters": 10, "nullspace_block": est.block, "signal_rank": rs,
                        "device_status": mixed["status"] | plain["status"],
-                       "plain_fp32": {"value": plain["value"], "ms_per_step": plain["ms"]}},
+                       "plain_fp32": {"value": plain["value"], "ms_per_step": plain["ms"]},
+                       "mixed_graph": {"value": nout / g1_ms / 1e3, "ms_per_step": g1_ms,
+                                       "nullspace_products": g1_products,
+                                       "device_status": g1_status}},
             "roofline": roof}
     if not args.no_learned:
         line["config"]["learned_warm_start"] = learned_report(w, acs, args.learned_scans)
