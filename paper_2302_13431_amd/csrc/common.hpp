@@ -162,7 +162,7 @@ struct NullWs {
   double2* U;      // [b][b] Ritz vectors of H
   double2* M;      // [b][b] combined update
   double* theta;   // [b]
-  double* lam;     // [b]
+  double* filt;    // [8] Chebyshev filter coefficients (two steps of three)
   double* resid;   // [b]
   double2* part;   // split-K partials
   int* ctl;        // [8] control words

@@ -153,6 +153,29 @@ __global__ void k_sum_parts(const double2* __restrict__ parts, double2* __restri
   out[i] = s;
 }
 
+// One step of the Chebyshev-filtered product: with S = A Y (the split-K
+// partials summed in fixed order), out = a S + b Y + g P, (a, b, g) =
+// coef[0..2] read from device memory so that a captured schedule needs no
+// host value.  P may be null (g is then ignored); out may be P (each
+// element is read before it is written by the same thread) but not Y.
+__global__ void k_sum_cheb(const double2* __restrict__ parts, const double2* __restrict__ Y,
+                           const double2* P, double2* out, long long len, int nparts,
+                           const double* __restrict__ coef) {
+  const long long i = blockIdx.x * 256LL + threadIdx.x;
+  if (i >= len) return;
+  double2 s = parts[i];
+  for (int k = 1; k < nparts; ++k) s = zadd(s, parts[size_t(k) * len + i]);
+  const double a = coef[0], bc = coef[1], g = coef[2];
+  const double2 y = Y[i];
+  double2 r = make_double2(a * s.x + bc * y.x, a * s.y + bc * y.y);
+  if (P) {
+    const double2 q = P[i];
+    r.x += g * q.x;
+    r.y += g * q.y;
+  }
+  out[i] = r;
+}
+
 // part[chunk] = P[rows of chunk, :]^H Q[rows of chunk, :]; P, Q column-major
 // n x b (b a multiple of 32); part is column-major b x b.  Rows are split
 // in chunks of kTnRows.  One wave per 32 x 32 block of the result and row
@@ -515,19 +538,58 @@ __global__ void k_control(const double* __restrict__ theta, const double* __rest
   if (!finite) atomicOr(status, PISCO_FLAG_NONFINITE);
 }
 
-// Iterations still needed, predicted from the Cholesky diagonal d_j (about
-// lambda_j): rate d_{b-1} / d_{r}, r the number of d_j >= thr2 d_0, from an
-// error of order one after `done` products.  ctl[6] = prediction.
-__global__ void k_predict(const double* __restrict__ d, int b, double thr2, double tol,
-                          int done, int* ctl) {
+// Schedule of the first Rayleigh-Ritz step and the Chebyshev filter, both
+// from the Cholesky diagonal d_j after three products (d_j follows the
+// eigenvalues of A on the leading columns of the block).
+//
+// Filter: with c = 1.05 d_{b-1}, every eigenvalue below c maps into [-1, 1]
+// under x = 2 lambda / c - 1, where the Chebyshev polynomial T_j stays
+// within [-1, 1], while an eigenvalue lambda_r of the signal subspace grows
+// as T_j(2 lambda_r / c - 1), far faster than lambda_r^j / lambda_b^j.  A
+// chain of j products then applies T_j(2A/c - I) by the three-term
+// recurrence Y_1 = (2/c) A X - X, Y_{i+1} = (4/c) A Y_i - 2 Y_i - Y_{i-1}.
+// coef[0..2] holds the first step, coef[3..5] the later ones; without a
+// usable c (no gap, zero data) both are (1, 0, 0), plain products.
+//
+// Prediction: the worst residual over the signal columns, relative to
+// theta_1, after a Rayleigh-Ritz step on the next product is about
+// (d_{b-1} / d_0) rho^2 with rho = d_{b-1} / d_{r-1} (r the signal rank by
+// the threshold); every further product divides it by the growth of its
+// chain (chains of three, the remainder last, as the driver forms them) or
+// by 1 / rho without the filter.  The prediction aims ten times below the
+// tolerance, since a Rayleigh-Ritz step that fails costs several products.
+// ctl[6] = products until (and including) the one the step is taken on.
+__global__ void k_predict(const double* __restrict__ d, int b, double thr2, double tol, int* ctl,
+                          double* __restrict__ coef) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   int r = 0;
   for (int k = 0; k < b; ++k) r += d[k] >= thr2 * d[0];
+  const bool ok = r > 0 && r < b && d[r - 1] > 0.0 && d[b - 1] > 0.0 && isfinite(d[0]);
+  const double c = 1.05 * (ok ? d[b - 1] : 0.0);
+  const double x = ok ? 2.0 * d[r - 1] / c - 1.0 : 0.0;
+  const bool filter = ok && x > 1.0 && isfinite(2.0 / c);
+  const double f[6] = {filter ? 2.0 / c : 1.0, filter ? -1.0 : 0.0, 0.0,
+                       filter ? 4.0 / c : 1.0, filter ? -2.0 : 0.0, filter ? -1.0 : 0.0};
+  for (int k = 0; k < 6; ++k) coef[k] = f[k];
   int need = 4;
-  if (r > 0 && r < b && d[r - 1] > 0.0) {
+  if (ok) {
     double rho = d[b - 1] / d[r - 1];
     rho = rho < 1e-3 ? 1e-3 : (rho > 0.95 ? 0.95 : rho);
-    need = int(ceil(log(tol) / log(rho))) - done + 1;
+    const double target = log(0.1 * tol);
+    const double e0 = log(d[b - 1] / d[0]) + 2.0 * log(rho);
+    // log growth of chains of one, two and three filtered products
+    const double g1 = filter ? log(x) : -log(rho);
+    const double g2 = filter ? log(2.0 * x * x - 1.0) : -2.0 * log(rho);
+    const double g3 = filter ? log((4.0 * x * x - 3.0) * x) : -3.0 * log(rho);
+    need = 40;
+    for (int k = 0; k < 40; ++k) {
+      const int rem = k % 3;
+      const double e = e0 - (k / 3) * g3 - (rem == 1 ? g1 : (rem == 2 ? g2 : 0.0));
+      if (e <= target) {
+        need = k + 1;
+        break;
+      }
+    }
   }
   ctl[6] = need < 1 ? 1 : (need > 40 ? 40 : need);
 }
@@ -639,54 +701,71 @@ pisco_status_t run_nullspace(Handle* h, const Plan& p, int b, int max_iters,
   const int kchunk = 16 * int(ceil_div(ceil_div(n, want), 16));
   const int ksplit = int(ceil_div(n, kchunk));
   const int rchunks = int(ceil_div(n, 1024));
-  // Z = A X (split-K partials in `part`, summed in fixed order)
-  auto product = [&](const double2* in, double2* out) -> pisco_status_t {
+  // out = A in (split-K partials in `part`, summed in fixed order); with
+  // step 1 or 2 the sum forms the first or a later step of the Chebyshev
+  // recurrence instead (prev = the previous block of the chain)
+  auto product = [&](const double2* in, double2* out, const double2* prev,
+                     int step) -> pisco_status_t {
     dim3 g(ceil_div(n, 32), ceil_div(b, 32), ksplit);
     PISCO_KERNEL(h, k_gemm_ax, g, dim3(64), 0, gram, in, c.w.part, n, b, kchunk);
-    PISCO_KERNEL(h, k_sum_parts, dim3(ceil_div(nb, 256)), dim3(256), 0, c.w.part, out, nb,
-                 ksplit);
+    if (step == 0)
+      PISCO_KERNEL(h, k_sum_parts, dim3(ceil_div(nb, 256)), dim3(256), 0, c.w.part, out, nb,
+                   ksplit);
+    else
+      PISCO_KERNEL(h, k_sum_cheb, dim3(ceil_div(nb, 256)), dim3(256), 0, c.w.part, in, prev,
+                   out, nb, ksplit, c.w.filt + 3 * (step - 1));
     return PISCO_OK;
   };
-  // Products are counted in `done`.  The first Rayleigh-Ritz step is
-  // scheduled from the Cholesky diagonal seen after three products, later
-  // ones from the Ritz values and residuals.  After the third product the
-  // scaled block stays well conditioned (kappa of order 10 for two more
-  // products), so up to three products share one Cholesky QR pass.
+  // Products are counted in `done`.  Each of the first three is
+  // orthonormalised on its own; the Cholesky diagonal seen after the third
+  // sets the Chebyshev filter and (adaptive mode) the first Rayleigh-Ritz
+  // step; later ones are scheduled from the Ritz values and residuals.
+  // From then on up to three products form one filtered chain per Cholesky
+  // QR pass (the scaled block stays well conditioned over such a chain).
+  // The product a Rayleigh-Ritz step is taken on is a plain one.
   // With fixed_products > 0 the schedule is set in advance (that many
   // products, one Rayleigh-Ritz step at the end) and nothing is read back on
-  // the host, so the whole call can be captured in a graph; convergence is
-  // still tested on the device and reported through counts and the status.
+  // the host, so the whole call can be captured in a graph; the filter
+  // coefficients stay on the device and convergence is still tested there,
+  // reported through counts and the status.
   constexpr int kUnscheduled = 1 << 30;
   const bool fixed = fixed_products > 0;
   int rr_at = fixed ? (fixed_products < 3 ? 3 : fixed_products) : kUnscheduled;
   int done = 0;
+  bool filtered = false;  // filter coefficients set
   while (true) {
-    if ((st = product(X, Z))) return st;
+    const bool rr_next = done + 1 >= rr_at || done + 1 >= max_iters;
+    const bool chain = filtered && !rr_next;
+    if ((st = product(X, Z, nullptr, chain ? 1 : 0))) return st;
     ++done;
     if (done < rr_at && done < max_iters) {
       int extra = 0;
-      if (done >= 3 && rr_at != kUnscheduled) {
+      if (done > 3 && rr_at != kUnscheduled) {
         // in the fixed schedule the last orthonormalisation before the single
         // Rayleigh-Ritz step follows one product only (best conditioned)
         extra = rr_at - done - (fixed ? 2 : 1);
         extra = extra < 0 ? 0 : (extra > 2 ? 2 : extra);
       }
       for (int e = 0; e < extra; ++e) {
-        if ((st = product(Z, X))) return st;
+        // next block of the chain, written over the previous one (in X)
+        if ((st = chain ? product(Z, X, X, 2) : product(Z, X, nullptr, 0))) return st;
         std::swap(X, Z);
         ++done;
       }
-      const bool predict = !fixed && done == 3 && rr_at == kUnscheduled;
-      if ((st = orth(c, Z, X, predict ? c.w.resid : nullptr, done == 1 ? 1e-12 : 0.0)))
+      const bool at3 = done == 3 && !filtered;
+      if ((st = orth(c, Z, X, at3 ? c.w.resid : nullptr, done == 1 ? 1e-12 : 0.0)))
         return st;
-      if (predict) {
-        PISCO_KERNEL(h, k_predict, dim3(1), dim3(64), 0, c.w.resid, b, thr2, tol, done,
-                     c.w.ctl);
-        hipError_t e = hipMemcpyAsync(h->host_pinned, c.w.ctl, 8 * sizeof(int),
-                                      hipMemcpyDeviceToHost, s);
-        if (e == hipSuccess) e = hipStreamSynchronize(s);
-        if (e != hipSuccess) return hip_check(h, e, "nullspace predict");
-        rr_at = done + reinterpret_cast<const int*>(h->host_pinned)[6];
+      if (at3) {
+        PISCO_KERNEL(h, k_predict, dim3(1), dim3(64), 0, c.w.resid, b, thr2, tol, c.w.ctl,
+                     c.w.filt);
+        filtered = true;
+        if (!fixed) {
+          hipError_t e = hipMemcpyAsync(h->host_pinned, c.w.ctl, 8 * sizeof(int),
+                                        hipMemcpyDeviceToHost, s);
+          if (e == hipSuccess) e = hipStreamSynchronize(s);
+          if (e != hipSuccess) return hip_check(h, e, "nullspace predict");
+          rr_at = done + reinterpret_cast<const int*>(h->host_pinned)[6];
+        }
       }
       continue;
     }

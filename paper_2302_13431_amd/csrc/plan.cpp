@@ -108,7 +108,7 @@ size_t layout_null(const Plan& p, int b, void* ws, NullWs* o) {
   w.U = c.take<double2>(bb);
   w.M = c.take<double2>(bb);
   w.theta = c.take<double>(b);
-  w.lam = c.take<double>(b);
+  w.filt = c.take<double>(8);
   w.resid = c.take<double>(b);
   // split-K partials of A X (up to kAxSplit slabs of n x b), row-chunk
   // partials of the b x b products, and residual partials share one buffer
