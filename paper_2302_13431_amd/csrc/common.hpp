@@ -161,6 +161,8 @@ struct NullWs {
   double2* S;      // [b][b] Z^H Z
   double2* U;      // [b][b] Ritz vectors of H
   double2* M;      // [b][b] combined update
+  double2* R;      // [b][b] Cholesky factor (column-major, upper)
+  double* dsc;     // [b] column scaling of the factorised Gram
   double* theta;   // [b]
   double* filt;    // [8] Chebyshev filter coefficients (two steps of three)
   double* resid;   // [b]

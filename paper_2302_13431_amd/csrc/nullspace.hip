@@ -298,40 +298,30 @@ __global__ void __launch_bounds__(64) k_gemm_nn(const double2* __restrict__ Pm,
 constexpr int kCholLdsMax = 96;  // largest b factored with the matrix in LDS
 constexpr int kCholThreads = 512;
 
-// Cholesky factor of D S D + shift I (D = diag(S)^{-1/2}) and M = D R^{-1},
-// so that Y M has orthonormal columns when S = Y^H Y (up to the shift).  One
+// Cholesky factor of D S D + shift I, D = diag(S)^{-1/2}: R (upper, column-
+// major b x b, entries below the diagonal zero) and D itself (dsc), so that
+// Y D R^{-1} has orthonormal columns when S = Y^H Y (up to the shift).  One
 // workgroup; the working matrix T (row-major, ld = b + 1 so that column
 // walks spread over the LDS banks) is in LDS when kLds (b <= 96) and in
 // `gwork` otherwise.  A pivot that is not positive is replaced by a tiny
 // one and reported through *flag.
 //
 // Blocked in panels of kNB = 8 columns (b must be a multiple).  Per panel
-// J: (a) one wave factors the diagonal block, lane j holding column j in
-// registers (pivot rows are broadcast with readlane), then inverts it,
-// X_JJ = R_JJ^{-1}, lane c forming column c, and stores X_JJ in place of
-// R_JJ (R_JJ itself is not needed again); (b) the panel row
-// R_J,j = X_JJ^H T_J,j for all later columns; (c) the trailing update
-// T_ij -= R_Ji^H R_Jj.  Then R^{-1} is formed in place block column by block
-// column: X_IJ = -(sum_K X_IK R_KJ) X_JJ, the partial sums staged in the
-// unused strict lower triangle.  Phase (a) runs on one wave and is bound by
-// its instruction count, which grows with b times the panel width; narrow
-// panels keep it short at the price of more barriers in the other phases.
-__device__ inline double readlane_f64(double v, int lane) {
-  const long long x = __double_as_longlong(v);
-  const unsigned lo = __builtin_amdgcn_readlane(int(x), lane);
-  const unsigned hi = __builtin_amdgcn_readlane(int(x >> 32), lane);
-  return __longlong_as_double((static_cast<long long>(hi) << 32) | lo);
-}
-
+// J, every thread that owns a later column j factors the diagonal block
+// R_JJ^H R_JJ = T_JJ entirely in its own registers (the same few hundred
+// operations in every lane: no cross-lane traffic, no barrier), then solves
+// R_JJ^H R_J,j = T_J,j for its column of the panel row.  After a barrier
+// R_JJ is stored and the trailing update T_ij -= R_Ji^H R_Jj runs in 2 x 2
+// patches of the upper triangle, one per thread, operands in registers.
 template <bool kLds>
-__global__ void __launch_bounds__(kCholThreads) k_chol_inv(const double2* __restrict__ S, int b,
-                                                   double shift, double2* __restrict__ M,
-                                                   double2* __restrict__ gwork,
-                                                   int* __restrict__ flag,
-                                                   double* __restrict__ rdiag) {
+__global__ void __launch_bounds__(kCholThreads) k_chol(const double2* __restrict__ S, int b,
+                                               double shift, double2* __restrict__ R,
+                                               double* __restrict__ dsc_out,
+                                               double2* __restrict__ gwork,
+                                               int* __restrict__ flag,
+                                               double* __restrict__ rdiag) {
   constexpr int kNB = 8;                        // panel width (b is a multiple)
   constexpr int kNT = kCholThreads;
-  constexpr int kOut = kLds ? 3 : 32;           // panel outputs per thread
   __shared__ double2 lds_mat[kLds ? kCholLdsMax * (kCholLdsMax + 1) : 1];
   __shared__ double dsc[kLds ? kCholLdsMax : 1024];
   double2* T = kLds ? lds_mat : gwork;
@@ -352,124 +342,213 @@ __global__ void __launch_bounds__(kCholThreads) k_chol_inv(const double2* __rest
   }
   __syncthreads();
   for (int k0 = 0; k0 < b; k0 += kNB) {
-    const int w = kNB;
-    const int k1 = k0 + w;
-    // (a) wave 0: factor and invert the diagonal block (every loop bound is
-    // a constant).  Lane t keeps column t % kNB in registers; rows below the
-    // diagonal are carried along but never used, which keeps the code free
-    // of per-lane branches.  The pivot row is broadcast with readlane.  Then
-    // lane t forms column t % kNB of X = R^{-1} by back substitution (R_il is
-    // lane l's entry i, again by readlane), and X is stored in place of R.
-    if (t < 64) {
-      // tc goes through an empty asm statement so that the compiler cannot
-      // hoist per-lane constants of this phase out of the panel loop
-      int tc = t & (kNB - 1);
-      asm volatile("" : "+v"(tc));
-      double2 c[kNB];
+    const int k1 = k0 + kNB, nc = b - k1;
+    // threads owning a later column (whole waves; wave 0 at least, which
+    // also serves the last panel)
+    const int nact = nc > 64 ? ((nc + 63) & ~63) : 64;
+    double2 x[kNB][kNB];
+    if (t < nact) {
 #pragma unroll
-      for (int i = 0; i < kNB; ++i) c[i] = at(k0 + i, k0 + tc);
+      for (int i = 0; i < kNB; ++i)
 #pragma unroll
-      for (int kk = 0; kk < kNB; ++kk) {
-        double dk = readlane_f64(c[kk].x, kk);
-        const bool bad = !(dk > 1e-300);
-        dk = bad ? 1e-300 : dk;
-        const double r = sqrt(dk), rinv = 1.0 / r;
-        if (t == 0) {
-          if (bad) *flag = 1;
-          // diagonal of the unscaled factor (R' D^-1): converges to the
-          // eigenvalue magnitudes in orthogonal iteration
-          if (rdiag) rdiag[k0 + kk] = dsc[k0 + kk] > 0.0 ? r / dsc[k0 + kk] : 0.0;
-        }
-        const double2 ck = tc == kk ? make_double2(r, 0.0) : zscale(c[kk], rinv);
-        c[kk] = ck;
+        for (int j = i; j < kNB; ++j) x[i][j] = at(k0 + i, k0 + j);
+      bool bad = false;
+      double ri[kNB];
 #pragma unroll
-        for (int i = kk + 1; i < kNB; ++i) {
-          const double2 rki = make_double2(readlane_f64(ck.x, i), readlane_f64(ck.y, i));
-          c[i] = zsub(c[i], zmulc(rki, ck));
-        }
+      for (int k = 0; k < kNB; ++k) {
+        double d = x[k][k].x;
+        bad |= !(d > 1e-300);
+        d = d > 1e-300 ? d : 1e-300;
+        ri[k] = rsqrt(d);
+        x[k][k] = make_double2(d * ri[k], 0.0);
+#pragma unroll
+        for (int j = k + 1; j < kNB; ++j) x[k][j] = zscale(x[k][j], ri[k]);
+#pragma unroll
+        for (int i = k + 1; i < kNB; ++i)
+#pragma unroll
+          for (int j = i; j < kNB; ++j) x[i][j] = zsub(x[i][j], zmulc(x[k][i], x[k][j]));
       }
-      double2 x[kNB];
+      if (t == 0) {
+        if (bad) *flag = 1;
+        // diagonal of the unscaled factor (R' D^-1): converges to the
+        // eigenvalue magnitudes in orthogonal iteration
+        if (rdiag)
 #pragma unroll
-      for (int i = kNB - 1; i >= 0; --i) {
-        const double dinv = 1.0 / readlane_f64(c[i].x, i);
-        double2 acc = make_double2(0.0, 0.0);
-#pragma unroll
-        for (int l = i + 1; l < kNB; ++l) {
-          const double2 ril = make_double2(readlane_f64(c[i].x, l), readlane_f64(c[i].y, l));
-          acc = zadd(acc, zmul(ril, x[l]));
-        }
-        const double2 xi = i == tc ? make_double2(dinv, 0.0) : zscale(acc, -dinv);
-        x[i] = i <= tc ? xi : make_double2(0.0, 0.0);
+          for (int k = 0; k < kNB; ++k)
+            rdiag[k0 + k] = dsc[k0 + k] > 0.0 ? x[k][k].x / dsc[k0 + k] : 0.0;
       }
-      if (t < kNB) {
+      // panel row, one column per thread (read and written by that thread
+      // only): forward substitution with R_JJ^H
+      for (int j = k1 + t; j < b; j += nact) {
+        double2 w[kNB];
 #pragma unroll
-        for (int i = 0; i < kNB; ++i)
-          if (i <= t) at(k0 + i, k0 + t) = x[i];
+        for (int r = 0; r < kNB; ++r) {
+          double2 acc = at(k0 + r, j);
+#pragma unroll
+          for (int l = 0; l < r; ++l) acc = zsub(acc, zmulc(x[l][r], w[l]));
+          w[r] = zscale(acc, ri[r]);
+          at(k0 + r, j) = w[r];
+        }
       }
     }
     __syncthreads();
-    if (k1 < b) {
-      // (b) R[k0+r][j] = sum_{l <= r} conj(X_lr) T[k0+l][j] for j >= k1
-      const int nc = b - k1, nout = w * nc;
-      double2 res[kOut];
+    if (t == 0) {
 #pragma unroll
-      for (int q = 0; q < kOut; ++q) {
-        const int o = t + kNT * q;
-        res[q] = make_double2(0.0, 0.0);
-        if (o < nout) {
-          const int r = o / nc, j = k1 + o % nc;
-          double2 acc = make_double2(0.0, 0.0);
-          for (int l = 0; l <= r; ++l) acc = zadd(acc, zmulc(at(k0 + l, k0 + r), at(k0 + l, j)));
-          res[q] = acc;
-        }
-      }
-      __syncthreads();
+      for (int i = 0; i < kNB; ++i)
 #pragma unroll
-      for (int q = 0; q < kOut; ++q) {
-        const int o = t + kNT * q;
-        if (o < nout) at(k0 + o / nc, k1 + o % nc) = res[q];
-      }
-      __syncthreads();
-      // (c) T_ij -= sum_{l in panel} conj(R_li) R_lj for k1 <= i <= j
-      for (int i = k1 + (t >> 6); i < b; i += kNT / 64) {
-        for (int j = i + (t & 63); j < b; j += 64) {
-          double2 acc = at(i, j);
-          for (int l = k0; l < k1; ++l) acc = zsub(acc, zmulc(at(l, i), at(l, j)));
-          at(i, j) = acc;
-        }
-      }
-      __syncthreads();
+        for (int j = i; j < kNB; ++j) at(k0 + i, k0 + j) = x[i][j];
     }
-  }
-  // R^{-1} in place, block column J = [k0, k1) for k0 >= 16: P_i,c =
-  // sum_{l = i .. k0-1} X_il R_l,k0+c (staged at (k0+c, i)), then
-  // X_i,k0+c = -sum_{l <= c} P_i,l (X_JJ)_l,c.
-  for (int k0 = kNB; k0 < b; k0 += kNB) {
-    constexpr int w = kNB;
-    for (int o = t; o < k0 * w; o += kNT) {
-      const int i = o / w, c = o % w;
-      double2 a0 = make_double2(0.0, 0.0), a1 = make_double2(0.0, 0.0);
-      int l = i;
-      for (; l + 1 < k0; l += 2) {
-        a0 = zadd(a0, zmul(at(i, l), at(l, k0 + c)));
-        a1 = zadd(a1, zmul(at(i, l + 1), at(l + 1, k0 + c)));
+    // trailing update in 2 x 2 patches (pi <= pj) of the upper triangle
+    const int m = nc >> 1;
+    const int npatch = m * (m + 1) / 2;
+    for (int q = t; q < npatch; q += kNT) {
+      // row of patches: start(p) = p m - p (p - 1) / 2 <= q < start(p + 1)
+      const double tm = 2.0 * m + 1.0;
+      int pi = int((tm - sqrt(tm * tm - 8.0 * q)) * 0.5);
+      pi = pi < 0 ? 0 : (pi > m - 1 ? m - 1 : pi);
+      while (pi > 0 && pi * m - pi * (pi - 1) / 2 > q) --pi;
+      while (pi + 1 < m && (pi + 1) * m - (pi + 1) * pi / 2 <= q) ++pi;
+      const int pj = pi + q - (pi * m - pi * (pi - 1) / 2);
+      const int i0 = k1 + 2 * pi, j0 = k1 + 2 * pj;
+      const bool diag = pi == pj;
+      double2 a00 = at(i0, j0), a01 = at(i0, j0 + 1), a11 = at(i0 + 1, j0 + 1);
+      double2 a10 = diag ? make_double2(0.0, 0.0) : at(i0 + 1, j0);
+#pragma unroll
+      for (int l = 0; l < kNB; ++l) {
+        const double2 ri0 = at(k0 + l, i0), ri1 = at(k0 + l, i0 + 1);
+        const double2 rj0 = at(k0 + l, j0), rj1 = at(k0 + l, j0 + 1);
+        a00 = zsub(a00, zmulc(ri0, rj0));
+        a01 = zsub(a01, zmulc(ri0, rj1));
+        a10 = zsub(a10, zmulc(ri1, rj0));
+        a11 = zsub(a11, zmulc(ri1, rj1));
       }
-      if (l < k0) a0 = zadd(a0, zmul(at(i, l), at(l, k0 + c)));
-      at(k0 + c, i) = zadd(a0, a1);
-    }
-    __syncthreads();
-    for (int o = t; o < k0 * w; o += kNT) {
-      const int i = o / w, c = o % w;
-      double2 acc = make_double2(0.0, 0.0);
-      for (int l = 0; l <= c; ++l) acc = zadd(acc, zmul(at(k0 + l, i), at(k0 + l, k0 + c)));
-      at(i, k0 + c) = make_double2(-acc.x, -acc.y);
+      at(i0, j0) = a00;
+      at(i0, j0 + 1) = a01;
+      at(i0 + 1, j0 + 1) = a11;
+      if (!diag) at(i0 + 1, j0) = a10;
     }
     __syncthreads();
   }
-  // M = D R^{-1} (rows scaled), column-major, zero below the diagonal
   for (int e = t; e < b * b; e += kNT) {
     const int i = e % b, j = e / b;
-    M[e] = i <= j ? zscale(at(i, j), dsc[i]) : make_double2(0.0, 0.0);
+    R[e] = i <= j ? at(i, j) : make_double2(0.0, 0.0);
+  }
+  for (int k = t; k < b; k += kNT) dsc_out[k] = dsc[k];
+}
+
+__device__ inline double readlane_f64(double v, int lane) {
+  const long long x = __double_as_longlong(v);
+  const unsigned lo = __builtin_amdgcn_readlane(int(x), lane);
+  const unsigned hi = __builtin_amdgcn_readlane(int(x >> 32), lane);
+  return __longlong_as_double((static_cast<long long>(hi) << 32) | lo);
+}
+
+// M = D R^{-1}, one column j per wave: back substitution R x = e_j in
+// column (axpy) order, k = j down to 0: x_k = r_k / R_kk, then
+// r_i -= R_ik x_k for i < k.  Lane l holds rows l + 64 s; x_k goes from its
+// owner to the wave by readlane.  Columns are independent, so the b columns
+// run side by side, kTriWaves to a workgroup.  The entries of R the steps
+// use are read eight steps at a time into registers, so that the chain of
+// steps does not wait on memory.  With kStage the strict upper triangle of
+// the columns the workgroup needs is first copied to LDS (packed, column k
+// at k (k - 1) / 2); otherwise (large b) they come from global memory.
+constexpr int kTriWaves = 4;
+constexpr int kTriStageMax = 128;  // largest b staged in LDS
+
+template <int kRows, bool kStage>
+__global__ void __launch_bounds__(64 * kTriWaves) k_tri_inv(const double2* __restrict__ R,
+                                                            const double* __restrict__ dsc,
+                                                            double2* __restrict__ M, int b) {
+  constexpr int kMaxB = 64 * kRows;  // b <= kMaxB (at most kTriStageMax when staged)
+  constexpr int kStep = kRows <= 4 ? 8 : 32 / kRows;  // steps per register batch
+  __shared__ double2 tri[kStage ? kMaxB * (kMaxB - 1) / 2 : 1];
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int j = blockIdx.x * kTriWaves + wave;
+  // the wave's own global reads first, so that their latency overlaps the
+  // staging: the diagonal of R and D for rows lane + 64 s
+  double rdia[kRows], dg[kRows];
+#pragma unroll
+  for (int s = 0; s < kRows; ++s) {
+    const int i = lane + 64 * s;
+    rdia[s] = i <= j && j < b ? R[size_t(i) * b + i].x : 1.0;
+    dg[s] = i < b ? dsc[i] : 0.0;
+  }
+  if (kStage) {
+    int jmax = blockIdx.x * kTriWaves + kTriWaves - 1;
+    jmax = jmax < b - 1 ? jmax : b - 1;
+    // wave w copies columns 1 + w, 1 + w + kTriWaves, ...; a batch of
+    // columns is loaded before it is stored
+    constexpr int kCols = 16;
+    for (int c0 = 1 + wave; c0 <= jmax; c0 += kCols * kTriWaves) {
+      double2 v[kCols][kRows];
+#pragma unroll
+      for (int c = 0; c < kCols; ++c) {
+        const int k = c0 + c * kTriWaves;
+#pragma unroll
+        for (int s = 0; s < kRows; ++s) {
+          const int i = lane + 64 * s;
+          v[c][s] = k <= jmax && i < k ? R[size_t(k) * b + i] : make_double2(0.0, 0.0);
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < kCols; ++c) {
+        const int k = c0 + c * kTriWaves;
+#pragma unroll
+        for (int s = 0; s < kRows; ++s) {
+          const int i = lane + 64 * s;
+          if (k <= jmax && i < k) tri[k * (k - 1) / 2 + i] = v[c][s];
+        }
+      }
+    }
+    __syncthreads();
+  }
+  if (j >= b) return;
+  double2 y[kRows];
+  double rinv[kRows];
+#pragma unroll
+  for (int s = 0; s < kRows; ++s) {
+    const int i = lane + 64 * s;
+    y[s] = make_double2(i == j ? 1.0 : 0.0, 0.0);
+    rinv[s] = 1.0 / rdia[s];
+  }
+  for (int kb = j; kb >= 0; kb -= kStep) {
+    double2 cb[kStep][kRows];
+#pragma unroll
+    for (int u = 0; u < kStep; ++u) {
+      const int k = kb - u;
+#pragma unroll
+      for (int s = 0; s < kRows; ++s) {
+        const int i = lane + 64 * s;
+        cb[u][s] = i < k ? (kStage ? tri[k * (k - 1) / 2 + i] : R[size_t(k) * b + i])
+                         : make_double2(0.0, 0.0);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kStep; ++u) {
+      const int k = kb - u;
+      if (k < 0) continue;
+      const int so = k >> 6, lo = k & 63;
+      double2 mine = zscale(y[0], rinv[0]);
+#pragma unroll
+      for (int s = 1; s < kRows; ++s)
+        if (s == so) mine = zscale(y[s], rinv[s]);
+      const double2 xk = make_double2(readlane_f64(mine.x, lo), readlane_f64(mine.y, lo));
+#pragma unroll
+      for (int s = 0; s < kRows; ++s) {
+        const int i = lane + 64 * s;
+        const double2 upd = zsub(y[s], zmul(cb[u][s], xk));
+        // component-wise selects (a select of the pair can go through memory)
+        const bool lt = i < k, eq = i == k;
+        y[s].x = lt ? upd.x : (eq ? xk.x : y[s].x);
+        y[s].y = lt ? upd.y : (eq ? xk.y : y[s].y);
+      }
+    }
+  }
+#pragma unroll
+  for (int s = 0; s < kRows; ++s) {
+    const int i = lane + 64 * s;
+    if (i < b) M[size_t(j) * b + i] = i <= j ? zscale(y[s], dg[s]) : make_double2(0.0, 0.0);
   }
 }
 
@@ -645,17 +724,28 @@ pisco_status_t gemm_nn(NullCtx& c, const double2* P, const double2* M, double2* 
 pisco_status_t chol_inv(NullCtx& c, const double2* S, double shift, double2* M,
                         double* rdiag = nullptr) {
   const int b = c.b;
-  if (b % 8 != 0) {
-    c.h->last_error = "nullspace: block size must be a multiple of 8";
+  if (b % 8 != 0 || b > 1024) {
+    c.h->last_error = "nullspace: block size must be a multiple of 8, at most 1024";
     return PISCO_ERR_UNSUPPORTED;
   }
   int* flag = c.w.ctl + 8;
   if (b <= kCholLdsMax)
-    PISCO_KERNEL(c.h, k_chol_inv<true>, dim3(1), dim3(kCholThreads), 0, S, b, shift, M,
-                 reinterpret_cast<double2*>(c.w.jac), flag, rdiag);
+    PISCO_KERNEL(c.h, k_chol<true>, dim3(1), dim3(kCholThreads), 0, S, b, shift, c.w.R,
+                 c.w.dsc, reinterpret_cast<double2*>(c.w.jac), flag, rdiag);
   else
-    PISCO_KERNEL(c.h, k_chol_inv<false>, dim3(1), dim3(kCholThreads), 0, S, b, shift, M,
-                 reinterpret_cast<double2*>(c.w.jac), flag, rdiag);
+    PISCO_KERNEL(c.h, k_chol<false>, dim3(1), dim3(kCholThreads), 0, S, b, shift, c.w.R,
+                 c.w.dsc, reinterpret_cast<double2*>(c.w.jac), flag, rdiag);
+  const dim3 tg(ceil_div(b, kTriWaves)), tb(64 * kTriWaves);
+  if (b <= 64)
+    PISCO_KERNEL(c.h, (k_tri_inv<1, true>), tg, tb, 0, c.w.R, c.w.dsc, M, b);
+  else if (b <= kTriStageMax)
+    PISCO_KERNEL(c.h, (k_tri_inv<2, true>), tg, tb, 0, c.w.R, c.w.dsc, M, b);
+  else if (b <= 256)
+    PISCO_KERNEL(c.h, (k_tri_inv<4, false>), tg, tb, 0, c.w.R, c.w.dsc, M, b);
+  else if (b <= 512)
+    PISCO_KERNEL(c.h, (k_tri_inv<8, false>), tg, tb, 0, c.w.R, c.w.dsc, M, b);
+  else
+    PISCO_KERNEL(c.h, (k_tri_inv<16, false>), tg, tb, 0, c.w.R, c.w.dsc, M, b);
   return PISCO_OK;
 }
 

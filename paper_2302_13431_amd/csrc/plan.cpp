@@ -107,6 +107,8 @@ size_t layout_null(const Plan& p, int b, void* ws, NullWs* o) {
   w.S = c.take<double2>(bb);
   w.U = c.take<double2>(bb);
   w.M = c.take<double2>(bb);
+  w.R = c.take<double2>(bb);
+  w.dsc = c.take<double>(b);
   w.theta = c.take<double>(b);
   w.filt = c.take<double>(8);
   w.resid = c.take<double>(b);
