@@ -237,60 +237,59 @@ __global__ void __launch_bounds__(64) k_gemm_tn(const double2* __restrict__ P,
 }
 
 // Y = P M; P column-major m x k, M column-major k x b, Y column-major m x b
-// (b a multiple of 32).  One wave per 32 x 32 tile on FP64 matrix cores:
-// Re += Pr Mr - Pi Mi, Im += Pr Mi + Pi Mr.
+// (b a multiple of 16).  One wave per 16 x 16 tile of Y on FP64 matrix cores
+// (Re += Pr Mr - Pi Mi, Im += Pr Mi + Pi Mr), so that a block of b = 96
+// columns gives 6 m / 16 waves.  With tri, M is upper triangular and the
+// sum over k stops at the tile's last column.  The operands of the next 16
+// k are loaded before the products of the current ones; even and odd steps
+// of 4 k go to separate accumulators.
 __global__ void __launch_bounds__(64) k_gemm_nn(const double2* __restrict__ Pm,
                                                 const double2* __restrict__ M,
                                                 double2* __restrict__ Y, int m, int k,
-                                                int b) {
+                                                int b, int tri) {
   const int l = threadIdx.x, li = l & 15, lk = l >> 4;
-  const int r0 = blockIdx.x * 32, c0 = blockIdx.y * 32;
-  const bool v0 = r0 + li < m, v1 = r0 + 16 + li < m;
-  const double2* Mc[2] = {M + size_t(c0 + li) * k, M + size_t(c0 + 16 + li) * k};
-  f64x4 cr[2][2], ci[2][2];
+  const int r0 = blockIdx.x * 16, c0 = blockIdx.y * 16;
+  const bool v = r0 + li < m;
+  const int kend = tri ? min(k, c0 + 16) : k;
+  const double2* Mc = M + size_t(c0 + li) * k;
+  const double2* Pr = Pm + (v ? r0 + li : 0);
+  f64x4 cr[2], ci[2];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int h = 0; h < 2; ++h) cr[h] = ci[h] = f64x4{0.0, 0.0, 0.0, 0.0};
+  double2 pv[4], mv[4], pn[4], mn[4];
+  auto load = [&](int k0, double2 (&p)[4], double2 (&q)[4]) {
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      cr[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
-      ci[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
+    for (int u = 0; u < 4; ++u) {
+      const int kk = k0 + 4 * u + lk;
+      const bool ok = kk < kend;
+      p[u] = ok && v ? Pr[size_t(kk) * m] : make_double2(0.0, 0.0);
+      q[u] = ok ? Mc[kk] : make_double2(0.0, 0.0);
     }
-  for (int k0 = 0; k0 < k; k0 += 16) {
-    double2 pv[2][4], mv[2][4];
+  };
+  load(0, pv, mv);
+  for (int k0 = 0; k0 < kend; k0 += 16) {
+    if (k0 + 16 < kend) load(k0 + 16, pn, mn);
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int kk = k0 + 4 * q + lk;
-      const bool ok = kk < k;
-      const double2* col = Pm + size_t(ok ? kk : 0) * m;
-      pv[0][q] = (ok && v0) ? col[r0 + li] : make_double2(0.0, 0.0);
-      pv[1][q] = (ok && v1) ? col[r0 + 16 + li] : make_double2(0.0, 0.0);
-      mv[0][q] = ok ? Mc[0][kk] : make_double2(0.0, 0.0);
-      mv[1][q] = ok ? Mc[1][kk] : make_double2(0.0, 0.0);
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int half = 0; half < 2; ++half) {
+        const double2 x = pv[u], y = mv[u];
+        cr[u & 1] = __builtin_amdgcn_mfma_f64_16x16x4f64(half ? -x.y : x.x, half ? y.y : y.x,
+                                                         cr[u & 1], 0, 0, 0);
+        ci[u & 1] = __builtin_amdgcn_mfma_f64_16x16x4f64(half ? x.y : x.x, half ? y.x : y.y,
+                                                         ci[u & 1], 0, 0, 0);
+      }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      pv[u] = pn[u];
+      mv[u] = mn[u];
     }
-#pragma unroll
-    for (int st = 0; st < 4; ++st)
-#pragma unroll
-      for (int half = 0; half < 2; ++half)
-#pragma unroll
-        for (int i = 0; i < 2; ++i)
-#pragma unroll
-          for (int j = 0; j < 2; ++j) {
-            const double2 x = pv[i][st], y = mv[j][st];
-            cr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(half ? -x.y : x.x, half ? y.y : y.x,
-                                                            cr[i][j], 0, 0, 0);
-            ci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(half ? x.y : x.x, half ? y.x : y.y,
-                                                            ci[i][j], 0, 0, 0);
-          }
   }
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int row = r0 + 16 * i + lk + 4 * v, col = c0 + 16 * j + li;
-        if (row < m) Y[size_t(col) * m + row] = make_double2(cr[i][j][v], ci[i][j][v]);
-      }
+  for (int e = 0; e < 4; ++e) {
+    const int row = r0 + lk + 4 * e, col = c0 + li;
+    if (row < m) Y[size_t(col) * m + row] = make_double2(cr[0][e] + cr[1][e], ci[0][e] + ci[1][e]);
+  }
 }
 
 // ------------------------------------------------------------------ Cholesky QR
@@ -582,20 +581,27 @@ __global__ void __launch_bounds__(256) k_colresid(const double2* __restrict__ Y,
 __global__ void k_control(const double* __restrict__ theta, const double* __restrict__ rpart,
                           int nchunks, int b, double thr2, double tol, int margin, int iter,
                           int* ctl, unsigned* status) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  // one wave: the counts by ballot, the largest residual by lane shuffles
+  const int t = threadIdx.x;
   const double t0 = theta[0];
   int rs = 0;
-  for (int k = 0; k < b; ++k) rs += theta[k] >= thr2 * t0;
+  for (int k0 = 0; k0 < b; k0 += 64) {
+    const int k = k0 + t;
+    rs += __popcll(__ballot(k < b && theta[k] >= thr2 * t0));
+  }
   const int upto = rs + 1 < b ? rs + 1 : b;
   double worst = 0.0;
-  bool finite = isfinite(t0);
-  for (int k = 0; k < upto; ++k) {
+  bool bad = false;
+  for (int k = t; k < upto; k += 64) {
     double s = 0.0;
     for (int c = 0; c < nchunks; ++c) s += rpart[size_t(c) * b + k];
     const double r = sqrt(s);
-    if (!isfinite(r)) finite = false;
+    bad |= !isfinite(r);
     worst = r > worst ? r : worst;
   }
+  for (int off = 32; off > 0; off >>= 1) worst = fmax(worst, __shfl_xor(worst, off, 64));
+  const bool finite = isfinite(t0) && __ballot(bad) == 0ull;
+  if (t != 0) return;
   const int zero = !(t0 > 0.0);
   if (zero) rs = 0;
   const int too_small = rs > b - margin;
@@ -640,9 +646,13 @@ __global__ void k_control(const double* __restrict__ theta, const double* __rest
 // ctl[6] = products until (and including) the one the step is taken on.
 __global__ void k_predict(const double* __restrict__ d, int b, double thr2, double tol, int* ctl,
                           double* __restrict__ coef) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const int t = threadIdx.x;  // one wave: the count by ballot, the rest in lane 0
   int r = 0;
-  for (int k = 0; k < b; ++k) r += d[k] >= thr2 * d[0];
+  for (int k0 = 0; k0 < b; k0 += 64) {
+    const int k = k0 + t;
+    r += __popcll(__ballot(k < b && d[k] >= thr2 * d[0]));
+  }
+  if (t != 0) return;
   const bool ok = r > 0 && r < b && d[r - 1] > 0.0 && d[b - 1] > 0.0 && isfinite(d[0]);
   const double c = 1.05 * (ok ? d[b - 1] : 0.0);
   const double x = ok ? 2.0 * d[r - 1] / c - 1.0 : 0.0;
@@ -715,9 +725,9 @@ pisco_status_t gemm_tn(NullCtx& c, const double2* P, const double2* Qm, double2*
 }
 
 pisco_status_t gemm_nn(NullCtx& c, const double2* P, const double2* M, double2* Y, int m,
-                       int k) {
-  dim3 g(ceil_div(m, 32), ceil_div(c.b, 32));
-  PISCO_KERNEL(c.h, k_gemm_nn, g, dim3(64), 0, P, M, Y, m, k, c.b);
+                       int k, bool tri = false) {
+  dim3 g(ceil_div(m, 16), ceil_div(c.b, 16));
+  PISCO_KERNEL(c.h, k_gemm_nn, g, dim3(64), 0, P, M, Y, m, k, c.b, tri ? 1 : 0);
   return PISCO_OK;
 }
 
@@ -759,7 +769,7 @@ pisco_status_t orth(NullCtx& c, const double2* Y, double2* tmp, double* rdiag, d
   pisco_status_t st;
   if ((st = gemm_tn(c, Y, Y, c.w.S, n))) return st;
   if ((st = chol_inv(c, c.w.S, shift, c.w.M, rdiag))) return st;
-  return gemm_nn(c, Y, c.w.M, tmp, n, b);
+  return gemm_nn(c, Y, c.w.M, tmp, n, b, true);
 }
 
 }  // namespace
