@@ -96,7 +96,7 @@ struct TraceScope {
 
 constexpr int kMaxQ = 32;
 constexpr int kAxSplit = 8;  // most K slices of the nullspace product A X
-constexpr int kTnRows = 64;  // row chunk of the b x b products X^H Y
+constexpr int kTnRows = 128;  // row chunk of the b x b products X^H Y
 constexpr int kMaxSupport = 4096;
 
 // Sizes derived from a problem description; everything a stage needs on the

@@ -177,63 +177,61 @@ __global__ void k_sum_cheb(const double2* __restrict__ parts, const double2* __r
 }
 
 // part[chunk] = P[rows of chunk, :]^H Q[rows of chunk, :]; P, Q column-major
-// n x b (b a multiple of 32); part is column-major b x b.  Rows are split
-// in chunks of kTnRows.  One wave per 32 x 32 block of the result and row
+// n x b (b a multiple of 16); part is column-major b x b.  Rows are split
+// in chunks of kTnRows.  One wave per 16 x 16 block of the result and row
 // chunk, on FP64 matrix cores (operand and accumulator lanes as in
-// k_gemm_ax): Re += Pr Qr + Pi Qi, Im += Pr Qi - Pi Qr.
+// k_gemm_ax): Re += Pr Qr + Pi Qi, Im += Pr Qi - Pi Qr.  With upper, blocks
+// below the diagonal are skipped (their entries of part are left as they
+// are).  The rows of the next 16 are loaded before the products of the
+// current ones; even and odd steps go to separate accumulators.
 __global__ void __launch_bounds__(64) k_gemm_tn(const double2* __restrict__ P,
                                                 const double2* __restrict__ Qm,
-                                                double2* __restrict__ part, int n, int b) {
+                                                double2* __restrict__ part, int n, int b,
+                                                int upper) {
+  if (upper && blockIdx.x > blockIdx.y) return;
   const int l = threadIdx.x, li = l & 15, lk = l >> 4;
-  const int i0 = blockIdx.x * 32, j0 = blockIdx.y * 32;
+  const int i0 = blockIdx.x * 16, j0 = blockIdx.y * 16;
   const int rbeg = blockIdx.z * kTnRows, rend = min(n, rbeg + kTnRows);
-  const double2* Pc[2] = {P + size_t(i0 + li) * n, P + size_t(i0 + 16 + li) * n};
-  const double2* Qc[2] = {Qm + size_t(j0 + li) * n, Qm + size_t(j0 + 16 + li) * n};
-  f64x4 cr[2][2], ci[2][2];
+  const double2* Pc = P + size_t(i0 + li) * n;
+  const double2* Qc = Qm + size_t(j0 + li) * n;
+  f64x4 cr[2], ci[2];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int h = 0; h < 2; ++h) cr[h] = ci[h] = f64x4{0.0, 0.0, 0.0, 0.0};
+  double2 pv[4], qv[4], pn[4], qn[4];
+  auto load = [&](int r0, double2 (&p)[4], double2 (&q)[4]) {
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      cr[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
-      ci[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
-    }
-  for (int r0 = rbeg; r0 < rend; r0 += 16) {
-    double2 pv[2][4], qv[2][4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int r = r0 + 4 * q + lk;
+    for (int u = 0; u < 4; ++u) {
+      const int r = r0 + 4 * u + lk;
       const bool ok = r < rend;
-#pragma unroll
-      for (int c = 0; c < 2; ++c) {
-        pv[c][q] = ok ? Pc[c][r] : make_double2(0.0, 0.0);
-        qv[c][q] = ok ? Qc[c][r] : make_double2(0.0, 0.0);
-      }
+      p[u] = ok ? Pc[r] : make_double2(0.0, 0.0);
+      q[u] = ok ? Qc[r] : make_double2(0.0, 0.0);
     }
+  };
+  load(rbeg, pv, qv);
+  for (int r0 = rbeg; r0 < rend; r0 += 16) {
+    if (r0 + 16 < rend) load(r0 + 16, pn, qn);
 #pragma unroll
-    for (int st = 0; st < 4; ++st)
+    for (int u = 0; u < 4; ++u)
 #pragma unroll
-      for (int half = 0; half < 2; ++half)
+      for (int half = 0; half < 2; ++half) {
+        const double2 x = pv[u], y = qv[u];
+        cr[u & 1] = __builtin_amdgcn_mfma_f64_16x16x4f64(half ? x.y : x.x, half ? y.y : y.x,
+                                                         cr[u & 1], 0, 0, 0);
+        ci[u & 1] = __builtin_amdgcn_mfma_f64_16x16x4f64(half ? -x.y : x.x, half ? y.x : y.y,
+                                                         ci[u & 1], 0, 0, 0);
+      }
 #pragma unroll
-        for (int i = 0; i < 2; ++i)
-#pragma unroll
-          for (int j = 0; j < 2; ++j) {
-            const double2 x = pv[i][st], y = qv[j][st];
-            cr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(half ? x.y : x.x, half ? y.y : y.x,
-                                                            cr[i][j], 0, 0, 0);
-            ci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(half ? -x.y : x.x, half ? y.x : y.y,
-                                                            ci[i][j], 0, 0, 0);
-          }
+    for (int u = 0; u < 4; ++u) {
+      pv[u] = pn[u];
+      qv[u] = qn[u];
+    }
   }
   double2* out = part + size_t(blockIdx.z) * b * b;
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int row = i0 + 16 * i + lk + 4 * v, col = j0 + 16 * j + li;
-        out[size_t(col) * b + row] = make_double2(cr[i][j][v], ci[i][j][v]);
-      }
+  for (int e = 0; e < 4; ++e) {
+    const int row = i0 + lk + 4 * e, col = j0 + li;
+    out[size_t(col) * b + row] = make_double2(cr[0][e] + cr[1][e], ci[0][e] + ci[1][e]);
+  }
 }
 
 // Y = P M; P column-major m x k, M column-major k x b, Y column-major m x b
@@ -714,11 +712,12 @@ struct NullCtx {
   NullWs w;
 };
 
-pisco_status_t gemm_tn(NullCtx& c, const double2* P, const double2* Qm, double2* out, int rows) {
+pisco_status_t gemm_tn(NullCtx& c, const double2* P, const double2* Qm, double2* out, int rows,
+                       bool upper = false) {
   const int b = c.b;
   const int chunks = int(ceil_div(rows, kTnRows));
-  dim3 g(ceil_div(b, 32), ceil_div(b, 32), chunks);
-  PISCO_KERNEL(c.h, k_gemm_tn, g, dim3(64), 0, P, Qm, c.w.part, rows, b);
+  dim3 g(ceil_div(b, 16), ceil_div(b, 16), chunks);
+  PISCO_KERNEL(c.h, k_gemm_tn, g, dim3(64), 0, P, Qm, c.w.part, rows, b, upper ? 1 : 0);
   const long long len = 1LL * b * b;
   PISCO_KERNEL(c.h, k_sum_parts, dim3(ceil_div(len, 256)), dim3(256), 0, c.w.part, out, len, chunks);
   return PISCO_OK;
@@ -767,7 +766,7 @@ pisco_status_t chol_inv(NullCtx& c, const double2* S, double shift, double2* M,
 pisco_status_t orth(NullCtx& c, const double2* Y, double2* tmp, double* rdiag, double shift) {
   const int n = c.p->n, b = c.b;
   pisco_status_t st;
-  if ((st = gemm_tn(c, Y, Y, c.w.S, n))) return st;
+  if ((st = gemm_tn(c, Y, Y, c.w.S, n, true))) return st;  // the factor reads the upper part
   if ((st = chol_inv(c, c.w.S, shift, c.w.M, rdiag))) return st;
   return gemm_nn(c, Y, c.w.M, tmp, n, b, true);
 }
