@@ -166,7 +166,7 @@ struct NullWs {
   double* theta;   // [b]
   double* filt;    // [8] Chebyshev filter coefficients (two steps of three)
   double* resid;   // [b]
-  double2* part;   // split-K partials
+  double2* part;   // row-chunk partials of the b x b products; residual partials
   int* ctl;        // [8] control words
   double* jac;     // Cholesky scratch (global-memory fallback) [b*(b+1)*2]
   double* heev;    // eigen-decomposition scratch [heev_workspace_doubles(b)]

@@ -50,9 +50,9 @@ __global__ void k_init_block(double2* X, int n, int b) {
 
 // ------------------------------------------------------------------ GEMMs
 
-// Z_part[ks] = A[:, kslice] X[kslice, :], A float2 row-major n x n (widened
-// exactly to FP64), X and Z column-major n x b (double2).  One wave per
-// 32 x 32 output tile and K slice, on FP64 matrix cores: each complex
+// Z = A X, A float2 row-major n x n (widened exactly to FP64), X and Z
+// column-major n x b (double2).  One wave per 32 x 32 output tile and K
+// slice, on FP64 matrix cores: each complex
 // 16 x 16 x 4 block step is four real v_mfma_f64_16x16x4f64 products
 // (Re += Ar Xr - Ai Xi, Im += Ar Xi + Ai Xr).  Operand lanes: lane l
 // supplies row (or column) l % 16 at k = k0 + 4 s + l / 16 for step s, so a
@@ -82,14 +82,25 @@ __device__ inline void ax_load(AxChunk& ch, const float2* Ar0, const float2* Ar1
   }
 }
 
-__global__ void __launch_bounds__(64) k_gemm_ax(const float2* __restrict__ A,
-                                                const double2* __restrict__ X,
-                                                double2* __restrict__ Zp, int n, int b,
-                                                int kchunk) {
-  const int l = threadIdx.x;
+// The kKS K slices of one tile are the kKS waves of one workgroup: each
+// leaves its 32 x 32 partial in LDS (column stride 33: no bank conflicts),
+// and the workgroup adds them in slice order (deterministic) and writes
+// out = a S + bc Y + g P with (a, bc, g) = coef[0..2] (Chebyshev steps; Y =
+// the block multiplied, P = prev, may be null) or out = S when coef is
+// null.  out may be prev (each element is read before it is written by the
+// same thread) but not X.
+template <int kKS>
+__global__ void __launch_bounds__(64 * kKS) k_gemm_ax(const float2* __restrict__ A,
+                                                      const double2* __restrict__ X,
+                                                      double2* out, int n, int b, int kchunk,
+                                                      const double* __restrict__ coef,
+                                                      const double2* prev) {
+  __shared__ double2 red[kKS > 1 ? kKS * 32 * 33 : 1];
+  const int l = threadIdx.x & 63;
+  const int z = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int li = l & 15, lk = l >> 4;
   const int r0 = blockIdx.x * 32, c0 = blockIdx.y * 32;
-  const int kbeg = blockIdx.z * kchunk;
+  const int kbeg = z * kchunk;
   const int kend = min(n, kbeg + kchunk);
   const bool v0 = r0 + li < n, v1 = r0 + 16 + li < n;
   const float2* Ar0 = A + size_t(v0 ? r0 + li : 0) * n;
@@ -130,18 +141,59 @@ __global__ void __launch_bounds__(64) k_gemm_ax(const float2* __restrict__ A,
     }
     cur = nxt;
   }
-  double2* out = Zp + size_t(blockIdx.z) * n * b;
+  // partial tile -> LDS slot z (row 16 i + lk + 4 v, column 16 j + li)
+  double2* slot = red + (kKS > 1 ? z * 32 * 33 : 0);
+  if (kKS > 1) {
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+      for (int j = 0; j < 2; ++j)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int row = r0 + 16 * i + lk + 4 * v, col = c0 + 16 * j + li;
-        if (row < n) out[size_t(col) * n + row] = make_double2(cr[i][j][v], ci[i][j][v]);
+        for (int v = 0; v < 4; ++v)
+          slot[(16 * j + li) * 33 + 16 * i + lk + 4 * v] = make_double2(cr[i][j][v], ci[i][j][v]);
+    __syncthreads();
+  }
+  double a = 1.0, bc = 0.0, g = 0.0;
+  if (coef) {
+    a = coef[0];
+    bc = coef[1];
+    g = coef[2];
+  }
+  auto emit = [&](int row, int col, double2 sum) {
+    const size_t o = size_t(c0 + col) * n + r0 + row;
+    double2 r = sum;
+    if (coef) {
+      const double2 y = X[o];
+      r = make_double2(a * sum.x + bc * y.x, a * sum.y + bc * y.y);
+      if (prev) {
+        const double2 q = prev[o];
+        r.x += g * q.x;
+        r.y += g * q.y;
       }
+    }
+    out[o] = r;
+  };
+  if (kKS > 1) {
+    for (int e = threadIdx.x; e < 32 * 32; e += 64 * kKS) {
+      const int row = e & 31, col = e >> 5;
+      if (r0 + row >= n) continue;
+      double2 sum = red[col * 33 + row];
+#pragma unroll
+      for (int q = 1; q < kKS; ++q) sum = zadd(sum, red[q * 32 * 33 + col * 33 + row]);
+      emit(row, col, sum);
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int row = 16 * i + lk + 4 * v, col = 16 * j + li;
+          if (r0 + row < n) emit(row, col, make_double2(cr[i][j][v], ci[i][j][v]));
+        }
+  }
 }
-
 
 // out = sum over `parts` slabs of size `len` (fixed order: deterministic)
 __global__ void k_sum_parts(const double2* __restrict__ parts, double2* __restrict__ out,
@@ -151,29 +203,6 @@ __global__ void k_sum_parts(const double2* __restrict__ parts, double2* __restri
   double2 s = parts[i];
   for (int k = 1; k < nparts; ++k) s = zadd(s, parts[size_t(k) * len + i]);
   out[i] = s;
-}
-
-// One step of the Chebyshev-filtered product: with S = A Y (the split-K
-// partials summed in fixed order), out = a S + b Y + g P, (a, b, g) =
-// coef[0..2] read from device memory so that a captured schedule needs no
-// host value.  P may be null (g is then ignored); out may be P (each
-// element is read before it is written by the same thread) but not Y.
-__global__ void k_sum_cheb(const double2* __restrict__ parts, const double2* __restrict__ Y,
-                           const double2* P, double2* out, long long len, int nparts,
-                           const double* __restrict__ coef) {
-  const long long i = blockIdx.x * 256LL + threadIdx.x;
-  if (i >= len) return;
-  double2 s = parts[i];
-  for (int k = 1; k < nparts; ++k) s = zadd(s, parts[size_t(k) * len + i]);
-  const double a = coef[0], bc = coef[1], g = coef[2];
-  const double2 y = Y[i];
-  double2 r = make_double2(a * s.x + bc * y.x, a * s.y + bc * y.y);
-  if (P) {
-    const double2 q = P[i];
-    r.x += g * q.x;
-    r.y += g * q.y;
-  }
-  out[i] = r;
 }
 
 // part[chunk] = P[rows of chunk, :]^H Q[rows of chunk, :]; P, Q column-major
@@ -795,24 +824,33 @@ pisco_status_t run_nullspace(Handle* h, const Plan& p, int b, int max_iters,
   const int margin = b / 8 > 4 ? b / 8 : 4;
   // K slices so that the product runs about ax_waves waves (at most kAxSplit)
   const long long tiles = 1LL * ceil_div(n, 32) * ceil_div(b, 32);
+  // (a power of two: the slices of a tile form one workgroup)
   int want = int(ceil_div(ax_waves > 0 ? ax_waves : 2048, tiles));
   want = want < 1 ? 1 : (want > kAxSplit ? kAxSplit : want);
+  while (want & (want - 1)) want &= want - 1;
   const int kchunk = 16 * int(ceil_div(ceil_div(n, want), 16));
-  const int ksplit = int(ceil_div(n, kchunk));
+  const int ksplit = want;  // slices past n (rounding) have an empty K range
   const int rchunks = int(ceil_div(n, 1024));
-  // out = A in (split-K partials in `part`, summed in fixed order); with
+  // out = A in (the K slices of a tile summed in fixed order in LDS); with
   // step 1 or 2 the sum forms the first or a later step of the Chebyshev
   // recurrence instead (prev = the previous block of the chain)
   auto product = [&](const double2* in, double2* out, const double2* prev,
                      int step) -> pisco_status_t {
-    dim3 g(ceil_div(n, 32), ceil_div(b, 32), ksplit);
-    PISCO_KERNEL(h, k_gemm_ax, g, dim3(64), 0, gram, in, c.w.part, n, b, kchunk);
-    if (step == 0)
-      PISCO_KERNEL(h, k_sum_parts, dim3(ceil_div(nb, 256)), dim3(256), 0, c.w.part, out, nb,
-                   ksplit);
-    else
-      PISCO_KERNEL(h, k_sum_cheb, dim3(ceil_div(nb, 256)), dim3(256), 0, c.w.part, in, prev,
-                   out, nb, ksplit, c.w.filt + 3 * (step - 1));
+    const dim3 g(ceil_div(n, 32), ceil_div(b, 32));
+    const double* coef = step ? c.w.filt + 3 * (step - 1) : nullptr;
+    switch (ksplit) {
+      case 8:
+        PISCO_KERNEL(h, k_gemm_ax<8>, g, dim3(512), 0, gram, in, out, n, b, kchunk, coef, prev);
+        break;
+      case 4:
+        PISCO_KERNEL(h, k_gemm_ax<4>, g, dim3(256), 0, gram, in, out, n, b, kchunk, coef, prev);
+        break;
+      case 2:
+        PISCO_KERNEL(h, k_gemm_ax<2>, g, dim3(128), 0, gram, in, out, n, b, kchunk, coef, prev);
+        break;
+      default:
+        PISCO_KERNEL(h, k_gemm_ax<1>, g, dim3(64), 0, gram, in, out, n, b, kchunk, coef, prev);
+    }
     return PISCO_OK;
   };
   // Products are counted in `done`.  Each of the first three is

@@ -112,11 +112,12 @@ size_t layout_null(const Plan& p, int b, void* ws, NullWs* o) {
   w.theta = c.take<double>(b);
   w.filt = c.take<double>(8);
   w.resid = c.take<double>(b);
-  // split-K partials of A X (up to kAxSplit slabs of n x b), row-chunk
-  // partials of the b x b products, and residual partials share one buffer
+  // row-chunk partials of the b x b products and residual partials share
+  // one buffer (the split-K partials of A X stay in LDS)
   const size_t chunks = (size_t(p.n) + kTnRows - 1) / kTnRows;
-  size_t part = size_t(kAxSplit) * nb;
-  if (chunks * bb > part) part = chunks * bb;
+  size_t part = chunks * bb;
+  const size_t rpart = ((size_t(p.n) + 1023) / 1024) * b;  // doubles
+  if (rpart > 2 * part) part = (rpart + 1) / 2;
   w.part = c.take<double2>(part);
   w.ctl = c.take<int>(16);
   w.jac = c.take<double>((size_t(b) + 1) * b * 2);
