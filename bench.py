@@ -78,7 +78,8 @@ def kernel_model(name: str, w, est, rs: int):
 
 
 KERNEL_SOURCES = {"k_gemm_ax": "nullspace.hip", "k_hetrd": "heev.hip",
-                  "k_chol_inv": "nullspace.hip", "k_gemm_tn": "nullspace.hip",
+                  "k_chol": "nullspace.hip", "k_tri_inv": "nullspace.hip",
+                  "k_gemm_tn": "nullspace.hip",
                   "k_gemm_nn": "nullspace.hip", "k_herk": "gx.hip", "k_power": "eig.hip",
                   "k_gather": "gram.hip", "k_rss": "maps.hip"}
 
