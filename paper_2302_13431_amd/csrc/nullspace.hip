@@ -12,8 +12,9 @@
 //   Z = A X                        (A = FP32 Gram widened exactly to FP64)
 //   X <- orth(Z) by Cholesky QR with column scaling; after the third product
 //        up to three products share one orthonormalisation, the scaled
-//        block staying well conditioned;
-// and, when the rate predicted from the Cholesky diagonal (about the
+//        block staying well conditioned, and such a chain applies a
+//        Chebyshev polynomial of A that damps everything below the block;
+// and, when an error model built from the Cholesky diagonal (about the
 // eigenvalues in orthogonal iteration) says the block has converged, a
 // Rayleigh-Ritz step
 //   H = X^H Z, eig(H) = U diag(theta) U^H     (tridiagonal route, heev.hip)
