@@ -7,10 +7,13 @@
  * Conventions shared by every entry point
  * ---------------------------------------
  *  - All array arguments except those marked "host" are DEVICE pointers owned
- *    by the caller.  The library never allocates device memory inside a
- *    call; scratch space comes from the caller's workspace, whose size is
- *    given by pisco_workspace_size().  Workspace pointers must be 256-byte
- *    aligned.
+ *    by the caller.  Scratch space comes from the caller's workspace, whose
+ *    size is given by pisco_workspace_size().  Workspace pointers must be
+ *    256-byte aligned.  The only device memory the library allocates inside
+ *    a call are plan-constant tables (DFT and sinc matrices, the support
+ *    list and its box map: a function of the sizes alone, at most a few MB
+ *    per problem shape), built by the first call that needs them, kept by
+ *    the handle and freed by pisco_destroy (see pisco_create).
  *  - Calls enqueue kernels on the handle's stream and return without
  *    synchronising, except where stated.  Results are valid once the stream
  *    has been synchronised.  No call issues hipMemsetAsync or host<->device
@@ -106,9 +109,13 @@ typedef struct {
 #define PISCO_STAGE_ALL       0   /* pisco_estimate, intermediates included */
 
 /* Handle creation.  `stream` is a hipStream_t (NULL = default stream).  The
- * handle owns only host state and one small device status word allocated
- * here (the one allocation the library makes; freed by pisco_destroy).  A
- * handle must not be used from two threads at once. */
+ * handle owns host state, one small device status word allocated here, and
+ * the plan-constant tables that calls build on first use with a problem
+ * shape (each build synchronises the stream once); pisco_destroy frees all
+ * of it.  A call that would build a table while its stream is being captured
+ * into a graph returns PISCO_ERR_UNSUPPORTED: run it once outside capture
+ * first (pisco_batch_create does so for every slice).  A handle must not be
+ * used from two threads at once. */
 pisco_status_t pisco_create(pisco_handle_t* handle, void* stream);
 pisco_status_t pisco_destroy(pisco_handle_t handle);
 pisco_status_t pisco_set_stream(pisco_handle_t handle, void* stream);

@@ -118,6 +118,41 @@ EstLayout est_layout(const Plan& p, int b, void* ws) {
 
 namespace pisco {
 
+pisco_status_t cached_table(Handle* h, const std::string& key, size_t bytes, void** out,
+                            const std::function<pisco_status_t(void*)>& build) {
+  auto& tables = h->table_owner ? h->table_owner->tables : h->tables;
+  auto it = tables.find(key);
+  if (it != tables.end()) {
+    *out = it->second;
+    return PISCO_OK;
+  }
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  hipError_t e = hipStreamIsCapturing(h->stream, &cs);
+  if (e != hipSuccess) return hip_check(h, e, "table capture query");
+  if (cs != hipStreamCaptureStatusNone) {
+    h->last_error = "a plan-constant table for this problem is not built yet; run the call "
+                    "once outside stream capture";
+    return PISCO_ERR_UNSUPPORTED;
+  }
+  void* p = nullptr;
+  e = hipMalloc(&p, bytes ? bytes : 1);
+  if (e != hipSuccess) return hip_check(h, e, "table allocation");
+  pisco_status_t st = build(p);
+  if (st == PISCO_OK) {
+    e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) st = hip_check(h, e, "table build");
+  }
+  if (st != PISCO_OK) {
+    (void)hipStreamSynchronize(h->stream);
+    (void)hipFree(p);
+    return st;
+  }
+  tables[key] = p;
+  *out = p;
+  return PISCO_OK;
+}
+
+
 size_t estimate_ws_size(const Plan& p, int b) { return est_layout(p, b, nullptr).total; }
 
 pisco_status_t estimate_core(Handle* h, const Plan& p, const pisco_opts_t& o, int b,
@@ -175,6 +210,7 @@ pisco_status_t pisco_destroy(pisco_handle_t handle) {
   Handle* h = reinterpret_cast<Handle*>(handle);
   if (!h) return PISCO_ERR_ARG;
   (void)hipStreamSynchronize(h->stream);
+  for (auto& kv : h->tables) (void)hipFree(kv.second);
   (void)hipHostFree(h->host_pinned);
   (void)hipFree(h->status_dev);
   delete h;
@@ -614,6 +650,7 @@ pisco_status_t pisco_batch_create(pisco_handle_t handle, int32_t B, const pisco_
       sh->stream = s;
       sh->status_dev = h->status_dev;
       sh->host_pinned = h->host_pinned;
+      sh->table_owner = h;
       bt->sub.push_back(sh);
     }
   }

@@ -5,6 +5,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <functional>
 #include <map>
 #include <string>
 #include <vector>
@@ -71,7 +72,19 @@ struct Handle {
   std::vector<TraceRec> records;
   // autotuner results per problem shape: nullspace block and product waves
   std::map<std::string, std::pair<int, int>> tuned;
+  // plan-constant device tables (DFT and sinc matrices, support lists, index
+  // maps) keyed by their exact parameters; freed by pisco_destroy.  A batch's
+  // per-stream handles use their parent's (table_owner).
+  std::map<std::string, void*> tables;
+  Handle* table_owner = nullptr;
 };
+
+// A handle-owned device table of `bytes` bytes identified by `key`: on first
+// use it is allocated, filled by `build` (kernels on the handle's stream)
+// and the stream synchronised, so that any later stream may read it.  A
+// first use while the stream is being captured is refused.
+pisco_status_t cached_table(Handle* h, const std::string& key, size_t bytes, void** out,
+                            const std::function<pisco_status_t(void*)>& build);
 
 // Brackets one kernel launch with events when tracing is on and the kernel
 // name contains the filter.
@@ -255,7 +268,14 @@ pisco_status_t axis_transform64(Handle* h, const double2* in, double2* out,
 pisco_status_t build_sinc(Handle* h, float2* M, int nout, int nin);
 
 // Writes the support offsets (z, y, x, 0) into `out` on the device.
-pisco_status_t launch_support(Handle* h, int4* out, int D, float radius);
+// Handle-cached (plan-constant) tables: the builders above and the support
+// list of |Lambda| = L points (cached_table); valid until pisco_destroy.
+pisco_status_t dft_table(Handle* h, const float2** M, int nout, int nin, int co, int ci,
+                         double period, double sign, double scale, double sigma);
+pisco_status_t dft_table(Handle* h, const double2** M, int nout, int nin, int co, int ci,
+                         double period, double sign, double scale, double sigma);
+pisco_status_t sinc_table(Handle* h, const float2** M, int nout, int nin);
+pisco_status_t support_table(Handle* h, const int4** out, int D, float radius, int L);
 
 inline pisco_status_t hip_check(Handle* h, hipError_t e, const char* what) {
   if (e == hipSuccess) return PISCO_OK;

@@ -12,6 +12,8 @@
 // Hermitian.  Transforms are separable passes of radix-2 Stockham FFTs held in
 // LDS; the forward passes skip the zero padding on input and the inverse passes
 // keep only the 4 tau + 1 lags per dimension on output.
+#include <cstdio>
+
 #include "common.hpp"
 
 namespace pisco {
@@ -283,9 +285,16 @@ __global__ void __launch_bounds__(256) k_gather(const float2* __restrict__ R,
   gram[size_t(r) * n + c] = v;
 }
 
-pisco_status_t launch_support(Handle* h, int4* out, int D, float radius) {
-  PISCO_KERNEL(h, k_support, dim3(1), dim3(64), 0, out, D, radius);
-  return PISCO_OK;
+pisco_status_t support_table(Handle* h, const int4** out, int D, float radius, int L) {
+  char key[64];
+  std::snprintf(key, sizeof key, "support %d %.9g", D, double(radius));
+  void* p = nullptr;
+  pisco_status_t st = cached_table(h, key, sizeof(int4) * size_t(L), &p, [&](void* q) {
+    PISCO_KERNEL(h, k_support, dim3(1), dim3(64), 0, static_cast<int4*>(q), D, radius);
+    return PISCO_OK;
+  });
+  *out = static_cast<const int4*>(p);
+  return st;
 }
 
 static unsigned blocks_for(const PassGeom& g) { return ceil_div(g.nlines, g.lpb); }
@@ -299,7 +308,9 @@ pisco_status_t run_gram(Handle* h, const Plan& p, const float2* acs, float2* gra
   const int F0 = p.F[0], F1 = p.F[1], F2 = p.F[2];
   const int B0 = p.B[0], B1 = p.B[1], B2 = p.B[2];
 
-  PISCO_KERNEL(h, k_support, dim3(1), dim3(64), 0, w.support, p.D, p.radius);
+  const int4* support = nullptr;
+  pisco_status_t sst = support_table(h, &support, p.D, p.radius, p.L);
+  if (sst) return sst;
 
   // forward: x, y, (z)
   float2* S1 = w.S;                                   // [Q][A0][A1][F2]
@@ -331,7 +342,7 @@ pisco_status_t run_gram(Handle* h, const Plan& p, const float2* acs, float2* gra
   PISCO_KERNEL(h, k_inv_x, dim3(blocks_for(ix)), dim3(256), 0, w.T2, w.R, ix, F2, B2, scale);
 
   dim3 gg(ceil_div(p.n, 256), p.n);
-  PISCO_KERNEL(h, k_gather, gg, dim3(256), 0, w.R, w.support, gram, Q, p.L, B0, B1, B2, p.nlag);
+  PISCO_KERNEL(h, k_gather, gg, dim3(256), 0, w.R, support, gram, Q, p.L, B0, B1, B2, p.nlag);
   return PISCO_OK;
 }
 

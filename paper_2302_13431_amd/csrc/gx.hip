@@ -17,6 +17,8 @@
 // Lk = 4 tau + 1 is the smallest grid that holds every lag without aliasing.
 #include <cmath>
 
+#include <cstdio>
+
 #include "common.hpp"
 
 namespace pisco {
@@ -301,33 +303,37 @@ pisco_status_t run_gx(Handle* h, const Plan& p, int b, int precision, const doub
   const int Bz = p.D == 3 ? box : 1, tz = p.D == 3 ? tau : 0;
   const int ncell = Bz * box * box;
   pisco_status_t st;
-  if ((st = launch_support(h, w.support, p.D, p.radius))) return st;
-
-  // transform matrices
-  float2* m = w.Mx;
-  float2* M1[3];
-  float2* M3[3];
-  float2* M4[3];
+  // plan-constant tables (built once per handle and problem shape)
+  const int4* support = nullptr;
+  if ((st = support_table(h, &support, p.D, p.radius, p.L))) return st;
+  const float2* M1[3] = {nullptr, nullptr, nullptr};
+  const float2* M3[3] = {nullptr, nullptr, nullptr};
+  const float2* M4[3] = {nullptr, nullptr, nullptr};
   for (int d = 0; d < 3; ++d) {
     const bool used = d > 0 || p.D == 3;
-    const int Lk = p.K[d], bd = used ? box : 1, Bd = p.B[d], lr = p.lr[d];
-    M1[d] = m;
-    m += size_t(Lk) * bd;
-    M3[d] = m;
-    m += size_t(Bd) * Lk;
-    M4[d] = m;
-    m += size_t(lr) * Bd;
     if (!used) continue;
+    const int Lk = p.K[d], Bd = p.B[d], lr = p.lr[d];
     // filter spectra: e^{+i 2 pi n f / Lk}, n = box index - tau
-    if ((st = build_dft(h, M1[d], Lk, bd, 0, tau, Lk, +1.0, 1.0, 0.0))) return st;
+    if ((st = dft_table(h, &M1[d], Lk, box, 0, tau, Lk, +1.0, 1.0, 0.0))) return st;
     // lags from spectra: (1/Lk) e^{+i 2 pi m f / Lk}, m = out index - 2 tau
-    if ((st = build_dft(h, M3[d], Bd, Lk, 2 * tau, 0, Lk, +1.0, 1.0 / Lk, 0.0))) return st;
+    if ((st = dft_table(h, &M3[d], Bd, Lk, 2 * tau, 0, Lk, +1.0, 1.0 / Lk, 0.0))) return st;
     // low-res evaluation: e^{-i 2 pi m x}, x = (a - floor(N/2)) / N
-    if ((st = build_dft(h, M4[d], lr, Bd, lr / 2, 2 * tau, lr, -1.0, 1.0, 0.0))) return st;
+    if ((st = dft_table(h, &M4[d], lr, Bd, lr / 2, 2 * tau, lr, -1.0, 1.0, 0.0))) return st;
   }
-
-  int* map = reinterpret_cast<int*>(w.Kh);  // Kh is free until step 2
-  PISCO_KERNEL(h, k_box_map, dim3(ceil_div(ncell, 256)), dim3(256), 0, w.support, p.L, map, tz, tau, box, box, ncell);
+  // support-box cell -> support index
+  const int* map = nullptr;
+  {
+    char key[96];
+    std::snprintf(key, sizeof key, "boxmap %d %.9g %d", p.D, double(p.radius), tau);
+    void* q = nullptr;
+    st = cached_table(h, key, sizeof(int) * size_t(ncell), &q, [&](void* t) {
+      PISCO_KERNEL(h, k_box_map, dim3(ceil_div(ncell, 256)), dim3(256), 0, support, p.L,
+                   static_cast<int*>(t), tz, tau, box, box, ncell);
+      return PISCO_OK;
+    });
+    if (st) return st;
+    map = static_cast<const int*>(q);
+  }
   float2* bufA = w.Tmp;
   float2* bufB = w.Tmp + w.tmp_half;
   PISCO_KERNEL(h, k_scatter_box, dim3(ceil_div(1LL * b * Q * ncell, 256)), dim3(256), 0, basis, counts, map, bufA, p.n, p.L, Q, b, ncell);

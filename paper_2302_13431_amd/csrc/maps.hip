@@ -101,21 +101,15 @@ pisco_status_t run_maps(Handle* h, const Plan& p, int phase_rule, const float2* 
   const long long N = p.Nlr;
   pisco_status_t st;
   const int first = p.D == 3 ? 0 : 1;
-  // matrices: apodized DFT (acs -> lr, FP64) and sinc (lr -> out) per dimension
-  double2* ma = w.Ma;
-  float2* m = w.Mx;
-  double2* Ma[3];
-  float2* Ms[3];
-  for (int d = 0; d < 3; ++d) {
-    Ma[d] = ma;
-    ma += size_t(p.lr[d]) * p.acs[d];
-    Ms[d] = m;
-    m += size_t(p.out[d]) * p.lr[d];
-    if (d < first) continue;
+  // plan-constant matrices (built once per handle and problem shape):
+  // apodized DFT (acs -> lr, FP64) and sinc (lr -> out) per dimension
+  const double2* Ma[3] = {nullptr, nullptr, nullptr};
+  const float2* Ms[3] = {nullptr, nullptr, nullptr};
+  for (int d = first; d < 3; ++d) {
     const int A = p.acs[d], n = p.lr[d];
     if (phase_rule == 0)
-      if ((st = build_dft(h, Ma[d], n, A, n / 2, A / 2, n, +1.0, 1.0, A / 4.0))) return st;
-    if ((st = build_sinc(h, Ms[d], p.out[d], n))) return st;
+      if ((st = dft_table(h, &Ma[d], n, A, n / 2, A / 2, n, +1.0, 1.0, A / 4.0))) return st;
+    if ((st = sinc_table(h, &Ms[d], p.out[d], n))) return st;
   }
   if (phase_rule == 0) {
     // rho~ = apodized low-res reconstruction in FP64: [Q][A0][A1][A2] -> [Q][lr]

@@ -6,6 +6,8 @@
 // one-axis passes.
 #include <cmath>
 
+#include <cstdio>
+
 #include "common.hpp"
 
 namespace pisco {
@@ -203,6 +205,46 @@ pisco_status_t build_dft(Handle* h, double2* M, int nout, int nin, int co, int c
 pisco_status_t build_sinc(Handle* h, float2* M, int nout, int nin) {
   PISCO_KERNEL(h, k_build_sinc, dim3(ceil_div(nout * nin, 256)), dim3(256), 0, M, nout, nin);
   return PISCO_OK;
+}
+
+namespace {
+template <class T>
+pisco_status_t dft_table_t(Handle* h, const T** M, const char* tag, int nout, int nin, int co,
+                           int ci, double period, double sign, double scale, double sigma) {
+  char key[192];
+  std::snprintf(key, sizeof key, "%s %d %d %d %d %.17g %.17g %.17g %.17g", tag, nout, nin, co,
+                ci, period, sign, scale, sigma);
+  void* p = nullptr;
+  pisco_status_t st = cached_table(h, key, sizeof(T) * size_t(nout) * nin, &p,
+                                   [&](void* q) {
+                                     return build_dft(h, static_cast<T*>(q), nout, nin, co, ci,
+                                                      period, sign, scale, sigma);
+                                   });
+  *M = static_cast<const T*>(p);
+  return st;
+}
+}  // namespace
+
+pisco_status_t dft_table(Handle* h, const float2** M, int nout, int nin, int co, int ci,
+                         double period, double sign, double scale, double sigma) {
+  return dft_table_t(h, M, "dft32", nout, nin, co, ci, period, sign, scale, sigma);
+}
+
+pisco_status_t dft_table(Handle* h, const double2** M, int nout, int nin, int co, int ci,
+                         double period, double sign, double scale, double sigma) {
+  return dft_table_t(h, M, "dft64", nout, nin, co, ci, period, sign, scale, sigma);
+}
+
+pisco_status_t sinc_table(Handle* h, const float2** M, int nout, int nin) {
+  char key[64];
+  std::snprintf(key, sizeof key, "sinc %d %d", nout, nin);
+  void* p = nullptr;
+  pisco_status_t st = cached_table(h, key, sizeof(float2) * size_t(nout) * nin, &p,
+                                   [&](void* q) {
+                                     return build_sinc(h, static_cast<float2*>(q), nout, nin);
+                                   });
+  *M = static_cast<const float2*>(p);
+  return st;
 }
 
 }  // namespace pisco
