@@ -196,7 +196,14 @@ pisco_status_t pisco_create(pisco_handle_t* handle, void* stream) {
   }
   std::memset(h->host_pinned, 0, 256);
   e = hipMemcpy(h->status_dev, h->host_pinned, 64, hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipHostMalloc(reinterpret_cast<void**>(&h->host_ctl), 64, hipHostMallocCoherent);
+  if (e == hipSuccess) {
+    std::memset(h->host_ctl, 0, 64);
+    e = hipHostGetDevicePointer(reinterpret_cast<void**>(&h->host_ctl_dev), h->host_ctl, 0);
+  }
   if (e != hipSuccess) {
+    if (h->host_ctl) (void)hipHostFree(h->host_ctl);
     (void)hipHostFree(h->host_pinned);
     (void)hipFree(h->status_dev);
     delete h;
@@ -211,6 +218,7 @@ pisco_status_t pisco_destroy(pisco_handle_t handle) {
   if (!h) return PISCO_ERR_ARG;
   (void)hipStreamSynchronize(h->stream);
   for (auto& kv : h->tables) (void)hipFree(kv.second);
+  (void)hipHostFree(h->host_ctl);
   (void)hipHostFree(h->host_pinned);
   (void)hipFree(h->status_dev);
   delete h;
@@ -650,6 +658,8 @@ pisco_status_t pisco_batch_create(pisco_handle_t handle, int32_t B, const pisco_
       sh->stream = s;
       sh->status_dev = h->status_dev;
       sh->host_pinned = h->host_pinned;
+      sh->host_ctl = h->host_ctl;
+      sh->host_ctl_dev = h->host_ctl_dev;
       sh->table_owner = h;
       bt->sub.push_back(sh);
     }

@@ -63,6 +63,10 @@ struct Handle {
   hipStream_t stream = nullptr;
   uint32_t* status_dev = nullptr;   // device status word (PISCO_FLAG_*)
   uint32_t* host_pinned = nullptr;  // pinned host mirror for status/flags
+  // fine-grained pinned words the schedule kernels write directly (host
+  // pointer and the device's pointer to the same memory)
+  int* host_ctl = nullptr;
+  int* host_ctl_dev = nullptr;
   std::string last_error;
   // kernel tracing (pisco_trace_enable): events bracket matching launches
   bool trace = false;
@@ -159,7 +163,6 @@ struct Carver {
 // Workspace layouts; each `layout_*` fills pointers when `ws` is non-null and
 // returns the bytes used.
 struct GramWs {
-  int4* support;   // [L] (z, y, x, 0)
   float2* S;       // [Q][F0][F1][F2] coil spectra (plus the stage buffers)
   float2* T1;      // pair intermediates
   float2* T2;
@@ -187,13 +190,11 @@ struct NullWs {
 size_t layout_null(const Plan& p, int b, void* ws, NullWs* out);
 
 struct GxWs {
-  int4* support;   // [L]
   float2* Fh;      // [b][Q][nK] filter spectra
   float2* Tmp;     // separable-transform scratch, two halves of tmp_half
   size_t tmp_half;
   float2* Kh;      // [P][nK] K^(f)
   float2* Klag;    // [P][nlag]
-  float2* Mx;      // DFT matrices (3 dims, forward and lag)
 };
 size_t layout_gx(const Plan& p, int b, void* ws, GxWs* out);
 
@@ -203,11 +204,9 @@ struct MapsWs {
   double2* rtB;
   double2* m;      // [Nlr] coil combination (FP64)
   double* pmax;    // per-block maxima of |m|
-  double2* Ma;     // apodized DFT matrices (FP64)
   float2* tmpA;    // separable-transform scratch
   float2* tmpB;
   float2* cref;    // [Q][Nlr] phase-referenced maps
-  float2* Mx;      // interpolation matrices
 };
 size_t layout_maps(const Plan& p, void* ws, MapsWs* out);
 

@@ -608,7 +608,7 @@ __global__ void __launch_bounds__(256) k_colresid(const double2* __restrict__ Y,
 //   ctl[5] = plain steps predicted before the next Rayleigh-Ritz
 __global__ void k_control(const double* __restrict__ theta, const double* __restrict__ rpart,
                           int nchunks, int b, double thr2, double tol, int margin, int iter,
-                          int* ctl, unsigned* status) {
+                          int* ctl, unsigned* status, int* host_ctl) {
   // one wave: the counts by ballot, the largest residual by lane shuffles
   const int t = threadIdx.x;
   const double t0 = theta[0];
@@ -649,6 +649,10 @@ __global__ void k_control(const double* __restrict__ theta, const double* __rest
   }
   ctl[5] = need;
   if (!finite) atomicOr(status, PISCO_FLAG_NONFINITE);
+  if (host_ctl) {  // the same words, straight to pinned host memory
+    for (int k = 0; k < 6; ++k) host_ctl[k] = ctl[k];
+    __threadfence_system();
+  }
 }
 
 // Schedule of the first Rayleigh-Ritz step and the Chebyshev filter, both
@@ -673,7 +677,7 @@ __global__ void k_control(const double* __restrict__ theta, const double* __rest
 // tolerance, since a Rayleigh-Ritz step that fails costs several products.
 // ctl[6] = products until (and including) the one the step is taken on.
 __global__ void k_predict(const double* __restrict__ d, int b, double thr2, double tol, int* ctl,
-                          double* __restrict__ coef) {
+                          double* __restrict__ coef, int* host_ctl) {
   const int t = threadIdx.x;  // one wave: the count by ballot, the rest in lane 0
   int r = 0;
   for (int k0 = 0; k0 < b; k0 += 64) {
@@ -709,6 +713,10 @@ __global__ void k_predict(const double* __restrict__ d, int b, double thr2, doub
     }
   }
   ctl[6] = need < 1 ? 1 : (need > 40 ? 40 : need);
+  if (host_ctl) {
+    host_ctl[6] = ctl[6];
+    __threadfence_system();
+  }
 }
 
 __global__ void k_finalize(const double2* __restrict__ W, const double* __restrict__ theta,
@@ -895,14 +903,12 @@ pisco_status_t run_nullspace(Handle* h, const Plan& p, int b, int max_iters,
         return st;
       if (at3) {
         PISCO_KERNEL(h, k_predict, dim3(1), dim3(64), 0, c.w.resid, b, thr2, tol, c.w.ctl,
-                     c.w.filt);
+                     c.w.filt, fixed ? nullptr : h->host_ctl_dev);
         filtered = true;
         if (!fixed) {
-          hipError_t e = hipMemcpyAsync(h->host_pinned, c.w.ctl, 8 * sizeof(int),
-                                        hipMemcpyDeviceToHost, s);
-          if (e == hipSuccess) e = hipStreamSynchronize(s);
+          hipError_t e = hipStreamSynchronize(s);
           if (e != hipSuccess) return hip_check(h, e, "nullspace predict");
-          rr_at = done + reinterpret_cast<const int*>(h->host_pinned)[6];
+          rr_at = done + reinterpret_cast<volatile int*>(h->host_ctl)[6];
         }
       }
       continue;
@@ -915,14 +921,11 @@ pisco_status_t run_nullspace(Handle* h, const Plan& p, int b, int max_iters,
     double* rpart = reinterpret_cast<double*>(c.w.part);
     PISCO_KERNEL(h, k_colresid, dim3(rchunks, b), dim3(256), 0, X, W, c.w.theta, rpart, n, b);
     PISCO_KERNEL(h, k_control, dim3(1), dim3(64), 0, c.w.theta, rpart, rchunks, b, thr2, tol,
-                 margin, done - 1, c.w.ctl, h->status_dev);
+                 margin, done - 1, c.w.ctl, h->status_dev, fixed ? nullptr : h->host_ctl_dev);
     if (fixed) break;
-    hipError_t e = hipMemcpyAsync(h->host_pinned, c.w.ctl, 6 * sizeof(int),
-                                  hipMemcpyDeviceToHost, s);
-    if (e != hipSuccess) return hip_check(h, e, "nullspace ctl copy");
-    e = hipStreamSynchronize(s);
+    hipError_t e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_check(h, e, "nullspace sync");
-    const int* hc = reinterpret_cast<const int*>(h->host_pinned);
+    const volatile int* hc = h->host_ctl;
     if (hc[1] || hc[3] || hc[4]) break;
     if (done >= max_iters) break;
     rr_at = done + hc[5];

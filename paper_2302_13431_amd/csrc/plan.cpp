@@ -85,7 +85,6 @@ pisco_status_t make_plan(const pisco_problem_t* prob, Plan* p, std::string* err)
 size_t layout_gram(const Plan& p, void* ws, GramWs* o) {
   Carver c(ws);
   GramWs w{};
-  w.support = c.take<int4>(p.L);
   // Forward spectra need two buffers (pass ping-pong); the pair passes need
   // T1 = [P][B0][F1][F2] and T2 = [P][B0][B1][F2].
   const size_t s1 = size_t(p.Q) * p.F[0] * p.F[1] * p.F[2];
@@ -129,7 +128,6 @@ size_t layout_null(const Plan& p, int b, void* ws, NullWs* o) {
 size_t layout_gx(const Plan& p, int b, void* ws, GxWs* o) {
   Carver c(ws);
   GxWs w{};
-  w.support = c.take<int4>(p.L);
   w.Fh = c.take<float2>(size_t(b) * p.Q * p.nK);
   // scratch for the separable passes: filter spectra (b Q planes on the K
   // grid), lag planes (P on the K grid) and the lag -> low-res passes
@@ -141,11 +139,6 @@ size_t layout_gx(const Plan& p, int b, void* ws, GxWs* o) {
   w.Tmp = c.take<float2>(2 * half);
   w.Kh = c.take<float2>(size_t(p.P) * p.nK);
   w.Klag = c.take<float2>(size_t(p.P) * p.nlag);
-  size_t msz = 0;
-  for (int d = 0; d < 3; ++d)
-    msz += size_t(p.K[d]) * (2 * p.tau + 1) + size_t(p.B[d]) * p.K[d] +
-           size_t(p.lr[d]) * p.B[d];
-  w.Mx = c.take<float2>(msz + 64);
   if (o) *o = w;
   return c.used + 256;
 }
@@ -160,18 +153,12 @@ size_t layout_maps(const Plan& p, void* ws, MapsWs* o) {
   w.rtB = c.take<double2>(r1 > r2 ? r1 : r2);
   w.m = c.take<double2>(p.Nlr);
   w.pmax = c.take<double>((p.Nlr + 255) / 256 + 1);
-  size_t ma = 0;
-  for (int d = 0; d < 3; ++d) ma += size_t(p.lr[d]) * p.acs[d];
-  w.Ma = c.take<double2>(ma + 8);
   // largest intermediate of the interpolation passes (lr -> out in x, y, z order)
   const size_t a = size_t(p.Q) * p.lr[0] * p.lr[1] * p.out[2];
   const size_t b = size_t(p.Q) * p.lr[0] * p.out[1] * p.out[2];
   w.tmpA = c.take<float2>(a > b ? a : b);
   w.tmpB = c.take<float2>(a > b ? a : b);
   w.cref = c.take<float2>(size_t(p.Q) * p.Nlr);
-  size_t msz = 0;
-  for (int d = 0; d < 3; ++d) msz += size_t(p.out[d]) * p.lr[d];
-  w.Mx = c.take<float2>(msz + 64);
   if (o) *o = w;
   return c.used + 256;
 }
