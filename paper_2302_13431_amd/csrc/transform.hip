@@ -27,11 +27,11 @@ template <class T, class U> __device__ inline T widen(U v) { return T{v.x, v.y};
 // out[outer][o][inner] = sum_i M[o][i] in[outer][i][inner]   (inner > 1)
 // Block = 256 consecutive (outer, inner) columns x a tile of kOT outputs;
 // the tile's rows of M are staged in LDS and read as broadcasts, each input
-// load feeds kOT complex multiply-adds.
-constexpr int kOT = 16;
+// load feeds kOT complex multiply-adds.  kOT = 4 is used when 16 would leave
+// the launch with too few workgroups to fill the chip.
 constexpr int kMidMaxIn = 256;
 
-template <class TI, class TO>
+template <class TI, class TO, int kOT>
 __global__ void __launch_bounds__(256) k_axis_mid(const TI* __restrict__ in,
                                                   TO* __restrict__ out,
                                                   const TO* __restrict__ M, long long outer,
@@ -65,31 +65,35 @@ __global__ void __launch_bounds__(256) k_axis_mid(const TI* __restrict__ in,
 }
 
 // out[line][o] = sum_i M[o][i] in[line][i]   (contiguous lines)
-// A block stages 16 lines in LDS; thread (line, o) computes one output.
+// One output per thread: a block takes lpb = max(1, 256 / nout) lines,
+// staged in LDS, so that even a long output line spreads over many
+// workgroups; the rows of M come through the caches.
 template <class TI, class TO>
 __global__ void __launch_bounds__(256) k_axis_last(const TI* __restrict__ in,
                                                    TO* __restrict__ out,
                                                    const TO* __restrict__ M, long long lines,
-                                                   int nin, int nout) {
+                                                   int nin, int nout, int lpb) {
   using S = typename Acc<TO>::S;
   extern __shared__ unsigned char smem[];
-  TO* sl = reinterpret_cast<TO*>(smem);  // [16][nin]
-  const long long l0 = blockIdx.x * 16LL;
-  const int nl = lines - l0 < 16 ? int(lines - l0) : 16;
+  TO* sl = reinterpret_cast<TO*>(smem);  // [lpb][nin]
+  const int per = (nout + 255) / 256;    // blocks per line when lpb == 1
+  const long long l0 = per > 1 ? blockIdx.x / per : blockIdx.x * (long long)lpb;
+  const int obase = per > 1 ? int(blockIdx.x % per) * 256 : 0;
+  const int nl = per > 1 ? 1 : (lines - l0 < lpb ? int(lines - l0) : lpb);
   for (int e = threadIdx.x; e < nl * nin; e += 256) sl[e] = widen<TO>(in[size_t(l0) * nin + e]);
   __syncthreads();
-  for (int e = threadIdx.x; e < nl * nout; e += 256) {
-    const int ln = e / nout, o = e - ln * nout;
-    const TO* x = sl + ln * nin;
-    const TO* m = M + size_t(o) * nin;
-    S ar = 0, ai = 0;
-    for (int i = 0; i < nin; ++i) {
-      const TO mv = m[i], xv = x[i];
-      ar = fma(mv.x, xv.x, fma(-mv.y, xv.y, ar));
-      ai = fma(mv.x, xv.y, fma(mv.y, xv.x, ai));
-    }
-    out[size_t(l0 + ln) * nout + o] = TO{ar, ai};
+  const int span = per > 1 ? 256 : nout;
+  const int ln = threadIdx.x / span, o = obase + threadIdx.x % span;
+  if (ln >= nl || o >= nout) return;
+  const TO* x = sl + ln * nin;
+  const TO* m = M + size_t(o) * nin;
+  S ar = 0, ai = 0;
+  for (int i = 0; i < nin; ++i) {
+    const TO mv = m[i], xv = x[i];
+    ar = fma(mv.x, xv.x, fma(-mv.y, xv.y, ar));
+    ai = fma(mv.x, xv.y, fma(mv.y, xv.x, ai));
   }
+  out[size_t(l0 + ln) * nout + o] = TO{ar, ai};
 }
 
 template <class TI, class TO>
@@ -101,14 +105,24 @@ static pisco_status_t axis_impl(Handle* h, const TI* in, TO* out, const int shap
   for (int d = axis + 1; d < 4; ++d) inner *= shape_in[d];
   const int nin = shape_in[axis];
   if (inner == 1) {
-    const size_t lds = size_t(16) * nin * sizeof(TO);
-    if (lds > 64 * 1024) return PISCO_ERR_UNSUPPORTED;
-    PISCO_KERNEL(h, (k_axis_last<TI, TO>), dim3(ceil_div(outer, 16)), dim3(256), lds, in, out, M,
-                 outer, nin, nout);
+    int lpb = nout >= 256 ? 1 : 256 / nout;
+    const int fit = int((64 * 1024) / (size_t(nin) * sizeof(TO)));  // staged lines in 64 KB
+    lpb = lpb < fit ? lpb : fit;
+    const int per = (nout + 255) / 256;
+    const size_t lds = size_t(lpb) * nin * sizeof(TO);
+    if (lpb < 1) return PISCO_ERR_UNSUPPORTED;
+    const long long blocks = per > 1 ? outer * per : ceil_div(outer, lpb);
+    PISCO_KERNEL(h, (k_axis_last<TI, TO>), dim3(blocks), dim3(256), lds, in, out, M, outer, nin,
+                 nout, lpb);
   } else {
     if (nin > kMidMaxIn) return PISCO_ERR_UNSUPPORTED;
-    PISCO_KERNEL(h, (k_axis_mid<TI, TO>), dim3(ceil_div(outer * inner, 256), ceil_div(nout, kOT)),
-                 dim3(256), 0, in, out, M, outer, nin, nout, int(inner));
+    const long long cols = ceil_div(outer * inner, 256);
+    if (cols * ceil_div(nout, 16) >= 1024)
+      PISCO_KERNEL(h, (k_axis_mid<TI, TO, 16>), dim3(cols, ceil_div(nout, 16)), dim3(256), 0, in,
+                   out, M, outer, nin, nout, int(inner));
+    else
+      PISCO_KERNEL(h, (k_axis_mid<TI, TO, 4>), dim3(cols, ceil_div(nout, 4)), dim3(256), 0, in,
+                   out, M, outer, nin, nout, int(inner));
   }
   return PISCO_OK;
 }
