@@ -32,9 +32,29 @@ namespace {
 constexpr int kTrdLdsMax = 96;   // largest b reduced with the matrix in LDS
 constexpr int kTriMax = 1024;    // largest b of the tridiagonal kernels
 
+// Sum over the 64 lanes of a wave (all lanes active), every lane getting
+// the total: an inclusive scan within each row of 16 lanes by DPP moves
+// (row_shr 1, 2, 4, 8), then row_bcast:15 into rows 1 and 3 and
+// row_bcast:31 into rows 2 and 3, so that lane 63 holds the sum, read back
+// with readlane.  No LDS round trips.
+template <int kCtrl, int kRowMask>
+__device__ inline double dpp_f64(double v) {
+  const long long x = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, int(x), kCtrl, kRowMask, 0xf, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, int(x >> 32), kCtrl, kRowMask, 0xf, true);
+  return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned>(lo));
+}
 __device__ inline double wave_sum(double v) {
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
+  v += dpp_f64<0x111, 0xf>(v);  // row_shr:1
+  v += dpp_f64<0x112, 0xf>(v);  // row_shr:2
+  v += dpp_f64<0x114, 0xf>(v);  // row_shr:4
+  v += dpp_f64<0x118, 0xf>(v);  // row_shr:8
+  v += dpp_f64<0x142, 0xa>(v);  // row_bcast:15
+  v += dpp_f64<0x143, 0xc>(v);  // row_bcast:31
+  const long long x = __double_as_longlong(v);
+  const unsigned lo = __builtin_amdgcn_readlane(int(x), 63);
+  const unsigned hi = __builtin_amdgcn_readlane(int(x >> 32), 63);
+  return __longlong_as_double((static_cast<long long>(hi) << 32) | lo);
 }
 __device__ inline double wave_max(double v) {
   for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
@@ -248,16 +268,28 @@ __device__ void back_transform(const double* z, int b, const double2* __restrict
     const int r = t + 64 * q;
     u[q] = make_double2(r < b ? z[r] : 0.0, 0.0);
   }
-  for (int k = b - 2; k >= 0; --k) {
-    const double2 tk = tau[k];
-    if (tk.x == 0.0 && tk.y == 0.0) continue;
-    const double2* v = refl + size_t(k) * b;
-    double2 vq[kPL];
-    double sr = 0.0, si = 0.0;  // v^H u
+  // the reflector of the next step is loaded while this one is applied
+  auto load = [&](int k, double2 (&vq)[kPL], double2& tk) {
+    tk = k >= 0 ? tau[k] : make_double2(0.0, 0.0);
+    const double2* v = refl + size_t(k >= 0 ? k : 0) * b;
 #pragma unroll
     for (int q = 0; q < kPL; ++q) {
       const int r = t + 64 * q;
-      vq[q] = (r > k && r < b) ? v[r] : make_double2(0.0, 0.0);
+      vq[q] = (k >= 0 && r > k && r < b) ? v[r] : make_double2(0.0, 0.0);
+    }
+  };
+  double2 vn[kPL], tn;
+  load(b - 2, vn, tn);
+  for (int k = b - 2; k >= 0; --k) {
+    double2 vq[kPL];
+#pragma unroll
+    for (int q = 0; q < kPL; ++q) vq[q] = vn[q];
+    const double2 tk = tn;
+    load(k - 1, vn, tn);
+    if (tk.x == 0.0 && tk.y == 0.0) continue;
+    double sr = 0.0, si = 0.0;  // v^H u
+#pragma unroll
+    for (int q = 0; q < kPL; ++q) {
       sr += vq[q].x * u[q].x + vq[q].y * u[q].y;
       si += vq[q].x * u[q].y - vq[q].y * u[q].x;
     }
