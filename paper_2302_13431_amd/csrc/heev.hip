@@ -261,6 +261,9 @@ template <int kPL>
 __device__ void back_transform(const double* z, int b, const double2* __restrict__ refl,
                                const double2* __restrict__ tau, double2* __restrict__ U,
                                int col) {
+  // reflectors come from global memory kDepth steps ahead of their use (a
+  // ring of registers), so that the chain of steps does not wait on the L2
+  constexpr int kDepth = kPL <= 2 ? 4 : 1;
   const int t = threadIdx.x;
   double2 u[kPL];
 #pragma unroll
@@ -268,7 +271,6 @@ __device__ void back_transform(const double* z, int b, const double2* __restrict
     const int r = t + 64 * q;
     u[q] = make_double2(r < b ? z[r] : 0.0, 0.0);
   }
-  // the reflector of the next step is loaded while this one is applied
   auto load = [&](int k, double2 (&vq)[kPL], double2& tk) {
     tk = k >= 0 ? tau[k] : make_double2(0.0, 0.0);
     const double2* v = refl + size_t(k >= 0 ? k : 0) * b;
@@ -278,32 +280,121 @@ __device__ void back_transform(const double* z, int b, const double2* __restrict
       vq[q] = (k >= 0 && r > k && r < b) ? v[r] : make_double2(0.0, 0.0);
     }
   };
-  double2 vn[kPL], tn;
-  load(b - 2, vn, tn);
-  for (int k = b - 2; k >= 0; --k) {
-    double2 vq[kPL];
+  double2 ring[kDepth][kPL], tr[kDepth];
 #pragma unroll
-    for (int q = 0; q < kPL; ++q) vq[q] = vn[q];
-    const double2 tk = tn;
-    load(k - 1, vn, tn);
-    if (tk.x == 0.0 && tk.y == 0.0) continue;
-    double sr = 0.0, si = 0.0;  // v^H u
+  for (int dd = 0; dd < kDepth; ++dd) load(b - 2 - dd, ring[dd], tr[dd]);
+  for (int k0 = b - 2; k0 >= 0; k0 -= kDepth) {
 #pragma unroll
-    for (int q = 0; q < kPL; ++q) {
-      sr += vq[q].x * u[q].x + vq[q].y * u[q].y;
-      si += vq[q].x * u[q].y - vq[q].y * u[q].x;
+    for (int dd = 0; dd < kDepth; ++dd) {
+      const int k = k0 - dd;
+      if (k >= 0) {
+        double2 vq[kPL];
+#pragma unroll
+        for (int q = 0; q < kPL; ++q) vq[q] = ring[dd][q];
+        const double2 tk = tr[dd];
+        load(k - kDepth, ring[dd], tr[dd]);
+        if (tk.x != 0.0 || tk.y != 0.0) {
+          double sr = 0.0, si = 0.0;  // v^H u
+#pragma unroll
+          for (int q = 0; q < kPL; ++q) {
+            sr += vq[q].x * u[q].x + vq[q].y * u[q].y;
+            si += vq[q].x * u[q].y - vq[q].y * u[q].x;
+          }
+          sr = wave_sum(sr);
+          si = wave_sum(si);
+          const double2 ts = zmul(tk, make_double2(sr, si));
+#pragma unroll
+          for (int q = 0; q < kPL; ++q) u[q] = zsub(u[q], zmul(vq[q], ts));
+        }
+      }
     }
-    sr = wave_sum(sr);
-    si = wave_sum(si);
-    const double2 ts = zmul(tk, make_double2(sr, si));
-#pragma unroll
-    for (int q = 0; q < kPL; ++q) u[q] = zsub(u[q], zmul(vq[q], ts));
   }
 #pragma unroll
   for (int q = 0; q < kPL; ++q) {
     const int r = t + 64 * q;
     if (r < b) U[size_t(col) * b + r] = u[q];
   }
+}
+
+// Eigenvector z of T for lambda by the twisted factorisation, the same
+// arithmetic as tri::twisted_vector but on one wave: the top-down pivots
+// D+ and ratios L+ (lane 0) and the bottom-up D- and U- (lane 1) run side by
+// side, the twist index (smallest |gamma|, the larger index on ties) is a
+// wave reduction, the two outward recurrences for z again run on lanes 0
+// and 1, and the norm is a wave sum.  Lp, Um, Dp, Dm are n-length LDS
+// scratch; all 64 lanes call it.
+__device__ void twisted_vector_wave(const double* d, const double* e, int n, double lambda,
+                                    double pivmin, double* Lp, double* Um, double* Dp,
+                                    double* Dm, double* z) {
+  const int t = threadIdx.x;
+  if (n == 1) {
+    if (t == 0) z[0] = 1.0;
+    __syncthreads();
+    return;
+  }
+  if (t < 2) {
+    const bool up = t == 1;
+    double q = d[up ? n - 1 : 0] - lambda;
+    if (fabs(q) < pivmin) q = -pivmin;
+    if (up)
+      Dm[n - 1] = q;
+    else
+      Dp[0] = q;
+    for (int s = 0; s + 1 < n; ++s) {
+      const int ie = up ? n - 2 - s : s;      // off-diagonal entry
+      const int id = up ? n - 2 - s : s + 1;  // diagonal entry of the new pivot
+      const double ratio = e[ie] / q;
+      double nq = d[id] - lambda - ratio * e[ie];
+      if (fabs(nq) < pivmin) nq = -pivmin;
+      if (up) {
+        Um[n - 1 - s] = ratio;
+        Dm[id] = nq;
+      } else {
+        Lp[s] = ratio;
+        Dp[id] = nq;
+      }
+      q = nq;
+    }
+  }
+  __syncthreads();
+  // twist: gamma_{n-1} = D+(n-1), gamma_i = D+(i) + D-(i) - (d_i - lambda)
+  double best = INFINITY;
+  int r = -1;
+  for (int i = t; i < n; i += 64) {
+    const double g = i == n - 1 ? fabs(Dp[n - 1]) : fabs(Dp[i] + Dm[i] - (d[i] - lambda));
+    if (g < best || (g == best && i > r)) {
+      best = g;
+      r = i;
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    const double ob = __shfl_xor(best, off, 64);
+    const int orr = __shfl_xor(r, off, 64);
+    if (ob < best || (ob == best && orr > r)) {
+      best = ob;
+      r = orr;
+    }
+  }
+  if (r < 0) r = n - 1;  // every gamma NaN: the sequential rule keeps n - 1
+  for (int i = t; i < n; i += 64) z[i] = i == r ? 1.0 : 0.0;
+  __syncthreads();
+  if (t < 2) {
+    const bool up = t == 1;
+    const int len = up ? n - 1 - r : r;
+    double zz = 1.0;
+    for (int s = 0; s < len; ++s) {
+      const int i = up ? r + 1 + s : r - 1 - s;
+      zz = -(up ? Um[i] : Lp[i]) * zz;
+      z[i] = zz;
+    }
+  }
+  __syncthreads();
+  double ss = 0.0;
+  for (int i = t; i < n; i += 64) ss += z[i] * z[i];
+  ss = wave_sum(ss);
+  const double inv = 1.0 / sqrt(ss);
+  for (int i = t; i < n; i += 64) z[i] *= inv;
+  __syncthreads();
 }
 
 // One workgroup (one wave) per eigenvalue j.  Members of a cluster (gaps
@@ -344,8 +435,7 @@ __global__ void __launch_bounds__(64) k_tri_vector(const double* __restrict__ d,
   if (cs != j) return;  // the cluster's first workgroup computes it
   bool inverse = ce > cs;
   if (!inverse) {
-    if (t == 0) tri::twisted_vector(sd, se, b, sl[j], pivmin, w0, w1, z);
-    __syncthreads();
+    twisted_vector_wave(sd, se, b, sl[j], pivmin, w0, w1, w2, w3, z);
     // residual ||(T - lambda) z||_inf against a few ulps of ||T||
     const double lj = sl[j];
     double r = 0.0;
