@@ -320,6 +320,13 @@ __global__ void __launch_bounds__(64) k_gemm_nn(const double2* __restrict__ Pm,
   }
 }
 
+__device__ inline double readlane_f64(double v, int lane) {
+  const long long x = __double_as_longlong(v);
+  const unsigned lo = __builtin_amdgcn_readlane(int(x), lane);
+  const unsigned hi = __builtin_amdgcn_readlane(int(x >> 32), lane);
+  return __longlong_as_double((static_cast<long long>(hi) << 32) | lo);
+}
+
 // ------------------------------------------------------------------ Cholesky QR
 
 constexpr int kCholLdsMax = 96;  // largest b factored with the matrix in LDS
@@ -333,12 +340,16 @@ constexpr int kCholThreads = 512;
 // `gwork` otherwise.  A pivot that is not positive is replaced by a tiny
 // one and reported through *flag.
 //
-// Blocked in panels of kNB = 8 columns (b must be a multiple).  Per panel
-// J, every thread that owns a later column j factors the diagonal block
-// R_JJ^H R_JJ = T_JJ entirely in its own registers (the same few hundred
-// operations in every lane: no cross-lane traffic, no barrier), then solves
-// R_JJ^H R_J,j = T_J,j for its column of the panel row.  After a barrier
-// R_JJ is stored and the trailing update T_ij -= R_Ji^H R_Jj runs in 2 x 2
+// Blocked in panels of kNB = 8 rows (b must be a multiple).  Per panel J
+// the block row T_J,J: is eliminated right-looking, one column per lane:
+// lanes 0..7 of a wave hold the diagonal block's columns, lanes 8..63 a
+// group of 56 later columns, each lane its column's 8 panel entries in
+// registers.  Step k takes the pivot and row k of the diagonal block from
+// lanes 0..7 by readlane, so the 8 steps run without barriers or LDS
+// round trips; every wave that owns a column group repeats the diagonal
+// lanes.  The finished block row R_J,: goes straight to R, and its part
+// right of the diagonal block to LDS for the trailing update.
+// After a barrier the trailing update T_ij -= R_Ji^H R_Jj runs in 2 x 2
 // patches of the upper triangle, one per thread, operands in registers.
 template <bool kLds>
 __global__ void __launch_bounds__(kCholThreads) k_chol(const double2* __restrict__ S, int b,
@@ -347,84 +358,102 @@ __global__ void __launch_bounds__(kCholThreads) k_chol(const double2* __restrict
                                                double2* __restrict__ gwork,
                                                int* __restrict__ flag,
                                                double* __restrict__ rdiag) {
-  constexpr int kNB = 8;                        // panel width (b is a multiple)
+  constexpr int kNB = 8;                        // panel height (b is a multiple)
   constexpr int kNT = kCholThreads;
+  constexpr int kCols = 64 - kNB;               // later columns per wave and group
   __shared__ double2 lds_mat[kLds ? kCholLdsMax * (kCholLdsMax + 1) : 1];
   __shared__ double dsc[kLds ? kCholLdsMax : 1024];
   double2* T = kLds ? lds_mat : gwork;
   const int ld = b + 1;
-  const int t = threadIdx.x;
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   auto at = [&](int i, int j) -> double2& { return T[i * ld + j]; };
-  for (int k = t; k < b; k += kNT) {
-    const double d = S[size_t(k) * b + k].x;
-    dsc[k] = d > 0.0 ? 1.0 / sqrt(d) : 0.0;
-  }
-  __syncthreads();
-  for (int e = t; e < b * b; e += kNT) {
-    const int i = e % b, j = e / b;  // S is column-major: e = j b + i
-    if (j < i) continue;
-    double2 v = zscale(S[e], dsc[i] * dsc[j]);
+  auto stage = [&](int e, double2 v) {
+    const int i = e % b, j = e / b;  // S and R are column-major: e = j b + i
+    if (j < i) {
+      R[e] = make_double2(0.0, 0.0);  // below the diagonal; the rest per panel
+      return;
+    }
+    v = zscale(v, dsc[i] * dsc[j]);
     if (i == j) v = make_double2(v.x + shift, 0.0);
     at(i, j) = v;
+  };
+  if constexpr (kLds) {
+    // every load in flight at once, before the scales are known
+    constexpr int kPer = (kCholLdsMax * kCholLdsMax + kNT - 1) / kNT;
+    double2 v[kPer];
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int e = t + kNT * q;
+      v[q] = e < b * b ? S[e] : make_double2(0.0, 0.0);
+    }
+    if (t < b) {
+      const double d = S[size_t(t) * b + t].x;
+      dsc[t] = d > 0.0 ? 1.0 / sqrt(d) : 0.0;
+      dsc_out[t] = dsc[t];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int e = t + kNT * q;
+      if (e < b * b) stage(e, v[q]);
+    }
+  } else {
+    for (int k = t; k < b; k += kNT) {
+      const double d = S[size_t(k) * b + k].x;
+      dsc[k] = d > 0.0 ? 1.0 / sqrt(d) : 0.0;
+      dsc_out[k] = dsc[k];
+    }
+    __syncthreads();
+    for (int e = t; e < b * b; e += kNT) stage(e, S[e]);
   }
   __syncthreads();
   for (int k0 = 0; k0 < b; k0 += kNB) {
     const int k1 = k0 + kNB, nc = b - k1;
-    // threads owning a later column (whole waves; wave 0 at least, which
-    // also serves the last panel)
-    const int nact = nc > 64 ? ((nc + 63) & ~63) : 64;
-    double2 x[kNB][kNB];
-    if (t < nact) {
+    const int groups = nc > 0 ? (nc + kCols - 1) / kCols : 1;
+    for (int g = wave; g < groups; g += kNT / 64) {
+      const int c = lane < kNB ? k0 + lane : k1 + kCols * g + (lane - kNB);
+      const bool live = c < b;
+      double2 x[kNB];  // x[r] = T(k0 + r, c); rows below the diagonal start at zero
 #pragma unroll
-      for (int i = 0; i < kNB; ++i)
-#pragma unroll
-        for (int j = i; j < kNB; ++j) x[i][j] = at(k0 + i, k0 + j);
+      for (int r = 0; r < kNB; ++r)
+        x[r] = live && k0 + r <= c ? at(k0 + r, c) : make_double2(0.0, 0.0);
       bool bad = false;
-      double ri[kNB];
 #pragma unroll
       for (int k = 0; k < kNB; ++k) {
-        double d = x[k][k].x;
+        double d = readlane_f64(x[k].x, k);
         bad |= !(d > 1e-300);
         d = d > 1e-300 ? d : 1e-300;
-        ri[k] = rsqrt(d);
-        x[k][k] = make_double2(d * ri[k], 0.0);
+        const double ri = rsqrt(d);
+        const bool piv = lane == k;
+        x[k].x = piv ? d * ri : x[k].x * ri;
+        x[k].y = piv ? 0.0 : x[k].y * ri;
 #pragma unroll
-        for (int j = k + 1; j < kNB; ++j) x[k][j] = zscale(x[k][j], ri[k]);
-#pragma unroll
-        for (int i = k + 1; i < kNB; ++i)
-#pragma unroll
-          for (int j = i; j < kNB; ++j) x[i][j] = zsub(x[i][j], zmulc(x[k][i], x[k][j]));
-      }
-      if (t == 0) {
-        if (bad) *flag = 1;
-        // diagonal of the unscaled factor (R' D^-1): converges to the
-        // eigenvalue magnitudes in orthogonal iteration
-        if (rdiag)
-#pragma unroll
-          for (int k = 0; k < kNB; ++k)
-            rdiag[k0 + k] = dsc[k0 + k] > 0.0 ? x[k][k].x / dsc[k0 + k] : 0.0;
-      }
-      // panel row, one column per thread (read and written by that thread
-      // only): forward substitution with R_JJ^H
-      for (int j = k1 + t; j < b; j += nact) {
-        double2 w[kNB];
-#pragma unroll
-        for (int r = 0; r < kNB; ++r) {
-          double2 acc = at(k0 + r, j);
-#pragma unroll
-          for (int l = 0; l < r; ++l) acc = zsub(acc, zmulc(x[l][r], w[l]));
-          w[r] = zscale(acc, ri[r]);
-          at(k0 + r, j) = w[r];
+        for (int i = k + 1; i < kNB; ++i) {
+          const double2 rki = make_double2(readlane_f64(x[k].x, i), readlane_f64(x[k].y, i));
+          x[i] = zsub(x[i], zmulc(rki, x[k]));
         }
+      }
+      if (bad && t == 0) *flag = 1;
+      // diagonal of the unscaled factor (R' D^-1): converges to the
+      // eigenvalue magnitudes in orthogonal iteration
+      if (rdiag && g == 0 && lane < kNB) {
+        double dg = 0.0;
+#pragma unroll
+        for (int r = 0; r < kNB; ++r) dg = r == lane ? x[r].x : dg;
+        rdiag[k0 + lane] = dsc[k0 + lane] > 0.0 ? dg / dsc[k0 + lane] : 0.0;
+      }
+      // the diagonal block is not read again (and other groups may still be
+      // loading it): its lanes write R only
+      if (live && (lane >= kNB || g == 0)) {
+#pragma unroll
+        for (int r = 0; r < kNB; ++r)
+          if (k0 + r <= c) {
+            if (lane >= kNB) at(k0 + r, c) = x[r];
+            R[size_t(c) * b + k0 + r] = x[r];
+          }
       }
     }
     __syncthreads();
-    if (t == 0) {
-#pragma unroll
-      for (int i = 0; i < kNB; ++i)
-#pragma unroll
-        for (int j = i; j < kNB; ++j) at(k0 + i, k0 + j) = x[i][j];
-    }
     // trailing update in 2 x 2 patches (pi <= pj) of the upper triangle
     const int m = nc >> 1;
     const int npatch = m * (m + 1) / 2;
@@ -456,19 +485,8 @@ __global__ void __launch_bounds__(kCholThreads) k_chol(const double2* __restrict
     }
     __syncthreads();
   }
-  for (int e = t; e < b * b; e += kNT) {
-    const int i = e % b, j = e / b;
-    R[e] = i <= j ? at(i, j) : make_double2(0.0, 0.0);
-  }
-  for (int k = t; k < b; k += kNT) dsc_out[k] = dsc[k];
 }
 
-__device__ inline double readlane_f64(double v, int lane) {
-  const long long x = __double_as_longlong(v);
-  const unsigned lo = __builtin_amdgcn_readlane(int(x), lane);
-  const unsigned hi = __builtin_amdgcn_readlane(int(x >> 32), lane);
-  return __longlong_as_double((static_cast<long long>(hi) << 32) | lo);
-}
 
 // M = D R^{-1}, one column j per wave: back substitution R x = e_j in
 // column (axpy) order, k = j down to 0: x_k = r_k / R_kk, then
