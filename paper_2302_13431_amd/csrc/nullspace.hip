@@ -330,7 +330,7 @@ __device__ inline double readlane_f64(double v, int lane) {
 // ------------------------------------------------------------------ Cholesky QR
 
 constexpr int kCholLdsMax = 96;  // largest b factored with the matrix in LDS
-constexpr int kCholThreads = 512;
+constexpr int kCholThreads = 1024;
 
 // Cholesky factor of D S D + shift I, D = diag(S)^{-1/2}: R (upper, column-
 // major b x b, entries below the diagonal zero) and D itself (dsc), so that
@@ -367,15 +367,18 @@ __global__ void __launch_bounds__(kCholThreads) k_chol(const double2* __restrict
   const int ld = b + 1;
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   auto at = [&](int i, int j) -> double2& { return T[i * ld + j]; };
-  auto stage = [&](int e, double2 v) {
-    const int i = e % b, j = e / b;  // S and R are column-major: e = j b + i
-    if (j < i) {
-      R[e] = make_double2(0.0, 0.0);  // below the diagonal; the rest per panel
-      return;
-    }
+  // S and R are column-major.  The upper triangle of T is staged here and
+  // the part of R below the diagonal zeroed, in a loop of its own (merged
+  // into one branch, the two kinds of store become flat stores that wait
+  // on memory); the rest of R is written per panel
+  auto stage = [&](int i, int j, double2 v) {
+    if (j < i) return;
     v = zscale(v, dsc[i] * dsc[j]);
     if (i == j) v = make_double2(v.x + shift, 0.0);
     at(i, j) = v;
+  };
+  auto zero_lower = [&](int i, int j) {
+    if (j < i) R[size_t(j) * b + i] = make_double2(0.0, 0.0);
   };
   if constexpr (kLds) {
     // every load in flight at once, before the scales are known
@@ -392,10 +395,31 @@ __global__ void __launch_bounds__(kCholThreads) k_chol(const double2* __restrict
       dsc_out[t] = dsc[t];
     }
     __syncthreads();
+    // element e = t + kNT q is (i, j) = (e mod b, e div b), stepped
+    // without a division per element
+    const int di = kNT % b, dj = kNT / b;
+    int i = t % b, j = t / b;
 #pragma unroll
     for (int q = 0; q < kPer; ++q) {
-      const int e = t + kNT * q;
-      if (e < b * b) stage(e, v[q]);
+      if (t + kNT * q < b * b) stage(i, j, v[q]);
+      i += di;
+      j += dj;
+      if (i >= b) {
+        i -= b;
+        ++j;
+      }
+    }
+    i = t % b;
+    j = t / b;
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      if (t + kNT * q < b * b) zero_lower(i, j);
+      i += di;
+      j += dj;
+      if (i >= b) {
+        i -= b;
+        ++j;
+      }
     }
   } else {
     for (int k = t; k < b; k += kNT) {
@@ -404,7 +428,8 @@ __global__ void __launch_bounds__(kCholThreads) k_chol(const double2* __restrict
       dsc_out[k] = dsc[k];
     }
     __syncthreads();
-    for (int e = t; e < b * b; e += kNT) stage(e, S[e]);
+    for (int e = t; e < b * b; e += kNT) stage(e % b, e / b, S[e]);
+    for (int e = t; e < b * b; e += kNT) zero_lower(e % b, e / b);
   }
   __syncthreads();
   for (int k0 = 0; k0 < b; k0 += kNB) {
@@ -429,8 +454,10 @@ __global__ void __launch_bounds__(kCholThreads) k_chol(const double2* __restrict
         x[k].y = piv ? 0.0 : x[k].y * ri;
 #pragma unroll
         for (int i = k + 1; i < kNB; ++i) {
+          // x_i -= conj(r_ki) x_k as four fused multiply-adds
           const double2 rki = make_double2(readlane_f64(x[k].x, i), readlane_f64(x[k].y, i));
-          x[i] = zsub(x[i], zmulc(rki, x[k]));
+          x[i].x = fma(-rki.x, x[k].x, fma(-rki.y, x[k].y, x[i].x));
+          x[i].y = fma(-rki.x, x[k].y, fma(rki.y, x[k].x, x[i].y));
         }
       }
       if (bad && t == 0) *flag = 1;
