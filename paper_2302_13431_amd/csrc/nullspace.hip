@@ -54,8 +54,11 @@ __global__ void k_init_block(double2* X, int n, int b) {
 // Z = A X, A float2 row-major n x n (widened exactly to FP64), X and Z
 // column-major n x b (double2).  One wave per 32 x 32 output tile and K
 // slice, on FP64 matrix cores: each complex
-// 16 x 16 x 4 block step is four real v_mfma_f64_16x16x4f64 products
-// (Re += Ar Xr - Ai Xi, Im += Ar Xi + Ai Xr).  Operand lanes: lane l
+// 16 x 16 x 4 block step is three real v_mfma_f64_16x16x4f64 products, the
+// three-multiplication form of a complex product: T1 += Ar Xr, T2 += Ai Xi,
+// T3 += (Ar + Ai)(Xr + Xi), and at the end Re = T1 - T2, Im = T3 - T1 - T2
+// (a quarter fewer matrix-core products than Re += Ar Xr - Ai Xi, Im += Ar
+// Xi + Ai Xr; the rounding error stays of order eps sum |A||X|).  Operand lanes: lane l
 // supplies row (or column) l % 16 at k = k0 + 4 s + l / 16 for step s, so a
 // lane's four k of one chunk are 4 apart and every load instruction reads
 // 4 consecutive elements per row; accumulator element v of lane l is row
@@ -91,7 +94,7 @@ __device__ inline void ax_load(AxChunk& ch, const float2* Ar0, const float2* Ar1
 // null.  out may be prev (each element is read before it is written by the
 // same thread) but not X.
 template <int kKS>
-__global__ void __launch_bounds__(64 * kKS) k_gemm_ax(const float2* __restrict__ A,
+__global__ void __launch_bounds__(64 * kKS) __attribute__((amdgpu_waves_per_eu(2))) k_gemm_ax(const float2* __restrict__ A,
                                                       const double2* __restrict__ X,
                                                       double2* out, int n, int b, int kchunk,
                                                       const double* __restrict__ coef,
@@ -108,40 +111,47 @@ __global__ void __launch_bounds__(64 * kKS) k_gemm_ax(const float2* __restrict__
   const float2* Ar1 = A + size_t(v1 ? r0 + 16 + li : 0) * n;
   const double2* X0 = X + size_t(c0 + li) * n;
   const double2* X1 = X + size_t(c0 + 16 + li) * n;
-  f64x4 cr[2][2], ci[2][2];
+  f64x4 t1[2][2], t2[2][2], t3[2][2];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
-      cr[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
-      ci[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
+      t1[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
+      t2[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
+      t3[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
     }
   AxChunk cur, nxt;
   ax_load(cur, Ar0, Ar1, v0, v1, X0, X1, kbeg, lk, kend);
   for (int k0 = kbeg; k0 < kend; k0 += 16) {
     if (k0 + 16 < kend) ax_load(nxt, Ar0, Ar1, v0, v1, X0, X1, k0 + 16, lk, kend);
-    // the eight accumulators are updated in turn, so that the two products
+    // the twelve accumulators are updated in turn, so that two products
     // into one accumulator are never back to back
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
 #pragma unroll
-      for (int half = 0; half < 2; ++half) {
+      for (int i = 0; i < 2; ++i) {
+        const double ar = cur.a[i][s].x, ai = cur.a[i][s].y, as = ar + ai;
 #pragma unroll
-        for (int i = 0; i < 2; ++i) {
-          const double ar = cur.a[i][s].x, ai = cur.a[i][s].y;
-#pragma unroll
-          for (int j = 0; j < 2; ++j) {
-            const double xr = cur.x[j][s].x, xi = cur.x[j][s].y;
-            cr[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(half ? -ai : ar, half ? xi : xr,
-                                                            cr[i][j], 0, 0, 0);
-            ci[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(half ? ai : ar, half ? xr : xi,
-                                                            ci[i][j], 0, 0, 0);
-          }
+        for (int j = 0; j < 2; ++j) {
+          const double xr = cur.x[j][s].x, xi = cur.x[j][s].y;
+          t1[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar, xr, t1[i][j], 0, 0, 0);
+          t2[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai, xi, t2[i][j], 0, 0, 0);
+          t3[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(as, xr + xi, t3[i][j], 0, 0, 0);
         }
       }
     }
     cur = nxt;
   }
+  f64x4 cr[2][2], ci[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        cr[i][j][v] = t1[i][j][v] - t2[i][j][v];
+        ci[i][j][v] = t3[i][j][v] - t1[i][j][v] - t2[i][j][v];
+      }
   // partial tile -> LDS slot z (row 16 i + lk + 4 v, column 16 j + li)
   double2* slot = red + (kKS > 1 ? z * 32 * 33 : 0);
   if (kKS > 1) {
