@@ -103,7 +103,20 @@ __global__ void __launch_bounds__(64 * kKS) __attribute__((amdgpu_waves_per_eu(2
   const int l = threadIdx.x & 63;
   const int z = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int li = l & 15, lk = l >> 4;
-  const int r0 = blockIdx.x * 32, c0 = blockIdx.y * 32;
+  // Workgroups go to the eight XCDs in turn (linear id mod 8).  Tiles are
+  // dealt so that each XCD runs one contiguous range, row tile by row tile
+  // with its column tiles adjacent: the column tiles of a row tile then run
+  // together on one XCD and share the rows of A they read in its L2.
+  int r0, c0;
+  {
+    const int ntx = gridDim.x, nty = gridDim.y, total = ntx * nty;
+    const int id = blockIdx.x + ntx * blockIdx.y;
+    const int xcd = id % 8, slot = id / 8;
+    const int base = total / 8, extra = total % 8;
+    const int tile = xcd * base + (xcd < extra ? xcd : extra) + slot;
+    r0 = (tile / nty) * 32;
+    c0 = (tile % nty) * 32;
+  }
   const int kbeg = z * kchunk;
   const int kend = min(n, kbeg + kchunk);
   const bool v0 = r0 + li < n, v1 = r0 + 16 + li < n;
