@@ -272,8 +272,21 @@ __global__ void __launch_bounds__(256) k_gather(const float2* __restrict__ R,
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   const int r = blockIdx.y;
   if (c >= n) return;
-  const int lo = r <= c ? r : c, hi = r <= c ? c : r;
-  const int p = lo / L, i = lo - p * L, q = hi / L, j = hi - q * L;
+  // (coil, support point) of the row once per workgroup; of the column by a
+  // float reciprocal with a one-step correction (exact: n <= 32 x 4096 = 2^17,
+  // far below where the estimate could be off by more than one)
+  const int pr = r / L, ir = r - pr * L;
+  int pc = __float2int_rz(float(c) * (1.0f / float(L)));
+  int ic = c - pc * L;
+  if (ic < 0) {
+    --pc;
+    ic += L;
+  } else if (ic >= L) {
+    ++pc;
+    ic -= L;
+  }
+  const bool up = r <= c;
+  const int p = up ? pr : pc, i = up ? ir : ic, q = up ? pc : pr, j = up ? ic : ir;
   const int4 ni = sup[i], nj = sup[j];
   const int dz = ni.x - nj.x + (B0 - 1) / 2;
   const int dy = ni.y - nj.y + (B1 - 1) / 2;

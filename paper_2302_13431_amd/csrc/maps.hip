@@ -25,12 +25,24 @@ __global__ void __launch_bounds__(256) k_phase_m(const float2* __restrict__ c,
   const long long v = blockIdx.x * 256LL + threadIdx.x;
   double mag = 0.0;
   if (v < N) {
+    // coils in batches of eight, each batch's loads in flight together
+    constexpr int kB = 8;
     double2 acc = make_double2(0.0, 0.0);
-    for (int q = 0; q < Q; ++q) {
-      const float2 a = c[size_t(q) * N + v];
-      const double2 r = rho[size_t(q) * N + v];
-      acc.x = fma(double(a.x), r.x, fma(double(a.y), r.y, acc.x));
-      acc.y = fma(double(a.x), r.y, fma(-double(a.y), r.x, acc.y));
+    for (int q0 = 0; q0 < Q; q0 += kB) {
+      float2 a[kB];
+      double2 r[kB];
+#pragma unroll
+      for (int u = 0; u < kB; ++u) {
+        const bool ok = q0 + u < Q;
+        a[u] = ok ? c[size_t(q0 + u) * N + v] : make_float2(0.f, 0.f);
+        r[u] = ok ? rho[size_t(q0 + u) * N + v] : make_double2(0.0, 0.0);
+      }
+#pragma unroll
+      for (int u = 0; u < kB; ++u) {
+        if (q0 + u >= Q) break;
+        acc.x = fma(double(a[u].x), r[u].x, fma(double(a[u].y), r[u].y, acc.x));
+        acc.y = fma(double(a[u].x), r[u].y, fma(-double(a[u].y), r[u].x, acc.y));
+      }
     }
     m[v] = acc;
     mag = sqrt(zabs2(acc));
@@ -51,10 +63,11 @@ __global__ void __launch_bounds__(256) k_phase_apply(const float2* __restrict__ 
                                                      float2* __restrict__ cref, int Q,
                                                      long long N) {
   __shared__ double gmax;
-  if (threadIdx.x == 0) {
+  if (threadIdx.x < 64) {  // the block maxima, read by one wave in parallel
     double g = 0.0;
-    for (int i = 0; i < nblk; ++i) g = fmax(g, pmax[i]);
-    gmax = g;
+    for (int i = threadIdx.x; i < nblk; i += 64) g = fmax(g, pmax[i]);
+    for (int off = 32; off > 0; off >>= 1) g = fmax(g, __shfl_xor(g, off, 64));
+    if (threadIdx.x == 0) gmax = g;
   }
   __syncthreads();
   const long long v = blockIdx.x * 256LL + threadIdx.x;
@@ -63,10 +76,17 @@ __global__ void __launch_bounds__(256) k_phase_apply(const float2* __restrict__ 
   const double mag = sqrt(zabs2(mv));
   double2 a = make_double2(1.0, 0.0);
   if (mag > 1e-12 * gmax && mag > 0.0) a = make_double2(mv.x / mag, mv.y / mag);
-  for (int q = 0; q < Q; ++q) {
-    const float2 cv = c[size_t(q) * N + v];
-    cref[size_t(q) * N + v] = make_float2(float(cv.x * a.x - cv.y * a.y),
-                                          float(cv.x * a.y + cv.y * a.x));
+  constexpr int kB = 8;  // coils in batches, each batch's loads in flight together
+  for (int q0 = 0; q0 < Q; q0 += kB) {
+    float2 cv[kB];
+#pragma unroll
+    for (int u = 0; u < kB; ++u)
+      cv[u] = q0 + u < Q ? c[size_t(q0 + u) * N + v] : make_float2(0.f, 0.f);
+#pragma unroll
+    for (int u = 0; u < kB; ++u)
+      if (q0 + u < Q)
+        cref[size_t(q0 + u) * N + v] = make_float2(float(cv[u].x * a.x - cv[u].y * a.y),
+                                                   float(cv[u].x * a.y + cv[u].y * a.x));
   }
 }
 
@@ -83,14 +103,22 @@ __global__ void __launch_bounds__(256) k_phase_coil(const float2* __restrict__ c
 }
 
 // c[:, v] /= ||c[:, v]||_2 (zero stays zero)
+// The voxel's Q coil values are loaded once, all loads in flight together,
+// and kept in registers for the scaling.
 __global__ void __launch_bounds__(256) k_rss(float2* __restrict__ c, int Q, long long N) {
   const long long v = blockIdx.x * 256LL + threadIdx.x;
   if (v >= N) return;
+  float2 x[kMaxQ];
+#pragma unroll
+  for (int q = 0; q < kMaxQ; ++q) x[q] = q < Q ? c[size_t(q) * N + v] : make_float2(0.f, 0.f);
   float s = 0.f;
-  for (int q = 0; q < Q; ++q) s += cabs2(c[size_t(q) * N + v]);
+#pragma unroll
+  for (int q = 0; q < kMaxQ; ++q) s += cabs2(x[q]);
   if (!(s > 0.f)) return;
   const float inv = 1.f / sqrtf(s);
-  for (int q = 0; q < Q; ++q) c[size_t(q) * N + v] = cscale(c[size_t(q) * N + v], inv);
+#pragma unroll
+  for (int q = 0; q < kMaxQ; ++q)
+    if (q < Q) c[size_t(q) * N + v] = cscale(x[q], inv);
 }
 
 pisco_status_t run_maps(Handle* h, const Plan& p, int phase_rule, const float2* acs,

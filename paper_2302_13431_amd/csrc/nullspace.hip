@@ -219,13 +219,25 @@ __global__ void __launch_bounds__(64 * kKS) __attribute__((amdgpu_waves_per_eu(2
   }
 }
 
-// out = sum over `parts` slabs of size `len` (fixed order: deterministic)
-__global__ void k_sum_parts(const double2* __restrict__ parts, double2* __restrict__ out,
-                            long long len, int nparts) {
-  const long long i = blockIdx.x * 256LL + threadIdx.x;
+// out = sum over `parts` slabs of size `len` (fixed order: deterministic).
+// The slabs are read 24 at a time, all of those loads in flight together;
+// workgroups of one wave spread the few thousand elements over many CUs.
+__global__ void __launch_bounds__(64) k_sum_parts(const double2* __restrict__ parts,
+                                                  double2* __restrict__ out, long long len,
+                                                  int nparts) {
+  constexpr int kU = 24;
+  const long long i = blockIdx.x * 64LL + threadIdx.x;
   if (i >= len) return;
-  double2 s = parts[i];
-  for (int k = 1; k < nparts; ++k) s = zadd(s, parts[size_t(k) * len + i]);
+  double2 s = make_double2(0.0, 0.0);
+  for (int k0 = 0; k0 < nparts; k0 += kU) {
+    double2 v[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u)
+      v[u] = k0 + u < nparts ? parts[size_t(k0 + u) * len + i] : make_double2(0.0, 0.0);
+#pragma unroll
+    for (int u = 0; u < kU; ++u)
+      if (k0 + u < nparts) s = zadd(s, v[u]);
+  }
   out[i] = s;
 }
 
@@ -825,7 +837,7 @@ pisco_status_t gemm_tn(NullCtx& c, const double2* P, const double2* Qm, double2*
   dim3 g(ceil_div(b, 16), ceil_div(b, 16), chunks);
   PISCO_KERNEL(c.h, k_gemm_tn, g, dim3(64), 0, P, Qm, c.w.part, rows, b, upper ? 1 : 0);
   const long long len = 1LL * b * b;
-  PISCO_KERNEL(c.h, k_sum_parts, dim3(ceil_div(len, 256)), dim3(256), 0, c.w.part, out, len, chunks);
+  PISCO_KERNEL(c.h, k_sum_parts, dim3(ceil_div(len, 64)), dim3(64), 0, c.w.part, out, len, chunks);
   return PISCO_OK;
 }
 
