@@ -90,6 +90,7 @@ struct EstLayout {
   float2* G;
   float2* maps_lr;
   float* lam;
+  void* null_ws;
   void* stage_ws;
   size_t total;
 };
@@ -104,9 +105,12 @@ EstLayout est_layout(const Plan& p, int b, void* ws) {
   e.G = c.take<float2>(size_t(p.P) * p.Nlr);
   e.maps_lr = c.take<float2>(size_t(p.Q) * p.Nlr);
   e.lam = c.take<float>(p.Nlr);
+  // the nullspace stage has a region of its own: the later stages may be
+  // enqueued while its iteration can still go on
+  e.null_ws = c.take<char>(ws_stage(p, b, 2));
   size_t m = 0;
   for (int st = 1; st <= 5; ++st) {
-    const size_t v = ws_stage(p, b, st);
+    const size_t v = st == 2 ? 0 : ws_stage(p, b, st);
     m = v > m ? v : m;
   }
   e.stage_ws = c.take<char>(m);
@@ -162,15 +166,20 @@ pisco_status_t estimate_core(Handle* h, const Plan& p, const pisco_opts_t& o, in
   if (counts_out) *counts_out = e.counts;
   pisco_status_t st;
   if ((st = run_gram(h, p, acs, e.gram, e.stage_ws))) return st;
-  if ((st = run_nullspace(h, p, b, o.max_subspace_iters, e.gram, e.eigvals, e.basis, e.counts,
-                          e.stage_ws, fixed_products, ax_waves)))
-    return st;
-  if ((st = run_gx(h, p, b, o.precision, e.basis, e.counts, e.G, e.stage_ws))) return st;
   float* lam = lam_min ? lam_min : e.lam;
-  if ((st = run_eig(h, p.Q, p.Nlr, float(p.L), o.power_iters, o.tol, e.G, nullptr, e.maps_lr,
-                    lam, nullptr)))
+  const std::function<pisco_status_t()> later = [&]() -> pisco_status_t {
+    pisco_status_t s2;
+    if ((s2 = run_gx(h, p, b, o.precision, e.basis, e.counts, e.G, e.stage_ws))) return s2;
+    if ((s2 = run_eig(h, p.Q, p.Nlr, float(p.L), o.power_iters, o.tol, e.G, nullptr,
+                      e.maps_lr, lam, nullptr)))
+      return s2;
+    return run_maps(h, p, o.phase_rule, acs, e.maps_lr, maps_out, e.stage_ws);
+  };
+  bool queued = false;
+  if ((st = run_nullspace(h, p, b, o.max_subspace_iters, e.gram, e.eigvals, e.basis, e.counts,
+                          e.null_ws, fixed_products, ax_waves, &later, &queued)))
     return st;
-  return run_maps(h, p, o.phase_rule, acs, e.maps_lr, maps_out, e.stage_ws);
+  return queued ? PISCO_OK : later();
 }
 
 }  // namespace pisco
@@ -218,6 +227,7 @@ pisco_status_t pisco_destroy(pisco_handle_t handle) {
   if (!h) return PISCO_ERR_ARG;
   (void)hipStreamSynchronize(h->stream);
   for (auto& kv : h->tables) (void)hipFree(kv.second);
+  if (h->sched_ev) (void)hipEventDestroy(h->sched_ev);
   (void)hipHostFree(h->host_ctl);
   (void)hipHostFree(h->host_pinned);
   (void)hipFree(h->status_dev);
@@ -501,7 +511,10 @@ void batch_free(pisco_batch_s* bt) {
   if (bt->exec) (void)hipGraphExecDestroy(bt->exec);
   if (bt->graph) (void)hipGraphDestroy(bt->graph);
   for (hipEvent_t e : bt->events) (void)hipEventDestroy(e);
-  for (Handle* s : bt->sub) delete s;  // status word and pinned buffer are borrowed
+  for (Handle* s : bt->sub) {  // status word and pinned buffers are borrowed
+    if (s->sched_ev) (void)hipEventDestroy(s->sched_ev);
+    delete s;
+  }
   for (hipStream_t s : bt->streams) (void)hipStreamDestroy(s);
   delete bt;
 }

@@ -67,6 +67,9 @@ struct Handle {
   // pointer and the device's pointer to the same memory)
   int* host_ctl = nullptr;
   int* host_ctl_dev = nullptr;
+  // recorded after the schedule kernel so that the host waits for it alone
+  // while later work runs (created on first use by the adaptive schedule)
+  hipEvent_t sched_ev = nullptr;
   std::string last_error;
   // kernel tracing (pisco_trace_enable): events bracket matching launches
   bool trace = false;
@@ -180,7 +183,7 @@ struct NullWs {
   double2* R;      // [b][b] Cholesky factor (column-major, upper)
   double* dsc;     // [b] column scaling of the factorised Gram
   double* theta;   // [b]
-  double* filt;    // [8] Chebyshev filter coefficients (two steps of three)
+  double* filt;    // [12] Chebyshev filter coefficients: steps 1 and 2, the next product
   double* resid;   // [b]
   double2* part;   // row-chunk partials of the b x b products; residual partials
   int* ctl;        // [8] control words
@@ -217,10 +220,18 @@ pisco_status_t run_gram(Handle* h, const Plan& p, const float2* acs, float2* gra
 // fixed_products > 0: that many products and one Rayleigh-Ritz step, no host
 // read-back (graph-capturable); 0: adaptive schedule with host reads.
 // ax_waves: wave count targeted by the split-K product (0 = 2048).
+// downstream (adaptive schedule only, nullable): enqueues the caller's later
+// stages, which read basis/eigvals/counts; it is called after each
+// Rayleigh-Ritz step before the host looks at the result (so that the GPU
+// goes on while the host waits), again after a later step when that one was
+// not final, and *downstream_queued tells the caller whether the last call
+// stands.  Its work must not touch `ws`.
 pisco_status_t run_nullspace(Handle* h, const Plan& p, int b, int max_iters,
                              const float2* gram, double* eigvals, double2* basis,
                              int32_t* counts, void* ws, int fixed_products = 0,
-                             int ax_waves = 0);
+                             int ax_waves = 0,
+                             const std::function<pisco_status_t()>* downstream = nullptr,
+                             bool* downstream_queued = nullptr);
 pisco_status_t run_gx(Handle* h, const Plan& p, int b, int precision, const double2* basis,
                       const int32_t* counts, float2* G, void* ws);
 pisco_status_t run_eig(Handle* h, int Q, long long N, float bound, int iters,

@@ -793,16 +793,25 @@ __global__ void k_predict(const double* __restrict__ d, int b, double thr2, doub
     }
   }
   ctl[6] = need < 1 ? 1 : (need > 40 ? 40 : need);
+  // slot 3: the coefficients of the next product, a chain's first step or a
+  // plain product (1, 0, 0) when the Rayleigh-Ritz step is taken on it, so
+  // that the host can enqueue it before it reads the schedule
+  const bool plain = ctl[6] <= 1;
+  for (int k = 0; k < 3; ++k) coef[6 + k] = plain ? (k == 0 ? 1.0 : 0.0) : f[k];
   if (host_ctl) {
     host_ctl[6] = ctl[6];
     __threadfence_system();
   }
 }
 
+// Flags are raised only for a final result (converged, stopped, or at the
+// product limit `max_iters`, done products so far): the adaptive schedule
+// also runs this ahead of its host check and goes on when the step is not
+// final.  done = max_iters = 0: always final.
 __global__ void k_finalize(const double2* __restrict__ W, const double* __restrict__ theta,
                            const int* __restrict__ ctl, double2* __restrict__ basis,
                            double* __restrict__ eigvals, int32_t* __restrict__ counts,
-                           long long nb, int b, unsigned* status) {
+                           long long nb, int b, int done, int max_iters, unsigned* status) {
   const long long i = blockIdx.x * 256LL + threadIdx.x;
   if (i < nb) basis[i] = W[i];
   if (i < b) eigvals[i] = theta[i];
@@ -812,6 +821,8 @@ __global__ void k_finalize(const double2* __restrict__ W, const double* __restri
     counts[2] = ctl[2];
     counts[3] = ctl[1];
     unsigned f = 0;
+    const bool final = ctl[1] || ctl[3] || ctl[4] || done >= max_iters;
+    if (!final) return;
     if (!ctl[1]) f |= PISCO_FLAG_NOT_CONVERGED;
     if (ctl[3]) f |= PISCO_FLAG_BLOCK_TOO_SMALL;
     if (ctl[4]) f |= PISCO_FLAG_ZERO_DATA;
@@ -893,7 +904,10 @@ pisco_status_t orth(NullCtx& c, const double2* Y, double2* tmp, double* rdiag, d
 
 pisco_status_t run_nullspace(Handle* h, const Plan& p, int b, int max_iters,
                              const float2* gram, double* eigvals, double2* basis,
-                             int32_t* counts, void* ws, int fixed_products, int ax_waves) {
+                             int32_t* counts, void* ws, int fixed_products, int ax_waves,
+                             const std::function<pisco_status_t()>* downstream,
+                             bool* downstream_queued) {
+  if (downstream_queued) *downstream_queued = false;
   NullCtx c{h, &p, b, {}};
   layout_null(p, b, ws, &c.w);
   hipStream_t s = h->stream;
@@ -959,10 +973,12 @@ pisco_status_t run_nullspace(Handle* h, const Plan& p, int b, int max_iters,
   int rr_at = fixed ? (fixed_products < 3 ? 3 : fixed_products) : kUnscheduled;
   int done = 0;
   bool filtered = false;  // filter coefficients set
+  bool queued = false;    // the next product is already enqueued
   while (true) {
     const bool rr_next = done + 1 >= rr_at || done + 1 >= max_iters;
     const bool chain = filtered && !rr_next;
-    if ((st = product(X, Z, nullptr, chain ? 1 : 0))) return st;
+    if (!queued && (st = product(X, Z, nullptr, chain ? 1 : 0))) return st;
+    queued = false;
     ++done;
     if (done < rr_at && done < max_iters) {
       int extra = 0;
@@ -986,7 +1002,17 @@ pisco_status_t run_nullspace(Handle* h, const Plan& p, int b, int max_iters,
                      c.w.filt, fixed ? nullptr : h->host_ctl_dev);
         filtered = true;
         if (!fixed) {
-          hipError_t e = hipStreamSynchronize(s);
+          // whatever the schedule, a product comes next: enqueued now with
+          // the coefficients k_predict leaves in slot 3 (plain when the
+          // iteration limit makes it the last), so that it runs while the
+          // host waits (on an event, for k_predict alone) for the schedule
+          hipError_t e = hipSuccess;
+          if (!h->sched_ev) e = hipEventCreateWithFlags(&h->sched_ev, hipEventDisableTiming);
+          if (e == hipSuccess) e = hipEventRecord(h->sched_ev, s);
+          if (e != hipSuccess) return hip_check(h, e, "nullspace schedule event");
+          if ((st = product(X, Z, nullptr, done + 1 >= max_iters ? 0 : 3))) return st;
+          queued = true;
+          e = hipEventSynchronize(h->sched_ev);
           if (e != hipSuccess) return hip_check(h, e, "nullspace predict");
           rr_at = done + reinterpret_cast<volatile int*>(h->host_ctl)[6];
         }
@@ -1003,17 +1029,34 @@ pisco_status_t run_nullspace(Handle* h, const Plan& p, int b, int max_iters,
     PISCO_KERNEL(h, k_control, dim3(1), dim3(64), 0, c.w.theta, rpart, rchunks, b, thr2, tol,
                  margin, done - 1, c.w.ctl, h->status_dev, fixed ? nullptr : h->host_ctl_dev);
     if (fixed) break;
-    hipError_t e = hipStreamSynchronize(s);
+    // Most steps are final: k_finalize and the caller's later stages go in
+    // now and the host waits (on an event) for k_control alone.  When the
+    // step is not final the iteration goes on; those results are then
+    // overwritten after a later step (k_finalize raises flags only for a
+    // final result, and the later stages do not touch this workspace).
+    hipError_t e = hipSuccess;
+    if (!h->sched_ev) e = hipEventCreateWithFlags(&h->sched_ev, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventRecord(h->sched_ev, s);
+    if (e != hipSuccess) return hip_check(h, e, "nullspace schedule event");
+    PISCO_KERNEL(h, k_finalize, dim3(ceil_div(nb > b ? nb : b, 256)), dim3(256), 0, W,
+                 c.w.theta, c.w.ctl, basis, eigvals, counts, nb, b, done, max_iters,
+                 h->status_dev);
+    if (downstream && *downstream) {
+      if ((st = (*downstream)())) return st;
+      if (downstream_queued) *downstream_queued = true;
+    }
+    e = hipEventSynchronize(h->sched_ev);
     if (e != hipSuccess) return hip_check(h, e, "nullspace sync");
     const volatile int* hc = h->host_ctl;
-    if (hc[1] || hc[3] || hc[4]) break;
-    if (done >= max_iters) break;
+    if (hc[1] || hc[3] || hc[4] || done >= max_iters) return PISCO_OK;
+    if (downstream_queued) *downstream_queued = false;
     rr_at = done + hc[5];
     // next block: orth(A * Ritz vectors) (held in X; nearly orthogonal columns)
     if ((st = orth(c, X, Z, nullptr, 0.0))) return st;
     std::swap(X, Z);
   }
-  PISCO_KERNEL(h, k_finalize, dim3(ceil_div(nb > b ? nb : b, 256)), dim3(256), 0, W, c.w.theta, c.w.ctl, basis, eigvals, counts, nb, b, h->status_dev);
+  PISCO_KERNEL(h, k_finalize, dim3(ceil_div(nb > b ? nb : b, 256)), dim3(256), 0, W,
+               c.w.theta, c.w.ctl, basis, eigvals, counts, nb, b, 0, 0, h->status_dev);
   return PISCO_OK;
 }
 

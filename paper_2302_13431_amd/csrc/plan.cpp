@@ -109,7 +109,7 @@ size_t layout_null(const Plan& p, int b, void* ws, NullWs* o) {
   w.R = c.take<double2>(bb);
   w.dsc = c.take<double>(b);
   w.theta = c.take<double>(b);
-  w.filt = c.take<double>(8);
+  w.filt = c.take<double>(12);
   w.resid = c.take<double>(b);
   // row-chunk partials of the b x b products and residual partials share
   // one buffer (the split-K partials of A X stay in LDS)
