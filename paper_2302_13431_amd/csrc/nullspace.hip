@@ -62,27 +62,54 @@ __global__ void k_init_block(double2* X, int n, int b) {
 // supplies row (or column) l % 16 at k = k0 + 4 s + l / 16 for step s, so a
 // lane's four k of one chunk are 4 apart and every load instruction reads
 // 4 consecutive elements per row; accumulator element v of lane l is row
-// l / 16 + 4 v, column l % 16.  Operands for the next chunk of 16 k are loaded before the
-// products of the current one.  Every wave reads only its own rows of A, so
-// the three column tiles of a row share A through the caches.
+// l / 16 + 4 v, column l % 16.  Operands for the next chunk of 16 k are
+// loaded before the products of the current one, into the other of two
+// buffers.  Every wave reads only its own rows of A, so the three column
+// tiles of a row share A through the caches.
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
+constexpr int kAxQ = 4;           // k steps of 4 per operand chunk
+constexpr int kAxK = 4 * kAxQ;    // k per chunk
 struct AxChunk {
-  float2 a[2][4];    // rows r0 + li (+16), k = k0 + 4 q + lk
-  double2 x[2][4];   // columns c0 + li (+16), same k
+  float2 a[2][kAxQ];    // rows r0 + li (+16), k = k0 + 4 q + lk
+  double2 x[2][kAxQ];   // columns c0 + li (+16), same k
 };
 
+// A whole chunk inside the slice: one base address per row and column and
+// constant offsets (rows past n read row 0 of the tile and are zeroed).
+__device__ inline void ax_load_full(AxChunk& ch, const float2* Ar0, const float2* Ar1, bool v0,
+                                    bool v1, const double2* X0, const double2* X1, int k0,
+                                    int lk) {
+  const float2* a0 = Ar0 + k0 + lk;
+  const float2* a1 = Ar1 + k0 + lk;
+  const double2* x0 = X0 + k0 + lk;
+  const double2* x1 = X1 + k0 + lk;
+#pragma unroll
+  for (int q = 0; q < kAxQ; ++q) {
+    const float2 u0 = a0[4 * q], u1 = a1[4 * q];
+    ch.a[0][q] = make_float2(v0 ? u0.x : 0.f, v0 ? u0.y : 0.f);
+    ch.a[1][q] = make_float2(v1 ? u1.x : 0.f, v1 ? u1.y : 0.f);
+    ch.x[0][q] = x0[4 * q];
+    ch.x[1][q] = x1[4 * q];
+  }
+}
+
+// The last, partial chunk of a slice, branch-free: every lane loads from a
+// valid address (k clamped to the slice) and the value is zeroed after.
 __device__ inline void ax_load(AxChunk& ch, const float2* Ar0, const float2* Ar1, bool v0,
                                bool v1, const double2* X0, const double2* X1, int k0, int lk,
                                int kend) {
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
+  for (int q = 0; q < kAxQ; ++q) {
     const int k = k0 + 4 * q + lk;
     const bool ok = k < kend;
-    ch.a[0][q] = (ok && v0) ? Ar0[k] : make_float2(0.f, 0.f);
-    ch.a[1][q] = (ok && v1) ? Ar1[k] : make_float2(0.f, 0.f);
-    ch.x[0][q] = ok ? X0[k] : make_double2(0.0, 0.0);
-    ch.x[1][q] = ok ? X1[k] : make_double2(0.0, 0.0);
+    const int kk = ok ? k : kend - 1;
+    const float2 a0 = Ar0[kk], a1 = Ar1[kk];
+    const double2 x0 = X0[kk], x1 = X1[kk];
+    ch.a[0][q] = make_float2(ok && v0 ? a0.x : 0.f, ok && v0 ? a0.y : 0.f);
+    ch.a[1][q] = make_float2(ok && v1 ? a1.x : 0.f, ok && v1 ? a1.y : 0.f);
+    ch.x[0][q] = make_double2(ok ? x0.x : 0.0, ok ? x0.y : 0.0);
+    ch.x[1][q] = make_double2(ok ? x1.x : 0.0, ok ? x1.y : 0.0);
   }
 }
 
@@ -133,14 +160,11 @@ __global__ void __launch_bounds__(64 * kKS) __attribute__((amdgpu_waves_per_eu(2
       t2[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
       t3[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
     }
-  AxChunk cur, nxt;
-  ax_load(cur, Ar0, Ar1, v0, v1, X0, X1, kbeg, lk, kend);
-  for (int k0 = kbeg; k0 < kend; k0 += 16) {
-    if (k0 + 16 < kend) ax_load(nxt, Ar0, Ar1, v0, v1, X0, X1, k0 + 16, lk, kend);
-    // the twelve accumulators are updated in turn, so that two products
-    // into one accumulator are never back to back
+  // the twelve accumulators are updated in turn, so that two products
+  // into one accumulator are never back to back
+  auto mma = [&](const AxChunk& cur) {
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
+    for (int s = 0; s < kAxQ; ++s) {
 #pragma unroll
       for (int i = 0; i < 2; ++i) {
         const double ar = cur.a[i][s].x, ai = cur.a[i][s].y, as = ar + ai;
@@ -153,7 +177,27 @@ __global__ void __launch_bounds__(64 * kKS) __attribute__((amdgpu_waves_per_eu(2
         }
       }
     }
-    cur = nxt;
+  };
+  // two operand buffers in turn (a copy from one to the other would make
+  // the copy wait for the loads just issued): the next chunk's loads are in
+  // flight while the current chunk's products run
+  // complete chunks in the loop, a partial last one after it
+  auto load = [&](AxChunk& ch, int k0) { ax_load_full(ch, Ar0, Ar1, v0, v1, X0, X1, k0, lk); };
+  const int kfull = kend > kbeg ? kbeg + (kend - kbeg) / kAxK * kAxK : kbeg;
+  AxChunk q0, q1;
+  if (kfull > kbeg) {
+    load(q0, kbeg);
+    for (int k0 = kbeg; k0 < kfull; k0 += 2 * kAxK) {
+      if (k0 + kAxK < kfull) load(q1, k0 + kAxK);
+      mma(q0);
+      if (k0 + kAxK >= kfull) break;
+      if (k0 + 2 * kAxK < kfull) load(q0, k0 + 2 * kAxK);
+      mma(q1);
+    }
+  }
+  if (kfull < kend) {
+    ax_load(q0, Ar0, Ar1, v0, v1, X0, X1, kfull, lk, kend);
+    mma(q0);
   }
   f64x4 cr[2][2], ci[2][2];
 #pragma unroll
