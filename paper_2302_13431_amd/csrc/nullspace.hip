@@ -186,12 +186,15 @@ __global__ void __launch_bounds__(64 * kKS) __attribute__((amdgpu_waves_per_eu(2
   const int kfull = kend > kbeg ? kbeg + (kend - kbeg) / kAxK * kAxK : kbeg;
   AxChunk q0, q1;
   if (kfull > kbeg) {
+    // loads unconditional (past the end they repeat the last chunk,
+    // unused): no branch, so each product waits only for its own buffer
+    const int klast = kfull - kAxK;
     load(q0, kbeg);
     for (int k0 = kbeg; k0 < kfull; k0 += 2 * kAxK) {
-      if (k0 + kAxK < kfull) load(q1, k0 + kAxK);
+      load(q1, min(k0 + kAxK, klast));
       mma(q0);
       if (k0 + kAxK >= kfull) break;
-      if (k0 + 2 * kAxK < kfull) load(q0, k0 + 2 * kAxK);
+      load(q0, min(k0 + 2 * kAxK, klast));
       mma(q1);
     }
   }
@@ -306,19 +309,20 @@ __global__ void __launch_bounds__(64) k_gemm_tn(const double2* __restrict__ P,
   f64x4 cr[2], ci[2];
 #pragma unroll
   for (int h = 0; h < 2; ++h) cr[h] = ci[h] = f64x4{0.0, 0.0, 0.0, 0.0};
-  double2 pv[4], qv[4], pn[4], qn[4];
+  // two operand buffers in turn (a copy from one to the other would make
+  // the copy wait for the loads just issued); complete steps of 16 rows in
+  // the loop with plain loads, a partial last one after it (rows clamped
+  // and zeroed: predicated loads, or a zeroing select at load time, would
+  // make the products wait for every load in flight)
+  double2 pa[4], qa[4], pb[4], qb[4];
   auto load = [&](int r0, double2 (&p)[4], double2 (&q)[4]) {
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      const int r = r0 + 4 * u + lk;
-      const bool ok = r < rend;
-      p[u] = ok ? Pc[r] : make_double2(0.0, 0.0);
-      q[u] = ok ? Qc[r] : make_double2(0.0, 0.0);
+      p[u] = Pc[r0 + 4 * u + lk];
+      q[u] = Qc[r0 + 4 * u + lk];
     }
   };
-  load(rbeg, pv, qv);
-  for (int r0 = rbeg; r0 < rend; r0 += 16) {
-    if (r0 + 16 < rend) load(r0 + 16, pn, qn);
+  auto mma = [&](const double2 (&pv)[4], const double2 (&qv)[4]) {
 #pragma unroll
     for (int u = 0; u < 4; ++u)
 #pragma unroll
@@ -329,11 +333,32 @@ __global__ void __launch_bounds__(64) k_gemm_tn(const double2* __restrict__ P,
         ci[u & 1] = __builtin_amdgcn_mfma_f64_16x16x4f64(half ? -x.y : x.x, half ? y.x : y.y,
                                                          ci[u & 1], 0, 0, 0);
       }
+  };
+  const int rfull = rend > rbeg ? rbeg + (rend - rbeg) / 16 * 16 : rbeg;
+  if (rfull > rbeg) {
+    // loads unconditional (past the end they repeat the last step, unused):
+    // no branch, so each product waits only for its own buffer
+    const int rlast = rfull - 16;
+    load(rbeg, pa, qa);
+    for (int r0 = rbeg; r0 < rfull; r0 += 32) {
+      load(min(r0 + 16, rlast), pb, qb);
+      mma(pa, qa);
+      if (r0 + 16 >= rfull) break;
+      load(min(r0 + 32, rlast), pa, qa);
+      mma(pb, qb);
+    }
+  }
+  if (rfull < rend) {
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      pv[u] = pn[u];
-      qv[u] = qn[u];
+      const int r = rfull + 4 * u + lk;
+      const bool ok = r < rend;
+      const int rr = ok ? r : rend - 1;
+      const double2 x = Pc[rr], y = Qc[rr];
+      pa[u] = make_double2(ok ? x.x : 0.0, ok ? x.y : 0.0);
+      qa[u] = make_double2(ok ? y.x : 0.0, ok ? y.y : 0.0);
     }
+    mma(pa, qa);
   }
   double2* out = part + size_t(blockIdx.z) * b * b;
 #pragma unroll
