@@ -388,19 +388,22 @@ __global__ void __launch_bounds__(64) k_gemm_nn(const double2* __restrict__ Pm,
   f64x4 cr[2], ci[2];
 #pragma unroll
   for (int h = 0; h < 2; ++h) cr[h] = ci[h] = f64x4{0.0, 0.0, 0.0, 0.0};
-  double2 pv[4], mv[4], pn[4], mn[4];
+  // two operand buffers in turn (a copy from one to the other would make
+  // the copy wait for the loads just issued); complete steps of 16 k in the
+  // loop with unconditional loads (past the end they repeat the last step,
+  // unused: no branch, so each product waits only for its own buffer), a
+  // partial last step after it (k clamped and zeroed); rows past m read row
+  // 0 of the tile and are zeroed where they are stored
+  double2 pa[4], ma[4], pb[4], mb[4];
   auto load = [&](int k0, double2 (&p)[4], double2 (&q)[4]) {
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int kk = k0 + 4 * u + lk;
-      const bool ok = kk < kend;
-      p[u] = ok && v ? Pr[size_t(kk) * m] : make_double2(0.0, 0.0);
-      q[u] = ok ? Mc[kk] : make_double2(0.0, 0.0);
+      p[u] = Pr[size_t(kk) * m];
+      q[u] = Mc[kk];
     }
   };
-  load(0, pv, mv);
-  for (int k0 = 0; k0 < kend; k0 += 16) {
-    if (k0 + 16 < kend) load(k0 + 16, pn, mn);
+  auto mma = [&](const double2 (&pv)[4], const double2 (&mv)[4]) {
 #pragma unroll
     for (int u = 0; u < 4; ++u)
 #pragma unroll
@@ -411,11 +414,30 @@ __global__ void __launch_bounds__(64) k_gemm_nn(const double2* __restrict__ Pm,
         ci[u & 1] = __builtin_amdgcn_mfma_f64_16x16x4f64(half ? x.y : x.x, half ? y.x : y.y,
                                                          ci[u & 1], 0, 0, 0);
       }
+  };
+  const int kfull = kend / 16 * 16;
+  if (kfull > 0) {
+    const int klast = kfull - 16;
+    load(0, pa, ma);
+    for (int k0 = 0; k0 < kfull; k0 += 32) {
+      load(min(k0 + 16, klast), pb, mb);
+      mma(pa, ma);
+      if (k0 + 16 >= kfull) break;
+      load(min(k0 + 32, klast), pa, ma);
+      mma(pb, mb);
+    }
+  }
+  if (kfull < kend) {
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      pv[u] = pn[u];
-      mv[u] = mn[u];
+      const int kk = kfull + 4 * u + lk;
+      const bool ok = kk < kend;
+      const int kc = ok ? kk : kend - 1;
+      const double2 x = Pr[size_t(kc) * m], y = Mc[kc];
+      pa[u] = make_double2(ok ? x.x : 0.0, ok ? x.y : 0.0);
+      ma[u] = make_double2(ok ? y.x : 0.0, ok ? y.y : 0.0);
     }
+    mma(pa, ma);
   }
 #pragma unroll
   for (int e = 0; e < 4; ++e) {
