@@ -31,6 +31,21 @@ template <class T, class U> __device__ inline T widen(U v) { return T{v.x, v.y};
 // the launch with too few workgroups to fill the chip.
 constexpr int kMidMaxIn = 256;
 
+// dst[e] = widen(src[e]) for e < n by a workgroup of 256 threads, four
+// loads per thread in flight at once
+template <class TO, class TI>
+__device__ inline void stage_rows(TO* dst, const TI* __restrict__ src, int n) {
+  int e0 = threadIdx.x;
+  for (; e0 + 3 * 256 < n; e0 += 4 * 256) {
+    TI v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) v[u] = src[e0 + u * 256];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) dst[e0 + u * 256] = widen<TO>(v[u]);
+  }
+  for (; e0 < n; e0 += 256) dst[e0] = widen<TO>(src[e0]);
+}
+
 template <class TI, class TO, int kOT>
 __global__ void __launch_bounds__(256) k_axis_mid(const TI* __restrict__ in,
                                                   TO* __restrict__ out,
@@ -39,7 +54,7 @@ __global__ void __launch_bounds__(256) k_axis_mid(const TI* __restrict__ in,
   __shared__ TO Ms[kOT * kMidMaxIn];
   const int o0 = blockIdx.y * kOT;
   const int cnt = nout - o0 < kOT ? nout - o0 : kOT;
-  for (int e = threadIdx.x; e < cnt * nin; e += 256) Ms[e] = M[size_t(o0) * nin + e];
+  stage_rows(Ms, M + size_t(o0) * nin, cnt * nin);
   __syncthreads();
   const long long col = blockIdx.x * 256LL + threadIdx.x;
   if (col >= outer * inner) return;
@@ -50,15 +65,25 @@ __global__ void __launch_bounds__(256) k_axis_mid(const TI* __restrict__ in,
   TO acc[kOT];
 #pragma unroll
   for (int k = 0; k < kOT; ++k) acc[k] = Acc<TO>::zero();
-  for (int i = 0; i < nin; ++i) {
-    const TO x = widen<TO>(src[size_t(i) * inner]);
+  // inputs eight at a time, all eight loads in flight before the first is
+  // used (one load per step would wait for each in turn)
+  auto step = [&](const TO& x, int i) {
 #pragma unroll
     for (int k = 0; k < kOT; ++k) {
       const TO m = Ms[k * nin + i];
       acc[k].x = fma(m.x, x.x, fma(-m.y, x.y, acc[k].x));
       acc[k].y = fma(m.x, x.y, fma(m.y, x.x, acc[k].y));
     }
+  };
+  int i = 0;
+  for (; i + 8 <= nin; i += 8) {
+    TO x[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) x[u] = widen<TO>(src[size_t(i + u) * inner]);
+#pragma unroll
+    for (int u = 0; u < 8; ++u) step(x[u], i + u);
   }
+  for (; i < nin; ++i) step(widen<TO>(src[size_t(i) * inner]), i);
 #pragma unroll
   for (int k = 0; k < kOT; ++k)
     if (k < cnt) dst[size_t(o0 + k) * inner] = acc[k];
@@ -80,7 +105,7 @@ __global__ void __launch_bounds__(256) k_axis_last(const TI* __restrict__ in,
   const long long l0 = per > 1 ? blockIdx.x / per : blockIdx.x * (long long)lpb;
   const int obase = per > 1 ? int(blockIdx.x % per) * 256 : 0;
   const int nl = per > 1 ? 1 : (lines - l0 < lpb ? int(lines - l0) : lpb);
-  for (int e = threadIdx.x; e < nl * nin; e += 256) sl[e] = widen<TO>(in[size_t(l0) * nin + e]);
+  stage_rows(sl, in + size_t(l0) * nin, nl * nin);
   __syncthreads();
   const int span = per > 1 ? 256 : nout;
   const int ln = threadIdx.x / span, o = obase + threadIdx.x % span;
