@@ -185,15 +185,22 @@ __global__ void __launch_bounds__(1024) k_hetrd(const double2* __restrict__ H, i
 
 // ------------------------------------------------------------------ eigenvalues
 
-// Eigenvalue j (ascending, 0-based) of T by multisection: each of the 64
-// lanes takes the Sturm count at one of 64 interior points of the bracket.
-__global__ void __launch_bounds__(64) k_tri_eigval(const double* __restrict__ d,
-                                                   const double* __restrict__ e, int b,
-                                                   double* __restrict__ lam) {
+// Eigenvalue j (ascending, 0-based) of T by multisection: each of the
+// kEigThreads lanes of the workgroup takes the Sturm count at one of
+// kEigThreads interior points of the bracket (8 bits per step with 256).
+// The waves' ballots meet in LDS (double-buffered: one barrier per step);
+// every lane recomputes the chosen points from their formula.
+constexpr int kEigThreads = 256;
+__global__ void __launch_bounds__(kEigThreads) k_tri_eigval(const double* __restrict__ d,
+                                                            const double* __restrict__ e,
+                                                            int b, double* __restrict__ lam) {
+  constexpr int kW = kEigThreads / 64;
   __shared__ double sd[kTriMax], se2[kTriMax];
-  const int t = threadIdx.x, j = blockIdx.x;
+  __shared__ double red[3][kW];
+  __shared__ unsigned long long masks[2][kW];
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6, j = blockIdx.x;
   double glo = INFINITY, ghi = -INFINITY, emax2 = 0.0;
-  for (int i = t; i < b; i += 64) {
+  for (int i = t; i < b; i += kEigThreads) {
     const double di = d[i];
     const double el = i > 0 ? e[i - 1] : 0.0, er = i + 1 < b ? e[i] : 0.0;
     sd[i] = di;
@@ -206,26 +213,38 @@ __global__ void __launch_bounds__(64) k_tri_eigval(const double* __restrict__ d,
   glo = wave_min(glo);
   ghi = wave_max(ghi);
   emax2 = wave_max(emax2);
+  if (lane == 0) {
+    red[0][wave] = glo;
+    red[1][wave] = ghi;
+    red[2][wave] = emax2;
+  }
   __syncthreads();
+#pragma unroll
+  for (int w = 0; w < kW; ++w) {
+    glo = fmin(glo, red[0][w]);
+    ghi = fmax(ghi, red[1][w]);
+    emax2 = fmax(emax2, red[2][w]);
+  }
   const double pivmin = DBL_MIN * fmax(1.0, emax2);
   const double wide = 2.0 * DBL_EPSILON * fmax(fabs(glo), fabs(ghi)) + 2.0 * pivmin;
   double lo = glo - wide, hi = ghi + wide;
+  constexpr double kInv = 1.0 / double(kEigThreads + 1);
   for (int it = 0; it < 64; ++it) {
     const double w = hi - lo;
     if (!(w > 2.0 * DBL_EPSILON * fmax(fabs(lo), fabs(hi)) + 4.0 * pivmin)) break;
-    const double x = lo + w * (double(t + 1) / 65.0);
-    const int c = tri::negcount(sd, se2, b, x, pivmin);
-    const unsigned long long mask = __ballot(c > j);
-    double nlo, nhi;
-    if (mask == 0ull) {
-      nlo = __shfl(x, 63, 64);
-      nhi = hi;
-    } else {
-      const int l = __builtin_ctzll(mask);
-      nhi = __shfl(x, l, 64);
-      const double xl = __shfl(x, l > 0 ? l - 1 : 0, 64);
-      nlo = l > 0 ? xl : lo;
+    auto point = [&](int q) { return lo + w * (double(q + 1) * kInv); };
+    const int c = tri::negcount(sd, se2, b, point(t), pivmin);
+    const unsigned long long mk = __ballot(c > j);
+    if (lane == 0) masks[it & 1][wave] = mk;
+    __syncthreads();
+    int l = kEigThreads;  // first point whose count exceeds j
+#pragma unroll
+    for (int q = kW - 1; q >= 0; --q) {
+      const unsigned long long m = masks[it & 1][q];
+      if (m) l = 64 * q + __builtin_ctzll(m);
     }
+    const double nlo = l == 0 ? lo : point(l - 1);
+    const double nhi = l == kEigThreads ? hi : point(l);
     if (nlo == lo && nhi == hi) break;
     lo = nlo;
     hi = nhi;
@@ -514,7 +533,7 @@ pisco_status_t run_heev(Handle* h, const double2* H, int b, double2* U, double* 
     PISCO_KERNEL(h, k_hetrd<true>, dim3(1), dim3(1024), 0, H, b, gwork, refl, tau, d, e);
   else
     PISCO_KERNEL(h, k_hetrd<false>, dim3(1), dim3(1024), 0, H, b, gwork, refl, tau, d, e);
-  PISCO_KERNEL(h, k_tri_eigval, dim3(b), dim3(64), 0, d, e, b, lam);
+  PISCO_KERNEL(h, k_tri_eigval, dim3(b), dim3(kEigThreads), 0, d, e, b, lam);
   if (b <= 128)
     PISCO_KERNEL(h, k_tri_vector<2>, dim3(b), dim3(64), 0, d, e, lam, b, refl, tau, zwork, U, theta);
   else if (b <= 256)
