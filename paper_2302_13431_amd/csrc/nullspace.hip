@@ -306,9 +306,11 @@ __global__ void __launch_bounds__(64) k_gemm_tn(const double2* __restrict__ P,
   const int rbeg = blockIdx.z * kTnRows, rend = min(n, rbeg + kTnRows);
   const double2* Pc = P + size_t(i0 + li) * n;
   const double2* Qc = Qm + size_t(j0 + li) * n;
-  f64x4 cr[2], ci[2];
+  // three real products per complex step: with a = Pr, b = -Pi, c = Qr,
+  // d = Qi, conj(P) Q = (ac - bd) + i((a + b)(c + d) - ac - bd)
+  f64x4 t1[2], t2[2], t3[2];
 #pragma unroll
-  for (int h = 0; h < 2; ++h) cr[h] = ci[h] = f64x4{0.0, 0.0, 0.0, 0.0};
+  for (int h = 0; h < 2; ++h) t1[h] = t2[h] = t3[h] = f64x4{0.0, 0.0, 0.0, 0.0};
   // two operand buffers in turn (a copy from one to the other would make
   // the copy wait for the loads just issued); complete steps of 16 rows in
   // the loop with plain loads, a partial last one after it (rows clamped
@@ -324,15 +326,12 @@ __global__ void __launch_bounds__(64) k_gemm_tn(const double2* __restrict__ P,
   };
   auto mma = [&](const double2 (&pv)[4], const double2 (&qv)[4]) {
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
-#pragma unroll
-      for (int half = 0; half < 2; ++half) {
-        const double2 x = pv[u], y = qv[u];
-        cr[u & 1] = __builtin_amdgcn_mfma_f64_16x16x4f64(half ? x.y : x.x, half ? y.y : y.x,
-                                                         cr[u & 1], 0, 0, 0);
-        ci[u & 1] = __builtin_amdgcn_mfma_f64_16x16x4f64(half ? -x.y : x.x, half ? y.x : y.y,
-                                                         ci[u & 1], 0, 0, 0);
-      }
+    for (int u = 0; u < 4; ++u) {
+      const double2 x = pv[u], y = qv[u];
+      t1[u & 1] = __builtin_amdgcn_mfma_f64_16x16x4f64(x.x, y.x, t1[u & 1], 0, 0, 0);
+      t2[u & 1] = __builtin_amdgcn_mfma_f64_16x16x4f64(-x.y, y.y, t2[u & 1], 0, 0, 0);
+      t3[u & 1] = __builtin_amdgcn_mfma_f64_16x16x4f64(x.x - x.y, y.x + y.y, t3[u & 1], 0, 0, 0);
+    }
   };
   const int rfull = rend > rbeg ? rbeg + (rend - rbeg) / 16 * 16 : rbeg;
   if (rfull > rbeg) {
@@ -364,7 +363,8 @@ __global__ void __launch_bounds__(64) k_gemm_tn(const double2* __restrict__ P,
 #pragma unroll
   for (int e = 0; e < 4; ++e) {
     const int row = i0 + lk + 4 * e, col = j0 + li;
-    out[size_t(col) * b + row] = make_double2(cr[0][e] + cr[1][e], ci[0][e] + ci[1][e]);
+    const double a = t1[0][e] + t1[1][e], c = t2[0][e] + t2[1][e], d = t3[0][e] + t3[1][e];
+    out[size_t(col) * b + row] = make_double2(a - c, d - a - c);
   }
 }
 
@@ -385,9 +385,11 @@ __global__ void __launch_bounds__(64) k_gemm_nn(const double2* __restrict__ Pm,
   const int kend = tri ? min(k, c0 + 16) : k;
   const double2* Mc = M + size_t(c0 + li) * k;
   const double2* Pr = Pm + (v ? r0 + li : 0);
-  f64x4 cr[2], ci[2];
+  // three real products per complex step: T1 = Pr Mr, T2 = Pi Mi,
+  // T3 = (Pr + Pi)(Mr + Mi); Re = T1 - T2, Im = T3 - T1 - T2
+  f64x4 t1[2], t2[2], t3[2];
 #pragma unroll
-  for (int h = 0; h < 2; ++h) cr[h] = ci[h] = f64x4{0.0, 0.0, 0.0, 0.0};
+  for (int h = 0; h < 2; ++h) t1[h] = t2[h] = t3[h] = f64x4{0.0, 0.0, 0.0, 0.0};
   // two operand buffers in turn (a copy from one to the other would make
   // the copy wait for the loads just issued); complete steps of 16 k in the
   // loop with unconditional loads (past the end they repeat the last step,
@@ -405,15 +407,12 @@ __global__ void __launch_bounds__(64) k_gemm_nn(const double2* __restrict__ Pm,
   };
   auto mma = [&](const double2 (&pv)[4], const double2 (&mv)[4]) {
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
-#pragma unroll
-      for (int half = 0; half < 2; ++half) {
-        const double2 x = pv[u], y = mv[u];
-        cr[u & 1] = __builtin_amdgcn_mfma_f64_16x16x4f64(half ? -x.y : x.x, half ? y.y : y.x,
-                                                         cr[u & 1], 0, 0, 0);
-        ci[u & 1] = __builtin_amdgcn_mfma_f64_16x16x4f64(half ? x.y : x.x, half ? y.x : y.y,
-                                                         ci[u & 1], 0, 0, 0);
-      }
+    for (int u = 0; u < 4; ++u) {
+      const double2 x = pv[u], y = mv[u];
+      t1[u & 1] = __builtin_amdgcn_mfma_f64_16x16x4f64(x.x, y.x, t1[u & 1], 0, 0, 0);
+      t2[u & 1] = __builtin_amdgcn_mfma_f64_16x16x4f64(x.y, y.y, t2[u & 1], 0, 0, 0);
+      t3[u & 1] = __builtin_amdgcn_mfma_f64_16x16x4f64(x.x + x.y, y.x + y.y, t3[u & 1], 0, 0, 0);
+    }
   };
   const int kfull = kend / 16 * 16;
   if (kfull > 0) {
@@ -442,7 +441,8 @@ __global__ void __launch_bounds__(64) k_gemm_nn(const double2* __restrict__ Pm,
 #pragma unroll
   for (int e = 0; e < 4; ++e) {
     const int row = r0 + lk + 4 * e, col = c0 + li;
-    if (row < m) Y[size_t(col) * m + row] = make_double2(cr[0][e] + cr[1][e], ci[0][e] + ci[1][e]);
+    const double a = t1[0][e] + t1[1][e], c = t2[0][e] + t2[1][e], d = t3[0][e] + t3[1][e];
+    if (row < m) Y[size_t(col) * m + row] = make_double2(a - c, d - a - c);
   }
 }
 
