@@ -277,12 +277,13 @@ __device__ void wave_normalize(double* z, int b) {
 // `col` of U (b x b column-major).  Lane t keeps rows t + 64 q in registers;
 // the reflectors are applied last to first.
 template <int kPL>
-__device__ void back_transform(const double* z, int b, const double2* __restrict__ refl,
+__device__ __attribute__((always_inline)) void back_transform(const double* z, int b, const double2* __restrict__ refl,
                                const double2* __restrict__ tau, double2* __restrict__ U,
                                int col) {
-  // reflectors come from global memory kDepth steps ahead of their use (a
-  // ring of registers), so that the chain of steps does not wait on the L2
-  constexpr int kDepth = kPL <= 2 ? 4 : 1;
+  // reflectors come from global memory kDepth - 1 steps ahead of their use
+  // (a ring of registers, each slot refilled right after its step), so that
+  // the chain of steps does not wait on the L2
+  constexpr int kDepth = kPL <= 2 ? 8 : 1;
   const int t = threadIdx.x;
   double2 u[kPL];
 #pragma unroll
@@ -290,44 +291,60 @@ __device__ void back_transform(const double* z, int b, const double2* __restrict
     const int r = t + 64 * q;
     u[q] = make_double2(r < b ? z[r] : 0.0, 0.0);
   }
+  // loads are unconditional (a clamped, valid address) and the entries
+  // outside the reflector are zeroed where they are used: a predicated load
+  // would make every later use wait for all the loads in flight
   auto load = [&](int k, double2 (&vq)[kPL], double2& tk) {
-    tk = k >= 0 ? tau[k] : make_double2(0.0, 0.0);
-    const double2* v = refl + size_t(k >= 0 ? k : 0) * b;
+    const int kc = k >= 0 ? k : 0;
+    tk = tau[kc];
+    const double2* v = refl + size_t(kc) * b;
 #pragma unroll
     for (int q = 0; q < kPL; ++q) {
       const int r = t + 64 * q;
-      vq[q] = (k >= 0 && r > k && r < b) ? v[r] : make_double2(0.0, 0.0);
+      vq[q] = v[r < b ? r : b - 1];
     }
+  };
+  // one reflector step; a zero tau gives ts = 0 and leaves u unchanged, so
+  // the step has no branch (a branch would make the loop wait for every load
+  // in flight where its paths join)
+  auto apply = [&](int k, const double2 (&ring_k)[kPL], double2 tk) {
+    double2 vq[kPL];
+#pragma unroll
+    for (int q = 0; q < kPL; ++q) {
+      const int r = t + 64 * q;
+      const bool in = r > k && r < b;  // the reflector's rows
+      vq[q] = make_double2(in ? ring_k[q].x : 0.0, in ? ring_k[q].y : 0.0);
+    }
+    double sr = 0.0, si = 0.0;  // v^H u
+#pragma unroll
+    for (int q = 0; q < kPL; ++q) {
+      sr += vq[q].x * u[q].x + vq[q].y * u[q].y;
+      si += vq[q].x * u[q].y - vq[q].y * u[q].x;
+    }
+    sr = wave_sum(sr);
+    si = wave_sum(si);
+    const double2 ts = zmul(tk, make_double2(sr, si));
+#pragma unroll
+    for (int q = 0; q < kPL; ++q) u[q] = zsub(u[q], zmul(vq[q], ts));
   };
   double2 ring[kDepth][kPL], tr[kDepth];
 #pragma unroll
   for (int dd = 0; dd < kDepth; ++dd) load(b - 2 - dd, ring[dd], tr[dd]);
-  for (int k0 = b - 2; k0 >= 0; k0 -= kDepth) {
+  // whole groups of kDepth steps (k = b-2 down to b-1-ngrp*kDepth), then the
+  // remaining steps down to k = 0
+  const int ngrp = (b - 1) / kDepth;
+  int k0 = b - 2;
+  for (int g = 0; g < ngrp; ++g, k0 -= kDepth) {
 #pragma unroll
     for (int dd = 0; dd < kDepth; ++dd) {
       const int k = k0 - dd;
-      if (k >= 0) {
-        double2 vq[kPL];
-#pragma unroll
-        for (int q = 0; q < kPL; ++q) vq[q] = ring[dd][q];
-        const double2 tk = tr[dd];
-        load(k - kDepth, ring[dd], tr[dd]);
-        if (tk.x != 0.0 || tk.y != 0.0) {
-          double sr = 0.0, si = 0.0;  // v^H u
-#pragma unroll
-          for (int q = 0; q < kPL; ++q) {
-            sr += vq[q].x * u[q].x + vq[q].y * u[q].y;
-            si += vq[q].x * u[q].y - vq[q].y * u[q].x;
-          }
-          sr = wave_sum(sr);
-          si = wave_sum(si);
-          const double2 ts = zmul(tk, make_double2(sr, si));
-#pragma unroll
-          for (int q = 0; q < kPL; ++q) u[q] = zsub(u[q], zmul(vq[q], ts));
-        }
-      }
+      apply(k, ring[dd], tr[dd]);
+      load(k - kDepth, ring[dd], tr[dd]);
     }
   }
+#pragma unroll
+  for (int dd = 0; dd < kDepth; ++dd)
+    if (k0 - dd >= 0) apply(k0 - dd, ring[dd], tr[dd]);
 #pragma unroll
   for (int q = 0; q < kPL; ++q) {
     const int r = t + 64 * q;
@@ -341,10 +358,12 @@ __device__ void back_transform(const double* z, int b, const double2* __restrict
 // side, the twist index (smallest |gamma|, the larger index on ties) is a
 // wave reduction, the two outward recurrences for z again run on lanes 0
 // and 1, and the norm is a wave sum.  Lp, Um, Dp, Dm are n-length LDS
-// scratch; all 64 lanes call it.
-__device__ void twisted_vector_wave(const double* d, const double* e, int n, double lambda,
-                                    double pivmin, double* Lp, double* Um, double* Dp,
-                                    double* Dm, double* z) {
+// scratch, distinct from d, e and z (restrict: the next step's loads need
+// not wait behind this step's stores); all 64 lanes call it.
+__device__ void twisted_vector_wave(const double* __restrict__ d, const double* __restrict__ e,
+                                    int n, double lambda, double pivmin, double* __restrict__ Lp,
+                                    double* __restrict__ Um, double* __restrict__ Dp,
+                                    double* __restrict__ Dm, double* __restrict__ z) {
   const int t = threadIdx.x;
   if (n == 1) {
     if (t == 0) z[0] = 1.0;
@@ -355,23 +374,26 @@ __device__ void twisted_vector_wave(const double* d, const double* e, int n, dou
     const bool up = t == 1;
     double q = d[up ? n - 1 : 0] - lambda;
     if (fabs(q) < pivmin) q = -pivmin;
-    if (up)
-      Dm[n - 1] = q;
-    else
-      Dp[0] = q;
-    for (int s = 0; s + 1 < n; ++s) {
-      const int ie = up ? n - 2 - s : s;      // off-diagonal entry
-      const int id = up ? n - 2 - s : s + 1;  // diagonal entry of the new pivot
-      const double ratio = e[ie] / q;
-      double nq = d[id] - lambda - ratio * e[ie];
+    (up ? Dm : Dp)[up ? n - 1 : 0] = q;
+    // step s uses the off-diagonal entry ie(s) and the diagonal entry id(s)
+    // of the new pivot; the next step's pair is loaded one step ahead (a
+    // clamped index past the end, unused) and the stores go through a
+    // selected address, so that the loop has no branch
+    auto ie = [&](int st) { return up ? n - 2 - st : st; };
+    auto id = [&](int st) { return up ? n - 2 - st : st + 1; };
+    double en = e[ie(0)], dn = d[id(0)];
+    for (int st = 0; st + 1 < n; ++st) {
+      const double ec = en, dc = dn;
+      const int nx = st + 2 < n ? st + 1 : st;
+      en = e[ie(nx)];
+      dn = d[id(nx)];
+      const double ratio = ec / q;
+      double nq = dc - lambda - ratio * ec;
       if (fabs(nq) < pivmin) nq = -pivmin;
-      if (up) {
-        Um[n - 1 - s] = ratio;
-        Dm[id] = nq;
-      } else {
-        Lp[s] = ratio;
-        Dp[id] = nq;
-      }
+      double* rp = up ? Um + (n - 1 - st) : Lp + st;
+      double* pp = up ? Dm + id(st) : Dp + id(st);
+      *rp = ratio;
+      *pp = nq;
       q = nq;
     }
   }
