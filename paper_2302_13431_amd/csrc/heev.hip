@@ -79,9 +79,9 @@ __global__ void __launch_bounds__(1024) k_hetrd(const double2* __restrict__ H, i
                                                 double2* __restrict__ tau_out,
                                                 double* __restrict__ d_out,
                                                 double* __restrict__ e_out) {
-  constexpr int kVec = kLds ? 128 : kTriMax;  // vector capacity
-  constexpr int kPR = kLds ? 128 : 256;       // product: row stride
-  constexpr int kPS = 4;                      // product: column slices
+  constexpr int kVec = kLds ? kTrdLdsMax : kTriMax;  // vector capacity
+  constexpr int kPR = kLds ? 128 : 256;              // product: row stride
+  constexpr int kPS = 1024 / kPR;                    // product: column slices
   constexpr int kUR = kLds ? 128 : 256;       // update: row stride
   constexpr int kUS = 1024 / kUR;             // update: column slices
   __shared__ double2 lds_mat[kLds ? kTrdLdsMax * kTrdLdsMax : 1];
@@ -134,7 +134,23 @@ __global__ void __launch_bounds__(1024) k_hetrd(const double2* __restrict__ H, i
       if (sl < kPS) {
         for (int i = i0; i < m; i += kPR) {
           double2 acc = make_double2(0.0, 0.0);
-          for (int j = sl; j < m; j += kPS) {
+          int j = sl;
+          // four columns per pass with their loads issued together, then
+          // the remaining columns one by one
+          for (; j + 3 * kPS < m; j += 4 * kPS) {
+            double2 a[4], v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              a[u] = a22[size_t(j + u * kPS) * b + i];
+              v[u] = vs[j + u * kPS];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+              acc.x += a[u].x * v[u].x - a[u].y * v[u].y;
+              acc.y += a[u].x * v[u].y + a[u].y * v[u].x;
+            }
+          }
+          for (; j < m; j += kPS) {
             const double2 a = a22[size_t(j) * b + i], v = vs[j];
             acc.x += a.x * v.x - a.y * v.y;
             acc.y += a.x * v.y + a.y * v.x;
@@ -376,17 +392,12 @@ __device__ void twisted_vector_wave(const double* __restrict__ d, const double* 
     if (fabs(q) < pivmin) q = -pivmin;
     (up ? Dm : Dp)[up ? n - 1 : 0] = q;
     // step s uses the off-diagonal entry ie(s) and the diagonal entry id(s)
-    // of the new pivot; the next step's pair is loaded one step ahead (a
-    // clamped index past the end, unused) and the stores go through a
-    // selected address, so that the loop has no branch
+    // of the new pivot; the pairs of kChunk steps are read together, so that
+    // the chain of divisions waits on LDS once per chunk, and the stores go
+    // through a selected address, so that the steps have no branch
     auto ie = [&](int st) { return up ? n - 2 - st : st; };
     auto id = [&](int st) { return up ? n - 2 - st : st + 1; };
-    double en = e[ie(0)], dn = d[id(0)];
-    for (int st = 0; st + 1 < n; ++st) {
-      const double ec = en, dc = dn;
-      const int nx = st + 2 < n ? st + 1 : st;
-      en = e[ie(nx)];
-      dn = d[id(nx)];
+    auto step = [&](int st, double ec, double dc) {
       const double ratio = ec / q;
       double nq = dc - lambda - ratio * ec;
       if (fabs(nq) < pivmin) nq = -pivmin;
@@ -395,7 +406,20 @@ __device__ void twisted_vector_wave(const double* __restrict__ d, const double* 
       *rp = ratio;
       *pp = nq;
       q = nq;
+    };
+    constexpr int kChunk = 8;
+    int st = 0;
+    for (; st + kChunk <= n - 1; st += kChunk) {
+      double ec[kChunk], dc[kChunk];
+#pragma unroll
+      for (int u = 0; u < kChunk; ++u) {
+        ec[u] = e[ie(st + u)];
+        dc[u] = d[id(st + u)];
+      }
+#pragma unroll
+      for (int u = 0; u < kChunk; ++u) step(st + u, ec[u], dc[u]);
     }
+    for (; st + 1 < n; ++st) step(st, e[ie(st)], d[id(st)]);
   }
   __syncthreads();
   // twist: gamma_{n-1} = D+(n-1), gamma_i = D+(i) + D-(i) - (d_i - lambda)
