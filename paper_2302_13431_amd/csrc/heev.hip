@@ -1,13 +1,15 @@
 // Eigen-decomposition of the small Hermitian Rayleigh-Ritz matrix H = X^H A X
 // (order b, FP64) used by the signal/null split.
 //
-//   k_hetrd       one workgroup: Householder reduction H = Q T Q^H with T real
+//   k_hetrd(_reg) one workgroup: Householder reduction H = Q T Q^H with T real
 //                 symmetric tridiagonal (each reflector H_k = I - tau_k v_k v_k^H
 //                 is chosen so that H_k^H maps the column below the diagonal
 //                 onto a real multiple of the first unit vector); the
-//                 reflectors are kept for the back-transformation.
+//                 reflectors are kept for the back-transformation.  Up to
+//                 order 96 the matrix stays in registers (k_hetrd_reg),
+//                 beyond that in global memory.
 //   k_tri_eigval  one workgroup per eigenvalue: multisection on Sturm counts
-//                 (64 points per step), to about eps * ||T||.
+//                 (256 points per step), to about eps * ||T||.
 //   k_tri_vector  one workgroup per eigenvalue: the eigenvector of T by the
 //                 twisted factorisation; eigenvalues closer than 1e-12 ||T||
 //                 (and the rare vector whose residual is not small) go to
@@ -16,7 +18,7 @@
 //                 rows in registers, and written in descending eigenvalue
 //                 order.
 //
-// Cost for b = 96: b - 1 reduction steps of four barriers each in LDS, then
+// Cost for b = 96: b - 1 reduction steps of four barriers each, then
 // independent per-eigenvalue work spread over b workgroups.  The former
 // one-sided Jacobi needed about seven sweeps of b - 1 barrier rounds for the
 // Rayleigh-Ritz matrices met here (far from diagonal).
@@ -29,7 +31,7 @@ namespace pisco {
 
 namespace {
 
-constexpr int kTrdLdsMax = 96;   // largest b reduced with the matrix in LDS
+constexpr int kTrdLdsMax = 96;   // largest b reduced with the matrix in registers
 constexpr int kTriMax = 1024;    // largest b of the tridiagonal kernels
 
 // Sum over the 64 lanes of a wave (all lanes active), every lane getting
@@ -67,28 +69,27 @@ __device__ inline double wave_min(double v) {
 
 // ------------------------------------------------------------------ reduction
 
-// A (column-major b x b, Hermitian part of H) is reduced in place: in LDS for
-// b <= kTrdLdsMax, else in `gwork` (global, b*b).  Step k: wave 0 builds the
+// A (column-major b x b, Hermitian part of H) is reduced in place in `gwork`
+// (global, b*b); orders up to kTrdLdsMax take k_hetrd_reg below, which keeps A
+// in registers.  Step k: wave 0 builds the
 // reflector from column k; the product x = tau A22 v is formed in column
 // slices (partial sums in LDS), wave 0 forms w = x - (tau/2)(x^H v) v, and
 // all threads apply A22 <- A22 - v w^H - w v^H, which equals H_k^H A22 H_k.
-template <bool kLds>
 __global__ void __launch_bounds__(1024) k_hetrd(const double2* __restrict__ H, int b,
                                                 double2* __restrict__ gwork,
                                                 double2* __restrict__ refl,
                                                 double2* __restrict__ tau_out,
                                                 double* __restrict__ d_out,
                                                 double* __restrict__ e_out) {
-  constexpr int kVec = kLds ? kTrdLdsMax : kTriMax;  // vector capacity
-  constexpr int kPR = kLds ? 128 : 256;              // product: row stride
-  constexpr int kPS = 1024 / kPR;                    // product: column slices
-  constexpr int kUR = kLds ? 128 : 256;       // update: row stride
-  constexpr int kUS = 1024 / kUR;             // update: column slices
-  __shared__ double2 lds_mat[kLds ? kTrdLdsMax * kTrdLdsMax : 1];
+  constexpr int kVec = kTriMax;      // vector capacity
+  constexpr int kPR = 256;           // product: row stride
+  constexpr int kPS = 1024 / kPR;    // product: column slices
+  constexpr int kUR = 256;           // update: row stride
+  constexpr int kUS = 1024 / kUR;    // update: column slices
   __shared__ double2 part[kPS][kVec];
   __shared__ double2 vs[kVec], ws[kVec];
   __shared__ double2 sh_tau;
-  double2* A = kLds ? lds_mat : gwork;
+  double2* A = gwork;
   const int t = threadIdx.x;
   for (int e = t; e < b * b; e += 1024) {
     const int i = e % b, j = e / b;
@@ -196,6 +197,149 @@ __global__ void __launch_bounds__(1024) k_hetrd(const double2* __restrict__ H, i
   if (t == 0) {
     d_out[b - 1] = A[size_t(b - 1) * b + (b - 1)].x;
     if (b >= 1) e_out[b - 1] = 0.0;
+  }
+}
+
+// The same reduction for b <= kTrdLdsMax with A held in registers: thread t
+// owns row i = t % 128 of the columns j = sl + 8 u (sl = t / 128, u < 12).
+// The product and the rank-2 update then read only v and w (broadcast) from
+// LDS, and the column the next reflector is built from is passed through
+// LDS by its owners.  v and w are zero outside rows k+1 .. b-1, so the
+// update leaves the eliminated rows and columns alone without a branch;
+// groups of four columns that are all eliminated are skipped (uniform per
+// wave).
+__global__ void __launch_bounds__(1024) k_hetrd_reg(const double2* __restrict__ H, int b,
+                                                    double2* __restrict__ refl,
+                                                    double2* __restrict__ tau_out,
+                                                    double* __restrict__ d_out,
+                                                    double* __restrict__ e_out) {
+  constexpr int kR = 128, kS = 8, kU = kTrdLdsMax / kS, kG = 4;
+  static_assert(kU % kG == 0, "column groups");
+  __shared__ double2 colbuf[kTrdLdsMax];
+  __shared__ double2 part[kS][kTrdLdsMax];
+  __shared__ double2 vs[kTrdLdsMax], ws[kTrdLdsMax];
+  __shared__ double2 sh_tau;
+  const int t = threadIdx.x, i = t % kR, sl = t / kR;
+  const bool rowok = i < b;
+  const double2 zero = make_double2(0.0, 0.0);
+  double2 a[kU];
+#pragma unroll
+  for (int u = 0; u < kU; ++u) {
+    const int j = sl + kS * u;
+    a[u] = zero;
+    if (rowok && j < b) {
+      const double2 x = H[size_t(j) * b + i], y = H[size_t(i) * b + j];
+      a[u] = make_double2(0.5 * (x.x + y.x), 0.5 * (x.y - y.y));
+    }
+  }
+  if (t < kTrdLdsMax) {
+    vs[t] = zero;
+    ws[t] = zero;
+  }
+  if (sl == 0 && rowok) colbuf[i] = a[0];
+  __syncthreads();
+  for (int k = 0; k + 1 < b; ++k) {
+    if (t < 64) {
+      double s = 0.0;
+      for (int r = k + 2 + t; r < b; r += 64) s += zabs2(colbuf[r]);
+      s = wave_sum(s);
+      const double2 al = colbuf[k + 1];
+      double2 tau = zero, scale = zero;
+      double beta = al.x;
+      if (s > 0.0 || al.y != 0.0) {
+        const double nrm = sqrt(zabs2(al) + s);
+        beta = al.x >= 0.0 ? -nrm : nrm;
+        tau = make_double2((beta - al.x) / beta, -al.y / beta);
+        const double2 den = make_double2(al.x - beta, al.y);  // |den| >= nrm
+        const double inv = 1.0 / zabs2(den);
+        scale = make_double2(den.x * inv, -den.y * inv);
+      }
+      for (int r = t; r < b; r += 64) {
+        const double2 v = r <= k ? zero : r == k + 1 ? make_double2(1.0, 0.0)
+                                                     : zmul(colbuf[r], scale);
+        vs[r] = v;
+        if (r > k) refl[size_t(k) * b + r] = v;
+      }
+      if (t == 0) {
+        sh_tau = tau;
+        tau_out[k] = tau;
+        e_out[k] = beta;
+        d_out[k] = colbuf[k].x;
+      }
+    }
+    __syncthreads();
+    const double2 tau = sh_tau;
+    {
+      double2 acc = zero;
+#pragma unroll
+      for (int g = 0; g < kU / kG; ++g) {
+        if (sl + kS * (kG * g + kG - 1) > k) {
+          double2 v[kG];
+#pragma unroll
+          for (int uu = 0; uu < kG; ++uu) v[uu] = vs[sl + kS * (kG * g + uu)];
+#pragma unroll
+          for (int uu = 0; uu < kG; ++uu) {
+            const double2 x = a[kG * g + uu];
+            acc.x += x.x * v[uu].x - x.y * v[uu].y;
+            acc.y += x.x * v[uu].y + x.y * v[uu].x;
+          }
+        }
+      }
+      if (rowok) part[sl][i] = acc;
+    }
+    __syncthreads();
+    if (t < 64) {
+      double dr = 0.0, di = 0.0;  // x^H v
+      for (int r = t; r < b; r += 64) {
+        double2 x = part[0][r];
+#pragma unroll
+        for (int q = 1; q < kS; ++q) x = zadd(x, part[q][r]);
+        x = zmul(tau, x);
+        part[0][r] = x;
+        const double2 v = vs[r];
+        dr += x.x * v.x + x.y * v.y;
+        di += x.x * v.y - x.y * v.x;
+      }
+      dr = wave_sum(dr);
+      di = wave_sum(di);
+      const double2 ap = zmul(make_double2(-0.5 * tau.x, -0.5 * tau.y), make_double2(dr, di));
+      for (int r = t; r < b; r += 64)
+        ws[r] = r <= k ? zero : zadd(part[0][r], zmul(ap, vs[r]));
+    }
+    __syncthreads();
+    {
+      const double2 vi = rowok ? vs[i] : zero, wi = rowok ? ws[i] : zero;
+#pragma unroll
+      for (int g = 0; g < kU / kG; ++g) {
+        if (sl + kS * (kG * g + kG - 1) > k) {
+          double2 vj[kG], wj[kG];
+#pragma unroll
+          for (int uu = 0; uu < kG; ++uu) {
+            vj[uu] = vs[sl + kS * (kG * g + uu)];
+            wj[uu] = ws[sl + kS * (kG * g + uu)];
+          }
+#pragma unroll
+          for (int uu = 0; uu < kG; ++uu) {
+            double2& x = a[kG * g + uu];
+            x.x -= vi.x * wj[uu].x + vi.y * wj[uu].y + wi.x * vj[uu].x + wi.y * vj[uu].y;
+            x.y -= vi.y * wj[uu].x - vi.x * wj[uu].y + wi.y * vj[uu].x - wi.x * vj[uu].y;
+          }
+        }
+      }
+      // column k + 1 to LDS for the next reflector
+      const int jn = k + 1;
+      if (rowok && sl == jn % kS) {
+        const int un = jn / kS;
+#pragma unroll
+        for (int u = 0; u < kU; ++u)
+          if (u == un) colbuf[i] = a[u];
+      }
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    d_out[b - 1] = colbuf[b - 1].x;
+    e_out[b - 1] = 0.0;
   }
 }
 
@@ -556,7 +700,7 @@ __global__ void __launch_bounds__(64) k_tri_vector(const double* __restrict__ d,
 // heev_workspace_doubles(b) doubles.
 size_t heev_workspace_doubles(int b) {
   const size_t bb = size_t(b) * b;
-  // refl (complex b*b), reduction matrix when not in LDS (complex b*b),
+  // refl (complex b*b), reduction matrix for orders above kTrdLdsMax (complex b*b),
   // zwork (b*b), tau (complex b), d, e, lam (b each)
   return 2 * bb + 2 * bb + bb + 2 * size_t(b) + 3 * size_t(b) + 64;
 }
@@ -576,9 +720,9 @@ pisco_status_t run_heev(Handle* h, const double2* H, int b, double2* U, double* 
   double* e = d + b;
   double* lam = e + b;
   if (b <= kTrdLdsMax)
-    PISCO_KERNEL(h, k_hetrd<true>, dim3(1), dim3(1024), 0, H, b, gwork, refl, tau, d, e);
+    PISCO_KERNEL(h, k_hetrd_reg, dim3(1), dim3(1024), 0, H, b, refl, tau, d, e);
   else
-    PISCO_KERNEL(h, k_hetrd<false>, dim3(1), dim3(1024), 0, H, b, gwork, refl, tau, d, e);
+    PISCO_KERNEL(h, k_hetrd, dim3(1), dim3(1024), 0, H, b, gwork, refl, tau, d, e);
   PISCO_KERNEL(h, k_tri_eigval, dim3(b), dim3(kEigThreads), 0, d, e, b, lam);
   if (b <= 128)
     PISCO_KERNEL(h, k_tri_vector<2>, dim3(b), dim3(64), 0, d, e, lam, b, refl, tau, zwork, U, theta);
