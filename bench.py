@@ -77,7 +77,7 @@ def kernel_model(name: str, w, est, rs: int):
     return None
 
 
-KERNEL_SOURCES = {"k_gemm_ax": "nullspace.hip", "k_hetrd": "heev.hip",
+KERNEL_SOURCES = {"k_gemm_ax": "nullspace.hip", "k_hetrd": "heev.hip", "k_hetrd_reg": "heev.hip",
                   "k_chol": "nullspace.hip", "k_tri_inv": "nullspace.hip",
                   "k_gemm_tn": "nullspace.hip",
                   "k_gemm_nn": "nullspace.hip", "k_herk": "gx.hip", "k_power": "eig.hip",
