@@ -350,6 +350,36 @@ __global__ void __launch_bounds__(1024) k_hetrd_reg(const double2* __restrict__ 
 // kEigThreads interior points of the bracket (8 bits per step with 256).
 // The waves' ballots meet in LDS (double-buffered: one barrier per step);
 // every lane recomputes the chosen points from their formula.
+// The Sturm count of tri::negcount (the same arithmetic in the same order,
+// so the same count), with eight steps' operands read from LDS at once, so
+// that the chain of divisions waits on LDS once per chunk.
+__device__ inline int negcount_chunked(const double* d, const double* e2, int n, double x,
+                                       double pivmin) {
+  int c = 0;
+  double q = d[0] - x;
+  if (fabs(q) < pivmin) q = -pivmin;
+  c += q < 0.0;
+  constexpr int kChunk = 8;
+  auto step = [&](double di, double ei) {
+    q = di - x - ei / q;
+    if (fabs(q) < pivmin) q = -pivmin;
+    c += q < 0.0;
+  };
+  int i = 1;
+  for (; i + kChunk <= n; i += kChunk) {
+    double dc[kChunk], ec[kChunk];
+#pragma unroll
+    for (int u = 0; u < kChunk; ++u) {
+      dc[u] = d[i + u];
+      ec[u] = e2[i + u - 1];
+    }
+#pragma unroll
+    for (int u = 0; u < kChunk; ++u) step(dc[u], ec[u]);
+  }
+  for (; i < n; ++i) step(d[i], e2[i - 1]);
+  return c;
+}
+
 constexpr int kEigThreads = 256;
 __global__ void __launch_bounds__(kEigThreads) k_tri_eigval(const double* __restrict__ d,
                                                             const double* __restrict__ e,
@@ -393,7 +423,7 @@ __global__ void __launch_bounds__(kEigThreads) k_tri_eigval(const double* __rest
     const double w = hi - lo;
     if (!(w > 2.0 * DBL_EPSILON * fmax(fabs(lo), fabs(hi)) + 4.0 * pivmin)) break;
     auto point = [&](int q) { return lo + w * (double(q + 1) * kInv); };
-    const int c = tri::negcount(sd, se2, b, point(t), pivmin);
+    const int c = negcount_chunked(sd, se2, b, point(t), pivmin);
     const unsigned long long mk = __ballot(c > j);
     if (lane == 0) masks[it & 1][wave] = mk;
     __syncthreads();
@@ -437,9 +467,10 @@ __device__ void wave_normalize(double* z, int b) {
 // `col` of U (b x b column-major).  Lane t keeps rows t + 64 q in registers;
 // the reflectors are applied last to first.
 template <int kPL>
-__device__ __attribute__((always_inline)) void back_transform(const double* z, int b, const double2* __restrict__ refl,
-                               const double2* __restrict__ tau, double2* __restrict__ U,
-                               int col) {
+__device__ __attribute__((always_inline)) void back_transform(const double* z, int b,
+                                                              const double2* __restrict__ refl,
+                                                              const double2* __restrict__ tau,
+                                                              double2* __restrict__ U, int col) {
   // reflectors come from global memory kDepth - 1 steps ahead of their use
   // (a ring of registers, each slot refilled right after its step), so that
   // the chain of steps does not wait on the L2
