@@ -195,9 +195,13 @@ __global__ void k_ws_loss(const float* __restrict__ Y, const float2* __restrict_
                           float* __restrict__ loss, _Float16* __restrict__ dY) {
   const long long v = blockIdx.x * 256LL + threadIdx.x;
   if (v >= N) return;
+  // loops over the kMaxQ bound (unrolled, guarded by q < Q) keep ch in
+  // registers; a loop to Q would index it at run time, in scratch memory
   float2 ch[kMaxQ];
   float sr = 0.f, si = 0.f, nn = 0.f;
-  for (int q = 0; q < Q; ++q) {
+#pragma unroll
+  for (int q = 0; q < kMaxQ; ++q) {
+    if (q >= Q) continue;
     const float2 n = nb[size_t(q) * N + v], c = target[size_t(q) * N + v];
     const float2 a = make_float2(n.x + Y[size_t(v) * 2 * Q + 2 * q],
                                  n.y + Y[size_t(v) * 2 * Q + 2 * q + 1]);
@@ -209,7 +213,9 @@ __global__ void k_ws_loss(const float* __restrict__ Y, const float2* __restrict_
   const float s2 = sr * sr + si * si;
   const float inv = nn > 0.f ? 1.f / nn : 0.f;
   loss[v] = 1.f - s2 * inv;
-  for (int q = 0; q < Q; ++q) {
+#pragma unroll
+  for (int q = 0; q < kMaxQ; ++q) {
+    if (q >= Q) continue;
     const float2 c = target[size_t(q) * N + v];
     // conj(s) c
     const float ur = sr * c.x + si * c.y, ui = sr * c.y - si * c.x;
@@ -273,15 +279,21 @@ __global__ void k_ws_apply(const float* __restrict__ Y, const float2* __restrict
                            long long N, float2* __restrict__ out) {
   const long long v = blockIdx.x * 256LL + threadIdx.x;
   if (v >= N) return;
-  float2 c[kMaxQ];
+  float2 c[kMaxQ];  // in registers: loops over the kMaxQ bound, unrolled
   float nn = 0.f;
-  for (int q = 0; q < Q; ++q) {
+#pragma unroll
+  for (int q = 0; q < kMaxQ; ++q) {
+    if (q >= Q) continue;
     const float2 n = nb[size_t(q) * N + v];
     c[q] = make_float2(n.x + Y[size_t(v) * 2 * Q + 2 * q], n.y + Y[size_t(v) * 2 * Q + 2 * q + 1]);
     nn += c[q].x * c[q].x + c[q].y * c[q].y;
   }
   const float inv = nn > 0.f ? rsqrtf(nn) : 0.f;
-  for (int q = 0; q < Q; ++q) out[size_t(q) * N + v] = make_float2(c[q].x * inv, c[q].y * inv);
+#pragma unroll
+  for (int q = 0; q < kMaxQ; ++q) {
+    if (q >= Q) continue;
+    out[size_t(q) * N + v] = make_float2(c[q].x * inv, c[q].y * inv);
+  }
 }
 
 // Neighbour vectors: voxel (z, y, x) of the grid lr takes the coarse voxel
@@ -302,21 +314,26 @@ __global__ void k_ws_neighbor(const float2* __restrict__ coarse, int Q, int3 lr,
   const long long Nc = 1LL * lc.x * lc.y * lc.z;
   const long long pv = (1LL * parent(iz, lr.z, lc.z) * lc.y + parent(iy, lr.y, lc.y)) * lc.x +
                        parent(ix, lr.x, lc.x);
-  float2 c[kMaxQ];
+  float2 c[kMaxQ];  // in registers: loops over the kMaxQ bound, unrolled
   float best = -1.f;
-  int kb = 0;
-  for (int q = 0; q < Q; ++q) {
+  float2 cb = make_float2(0.f, 0.f);  // the largest entry (lowest index on ties)
+#pragma unroll
+  for (int q = 0; q < kMaxQ; ++q) {
+    if (q >= Q) continue;
     c[q] = coarse[size_t(q) * Nc + pv];
     const float m = c[q].x * c[q].x + c[q].y * c[q].y;
     if (m > best) {
       best = m;
-      kb = q;
+      cb = c[q];
     }
   }
   const float mag = sqrtf(best);
-  const float2 ph = mag > 0.f ? make_float2(c[kb].x / mag, -c[kb].y / mag) : make_float2(1.f, 0.f);
-  for (int q = 0; q < Q; ++q)
+  const float2 ph = mag > 0.f ? make_float2(cb.x / mag, -cb.y / mag) : make_float2(1.f, 0.f);
+#pragma unroll
+  for (int q = 0; q < kMaxQ; ++q) {
+    if (q >= Q) continue;
     nb[size_t(q) * N + v] = make_float2(c[q].x * ph.x - c[q].y * ph.y, c[q].x * ph.y + c[q].y * ph.x);
+  }
 }
 
 // He-uniform weights (limit sqrt(6 / fan_in)), the output layer scaled by
