@@ -6,7 +6,7 @@
 //                 is chosen so that H_k^H maps the column below the diagonal
 //                 onto a real multiple of the first unit vector); the
 //                 reflectors are kept for the back-transformation.  Up to
-//                 order 96 the matrix stays in registers (k_hetrd_reg),
+//                 order 128 the matrix stays in registers (k_hetrd_reg),
 //                 beyond that in global memory.
 //   k_tri_eigval  one workgroup per eigenvalue: multisection on Sturm counts
 //                 (256 points per step), to about eps * ||T||.
@@ -31,7 +31,7 @@ namespace pisco {
 
 namespace {
 
-constexpr int kTrdLdsMax = 96;   // largest b reduced with the matrix in registers
+constexpr int kTrdLdsMax = 96;   // largest b reduced with twelve register columns per thread
 constexpr int kTriMax = 1024;    // largest b of the tridiagonal kernels
 
 // Sum over the 64 lanes of a wave (all lanes active), every lane getting
@@ -70,8 +70,8 @@ __device__ inline double wave_min(double v) {
 // ------------------------------------------------------------------ reduction
 
 // A (column-major b x b, Hermitian part of H) is reduced in place in `gwork`
-// (global, b*b); orders up to kTrdLdsMax take k_hetrd_reg below, which keeps A
-// in registers.  Step k: wave 0 builds the
+// (global, b*b); orders up to 128 take k_hetrd_reg below, which keeps A in
+// registers.  Step k: wave 0 builds the
 // reflector from column k; the product x = tau A22 v is formed in column
 // slices (partial sums in LDS), wave 0 forms w = x - (tau/2)(x^H v) v, and
 // all threads apply A22 <- A22 - v w^H - w v^H, which equals H_k^H A22 H_k.
@@ -200,24 +200,27 @@ __global__ void __launch_bounds__(1024) k_hetrd(const double2* __restrict__ H, i
   }
 }
 
-// The same reduction for b <= kTrdLdsMax with A held in registers: thread t
-// owns row i = t % 128 of the columns j = sl + 8 u (sl = t / 128, u < 12).
+// The same reduction for b <= 8 kU with A held in registers: thread t owns
+// row i = t % 128 of the columns j = sl + 8 u (sl = t / 128, u < kU; kU = 12
+// for b <= 96, 16 for b <= 128).
 // The product and the rank-2 update then read only v and w (broadcast) from
 // LDS, and the column the next reflector is built from is passed through
 // LDS by its owners.  v and w are zero outside rows k+1 .. b-1, so the
 // update leaves the eliminated rows and columns alone without a branch;
 // groups of four columns that are all eliminated are skipped (uniform per
 // wave).
+template <int kU>
 __global__ void __launch_bounds__(1024) k_hetrd_reg(const double2* __restrict__ H, int b,
                                                     double2* __restrict__ refl,
                                                     double2* __restrict__ tau_out,
                                                     double* __restrict__ d_out,
                                                     double* __restrict__ e_out) {
-  constexpr int kR = 128, kS = 8, kU = kTrdLdsMax / kS, kG = 4;
-  static_assert(kU % kG == 0, "column groups");
-  __shared__ double2 colbuf[kTrdLdsMax];
-  __shared__ double2 part[kS][kTrdLdsMax];
-  __shared__ double2 vs[kTrdLdsMax], ws[kTrdLdsMax];
+  // column groups of four, or two where sixteen columns leave fewer registers
+  constexpr int kR = 128, kS = 8, kN = kS * kU, kG = kU > 12 ? 2 : 4;
+  static_assert(kU % kG == 0 && kN <= kR, "column groups");
+  __shared__ double2 colbuf[kN];
+  __shared__ double2 part[kS][kN];
+  __shared__ double2 vs[kN], ws[kN];
   __shared__ double2 sh_tau;
   const int t = threadIdx.x, i = t % kR, sl = t / kR;
   const bool rowok = i < b;
@@ -232,7 +235,7 @@ __global__ void __launch_bounds__(1024) k_hetrd_reg(const double2* __restrict__ 
       a[u] = make_double2(0.5 * (x.x + y.x), 0.5 * (x.y - y.y));
     }
   }
-  if (t < kTrdLdsMax) {
+  if (t < kN) {
     vs[t] = zero;
     ws[t] = zero;
   }
@@ -731,7 +734,7 @@ __global__ void __launch_bounds__(64) k_tri_vector(const double* __restrict__ d,
 // heev_workspace_doubles(b) doubles.
 size_t heev_workspace_doubles(int b) {
   const size_t bb = size_t(b) * b;
-  // refl (complex b*b), reduction matrix for orders above kTrdLdsMax (complex b*b),
+  // refl (complex b*b), reduction matrix for orders above 128 (complex b*b),
   // zwork (b*b), tau (complex b), d, e, lam (b each)
   return 2 * bb + 2 * bb + bb + 2 * size_t(b) + 3 * size_t(b) + 64;
 }
@@ -751,7 +754,9 @@ pisco_status_t run_heev(Handle* h, const double2* H, int b, double2* U, double* 
   double* e = d + b;
   double* lam = e + b;
   if (b <= kTrdLdsMax)
-    PISCO_KERNEL(h, k_hetrd_reg, dim3(1), dim3(1024), 0, H, b, refl, tau, d, e);
+    PISCO_KERNEL(h, k_hetrd_reg<kTrdLdsMax / 8>, dim3(1), dim3(1024), 0, H, b, refl, tau, d, e);
+  else if (b <= 128)
+    PISCO_KERNEL(h, k_hetrd_reg<16>, dim3(1), dim3(1024), 0, H, b, refl, tau, d, e);
   else
     PISCO_KERNEL(h, k_hetrd, dim3(1), dim3(1024), 0, H, b, gwork, refl, tau, d, e);
   PISCO_KERNEL(h, k_tri_eigval, dim3(b), dim3(kEigThreads), 0, d, e, b, lam);
