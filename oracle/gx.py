@@ -57,3 +57,13 @@ def gx_from_lag_kernel(K: np.ndarray, lags: np.ndarray, x: np.ndarray,
         E = np.exp(-2j * np.pi * (x[a:a + chunk] @ lags.T))   # [nx, L]
         out[a:a + chunk] = (E @ Kf.T).reshape(-1, Q, Q)
     return out
+
+
+def espirit_operator(G: np.ndarray, bound: float) -> np.ndarray:
+    """ESPIRiT's per-voxel operator B(x) = I - G(x)/|Lambda| (Eq. 20).
+
+    Its eigenvector for the largest eigenvalue is the nullspace method's map;
+    [Nx, Q, Q]."""
+    G = np.asarray(G, dtype=np.complex128)
+    Q = G.shape[-1]
+    return np.eye(Q)[None] - G / float(bound)

@@ -95,3 +95,20 @@ def normalize_rss(c: np.ndarray) -> np.ndarray:
     ok = rss > 0
     out[:, ok] = c[:, ok] / rss[ok]
     return out
+
+
+def support_mask(lam_min_lr: np.ndarray, bound: float, grid_out,
+                 thresh: float = 0.1) -> np.ndarray:
+    """Binary mask of the image support (Sec. III-D, optional last step).
+
+    The smallest singular value of H(x) is about zero inside the support and
+    clearly positive outside it (Sec. III-B, III-C).  Its square is
+    lambda_min(G(x)); normalised by |Lambda| (the scale the paper plots) the
+    map lies in [0, 1].  Reading taken here: the low-resolution map
+    lambda_min / |Lambda| is brought to the output grid by the same periodic
+    sinc interpolation as the maps, and a voxel is inside the support where
+    the interpolated value is below `thresh`.  Returns a bool array shaped
+    grid_out."""
+    lr = np.asarray(lam_min_lr, dtype=np.float64) / float(bound)
+    up = interpolate(lr[None].astype(np.complex128), grid_out)[0]
+    return up.real < thresh

@@ -126,12 +126,12 @@ def _fibonacci_dirs(Q: int) -> np.ndarray:
                      np.sin(phi) * np.cos(theta)], axis=1)
 
 
-def _maps(rng: np.random.Generator, grid, Q: int) -> np.ndarray:
-    D = len(grid)
-    xs = _coords(grid)
-    maps = np.zeros((Q,) + tuple(grid), dtype=np.complex128)
+def _draw_bumps(rng: np.random.Generator, D: int, Q: int) -> list:
+    """Three Gaussian bumps per coil: [(centre, width, amplitude)] per q."""
     dirs3 = _fibonacci_dirs(Q) if D == 3 else None
+    bumps = []
     for q in range(Q):
+        coil = []
         for _ in range(3):
             radius = rng.uniform(0.55, 0.75)
             if D == 2:
@@ -142,8 +142,26 @@ def _maps(rng: np.random.Generator, grid, Q: int) -> np.ndarray:
                 centre = radius * d / np.linalg.norm(d)
             width = rng.uniform(0.25, 0.5)
             amp = rng.uniform(0.5, 1.0) * np.exp(1j * rng.uniform(0, 2 * np.pi))
-            r2 = sum((x - c) ** 2 for x, c in zip(xs, centre))
-            maps[q] = maps[q] + amp * np.exp(-r2 / (2 * width ** 2))
+            coil.append((centre, width, amp))
+        bumps.append(coil)
+    return bumps
+
+
+def _raw_map(xs, coil_bumps) -> np.ndarray:
+    """One coil's bump mixture before the RSS normalisation."""
+    out = 0.0
+    for centre, width, amp in coil_bumps:
+        r2 = sum((x - c) ** 2 for x, c in zip(xs, centre))
+        out = out + amp * np.exp(-r2 / (2 * width ** 2))
+    return out
+
+
+def _maps(rng: np.random.Generator, grid, Q: int) -> np.ndarray:
+    xs = _coords(grid)
+    bumps = _draw_bumps(rng, len(grid), Q)
+    maps = np.zeros((Q,) + tuple(grid), dtype=np.complex128)
+    for q in range(Q):
+        maps[q] = maps[q] + _raw_map(xs, bumps[q])
     rss = np.sqrt((np.abs(maps) ** 2).sum(axis=0))
     return maps / rss[None]
 
@@ -186,3 +204,55 @@ def as_device_input(acs: np.ndarray) -> np.ndarray:
     same rounded array (widened back to complex128) so both sides see
     identical inputs."""
     return np.ascontiguousarray(acs.astype(np.complex64))
+
+
+def _acs_dft(n: int, a: int) -> np.ndarray:
+    """[a, n] rows of the centred orthonormal DFT for the a central
+    frequencies k = -floor(a/2) ... (e^{-i 2 pi k x})."""
+    k = np.arange(a) - a // 2
+    return np.exp(-2j * np.pi * np.outer(k, grid_positions(n))) / np.sqrt(n)
+
+
+def make_acs_scan(seed: int, grid: Sequence[int], Q: int, acs_shape: Sequence[int],
+                  n_shapes: int, snr_db: float) -> Scan:
+    """Draw a scan too large to hold as full k-space: only the ACS block.
+
+    Same phantom and map distributions as make_scan.  Each coil image
+    rho * c_q is formed in turn and its centred ACS block taken by a
+    separable partial DFT (exact: the same samples the full orthonormal DFT
+    would give).  The noise variance comes from the mean coil energy over
+    the whole grid as in make_scan; noise is drawn for the ACS samples only
+    (independent per sample, so its statistics there are those of the full
+    k-space).  image, maps and kspace are not kept (maps is None-shaped: an
+    empty array)."""
+    grid = tuple(int(g) for g in grid)
+    acs_shape = tuple(int(a) for a in acs_shape)
+    D = len(grid)
+    if len(acs_shape) != D or D not in (2, 3):
+        raise ValueError("grid and acs_shape must both have rank 2 or 3")
+    rng = np.random.Generator(np.random.PCG64(seed))
+    shapes = _draw_shapes(rng, D, n_shapes)
+    image = _phantom(grid, shapes)
+    xs = _coords(grid)
+    bumps = _draw_bumps(rng, D, Q)
+    rss2 = np.zeros(grid, dtype=np.float64)
+    for q in range(Q):
+        rss2 += np.abs(_raw_map(xs, bumps[q])) ** 2
+    inv_rss = 1.0 / np.sqrt(rss2)
+    del rss2
+    mats = [_acs_dft(n, a) for n, a in zip(grid, acs_shape)]
+    acs = np.empty((Q,) + acs_shape, dtype=np.complex128)
+    energy = 0.0
+    for q in range(Q):
+        coil = _raw_map(xs, bumps[q]) * inv_rss * image
+        energy += float(np.sum(np.abs(coil) ** 2))
+        blk = coil
+        for d in range(D - 1, -1, -1):
+            blk = np.moveaxis(np.tensordot(mats[d], blk, axes=([1], [d])), 0, d)
+        acs[q] = blk
+    sigma2 = energy / (Q * float(np.prod(grid))) / 10 ** (snr_db / 10.0)
+    noise = rng.standard_normal(acs.shape) + 1j * rng.standard_normal(acs.shape)
+    acs = acs + np.sqrt(sigma2 / 2.0) * noise
+    return Scan(grid=grid, Q=Q, acs_shape=acs_shape, image=np.empty(0),
+                maps=np.empty(0), kspace=None, acs=np.ascontiguousarray(acs),
+                sigma2=sigma2, seed=seed)

@@ -444,3 +444,167 @@ def test_map_error_has_no_cancellation_floor():
     b = (a * np.cos(t) + w * np.sin(t)) * np.exp(1j * np.array([0.3, 1.3, 2.0, -1.0, 3.0]))
     e = metrics.map_error(a, b)
     assert np.allclose(e, 2 * np.sin(t / 2), rtol=1e-6, atol=0)
+
+
+# ---------------------------------------------------------------- start vector, coil reference
+
+
+def test_initial_index_picks_smallest_diagonal_lowest_on_ties():
+    """q* = argmin diag G(x), lowest index on ties: a constructed field where
+    argmax, the last minimum, or the off-diagonal would pick another index."""
+    Q = 5
+    diag = np.array([
+        [3.0, 1.0, 2.0, 5.0, 4.0],    # unique minimum at 1
+        [2.0, 0.5, 0.5, 9.0, 0.5],    # three-way tie at 1, 2, 4 -> 1
+        [7.0, 7.0, 7.0, 7.0, 7.0],    # all equal -> 0
+        [4.0, 4.0, 4.0, 4.0, 0.25],   # minimum last -> 4
+    ])
+    G = np.zeros((len(diag), Q, Q), dtype=np.complex128)
+    for x, d in enumerate(diag):
+        G[x] = np.diag(d)
+        # large off-diagonal entries must not influence the choice
+        G[x, 0, 3] = 50.0 + 20.0j
+        G[x, 3, 0] = 50.0 - 20.0j
+    q = eig.initial_index(G)
+    assert list(q) == [1, 1, 0, 4]
+    # the start vector the iteration uses is e_{q*}: zero steps return it
+    c, _, _, it = eig.power_iteration(G, 100.0, n_iter=0)
+    assert np.all(it == 0)
+    ref = np.zeros((len(diag), Q))
+    ref[np.arange(len(diag)), [1, 1, 0, 4]] = 1.0
+    assert np.array_equal(c, ref)
+
+
+def test_coil_reference_rule():
+    """Sec. V rule: after referencing, the reference channel is real and
+    non-negative, magnitudes are unchanged, and the result does not depend on
+    a per-voxel phase of the input; a voxel whose reference entry is zero is
+    left unchanged."""
+    rng = np.random.default_rng(21)
+    Q, grid = 4, (5, 6)
+    c = rng.standard_normal((Q,) + grid) + 1j * rng.standard_normal((Q,) + grid)
+    c[0, 1, 2] = 0.0
+    out = maps.coil_reference(c)
+    nz = np.abs(c[0]) > 0
+    assert np.all(np.abs(out[0][nz].imag) <= 1e-15 * np.abs(out[0][nz]))
+    assert np.all(out[0][nz].real > 0)
+    assert np.allclose(np.abs(out), np.abs(c), rtol=1e-15, atol=0)
+    assert np.array_equal(out[:, 1, 2], c[:, 1, 2])
+    phase = np.exp(1j * rng.uniform(0, 2 * np.pi, size=grid))
+    again = maps.coil_reference(c * phase[None])
+    assert np.allclose(again[:, nz], out[:, nz], atol=1e-14)
+    # another reference channel
+    out2 = maps.coil_reference(c, q_ref=2)
+    assert np.all(np.abs(out2[2].imag) <= 1e-15 * np.abs(out2[2]))
+    assert np.all(out2[2].real > 0)
+    # closed form for Q = 2: (r e^{ia}, s e^{ib}) -> (r, s e^{i(b - a)})
+    two = np.array([[2.0 * np.exp(0.7j)], [3.0 * np.exp(-1.1j)]])
+    assert np.allclose(maps.coil_reference(two), [[2.0], [3.0 * np.exp(-1.8j)]], atol=1e-15)
+
+
+# ---------------------------------------------------------------- end to end (P-R1)
+
+
+def _recovery(sc, radius, grid_lr):
+    from scipy import ndimage
+    from oracle import pipeline
+    acs = generator.as_device_input(sc.acs)
+    res = pipeline.estimate(acs, radius, grid_lr, sc.grid)
+    inner = ndimage.binary_erosion(np.abs(sc.image) > 0, iterations=2)
+    e = metrics.map_error(sc.maps, res.maps)[inner]
+    axes = tuple(range(1, sc.image.ndim + 1))
+    coil_noisy = generator.centred_ifft(sc.kspace, axes)
+    return res, e, coil_noisy
+
+
+@pytest.mark.parametrize("seed", [1000, 1002])
+def test_pipeline_recovers_generator_maps_2d(seed):
+    """The whole oracle pipeline (C_full Gram, eigen split, lag kernel, G(x),
+    power iteration, phase reference, interpolation, RSS) on a seeded scan
+    of the 64^2, 8-coil, 24^2-ACS family recovers the generator's maps up to
+    the per-voxel scale (Sec. II) on the object eroded by two voxels.  The
+    maps are smooth but not band-limited, so recovery is approximate: on the
+    full-resolution estimation grid the median distance is below 1e-2; on the
+    workload's 32^2 grid, interpolation adds a few 1e-2 (Sec. IV-D).  A
+    wrong sign, lag or transposed block gives distances of order one."""
+    w = workloads.SMALL_2D
+    sc = w.scan(seed)
+    res, e, coil = _recovery(sc, w.radius, sc.grid)
+    assert np.median(e) <= 1e-2
+    assert np.percentile(e, 90) <= 2.5e-2
+    # the projection residual sits near the noise floor (the residual of the
+    # true maps is the noise's share of the data)
+    r_est = metrics.projection_residual(coil, res.maps)
+    r_true = metrics.projection_residual(coil, sc.maps)
+    assert r_true <= r_est <= 2.0 * r_true
+    # Table I pattern: ESPIRiT-form maps (top eigenvector of the operator
+    # built from the SIGNAL filters) give the same maps and the same residual
+    x = gx.grid_points(sc.grid)
+    Bs = gx.gx_from_filters(res.split.signal, res.lam, x, sc.Q) / len(res.lam)
+    _, V = np.linalg.eigh(Bs)
+    c_esp = V[:, :, -1].T.reshape(res.c_lr.shape)
+    c_esp, _ = maps.phase_reference(c_esp, res.rho_lr)
+    m_esp = maps.normalize_rss(maps.interpolate(c_esp, sc.grid))
+    r_esp = metrics.projection_residual(coil, m_esp)
+    _, c_ns, _ = eig.smallest_exact(res.G)
+    c_ns, _ = maps.phase_reference(c_ns.T.reshape(res.c_lr.shape), res.rho_lr)
+    r_ns = metrics.projection_residual(coil, maps.normalize_rss(maps.interpolate(c_ns, sc.grid)))
+    assert abs(r_esp - r_ns) <= 1e-12 * r_ns
+    # ten power-iteration steps (Sec. IV-E) change the residual only slightly
+    assert abs(r_est - r_ns) <= 1e-4 * r_ns
+    # the workload's own low-res grid
+    _, e_lr, _ = _recovery(sc, w.radius, w.grid_lr)
+    assert np.median(e_lr) <= 3e-2
+
+
+def test_pipeline_recovers_generator_maps_3d():
+    sc = generator.make_scan(7, (24, 24, 24), 4, (12, 12, 12), 5, 40.0)
+    res, e, coil = _recovery(sc, 2.0, sc.grid)
+    assert np.median(e) <= 2e-2
+    assert np.percentile(e, 90) <= 3e-2
+    r_est = metrics.projection_residual(coil, res.maps)
+    r_true = metrics.projection_residual(coil, sc.maps)
+    assert r_true <= r_est <= 4.0 * r_true
+
+
+# ---------------------------------------------------------------- ESPIRiT operator, support mask
+
+
+def test_espirit_operator_equals_signal_filter_form():
+    """Eq. 20: I - G/|Lambda| built from the NULL filters equals the operator
+    built from the SIGNAL filters, (1/|Lambda|) H_s^H H_s; its top eigenvector
+    is G's bottom one."""
+    sc = _tiny_acs(seed=4, Q=3)
+    lam = support.kernel_support(2, 2.0)
+    lags = support.difference_set(lam)
+    gram = calib.gram_from_lags(calib.correlation_lags(sc.acs, lags), lam, lags)
+    sp = nullspace.split_from_gram(gram)
+    x = np.random.default_rng(5).uniform(-0.5, 0.5, size=(40, 2))
+    G = gx.gx_from_filters(sp.null, lam, x, 3)
+    B = gx.espirit_operator(G, len(lam))
+    Bs = gx.gx_from_filters(sp.signal, lam, x, 3) / len(lam)
+    assert np.max(np.abs(B - Bs)) <= 1e-12
+    wB, VB = np.linalg.eigh(B)
+    _, cmin, _ = eig.smallest_exact(G)
+    assert np.max(metrics.map_error(VB[:, :, -1], cmin, axis=1)) <= 1e-7
+
+
+def test_support_mask_separates_object_from_background():
+    """Sec. III-D step 6 / Sec. III-B: lambda_min(G)/|Lambda| is near zero on
+    the object and clearly positive off it; thresholding its interpolated map
+    recovers the support away from the edges."""
+    from scipy import ndimage
+    from oracle import pipeline
+    w = workloads.SMALL_2D
+    sc = w.scan(1000)
+    res = pipeline.estimate(generator.as_device_input(sc.acs), w.radius, w.grid_lr, sc.grid)
+    obj = np.abs(sc.image) > 0
+    inner = ndimage.binary_erosion(obj, iterations=2)
+    outer = ~ndimage.binary_dilation(obj, iterations=2)
+    m = maps.support_mask(res.lam_min.reshape(w.grid_lr), len(res.lam), sc.grid, 0.02)
+    assert m.shape == sc.grid
+    assert np.all(m[inner])
+    assert np.mean(~m[outer]) >= 0.98
+    # threshold monotone: a lower level keeps a subset
+    m2 = maps.support_mask(res.lam_min.reshape(w.grid_lr), len(res.lam), sc.grid, 0.01)
+    assert np.all(m[m2])
