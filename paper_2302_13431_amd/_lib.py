@@ -203,6 +203,11 @@ class Handle:
         self.h = _P()
         _check(lib().pisco_create(ctypes.byref(self.h), _P(stream.cuda_stream)), "pisco_create")
 
+    def set_stream(self, stream=None):
+        """Bind the handle to `stream` (None: the stream it was created with)."""
+        s = self.stream if stream is None else stream
+        _check(lib().pisco_set_stream(self.h, _P(s.cuda_stream)), "pisco_set_stream", self.h)
+
     def close(self):
         if self.h:
             lib().pisco_destroy(self.h)

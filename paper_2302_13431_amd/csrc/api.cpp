@@ -165,6 +165,17 @@ pisco_status_t estimate_core(Handle* h, const Plan& p, const pisco_opts_t& o, in
   EstLayout e = est_layout(p, b, ws);
   if (counts_out) *counts_out = e.counts;
   pisco_status_t st;
+  if (fixed_products <= 0) {
+    // refused before anything is enqueued (see run_nullspace)
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    const hipError_t ce = hipStreamIsCapturing(h->stream, &cs);
+    if (ce != hipSuccess) return hip_check(h, ce, "estimate capture query");
+    if (cs != hipStreamCaptureStatusNone) {
+      h->last_error = "the adaptive nullspace schedule reads control words on the host and "
+                      "cannot be captured; use a fixed product count";
+      return PISCO_ERR_UNSUPPORTED;
+    }
+  }
   if ((st = run_gram(h, p, acs, e.gram, e.stage_ws))) return st;
   float* lam = lam_min ? lam_min : e.lam;
   const std::function<pisco_status_t()> later = [&]() -> pisco_status_t {
@@ -444,6 +455,8 @@ struct BatchSlice {
   Plan p;
   pisco_opts_t o;
   int b = 0, products = 0, ax_waves = 0;
+  int bmax = 0;        // widest block the slice's workspace region holds
+  size_t ws_bytes = 0;  // size of that region
   const float2* acs = nullptr;
   float2* out = nullptr;
   float* lam = nullptr;
@@ -498,8 +511,9 @@ pisco_status_t batch_prepare(Handle* h, int32_t B, const pisco_problem_t* probs,
     if ((st = block_of(sl.p, sl.o, &sl.b, &err))) return fail(h, st, err.c_str());
     if (sl.o.precision < PISCO_PREC_FP32 || sl.o.precision > PISCO_PREC_SPLIT_BF16)
       return fail(h, PISCO_ERR_ARG, "unknown precision");
-    const int bmax = sl.o.block > 0 ? sl.b : max_block(sl.p, sl.b);
-    sum += (estimate_ws_size(sl.p, bmax) + 255) & ~size_t(255);
+    sl.bmax = sl.o.block > 0 ? sl.b : max_block(sl.p, sl.b);
+    sl.ws_bytes = (estimate_ws_size(sl.p, sl.bmax) + 255) & ~size_t(255);
+    sum += sl.ws_bytes;
     out->push_back(sl);
   }
   *total = sum;
@@ -552,9 +566,15 @@ pisco_status_t pisco_batch_create(pisco_handle_t handle, int32_t B, const pisco_
     sl[i].out = static_cast<float2*>(maps_out[i]);
     sl[i].lam = lam_min ? lam_min[i] : nullptr;
     sl[i].ws = base;
-    const int bmax = sl[i].o.block > 0 ? sl[i].b : max_block(sl[i].p, sl[i].b);
-    base += (estimate_ws_size(sl[i].p, bmax) + 255) & ~size_t(255);
+    base += sl[i].ws_bytes;
   }
+  // every run of a slice checks that its block fits the slice's region
+  auto run = [&](const BatchSlice& x, Handle* hh, int bb, int fixed, int waves,
+                 int32_t** counts) -> pisco_status_t {
+    if (bb > x.bmax || estimate_ws_size(x.p, bb) > x.ws_bytes)
+      return fail(h, PISCO_ERR_WORKSPACE, "batch: block exceeds the slice's workspace region");
+    return estimate_core(hh, x.p, x.o, bb, x.acs, x.out, x.lam, x.ws, fixed, waves, counts);
+  };
   uint32_t saved = 0, flags = 0, tune_flags = 0;
   if ((st = take_flags(h, &saved))) return st;
   hipEvent_t t0 = nullptr, t1 = nullptr;
@@ -574,7 +594,7 @@ pisco_status_t pisco_batch_create(pisco_handle_t handle, int32_t B, const pisco_
     auto it = h->tuned.find(key);
     if (it == h->tuned.end()) {
       std::vector<int> blocks{x.b};
-      const int bcap = x.o.block > 0 ? x.b : max_block(x.p, x.b);
+      const int bcap = x.bmax;
       if (x.b + 32 <= bcap) blocks.push_back(x.b + 32);
       const int waves[3] = {1024, 2048, 4096};
       float best = 3.0e38f;
@@ -586,7 +606,7 @@ pisco_status_t pisco_batch_create(pisco_handle_t handle, int32_t B, const pisco_
           float ms = 0.f;
           for (int rep = 0; rep < 2 && !st; ++rep) {
             if (rep == 1) e = hipEventRecord(t0, h->stream);
-            st = estimate_core(h, x.p, x.o, bb, x.acs, x.out, x.lam, x.ws, 0, wv);
+            st = run(x, h, bb, 0, wv, nullptr);
             if (rep == 1 && e == hipSuccess) e = hipEventRecord(t1, h->stream);
           }
           if (st) {
@@ -614,16 +634,17 @@ pisco_status_t pisco_batch_create(pisco_handle_t handle, int32_t B, const pisco_
       }
       it = h->tuned.emplace(key, choice).first;
     }
-    x.b = it->second.first;
+    // a shape's cached choice was tuned within the same bmax (same shape key)
+    x.b = it->second.first < x.bmax ? it->second.first : x.bmax;
     x.ax_waves = it->second.second;
     // planning run; the signal rank depends on the data, so a slice whose
-    // rank reaches the tuned block gets a wider block of its own
-    const int bcap = x.o.block > 0 ? x.b : max_block(x.p, x.b);
+    // rank reaches the tuned block gets a wider block of its own, up to the
+    // block its workspace region was sized for
+    const int bcap = x.bmax;
     uint32_t plan_flags = 0;
     while (true) {
       int32_t* counts = nullptr;
-      if ((st = estimate_core(h, x.p, x.o, x.b, x.acs, x.out, x.lam, x.ws, 0, x.ax_waves,
-                              &counts))) {
+      if ((st = run(x, h, x.b, 0, x.ax_waves, &counts))) {
         cleanup_events();
         return st;
       }
@@ -692,8 +713,7 @@ pisco_status_t pisco_batch_create(pisco_handle_t handle, int32_t B, const pisco_
   for (int k = 1; k < S && e == hipSuccess; ++k) e = hipStreamWaitEvent(bt->streams[k], bt->events[0], 0);
   for (int i = 0; i < B && e == hipSuccess && !st; ++i) {
     const BatchSlice& x = bt->slices[i];
-    st = estimate_core(bt->sub[i % S], x.p, x.o, x.b, x.acs, x.out, x.lam, x.ws, x.products,
-                       x.ax_waves);
+    st = run(x, bt->sub[i % S], x.b, x.products, x.ax_waves, nullptr);
   }
   for (int k = 1; k < S && e == hipSuccess; ++k) {
     e = hipEventRecord(bt->events[k], bt->streams[k]);

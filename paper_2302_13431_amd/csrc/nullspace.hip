@@ -999,6 +999,18 @@ pisco_status_t run_nullspace(Handle* h, const Plan& p, int b, int max_iters,
                              const std::function<pisco_status_t()>* downstream,
                              bool* downstream_queued) {
   if (downstream_queued) *downstream_queued = false;
+  if (fixed_products <= 0) {
+    // the adaptive schedule waits on the host for control words the kernels
+    // write: it cannot be recorded into a graph
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    const hipError_t e = hipStreamIsCapturing(h->stream, &cs);
+    if (e != hipSuccess) return hip_check(h, e, "nullspace capture query");
+    if (cs != hipStreamCaptureStatusNone) {
+      h->last_error = "the adaptive nullspace schedule reads control words on the host and "
+                      "cannot be captured; use a fixed product count";
+      return PISCO_ERR_UNSUPPORTED;
+    }
+  }
   NullCtx c{h, &p, b, {}};
   layout_null(p, b, ws, &c.w);
   hipStream_t s = h->stream;

@@ -13,7 +13,7 @@ from typing import List, Tuple
 
 import numpy as np
 
-from .generator import Scan, make_scan
+from .generator import Scan, make_acs_scan, make_scan
 
 
 @dataclasses.dataclass(frozen=True)
@@ -27,6 +27,7 @@ class Workload:
     n_shapes: int
     snr_db: float
     seeds: Tuple[int, ...]
+    acs_only: bool = False      # scan too large for full k-space: ACS block only
 
     @property
     def D(self) -> int:
@@ -34,6 +35,9 @@ class Workload:
 
     def scan(self, seed: int | None = None, keep_kspace: bool = True) -> Scan:
         s = self.seeds[0] if seed is None else seed
+        if self.acs_only:
+            return make_acs_scan(s, self.grid, self.Q, self.acs, self.n_shapes,
+                                 self.snr_db)
         return make_scan(s, self.grid, self.Q, self.acs, self.n_shapes,
                          self.snr_db, keep_kspace=keep_kspace)
 
@@ -51,7 +55,14 @@ VOLUME_3D = Workload("3d_96x160x160_q16_acs24_r4", (96, 160, 160), 16,
                      (24, 24, 24), 4.0, (24, 40, 40), 20, 30.0,
                      (3000, 3001, 3002))
 
-ALL = {w.name: w for w in (SMALL_2D, BRAIN_2D, VOLUME_3D)}
+# 3D 256x256x128 (z = 128 slowest), 32 coils, 32^3 ACS, radius 5 (n = 16480);
+# low-res grid ACS + 24 = 56 per dim; the application size of the learned
+# warm start.  Shapes and SNR as the other 3D volume; drawn ACS-only.
+APP_3D = Workload("3d_128x256x256_q32_acs32_r5", (128, 256, 256), 32,
+                  (32, 32, 32), 5.0, (56, 56, 56), 20, 30.0, (20000,),
+                  acs_only=True)
+
+ALL = {w.name: w for w in (SMALL_2D, BRAIN_2D, VOLUME_3D, APP_3D)}
 
 
 def tiny(seed: int = 7, Q: int = 4, grid=(32, 32), acs=(16, 16), radius=2.0,

@@ -345,6 +345,61 @@ def test_zero_data_is_flagged():
     assert torch.isfinite(torch.view_as_real(out)).all()
 
 
+def test_block_too_small_is_flagged():
+    """A block narrower than the signal rank plus its margin (forced from the
+    host: block 32 against the 71 signal eigenvalues of the 256^2 scan)."""
+    import paper_2302_13431_amd as P
+    name = "2d_256x256_q32_acs32_r5"
+    _, _, _, g32, sp = oracle_gram_split(name)
+    assert sp.r_signal > 32
+    est = estimator(name, block=32)
+    ev, basis, counts = est.nullspace(cuda(g32))
+    flags = est.status()
+    report("block too small", flags=flags, counts=str(counts.cpu().numpy().tolist()))
+    assert flags & P._lib.FLAG_BLOCK_TOO_SMALL
+
+
+def test_not_converged_is_flagged():
+    """An iteration cap the schedule cannot meet (forced from the host: at
+    most three products, before the first Rayleigh-Ritz step is due)."""
+    import paper_2302_13431_amd as P
+    name = "2d_256x256_q32_acs32_r5"
+    _, _, _, g32, _ = oracle_gram_split(name)
+    est = estimator(name, max_subspace_iters=3)
+    ev, basis, counts = est.nullspace(cuda(g32))
+    counts = counts.cpu().numpy()
+    flags = est.status()
+    report("not converged", flags=flags, counts=str(counts.tolist()))
+    assert flags & P._lib.FLAG_NOT_CONVERGED
+    assert counts[3] == 0
+
+
+def test_adaptive_schedule_refuses_capture():
+    """The adaptive schedule reads control words on the host: inside a graph
+    capture pisco_estimate must refuse before enqueuing anything."""
+    import paper_2302_13431_amd as P
+    w, acs = scan_inputs("2d_64x64_q8_acs24_r3")
+    est = estimator("2d_64x64_q8_acs24_r3")
+    x = cuda(acs)
+    est.estimate(x)  # tables and workspace exist before the capture
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    err = None
+    with torch.cuda.stream(s):
+        est.h.set_stream(s)
+        try:
+            with torch.cuda.graph(g, stream=s):
+                try:
+                    est.estimate(x)
+                except P.PiscoError as e:
+                    err = e
+        finally:
+            est.h.set_stream(None)
+    torch.cuda.synchronize()
+    assert err is not None and err.status == 4
+
+
 def test_workspace_too_small_is_rejected():
     import paper_2302_13431_amd as P
     w, acs = scan_inputs("2d_64x64_q8_acs24_r3")
