@@ -219,6 +219,19 @@ pisco_status_t pisco_eig_from(pisco_handle_t handle, int32_t Q, int64_t N,
                               float* lam_min, int32_t* iters, void* workspace,
                               size_t workspace_bytes);
 
+/* As pisco_eig_from (init may be NULL: start from e_q*), plus an FP64
+ * Rayleigh check of the FP32 result (Sec. IV-E; the final check the method
+ * keeps in FP64): with c the stored map widened to FP64 and normalised, and
+ * G the FP32 input widened exactly,
+ *   lam64   : double [N], c^H G c (may be NULL)
+ *   resid64 : double [N], ||G c - lam64 c||_2 (may be NULL). */
+pisco_status_t pisco_eig_checked(pisco_handle_t handle, int32_t Q, int64_t N,
+                                 float bound, const pisco_opts_t* opts,
+                                 const void* G, const void* init, void* maps,
+                                 float* lam_min, int32_t* iters, double* lam64,
+                                 double* resid64, void* workspace,
+                                 size_t workspace_bytes);
+
 /* ---- Batches in one graph launch (not in the paper) ---------------------
  * Many problems (slices or scans of any sizes and channel counts) run as
  * one captured HIP graph, launched with a single call.  pisco_batch_create

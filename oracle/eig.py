@@ -25,6 +25,19 @@ def smallest_exact(G: np.ndarray):
     return w[:, 0], V[:, :, 0], w[:, 1]
 
 
+def rayleigh(G: np.ndarray, c: np.ndarray):
+    """Rayleigh quotient and residual of given vectors (Sec. IV-E check).
+
+    G: [N, Q, Q] Hermitian, c: [N, Q].  Each c is normalised first; returns
+    (lambda = c^H G c [N], ||G c - lambda c||_2 [N])."""
+    G = np.asarray(G, dtype=np.complex128)
+    c = np.asarray(c, dtype=np.complex128)
+    c = c / np.linalg.norm(c, axis=1, keepdims=True)
+    Gc = np.einsum("xpq,xq->xp", G, c)
+    lam = np.real(np.einsum("xp,xp->x", c.conj(), Gc))
+    return lam, np.linalg.norm(Gc - lam[:, None] * c, axis=1)
+
+
 def initial_index(G: np.ndarray) -> np.ndarray:
     """q* = argmin_q G_qq(x) (first index on ties)."""
     return np.argmin(np.real(np.einsum("xqq->xq", G)), axis=1)

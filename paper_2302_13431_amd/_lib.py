@@ -80,6 +80,9 @@ _SIGS = {
                         ctypes.c_size_t], ctypes.c_int),
     "pisco_eig_from": ([_P, ctypes.c_int32, ctypes.c_int64, ctypes.c_float, ctypes.POINTER(Opts),
                         _P, _P, _P, _P, _P, _P, ctypes.c_size_t], ctypes.c_int),
+    "pisco_eig_checked": ([_P, ctypes.c_int32, ctypes.c_int64, ctypes.c_float,
+                           ctypes.POINTER(Opts), _P, _P, _P, _P, _P, _P, _P, _P,
+                           ctypes.c_size_t], ctypes.c_int),
     "pisco_ws_param_count": ([ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
     "pisco_ws_workspace_size": ([ctypes.c_int32, ctypes.c_int64, ctypes.POINTER(ctypes.c_size_t)],
                                 ctypes.c_int),
@@ -250,6 +253,13 @@ def pisco_eig_from(h: Handle, Q: int, N: int, bound: float, opts: Opts, G, init,
                    iters=None):
     _check(lib().pisco_eig_from(h.h, Q, N, bound, ctypes.byref(opts), _ptr(G), _ptr(init),
                                 _ptr(maps), _ptr(lam), _ptr(iters), None, 0), "pisco_eig_from", h.h)
+
+
+def pisco_eig_checked(h: Handle, Q: int, N: int, bound: float, opts: Opts, G, init, maps,
+                      lam=None, iters=None, lam64=None, resid64=None):
+    _check(lib().pisco_eig_checked(h.h, Q, N, bound, ctypes.byref(opts), _ptr(G), _ptr(init),
+                                   _ptr(maps), _ptr(lam), _ptr(iters), _ptr(lam64),
+                                   _ptr(resid64), None, 0), "pisco_eig_checked", h.h)
 
 
 def pisco_ws_param_count(Q: int) -> int:

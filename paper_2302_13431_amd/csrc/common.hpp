@@ -234,9 +234,12 @@ pisco_status_t run_nullspace(Handle* h, const Plan& p, int b, int max_iters,
                              bool* downstream_queued = nullptr);
 pisco_status_t run_gx(Handle* h, const Plan& p, int b, int precision, const double2* basis,
                       const int32_t* counts, float2* G, void* ws);
+// lam64 / res64 (nullable): FP64 Rayleigh quotient and residual of the
+// FP32 result, computed from the FP32 G widened to FP64.
 pisco_status_t run_eig(Handle* h, int Q, long long N, float bound, int iters,
                        float tol, const float2* G, const float2* init, float2* maps,
-                       float* lam, int32_t* it_out);
+                       float* lam, int32_t* it_out, double* lam64 = nullptr,
+                       double* res64 = nullptr);
 pisco_status_t run_maps(Handle* h, const Plan& p, int phase_rule, const float2* acs,
                         const float2* maps_lr, float2* maps_out, void* ws);
 

@@ -95,6 +95,25 @@ class Estimator:
         L.pisco_eig(self.h, Q, N, bound, opts or self.opts, G.contiguous(), maps, lam, it)
         return maps, lam, it
 
+    def eig_checked(self, G, init=None, opts: Optional[L.Opts] = None,
+                    N: Optional[int] = None, Q: Optional[int] = None,
+                    bound: Optional[float] = None):
+        """Power iteration plus the FP64 Rayleigh check of the result:
+        (maps, lam, iters, lam64, resid64)."""
+        t = self.torch
+        N = self.Nlr if N is None else int(N)
+        Q = self.Q if Q is None else int(Q)
+        bound = float(self.nsup) if bound is None else float(bound)
+        maps = self._alloc((Q, N), t.complex64)
+        lam = self._alloc((N,), t.float32)
+        it = self._alloc((N,), t.int32)
+        lam64 = self._alloc((N,), t.float64)
+        res64 = self._alloc((N,), t.float64)
+        L.pisco_eig_checked(self.h, Q, N, bound, opts or self.opts, G.contiguous(),
+                            None if init is None else init.contiguous(), maps, lam, it, lam64,
+                            res64)
+        return maps, lam, it, lam64, res64
+
     def eig_from(self, G, init, opts: Optional[L.Opts] = None):
         """Power iteration from the given start vectors (float2 [Q][N_lr])."""
         t = self.torch

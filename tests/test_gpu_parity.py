@@ -235,6 +235,39 @@ def test_eig_empty():
     torch.cuda.synchronize()
 
 
+@pytest.mark.parametrize("name", WL2D)
+@pytest.mark.parametrize("tol", [0.0, 1e-4])
+def test_eig_fp64_rayleigh_check(name, tol):
+    """FP64 Rayleigh quotient and residual of the FP32 maps (Sec. IV-E check)
+    against the oracle's definition on the same vectors and the same (FP32)
+    matrices, to 1e-12 |Lambda|; in tolerance mode every voxel that stopped
+    before the cap meets the tolerance in FP64 too (up to FP32 rounding of
+    the stopping test)."""
+    import paper_2302_13431_amd as P
+    ref = oracle_full(name)
+    w = workloads.ALL[name]
+    bound = float(len(ref.lam))
+    G32 = ref.G.astype(np.complex64)
+    est = estimator(name)
+    opts = P.make_opts(power_iters=10 if tol == 0 else 100, tol=tol)
+    maps, lam, it, lam64, res64 = est.eig_checked(cuda(packed_upper(G32)), opts=opts)
+    maps, lam, it = maps.cpu().numpy(), lam.cpu().numpy(), it.cpu().numpy()
+    lam64, res64 = lam64.cpu().numpy(), res64.cpu().numpy()
+    lo, ro = oeig.rayleigh(G32.astype(np.complex128), maps.T)
+    e_l = float(np.abs(lam64 - lo).max() / bound)
+    e_r = float(np.abs(res64 - ro).max() / bound)
+    _, _, r_pi, _ = oeig.power_iteration(ref.G, bound, 10)
+    report(f"eig fp64 check {name} tol={tol}", err_lam64=e_l, err_res64=e_r,
+           res_max=float(res64.max() / bound), oracle_pi_res_max=float(r_pi.max() / bound),
+           lam32_vs_64=float(np.abs(lam - lam64).max() / bound))
+    assert e_l <= 1e-12 and e_r <= 1e-12
+    assert float(np.abs(lam - lam64).max() / bound) <= 1e-5
+    if tol > 0:
+        stopped = it < 100
+        assert stopped.mean() > 0.99
+        assert np.all(res64[stopped] <= tol * bound * (1 + 1e-2) + 1e-5 * bound)
+
+
 # ------------------------------------------------------------------ phase + interpolation
 
 

@@ -321,6 +321,29 @@ def test_power_iteration_bound_and_convergence():
     assert np.allclose(lam, lmin, atol=1e-10 * bound)
 
 
+def test_rayleigh_check():
+    """The Rayleigh check (Sec. IV-E): on exact eigenvectors (numpy eigh)
+    it returns their eigenvalue with a residual at rounding level; for a
+    perturbed vector c = u1 + e u2 of a diagonal G the closed forms
+    lambda = (l1 + e^2 l2)/(1 + e^2) and residual e |l2 - l1| / (1 + e^2)
+    hold; it is invariant to the scale and phase of c."""
+    rng = np.random.default_rng(21)
+    Q, bound = 7, 20.0
+    G, U, w = _random_psd_field(rng, 40, Q, bound)
+    lmin, cmin, _ = eig.smallest_exact(G)
+    lam, r = eig.rayleigh(G, cmin)
+    assert np.allclose(lam, lmin, atol=1e-13 * bound)
+    assert np.all(r <= 1e-13 * bound)
+    lam2, r2 = eig.rayleigh(G, cmin * (3.0 * np.exp(1j * rng.uniform(0, 6, (40, 1)))))
+    assert np.allclose(lam2, lam, atol=1e-13 * bound) and np.allclose(r2, r, atol=1e-13 * bound)
+    l1, l2, e = 2.0, 5.0, 0.3
+    D = np.diag([l1, l2, 9.0]).astype(complex)[None]
+    c = np.array([[1.0, e, 0.0]], dtype=complex)
+    lam3, r3 = eig.rayleigh(D, c)
+    assert np.isclose(lam3[0], (l1 + e * e * l2) / (1 + e * e), rtol=1e-14)
+    assert np.isclose(r3[0], e * abs(l2 - l1) / (1 + e * e), rtol=1e-13)
+
+
 # ---------------------------------------------------------------- phase, interpolation, normalisation
 
 
