@@ -9,15 +9,18 @@
  *  - All array arguments except those marked "host" are DEVICE pointers owned
  *    by the caller.  Scratch space comes from the caller's workspace, whose
  *    size is given by pisco_workspace_size().  Workspace pointers must be
- *    256-byte aligned.  The only device memory the library allocates inside
- *    a call are plan-constant tables (DFT and sinc matrices, the support
- *    list and its box map: a function of the sizes alone, at most a few MB
- *    per problem shape), built by the first call that needs them, kept by
- *    the handle and freed by pisco_destroy (see pisco_create).
+ *    256-byte aligned.  No call allocates device memory: the plan-constant
+ *    tables (DFT and sinc matrices, the support list and its box map, a
+ *    function of the sizes alone) live at the front of the workspace and
+ *    are rebuilt by one small kernel at the start of every call that uses
+ *    them.
  *  - Calls enqueue kernels on the handle's stream and return without
- *    synchronising, except where stated.  Results are valid once the stream
- *    has been synchronised.  No call issues hipMemsetAsync or host<->device
- *    copies, so a sequence of calls can be captured into a HIP graph.
+ *    synchronising, except where stated (pisco_get_status, pisco_trace_read,
+ *    pisco_batch_create, and the adaptive schedule of pisco_nullspace /
+ *    pisco_estimate, which waits on events for its control words).  Results
+ *    are valid once the stream has been synchronised.  No call issues
+ *    hipMemsetAsync or host<->device copies, so calls other than the
+ *    adaptive schedule can be captured into a HIP graph.
  *  - Complex data are interleaved single-precision pairs (float2, re then im)
  *    unless marked double2.
  *  - Spatial arrays are stored [z][y][x] with x fastest.  For D = 2 the z
@@ -106,16 +109,15 @@ typedef struct {
 #define PISCO_STAGE_GX        3
 #define PISCO_STAGE_EIG       4
 #define PISCO_STAGE_MAPS      5
+#define PISCO_STAGE_MASK      6   /* pisco_support_mask */
 #define PISCO_STAGE_ALL       0   /* pisco_estimate, intermediates included */
 
 /* Handle creation.  `stream` is a hipStream_t (NULL = default stream).  The
- * handle owns host state, one small device status word allocated here, and
- * the plan-constant tables that calls build on first use with a problem
- * shape (each build synchronises the stream once); pisco_destroy frees all
- * of it.  A call that would build a table while its stream is being captured
- * into a graph returns PISCO_ERR_UNSUPPORTED: run it once outside capture
- * first (pisco_batch_create does so for every slice).  A handle must not be
- * used from two threads at once. */
+ * handle owns host state, one small device status word and a few pinned
+ * host control words, all allocated here and freed by pisco_destroy.  It
+ * also resolves, for the current device, the address of the static scratch
+ * that pisco_gram_static uses.  A handle must not be used from two threads
+ * at once. */
 pisco_status_t pisco_create(pisco_handle_t* handle, void* stream);
 pisco_status_t pisco_destroy(pisco_handle_t handle);
 pisco_status_t pisco_set_stream(pisco_handle_t handle, void* stream);
@@ -231,6 +233,26 @@ pisco_status_t pisco_eig_checked(pisco_handle_t handle, int32_t Q, int64_t N,
                                  float* lam_min, int32_t* iters, double* lam64,
                                  double* resid64, void* workspace,
                                  size_t workspace_bytes);
+
+/* Image-support mask (Sec. III-D, the optional last step of the naive
+ * algorithm).  Inside the support H(x) has rank Q - 1 and lambda_min(G(x))
+ * (its smallest singular value squared) is about zero; outside it is
+ * clearly positive (Sec. III-B, III-C).  The low-resolution map
+ * lambda_min / |Lambda| is brought to grid_out by the periodic sinc
+ * interpolation of pisco_maps, in FP64, and a voxel is inside where the
+ * interpolated value is below `thresh` (in (0, 1)).
+ *   lam_min : float [N_lr], e.g. from pisco_eig or pisco_estimate
+ *   mask    : uint8 [grid_out], 1 inside, 0 outside
+ * Workspace: pisco_workspace_size(..., PISCO_STAGE_MASK, ...). */
+pisco_status_t pisco_support_mask(pisco_handle_t handle, const pisco_problem_t* prob,
+                                  const float* lam_min, float thresh, uint8_t* mask,
+                                  void* workspace, size_t workspace_bytes);
+
+/* ESPIRiT's operator B(x) = I - G(x) / bound (Eq. 20; bound = |Lambda|):
+ * its eigenvector for the eigenvalue one (its largest) is the map.
+ *   G, B : float2 packed as from pisco_gx, N voxels (B may alias G). */
+pisco_status_t pisco_espirit_operator(pisco_handle_t handle, int32_t Q, int64_t N,
+                                      float bound, const void* G, void* B);
 
 /* ---- Batches in one graph launch (not in the paper) ---------------------
  * Many problems (slices or scans of any sizes and channel counts) run as

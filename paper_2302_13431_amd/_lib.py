@@ -24,7 +24,7 @@ FLAG_NOT_CONVERGED = 0x2
 FLAG_BLOCK_TOO_SMALL = 0x4
 FLAG_ZERO_DATA = 0x8
 
-STAGE_ALL, STAGE_GRAM, STAGE_NULLSPACE, STAGE_GX, STAGE_EIG, STAGE_MAPS = 0, 1, 2, 3, 4, 5
+STAGE_ALL, STAGE_GRAM, STAGE_NULLSPACE, STAGE_GX, STAGE_EIG, STAGE_MAPS, STAGE_MASK = range(7)
 PREC_FP32, PREC_SPLIT_F16, PREC_SPLIT_BF16 = 0, 1, 2
 
 
@@ -68,6 +68,10 @@ _SIGS = {
     "pisco_nullspace_block": ([ctypes.POINTER(Problem), ctypes.POINTER(Opts),
                                ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
     "pisco_gram": ([_P, ctypes.POINTER(Problem), _P, _P, _P, ctypes.c_size_t], ctypes.c_int),
+    "pisco_support_mask": ([_P, ctypes.POINTER(Problem), _P, ctypes.c_float, _P, _P,
+                            ctypes.c_size_t], ctypes.c_int),
+    "pisco_espirit_operator": ([_P, ctypes.c_int32, ctypes.c_int64, ctypes.c_float, _P, _P],
+                               ctypes.c_int),
     "pisco_nullspace": ([_P, ctypes.POINTER(Problem), ctypes.POINTER(Opts), _P, _P, _P, _P, _P,
                          ctypes.c_size_t], ctypes.c_int),
     "pisco_gx": ([_P, ctypes.POINTER(Problem), ctypes.POINTER(Opts), _P, _P, _P, _P,
@@ -260,6 +264,17 @@ def pisco_eig_checked(h: Handle, Q: int, N: int, bound: float, opts: Opts, G, in
     _check(lib().pisco_eig_checked(h.h, Q, N, bound, ctypes.byref(opts), _ptr(G), _ptr(init),
                                    _ptr(maps), _ptr(lam), _ptr(iters), _ptr(lam64),
                                    _ptr(resid64), None, 0), "pisco_eig_checked", h.h)
+
+
+def pisco_support_mask(h: Handle, prob: Problem, lam, thresh: float, mask, ws):
+    _check(lib().pisco_support_mask(h.h, ctypes.byref(prob), _ptr(lam), float(thresh),
+                                    _ptr(mask), _ptr(ws), ws.numel() * ws.element_size()),
+           "pisco_support_mask", h.h)
+
+
+def pisco_espirit_operator(h: Handle, Q: int, N: int, bound: float, G, B):
+    _check(lib().pisco_espirit_operator(h.h, Q, N, bound, _ptr(G), _ptr(B)),
+           "pisco_espirit_operator", h.h)
 
 
 def pisco_ws_param_count(Q: int) -> int:

@@ -75,19 +75,49 @@ pisco_status_t block_of(const Plan& p, const pisco_opts_t& o, int* b, std::strin
   return PISCO_OK;
 }
 
-size_t ws_stage(const Plan& p, int b, int stage) {
+// Stage scratch without tables (pisco_estimate's shared stage region).
+size_t ws_stage_scratch(const Plan& p, int b, int stage) {
   switch (stage) {
     case PISCO_STAGE_GRAM: return layout_gram(p, nullptr, nullptr);
     case PISCO_STAGE_NULLSPACE: return layout_null(p, b, nullptr, nullptr);
     case PISCO_STAGE_GX: return layout_gx(p, b, nullptr, nullptr);
     case PISCO_STAGE_EIG: return 256;
     case PISCO_STAGE_MAPS: return layout_maps(p, nullptr, nullptr);
+    case PISCO_STAGE_MASK: return layout_mask(p, nullptr, nullptr, nullptr, nullptr);
     default: return 0;
   }
 }
 
+unsigned stage_tables(int stage) {
+  switch (stage) {
+    case PISCO_STAGE_GRAM: return kTabSupport;
+    case PISCO_STAGE_GX: return kTabGx;
+    case PISCO_STAGE_MAPS: return kTabMaps;
+    case PISCO_STAGE_MASK: return kTabMask;
+    default: return 0;
+  }
+}
+
+// A stage call's workspace: its tables, then its scratch.
+size_t ws_stage(const Plan& p, int b, int stage) {
+  const unsigned tb = stage_tables(stage);
+  const size_t tabs = tb ? (layout_tables(p, tb, nullptr, nullptr) + 255) & ~size_t(255) : 0;
+  return tabs + ws_stage_scratch(p, b, stage);
+}
+
+// Carves a stage call's tables from the front of ws, builds them and returns
+// the scratch that follows.
+pisco_status_t stage_prologue(Handle* h, const Plan& p, int stage, void* ws, Tables* t,
+                              void** scratch) {
+  const unsigned tb = stage_tables(stage);
+  const size_t tabs = (layout_tables(p, tb, ws, t) + 255) & ~size_t(255);
+  *scratch = static_cast<char*>(ws) + tabs;
+  return build_tables(h, p, tb, *t);
+}
+
 // Intermediates of pisco_estimate followed by the largest stage workspace.
 struct EstLayout {
+  Tables tabs;
   float2* gram;
   double* eigvals;
   double2* basis;
@@ -103,6 +133,9 @@ struct EstLayout {
 EstLayout est_layout(const Plan& p, int b, void* ws) {
   Carver c(ws);
   EstLayout e{};
+  // tables first: their offsets do not depend on the block size
+  char* tb = c.take<char>(layout_tables(p, kTabAll, nullptr, nullptr));
+  layout_tables(p, kTabAll, tb, &e.tabs);
   e.gram = c.take<float2>(size_t(p.n) * p.n);
   e.eigvals = c.take<double>(b);
   e.basis = c.take<double2>(size_t(b) * p.n);
@@ -112,10 +145,10 @@ EstLayout est_layout(const Plan& p, int b, void* ws) {
   e.lam = c.take<float>(p.Nlr);
   // the nullspace stage has a region of its own: the later stages may be
   // enqueued while its iteration can still go on
-  e.null_ws = c.take<char>(ws_stage(p, b, 2));
+  e.null_ws = c.take<char>(ws_stage_scratch(p, b, 2));
   size_t m = 0;
   for (int st = 1; st <= 5; ++st) {
-    const size_t v = st == 2 ? 0 : ws_stage(p, b, st);
+    const size_t v = st == 2 ? 0 : ws_stage_scratch(p, b, st);
     m = v > m ? v : m;
   }
   e.stage_ws = c.take<char>(m);
@@ -127,46 +160,12 @@ EstLayout est_layout(const Plan& p, int b, void* ws) {
 
 namespace pisco {
 
-pisco_status_t cached_table(Handle* h, const std::string& key, size_t bytes, void** out,
-                            const std::function<pisco_status_t(void*)>& build) {
-  auto& tables = h->table_owner ? h->table_owner->tables : h->tables;
-  auto it = tables.find(key);
-  if (it != tables.end()) {
-    *out = it->second;
-    return PISCO_OK;
-  }
-  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-  hipError_t e = hipStreamIsCapturing(h->stream, &cs);
-  if (e != hipSuccess) return hip_check(h, e, "table capture query");
-  if (cs != hipStreamCaptureStatusNone) {
-    h->last_error = "a plan-constant table for this problem is not built yet; run the call "
-                    "once outside stream capture";
-    return PISCO_ERR_UNSUPPORTED;
-  }
-  void* p = nullptr;
-  e = hipMalloc(&p, bytes ? bytes : 1);
-  if (e != hipSuccess) return hip_check(h, e, "table allocation");
-  pisco_status_t st = build(p);
-  if (st == PISCO_OK) {
-    e = hipStreamSynchronize(h->stream);
-    if (e != hipSuccess) st = hip_check(h, e, "table build");
-  }
-  if (st != PISCO_OK) {
-    (void)hipStreamSynchronize(h->stream);
-    (void)hipFree(p);
-    return st;
-  }
-  tables[key] = p;
-  *out = p;
-  return PISCO_OK;
-}
-
-
 size_t estimate_ws_size(const Plan& p, int b) { return est_layout(p, b, nullptr).total; }
 
 pisco_status_t estimate_core(Handle* h, const Plan& p, const pisco_opts_t& o, int b,
                              const float2* acs, float2* maps_out, float* lam_min, void* ws,
-                             int fixed_products, int ax_waves, int32_t** counts_out) {
+                             int fixed_products, int ax_waves, int32_t** counts_out,
+                             bool tables_ready) {
   EstLayout e = est_layout(p, b, ws);
   if (counts_out) *counts_out = e.counts;
   pisco_status_t st;
@@ -181,15 +180,17 @@ pisco_status_t estimate_core(Handle* h, const Plan& p, const pisco_opts_t& o, in
       return PISCO_ERR_UNSUPPORTED;
     }
   }
-  if ((st = run_gram(h, p, acs, e.gram, e.stage_ws))) return st;
+  if (!tables_ready && (st = build_tables(h, p, kTabAll, e.tabs))) return st;
+  if ((st = run_gram(h, p, e.tabs, acs, e.gram, e.stage_ws))) return st;
   float* lam = lam_min ? lam_min : e.lam;
   const std::function<pisco_status_t()> later = [&]() -> pisco_status_t {
     pisco_status_t s2;
-    if ((s2 = run_gx(h, p, b, o.precision, e.basis, e.counts, e.G, e.stage_ws))) return s2;
+    if ((s2 = run_gx(h, p, e.tabs, b, o.precision, e.basis, e.counts, e.G, e.stage_ws)))
+      return s2;
     if ((s2 = run_eig(h, p.Q, p.Nlr, float(p.L), o.power_iters, o.tol, e.G, nullptr,
                       e.maps_lr, lam, nullptr)))
       return s2;
-    return run_maps(h, p, o.phase_rule, acs, e.maps_lr, maps_out, e.stage_ws);
+    return run_maps(h, p, e.tabs, o.phase_rule, acs, e.maps_lr, maps_out, e.stage_ws);
   };
   bool queued = false;
   if ((st = run_nullspace(h, p, b, o.max_subspace_iters, e.gram, e.eigvals, e.basis, e.counts,
@@ -242,7 +243,6 @@ pisco_status_t pisco_destroy(pisco_handle_t handle) {
   Handle* h = reinterpret_cast<Handle*>(handle);
   if (!h) return PISCO_ERR_ARG;
   (void)hipStreamSynchronize(h->stream);
-  for (auto& kv : h->tables) (void)hipFree(kv.second);
   if (h->sched_ev) (void)hipEventDestroy(h->sched_ev);
   (void)hipHostFree(h->host_ctl);
   (void)hipHostFree(h->host_pinned);
@@ -317,7 +317,7 @@ pisco_status_t pisco_workspace_size(const pisco_problem_t* prob, const pisco_opt
     *bytes = est_layout(p, b, nullptr).total;
     return PISCO_OK;
   }
-  if (stage < 1 || stage > 5) return PISCO_ERR_ARG;
+  if (stage < 1 || stage > 6) return PISCO_ERR_ARG;
   *bytes = ws_stage(p, b, stage);
   return PISCO_OK;
 }
@@ -343,9 +343,12 @@ pisco_status_t pisco_gram(pisco_handle_t handle, const pisco_problem_t* prob, co
   pisco_status_t st = check_common(h, prob, &p);
   if (st) return st;
   if (!acs || !gram || !ws || !aligned(ws)) return fail(h, PISCO_ERR_ARG, "null or unaligned pointer");
-  if (ws_bytes < layout_gram(p, nullptr, nullptr))
+  if (ws_bytes < ws_stage(p, 0, PISCO_STAGE_GRAM))
     return fail(h, PISCO_ERR_WORKSPACE, "workspace too small for pisco_gram");
-  return run_gram(h, p, static_cast<const float2*>(acs), static_cast<float2*>(gram), ws);
+  Tables t;
+  void* scratch = nullptr;
+  if ((st = stage_prologue(h, p, PISCO_STAGE_GRAM, ws, &t, &scratch))) return st;
+  return run_gram(h, p, t, static_cast<const float2*>(acs), static_cast<float2*>(gram), scratch);
 }
 
 pisco_status_t pisco_nullspace(pisco_handle_t handle, const pisco_problem_t* prob,
@@ -380,12 +383,15 @@ pisco_status_t pisco_gx(pisco_handle_t handle, const pisco_problem_t* prob,
   if ((st = block_of(p, o, &b, &err))) return fail(h, st, err.c_str());
   if (!basis || !counts || !G || !ws || !aligned(ws))
     return fail(h, PISCO_ERR_ARG, "null or unaligned pointer");
-  if (ws_bytes < layout_gx(p, b, nullptr, nullptr))
+  if (ws_bytes < ws_stage(p, b, PISCO_STAGE_GX))
     return fail(h, PISCO_ERR_WORKSPACE, "workspace too small for pisco_gx");
   if (o.precision < PISCO_PREC_FP32 || o.precision > PISCO_PREC_SPLIT_BF16)
     return fail(h, PISCO_ERR_ARG, "unknown precision");
-  return run_gx(h, p, b, o.precision, static_cast<const double2*>(basis), counts,
-                static_cast<float2*>(G), ws);
+  Tables t;
+  void* scratch = nullptr;
+  if ((st = stage_prologue(h, p, PISCO_STAGE_GX, ws, &t, &scratch))) return st;
+  return run_gx(h, p, t, b, o.precision, static_cast<const double2*>(basis), counts,
+                static_cast<float2*>(G), scratch);
 }
 
 pisco_status_t pisco_eig(pisco_handle_t handle, int32_t Q, int64_t N, float bound,
@@ -434,10 +440,43 @@ pisco_status_t pisco_maps(pisco_handle_t handle, const pisco_problem_t* prob,
   if (o.phase_rule != 0 && o.phase_rule != 1) return fail(h, PISCO_ERR_ARG, "bad phase rule");
   if (!acs || !maps_lr || !maps_out || !ws || !aligned(ws))
     return fail(h, PISCO_ERR_ARG, "null or unaligned pointer");
-  if (ws_bytes < layout_maps(p, nullptr, nullptr))
+  if (ws_bytes < ws_stage(p, 0, PISCO_STAGE_MAPS))
     return fail(h, PISCO_ERR_WORKSPACE, "workspace too small for pisco_maps");
-  return run_maps(h, p, o.phase_rule, static_cast<const float2*>(acs),
-                  static_cast<const float2*>(maps_lr), static_cast<float2*>(maps_out), ws);
+  Tables t;
+  void* scratch = nullptr;
+  if ((st = stage_prologue(h, p, PISCO_STAGE_MAPS, ws, &t, &scratch))) return st;
+  return run_maps(h, p, t, o.phase_rule, static_cast<const float2*>(acs),
+                  static_cast<const float2*>(maps_lr), static_cast<float2*>(maps_out), scratch);
+}
+
+pisco_status_t pisco_support_mask(pisco_handle_t handle, const pisco_problem_t* prob,
+                                  const float* lam_min, float thresh, uint8_t* mask, void* ws,
+                                  size_t ws_bytes) {
+  Handle* h = reinterpret_cast<Handle*>(handle);
+  Plan p;
+  pisco_status_t st = check_common(h, prob, &p);
+  if (st) return st;
+  if (!lam_min || !mask || !ws || !aligned(ws))
+    return fail(h, PISCO_ERR_ARG, "null or unaligned pointer");
+  if (!(thresh > 0.f) || !(thresh < 1.f)) return fail(h, PISCO_ERR_ARG, "thresh must be in (0, 1)");
+  if (ws_bytes < ws_stage(p, 0, PISCO_STAGE_MASK))
+    return fail(h, PISCO_ERR_WORKSPACE, "workspace too small for pisco_support_mask");
+  Tables t;
+  void* scratch = nullptr;
+  if ((st = stage_prologue(h, p, PISCO_STAGE_MASK, ws, &t, &scratch))) return st;
+  return run_support_mask(h, p, t, lam_min, float(p.L), thresh, mask, scratch);
+}
+
+pisco_status_t pisco_espirit_operator(pisco_handle_t handle, int32_t Q, int64_t N, float bound,
+                                      const void* G, void* B) {
+  Handle* h = reinterpret_cast<Handle*>(handle);
+  if (!h) return PISCO_ERR_ARG;
+  if (Q < 2 || Q > kMaxQ) return fail(h, PISCO_ERR_ARG, "Q must be in [2, 32]");
+  if (N < 0) return fail(h, PISCO_ERR_ARG, "N must be >= 0");
+  if (!(bound > 0.f)) return fail(h, PISCO_ERR_ARG, "bound must be positive");
+  if (N > 0 && (!G || !B)) return fail(h, PISCO_ERR_ARG, "null pointer");
+  return run_espirit_operator(h, Q, N, bound, static_cast<const float2*>(G),
+                              static_cast<float2*>(B));
 }
 
 pisco_status_t pisco_estimate(pisco_handle_t handle, const pisco_problem_t* prob,
@@ -584,10 +623,11 @@ pisco_status_t pisco_batch_create(pisco_handle_t handle, int32_t B, const pisco_
   }
   // every run of a slice checks that its block fits the slice's region
   auto run = [&](const BatchSlice& x, Handle* hh, int bb, int fixed, int waves,
-                 int32_t** counts) -> pisco_status_t {
+                 int32_t** counts, bool tables_ready = false) -> pisco_status_t {
     if (bb > x.bmax || estimate_ws_size(x.p, bb) > x.ws_bytes)
       return fail(h, PISCO_ERR_WORKSPACE, "batch: block exceeds the slice's workspace region");
-    return estimate_core(hh, x.p, x.o, bb, x.acs, x.out, x.lam, x.ws, fixed, waves, counts);
+    return estimate_core(hh, x.p, x.o, bb, x.acs, x.out, x.lam, x.ws, fixed, waves, counts,
+                         tables_ready);
   };
   uint32_t saved = 0, flags = 0, tune_flags = 0;
   if ((st = take_flags(h, &saved))) return st;
@@ -708,7 +748,6 @@ pisco_status_t pisco_batch_create(pisco_handle_t handle, int32_t B, const pisco_
       sh->host_pinned = h->host_pinned;
       sh->host_ctl = h->host_ctl;
       sh->host_ctl_dev = h->host_ctl_dev;
-      sh->table_owner = h;
       bt->sub.push_back(sh);
     }
   }
@@ -727,7 +766,9 @@ pisco_status_t pisco_batch_create(pisco_handle_t handle, int32_t B, const pisco_
   for (int k = 1; k < S && e == hipSuccess; ++k) e = hipStreamWaitEvent(bt->streams[k], bt->events[0], 0);
   for (int i = 0; i < B && e == hipSuccess && !st; ++i) {
     const BatchSlice& x = bt->slices[i];
-    st = run(x, bt->sub[i % S], x.b, x.products, x.ax_waves, nullptr);
+    // the slice's planning run built its tables in its region (at the front
+    // of the layout, whatever the block): the graph does not rebuild them
+    st = run(x, bt->sub[i % S], x.b, x.products, x.ax_waves, nullptr, true);
   }
   for (int k = 1; k < S && e == hipSuccess; ++k) {
     e = hipEventRecord(bt->events[k], bt->streams[k]);

@@ -79,19 +79,7 @@ struct Handle {
   std::vector<TraceRec> records;
   // autotuner results per problem shape: nullspace block and product waves
   std::map<std::string, std::pair<int, int>> tuned;
-  // plan-constant device tables (DFT and sinc matrices, support lists, index
-  // maps) keyed by their exact parameters; freed by pisco_destroy.  A batch's
-  // per-stream handles use their parent's (table_owner).
-  std::map<std::string, void*> tables;
-  Handle* table_owner = nullptr;
 };
-
-// A handle-owned device table of `bytes` bytes identified by `key`: on first
-// use it is allocated, filled by `build` (kernels on the handle's stream)
-// and the stream synchronised, so that any later stream may read it.  A
-// first use while the stream is being captured is refused.
-pisco_status_t cached_table(Handle* h, const std::string& key, size_t bytes, void** out,
-                            const std::function<pisco_status_t(void*)>& build);
 
 // Brackets one kernel launch with events when tracing is on and the kernel
 // name contains the filter.
@@ -201,6 +189,37 @@ struct GxWs {
 };
 size_t layout_gx(const Plan& p, int b, void* ws, GxWs* out);
 
+// Plan-constant tables (functions of the sizes alone), carved from the
+// caller's workspace and built by one kernel in stream order by the call
+// that uses them, so that no call allocates or synchronises.
+//   sup    : int4 [L], support offsets (z, y, x, 0) in the library's order
+//   boxmap : int [box^D], support-box cell -> support index (-1 outside)
+//   M1[d]  : float2 [K_d][2 tau + 1]  filter spectra  e^{+i 2 pi n f / K_d}
+//   M3[d]  : float2 [B_d][K_d]        lags from spectra (1/K_d) e^{+i 2 pi m f / K_d}
+//   M4[d]  : float2 [lr_d][B_d]       low-res evaluation e^{-i 2 pi m x}
+//   Ma[d]  : double2 [lr_d][A_d]      apodized low-res image (FP64)
+//   Ms[d]  : float2 [out_d][lr_d]     periodic sinc interpolation
+//   Ms64[d]: double2 [out_d][lr_d]    the same in FP64 (support mask)
+// Dimensions d that the problem does not use (z for D = 2) stay null.
+struct Tables {
+  int4* sup = nullptr;
+  int* boxmap = nullptr;
+  float2* M1[3] = {nullptr, nullptr, nullptr};
+  float2* M3[3] = {nullptr, nullptr, nullptr};
+  float2* M4[3] = {nullptr, nullptr, nullptr};
+  double2* Ma[3] = {nullptr, nullptr, nullptr};
+  float2* Ms[3] = {nullptr, nullptr, nullptr};
+  double2* Ms64[3] = {nullptr, nullptr, nullptr};
+};
+// Which tables a call needs (bit mask).
+constexpr unsigned kTabSupport = 1u, kTabGx = 2u, kTabMaps = 4u, kTabMask = 8u;
+constexpr unsigned kTabAll = kTabSupport | kTabGx | kTabMaps;
+// Carves the tables of `which` from `ws` (sizes only when ws is null);
+// returns the bytes used.
+size_t layout_tables(const Plan& p, unsigned which, void* ws, Tables* out);
+// Builds the tables of `which` (one kernel launch).
+pisco_status_t build_tables(Handle* h, const Plan& p, unsigned which, const Tables& t);
+
 struct MapsWs {
   double2* rho;    // [Q][Nlr] apodized low-res images (FP64)
   double2* rtA;    // FP64 scratch of the apodized passes
@@ -215,8 +234,10 @@ size_t layout_maps(const Plan& p, void* ws, MapsWs* out);
 
 // ------------------------------------------------------------------ stage launchers
 
-pisco_status_t run_gram(Handle* h, const Plan& p, const float2* acs, float2* gram,
-                        void* ws);
+// support_ws (nullable): region of L int4 where the support list is built in
+// stream order instead of taken from the handle's table.
+pisco_status_t run_gram(Handle* h, const Plan& p, const Tables& t, const float2* acs,
+                        float2* gram, void* ws);
 // fixed_products > 0: that many products and one Rayleigh-Ritz step, no host
 // read-back (graph-capturable); 0: adaptive schedule with host reads.
 // ax_waves: wave count targeted by the split-K product (0 = 2048).
@@ -232,24 +253,35 @@ pisco_status_t run_nullspace(Handle* h, const Plan& p, int b, int max_iters,
                              int ax_waves = 0,
                              const std::function<pisco_status_t()>* downstream = nullptr,
                              bool* downstream_queued = nullptr);
-pisco_status_t run_gx(Handle* h, const Plan& p, int b, int precision, const double2* basis,
-                      const int32_t* counts, float2* G, void* ws);
+pisco_status_t run_gx(Handle* h, const Plan& p, const Tables& t, int b, int precision,
+                      const double2* basis, const int32_t* counts, float2* G, void* ws);
 // lam64 / res64 (nullable): FP64 Rayleigh quotient and residual of the
 // FP32 result, computed from the FP32 G widened to FP64.
 pisco_status_t run_eig(Handle* h, int Q, long long N, float bound, int iters,
                        float tol, const float2* G, const float2* init, float2* maps,
                        float* lam, int32_t* it_out, double* lam64 = nullptr,
                        double* res64 = nullptr);
-pisco_status_t run_maps(Handle* h, const Plan& p, int phase_rule, const float2* acs,
-                        const float2* maps_lr, float2* maps_out, void* ws);
+pisco_status_t run_maps(Handle* h, const Plan& p, const Tables& t, int phase_rule,
+                        const float2* acs, const float2* maps_lr, float2* maps_out, void* ws);
+
+// Support mask (FP64 interpolation of lambda_min / bound, thresholded) and
+// the ESPIRiT operator B = I - G / bound on packed planes.
+size_t layout_mask(const Plan& p, void* ws, double2** t0, double2** t1, double2** t2);
+pisco_status_t run_support_mask(Handle* h, const Plan& p, const Tables& t, const float* lam,
+                                float bound, float thresh, uint8_t* mask, void* ws);
+pisco_status_t run_espirit_operator(Handle* h, int Q, long long N, float bound,
+                                    const float2* G, float2* B);
 
 // The whole path for one problem on h's stream (pisco_estimate's body);
 // fixed_products / ax_waves as for run_nullspace; counts_out (nullable)
 // receives the device address of the nullspace counts in `ws`.
 size_t estimate_ws_size(const Plan& p, int b);
+// tables_ready: the tables in `ws` were built by an earlier run with the
+// same problem and block (a batch's captured graph skips rebuilding them).
 pisco_status_t estimate_core(Handle* h, const Plan& p, const pisco_opts_t& o, int b,
                              const float2* acs, float2* maps_out, float* lam_min, void* ws,
-                             int fixed_products, int ax_waves, int32_t** counts_out = nullptr);
+                             int fixed_products, int ax_waves, int32_t** counts_out = nullptr,
+                             bool tables_ready = false);
 
 // Eigen-decomposition H = U diag(theta) U^H of a b x b Hermitian matrix
 // (column-major, FP64), eigenvalues descending, 1 <= b <= 1024; `ws` holds
@@ -265,30 +297,12 @@ pisco_status_t axis_transform(Handle* h, const float2* in, float2* out,
                               const int shape_in[4], int axis, int nout,
                               const float2* M);
 
-// Matrix builders (float2, row-major [nout][nin]) for axis_transform:
-//   build_dft : M[o][i] = scale * g(i) * exp(i sign 2 pi (i - ci)(o - co) / period),
-//               g(i) = exp(-(i - ci)^2 / (2 sigma^2)) if sigma > 0 else 1
-//   build_sinc: periodic sinc interpolation n_in -> n_out centred samples
-pisco_status_t build_dft(Handle* h, float2* M, int nout, int nin, int co, int ci,
-                         double period, double sign, double scale, double sigma);
-pisco_status_t build_dft(Handle* h, double2* M, int nout, int nin, int co, int ci,
-                         double period, double sign, double scale, double sigma);
 // FP64 variants of axis_transform (input FP32 or FP64, output and matrix FP64)
 pisco_status_t axis_transform64(Handle* h, const float2* in, double2* out,
                                 const int shape_in[4], int axis, int nout, const double2* M);
 pisco_status_t axis_transform64(Handle* h, const double2* in, double2* out,
                                 const int shape_in[4], int axis, int nout, const double2* M);
-pisco_status_t build_sinc(Handle* h, float2* M, int nout, int nin);
 
-// Writes the support offsets (z, y, x, 0) into `out` on the device.
-// Handle-cached (plan-constant) tables: the builders above and the support
-// list of |Lambda| = L points (cached_table); valid until pisco_destroy.
-pisco_status_t dft_table(Handle* h, const float2** M, int nout, int nin, int co, int ci,
-                         double period, double sign, double scale, double sigma);
-pisco_status_t dft_table(Handle* h, const double2** M, int nout, int nin, int co, int ci,
-                         double period, double sign, double scale, double sigma);
-pisco_status_t sinc_table(Handle* h, const float2** M, int nout, int nin);
-pisco_status_t support_table(Handle* h, const int4** out, int D, float radius, int L);
 
 inline pisco_status_t hip_check(Handle* h, hipError_t e, const char* what) {
   if (e == hipSuccess) return PISCO_OK;

@@ -110,19 +110,6 @@ __device__ inline void map_thread(const PassGeom& g, int* ln, int* bt) {
   }
 }
 
-__global__ void k_support(int4* out, int D, float radius) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  const int t = int(floorf(radius));
-  const double r2 = double(radius) * double(radius);
-  const int zlo = (D == 3) ? -t : 0, zhi = (D == 3) ? t : 0;
-  int c = 0;
-  for (int z = zlo; z <= zhi; ++z)
-    for (int y = -t; y <= t; ++y)
-      for (int x = -t; x <= t; ++x)
-        if (double(z) * z + double(y) * y + double(x) * x <= r2)
-          out[c++] = make_int4(z, y, x, 0);
-}
-
 // ---------------------------------------------------------------- forward passes
 
 // x pass: lines (q, az, ay) of the ACS, zero-padded to F2 -> S1[q][az][ay][F2]
@@ -298,32 +285,17 @@ __global__ void __launch_bounds__(256) k_gather(const float2* __restrict__ R,
   gram[size_t(r) * n + c] = v;
 }
 
-pisco_status_t support_table(Handle* h, const int4** out, int D, float radius, int L) {
-  char key[64];
-  std::snprintf(key, sizeof key, "support %d %.9g", D, double(radius));
-  void* p = nullptr;
-  pisco_status_t st = cached_table(h, key, sizeof(int4) * size_t(L), &p, [&](void* q) {
-    PISCO_KERNEL(h, k_support, dim3(1), dim3(64), 0, static_cast<int4*>(q), D, radius);
-    return PISCO_OK;
-  });
-  *out = static_cast<const int4*>(p);
-  return st;
-}
-
 static unsigned blocks_for(const PassGeom& g) { return ceil_div(g.nlines, g.lpb); }
 
-pisco_status_t run_gram(Handle* h, const Plan& p, const float2* acs, float2* gram,
-                        void* ws) {
+pisco_status_t run_gram(Handle* h, const Plan& p, const Tables& t, const float2* acs,
+                        float2* gram, void* ws) {
   GramWs w;
   layout_gram(p, ws, &w);
   const int Q = p.Q, P = p.P;
   const int A0 = p.acs[0], A1 = p.acs[1], A2 = p.acs[2];
   const int F0 = p.F[0], F1 = p.F[1], F2 = p.F[2];
   const int B0 = p.B[0], B1 = p.B[1], B2 = p.B[2];
-
-  const int4* support = nullptr;
-  pisco_status_t sst = support_table(h, &support, p.D, p.radius, p.L);
-  if (sst) return sst;
+  const int4* support = t.sup;
 
   // forward: x, y, (z)
   float2* S1 = w.S;                                   // [Q][A0][A1][F2]

@@ -23,23 +23,6 @@
 
 namespace pisco {
 
-// dense map from support-box cell to support index (-1 outside Lambda)
-__global__ void k_box_map(const int4* __restrict__ sup, int L, int* __restrict__ map,
-                          int tz, int tau, int By, int Bx, int ncell) {
-  const int c = blockIdx.x * 256 + threadIdx.x;
-  if (c >= ncell) return;
-  const int bz = c / (By * Bx), rem = c - bz * By * Bx, by = rem / Bx, bx = rem - by * Bx;
-  int found = -1;
-  for (int i = 0; i < L; ++i) {
-    const int4 n = sup[i];
-    if (n.x + tz == bz && n.y + tau == by && n.z + tau == bx) {
-      found = i;
-      break;
-    }
-  }
-  map[c] = found;
-}
-
 // box[r][q][cell] = v_r[q|Lambda| + i(cell)] for r < r_s, else 0 (FP64 -> FP32)
 __global__ void k_scatter_box(const double2* __restrict__ basis,
                               const int32_t* __restrict__ counts, const int* __restrict__ map,
@@ -294,46 +277,19 @@ static pisco_status_t chain(Handle* h, const float2* in, float2* out, int shape[
   return st;
 }
 
-pisco_status_t run_gx(Handle* h, const Plan& p, int b, int precision, const double2* basis,
-                      const int32_t* counts, float2* G, void* ws) {
+pisco_status_t run_gx(Handle* h, const Plan& p, const Tables& t, int b, int precision,
+                      const double2* basis, const int32_t* counts, float2* G, void* ws) {
   GxWs w;
   layout_gx(p, b, ws, &w);
   const int Q = p.Q, tau = p.tau, P = p.P;
   const int box = 2 * tau + 1;
-  const int Bz = p.D == 3 ? box : 1, tz = p.D == 3 ? tau : 0;
+  const int Bz = p.D == 3 ? box : 1;
   const int ncell = Bz * box * box;
   pisco_status_t st;
-  // plan-constant tables (built once per handle and problem shape)
-  const int4* support = nullptr;
-  if ((st = support_table(h, &support, p.D, p.radius, p.L))) return st;
-  const float2* M1[3] = {nullptr, nullptr, nullptr};
-  const float2* M3[3] = {nullptr, nullptr, nullptr};
-  const float2* M4[3] = {nullptr, nullptr, nullptr};
-  for (int d = 0; d < 3; ++d) {
-    const bool used = d > 0 || p.D == 3;
-    if (!used) continue;
-    const int Lk = p.K[d], Bd = p.B[d], lr = p.lr[d];
-    // filter spectra: e^{+i 2 pi n f / Lk}, n = box index - tau
-    if ((st = dft_table(h, &M1[d], Lk, box, 0, tau, Lk, +1.0, 1.0, 0.0))) return st;
-    // lags from spectra: (1/Lk) e^{+i 2 pi m f / Lk}, m = out index - 2 tau
-    if ((st = dft_table(h, &M3[d], Bd, Lk, 2 * tau, 0, Lk, +1.0, 1.0 / Lk, 0.0))) return st;
-    // low-res evaluation: e^{-i 2 pi m x}, x = (a - floor(N/2)) / N
-    if ((st = dft_table(h, &M4[d], lr, Bd, lr / 2, 2 * tau, lr, -1.0, 1.0, 0.0))) return st;
-  }
-  // support-box cell -> support index
-  const int* map = nullptr;
-  {
-    char key[96];
-    std::snprintf(key, sizeof key, "boxmap %d %.9g %d", p.D, double(p.radius), tau);
-    void* q = nullptr;
-    st = cached_table(h, key, sizeof(int) * size_t(ncell), &q, [&](void* t) {
-      PISCO_KERNEL(h, k_box_map, dim3(ceil_div(ncell, 256)), dim3(256), 0, support, p.L,
-                   static_cast<int*>(t), tz, tau, box, box, ncell);
-      return PISCO_OK;
-    });
-    if (st) return st;
-    map = static_cast<const int*>(q);
-  }
+  const float2* const* M1 = t.M1;
+  const float2* const* M3 = t.M3;
+  const float2* const* M4 = t.M4;
+  const int* map = t.boxmap;
   float2* bufA = w.Tmp;
   float2* bufB = w.Tmp + w.tmp_half;
   PISCO_KERNEL(h, k_scatter_box, dim3(ceil_div(1LL * b * Q * ncell, 256)), dim3(256), 0, basis, counts, map, bufA, p.n, p.L, Q, b, ncell);

@@ -121,24 +121,16 @@ __global__ void __launch_bounds__(256) k_rss(float2* __restrict__ c, int Q, long
     if (q < Q) c[size_t(q) * N + v] = cscale(x[q], inv);
 }
 
-pisco_status_t run_maps(Handle* h, const Plan& p, int phase_rule, const float2* acs,
-                        const float2* maps_lr, float2* maps_out, void* ws) {
+pisco_status_t run_maps(Handle* h, const Plan& p, const Tables& t, int phase_rule,
+                        const float2* acs, const float2* maps_lr, float2* maps_out, void* ws) {
   MapsWs w;
   layout_maps(p, ws, &w);
   const int Q = p.Q;
   const long long N = p.Nlr;
   pisco_status_t st;
-  const int first = p.D == 3 ? 0 : 1;
-  // plan-constant matrices (built once per handle and problem shape):
   // apodized DFT (acs -> lr, FP64) and sinc (lr -> out) per dimension
-  const double2* Ma[3] = {nullptr, nullptr, nullptr};
-  const float2* Ms[3] = {nullptr, nullptr, nullptr};
-  for (int d = first; d < 3; ++d) {
-    const int A = p.acs[d], n = p.lr[d];
-    if (phase_rule == 0)
-      if ((st = dft_table(h, &Ma[d], n, A, n / 2, A / 2, n, +1.0, 1.0, A / 4.0))) return st;
-    if ((st = sinc_table(h, &Ms[d], p.out[d], n))) return st;
-  }
+  const double2* const* Ma = t.Ma;
+  const float2* const* Ms = t.Ms;
   if (phase_rule == 0) {
     // rho~ = apodized low-res reconstruction in FP64: [Q][A0][A1][A2] -> [Q][lr]
     int sh[4] = {Q, p.acs[0], p.acs[1], p.acs[2]};

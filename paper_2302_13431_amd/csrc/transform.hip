@@ -167,123 +167,215 @@ pisco_status_t axis_transform64(Handle* h, const double2* in, double2* out,
   return axis_impl<double2, double2>(h, in, out, shape_in, axis, nout, M);
 }
 
-// ------------------------------------------------------------------ matrix builders
+// ------------------------------------------------------------------ plan-constant tables
 
-// M[o][i] = scale * w(i) * exp(i * sign * 2 pi * (i - ci) * (o - co) / period)
-// with w(i) = exp(-(i - ci)^2 / (2 sigma^2)) when sigma > 0, else 1.
-template <class TM>
-__global__ void k_build_dft(TM* M, int nout, int nin, int co, int ci, double period,
-                            double sign, double scale, double sigma) {
-  const int idx = blockIdx.x * 256 + threadIdx.x;
-  if (idx >= nout * nin) return;
-  const int o = idx / nin, i = idx - o * nin;
-  const long long prod = 1LL * (i - ci) * (o - co);
-  // reduce the phase exactly in integers before the trigonometric call
-  const long long per = (long long)llround(period);
-  double frac;
-  if (double(per) == period && per > 0) {
-    long long r = prod % per;
-    if (r < 0) r += per;
-    frac = double(r) / period;
-  } else {
-    frac = double(prod) / period;
-  }
-  double sn, cs;
-  sincospi(2.0 * sign * frac, &sn, &cs);
-  double w = scale;
-  if (sigma > 0.0) {
-    const double k = double(i - ci);
-    w *= exp(-k * k / (2.0 * sigma * sigma));
-  }
-  M[idx] = TM{static_cast<decltype(TM{}.x)>(w * cs), static_cast<decltype(TM{}.x)>(w * sn)};
+// One kernel builds every table a call needs: blockIdx.y selects the job,
+// the blocks of a row stride over its elements.
+//   dft  : M[o][i] = scale * w(i) * exp(i sign 2 pi (i - ci)(o - co) / period),
+//          w(i) = exp(-(i - ci)^2 / (2 sigma^2)) when sigma > 0, else 1
+//          (float2 or double2 entries)
+//   sinc : periodic sinc (Dirichlet) interpolation from nin to nout >= nin
+//          (float2 or double2 entries)
+//          centred samples, M[o][a] = (1/nin) sum_k w_k exp(i 2 pi k (y_o - x_a))
+//          over the centred band of nin frequencies, the -nin/2 term split
+//          in half onto +-nin/2 when nin is even and nout > nin
+//   support : the points n of the box with ||n||_2 <= radius, lexicographic
+//          (z slowest), as int4 (z, y, x, 0)
+//   boxmap : box cell -> index of its point in the support list, -1 outside;
+//          the index of an inside cell is the number of inside cells before
+//          it in the same lexicographic order
+enum TableKind { kTDft32 = 0, kTDft64 = 1, kTSinc32 = 2, kTSupport = 3, kTBoxMap = 4,
+                 kTSinc64 = 5 };
+constexpr int kMaxTableJobs = 20;
+struct TableJob {
+  int kind, nout, nin, co, ci;
+  double period, sign, scale, sigma;
+  void* out;
+};
+struct TableJobs {
+  TableJob job[kMaxTableJobs];
+  int count;
+  int D, tau, tz;  // support box: x, y in [-tau, tau], z in [-tz, tz]
+  double r2;       // radius^2
+};
+
+__device__ inline bool in_ball(int z, int y, int x, double r2) {
+  return double(z) * z + double(y) * y + double(x) * x <= r2;
 }
 
-// Periodic sinc (Dirichlet) interpolation from n_in to n_out >= n_in centred
-// samples: M[o][a] = (1/n_in) sum_k w_k exp(i 2 pi k (y_o - x_a)) over the
-// centred band of n_in frequencies, the -n_in/2 term split in half onto
-// +-n_in/2 when n_in is even and n_out > n_in.
-__global__ void k_build_sinc(float2* M, int nout, int nin) {
-  const int idx = blockIdx.x * 256 + threadIdx.x;
-  if (idx >= nout * nin) return;
+__device__ void dft_entry(const TableJob& j, int idx, double* re, double* im) {
+  const int o = idx / j.nin, i = idx - o * j.nin;
+  const long long prod = 1LL * (i - j.ci) * (o - j.co);
+  // the phase reduced exactly in integers before the trigonometric call
+  const long long per = (long long)llround(j.period);
+  double frac;
+  if (double(per) == j.period && per > 0) {
+    long long r = prod % per;
+    if (r < 0) r += per;
+    frac = double(r) / j.period;
+  } else {
+    frac = double(prod) / j.period;
+  }
+  double sn, cs;
+  sincospi(2.0 * j.sign * frac, &sn, &cs);
+  double w = j.scale;
+  if (j.sigma > 0.0) {
+    const double k = double(i - j.ci);
+    w *= exp(-k * k / (2.0 * j.sigma * j.sigma));
+  }
+  *re = w * cs;
+  *im = w * sn;
+}
+
+__device__ void sinc_entry(const TableJob& j, int idx, double* re, double* im) {
+  const int nout = j.nout, nin = j.nin;
   const int o = idx / nin, a = idx - o * nin;
   const int kmin = -(nin / 2), kmax = (nin + 1) / 2 - 1;
   const bool split = (nin % 2 == 0) && nout > nin;
   const double y = double(o - nout / 2) / double(nout);
   const double x = double(a - nin / 2) / double(nin);
-  double re = 0.0, im = 0.0;
+  double sr = 0.0, si = 0.0;
   for (int k = kmin; k <= kmax; ++k) {
     double sn, cs;
     sincospi(2.0 * double(k) * (y - x), &sn, &cs);
     const double w = (split && k == kmin) ? 0.5 : 1.0;
-    re += w * cs;
-    im += w * sn;
+    sr += w * cs;
+    si += w * sn;
   }
   if (split) {
     double sn, cs;
     sincospi(2.0 * double(nin / 2) * (y - x), &sn, &cs);
-    re += 0.5 * cs;
-    im += 0.5 * sn;
+    sr += 0.5 * cs;
+    si += 0.5 * sn;
   }
-  M[idx] = make_float2(float(re / nin), float(im / nin));
+  *re = sr / nin;
+  *im = si / nin;
 }
 
-pisco_status_t build_dft(Handle* h, float2* M, int nout, int nin, int co, int ci,
-                         double period, double sign, double scale, double sigma) {
-  PISCO_KERNEL(h, k_build_dft<float2>, dim3(ceil_div(nout * nin, 256)), dim3(256), 0, M, nout,
-               nin, co, ci, period, sign, scale, sigma);
+__global__ void __launch_bounds__(256) k_build_tables(TableJobs jobs) {
+  const TableJob& j = jobs.job[blockIdx.y];
+  const int box = 2 * jobs.tau + 1, bz = 2 * jobs.tz + 1;
+  const int ncell = bz * box * box;
+  int total = 0;
+  switch (j.kind) {
+    case kTSupport: total = 1; break;
+    case kTBoxMap: total = ncell; break;
+    default: total = j.nout * j.nin;
+  }
+  for (int idx = blockIdx.x * 256 + threadIdx.x; idx < total; idx += gridDim.x * 256) {
+    if (j.kind == kTDft32 || j.kind == kTDft64 || j.kind == kTSinc32 || j.kind == kTSinc64) {
+      double re, im;
+      if (j.kind == kTSinc32 || j.kind == kTSinc64)
+        sinc_entry(j, idx, &re, &im);
+      else
+        dft_entry(j, idx, &re, &im);
+      if (j.kind == kTDft64 || j.kind == kTSinc64)
+        static_cast<double2*>(j.out)[idx] = make_double2(re, im);
+      else
+        static_cast<float2*>(j.out)[idx] = make_float2(float(re), float(im));
+    } else if (j.kind == kTSupport) {
+      // sequential enumeration (one thread): the order is the definition
+      int c = 0;
+      int4* out = static_cast<int4*>(j.out);
+      for (int z = -jobs.tz; z <= jobs.tz; ++z)
+        for (int y = -jobs.tau; y <= jobs.tau; ++y)
+          for (int x = -jobs.tau; x <= jobs.tau; ++x)
+            if (in_ball(z, y, x, jobs.r2)) out[c++] = make_int4(z, y, x, 0);
+    } else {
+      const int cz = idx / (box * box), rem = idx - cz * box * box;
+      const int cy = rem / box, cx = rem - cy * box;
+      int v = -1;
+      if (in_ball(cz - jobs.tz, cy - jobs.tau, cx - jobs.tau, jobs.r2)) {
+        v = 0;
+        for (int e = 0; e < idx; ++e) {
+          const int ez = e / (box * box), er = e - ez * box * box;
+          const int ey = er / box, ex = er - ey * box;
+          v += in_ball(ez - jobs.tz, ey - jobs.tau, ex - jobs.tau, jobs.r2) ? 1 : 0;
+        }
+      }
+      static_cast<int*>(j.out)[idx] = v;
+    }
+  }
+}
+
+size_t layout_tables(const Plan& p, unsigned which, void* ws, Tables* out) {
+  Carver c(ws);
+  Tables t;
+  const int first = p.D == 3 ? 0 : 1;
+  const int box = 2 * p.tau + 1;
+  if (which & (kTabSupport | kTabGx)) t.sup = c.take<int4>(p.L);
+  if (which & kTabGx) {
+    t.boxmap = c.take<int>(size_t(p.D == 3 ? box : 1) * box * box);
+    for (int d = first; d < 3; ++d) {
+      t.M1[d] = c.take<float2>(size_t(p.K[d]) * box);
+      t.M3[d] = c.take<float2>(size_t(p.B[d]) * p.K[d]);
+      t.M4[d] = c.take<float2>(size_t(p.lr[d]) * p.B[d]);
+    }
+  }
+  if (which & kTabMaps) {
+    for (int d = first; d < 3; ++d) {
+      t.Ma[d] = c.take<double2>(size_t(p.lr[d]) * p.acs[d]);
+      t.Ms[d] = c.take<float2>(size_t(p.out[d]) * p.lr[d]);
+    }
+  }
+  if (which & kTabMask)
+    for (int d = first; d < 3; ++d) t.Ms64[d] = c.take<double2>(size_t(p.out[d]) * p.lr[d]);
+  if (out) *out = t;
+  return c.used + 256;
+}
+
+pisco_status_t build_tables(Handle* h, const Plan& p, unsigned which, const Tables& t) {
+  TableJobs jobs{};
+  jobs.D = p.D;
+  jobs.tau = p.tau;
+  jobs.tz = p.D == 3 ? p.tau : 0;
+  jobs.r2 = double(p.radius) * double(p.radius);
+  int maxel = 1;
+  auto add = [&](int kind, void* out, int nout, int nin, int co, int ci, double period,
+                 double sign, double scale, double sigma) {
+    TableJob& j = jobs.job[jobs.count++];
+    j.kind = kind;
+    j.out = out;
+    j.nout = nout;
+    j.nin = nin;
+    j.co = co;
+    j.ci = ci;
+    j.period = period;
+    j.sign = sign;
+    j.scale = scale;
+    j.sigma = sigma;
+    const int n = kind == kTSupport ? 1 : nout * nin;
+    maxel = n > maxel ? n : maxel;
+  };
+  const int first = p.D == 3 ? 0 : 1;
+  const int tau = p.tau, box = 2 * tau + 1;
+  if (t.sup && (which & (kTabSupport | kTabGx))) add(kTSupport, t.sup, 1, 1, 0, 0, 1, 0, 0, 0);
+  if (which & kTabGx) {
+    add(kTBoxMap, t.boxmap, (p.D == 3 ? box : 1) * box, box, 0, 0, 1, 0, 0, 0);
+    for (int d = first; d < 3; ++d) {
+      const int Lk = p.K[d], Bd = p.B[d], lr = p.lr[d];
+      // filter spectra: e^{+i 2 pi n f / Lk}, n = box index - tau
+      add(kTDft32, t.M1[d], Lk, box, 0, tau, Lk, +1.0, 1.0, 0.0);
+      // lags from spectra: (1/Lk) e^{+i 2 pi m f / Lk}, m = out index - 2 tau
+      add(kTDft32, t.M3[d], Bd, Lk, 2 * tau, 0, Lk, +1.0, 1.0 / Lk, 0.0);
+      // low-res evaluation: e^{-i 2 pi m x}, x = (a - floor(N/2)) / N
+      add(kTDft32, t.M4[d], lr, Bd, lr / 2, 2 * tau, lr, -1.0, 1.0, 0.0);
+    }
+  }
+  if (which & kTabMaps) {
+    for (int d = first; d < 3; ++d) {
+      const int A = p.acs[d], n = p.lr[d];
+      // apodized reconstruction on the low-res grid, Gaussian of width A/4
+      add(kTDft64, t.Ma[d], n, A, n / 2, A / 2, n, +1.0, 1.0, A / 4.0);
+      add(kTSinc32, t.Ms[d], p.out[d], n, 0, 0, 1, 0, 0, 0);
+    }
+  }
+  if (which & kTabMask)
+    for (int d = first; d < 3; ++d) add(kTSinc64, t.Ms64[d], p.out[d], p.lr[d], 0, 0, 1, 0, 0, 0);
+  if (jobs.count == 0) return PISCO_OK;
+  const unsigned gx = ceil_div(maxel, 256) < 64 ? ceil_div(maxel, 256) : 64;
+  PISCO_KERNEL(h, k_build_tables, dim3(gx, jobs.count), dim3(256), 0, jobs);
   return PISCO_OK;
-}
-
-pisco_status_t build_dft(Handle* h, double2* M, int nout, int nin, int co, int ci,
-                         double period, double sign, double scale, double sigma) {
-  PISCO_KERNEL(h, k_build_dft<double2>, dim3(ceil_div(nout * nin, 256)), dim3(256), 0, M, nout,
-               nin, co, ci, period, sign, scale, sigma);
-  return PISCO_OK;
-}
-
-pisco_status_t build_sinc(Handle* h, float2* M, int nout, int nin) {
-  PISCO_KERNEL(h, k_build_sinc, dim3(ceil_div(nout * nin, 256)), dim3(256), 0, M, nout, nin);
-  return PISCO_OK;
-}
-
-namespace {
-template <class T>
-pisco_status_t dft_table_t(Handle* h, const T** M, const char* tag, int nout, int nin, int co,
-                           int ci, double period, double sign, double scale, double sigma) {
-  char key[192];
-  std::snprintf(key, sizeof key, "%s %d %d %d %d %.17g %.17g %.17g %.17g", tag, nout, nin, co,
-                ci, period, sign, scale, sigma);
-  void* p = nullptr;
-  pisco_status_t st = cached_table(h, key, sizeof(T) * size_t(nout) * nin, &p,
-                                   [&](void* q) {
-                                     return build_dft(h, static_cast<T*>(q), nout, nin, co, ci,
-                                                      period, sign, scale, sigma);
-                                   });
-  *M = static_cast<const T*>(p);
-  return st;
-}
-}  // namespace
-
-pisco_status_t dft_table(Handle* h, const float2** M, int nout, int nin, int co, int ci,
-                         double period, double sign, double scale, double sigma) {
-  return dft_table_t(h, M, "dft32", nout, nin, co, ci, period, sign, scale, sigma);
-}
-
-pisco_status_t dft_table(Handle* h, const double2** M, int nout, int nin, int co, int ci,
-                         double period, double sign, double scale, double sigma) {
-  return dft_table_t(h, M, "dft64", nout, nin, co, ci, period, sign, scale, sigma);
-}
-
-pisco_status_t sinc_table(Handle* h, const float2** M, int nout, int nin) {
-  char key[64];
-  std::snprintf(key, sizeof key, "sinc %d %d", nout, nin);
-  void* p = nullptr;
-  pisco_status_t st = cached_table(h, key, sizeof(float2) * size_t(nout) * nin, &p,
-                                   [&](void* q) {
-                                     return build_sinc(h, static_cast<float2*>(q), nout, nin);
-                                   });
-  *M = static_cast<const float2*>(p);
-  return st;
 }
 
 }  // namespace pisco

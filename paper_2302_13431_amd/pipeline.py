@@ -45,7 +45,7 @@ class Estimator:
         self.Nlr = _prod(self.grid_lr)
         self.Nout = _prod(self.grid_out)
         dev = torch.device("cuda")
-        ws_stage = max(L.pisco_workspace_size(self.prob, self.opts, s) for s in range(1, 6))
+        ws_stage = max(L.pisco_workspace_size(self.prob, self.opts, s) for s in range(1, 7))
         self.ws_stage = torch.empty(ws_stage + 256, dtype=torch.uint8, device=dev)
         self.ws_all = None
         self.dev = dev
@@ -131,6 +131,23 @@ class Estimator:
         L.pisco_maps(self.h, self.prob, self.opts, acs.contiguous(), maps_lr.contiguous(), out,
                      self._ws())
         return out
+
+    def support_mask(self, lam, thresh: float = 0.1):
+        """uint8 mask on grid_out from a low-res lambda_min map (pisco_support_mask)."""
+        t = self.torch
+        mask = self._alloc(self.grid_out, t.uint8)
+        L.pisco_support_mask(self.h, self.prob, lam.contiguous(), thresh, mask, self._ws())
+        return mask
+
+    def espirit_operator(self, G, Q: Optional[int] = None, N: Optional[int] = None,
+                         bound: Optional[float] = None):
+        """B = I - G / |Lambda| in G's packed layout (pisco_espirit_operator)."""
+        Q = self.Q if Q is None else int(Q)
+        N = self.Nlr if N is None else int(N)
+        bound = float(self.nsup) if bound is None else float(bound)
+        B = self.torch.empty_like(G)
+        L.pisco_espirit_operator(self.h, Q, N, bound, G.contiguous(), B)
+        return B
 
     def estimate(self, acs, out=None, lam=None):
         t = self.torch
