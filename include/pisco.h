@@ -152,6 +152,26 @@ pisco_status_t pisco_gram(pisco_handle_t handle, const pisco_problem_t* prob,
                           const void* acs, void* gram, void* workspace,
                           size_t workspace_bytes);
 
+/* pisco_gram for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation):
+ * the same kernels and results as pisco_gram, with no workspace argument.
+ * Scratch comes from a library-owned static device array of
+ * pisco_gram_static_bytes' `limit` bytes (64 MiB), one per GPU, held until
+ * the process ends; its address is resolved at pisco_create (or at the first
+ * call on another device).  The call allocates nothing and builds no handle
+ * table (the support list is rebuilt in the scratch on every call).
+ * Problems whose scratch need exceeds the limit are rejected with
+ * PISCO_ERR_UNSUPPORTED before any launch.  Every call on a GPU shares that
+ * GPU's array: calls that may overlap on one GPU (other streams, other
+ * handles, other threads) race and must be serialised by the caller. */
+pisco_status_t pisco_gram_static(pisco_handle_t handle, const pisco_problem_t* prob,
+                                 const void* acs, void* gram);
+
+/* Scratch bytes pisco_gram_static needs for `prob`, and the library's limit
+ * (either pointer may be NULL).  Host-only. */
+pisco_status_t pisco_gram_static_bytes(const pisco_problem_t* prob, size_t* bytes,
+                                       size_t* limit);
+
 /* Signal/null split of the Gram (Sec. III-A/B; threshold from the footnote
  * of Sec. III-B).  FP64 block subspace iteration with Rayleigh-Ritz on the
  * FP32 Gram widened exactly to FP64.  The filters h_r of the paper are the

@@ -68,6 +68,9 @@ _SIGS = {
     "pisco_nullspace_block": ([ctypes.POINTER(Problem), ctypes.POINTER(Opts),
                                ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
     "pisco_gram": ([_P, ctypes.POINTER(Problem), _P, _P, _P, ctypes.c_size_t], ctypes.c_int),
+    "pisco_gram_static": ([_P, ctypes.POINTER(Problem), _P, _P], ctypes.c_int),
+    "pisco_gram_static_bytes": ([ctypes.POINTER(Problem), ctypes.POINTER(ctypes.c_size_t),
+                                 ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
     "pisco_support_mask": ([_P, ctypes.POINTER(Problem), _P, ctypes.c_float, _P, _P,
                             ctypes.c_size_t], ctypes.c_int),
     "pisco_espirit_operator": ([_P, ctypes.c_int32, ctypes.c_int64, ctypes.c_float, _P, _P],
@@ -235,6 +238,20 @@ class Handle:
 def pisco_gram(h: Handle, prob: Problem, acs, gram, ws):
     _check(lib().pisco_gram(h.h, ctypes.byref(prob), _ptr(acs), _ptr(gram), _ptr(ws),
                             ws.numel() * ws.element_size()), "pisco_gram", h.h)
+
+
+def pisco_gram_static(h: Handle, prob: Problem, acs, gram):
+    """pisco_gram with the library's static scratch (no workspace argument)."""
+    _check(lib().pisco_gram_static(h.h, ctypes.byref(prob), _ptr(acs), _ptr(gram)),
+           "pisco_gram_static", h.h)
+
+
+def pisco_gram_static_bytes(prob: Problem):
+    """(scratch bytes needed, library limit) of pisco_gram_static."""
+    need, limit = ctypes.c_size_t(), ctypes.c_size_t()
+    _check(lib().pisco_gram_static_bytes(ctypes.byref(prob), ctypes.byref(need),
+                                         ctypes.byref(limit)), "pisco_gram_static_bytes")
+    return need.value, limit.value
 
 
 def pisco_nullspace(h: Handle, prob: Problem, opts: Opts, gram, eigvals, basis, counts, ws):

@@ -235,6 +235,15 @@ pisco_status_t pisco_create(pisco_handle_t* handle, void* stream) {
     delete h;
     return PISCO_ERR_HIP;
   }
+  // resolve the static scratch of pisco_gram_static on the current device
+  void* scratch_ptr = nullptr;
+  if (gram_scratch_address(h, &scratch_ptr) != PISCO_OK) {
+    (void)hipHostFree(h->host_ctl);
+    (void)hipHostFree(h->host_pinned);
+    (void)hipFree(h->status_dev);
+    delete h;
+    return PISCO_ERR_HIP;
+  }
   *handle = reinterpret_cast<pisco_handle_t>(h);
   return PISCO_OK;
 }
@@ -349,6 +358,28 @@ pisco_status_t pisco_gram(pisco_handle_t handle, const pisco_problem_t* prob, co
   void* scratch = nullptr;
   if ((st = stage_prologue(h, p, PISCO_STAGE_GRAM, ws, &t, &scratch))) return st;
   return run_gram(h, p, t, static_cast<const float2*>(acs), static_cast<float2*>(gram), scratch);
+}
+
+pisco_status_t pisco_gram_static(pisco_handle_t handle, const pisco_problem_t* prob,
+                                 const void* acs, void* gram) {
+  Handle* h = reinterpret_cast<Handle*>(handle);
+  Plan p;
+  pisco_status_t st = check_common(h, prob, &p);
+  if (st) return st;
+  if (!acs || !gram) return fail(h, PISCO_ERR_ARG, "null pointer");
+  return run_gram_static(h, p, static_cast<const float2*>(acs), static_cast<float2*>(gram));
+}
+
+pisco_status_t pisco_gram_static_bytes(const pisco_problem_t* prob, size_t* bytes,
+                                       size_t* limit) {
+  if (!bytes && !limit) return PISCO_ERR_ARG;
+  Plan p;
+  std::string err;
+  pisco_status_t st = make_plan(prob, &p, &err);
+  if (st) return st;
+  if (bytes) *bytes = gram_static_bytes(p);
+  if (limit) *limit = kGramScratchBytes;
+  return PISCO_OK;
 }
 
 pisco_status_t pisco_nullspace(pisco_handle_t handle, const pisco_problem_t* prob,

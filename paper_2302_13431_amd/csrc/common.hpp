@@ -238,6 +238,14 @@ size_t layout_maps(const Plan& p, void* ws, MapsWs* out);
 // stream order instead of taken from the handle's table.
 pisco_status_t run_gram(Handle* h, const Plan& p, const Tables& t, const float2* acs,
                         float2* gram, void* ws);
+// The Gram with the library's static per-device scratch (kGramScratchBytes)
+// as workspace: no allocation; calls that overlap on one GPU race.
+constexpr size_t kGramScratchBytes = size_t(64) << 20;
+constexpr int kMaxDevices = 64;
+size_t gram_static_bytes(const Plan& p);
+pisco_status_t run_gram_static(Handle* h, const Plan& p, const float2* acs, float2* gram);
+// Per-device address of that scratch (resolved once per device).
+pisco_status_t gram_scratch_address(Handle* h, void** out);
 // fixed_products > 0: that many products and one Rayleigh-Ritz step, no host
 // read-back (graph-capturable); 0: adaptive schedule with host reads.
 // ax_waves: wave count targeted by the split-K product (0 = 2048).

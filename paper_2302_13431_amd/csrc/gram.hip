@@ -13,10 +13,45 @@
 // LDS; the forward passes skip the zero padding on input and the inverse passes
 // keep only the 4 tau + 1 lags per dimension on output.
 #include <cstdio>
+#include <mutex>
 
 #include "common.hpp"
 
 namespace pisco {
+
+// Library-owned scratch of pisco_gram_static (for callers that cannot
+// allocate): one copy per GPU, held until the process ends.  Host code uses
+// the per-device address from hipGetSymbolAddress, never the array's name.
+static __device__ __align__(256) char scratch[kGramScratchBytes];
+
+namespace {
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+pisco_status_t gram_scratch_address(Handle* h, void** out) {
+  *out = nullptr;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_check(h, e, "scratch: current device");
+  if (dev < 0 || dev >= kMaxDevices) {
+    if (h) h->last_error = "scratch: device index out of range";
+    return PISCO_ERR_UNSUPPORTED;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_check(h, e, "scratch: symbol address");
+    if (!ptr) {
+      if (h) h->last_error = "scratch: null symbol address";
+      return PISCO_ERR_HIP;
+    }
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return PISCO_OK;
+}
 
 // In-LDS radix-2 Stockham FFT of LPB lines of length L, stored line-major in
 // `a` (scratch `b` of the same size).  Thread t handles butterfly `bt` of line
@@ -329,6 +364,30 @@ pisco_status_t run_gram(Handle* h, const Plan& p, const Tables& t, const float2*
   dim3 gg(ceil_div(p.n, 256), p.n);
   PISCO_KERNEL(h, k_gather, gg, dim3(256), 0, w.R, support, gram, Q, p.L, B0, B1, B2, p.nlag);
   return PISCO_OK;
+}
+
+size_t gram_static_bytes(const Plan& p) {
+  return ((layout_gram(p, nullptr, nullptr) + 255) & ~size_t(255)) +
+         layout_tables(p, kTabSupport, nullptr, nullptr);
+}
+
+pisco_status_t run_gram_static(Handle* h, const Plan& p, const float2* acs, float2* gram) {
+  const size_t need = gram_static_bytes(p);
+  if (need > kGramScratchBytes) {
+    h->last_error = "pisco_gram_static: problem needs " + std::to_string(need) +
+                    " bytes of scratch, more than the library's " +
+                    std::to_string(kGramScratchBytes);
+    return PISCO_ERR_UNSUPPORTED;
+  }
+  void* base = nullptr;
+  pisco_status_t st = gram_scratch_address(h, &base);
+  if (st) return st;
+  char* c = static_cast<char*>(base);
+  const size_t off = (layout_gram(p, nullptr, nullptr) + 255) & ~size_t(255);
+  Tables t;
+  layout_tables(p, kTabSupport, c + off, &t);
+  if ((st = build_tables(h, p, kTabSupport, t))) return st;
+  return run_gram(h, p, t, acs, gram, c);
 }
 
 }  // namespace pisco
