@@ -94,7 +94,14 @@ typedef struct {
   int32_t precision;    /* arithmetic of the G(x) contraction over the signal
                            vectors: PISCO_PREC_FP32, or matrix cores with FP32
                            accumulation and split operands (PISCO_PREC_SPLIT_*) */
+  int32_t schedule;     /* nullspace schedule: PISCO_SCHED_AUTO or
+                           PISCO_SCHED_DEVICE (see pisco_nullspace) */
 } pisco_opts_t;
+
+/* Nullspace schedules (pisco_opts_t.schedule). */
+#define PISCO_SCHED_AUTO   0  /* adaptive (host reads control words) outside
+                                 stream capture, device-resident under capture */
+#define PISCO_SCHED_DEVICE 1  /* device-resident: never reads back on the host */
 
 /* Precision choices (pisco_opts_t.precision). */
 #define PISCO_PREC_FP32       0  /* FP32 arithmetic */
@@ -185,7 +192,21 @@ pisco_status_t pisco_gram_static_bytes(const pisco_problem_t* prob, size_t* byte
  *             row, orthonormal; the first counts[0] span the signal space
  *   counts  : int32 [4] written on the device: {r_signal, block,
  *             iterations used, 1 if converged else 0}
- * `block` is opts->block or the automatic size (pisco_nullspace_block). */
+ * `block` is opts->block or the automatic size (pisco_nullspace_block).
+ *
+ * Schedule.  After three products (each orthonormalised) the Cholesky
+ * diagonal predicts how many more products the Rayleigh-Ritz step needs and
+ * sets the Chebyshev filter of the later chains.
+ *  - Adaptive (PISCO_SCHED_AUTO outside capture): the host waits on events
+ *    for that prediction and for the result of each Rayleigh-Ritz step (a
+ *    step that does not converge schedules more products).  This call then
+ *    blocks until those control words are written; it cannot be captured.
+ *  - Device-resident (PISCO_SCHED_DEVICE, or AUTO while the stream is being
+ *    captured): min(16, max_subspace_iters) products are enqueued in fixed
+ *    chains with one Rayleigh-Ritz step after the last; the device turns the
+ *    leading surplus products into block copies, so the step follows as many
+ *    products as predicted.  Nothing is read back; a result that has not
+ *    converged by the last product raises PISCO_FLAG_NOT_CONVERGED. */
 pisco_status_t pisco_nullspace(pisco_handle_t handle,
                                const pisco_problem_t* prob,
                                const pisco_opts_t* opts, const void* gram,

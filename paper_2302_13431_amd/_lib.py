@@ -26,6 +26,7 @@ FLAG_ZERO_DATA = 0x8
 
 STAGE_ALL, STAGE_GRAM, STAGE_NULLSPACE, STAGE_GX, STAGE_EIG, STAGE_MAPS, STAGE_MASK = range(7)
 PREC_FP32, PREC_SPLIT_F16, PREC_SPLIT_BF16 = 0, 1, 2
+SCHED_AUTO, SCHED_DEVICE = 0, 1
 
 
 class Problem(ctypes.Structure):
@@ -37,7 +38,8 @@ class Problem(ctypes.Structure):
 class Opts(ctypes.Structure):
     _fields_ = [("power_iters", ctypes.c_int32), ("tol", ctypes.c_float),
                 ("phase_rule", ctypes.c_int32), ("block", ctypes.c_int32),
-                ("max_subspace_iters", ctypes.c_int32), ("precision", ctypes.c_int32)]
+                ("max_subspace_iters", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("schedule", ctypes.c_int32)]
 
 
 class TraceEntry(ctypes.Structure):
@@ -146,11 +148,12 @@ def make_problem(D: int, Q: int, acs: Sequence[int], radius: float, grid_lr: Seq
 
 
 def make_opts(power_iters: int = 10, tol: float = 0.0, phase_rule: int = 0, block: int = 0,
-              max_subspace_iters: int = 60, precision: int = PREC_FP32) -> Opts:
+              max_subspace_iters: int = 60, precision: int = PREC_FP32,
+              schedule: int = 0) -> Opts:
     o = Opts()
     o.power_iters, o.tol, o.phase_rule = int(power_iters), float(tol), int(phase_rule)
     o.block, o.max_subspace_iters = int(block), int(max_subspace_iters)
-    o.precision = int(precision)
+    o.precision, o.schedule = int(precision), int(schedule)
     return o
 
 

@@ -18,6 +18,7 @@ pisco_opts_t default_opts() {
   o.block = 0;
   o.max_subspace_iters = 60;
   o.precision = PISCO_PREC_FP32;
+  o.schedule = PISCO_SCHED_AUTO;
   return o;
 }
 
@@ -162,6 +163,26 @@ namespace pisco {
 
 size_t estimate_ws_size(const Plan& p, int b) { return est_layout(p, b, nullptr).total; }
 
+pisco_status_t choose_schedule(Handle* h, const pisco_opts_t& o, int* device_products) {
+  *device_products = 0;
+  if (o.schedule != PISCO_SCHED_AUTO && o.schedule != PISCO_SCHED_DEVICE) {
+    h->last_error = "unknown nullspace schedule";
+    return PISCO_ERR_ARG;
+  }
+  bool device = o.schedule == PISCO_SCHED_DEVICE;
+  if (!device) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    const hipError_t e = hipStreamIsCapturing(h->stream, &cs);
+    if (e != hipSuccess) return hip_check(h, e, "schedule: capture query");
+    device = cs != hipStreamCaptureStatusNone;
+  }
+  if (device) {
+    const int cap = o.max_subspace_iters < kDeviceProducts ? o.max_subspace_iters : kDeviceProducts;
+    *device_products = cap < 4 ? 4 : cap;
+  }
+  return PISCO_OK;
+}
+
 pisco_status_t estimate_core(Handle* h, const Plan& p, const pisco_opts_t& o, int b,
                              const float2* acs, float2* maps_out, float* lam_min, void* ws,
                              int fixed_products, int ax_waves, int32_t** counts_out,
@@ -169,17 +190,8 @@ pisco_status_t estimate_core(Handle* h, const Plan& p, const pisco_opts_t& o, in
   EstLayout e = est_layout(p, b, ws);
   if (counts_out) *counts_out = e.counts;
   pisco_status_t st;
-  if (fixed_products <= 0) {
-    // refused before anything is enqueued (see run_nullspace)
-    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-    const hipError_t ce = hipStreamIsCapturing(h->stream, &cs);
-    if (ce != hipSuccess) return hip_check(h, ce, "estimate capture query");
-    if (cs != hipStreamCaptureStatusNone) {
-      h->last_error = "the adaptive nullspace schedule reads control words on the host and "
-                      "cannot be captured; use a fixed product count";
-      return PISCO_ERR_UNSUPPORTED;
-    }
-  }
+  int device_products = 0;
+  if (fixed_products <= 0 && (st = choose_schedule(h, o, &device_products))) return st;
   if (!tables_ready && (st = build_tables(h, p, kTabAll, e.tabs))) return st;
   if ((st = run_gram(h, p, e.tabs, acs, e.gram, e.stage_ws))) return st;
   float* lam = lam_min ? lam_min : e.lam;
@@ -194,7 +206,8 @@ pisco_status_t estimate_core(Handle* h, const Plan& p, const pisco_opts_t& o, in
   };
   bool queued = false;
   if ((st = run_nullspace(h, p, b, o.max_subspace_iters, e.gram, e.eigvals, e.basis, e.counts,
-                          e.null_ws, fixed_products, ax_waves, &later, &queued)))
+                          e.null_ws, fixed_products, ax_waves, &later, &queued,
+                          device_products)))
     return st;
   return queued ? PISCO_OK : later();
 }
@@ -397,8 +410,10 @@ pisco_status_t pisco_nullspace(pisco_handle_t handle, const pisco_problem_t* pro
     return fail(h, PISCO_ERR_ARG, "null or unaligned pointer");
   if (ws_bytes < layout_null(p, b, nullptr, nullptr))
     return fail(h, PISCO_ERR_WORKSPACE, "workspace too small for pisco_nullspace");
+  int device_products = 0;
+  if ((st = choose_schedule(h, o, &device_products))) return st;
   return run_nullspace(h, p, b, o.max_subspace_iters, static_cast<const float2*>(gram), eigvals,
-                       static_cast<double2*>(basis), counts, ws);
+                       static_cast<double2*>(basis), counts, ws, 0, 0, nullptr, nullptr, device_products);
 }
 
 pisco_status_t pisco_gx(pisco_handle_t handle, const pisco_problem_t* prob,

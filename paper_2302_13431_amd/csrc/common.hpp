@@ -174,7 +174,7 @@ struct NullWs {
   double* filt;    // [12] Chebyshev filter coefficients: steps 1 and 2, the next product
   double* resid;   // [b]
   double2* part;   // row-chunk partials of the b x b products; residual partials
-  int* ctl;        // [8] control words
+  int* ctl;        // [16] control words, then the device-resident schedule
   double* jac;     // Cholesky scratch (global-memory fallback) [b*(b+1)*2]
   double* heev;    // eigen-decomposition scratch [heev_workspace_doubles(b)]
 };
@@ -260,7 +260,13 @@ pisco_status_t run_nullspace(Handle* h, const Plan& p, int b, int max_iters,
                              int32_t* counts, void* ws, int fixed_products = 0,
                              int ax_waves = 0,
                              const std::function<pisco_status_t()>* downstream = nullptr,
-                             bool* downstream_queued = nullptr);
+                             bool* downstream_queued = nullptr, int device_products = 0);
+// Products the device-resident schedule enqueues (the cap on the products
+// it can run): at most kDeviceProducts, fewer when max_iters is smaller.
+constexpr int kDeviceProducts = 16;
+// Schedule of a nullspace call: device_products for run_nullspace (0 =
+// adaptive host-read schedule), or an error when that schedule is refused.
+pisco_status_t choose_schedule(Handle* h, const pisco_opts_t& o, int* device_products);
 pisco_status_t run_gx(Handle* h, const Plan& p, const Tables& t, int b, int precision,
                       const double2* basis, const int32_t* counts, float2* G, void* ws);
 // lam64 / res64 (nullable): FP64 Rayleigh quotient and residual of the

@@ -125,7 +125,8 @@ __global__ void __launch_bounds__(64 * kKS) __attribute__((amdgpu_waves_per_eu(2
                                                       const double2* __restrict__ X,
                                                       double2* out, int n, int b, int kchunk,
                                                       const double* __restrict__ coef,
-                                                      const double2* prev) {
+                                                      const double2* prev,
+                                                      const int* __restrict__ role) {
   __shared__ double2 red[kKS > 1 ? kKS * 32 * 33 : 1];
   const int l = threadIdx.x & 63;
   const int z = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -143,6 +144,20 @@ __global__ void __launch_bounds__(64 * kKS) __attribute__((amdgpu_waves_per_eu(2
     const int tile = xcd * base + (xcd < extra ? xcd : extra) + slot;
     r0 = (tile / nty) * 32;
     c0 = (tile % nty) * 32;
+  }
+  if (role) {
+    // device-resident schedule: the slot's role is decided on the device
+    // (0: skipped, the block is copied so that the buffers keep their
+    // roles; 1: first step of a chain, coef[0..2]; 2: later step, coef[3..5])
+    const int r = __builtin_amdgcn_readfirstlane(*role);
+    if (r == 0) {
+      for (int e = threadIdx.x; e < 32 * 32; e += 64 * kKS) {
+        const int row = e & 31, col = e >> 5;
+        if (r0 + row < n) out[size_t(c0 + col) * n + r0 + row] = X[size_t(c0 + col) * n + r0 + row];
+      }
+      return;
+    }
+    if (r == 2) coef += 3;
   }
   const int kbeg = z * kchunk;
   const int kend = min(n, kbeg + kchunk);
@@ -271,7 +286,8 @@ __global__ void __launch_bounds__(64 * kKS) __attribute__((amdgpu_waves_per_eu(2
 // workgroups of one wave spread the few thousand elements over many CUs.
 __global__ void __launch_bounds__(64) k_sum_parts(const double2* __restrict__ parts,
                                                   double2* __restrict__ out, long long len,
-                                                  int nparts) {
+                                                  int nparts, const int* __restrict__ skip) {
+  if (skip && *skip) return;
   constexpr int kU = 24;
   const long long i = blockIdx.x * 64LL + threadIdx.x;
   if (i >= len) return;
@@ -299,8 +315,9 @@ __global__ void __launch_bounds__(64) k_sum_parts(const double2* __restrict__ pa
 __global__ void __launch_bounds__(64) k_gemm_tn(const double2* __restrict__ P,
                                                 const double2* __restrict__ Qm,
                                                 double2* __restrict__ part, int n, int b,
-                                                int upper) {
+                                                int upper, const int* __restrict__ skip) {
   if (upper && blockIdx.x > blockIdx.y) return;
+  if (skip && *skip) return;
   const int l = threadIdx.x, li = l & 15, lk = l >> 4;
   const int i0 = blockIdx.x * 16, j0 = blockIdx.y * 16;
   const int rbeg = blockIdx.z * kTnRows, rend = min(n, rbeg + kTnRows);
@@ -378,9 +395,17 @@ __global__ void __launch_bounds__(64) k_gemm_tn(const double2* __restrict__ P,
 __global__ void __launch_bounds__(64) k_gemm_nn(const double2* __restrict__ Pm,
                                                 const double2* __restrict__ M,
                                                 double2* __restrict__ Y, int m, int k,
-                                                int b, int tri) {
+                                                int b, int tri, const int* __restrict__ copy) {
   const int l = threadIdx.x, li = l & 15, lk = l >> 4;
   const int r0 = blockIdx.x * 16, c0 = blockIdx.y * 16;
+  if (copy && *copy) {
+    // skipped orthonormalisation (k == b): Y = P, so the buffers keep their roles
+    for (int e = l; e < 256; e += 64) {
+      const int row = r0 + (e & 15), col = c0 + (e >> 4);
+      if (row < m) Y[size_t(col) * m + row] = Pm[size_t(col) * m + row];
+    }
+    return;
+  }
   const bool v = r0 + li < m;
   const int kend = tri ? min(k, c0 + 16) : k;
   const double2* Mc = M + size_t(c0 + li) * k;
@@ -483,7 +508,9 @@ __global__ void __launch_bounds__(kCholThreads) k_chol(const double2* __restrict
                                                double* __restrict__ dsc_out,
                                                double2* __restrict__ gwork,
                                                int* __restrict__ flag,
-                                               double* __restrict__ rdiag) {
+                                               double* __restrict__ rdiag,
+                                               const int* __restrict__ skip) {
+  if (skip && *skip) return;
   constexpr int kNB = 8;                        // panel height (b is a multiple)
   constexpr int kNT = kCholThreads;
   constexpr int kCols = 64 - kNB;               // later columns per wave and group
@@ -656,7 +683,9 @@ constexpr int kTriStageMax = 128;  // largest b staged in LDS
 template <int kRows, bool kStage>
 __global__ void __launch_bounds__(64 * kTriWaves) k_tri_inv(const double2* __restrict__ R,
                                                             const double* __restrict__ dsc,
-                                                            double2* __restrict__ M, int b) {
+                                                            double2* __restrict__ M, int b,
+                                                            const int* __restrict__ skip) {
+  if (skip && *skip) return;
   constexpr int kMaxB = 64 * kRows;  // b <= kMaxB (at most kTriStageMax when staged)
   constexpr int kStep = kRows <= 4 ? 8 : 32 / kRows;  // steps per register batch
   __shared__ double2 tri[kStage ? kMaxB * (kMaxB - 1) / 2 : 1];
@@ -779,7 +808,8 @@ __global__ void __launch_bounds__(256) k_colresid(const double2* __restrict__ Y,
 //   ctl[5] = plain steps predicted before the next Rayleigh-Ritz
 __global__ void k_control(const double* __restrict__ theta, const double* __restrict__ rpart,
                           int nchunks, int b, double thr2, double tol, int margin, int iter,
-                          int* ctl, unsigned* status, int* host_ctl) {
+                          int* ctl, unsigned* status, int* host_ctl,
+                          const int* __restrict__ sched) {
   // one wave: the counts by ballot, the largest residual by lane shuffles
   const int t = threadIdx.x;
   const double t0 = theta[0];
@@ -806,7 +836,7 @@ __global__ void k_control(const double* __restrict__ theta, const double* __rest
   const int too_small = rs > b - margin;
   ctl[0] = rs;
   ctl[1] = (finite && !zero && worst <= tol * t0 && !too_small) ? 1 : 0;
-  ctl[2] = iter + 1;
+  ctl[2] = iter + 1 - (sched ? sched[0] : 0);  // products run (skipped slots excluded)
   ctl[3] = too_small;
   ctl[4] = zero;
   // iterations predicted to reach the tolerance at rate theta_b / theta_rs
@@ -847,8 +877,23 @@ __global__ void k_control(const double* __restrict__ theta, const double* __rest
 // by 1 / rho without the filter.  The prediction aims ten times below the
 // tolerance, since a Rayleigh-Ritz step that fails costs several products.
 // ctl[6] = products until (and including) the one the step is taken on.
+// Device-resident schedule (plan.nslots > 0): the products between the
+// third and the last one are enqueued in advance as slots in fixed chains;
+// the first S = nslots - (ctl[6] - 1) slots are skipped (their product and,
+// for a chain with no product left, its orthonormalisation copy the block
+// instead), so that the step is taken after as many products as predicted.
+// sched[0] = S, sched[1 + j] = role of slot j (0 skipped, 1 first step of
+// its chain, 2 later step), sched[1 + kMaxSlots + j] = 1 when the chain
+// ending at slot j is skipped entirely.
+constexpr int kMaxSlots = 60;
+struct SlotPlan {
+  int nslots;
+  signed char pos[kMaxSlots];   // position of the slot in its chain
+};
+
 __global__ void k_predict(const double* __restrict__ d, int b, double thr2, double tol, int* ctl,
-                          double* __restrict__ coef, int* host_ctl) {
+                          double* __restrict__ coef, int* host_ctl, SlotPlan plan,
+                          int* __restrict__ sched) {
   const int t = threadIdx.x;  // one wave: the count by ballot, the rest in lane 0
   int r = 0;
   for (int k0 = 0; k0 < b; k0 += 64) {
@@ -889,6 +934,15 @@ __global__ void k_predict(const double* __restrict__ d, int b, double thr2, doub
   // that the host can enqueue it before it reads the schedule
   const bool plain = ctl[6] <= 1;
   for (int k = 0; k < 3; ++k) coef[6 + k] = plain ? (k == 0 ? 1.0 : 0.0) : f[k];
+  if (sched && plan.nslots > 0) {
+    int S = plan.nslots - (ctl[6] - 1);
+    S = S < 0 ? 0 : (S > plan.nslots ? plan.nslots : S);
+    sched[0] = S;
+    for (int j = 0; j < plan.nslots; ++j) {
+      sched[1 + j] = j < S ? 0 : ((plan.pos[j] == 0 || j - 1 < S) ? 1 : 2);
+      sched[1 + kMaxSlots + j] = j < S ? 1 : 0;
+    }
+  }
   if (host_ctl) {
     host_ctl[6] = ctl[6];
     __threadfence_system();
@@ -932,26 +986,28 @@ struct NullCtx {
   NullWs w;
 };
 
+// skip (device word, nullable): the orthonormalisation of a skipped chain
 pisco_status_t gemm_tn(NullCtx& c, const double2* P, const double2* Qm, double2* out, int rows,
-                       bool upper = false) {
+                       bool upper = false, const int* skip = nullptr) {
   const int b = c.b;
   const int chunks = int(ceil_div(rows, kTnRows));
   dim3 g(ceil_div(b, 16), ceil_div(b, 16), chunks);
-  PISCO_KERNEL(c.h, k_gemm_tn, g, dim3(64), 0, P, Qm, c.w.part, rows, b, upper ? 1 : 0);
+  PISCO_KERNEL(c.h, k_gemm_tn, g, dim3(64), 0, P, Qm, c.w.part, rows, b, upper ? 1 : 0, skip);
   const long long len = 1LL * b * b;
-  PISCO_KERNEL(c.h, k_sum_parts, dim3(ceil_div(len, 64)), dim3(64), 0, c.w.part, out, len, chunks);
+  PISCO_KERNEL(c.h, k_sum_parts, dim3(ceil_div(len, 64)), dim3(64), 0, c.w.part, out, len, chunks,
+               skip);
   return PISCO_OK;
 }
 
 pisco_status_t gemm_nn(NullCtx& c, const double2* P, const double2* M, double2* Y, int m,
-                       int k, bool tri = false) {
+                       int k, bool tri = false, const int* copy = nullptr) {
   dim3 g(ceil_div(m, 16), ceil_div(c.b, 16));
-  PISCO_KERNEL(c.h, k_gemm_nn, g, dim3(64), 0, P, M, Y, m, k, c.b, tri ? 1 : 0);
+  PISCO_KERNEL(c.h, k_gemm_nn, g, dim3(64), 0, P, M, Y, m, k, c.b, tri ? 1 : 0, copy);
   return PISCO_OK;
 }
 
 pisco_status_t chol_inv(NullCtx& c, const double2* S, double shift, double2* M,
-                        double* rdiag = nullptr) {
+                        double* rdiag = nullptr, const int* skip = nullptr) {
   const int b = c.b;
   if (b % 8 != 0 || b > 1024) {
     c.h->last_error = "nullspace: block size must be a multiple of 8, at most 1024";
@@ -960,21 +1016,21 @@ pisco_status_t chol_inv(NullCtx& c, const double2* S, double shift, double2* M,
   int* flag = c.w.ctl + 8;
   if (b <= kCholLdsMax)
     PISCO_KERNEL(c.h, k_chol<true>, dim3(1), dim3(kCholThreads), 0, S, b, shift, c.w.R,
-                 c.w.dsc, reinterpret_cast<double2*>(c.w.jac), flag, rdiag);
+                 c.w.dsc, reinterpret_cast<double2*>(c.w.jac), flag, rdiag, skip);
   else
     PISCO_KERNEL(c.h, k_chol<false>, dim3(1), dim3(kCholThreads), 0, S, b, shift, c.w.R,
-                 c.w.dsc, reinterpret_cast<double2*>(c.w.jac), flag, rdiag);
+                 c.w.dsc, reinterpret_cast<double2*>(c.w.jac), flag, rdiag, skip);
   const dim3 tg(ceil_div(b, kTriWaves)), tb(64 * kTriWaves);
   if (b <= 64)
-    PISCO_KERNEL(c.h, (k_tri_inv<1, true>), tg, tb, 0, c.w.R, c.w.dsc, M, b);
+    PISCO_KERNEL(c.h, (k_tri_inv<1, true>), tg, tb, 0, c.w.R, c.w.dsc, M, b, skip);
   else if (b <= kTriStageMax)
-    PISCO_KERNEL(c.h, (k_tri_inv<2, true>), tg, tb, 0, c.w.R, c.w.dsc, M, b);
+    PISCO_KERNEL(c.h, (k_tri_inv<2, true>), tg, tb, 0, c.w.R, c.w.dsc, M, b, skip);
   else if (b <= 256)
-    PISCO_KERNEL(c.h, (k_tri_inv<4, false>), tg, tb, 0, c.w.R, c.w.dsc, M, b);
+    PISCO_KERNEL(c.h, (k_tri_inv<4, false>), tg, tb, 0, c.w.R, c.w.dsc, M, b, skip);
   else if (b <= 512)
-    PISCO_KERNEL(c.h, (k_tri_inv<8, false>), tg, tb, 0, c.w.R, c.w.dsc, M, b);
+    PISCO_KERNEL(c.h, (k_tri_inv<8, false>), tg, tb, 0, c.w.R, c.w.dsc, M, b, skip);
   else
-    PISCO_KERNEL(c.h, (k_tri_inv<16, false>), tg, tb, 0, c.w.R, c.w.dsc, M, b);
+    PISCO_KERNEL(c.h, (k_tri_inv<16, false>), tg, tb, 0, c.w.R, c.w.dsc, M, b, skip);
   return PISCO_OK;
 }
 
@@ -983,12 +1039,14 @@ pisco_status_t chol_inv(NullCtx& c, const double2* S, double shift, double2* M,
 // diagonal) keeps the factorisation from breaking down on the first
 // product, whose columns may be nearly dependent; a block that is not yet
 // orthonormal to rounding is fine there, the next products correct it.
-pisco_status_t orth(NullCtx& c, const double2* Y, double2* tmp, double* rdiag, double shift) {
+// skip (device word, nullable): when set, tmp = Y.
+pisco_status_t orth(NullCtx& c, const double2* Y, double2* tmp, double* rdiag, double shift,
+                    const int* skip = nullptr) {
   const int n = c.p->n, b = c.b;
   pisco_status_t st;
-  if ((st = gemm_tn(c, Y, Y, c.w.S, n, true))) return st;  // the factor reads the upper part
-  if ((st = chol_inv(c, c.w.S, shift, c.w.M, rdiag))) return st;
-  return gemm_nn(c, Y, c.w.M, tmp, n, b, true);
+  if ((st = gemm_tn(c, Y, Y, c.w.S, n, true, skip))) return st;  // the factor reads the upper part
+  if ((st = chol_inv(c, c.w.S, shift, c.w.M, rdiag, skip))) return st;
+  return gemm_nn(c, Y, c.w.M, tmp, n, b, true, skip);
 }
 
 }  // namespace
@@ -997,9 +1055,10 @@ pisco_status_t run_nullspace(Handle* h, const Plan& p, int b, int max_iters,
                              const float2* gram, double* eigvals, double2* basis,
                              int32_t* counts, void* ws, int fixed_products, int ax_waves,
                              const std::function<pisco_status_t()>* downstream,
-                             bool* downstream_queued) {
+                             bool* downstream_queued, int device_products) {
   if (downstream_queued) *downstream_queued = false;
-  if (fixed_products <= 0) {
+  const bool device = device_products > 0 && fixed_products <= 0;
+  if (fixed_products <= 0 && !device) {
     // the adaptive schedule waits on the host for control words the kernels
     // write: it cannot be recorded into a graph
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
@@ -1007,7 +1066,7 @@ pisco_status_t run_nullspace(Handle* h, const Plan& p, int b, int max_iters,
     if (e != hipSuccess) return hip_check(h, e, "nullspace capture query");
     if (cs != hipStreamCaptureStatusNone) {
       h->last_error = "the adaptive nullspace schedule reads control words on the host and "
-                      "cannot be captured; use a fixed product count";
+                      "cannot be captured; use the device-resident or a fixed schedule";
       return PISCO_ERR_UNSUPPORTED;
     }
   }
@@ -1039,23 +1098,29 @@ pisco_status_t run_nullspace(Handle* h, const Plan& p, int b, int max_iters,
   const int rchunks = int(ceil_div(n, 1024));
   // out = A in (the K slices of a tile summed in fixed order in LDS); with
   // step 1 or 2 the sum forms the first or a later step of the Chebyshev
-  // recurrence instead (prev = the previous block of the chain)
-  auto product = [&](const double2* in, double2* out, const double2* prev,
-                     int step) -> pisco_status_t {
+  // recurrence instead (prev = the previous block of the chain); with a
+  // role word (device-resident schedule) the step, or a copy, is decided on
+  // the device from coef = the filter's six coefficients
+  auto product = [&](const double2* in, double2* out, const double2* prev, int step,
+                     const int* role = nullptr) -> pisco_status_t {
     const dim3 g(ceil_div(n, 32), ceil_div(b, 32));
-    const double* coef = step ? c.w.filt + 3 * (step - 1) : nullptr;
+    const double* coef = role ? c.w.filt : (step ? c.w.filt + 3 * (step - 1) : nullptr);
     switch (ksplit) {
       case 8:
-        PISCO_KERNEL(h, k_gemm_ax<8>, g, dim3(512), 0, gram, in, out, n, b, kchunk, coef, prev);
+        PISCO_KERNEL(h, k_gemm_ax<8>, g, dim3(512), 0, gram, in, out, n, b, kchunk, coef, prev,
+                     role);
         break;
       case 4:
-        PISCO_KERNEL(h, k_gemm_ax<4>, g, dim3(256), 0, gram, in, out, n, b, kchunk, coef, prev);
+        PISCO_KERNEL(h, k_gemm_ax<4>, g, dim3(256), 0, gram, in, out, n, b, kchunk, coef, prev,
+                     role);
         break;
       case 2:
-        PISCO_KERNEL(h, k_gemm_ax<2>, g, dim3(128), 0, gram, in, out, n, b, kchunk, coef, prev);
+        PISCO_KERNEL(h, k_gemm_ax<2>, g, dim3(128), 0, gram, in, out, n, b, kchunk, coef, prev,
+                     role);
         break;
       default:
-        PISCO_KERNEL(h, k_gemm_ax<1>, g, dim3(64), 0, gram, in, out, n, b, kchunk, coef, prev);
+        PISCO_KERNEL(h, k_gemm_ax<1>, g, dim3(64), 0, gram, in, out, n, b, kchunk, coef, prev,
+                     role);
     }
     return PISCO_OK;
   };
@@ -1071,16 +1136,41 @@ pisco_status_t run_nullspace(Handle* h, const Plan& p, int b, int max_iters,
   // the host, so the whole call can be captured in a graph; the filter
   // coefficients stay on the device and convergence is still tested there,
   // reported through counts and the status.
+  // The device-resident schedule enqueues the fixed schedule of
+  // device_products products, and k_predict turns the leading products past
+  // the third (and the orthonormalisations of chains left empty) into copies,
+  // so that the Rayleigh-Ritz step follows as many products as it predicts.
   constexpr int kUnscheduled = 1 << 30;
-  const bool fixed = fixed_products > 0;
-  int rr_at = fixed ? (fixed_products < 3 ? 3 : fixed_products) : kUnscheduled;
+  const bool fixed = fixed_products > 0 || device;
+  const int nprod = device ? device_products : fixed_products;
+  int rr_at = fixed ? (nprod < 3 ? 3 : nprod) : kUnscheduled;
+  // device-resident schedule: chain position of every slot (products
+  // 4 .. rr_at - 1), the structure the loop below forms for rr_at
+  SlotPlan plan{};
+  int* sched = device ? c.w.ctl + 16 : nullptr;
+  if (device) {
+    int d = 3;
+    while (d + 1 < rr_at) {
+      int extra = rr_at - (d + 1) - 2;
+      extra = extra < 0 ? 0 : (extra > 2 ? 2 : extra);
+      for (int e = 0; e <= extra; ++e) {
+        if (plan.nslots >= kMaxSlots) break;
+        plan.pos[plan.nslots++] = static_cast<signed char>(e);
+      }
+      d += extra + 1;
+    }
+  }
   int done = 0;
   bool filtered = false;  // filter coefficients set
   bool queued = false;    // the next product is already enqueued
   while (true) {
     const bool rr_next = done + 1 >= rr_at || done + 1 >= max_iters;
     const bool chain = filtered && !rr_next;
-    if (!queued && (st = product(X, Z, nullptr, chain ? 1 : 0))) return st;
+    // slot of the device-resident schedule this product fills (-1: none)
+    const int slot = device && filtered && !rr_next ? done - 3 : -1;
+    if (!queued &&
+        (st = product(X, Z, nullptr, chain ? 1 : 0, slot >= 0 ? sched + 1 + slot : nullptr)))
+      return st;
     queued = false;
     ++done;
     if (done < rr_at && done < max_iters) {
@@ -1093,16 +1183,21 @@ pisco_status_t run_nullspace(Handle* h, const Plan& p, int b, int max_iters,
       }
       for (int e = 0; e < extra; ++e) {
         // next block of the chain, written over the previous one (in X)
-        if ((st = chain ? product(Z, X, X, 2) : product(Z, X, nullptr, 0))) return st;
+        const int sl = device ? done - 3 : -1;
+        if ((st = chain ? product(Z, X, X, 2, sl >= 0 ? sched + 1 + sl : nullptr)
+                        : product(Z, X, nullptr, 0)))
+          return st;
         std::swap(X, Z);
         ++done;
       }
       const bool at3 = done == 3 && !filtered;
-      if ((st = orth(c, Z, X, at3 ? c.w.resid : nullptr, done == 1 ? 1e-12 : 0.0)))
+      // the chain just formed ended at slot done - 4
+      const int* skip = device && done > 3 ? sched + 1 + kMaxSlots + (done - 4) : nullptr;
+      if ((st = orth(c, Z, X, at3 ? c.w.resid : nullptr, done == 1 ? 1e-12 : 0.0, skip)))
         return st;
       if (at3) {
         PISCO_KERNEL(h, k_predict, dim3(1), dim3(64), 0, c.w.resid, b, thr2, tol, c.w.ctl,
-                     c.w.filt, fixed ? nullptr : h->host_ctl_dev);
+                     c.w.filt, fixed ? nullptr : h->host_ctl_dev, plan, sched);
         filtered = true;
         if (!fixed) {
           // whatever the schedule, a product comes next: enqueued now with
@@ -1130,7 +1225,8 @@ pisco_status_t run_nullspace(Handle* h, const Plan& p, int b, int max_iters,
     double* rpart = reinterpret_cast<double*>(c.w.part);
     PISCO_KERNEL(h, k_colresid, dim3(rchunks, b), dim3(256), 0, X, W, c.w.theta, rpart, n, b);
     PISCO_KERNEL(h, k_control, dim3(1), dim3(64), 0, c.w.theta, rpart, rchunks, b, thr2, tol,
-                 margin, done - 1, c.w.ctl, h->status_dev, fixed ? nullptr : h->host_ctl_dev);
+                 margin, done - 1, c.w.ctl, h->status_dev, fixed ? nullptr : h->host_ctl_dev,
+                 sched);
     if (fixed) break;
     // Most steps are final: k_finalize and the caller's later stages go in
     // now and the host waits (on an event) for k_control alone.  When the

@@ -118,7 +118,9 @@ size_t layout_null(const Plan& p, int b, void* ws, NullWs* o) {
   const size_t rpart = ((size_t(p.n) + 1023) / 1024) * b;  // doubles
   if (rpart > 2 * part) part = (rpart + 1) / 2;
   w.part = c.take<double2>(part);
-  w.ctl = c.take<int>(16);
+  // control words [16], then the device-resident schedule (slot roles and
+  // chain skips, 1 + 2 * 60 words)
+  w.ctl = c.take<int>(16 + 128);
   w.jac = c.take<double>((size_t(b) + 1) * b * 2);
   w.heev = c.take<double>(heev_workspace_doubles(b));
   if (o) *o = w;

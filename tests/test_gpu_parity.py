@@ -407,30 +407,73 @@ def test_not_converged_is_flagged():
     assert counts[3] == 0
 
 
-def test_adaptive_schedule_refuses_capture():
-    """The adaptive schedule reads control words on the host: inside a graph
-    capture pisco_estimate must refuse before enqueuing anything."""
+@pytest.mark.parametrize("name", WLALL)
+def test_device_schedule_matches_oracle(name):
+    """The device-resident nullspace schedule (nothing read back on the host)
+    against the oracle, stage and end to end."""
     import paper_2302_13431_amd as P
-    w, acs = scan_inputs("2d_64x64_q8_acs24_r3")
-    est = estimator("2d_64x64_q8_acs24_r3")
+    _, _, _, g32, sp = oracle_gram_split(name)
+    est = estimator(name, schedule=P._lib.SCHED_DEVICE)
+    ev, basis, counts = est.nullspace(cuda(g32))
+    ev, basis, counts = ev.cpu().numpy(), basis.cpu().numpy(), counts.cpu().numpy()
+    rs = int(counts[0])
+    Vs = basis[:rs].T
+    e_proj = float(np.abs(Vs @ Vs.conj().T - sp.signal @ sp.signal.conj().T).max())
+    e_eig = float(np.abs(ev[:rs + 1] - sp.eigvals[:rs + 1]).max() / sp.eigvals[0])
+    ref = oracle_full(name)
+    w, acs = scan_inputs(name)
+    out, lam = est.estimate(cuda(acs))
+    out, lam = out.cpu().numpy(), lam.cpu().numpy()
+    mo = output_mask(lowres_mask(ref.c_lr, ref.rho_lr, None), w.grid)
+    e = map_error(ref.maps, out)
+    e_lam = float(np.abs(lam - ref.lam_min).max() / len(ref.lam))
+    report("device schedule " + name, products=int(counts[2]), r=rs, err_eig=e_eig,
+           err_proj=e_proj, err_lam=e_lam, err_map=float(e[mo].max()))
+    assert counts[3] == 1 and rs == sp.r_signal
+    assert e_eig <= 1e-5 and e_proj <= 1e-7
+    assert e_lam <= 1e-5 and float(e[mo].max()) <= 1e-4
+    assert est.status() == 0
+
+
+def test_estimate_captured_on_fresh_handle():
+    """pisco_estimate recorded into a HIP graph on a handle that has never
+    run (default schedule: device-resident under capture; tables built in
+    the workspace by the captured call itself), replayed three times with
+    eager work in between, each replay against the oracle."""
+    import paper_2302_13431_amd as P
+    name = "2d_256x256_q32_acs32_r5"
+    ref = oracle_full(name)
+    w, acs = scan_inputs(name)
+    est = estimator(name)
     x = cuda(acs)
-    est.estimate(x)  # tables and workspace exist before the capture
+    out = torch.empty((w.Q,) + tuple(w.grid), dtype=torch.complex64, device="cuda")
+    lam = torch.empty((int(np.prod(w.grid_lr)),), dtype=torch.float32, device="cuda")
+    size = P._lib.pisco_workspace_size(est.prob, est.opts, P._lib.STAGE_ALL)
+    raw = torch.empty(size + 256, dtype=torch.uint8, device="cuda")
+    ws = raw[(-raw.data_ptr()) % 256:]
     torch.cuda.synchronize()
     g = torch.cuda.CUDAGraph()
     s = torch.cuda.Stream()
-    err = None
-    with torch.cuda.stream(s):
-        est.h.set_stream(s)
-        try:
-            with torch.cuda.graph(g, stream=s):
-                try:
-                    est.estimate(x)
-                except P.PiscoError as e:
-                    err = e
-        finally:
-            est.h.set_stream(None)
-    torch.cuda.synchronize()
-    assert err is not None and err.status == 4
+    est.h.set_stream(s)
+    try:
+        with torch.cuda.graph(g, stream=s):
+            P.pisco_estimate(est.h, est.prob, est.opts, x, out, lam, ws)
+    finally:
+        est.h.set_stream(None)
+    mo = output_mask(lowres_mask(ref.c_lr, ref.rho_lr, None), w.grid)
+    bound = float(len(ref.lam))
+    for rep in range(3):
+        out.zero_()
+        lam.fill_(-1.0)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        o, l = out.cpu().numpy(), lam.cpu().numpy()
+        e = map_error(ref.maps, o)
+        e_lam = float(np.abs(l - ref.lam_min).max() / bound)
+        report(f"captured estimate replay {rep}", err_lam=e_lam, err_map=float(e[mo].max()))
+        assert est.status() == 0
+        assert e_lam <= 1e-5 and float(e[mo].max()) <= 1e-4
 
 
 def test_workspace_too_small_is_rejected():
