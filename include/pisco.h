@@ -78,7 +78,24 @@ typedef struct {
   int32_t grid_out[3];  /* output grid z, y, x; each >= grid_lr */
   float thresh;         /* nullspace rule sigma_n < thresh * sigma_1; 0.05 in the
                            paper (Sec. III-B footnote) */
+  int32_t shape;        /* kernel support: PISCO_SHAPE_ELLIPSOID (Sec. IV-B) or
+                           PISCO_SHAPE_RECTANGLE (the conventional support of
+                           Sec. III-C) */
+  int32_t gram_rows;    /* rows of C in the Gram: PISCO_ROWS_ALL (every row
+                           the data touch, samples outside the ACS taken as
+                           zero: the correlation form of Sec. IV-A) or
+                           PISCO_ROWS_VALID (only rows whose whole
+                           neighbourhood lies inside the ACS: no implicit
+                           zeros, the masked form Sec. IV-A neglects) */
 } pisco_problem_t;
+
+/* Support shapes (pisco_problem_t.shape). */
+#define PISCO_SHAPE_ELLIPSOID 0  /* { n : ||n||_2 <= radius } */
+#define PISCO_SHAPE_RECTANGLE 1  /* { n : ||n||_inf <= floor(radius) } */
+
+/* Gram rows (pisco_problem_t.gram_rows). */
+#define PISCO_ROWS_ALL   0
+#define PISCO_ROWS_VALID 1
 
 /* Options of the per-voxel solve and the nullspace iteration. */
 typedef struct {
@@ -135,10 +152,11 @@ const char* pisco_last_error(pisco_handle_t handle);
  * accumulated since the last call and clears them (host pointer `flags`). */
 pisco_status_t pisco_get_status(pisco_handle_t handle, uint32_t* flags);
 
-/* Kernel support (Sec. IV-B).  Host-only.  Writes |Lambda| to *count and,
- * when `offsets` (host, int32[3 * count], z y x per point) is non-null, the
- * offsets in the library's order.  Needs D in {2,3}, radius in [1, 12]. */
-pisco_status_t pisco_support(int32_t D, float radius, int32_t* count,
+/* Kernel support (Sec. IV-B; shape PISCO_SHAPE_*).  Host-only.  Writes
+ * |Lambda| to *count and, when `offsets` (host, int32[3 * count], z y x per
+ * point) is non-null, the offsets in the library's order.  Needs D in {2,3},
+ * radius in [1, 12]. */
+pisco_status_t pisco_support(int32_t D, float radius, int32_t shape, int32_t* count,
                              int32_t* offsets);
 
 /* Bytes of workspace needed by one stage (or by pisco_estimate when stage is
@@ -147,6 +165,11 @@ pisco_status_t pisco_workspace_size(const pisco_problem_t* prob,
                                     const pisco_opts_t* opts, int32_t stage,
                                     size_t* bytes);
 
+/* Calibration Gram C^H C.  With PISCO_ROWS_ALL by zero-padded FFT
+ * correlation (Sec. IV-A), as below; with PISCO_ROWS_VALID the rows of C
+ * whose neighbourhood n - Lambda lies inside the ACS (a box of
+ * prod_d (A_d - 2 floor(radius)) rows) are formed explicitly and C^H C is
+ * their FP32 product (the masked Gram, exactly Hermitian as well). */
 /* Calibration Gram C^H C by zero-padded FFT correlation (Sec. IV-A).
  *   acs  : float2 [Q][acs z][acs y][acs x], the Nyquist-sampled ACS block
  *   gram : float2 [n][n], n = Q |Lambda|, row-major; entry ((p,i),(q,j)) is

@@ -35,14 +35,22 @@ class Result:
 
 def estimate(acs: np.ndarray, radius: float, grid_lr, grid_out=None,
              thresh: float = 0.05, n_iter: int = 10, tol: float | None = None,
-             phase: str = "combined", shape: str = "ellipsoid") -> Result:
+             phase: str = "combined", shape: str = "ellipsoid",
+             rows: str = "full") -> Result:
+    """rows="full": the correlation Gram of Sec. IV-A (masking neglected,
+    = C_full^H C_full); rows="valid": C_valid^H C_valid from the explicit
+    rows of C with no implicit zeros (the masked form)."""
     acs = np.asarray(acs, dtype=np.complex128)
     Q = acs.shape[0]
     D = acs.ndim - 1
     lam = support.kernel_support(D, radius, shape)
     lags = support.difference_set(lam)
     R = calib.correlation_lags(acs, lags)
-    gram = calib.gram_from_lags(R, lam, lags)
+    if rows == "valid":
+        C = calib.calibration_matrix(acs, lam, rows="valid")
+        gram = C.conj().T @ C
+    else:
+        gram = calib.gram_from_lags(R, lam, lags)
     sp = nullspace.split_from_gram(gram, thresh)
     K = lagkernel.lag_kernel_from_filters(sp.null, lam, lags, Q)
     x = gx.grid_points(grid_lr)

@@ -32,7 +32,8 @@ SCHED_AUTO, SCHED_DEVICE = 0, 1
 class Problem(ctypes.Structure):
     _fields_ = [("D", ctypes.c_int32), ("Q", ctypes.c_int32), ("acs", ctypes.c_int32 * 3),
                 ("radius", ctypes.c_float), ("grid_lr", ctypes.c_int32 * 3),
-                ("grid_out", ctypes.c_int32 * 3), ("thresh", ctypes.c_float)]
+                ("grid_out", ctypes.c_int32 * 3), ("thresh", ctypes.c_float),
+                ("shape", ctypes.c_int32), ("gram_rows", ctypes.c_int32)]
 
 
 class Opts(ctypes.Structure):
@@ -63,7 +64,8 @@ _SIGS = {
     "pisco_status_string": ([ctypes.c_int], ctypes.c_char_p),
     "pisco_last_error": ([_P], ctypes.c_char_p),
     "pisco_get_status": ([_P, ctypes.POINTER(ctypes.c_uint32)], ctypes.c_int),
-    "pisco_support": ([ctypes.c_int32, ctypes.c_float, ctypes.POINTER(ctypes.c_int32), _P],
+    "pisco_support": ([ctypes.c_int32, ctypes.c_float, ctypes.c_int32,
+                       ctypes.POINTER(ctypes.c_int32), _P],
                       ctypes.c_int),
     "pisco_workspace_size": ([ctypes.POINTER(Problem), ctypes.POINTER(Opts), ctypes.c_int32,
                               ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
@@ -132,14 +134,20 @@ def lib():
     return _lib
 
 
+SHAPE_ELLIPSOID, SHAPE_RECTANGLE = 0, 1
+ROWS_ALL, ROWS_VALID = 0, 1
+
+
 def make_problem(D: int, Q: int, acs: Sequence[int], radius: float, grid_lr: Sequence[int],
-                 grid_out: Sequence[int], thresh: float = 0.05) -> Problem:
+                 grid_out: Sequence[int], thresh: float = 0.05, shape: int = SHAPE_ELLIPSOID,
+                 gram_rows: int = ROWS_ALL) -> Problem:
     """Problem with extents given slowest-first; 2D shapes get z = 1."""
     def pad(v):
         v = list(v)
         return ([1] * (3 - len(v))) + v
     p = Problem()
     p.D, p.Q, p.radius, p.thresh = int(D), int(Q), float(radius), float(thresh)
+    p.shape, p.gram_rows = int(shape), int(gram_rows)
     for name, val in (("acs", acs), ("grid_lr", grid_lr), ("grid_out", grid_out)):
         arr = getattr(p, name)
         for i, x in enumerate(pad(val)):
@@ -175,12 +183,13 @@ def _ptr(t) -> Optional[int]:
 # ---------------------------------------------------------------- host-only calls
 
 
-def pisco_support(D: int, radius: float):
+def pisco_support(D: int, radius: float, shape: int = SHAPE_ELLIPSOID):
     """Support offsets as a list of (z, y, x) tuples in the library's order."""
     n = ctypes.c_int32()
-    _check(lib().pisco_support(D, radius, ctypes.byref(n), None), "pisco_support")
+    _check(lib().pisco_support(D, radius, shape, ctypes.byref(n), None), "pisco_support")
     buf = (ctypes.c_int32 * (3 * n.value))()
-    _check(lib().pisco_support(D, radius, ctypes.byref(n), ctypes.cast(buf, _P)), "pisco_support")
+    _check(lib().pisco_support(D, radius, shape, ctypes.byref(n), ctypes.cast(buf, _P)),
+           "pisco_support")
     return [tuple(buf[3 * i:3 * i + 3]) for i in range(n.value)]
 
 

@@ -313,12 +313,14 @@ pisco_status_t pisco_get_status(pisco_handle_t handle, uint32_t* flags) {
   return PISCO_OK;
 }
 
-pisco_status_t pisco_support(int32_t D, float radius, int32_t* count, int32_t* offsets) {
+pisco_status_t pisco_support(int32_t D, float radius, int32_t shape, int32_t* count,
+                             int32_t* offsets) {
   if (!count || (D != 2 && D != 3) || !(radius >= 1.0f) || radius > 12.0f)
     return PISCO_ERR_ARG;
-  const int n = enumerate_support(D, radius, nullptr, 0);
+  if (shape != PISCO_SHAPE_ELLIPSOID && shape != PISCO_SHAPE_RECTANGLE) return PISCO_ERR_ARG;
+  const int n = enumerate_support(D, radius, shape, nullptr, 0);
   *count = n;
-  if (offsets) enumerate_support(D, radius, offsets, n);
+  if (offsets) enumerate_support(D, radius, shape, offsets, n);
   return PISCO_OK;
 }
 

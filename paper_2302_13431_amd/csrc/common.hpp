@@ -110,6 +110,9 @@ constexpr int kMaxSupport = 4096;
 // Sizes derived from a problem description; everything a stage needs on the
 // host to size launches and to lay out its workspace.
 struct Plan {
+  int shape = PISCO_SHAPE_ELLIPSOID;  // support shape
+  int rows = PISCO_ROWS_ALL;          // rows of C in the Gram
+  long long Pvalid = 0;               // rows of C_valid: prod (A_d - 2 tau)
   int D = 2, Q = 0;
   int acs[3] = {1, 1, 1};
   int tau = 0;            // floor(radius): half-width of the support box
@@ -134,7 +137,7 @@ struct Plan {
 pisco_status_t make_plan(const pisco_problem_t* prob, Plan* plan, std::string* err);
 
 // Enumerates the support in the library's order (host).
-int enumerate_support(int D, float radius, int32_t* offsets /* 3 per point */,
+int enumerate_support(int D, float radius, int shape, int32_t* offsets /* 3 per point */,
                       int cap);
 
 // ------------------------------------------------------------------ workspace carving
@@ -158,6 +161,7 @@ struct GramWs {
   float2* T1;      // pair intermediates
   float2* T2;
   float2* R;       // [P][nlag] correlation lags
+  float2* C;       // [Pvalid][n] rows of C_valid (PISCO_ROWS_VALID only)
 };
 size_t layout_gram(const Plan& p, void* ws, GramWs* out);
 

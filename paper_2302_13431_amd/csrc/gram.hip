@@ -322,8 +322,104 @@ __global__ void __launch_bounds__(256) k_gather(const float2* __restrict__ R,
 
 static unsigned blocks_for(const PassGeom& g) { return ceil_div(g.nlines, g.lpb); }
 
+// ---------------------------------------------------------------- masked Gram
+
+// Rows of C_valid (Eq. 5 with no implicit zeros): row v is the point n of
+// the box [-floor(A/2) + tau, A - 1 - floor(A/2) - tau] per dimension
+// (lexicographic, z slowest), column q |Lambda| + i holds s_q[n - n_i].
+__global__ void k_cvalid(const float2* __restrict__ acs, const int4* __restrict__ sup,
+                         float2* __restrict__ C, int Q, int L, int A0, int A1, int A2, int tz,
+                         int tau, long long Pv, unsigned* status) {
+  const int n = Q * L;
+  const long long idx = blockIdx.x * 256LL + threadIdx.x;
+  if (idx >= Pv * n) return;
+  const long long v = idx / n;
+  const int col = int(idx - v * n);
+  const int q = col / L, i = col - q * L;
+  const int V1 = A1 - 2 * tau, V2 = A2 - 2 * tau;
+  const int vz = int(v / (1LL * V1 * V2)), vr = int(v - 1LL * vz * V1 * V2);
+  const int vy = vr / V2, vx = vr - vy * V2;
+  // array index of s_q[n - n_i]: n has array index (vz + tz, vy + tau, vx + tau)
+  const int4 ni = sup[i];
+  const int az = vz + tz - ni.x, ay = vy + tau - ni.y, ax = vx + tau - ni.z;
+  float2 s = acs[((size_t(q) * A0 + az) * A1 + ay) * A2 + ax];
+  if (!isfinite(s.x) || !isfinite(s.y)) {
+    atomicOr(status, PISCO_FLAG_NONFINITE);
+    s = make_float2(0.f, 0.f);
+  }
+  C[idx] = s;
+}
+
+// gram = C^H C for C [Pv][n] row-major (FP32 products, FP32 sums).  One
+// workgroup per 32 x 32 block of the upper triangle (block row <= block
+// column), 256 threads with 2 x 2 complex entries each; rows of C staged in
+// LDS 16 at a time.  The lower triangle is written as the conjugate of the
+// upper one and the diagonal is real, as for the correlation Gram.
+__global__ void __launch_bounds__(256) k_cherk_valid(const float2* __restrict__ C,
+                                                     float2* __restrict__ gram, int n,
+                                                     long long Pv) {
+  const int bi = blockIdx.y, bj = blockIdx.x;
+  if (bi > bj) return;
+  __shared__ float2 ta[16][33], tb[16][33];
+  const int t = threadIdx.x;
+  const int tr = t / 16, tc = t % 16;  // entries (2 tr + a, 2 tc + b) of the block
+  const int r0 = bi * 32, c0 = bj * 32;
+  float2 acc[2][2];
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b) acc[a][b] = make_float2(0.f, 0.f);
+  for (long long v0 = 0; v0 < Pv; v0 += 16) {
+    for (int e = t; e < 16 * 32; e += 256) {
+      const int rr = e / 32, cc = e % 32;
+      const long long v = v0 + rr;
+      const bool okv = v < Pv;
+      ta[rr][cc] = okv && r0 + cc < n ? C[size_t(v) * n + r0 + cc] : make_float2(0.f, 0.f);
+      tb[rr][cc] = okv && c0 + cc < n ? C[size_t(v) * n + c0 + cc] : make_float2(0.f, 0.f);
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int k = 0; k < 16; ++k) {
+      const float2 x0 = ta[k][2 * tr], x1 = ta[k][2 * tr + 1];
+      const float2 y0 = tb[k][2 * tc], y1 = tb[k][2 * tc + 1];
+      const float2 xs[2] = {x0, x1}, ys[2] = {y0, y1};
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+          // conj(x) y
+          acc[a][b].x = fmaf(xs[a].x, ys[b].x, fmaf(xs[a].y, ys[b].y, acc[a][b].x));
+          acc[a][b].y = fmaf(xs[a].x, ys[b].y, fmaf(-xs[a].y, ys[b].x, acc[a][b].y));
+        }
+    }
+    __syncthreads();
+  }
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b) {
+      const int r = r0 + 2 * tr + a, c = c0 + 2 * tc + b;
+      if (r >= n || c >= n || r > c) continue;
+      float2 v = acc[a][b];
+      if (r == c) v.y = 0.f;
+      gram[size_t(r) * n + c] = v;
+      if (r != c) gram[size_t(c) * n + r] = cconj(v);
+    }
+}
+
+static pisco_status_t run_gram_valid(Handle* h, const Plan& p, const Tables& t, const float2* acs,
+                                     float2* gram, void* ws) {
+  GramWs w;
+  layout_gram(p, ws, &w);
+  const int n = p.n;
+  const long long total = p.Pvalid * n;
+  PISCO_KERNEL(h, k_cvalid, dim3(ceil_div(total, 256)), dim3(256), 0, acs, t.sup, w.C, p.Q, p.L,
+               p.acs[0], p.acs[1], p.acs[2], p.D == 3 ? p.tau : 0, p.tau, p.Pvalid,
+               h->status_dev);
+  const unsigned nb = ceil_div(n, 32);
+  PISCO_KERNEL(h, k_cherk_valid, dim3(nb, nb), dim3(256), 0, w.C, gram, n, p.Pvalid);
+  return PISCO_OK;
+}
+
 pisco_status_t run_gram(Handle* h, const Plan& p, const Tables& t, const float2* acs,
                         float2* gram, void* ws) {
+  if (p.rows == PISCO_ROWS_VALID) return run_gram_valid(h, p, t, acs, gram, ws);
   GramWs w;
   layout_gram(p, ws, &w);
   const int Q = p.Q, P = p.P;

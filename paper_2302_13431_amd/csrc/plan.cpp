@@ -7,9 +7,10 @@
 
 namespace pisco {
 
-int enumerate_support(int D, float radius, int32_t* offsets, int cap) {
-  // Lambda = { n in Z^D : ||n||_2 <= radius } (Sec. IV-B), lexicographic
-  // order with z slowest and x fastest.  For D = 2 the z offset is 0.
+int enumerate_support(int D, float radius, int shape, int32_t* offsets, int cap) {
+  // Lambda = { n in Z^D : ||n||_2 <= radius } (Sec. IV-B) or the box
+  // ||n||_inf <= floor(radius) (Sec. III-C), lexicographic order with z
+  // slowest and x fastest.  For D = 2 the z offset is 0.
   const int t = static_cast<int>(std::floor(radius));
   const double r2 = double(radius) * double(radius);
   const int zlo = (D == 3) ? -t : 0, zhi = (D == 3) ? t : 0;
@@ -17,7 +18,8 @@ int enumerate_support(int D, float radius, int32_t* offsets, int cap) {
   for (int z = zlo; z <= zhi; ++z)
     for (int y = -t; y <= t; ++y)
       for (int x = -t; x <= t; ++x) {
-        if (double(z) * z + double(y) * y + double(x) * x > r2) continue;
+        if (shape == PISCO_SHAPE_ELLIPSOID && double(z) * z + double(y) * y + double(x) * x > r2)
+          continue;
         if (offsets && count < cap) {
           offsets[3 * count + 0] = z;
           offsets[3 * count + 1] = y;
@@ -46,6 +48,12 @@ pisco_status_t make_plan(const pisco_problem_t* prob, Plan* p, std::string* err)
     return fail("radius must be in [1, 12]");
   if (!(prob->thresh > 0.0f) || prob->thresh >= 1.0f)
     return fail("thresh must be in (0, 1)");
+  if (prob->shape != PISCO_SHAPE_ELLIPSOID && prob->shape != PISCO_SHAPE_RECTANGLE)
+    return fail("unknown support shape");
+  if (prob->gram_rows != PISCO_ROWS_ALL && prob->gram_rows != PISCO_ROWS_VALID)
+    return fail("unknown gram_rows");
+  p->shape = prob->shape;
+  p->rows = prob->gram_rows;
   p->D = prob->D;
   p->Q = prob->Q;
   p->radius = prob->radius;
@@ -70,7 +78,9 @@ pisco_status_t make_plan(const pisco_problem_t* prob, Plan* p, std::string* err)
     if (p->F[d] > 256) return fail("ACS + 2 * radius must be <= 256 per dimension");
     if (p->lr[d] > 1024 || p->out[d] > 4096) return fail("grid too large");
   }
-  p->L = enumerate_support(p->D, p->radius, nullptr, 0);
+  p->L = enumerate_support(p->D, p->radius, p->shape, nullptr, 0);
+  p->Pvalid = 1;
+  for (int d = first; d < 3; ++d) p->Pvalid *= p->acs[d] - 2 * p->tau;
   if (p->L > kMaxSupport) return fail("support too large");
   p->n = p->Q * p->L;
   p->P = p->Q * (p->Q + 1) / 2;
@@ -85,6 +95,12 @@ pisco_status_t make_plan(const pisco_problem_t* prob, Plan* p, std::string* err)
 size_t layout_gram(const Plan& p, void* ws, GramWs* o) {
   Carver c(ws);
   GramWs w{};
+  if (p.rows == PISCO_ROWS_VALID) {
+    // the explicit rows of C_valid
+    w.C = c.take<float2>(size_t(p.Pvalid) * p.n);
+    if (o) *o = w;
+    return c.used + 256;
+  }
   // Forward spectra need two buffers (pass ping-pong); the pair passes need
   // T1 = [P][B0][F1][F2] and T2 = [P][B0][B1][F2].
   const size_t s1 = size_t(p.Q) * p.F[0] * p.F[1] * p.F[2];

@@ -179,8 +179,9 @@ pisco_status_t axis_transform64(Handle* h, const double2* in, double2* out,
 //          centred samples, M[o][a] = (1/nin) sum_k w_k exp(i 2 pi k (y_o - x_a))
 //          over the centred band of nin frequencies, the -nin/2 term split
 //          in half onto +-nin/2 when nin is even and nout > nin
-//   support : the points n of the box with ||n||_2 <= radius, lexicographic
-//          (z slowest), as int4 (z, y, x, 0)
+//   support : the points n of the box with ||n||_2 <= radius (or the whole
+//          box for the rectangular support), lexicographic (z slowest), as
+//          int4 (z, y, x, 0)
 //   boxmap : box cell -> index of its point in the support list, -1 outside;
 //          the index of an inside cell is the number of inside cells before
 //          it in the same lexicographic order
@@ -196,11 +197,11 @@ struct TableJobs {
   TableJob job[kMaxTableJobs];
   int count;
   int D, tau, tz;  // support box: x, y in [-tau, tau], z in [-tz, tz]
-  double r2;       // radius^2
+  double r2;       // radius^2 (ellipsoid); a negative value: the whole box
 };
 
 __device__ inline bool in_ball(int z, int y, int x, double r2) {
-  return double(z) * z + double(y) * y + double(x) * x <= r2;
+  return r2 < 0.0 || double(z) * z + double(y) * y + double(x) * x <= r2;
 }
 
 __device__ void dft_entry(const TableJob& j, int idx, double* re, double* im) {
@@ -329,7 +330,7 @@ pisco_status_t build_tables(Handle* h, const Plan& p, unsigned which, const Tabl
   jobs.D = p.D;
   jobs.tau = p.tau;
   jobs.tz = p.D == 3 ? p.tau : 0;
-  jobs.r2 = double(p.radius) * double(p.radius);
+  jobs.r2 = p.shape == PISCO_SHAPE_RECTANGLE ? -1.0 : double(p.radius) * double(p.radius);
   int maxel = 1;
   auto add = [&](int kind, void* out, int nout, int nin, int co, int ci, double period,
                  double sign, double scale, double sigma) {

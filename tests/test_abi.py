@@ -52,6 +52,10 @@ def test_support_matches_definition():
             got = np.array(pts)
         ref = osup.kernel_support(D, r)
         assert np.array_equal(got, ref), (D, r)
+    for D, r in [(2, 1.0), (2, 3.5), (3, 2.0), (3, 3.0)]:
+        pts = L.pisco_support(D, r, L.SHAPE_RECTANGLE)
+        got = np.array([p[1:] for p in pts]) if D == 2 else np.array(pts)
+        assert np.array_equal(got, osup.kernel_support(D, r, "rectangle")), (D, r)
 
 
 def test_problem_validation():

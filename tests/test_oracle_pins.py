@@ -78,6 +78,39 @@ def test_lag_gram_equals_explicit_cfull(D, A, radius):
     assert np.max(np.abs(Cv.conj().T @ Cv - ref)) > 1e-3 * np.max(np.abs(ref))
 
 
+@pytest.mark.parametrize("D,A,radius,shape", [(2, (12, 11), 2.0, "ellipsoid"),
+                                               (2, (10, 10), 2.0, "rectangle"),
+                                               (3, (8, 9, 8), 1.5, "ellipsoid")])
+def test_valid_rows_gram(D, A, radius, shape):
+    """C_valid (Sec. IV-A's masked form): prod(A - 2 tau) rows, each row's
+    neighbourhood inside the ACS.  A row n outside C_valid has some n - n_i
+    outside the ACS along a coordinate, so every other entry n - n_j lies
+    within 2 tau of the border along it: when every sample within 2 tau of
+    the border is zero, those rows are all zero and C_valid^H C_valid equals
+    the correlation Gram (C_full^H C_full) exactly; otherwise it differs."""
+    rng = np.random.default_rng(31)
+    Q = 3
+    lam = support.kernel_support(D, radius, shape)
+    lags = support.difference_set(lam)
+    tau = int(np.floor(radius))
+    acs = rng.standard_normal((Q,) + A) + 1j * rng.standard_normal((Q,) + A)
+    Cv = calib.calibration_matrix(acs, lam, rows="valid")
+    assert Cv.shape == (int(np.prod([a - 2 * tau for a in A])), Q * len(lam))
+    full = calib.gram_from_lags(calib.correlation_lags(acs, lags), lam, lags)
+    assert np.abs(Cv.conj().T @ Cv - full).max() > 1e-3 * np.abs(full).max()
+    inner = acs.copy()
+    for d in range(D):
+        sl = [slice(None)] * (D + 1)
+        sl[d + 1] = slice(0, 2 * tau)
+        inner[tuple(sl)] = 0
+        sl[d + 1] = slice(A[d] - 2 * tau, A[d])
+        inner[tuple(sl)] = 0
+    assert np.abs(inner).max() > 0
+    Cv = calib.calibration_matrix(inner, lam, rows="valid")
+    full = calib.gram_from_lags(calib.correlation_lags(inner, lags), lam, lags)
+    assert np.abs(Cv.conj().T @ Cv - full).max() <= 1e-13 * np.abs(full).max()
+
+
 def test_gram_closed_forms():
     sc = _tiny_acs()
     acs = sc.acs
