@@ -432,6 +432,11 @@ def main():
     ap.add_argument("--learned-scans", type=int, default=64,
                     help="training scans for the learned warm start")
     ap.add_argument("--breakdown", action="store_true", help="per-kernel times to stderr")
+    ap.add_argument("--tol", type=float, default=None,
+                    help="power-iteration tolerance of every form (skips the search for the "
+                         "largest tolerance that meets the map-error target)")
+    ap.add_argument("--mixed-only", action="store_true",
+                    help="time the mixed form only (profiling runs)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run 5 device-to-device copies of MIB MiB (HBM counter "
                          "calibration under rocprofv3) and exit")
@@ -523,12 +528,17 @@ def main():
         del out
         return res
 
-    tol_mixed, sweep_mixed = pick_tol(P._lib.PREC_SPLIT_F16)
-    tol_plain, sweep_plain = pick_tol(P._lib.PREC_FP32)
+    if args.tol is not None:
+        tol_mixed, sweep_mixed = args.tol, None
+        tol_plain, sweep_plain = args.tol, None
+    else:
+        tol_mixed, sweep_mixed = pick_tol(P._lib.PREC_SPLIT_F16)
+        tol_plain, sweep_plain = (None, None) if args.mixed_only \
+            else pick_tol(P._lib.PREC_FP32)
     log(f"tolerances at p99 <= {TARGET_P99}: mixed {tol_mixed}, plain {tol_plain}")
     mixed = run_form(P._lib.PREC_SPLIT_F16, tol_mixed)
-    plain = run_form(P._lib.PREC_FP32, tol_plain)
-    paper = run_form(P._lib.PREC_SPLIT_F16, None)
+    plain = mixed if args.mixed_only else run_form(P._lib.PREC_FP32, tol_plain)
+    paper = mixed if args.mixed_only else run_form(P._lib.PREC_SPLIT_F16, None)
     log("forms timed")
     if args.breakdown:
         for tag, r in (("mixed", mixed), ("plain_fp32", plain)):
@@ -563,6 +573,8 @@ def main():
                 "avg_us": avg_s * 1e6, "work_per_launch": work, "work_unit": unit}
     for r in (mixed, plain, paper):
         r.pop("est", None)
+    if args.mixed_only:
+        args.no_learned = args.no_batched = args.no_cpu_baseline = True
 
     def form(r, tol, sweep):
         d = {"value": r["value"], "ms_per_step": r["ms"], "device_status": r["status"]}
