@@ -298,6 +298,23 @@ pisco_status_t pisco_eig_checked(pisco_handle_t handle, int32_t Q, int64_t N,
                                  double* resid64, void* workspace,
                                  size_t workspace_bytes);
 
+/* The `sets` smallest eigenpairs of G(x) per voxel by `krylov` Lanczos
+ * steps (Sec. IV-E: the remedy the paper names where the two smallest
+ * singular values are close and power iteration is slow; Sec. III-B
+ * footnote: one set of maps per small eigenvalue when the field of view is
+ * too small).  Lanczos on G(x) from e_q* with full reorthogonalisation, the
+ * tridiagonal projection solved in FP64, Ritz vectors of the smallest Ritz
+ * values; with krylov = Q the pairs are G's own to FP32 rounding.
+ *   G     : float2 packed as from pisco_gx, N voxels
+ *   bound : |Lambda| (scale of the invariant-subspace test)
+ *   sets  : 1..min(8, krylov);  krylov : 1..Q
+ *   maps  : float2 [sets][Q][N], unit-norm eigenvectors, ascending eigenvalue
+ *   lam   : float [sets][N], Rayleigh quotients c^H G c
+ *   resid : float [sets][N], ||G c - lam c|| (may be NULL) */
+pisco_status_t pisco_eig_sets(pisco_handle_t handle, int32_t Q, int64_t N, float bound,
+                              int32_t sets, int32_t krylov, const void* G, void* maps,
+                              float* lam, float* resid);
+
 /* Image-support mask (Sec. III-D, the optional last step of the naive
  * algorithm).  Inside the support H(x) has rank Q - 1 and lambda_min(G(x))
  * (its smallest singular value squared) is about zero; outside it is

@@ -25,6 +25,14 @@ def smallest_exact(G: np.ndarray):
     return w[:, 0], V[:, :, 0], w[:, 1]
 
 
+def smallest_set(G: np.ndarray, M: int):
+    """The M smallest eigenpairs per voxel (numpy eigh): one set of maps per
+    small eigenvalue when the field of view is too small for the object
+    (Sec. III-B footnote).  Returns (lambda [N, M] ascending, c [N, Q, M])."""
+    w, V = np.linalg.eigh(np.asarray(G, dtype=np.complex128))
+    return w[:, :M], V[:, :, :M]
+
+
 def rayleigh(G: np.ndarray, c: np.ndarray):
     """Rayleigh quotient and residual of given vectors (Sec. IV-E check).
 

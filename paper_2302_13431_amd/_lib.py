@@ -75,6 +75,8 @@ _SIGS = {
     "pisco_gram_static": ([_P, ctypes.POINTER(Problem), _P, _P], ctypes.c_int),
     "pisco_gram_static_bytes": ([ctypes.POINTER(Problem), ctypes.POINTER(ctypes.c_size_t),
                                  ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+    "pisco_eig_sets": ([_P, ctypes.c_int32, ctypes.c_int64, ctypes.c_float, ctypes.c_int32,
+                        ctypes.c_int32, _P, _P, _P, _P], ctypes.c_int),
     "pisco_support_mask": ([_P, ctypes.POINTER(Problem), _P, ctypes.c_float, _P, _P,
                             ctypes.c_size_t], ctypes.c_int),
     "pisco_espirit_operator": ([_P, ctypes.c_int32, ctypes.c_int64, ctypes.c_float, _P, _P],
@@ -293,6 +295,12 @@ def pisco_eig_checked(h: Handle, Q: int, N: int, bound: float, opts: Opts, G, in
     _check(lib().pisco_eig_checked(h.h, Q, N, bound, ctypes.byref(opts), _ptr(G), _ptr(init),
                                    _ptr(maps), _ptr(lam), _ptr(iters), _ptr(lam64),
                                    _ptr(resid64), None, 0), "pisco_eig_checked", h.h)
+
+
+def pisco_eig_sets(h: Handle, Q: int, N: int, bound: float, sets: int, krylov: int, G, maps,
+                   lam, resid=None):
+    _check(lib().pisco_eig_sets(h.h, Q, N, bound, sets, krylov, _ptr(G), _ptr(maps), _ptr(lam),
+                                _ptr(resid)), "pisco_eig_sets", h.h)
 
 
 def pisco_support_mask(h: Handle, prob: Problem, lam, thresh: float, mask, ws):

@@ -497,6 +497,22 @@ pisco_status_t pisco_maps(pisco_handle_t handle, const pisco_problem_t* prob,
                   static_cast<const float2*>(maps_lr), static_cast<float2*>(maps_out), scratch);
 }
 
+pisco_status_t pisco_eig_sets(pisco_handle_t handle, int32_t Q, int64_t N, float bound,
+                              int32_t sets, int32_t krylov, const void* G, void* maps,
+                              float* lam, float* resid) {
+  Handle* h = reinterpret_cast<Handle*>(handle);
+  if (!h) return PISCO_ERR_ARG;
+  if (Q < 2 || Q > kMaxQ) return fail(h, PISCO_ERR_ARG, "Q must be in [2, 32]");
+  if (N < 0) return fail(h, PISCO_ERR_ARG, "N must be >= 0");
+  if (!(bound > 0.f)) return fail(h, PISCO_ERR_ARG, "bound must be positive");
+  if (krylov < 1 || krylov > Q) return fail(h, PISCO_ERR_ARG, "krylov must be in [1, Q]");
+  if (sets < 1 || sets > 8 || sets > krylov)
+    return fail(h, PISCO_ERR_ARG, "sets must be in [1, min(8, krylov)]");
+  if (N > 0 && (!G || !maps || !lam)) return fail(h, PISCO_ERR_ARG, "null pointer");
+  return run_eig_sets(h, Q, N, bound, krylov, sets, static_cast<const float2*>(G),
+                      static_cast<float2*>(maps), lam, resid);
+}
+
 pisco_status_t pisco_support_mask(pisco_handle_t handle, const pisco_problem_t* prob,
                                   const float* lam_min, float thresh, uint8_t* mask, void* ws,
                                   size_t ws_bytes) {

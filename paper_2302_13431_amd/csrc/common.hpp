@@ -282,6 +282,11 @@ pisco_status_t run_eig(Handle* h, int Q, long long N, float bound, int iters,
 pisco_status_t run_maps(Handle* h, const Plan& p, const Tables& t, int phase_rule,
                         const float2* acs, const float2* maps_lr, float2* maps_out, void* ws);
 
+// The M smallest eigenpairs per voxel by K Lanczos steps (1 <= M <= 8,
+// M <= K <= Q): maps [M][Q][N], lam [M][N], resid [M][N] (nullable).
+pisco_status_t run_eig_sets(Handle* h, int Q, long long N, float bound, int K, int M,
+                            const float2* G, float2* maps, float* lam, float* resid);
+
 // Support mask (FP64 interpolation of lambda_min / bound, thresholded) and
 // the ESPIRiT operator B = I - G / bound on packed planes.
 size_t layout_mask(const Plan& p, void* ws, double2** t0, double2** t1, double2** t2);

@@ -115,6 +115,21 @@ class Estimator:
                             res64)
         return maps, lam, it, lam64, res64
 
+    def eig_sets(self, G, sets: int = 1, krylov: Optional[int] = None, N: Optional[int] = None,
+                 Q: Optional[int] = None, bound: Optional[float] = None):
+        """The `sets` smallest eigenpairs per voxel by Lanczos (pisco_eig_sets):
+        (maps [sets][Q][N], lam [sets][N], resid [sets][N])."""
+        t = self.torch
+        N = self.Nlr if N is None else int(N)
+        Q = self.Q if Q is None else int(Q)
+        K = Q if krylov is None else int(krylov)
+        bound = float(self.nsup) if bound is None else float(bound)
+        maps = self._alloc((sets, Q, N), t.complex64)
+        lam = self._alloc((sets, N), t.float32)
+        res = self._alloc((sets, N), t.float32)
+        L.pisco_eig_sets(self.h, Q, N, bound, sets, K, G.contiguous(), maps, lam, res)
+        return maps, lam, res
+
     def eig_from(self, G, init, opts: Optional[L.Opts] = None):
         """Power iteration from the given start vectors (float2 [Q][N_lr])."""
         t = self.torch

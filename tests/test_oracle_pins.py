@@ -354,6 +354,26 @@ def test_power_iteration_bound_and_convergence():
     assert np.allclose(lam, lmin, atol=1e-10 * bound)
 
 
+def test_smallest_set_recovers_constructed_spectrum():
+    """G = U diag(w) U^H with a known unitary U and known eigenvalues (two
+    near zero, as under aliasing): the M smallest pairs are the constructed
+    ones, in ascending order, up to a phase per vector."""
+    rng = np.random.default_rng(22)
+    Nv, Q, bound = 30, 6, 10.0
+    U = np.linalg.qr(rng.standard_normal((Nv, Q, Q)) + 1j * rng.standard_normal((Nv, Q, Q)))[0]
+    w = np.sort(rng.uniform(2.0, 9.0, size=(Nv, Q)), axis=1)
+    w[:, 0] = rng.uniform(0, 1e-3, Nv)
+    w[:, 1] = w[:, 0] + rng.uniform(0.05, 0.2, Nv)
+    G = np.einsum("xpk,xk,xqk->xpq", U, w, U.conj())
+    lam, c = eig.smallest_set(G, 3)
+    assert np.allclose(lam, w[:, :3], atol=1e-12 * bound)
+    for m in range(3):
+        ov = np.abs(np.einsum("xq,xq->x", U[:, :, m].conj(), c[:, :, m]))
+        assert np.allclose(ov, 1.0, atol=1e-10)
+    l1, c1, _ = eig.smallest_exact(G)
+    assert np.allclose(l1, lam[:, 0], atol=1e-12 * bound)
+
+
 def test_rayleigh_check():
     """The Rayleigh check (Sec. IV-E): on exact eigenvectors (numpy eigh)
     it returns their eigenvalue with a residual at rounding level; for a
