@@ -306,7 +306,8 @@ pisco_status_t pisco_eig_checked(pisco_handle_t handle, int32_t Q, int64_t N,
  * tridiagonal projection solved in FP64, Ritz vectors of the smallest Ritz
  * values; with krylov = Q the pairs are G's own to FP32 rounding.
  *   G     : float2 packed as from pisco_gx, N voxels
- *   bound : |Lambda| (scale of the invariant-subspace test)
+ *   bound : |Lambda| (scale of the invariant-subspace test); a value <= 0
+ *           uses each voxel's largest row sum of |G| instead
  *   sets  : 1..min(8, krylov);  krylov : 1..Q
  *   maps  : float2 [sets][Q][N], unit-norm eigenvectors, ascending eigenvalue
  *   lam   : float [sets][N], Rayleigh quotients c^H G c
@@ -314,6 +315,24 @@ pisco_status_t pisco_eig_checked(pisco_handle_t handle, int32_t Q, int64_t N,
 pisco_status_t pisco_eig_sets(pisco_handle_t handle, int32_t Q, int64_t N, float bound,
                               int32_t sets, int32_t krylov, const void* G, void* maps,
                               float* lam, float* resid);
+
+/* Many small partial SVDs at once (locally low-rank models, which Sec. I
+ * and Sec. V name as beneficiaries of the method's batched small
+ * eigen-problems).  For B Casorati matrices X_b of m rows and Q columns the
+ * `rank` largest singular values and right singular vectors come from the
+ * r largest eigenpairs of the Gram X_b^H X_b (FP32) by the per-voxel
+ * Lanczos solver with a full basis; sigma_k is resolved to about
+ * eps sigma_1^2 / sigma_k.
+ *   X     : float2 [B][Q][m] (column q of patch b contiguous)
+ *   sigma : float [rank][B], descending
+ *   V     : float2 [rank][Q][B], right singular vectors (may be NULL)
+ *   Xr    : float2 [B][Q][m], the rank-`rank` part X_b V V^H (may be NULL)
+ *   rank  : 1..min(8, Q);  Q : 2..32
+ * Workspace: pisco_llr_workspace_size. */
+pisco_status_t pisco_llr_workspace_size(int64_t B, int32_t Q, int32_t rank, size_t* bytes);
+pisco_status_t pisco_llr_svd(pisco_handle_t handle, int64_t B, int32_t m, int32_t Q,
+                             int32_t rank, const void* X, float* sigma, void* V, void* Xr,
+                             void* workspace, size_t workspace_bytes);
 
 /* Image-support mask (Sec. III-D, the optional last step of the naive
  * algorithm).  Inside the support H(x) has rank Q - 1 and lambda_min(G(x))

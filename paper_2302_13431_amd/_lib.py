@@ -77,6 +77,10 @@ _SIGS = {
                                  ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
     "pisco_eig_sets": ([_P, ctypes.c_int32, ctypes.c_int64, ctypes.c_float, ctypes.c_int32,
                         ctypes.c_int32, _P, _P, _P, _P], ctypes.c_int),
+    "pisco_llr_workspace_size": ([ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
+                                  ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+    "pisco_llr_svd": ([_P, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P,
+                       _P, _P, _P, _P, ctypes.c_size_t], ctypes.c_int),
     "pisco_support_mask": ([_P, ctypes.POINTER(Problem), _P, ctypes.c_float, _P, _P,
                             ctypes.c_size_t], ctypes.c_int),
     "pisco_espirit_operator": ([_P, ctypes.c_int32, ctypes.c_int64, ctypes.c_float, _P, _P],
@@ -301,6 +305,22 @@ def pisco_eig_sets(h: Handle, Q: int, N: int, bound: float, sets: int, krylov: i
                    lam, resid=None):
     _check(lib().pisco_eig_sets(h.h, Q, N, bound, sets, krylov, _ptr(G), _ptr(maps), _ptr(lam),
                                 _ptr(resid)), "pisco_eig_sets", h.h)
+
+
+def pisco_llr_svd(h: Handle, X, rank: int, V=None, Xr=None):
+    """Partial SVDs of the B Casorati matrices X (torch complex64 [B][Q][m]):
+    returns sigma [rank][B] (and fills V [rank][Q][B], Xr [B][Q][m] if given)."""
+    import torch
+    B, Q, m = (int(v) for v in X.shape)
+    size = ctypes.c_size_t()
+    _check(lib().pisco_llr_workspace_size(B, Q, rank, ctypes.byref(size)),
+           "pisco_llr_workspace_size")
+    raw = torch.empty(size.value + 256, dtype=torch.uint8, device=X.device)
+    ws = raw[(-raw.data_ptr()) % 256:]
+    sigma = torch.empty((rank, B), dtype=torch.float32, device=X.device)
+    _check(lib().pisco_llr_svd(h.h, B, m, Q, rank, _ptr(X.contiguous()), _ptr(sigma), _ptr(V),
+                               _ptr(Xr), _ptr(ws), size.value), "pisco_llr_svd", h.h)
+    return sigma
 
 
 def pisco_support_mask(h: Handle, prob: Problem, lam, thresh: float, mask, ws):

@@ -504,13 +504,36 @@ pisco_status_t pisco_eig_sets(pisco_handle_t handle, int32_t Q, int64_t N, float
   if (!h) return PISCO_ERR_ARG;
   if (Q < 2 || Q > kMaxQ) return fail(h, PISCO_ERR_ARG, "Q must be in [2, 32]");
   if (N < 0) return fail(h, PISCO_ERR_ARG, "N must be >= 0");
-  if (!(bound > 0.f)) return fail(h, PISCO_ERR_ARG, "bound must be positive");
+  if (!(bound > 0.f) && !(bound <= 0.f)) return fail(h, PISCO_ERR_ARG, "bound must be a number");
   if (krylov < 1 || krylov > Q) return fail(h, PISCO_ERR_ARG, "krylov must be in [1, Q]");
   if (sets < 1 || sets > 8 || sets > krylov)
     return fail(h, PISCO_ERR_ARG, "sets must be in [1, min(8, krylov)]");
   if (N > 0 && (!G || !maps || !lam)) return fail(h, PISCO_ERR_ARG, "null pointer");
   return run_eig_sets(h, Q, N, bound, krylov, sets, static_cast<const float2*>(G),
                       static_cast<float2*>(maps), lam, resid);
+}
+
+pisco_status_t pisco_llr_workspace_size(int64_t B, int32_t Q, int32_t rank, size_t* bytes) {
+  if (!bytes || B < 0 || Q < 2 || Q > kMaxQ || rank < 1 || rank > 8 || rank > Q)
+    return PISCO_ERR_ARG;
+  *bytes = layout_llr(B, Q, rank, nullptr, nullptr, nullptr, nullptr);
+  return PISCO_OK;
+}
+
+pisco_status_t pisco_llr_svd(pisco_handle_t handle, int64_t B, int32_t m, int32_t Q,
+                             int32_t rank, const void* X, float* sigma, void* V, void* Xr,
+                             void* ws, size_t ws_bytes) {
+  Handle* h = reinterpret_cast<Handle*>(handle);
+  if (!h) return PISCO_ERR_ARG;
+  if (B < 0 || m < 1) return fail(h, PISCO_ERR_ARG, "need B >= 0 and m >= 1");
+  if (Q < 2 || Q > kMaxQ) return fail(h, PISCO_ERR_ARG, "Q must be in [2, 32]");
+  if (rank < 1 || rank > 8 || rank > Q) return fail(h, PISCO_ERR_ARG, "rank must be in [1, min(8, Q)]");
+  if (B > 0 && (!X || !sigma || !ws || !aligned(ws)))
+    return fail(h, PISCO_ERR_ARG, "null or unaligned pointer");
+  if (ws_bytes < layout_llr(B, Q, rank, nullptr, nullptr, nullptr, nullptr))
+    return fail(h, PISCO_ERR_WORKSPACE, "workspace too small for pisco_llr_svd");
+  return run_llr(h, B, m, Q, rank, static_cast<const float2*>(X), sigma,
+                 static_cast<float2*>(V), static_cast<float2*>(Xr), ws);
 }
 
 pisco_status_t pisco_support_mask(pisco_handle_t handle, const pisco_problem_t* prob,

@@ -287,6 +287,13 @@ pisco_status_t run_maps(Handle* h, const Plan& p, const Tables& t, int phase_rul
 pisco_status_t run_eig_sets(Handle* h, int Q, long long N, float bound, int K, int M,
                             const float2* G, float2* maps, float* lam, float* resid);
 
+// Partial SVDs of B Casorati matrices X [B][Q][m] (r <= min(8, Q)): sigma
+// [r][B], right singular vectors [r][Q][B] (Vout nullable: in ws), rank-r
+// part Xr [B][Q][m] (nullable).
+size_t layout_llr(long long B, int Q, int r, void* ws, float2** A, float2** V, float** lam);
+pisco_status_t run_llr(Handle* h, long long B, int m, int Q, int r, const float2* X,
+                       float* sigma, float2* Vout, float2* Xr, void* ws);
+
 // Support mask (FP64 interpolation of lambda_min / bound, thresholded) and
 // the ESPIRiT operator B = I - G / bound on packed planes.
 size_t layout_mask(const Plan& p, void* ws, double2** t0, double2** t1, double2** t2);

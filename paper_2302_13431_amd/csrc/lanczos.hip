@@ -112,7 +112,18 @@ __global__ void __launch_bounds__(256) k_lanczos(const float2* __restrict__ G, i
       }
     return w;
   };
-  const float small = 1e-5f * bound;
+  // scale of the invariant-subspace test: bound, or (bound <= 0) the
+  // voxel's largest row sum of |G| (at least its spectral radius)
+  float scale = bound;
+  if (!(bound > 0.f)) {
+    float rs = 0.f;
+#pragma unroll
+    for (int p = 0; p < QG; ++p) rs += sqrtf(g[p].x * g[p].x + g[p].y * g[p].y);
+#pragma unroll
+    for (int off = QG / 2; off > 0; off >>= 1) rs = fmaxf(rs, __shfl_xor(rs, off, QG));
+    scale = rs > 0.f ? rs : 1.f;
+  }
+  const float small = 1e-5f * scale;
   float2 x = make_float2(row && lane == bidx ? 1.f : 0.f, 0.f), prev = make_float2(0.f, 0.f);
   float beta = 0.f;
   for (int j = 0; j < K; ++j) {

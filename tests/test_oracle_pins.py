@@ -10,7 +10,7 @@ import os
 import numpy as np
 import pytest
 
-from oracle import calib, eig, gx, lagkernel, maps, metrics, nullspace, support
+from oracle import calib, eig, gx, lagkernel, llr, maps, metrics, nullspace, support
 from synth import generator, workloads
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -372,6 +372,33 @@ def test_smallest_set_recovers_constructed_spectrum():
         assert np.allclose(ov, 1.0, atol=1e-10)
     l1, c1, _ = eig.smallest_exact(G)
     assert np.allclose(l1, lam[:, 0], atol=1e-12 * bound)
+
+
+def test_partial_svd_pins():
+    """Partial SVDs: a patch of exact rank r is reproduced to rounding; for
+    any patch the truncation error in the Frobenius norm is the root sum of
+    squares of the dropped singular values (Eckart-Young); the singular
+    values of a matrix built from known orthonormal factors are returned."""
+    rng = np.random.default_rng(23)
+    B, Q, m, r = 20, 6, 16, 2
+    A = rng.standard_normal((B, m, r)) + 1j * rng.standard_normal((B, m, r))
+    C = rng.standard_normal((B, r, Q)) + 1j * rng.standard_normal((B, r, Q))
+    X = np.transpose(A @ C, (0, 2, 1))
+    s, V, Xr = llr.partial_svd(X, r)
+    assert np.abs(Xr - X).max() <= 1e-12 * np.abs(X).max()
+    X = rng.standard_normal((B, Q, m)) + 1j * rng.standard_normal((B, Q, m))
+    s_all = np.linalg.svd(np.transpose(X, (0, 2, 1)), compute_uv=False)
+    s, V, Xr = llr.partial_svd(X, r)
+    err = np.linalg.norm((X - Xr).reshape(B, -1), axis=1)
+    assert np.allclose(err, np.sqrt(np.sum(s_all[:, r:] ** 2, axis=1)), rtol=1e-10)
+    Uo = np.linalg.qr(rng.standard_normal((B, m, Q)) + 1j * rng.standard_normal((B, m, Q)))[0]
+    Vo = np.linalg.qr(rng.standard_normal((B, Q, Q)) + 1j * rng.standard_normal((B, Q, Q)))[0]
+    sig = np.sort(rng.uniform(0.1, 2.0, (B, Q)), axis=1)[:, ::-1]
+    M = np.einsum("bik,bk,bqk->biq", Uo, sig, Vo.conj())
+    s, V, _ = llr.partial_svd(np.transpose(M, (0, 2, 1)), 3)
+    assert np.allclose(s, sig[:, :3], rtol=1e-12)
+    ov = np.abs(np.einsum("bqk,bqk->bk", Vo[:, :, :3].conj(), V))
+    assert np.allclose(ov, 1.0, atol=1e-9)
 
 
 def test_rayleigh_check():
