@@ -418,6 +418,110 @@ def batched_report(steps: int):
             "graph_vs_eager_map_error_p99_max": err}
 
 
+def lanczos_flops(Q: int, K: int, M: int) -> float:
+    """Algorithmic FP32 flops per voxel of K Lanczos steps with full
+    reorthogonalisation (two classical Gram-Schmidt passes) and M Ritz
+    vectors: a product with G is 8 Q^2 flops; step j (0-based) projects
+    against j + 1 basis vectors twice, 16 Q flops per vector and pass
+    (inner product and update); each Ritz vector is a combination of K basis
+    vectors (8 Q K) and its Rayleigh check one more product."""
+    return 8.0 * K * Q * Q + 2 * 16.0 * Q * K * (K + 1) / 2 + M * (8.0 * Q * K + 8.0 * Q * Q)
+
+
+def llr_patches(B: int, Q: int, m: int, rank: int, seed: int):
+    """Seeded Casorati matrices [B][Q][m] of a locally low-rank series: per
+    patch a rank-`rank` product of complex Gaussian factors with singular
+    values falling as 2^-k, plus complex Gaussian noise at 1e-2 of the
+    largest (drawn on the device: about 1 GB at the report's size)."""
+    import torch
+    g = torch.Generator(device="cuda")
+    g.manual_seed(seed)
+
+    def cn(*shape):
+        return torch.complex(torch.randn(*shape, generator=g, device="cuda"),
+                             torch.randn(*shape, generator=g, device="cuda"))
+    scale = torch.pow(2.0, -torch.arange(rank, device="cuda", dtype=torch.float32))
+    U = cn(B, Q, rank) * scale.to(torch.complex64)
+    W = cn(B, rank, m) / m ** 0.5
+    X = 1e-2 * cn(B, Q, m) / m ** 0.5
+    for k in range(rank):  # sum of rank-one terms (elementwise, no batched GEMM)
+        X += U[:, :, k, None] * W[:, None, k, :]
+    return X.contiguous()
+
+
+def next_rows_report(w, acs, steps: int):
+    """The per-voxel Lanczos solver beside the power iteration on this
+    workload's G(x), and many small partial SVDs (locally low-rank patches).
+
+    Lanczos: pisco_eig_sets with a full Krylov basis (K = Q) for one and two
+    sets of maps, timed over `steps` calls, against pisco_eig (ten power
+    steps).  Partial SVDs: 65,536 Casorati matrices of 8 x 8-pixel patches
+    (m = 64) over 32 frames, rank 4 (llr_patches).  Per-kernel times come
+    from HIP events on the library's stream."""
+    import torch
+    import paper_2302_13431_amd as P
+    est = P.Estimator(w.Q, w.acs, w.radius, w.grid_lr, w.grid)
+    log("next rows: Gram, nullspace and G(x) of the workload")
+    gram = est.gram(acs)
+    _, basis, counts = est.nullspace(gram)
+    del gram
+    G = est.gx(basis, counts)
+    del basis
+    torch.cuda.synchronize()
+    Q, N = est.Q, est.Nlr
+
+    def traced(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        P.pisco_trace_enable(est.h, True, None)
+        t = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        el = (time.perf_counter() - t) / reps
+        per = P.pisco_trace_read(est.h)
+        P.pisco_trace_enable(est.h, False)
+        return el, {k: v[1] / v[0] for k, v in per.items() if v[0]}
+
+    rep = {"voxels": N, "Q": Q}
+    log(f"next rows: power iteration, Q={Q} N={N}")
+    t_pow, k_pow = traced(lambda: est.eig(G), steps)
+    rep["power_ten_steps"] = {"ms": t_pow * 1e3, "kernel_us": {k: v * 1e3 for k, v in k_pow.items()}}
+    for sets in (1, 2):
+        log(f"next rows: pisco_eig_sets sets={sets} krylov={Q} Q={Q} N={N}")
+        t_lz, k_lz = traced(lambda: est.eig_sets(G, sets=sets, krylov=Q), steps)
+        name = max(k_lz, key=k_lz.get)
+        flops = lanczos_flops(Q, Q, sets) * N
+        rep[f"lanczos_sets{sets}"] = {
+            "ms": t_lz * 1e3, "kernel_us": {k: v * 1e3 for k, v in k_lz.items()},
+            "roofline": {"kernel": name, "bound": "alu", "achieved": flops / (k_lz[name] * 1e-3)
+                         / 1e12, "peak": PEAKS["fp32"][0], "unit": "TFLOP/s",
+                         "frac": flops / (k_lz[name] * 1e-3) / 1e12 / PEAKS["fp32"][0],
+                         "work_per_launch": flops, "work_unit": "flop"}}
+    del G
+    torch.cuda.empty_cache()
+    B, Qp, m, r = 65536, 32, 64, 4
+    log(f"next rows: pisco_llr_svd B={B} m={m} Q={Qp} rank={r}")
+    X = llr_patches(B, Qp, m, r, seed=7)
+    V = torch.empty((r, Qp, B), dtype=torch.complex64, device="cuda")
+    Xr = torch.empty_like(X)
+    t_llr, k_llr = traced(lambda: P.pisco_llr_svd(est.h, X, r, V, Xr), steps)
+    bytes_min = 16.0 * m * Qp * B   # read X, write X V V^H
+    rep["llr_partial_svd"] = {
+        "patches": B, "m": m, "Q": Qp, "rank": r, "ms": t_llr * 1e3,
+        "Mpatch_s": B / t_llr / 1e6, "kernel_us": {k: v * 1e3 for k, v in k_llr.items()},
+        "hbm": {"algorithmic_bytes": bytes_min, "achieved": bytes_min / t_llr / 1e9,
+                "peak": PEAKS["hbm"][0], "unit": "GB/s",
+                "frac": bytes_min / t_llr / 1e9 / PEAKS["hbm"][0]}}
+    sig = P.pisco_llr_svd(est.h, X, r, V, Xr)
+    torch.cuda.synchronize()
+    rep["llr_partial_svd"]["sigma_mean"] = [float(v) for v in sig.mean(dim=1).cpu().numpy()]
+    rep["device_status"] = est.status()
+    del X, Xr, V
+    torch.cuda.empty_cache()
+    return rep
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -429,6 +533,8 @@ def main():
                     help="skip training and measuring the learned warm start")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the batch of 64 uneven slices in one graph launch")
+    ap.add_argument("--no-next-rows", action="store_true",
+                    help="skip the Lanczos and locally low-rank partial-SVD reports")
     ap.add_argument("--learned-scans", type=int, default=64,
                     help="training scans for the learned warm start")
     ap.add_argument("--breakdown", action="store_true", help="per-kernel times to stderr")
@@ -574,7 +680,7 @@ def main():
     for r in (mixed, plain, paper):
         r.pop("est", None)
     if args.mixed_only:
-        args.no_learned = args.no_batched = args.no_cpu_baseline = True
+        args.no_learned = args.no_batched = args.no_cpu_baseline = args.no_next_rows = True
 
     def form(r, tol, sweep):
         d = {"value": r["value"], "ms_per_step": r["ms"], "device_status": r["status"]}
@@ -615,6 +721,9 @@ def main():
         torch.cuda.empty_cache()
     if not args.no_batched:
         line["config"]["batched"] = batched_report(args.steps)
+    if not args.no_next_rows:
+        line["config"]["lanczos_and_partial_svd"] = next_rows_report(w, acs, args.steps)
+        log("next rows timed")
     if not args.no_cpu_baseline:
         big = int(np.prod(w.grid_lr)) * w.Q * w.Q > 50_000_000 or len(w.grid) == 3
         line["cpu_baseline"] = (cpu_baseline_sampled if big else cpu_baseline_full)(w, acs_np)

@@ -311,7 +311,13 @@ def pisco_llr_svd(h: Handle, X, rank: int, V=None, Xr=None):
     """Partial SVDs of the B Casorati matrices X (torch complex64 [B][Q][m]):
     returns sigma [rank][B] (and fills V [rank][Q][B], Xr [B][Q][m] if given)."""
     import torch
+    if X.dtype != torch.complex64 or X.dim() != 3 or not X.is_cuda:
+        raise ValueError("X: need a CUDA complex64 tensor [B][Q][m]")
     B, Q, m = (int(v) for v in X.shape)
+    for name, t, shape in (("V", V, (rank, Q, B)), ("Xr", Xr, (B, Q, m))):
+        if t is not None and (t.dtype != torch.complex64 or tuple(t.shape) != shape
+                              or not t.is_contiguous() or not t.is_cuda):
+            raise ValueError(f"{name}: need a contiguous CUDA complex64 tensor {list(shape)}")
     size = ctypes.c_size_t()
     _check(lib().pisco_llr_workspace_size(B, Q, rank, ctypes.byref(size)),
            "pisco_llr_workspace_size")

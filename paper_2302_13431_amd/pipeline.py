@@ -55,6 +55,24 @@ class Estimator:
     def _alloc(self, shape, dtype):
         return self.torch.empty(tuple(shape), dtype=dtype, device=self.dev)
 
+    def _need(self, x, nbytes: int, what: str):
+        """The library takes raw device pointers: refuse a buffer that is not
+        on the GPU or is smaller than the call reads or writes."""
+        if x is None:
+            return None
+        if not (hasattr(x, "is_cuda") and x.is_cuda):
+            raise ValueError(f"{what}: need a CUDA tensor")
+        have = x.numel() * x.element_size()
+        if have < nbytes:
+            raise ValueError(f"{what}: {have} bytes, the call needs {nbytes}")
+        return x.contiguous()
+
+    def _need_out(self, x, nbytes: int, what: str):
+        """An output buffer: as _need, and written in place, so contiguous."""
+        if x is not None and hasattr(x, "is_contiguous") and not x.is_contiguous():
+            raise ValueError(f"{what}: output must be contiguous")
+        return self._need(x, nbytes, what)
+
     def _ws(self):
         # 256-byte aligned view of the stage workspace
         base = self.ws_stage.data_ptr()
@@ -65,7 +83,8 @@ class Estimator:
     def gram(self, acs):
         t = self.torch
         out = self._alloc((self.n, self.n), t.complex64)
-        L.pisco_gram(self.h, self.prob, acs.contiguous(), out, self._ws())
+        acs = self._need(acs, 8 * self.Q * _prod(self.acs_shape), "acs")
+        L.pisco_gram(self.h, self.prob, acs, out, self._ws())
         return out
 
     def nullspace(self, gram):
@@ -74,14 +93,16 @@ class Estimator:
         eig = self._alloc((b,), t.float64)
         basis = self._alloc((b, self.n), t.complex128)
         counts = self._alloc((4,), t.int32)
-        L.pisco_nullspace(self.h, self.prob, self.opts, gram.contiguous(), eig, basis, counts,
-                          self._ws())
+        gram = self._need(gram, 8 * self.n * self.n, "gram")
+        L.pisco_nullspace(self.h, self.prob, self.opts, gram, eig, basis, counts, self._ws())
         return eig, basis, counts
 
     def gx(self, basis, counts):
         t = self.torch
         G = self._alloc((self.P, self.Nlr), t.complex64)
-        L.pisco_gx(self.h, self.prob, self.opts, basis.contiguous(), counts, G, self._ws())
+        basis = self._need(basis, 16 * self.block * self.n, "basis")
+        counts = self._need(counts, 16, "counts")
+        L.pisco_gx(self.h, self.prob, self.opts, basis, counts, G, self._ws())
         return G
 
     def eig(self, G, N: Optional[int] = None, opts: Optional[L.Opts] = None,
@@ -93,7 +114,8 @@ class Estimator:
         maps = self._alloc((Q, N), t.complex64)
         lam = self._alloc((N,), t.float32)
         it = self._alloc((N,), t.int32)
-        L.pisco_eig(self.h, Q, N, bound, opts or self.opts, G.contiguous(), maps, lam, it)
+        G = self._need(G, 4 * Q * (Q + 1) * N, "G")
+        L.pisco_eig(self.h, Q, N, bound, opts or self.opts, G, maps, lam, it)
         return maps, lam, it
 
     def eig_checked(self, G, init=None, opts: Optional[L.Opts] = None,
@@ -110,9 +132,10 @@ class Estimator:
         it = self._alloc((N,), t.int32)
         lam64 = self._alloc((N,), t.float64)
         res64 = self._alloc((N,), t.float64)
-        L.pisco_eig_checked(self.h, Q, N, bound, opts or self.opts, G.contiguous(),
-                            None if init is None else init.contiguous(), maps, lam, it, lam64,
-                            res64)
+        G = self._need(G, 4 * Q * (Q + 1) * N, "G")
+        init = self._need(init, 8 * Q * N, "init")
+        L.pisco_eig_checked(self.h, Q, N, bound, opts or self.opts, G, init, maps, lam, it,
+                            lam64, res64)
         return maps, lam, it, lam64, res64
 
     def eig_sets(self, G, sets: int = 1, krylov: Optional[int] = None, N: Optional[int] = None,
@@ -127,7 +150,8 @@ class Estimator:
         maps = self._alloc((sets, Q, N), t.complex64)
         lam = self._alloc((sets, N), t.float32)
         res = self._alloc((sets, N), t.float32)
-        L.pisco_eig_sets(self.h, Q, N, bound, sets, K, G.contiguous(), maps, lam, res)
+        G = self._need(G, 4 * Q * (Q + 1) * N, "G")
+        L.pisco_eig_sets(self.h, Q, N, bound, sets, K, G, maps, lam, res)
         return maps, lam, res
 
     def eig_from(self, G, init, opts: Optional[L.Opts] = None):
@@ -137,22 +161,26 @@ class Estimator:
         maps = self._alloc((self.Q, N), t.complex64)
         lam = self._alloc((N,), t.float32)
         it = self._alloc((N,), t.int32)
-        L.pisco_eig_from(self.h, self.Q, N, float(self.nsup), opts or self.opts, G.contiguous(),
-                         init.contiguous(), maps, lam, it)
+        G = self._need(G, 4 * self.Q * (self.Q + 1) * N, "G")
+        init = self._need(init, 8 * self.Q * N, "init")
+        L.pisco_eig_from(self.h, self.Q, N, float(self.nsup), opts or self.opts, G, init, maps,
+                         lam, it)
         return maps, lam, it
 
     def maps(self, acs, maps_lr):
         t = self.torch
         out = self._alloc((self.Q,) + self.grid_out, t.complex64)
-        L.pisco_maps(self.h, self.prob, self.opts, acs.contiguous(), maps_lr.contiguous(), out,
-                     self._ws())
+        acs = self._need(acs, 8 * self.Q * _prod(self.acs_shape), "acs")
+        maps_lr = self._need(maps_lr, 8 * self.Q * self.Nlr, "maps_lr")
+        L.pisco_maps(self.h, self.prob, self.opts, acs, maps_lr, out, self._ws())
         return out
 
     def support_mask(self, lam, thresh: float = 0.1):
         """uint8 mask on grid_out from a low-res lambda_min map (pisco_support_mask)."""
         t = self.torch
         mask = self._alloc(self.grid_out, t.uint8)
-        L.pisco_support_mask(self.h, self.prob, lam.contiguous(), thresh, mask, self._ws())
+        lam = self._need(lam, 4 * self.Nlr, "lam")
+        L.pisco_support_mask(self.h, self.prob, lam, thresh, mask, self._ws())
         return mask
 
     def espirit_operator(self, G, Q: Optional[int] = None, N: Optional[int] = None,
@@ -161,8 +189,9 @@ class Estimator:
         Q = self.Q if Q is None else int(Q)
         N = self.Nlr if N is None else int(N)
         bound = float(self.nsup) if bound is None else float(bound)
+        G = self._need(G, 4 * Q * (Q + 1) * N, "G")
         B = self.torch.empty_like(G)
-        L.pisco_espirit_operator(self.h, Q, N, bound, G.contiguous(), B)
+        L.pisco_espirit_operator(self.h, Q, N, bound, G, B)
         return B
 
     def estimate(self, acs, out=None, lam=None):
@@ -176,7 +205,10 @@ class Estimator:
             out = self._alloc((self.Q,) + self.grid_out, t.complex64)
         if lam is None:
             lam = self._alloc((self.Nlr,), t.float32)
-        L.pisco_estimate(self.h, self.prob, self.opts, acs.contiguous(), out, lam, ws)
+        acs = self._need(acs, 8 * self.Q * _prod(self.acs_shape), "acs")
+        self._need_out(out, 8 * self.Q * self.Nout, "out")
+        self._need_out(lam, 4 * self.Nlr, "lam")
+        L.pisco_estimate(self.h, self.prob, self.opts, acs, out, lam, ws)
         return out, lam
 
     def status(self) -> int:

@@ -485,3 +485,29 @@ def test_workspace_too_small_is_rejected():
     with pytest.raises(P.PiscoError) as ex:
         P.pisco_gram(est.h, est.prob, cuda(acs), gram, tiny)
     assert ex.value.status == 2
+
+
+def test_binding_refuses_undersized_buffers():
+    """The library takes raw device pointers, so the binding checks every
+    buffer against the bytes the call will touch and raises before any
+    launch: a basis argument that is really the eigenvalue vector, a G field
+    for fewer voxels, a CPU tensor, a non-contiguous output."""
+    name = "2d_64x64_q8_acs24_r3"
+    w, acs = scan_inputs(name)
+    est = estimator(name)
+    ev = torch.zeros(est.block, dtype=torch.float64, device="cuda")
+    counts = torch.zeros(4, dtype=torch.int32, device="cuda")
+    with pytest.raises(ValueError, match="basis"):
+        est.gx(ev, counts)
+    G_small = torch.zeros((est.P, est.Nlr - 1), dtype=torch.complex64, device="cuda")
+    for call in (lambda: est.eig(G_small), lambda: est.eig_sets(G_small),
+                 lambda: est.espirit_operator(G_small)):
+        with pytest.raises(ValueError, match="G"):
+            call()
+    with pytest.raises(ValueError, match="CUDA"):
+        est.gram(torch.from_numpy(acs))
+    out = torch.empty((w.Q,) + tuple(w.grid)[::-1], dtype=torch.complex64,
+                      device="cuda").transpose(1, 2)
+    with pytest.raises(ValueError, match="contiguous"):
+        est.estimate(cuda(acs), out)
+    assert est.status() == 0
