@@ -302,7 +302,9 @@ pisco_status_t pisco_eig_checked(pisco_handle_t handle, int32_t Q, int64_t N,
  * steps (Sec. IV-E: the remedy the paper names where the two smallest
  * singular values are close and power iteration is slow; Sec. III-B
  * footnote: one set of maps per small eigenvalue when the field of view is
- * too small).  Lanczos on G(x) from e_q* with full reorthogonalisation, the
+ * too small).  Lanczos on G(x) from e_q* (three-term recurrence and one
+ * full reorthogonalisation pass per step; restarts from the least covered
+ * coordinate after an invariant subspace), the
  * tridiagonal projection solved in FP64, Ritz vectors of the smallest Ritz
  * values; with krylov = Q the pairs are G's own to FP32 rounding.
  *   G     : float2 packed as from pisco_gx, N voxels
@@ -311,10 +313,14 @@ pisco_status_t pisco_eig_checked(pisco_handle_t handle, int32_t Q, int64_t N,
  *   sets  : 1..min(8, krylov);  krylov : 1..Q
  *   maps  : float2 [sets][Q][N], unit-norm eigenvectors, ascending eigenvalue
  *   lam   : float [sets][N], Rayleigh quotients c^H G c
- *   resid : float [sets][N], ||G c - lam c|| (may be NULL) */
+ *   resid : float [sets][N], ||G c - lam c|| (may be NULL)
+ * Workspace: pisco_eig_sets_workspace_size bytes (a voxel-major copy of G,
+ * Q(Q+1)/2 * N * 8 bytes), 256-byte aligned; the call allocates nothing. */
+pisco_status_t pisco_eig_sets_workspace_size(int32_t Q, int64_t N, size_t* bytes);
 pisco_status_t pisco_eig_sets(pisco_handle_t handle, int32_t Q, int64_t N, float bound,
                               int32_t sets, int32_t krylov, const void* G, void* maps,
-                              float* lam, float* resid);
+                              float* lam, float* resid, void* workspace,
+                              size_t workspace_bytes);
 
 /* Many small partial SVDs at once (locally low-rank models, which Sec. I
  * and Sec. V name as beneficiaries of the method's batched small

@@ -6,7 +6,7 @@ helper that allocates device buffers with torch.
 """
 from ._lib import (  # noqa: F401
     Handle, Opts, PiscoError, Problem, lib, make_opts, make_problem, pisco_eig,
-    pisco_eig_checked, pisco_eig_from, pisco_eig_sets, pisco_espirit_operator, pisco_estimate, pisco_gram, pisco_gram_static,
+    pisco_eig_checked, pisco_eig_from, pisco_eig_sets, pisco_eig_sets_workspace_size, pisco_espirit_operator, pisco_estimate, pisco_gram, pisco_gram_static,
     pisco_gram_static_bytes, pisco_gx, pisco_llr_svd, pisco_maps, pisco_nullspace, pisco_nullspace_block,
     pisco_support, pisco_support_mask, pisco_status_string, pisco_trace_enable, pisco_trace_read,
     pisco_workspace_size, pisco_ws_forward, pisco_ws_init, pisco_ws_neighbor,

@@ -75,8 +75,10 @@ _SIGS = {
     "pisco_gram_static": ([_P, ctypes.POINTER(Problem), _P, _P], ctypes.c_int),
     "pisco_gram_static_bytes": ([ctypes.POINTER(Problem), ctypes.POINTER(ctypes.c_size_t),
                                  ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
+    "pisco_eig_sets_workspace_size": ([ctypes.c_int32, ctypes.c_int64,
+                                       ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
     "pisco_eig_sets": ([_P, ctypes.c_int32, ctypes.c_int64, ctypes.c_float, ctypes.c_int32,
-                        ctypes.c_int32, _P, _P, _P, _P], ctypes.c_int),
+                        ctypes.c_int32, _P, _P, _P, _P, _P, ctypes.c_size_t], ctypes.c_int),
     "pisco_llr_workspace_size": ([ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
                                   ctypes.POINTER(ctypes.c_size_t)], ctypes.c_int),
     "pisco_llr_svd": ([_P, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P,
@@ -301,10 +303,25 @@ def pisco_eig_checked(h: Handle, Q: int, N: int, bound: float, opts: Opts, G, in
                                    _ptr(resid64), None, 0), "pisco_eig_checked", h.h)
 
 
+def pisco_eig_sets_workspace_size(Q: int, N: int) -> int:
+    size = ctypes.c_size_t()
+    _check(lib().pisco_eig_sets_workspace_size(Q, N, ctypes.byref(size)),
+           "pisco_eig_sets_workspace_size")
+    return size.value
+
+
 def pisco_eig_sets(h: Handle, Q: int, N: int, bound: float, sets: int, krylov: int, G, maps,
-                   lam, resid=None):
+                   lam, resid=None, ws=None):
+    """ws: a 256-byte aligned device buffer of pisco_eig_sets_workspace_size
+    bytes (allocated here through torch when None)."""
+    if ws is None:
+        import torch
+        size = pisco_eig_sets_workspace_size(Q, N)
+        raw = torch.empty(size + 256, dtype=torch.uint8, device=G.device)
+        ws = raw[(-raw.data_ptr()) % 256:]
     _check(lib().pisco_eig_sets(h.h, Q, N, bound, sets, krylov, _ptr(G), _ptr(maps), _ptr(lam),
-                                _ptr(resid)), "pisco_eig_sets", h.h)
+                                _ptr(resid), _ptr(ws), ws.numel() * ws.element_size()),
+           "pisco_eig_sets", h.h)
 
 
 def pisco_llr_svd(h: Handle, X, rank: int, V=None, Xr=None):

@@ -497,9 +497,15 @@ pisco_status_t pisco_maps(pisco_handle_t handle, const pisco_problem_t* prob,
                   static_cast<const float2*>(maps_lr), static_cast<float2*>(maps_out), scratch);
 }
 
+pisco_status_t pisco_eig_sets_workspace_size(int32_t Q, int64_t N, size_t* bytes) {
+  if (!bytes || Q < 2 || Q > kMaxQ || N < 0) return PISCO_ERR_ARG;
+  *bytes = layout_eig_sets(Q, N);
+  return PISCO_OK;
+}
+
 pisco_status_t pisco_eig_sets(pisco_handle_t handle, int32_t Q, int64_t N, float bound,
                               int32_t sets, int32_t krylov, const void* G, void* maps,
-                              float* lam, float* resid) {
+                              float* lam, float* resid, void* ws, size_t ws_bytes) {
   Handle* h = reinterpret_cast<Handle*>(handle);
   if (!h) return PISCO_ERR_ARG;
   if (Q < 2 || Q > kMaxQ) return fail(h, PISCO_ERR_ARG, "Q must be in [2, 32]");
@@ -508,9 +514,12 @@ pisco_status_t pisco_eig_sets(pisco_handle_t handle, int32_t Q, int64_t N, float
   if (krylov < 1 || krylov > Q) return fail(h, PISCO_ERR_ARG, "krylov must be in [1, Q]");
   if (sets < 1 || sets > 8 || sets > krylov)
     return fail(h, PISCO_ERR_ARG, "sets must be in [1, min(8, krylov)]");
-  if (N > 0 && (!G || !maps || !lam)) return fail(h, PISCO_ERR_ARG, "null pointer");
+  if (N > 0 && (!G || !maps || !lam || !ws || !aligned(ws)))
+    return fail(h, PISCO_ERR_ARG, "null or unaligned pointer");
+  if (ws_bytes < layout_eig_sets(Q, N))
+    return fail(h, PISCO_ERR_WORKSPACE, "workspace too small for pisco_eig_sets");
   return run_eig_sets(h, Q, N, bound, krylov, sets, static_cast<const float2*>(G),
-                      static_cast<float2*>(maps), lam, resid);
+                      static_cast<float2*>(maps), lam, resid, ws);
 }
 
 pisco_status_t pisco_llr_workspace_size(int64_t B, int32_t Q, int32_t rank, size_t* bytes) {
@@ -526,6 +535,7 @@ pisco_status_t pisco_llr_svd(pisco_handle_t handle, int64_t B, int32_t m, int32_
   Handle* h = reinterpret_cast<Handle*>(handle);
   if (!h) return PISCO_ERR_ARG;
   if (B < 0 || m < 1) return fail(h, PISCO_ERR_ARG, "need B >= 0 and m >= 1");
+  if (B > 0x7fffffffLL) return fail(h, PISCO_ERR_ARG, "B must be < 2^31 (one workgroup per patch)");
   if (Q < 2 || Q > kMaxQ) return fail(h, PISCO_ERR_ARG, "Q must be in [2, 32]");
   if (rank < 1 || rank > 8 || rank > Q) return fail(h, PISCO_ERR_ARG, "rank must be in [1, min(8, Q)]");
   if (B > 0 && (!X || !sigma || !ws || !aligned(ws)))

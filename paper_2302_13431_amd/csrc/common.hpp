@@ -34,6 +34,15 @@ __host__ __device__ inline float2 cscale(float2 a, float s) {
 }
 __host__ __device__ inline float cabs2(float2 a) { return a.x * a.x + a.y * a.y; }
 
+// Orders the LDS accesses of one wave around it, for kernels whose
+// workgroup is a single wave (a wave's LDS operations are performed in
+// order): no s_barrier and no wait on memory counters.
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 __host__ __device__ inline double2 zmul(double2 a, double2 b) {
   return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
@@ -284,8 +293,14 @@ pisco_status_t run_maps(Handle* h, const Plan& p, const Tables& t, int phase_rul
 
 // The M smallest eigenpairs per voxel by K Lanczos steps (1 <= M <= 8,
 // M <= K <= Q): maps [M][Q][N], lam [M][N], resid [M][N] (nullable).
+// run_eig_sets takes G entry-major ([Q(Q+1)/2][N], as from the G(x) stage)
+// and copies it voxel-major into ws (layout_eig_sets bytes);
+// run_lanczos_vm takes G voxel-major ([N][Q(Q+1)/2]) directly.
+size_t layout_eig_sets(int Q, long long N);
 pisco_status_t run_eig_sets(Handle* h, int Q, long long N, float bound, int K, int M,
-                            const float2* G, float2* maps, float* lam, float* resid);
+                            const float2* G, float2* maps, float* lam, float* resid, void* ws);
+pisco_status_t run_lanczos_vm(Handle* h, int Q, long long N, float bound, int K, int M,
+                              const float2* Gvm, float2* maps, float* lam, float* resid);
 
 // Partial SVDs of B Casorati matrices X [B][Q][m] (r <= min(8, Q)): sigma
 // [r][B], right singular vectors [r][Q][B] (Vout nullable: in ws), rank-r
