@@ -32,7 +32,7 @@
 // subtracts sum_i h_i v_i from its component.  One wave per workgroup lets
 // the LDS exchanges be ordered without barriers.  The Sturm-count
 // multisection spreads QG probes over the lanes, so every round narrows the
-// interval QG + 1 fold.  Workgroups are dealt to
+// interval QG + 1 fold (QG / M + 1 fold for each of M sets).  Workgroups are dealt to
 // the eight XCDs in contiguous voxel ranges, so that the lines of G(x) one
 // workgroup reads are shared in its XCD's L2 with its neighbours.
 #include <cfloat>
@@ -49,6 +49,18 @@ __device__ inline int lz_pidx(int p, int q, int Q) {  // p <= q
 }
 
 constexpr int kMaxSets = 8;
+
+// a / b as a times the hardware reciprocal refined by one Newton step
+// (relative error about 2e-15 from the estimate's 4.6e-8): four
+// instructions in place of the ten of the IEEE division, in the Sturm counts
+// and the twisted factorisation of T
+struct FastDiv {
+  __device__ static double div(double a, double b) {
+    const double r0 = __builtin_amdgcn_rcp(b);
+    const double e = fma(-b, r0, 1.0);
+    return a * fma(r0, e, r0);
+  }
+};
 constexpr int kXcds = 8;
 
 // Workgroup b of nb is dispatched to XCD b % 8; the logical index gives each
@@ -57,6 +69,83 @@ __device__ inline long long xcd_block(unsigned b, unsigned nb) {
   const unsigned x = b % kXcds, k = b / kXcds, q = nb / kXcds, r = nb % kXcds;
   const unsigned base = x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q;
   return (long long)base + k;
+}
+
+// The twisted factorisation of tri::twisted_vector on two lanes: lane 0
+// runs the top-down pivots D+ (kept in z) and multipliers Lp while lane 1
+// runs the bottom-up pivots D- (kept in Dm) and multipliers Um; the twist
+// r = argmin_i |gamma_i| (the largest such i, as the serial scan from the
+// bottom takes it), gamma_i = D+_i + D-_i - (d_i - lambda), gamma_(n-1) =
+// D+_(n-1); then lane 0 forms z above r and lane 1 below, and both scale
+// their parts to unit norm.  Called by every lane of the group (the lanes
+// past 1 only synchronise); z, Lp, Um, Dm are n-length LDS arrays.
+__device__ inline void twisted2(const double* d, const double* e, int n, double lambda,
+                                double pivmin, double* Lp, double* Um, double* Dm, double* z,
+                                int lane) {
+  if (n == 1) {
+    if (lane == 0) z[0] = 1.0;
+    wave_sync();
+    return;
+  }
+  if (lane == 0) {
+    double dp = d[0] - lambda;
+    if (fabs(dp) < pivmin) dp = -pivmin;
+    z[0] = dp;
+    for (int i = 0; i + 1 < n; ++i) {
+      Lp[i] = FastDiv::div(e[i], dp);
+      dp = d[i + 1] - lambda - Lp[i] * e[i];
+      if (fabs(dp) < pivmin) dp = -pivmin;
+      z[i + 1] = dp;
+    }
+  } else if (lane == 1) {
+    double dm = d[n - 1] - lambda;
+    if (fabs(dm) < pivmin) dm = -pivmin;
+    Dm[n - 1] = dm;
+    for (int i = n - 1; i > 0; --i) {
+      Um[i] = FastDiv::div(e[i - 1], dm);
+      const double dn = d[i - 1] - lambda - Um[i] * e[i - 1];
+      dm = fabs(dn) < pivmin ? -pivmin : dn;
+      Dm[i - 1] = dm;
+    }
+  }
+  wave_sync();
+  int r = n - 1;
+  if (lane < 2) {
+    double best = fabs(z[n - 1]);
+    for (int i = n - 2; i >= 0; --i) {
+      const double gamma = z[i] + Dm[i] - (d[i] - lambda);
+      if (fabs(gamma) < best) {
+        best = fabs(gamma);
+        r = i;
+      }
+    }
+  }
+  wave_sync();  // every lane has read the pivots before z is overwritten
+  double s = 0.0;
+  if (lane == 0) {
+    double zi = 1.0;
+    for (int i = r - 1; i >= 0; --i) {
+      zi = -Lp[i] * zi;
+      z[i] = zi;
+      s += zi * zi;
+    }
+  } else if (lane == 1) {
+    double zi = 1.0;
+    for (int i = r + 1; i < n; ++i) {
+      zi = -Um[i] * zi;
+      z[i] = zi;
+      s += zi * zi;
+    }
+  }
+  if (lane < 2) Dm[lane] = s;  // partial sums of squares (Dm is free again)
+  wave_sync();
+  if (lane == 0) z[r] = 1.0;
+  const double inv = 1.0 / sqrt(1.0 + Dm[0] + Dm[1]);
+  wave_sync();
+  if (lane == 0)
+    for (int i = 0; i <= r; ++i) z[i] *= inv;
+  else if (lane == 1)
+    for (int i = r + 1; i < n; ++i) z[i] *= inv;
 }
 
 // G voxel-major: [N][Q(Q+1)/2], packed upper triangle of each voxel
@@ -73,6 +162,7 @@ __global__ void __launch_bounds__(64) k_lanczos(const float2* __restrict__ G, in
   __shared__ __align__(16) float2 xch[NG][QG];     // a vector or its coefficients
   __shared__ __align__(16) float red[NG][QG];
   __shared__ double td[NG][QG], te[NG][QG], te2[NG][QG], tz[NG][QG], tw[NG][2][QG];
+  __shared__ double th[NG][kMaxSets];
   const int lane = threadIdx.x % QG, grp = threadIdx.x / QG;
   const long long v0 = xcd_block(blockIdx.x, gridDim.x) * NG;
   const long long vraw = v0 + grp;
@@ -84,11 +174,21 @@ __global__ void __launch_bounds__(64) k_lanczos(const float2* __restrict__ G, in
   // in the basis area by coalesced loads (zeros past N), then every lane
   // takes its row
   {
+    constexpr int kIt = (NG * (QG * (QG + 1) / 2) + 63) / 64;  // loads per lane, at most
     float2* stage = &Vs[0][0][0];
     const int cnt = int((N - v0 < NG ? N - v0 : NG) * P);
     const float2* src = G + size_t(v0) * P;
-    for (int e = threadIdx.x; e < NG * P; e += 64)
-      stage[e] = e < cnt ? src[e] : make_float2(0.f, 0.f);
+    float2 tmp[kIt];
+#pragma unroll
+    for (int k = 0; k < kIt; ++k) {  // all loads in flight before the first store
+      const int e = threadIdx.x + 64 * k;
+      tmp[k] = e < cnt ? src[e] : make_float2(0.f, 0.f);
+    }
+#pragma unroll
+    for (int k = 0; k < kIt; ++k) {
+      const int e = threadIdx.x + 64 * k;
+      if (e < NG * P) stage[e] = tmp[k];
+    }
   }
   wave_sync();
   const float2* mine = &Vs[0][0][0] + grp * P;
@@ -148,20 +248,25 @@ __global__ void __launch_bounds__(64) k_lanczos(const float2* __restrict__ G, in
     }
   }
   wave_sync();
-  // y = G x, x given by its QG components in LDS (16-byte aligned)
+  // y = G x, x given by its QG components in LDS (16-byte aligned); four
+  // partial sums keep four independent FMA chains in flight
   auto matvec = [&](const float2* xv) {
     const float4* x4 = reinterpret_cast<const float4*>(xv);
-    float2 y = make_float2(0.f, 0.f);
+    float2 y[4] = {make_float2(0.f, 0.f), make_float2(0.f, 0.f), make_float2(0.f, 0.f),
+                   make_float2(0.f, 0.f)};
 #pragma unroll
     for (int p2 = 0; p2 < QG / 2; ++p2) {
       const float4 x = x4[p2];
       const float2 a = g[2 * p2], b = g[2 * p2 + 1];
-      y.x = fmaf(a.x, x.x, fmaf(-a.y, x.y, y.x));
-      y.y = fmaf(a.x, x.y, fmaf(a.y, x.x, y.y));
-      y.x = fmaf(b.x, x.z, fmaf(-b.y, x.w, y.x));
-      y.y = fmaf(b.x, x.w, fmaf(b.y, x.z, y.y));
+      float2& u = y[(2 * p2) & 3];
+      float2& w = y[(2 * p2 + 1) & 3];
+      u.x = fmaf(a.x, x.x, fmaf(-a.y, x.y, u.x));
+      u.y = fmaf(a.x, x.y, fmaf(a.y, x.x, u.y));
+      w.x = fmaf(b.x, x.z, fmaf(-b.y, x.w, w.x));
+      w.y = fmaf(b.x, x.w, fmaf(b.y, x.z, w.y));
     }
-    return y;
+    return make_float2((y[0].x + y[1].x) + (y[2].x + y[3].x),
+                       (y[0].y + y[1].y) + (y[2].y + y[3].y));
   };
   // one classical Gram-Schmidt pass of w against rows 0..cnt-1 of Vs;
   // returns the new w and (in hl) the coefficient of row cnt - 1
@@ -172,18 +277,25 @@ __global__ void __launch_bounds__(64) k_lanczos(const float2* __restrict__ G, in
     if (lane < cnt) {
       const float4* b4 = reinterpret_cast<const float4*>(Vs[grp][lane]);
       const float4* x4 = reinterpret_cast<const float4*>(xch[grp]);
+      float2 a[4] = {make_float2(0.f, 0.f), make_float2(0.f, 0.f), make_float2(0.f, 0.f),
+                     make_float2(0.f, 0.f)};
 #pragma unroll
       for (int p2 = 0; p2 < QG / 2; ++p2) {
         const float4 b = b4[p2], x = x4[p2];
-        h.x = fmaf(b.x, x.x, fmaf(b.y, x.y, h.x));
-        h.y = fmaf(b.x, x.y, fmaf(-b.y, x.x, h.y));
-        h.x = fmaf(b.z, x.z, fmaf(b.w, x.w, h.x));
-        h.y = fmaf(b.z, x.w, fmaf(-b.w, x.z, h.y));
+        float2& u = a[(2 * p2) & 3];
+        float2& t = a[(2 * p2 + 1) & 3];
+        u.x = fmaf(b.x, x.x, fmaf(b.y, x.y, u.x));
+        u.y = fmaf(b.x, x.y, fmaf(-b.y, x.x, u.y));
+        t.x = fmaf(b.z, x.z, fmaf(b.w, x.w, t.x));
+        t.y = fmaf(b.z, x.w, fmaf(-b.w, x.z, t.y));
       }
+      h = make_float2((a[0].x + a[1].x) + (a[2].x + a[3].x),
+                      (a[0].y + a[1].y) + (a[2].y + a[3].y));
     }
     wave_sync();
     xch[grp][lane] = h;  // zero beyond cnt
     wave_sync();
+    float2 w1 = make_float2(0.f, 0.f);  // odd rows, summed apart
     for (int i0 = 0; i0 < cnt; i0 += CH) {
 #pragma unroll
       for (int ii = 0; ii < CH; ii += 2) {
@@ -191,10 +303,12 @@ __global__ void __launch_bounds__(64) k_lanczos(const float2* __restrict__ G, in
         const float2 b0 = Vs[grp][i0 + ii][lane], b1 = Vs[grp][i0 + ii + 1][lane];
         w.x -= hh.x * b0.x - hh.y * b0.y;
         w.y -= hh.x * b0.y + hh.y * b0.x;
-        w.x -= hh.z * b1.x - hh.w * b1.y;
-        w.y -= hh.z * b1.y + hh.w * b1.x;
+        w1.x += hh.z * b1.x - hh.w * b1.y;
+        w1.y += hh.z * b1.y + hh.w * b1.x;
       }
     }
+    w.x -= w1.x;
+    w.y -= w1.y;
     *hl = xch[grp][cnt - 1];
     wave_sync();
     return w;
@@ -278,11 +392,13 @@ __global__ void __launch_bounds__(64) k_lanczos(const float2* __restrict__ G, in
     Vs[grp][j + 1][lane] = x;
   }
   wave_sync();
-  // T's M smallest eigenpairs in FP64: the group's lanes share the
-  // multisection (one probe per lane and round), to an absolute width of
-  // 4 eps ||T|| (the accuracy the twisted factorisation needs);
-  // lane 0 forms the vector by the twisted factorisation; all lanes form the
-  // Ritz vector
+  // T's M smallest eigenpairs in FP64.  The group's lanes share the
+  // multisection of all M eigenvalues at once: set s takes lanes
+  // [s W, s W + W), W = QG / M, one probe each per round (W + 1 fold), to an
+  // absolute width of 1e-13 ||T|| (a twisted-factorisation vector is off by
+  // about that width over the gap: 1e-8 at the closest pairs kept apart in
+  // FP32, gaps of 1e-5 ||T||); lanes 0 and 1 then form each vector by the
+  // twisted factorisation and all lanes form the Ritz vector.
   double emax2 = 0.0;
   for (int i = 0; i < K; ++i) {
     const double e = te[grp][i];
@@ -292,38 +408,52 @@ __global__ void __launch_bounds__(64) k_lanczos(const float2* __restrict__ G, in
   const double pivmin = DBL_MIN * fmax(1.0, emax2);
   double glo, ghi;
   tri::gershgorin(td[grp], te[grp], K, &glo, &ghi);
-  const double abstol = 4.0 * DBL_EPSILON * fmax(fabs(glo), fabs(ghi));
+  const double abstol = 1e-13 * fmax(fabs(glo), fabs(ghi));
   wave_sync();
   const unsigned long long gmask = ((1ull << QG) - 1ull) << (QG * grp);
+  {
+    const int W = QG / M, set = lane / W, k = lane - set * W;
+    const bool mine = set < M;  // lanes past M W probe nothing of use
+    const unsigned long long wmask = (1ull << W) - 1ull;
+    double lo = glo, hi = ghi;
+    for (int round = 0; round < 128; ++round) {
+      const bool open = mine && hi - lo > abstol + 4.4e-16 * fmax(fabs(lo), fabs(hi));
+      if (!(__ballot(open) & gmask)) break;
+      const double step = (hi - lo) / double(W + 1);
+      const int c = tri::negcount<FastDiv>(td[grp], te2[grp], K, lo + step * double(k + 1),
+                                           pivmin);
+      const unsigned long long above = (__ballot(mine && c > set) & gmask) >> (QG * grp);
+      const unsigned long long seg = mine ? (above >> (set * W)) & wmask : 0ull;
+      // first probe of the set above its eigenvalue (probe f at lo + (f + 1) step)
+      double nlo, nhi;
+      if (seg) {
+        const int f = __ffsll((long long)seg) - 1;
+        nhi = lo + step * double(f + 1);
+        nlo = f > 0 ? lo + step * double(f) : lo;
+      } else {
+        nlo = lo + step * double(W);
+        nhi = hi;
+      }
+      if (open) {
+        if (nhi - nlo < hi - lo) {
+          lo = nlo;
+          hi = nhi;
+        } else {  // no progress left in FP64
+          lo = hi = 0.5 * (lo + hi);
+        }
+      }
+    }
+    if (mine && k == 0) th[grp][set] = 0.5 * (lo + hi);
+  }
+  wave_sync();
   float2 u[kMaxSets];
 #pragma unroll
   for (int m = 0; m < kMaxSets; ++m) u[m] = make_float2(0.f, 0.f);
 #pragma unroll
   for (int m = 0; m < kMaxSets; ++m) {
     if (m >= M) break;
-    double lo = glo, hi = ghi;
-    for (int round = 0; round < 64; ++round) {
-      if (hi - lo <= abstol + 4.4e-16 * fmax(fabs(lo), fabs(hi))) break;
-      const double step = (hi - lo) / double(QG + 1);
-      const int c = tri::negcount(td[grp], te2[grp], K, lo + step * double(lane + 1), pivmin);
-      const unsigned long long above = (__ballot(c > m) & gmask) >> (QG * grp);
-      // first probe above the m-th eigenvalue (probe f sits at lo + (f + 1) step)
-      double nlo, nhi;
-      if (above) {
-        const int f = __ffsll((long long)above) - 1;
-        nhi = lo + step * double(f + 1);
-        nlo = f > 0 ? lo + step * double(f) : lo;
-      } else {
-        nlo = lo + step * double(QG);
-        nhi = hi;
-      }
-      if (!(nhi - nlo < hi - lo)) break;  // no progress left in FP64
-      lo = nlo;
-      hi = nhi;
-    }
-    const double theta = 0.5 * (lo + hi);
-    if (lane == 0)
-      tri::twisted_vector(td[grp], te[grp], K, theta, pivmin, tw[grp][0], tw[grp][1], tz[grp]);
+    twisted2(td[grp], te[grp], K, th[grp][m], pivmin, tw[grp][0], tw[grp][1], te2[grp],
+             tz[grp], lane);
     wave_sync();
     float2 r = make_float2(0.f, 0.f);
     for (int i = 0; i < K; ++i) {

@@ -21,8 +21,15 @@
 namespace pisco {
 namespace tri {
 
+// Division used by the recurrences below: IEEE a / b by default; a caller
+// may pass a policy with its own (a reciprocal refined by Newton's method).
+struct ExactDiv {
+  PISCO_HD static double div(double a, double b) { return a / b; }
+};
+
 // Number of eigenvalues of T smaller than x (Sturm count of the LDL^T
 // pivots).  e2[i] = e[i]^2; pivmin guards zero pivots.
+template <class Div = ExactDiv>
 PISCO_HD inline int negcount(const double* d, const double* e2, int n, double x,
                              double pivmin) {
   int c = 0;
@@ -30,7 +37,7 @@ PISCO_HD inline int negcount(const double* d, const double* e2, int n, double x,
   if (std::fabs(q) < pivmin) q = -pivmin;
   c += q < 0.0;
   for (int i = 1; i < n; ++i) {
-    q = d[i] - x - e2[i - 1] / q;
+    q = d[i] - x - Div::div(e2[i - 1], q);
     if (std::fabs(q) < pivmin) q = -pivmin;
     c += q < 0.0;
   }
@@ -53,6 +60,7 @@ PISCO_HD inline void gershgorin(const double* d, const double* e, int n, double*
 
 // j-th smallest eigenvalue (0-based) by bisection in [lo, hi] to a width of
 // about 4 eps max(|lo|,|hi|) + abstol.
+template <class Div = ExactDiv>
 PISCO_HD inline double bisect(const double* d, const double* e2, int n, int j, double lo,
                               double hi, double pivmin, double abstol) {
   for (int it = 0; it < 200; ++it) {
@@ -61,7 +69,7 @@ PISCO_HD inline double bisect(const double* d, const double* e2, int n, int j, d
     if (w <= 4.4e-16 * std::fmax(std::fabs(lo), std::fabs(hi)) + abstol || mid == lo ||
         mid == hi)
       break;
-    if (negcount(d, e2, n, mid, pivmin) > j)
+    if (negcount<Div>(d, e2, n, mid, pivmin) > j)
       hi = mid;
     else
       lo = mid;
@@ -71,6 +79,7 @@ PISCO_HD inline double bisect(const double* d, const double* e2, int n, int j, d
 
 // Eigenvector z (length n, unit 2-norm) of T for the eigenvalue lambda by the
 // twisted factorisation.  Lp, Um are n-length scratch arrays.
+template <class Div = ExactDiv>
 PISCO_HD inline void twisted_vector(const double* d, const double* e, int n, double lambda,
                                     double pivmin, double* Lp, double* Um, double* z) {
   if (n == 1) {
@@ -83,7 +92,7 @@ PISCO_HD inline void twisted_vector(const double* d, const double* e, int n, dou
   // store D+ in z temporarily, L+ in Lp
   z[0] = dp;
   for (int i = 0; i + 1 < n; ++i) {
-    Lp[i] = e[i] / dp;
+    Lp[i] = Div::div(e[i], dp);
     dp = d[i + 1] - lambda - Lp[i] * e[i];
     if (std::fabs(dp) < pivmin) dp = -pivmin;
     z[i + 1] = dp;
@@ -94,7 +103,7 @@ PISCO_HD inline void twisted_vector(const double* d, const double* e, int n, dou
   int r = n - 1;
   double best = std::fabs(z[n - 1]);  // gamma_{n-1} = D+(n-1)
   for (int i = n - 1; i > 0; --i) {
-    Um[i] = e[i - 1] / dm;
+    Um[i] = Div::div(e[i - 1], dm);
     const double dnext = d[i - 1] - lambda - Um[i] * e[i - 1];
     dm = std::fabs(dnext) < pivmin ? -pivmin : dnext;
     const double gamma = z[i - 1] + dm - (d[i - 1] - lambda);

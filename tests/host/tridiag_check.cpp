@@ -43,6 +43,17 @@ static void hetrd(std::vector<cd>& A, int b, std::vector<cd>& refl, std::vector<
   d[b-1] = A[size_t(b-1)*b + b-1].real();
 }
 
+// Division by a reciprocal with the worst relative error of the hardware
+// estimate (4.6e-8, measured over 2^20 values) refined by one Newton step,
+// as the per-voxel Lanczos solver divides on the device.
+struct NewtonDiv {
+  static double div(double a, double b) {
+    const double r0 = (1.0 / b) * (1.0 + 4.6e-8);
+    const double e = std::fma(-b, r0, 1.0);
+    return a * std::fma(r0, e, r0);
+  }
+};
+
 int main(int argc, char** argv) {
   int b = argc > 1 ? atoi(argv[1]) : 96;
   int mode = argc > 2 ? atoi(argv[2]) : 0;
@@ -76,6 +87,34 @@ int main(int argc, char** argv) {
   std::vector<double> lam(b);
   for (int j = 0; j < b; ++j) lam[j] = bisect(d.data(), e2.data(), b, j, lo, hi, pivmin, 0.0);
   double nrm = std::max(std::fabs(lam[0]), std::fabs(lam[b-1]));
+  // the same eigenvalues and single-eigenvalue vectors with the refined
+  // reciprocal in place of the division
+  {
+    std::vector<double> Lq(b), Uq(b), zq(b);
+    for (int j = 0; j < b; ++j) {
+      const double l2 = bisect<NewtonDiv>(d.data(), e2.data(), b, j, lo, hi, pivmin, 0.0);
+      if (!(std::fabs(l2 - lam[j]) <= 1e-13 * std::max(nrm, 1e-300) + 1e-300)) {
+        printf("refined-reciprocal bisection differs at j=%d: %.3e\n", j, l2 - lam[j]);
+        return 1;
+      }
+      const bool single = (j == 0 || lam[j] - lam[j - 1] > 1e-6 * nrm) &&
+                          (j + 1 == b || lam[j + 1] - lam[j] > 1e-6 * nrm);
+      if (!single || nrm == 0.0) continue;
+      twisted_vector<NewtonDiv>(d.data(), e.data(), b, lam[j], pivmin, Lq.data(), Uq.data(),
+                                zq.data());
+      double r = 0;
+      for (int i = 0; i < b; ++i) {
+        double v = (d[i] - lam[j]) * zq[i];
+        if (i > 0) v += e[i - 1] * zq[i - 1];
+        if (i + 1 < b) v += e[i] * zq[i + 1];
+        r = std::max(r, std::fabs(v));
+      }
+      if (!(r <= 1e3 * b * 2.2e-16 * nrm + pivmin)) {
+        printf("refined-reciprocal twisted vector residual %.3e at j=%d\n", r, j);
+        return 1;
+      }
+    }
+  }
   std::vector<double> Z(size_t(b)*b), Lp(b), Um(b), z(b);
   double ctol = 1e-12 * nrm;
   int nclus = 0;
