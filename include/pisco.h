@@ -113,7 +113,22 @@ typedef struct {
                            accumulation and split operands (PISCO_PREC_SPLIT_*) */
   int32_t schedule;     /* nullspace schedule: PISCO_SCHED_AUTO or
                            PISCO_SCHED_DEVICE (see pisco_nullspace) */
+  int32_t product;      /* Gram products of pisco_estimate's nullspace:
+                           PISCO_PRODUCT_AUTO, _DENSE or _STRUCTURED */
 } pisco_opts_t;
+
+/* Gram products in pisco_estimate (pisco_opts_t.product).  DENSE forms the
+ * n x n Gram and multiplies it on the FP64 matrix cores.  STRUCTURED never
+ * forms it: Gram[(p,i),(q,j)] = R_pq[n_i - n_j] (Sec. IV-A), so A X is a sum
+ * of correlations of each column with the lags, evaluated exactly (FP64) on
+ * the (4 tau + 1)^D frequency grid: pruned DFT passes and one Q x Q product
+ * per frequency, 8 (4 tau + 1)^D Q^2 b flops against 8 n^2 b.  AUTO picks
+ * STRUCTURED for 3D problems with n >= 4096 and the correlation Gram (gram_rows
+ * = PISCO_ROWS_ALL), DENSE otherwise.  pisco_nullspace always takes the
+ * explicit Gram. */
+#define PISCO_PRODUCT_AUTO       0
+#define PISCO_PRODUCT_DENSE      1
+#define PISCO_PRODUCT_STRUCTURED 2
 
 /* Nullspace schedules (pisco_opts_t.schedule). */
 #define PISCO_SCHED_AUTO   0  /* adaptive (host reads control words) outside

@@ -26,6 +26,7 @@ FLAG_ZERO_DATA = 0x8
 
 STAGE_ALL, STAGE_GRAM, STAGE_NULLSPACE, STAGE_GX, STAGE_EIG, STAGE_MAPS, STAGE_MASK = range(7)
 PREC_FP32, PREC_SPLIT_F16, PREC_SPLIT_BF16 = 0, 1, 2
+PRODUCT_AUTO, PRODUCT_DENSE, PRODUCT_STRUCTURED = 0, 1, 2
 SCHED_AUTO, SCHED_DEVICE = 0, 1
 
 
@@ -40,7 +41,7 @@ class Opts(ctypes.Structure):
     _fields_ = [("power_iters", ctypes.c_int32), ("tol", ctypes.c_float),
                 ("phase_rule", ctypes.c_int32), ("block", ctypes.c_int32),
                 ("max_subspace_iters", ctypes.c_int32), ("precision", ctypes.c_int32),
-                ("schedule", ctypes.c_int32)]
+                ("schedule", ctypes.c_int32), ("product", ctypes.c_int32)]
 
 
 class TraceEntry(ctypes.Structure):
@@ -165,11 +166,11 @@ def make_problem(D: int, Q: int, acs: Sequence[int], radius: float, grid_lr: Seq
 
 def make_opts(power_iters: int = 10, tol: float = 0.0, phase_rule: int = 0, block: int = 0,
               max_subspace_iters: int = 60, precision: int = PREC_FP32,
-              schedule: int = 0) -> Opts:
+              schedule: int = 0, product: int = 0) -> Opts:
     o = Opts()
     o.power_iters, o.tol, o.phase_rule = int(power_iters), float(tol), int(phase_rule)
     o.block, o.max_subspace_iters = int(block), int(max_subspace_iters)
-    o.precision, o.schedule = int(precision), int(schedule)
+    o.precision, o.schedule, o.product = int(precision), int(schedule), int(product)
     return o
 
 

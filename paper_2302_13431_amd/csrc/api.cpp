@@ -19,6 +19,7 @@ pisco_opts_t default_opts() {
   o.max_subspace_iters = 60;
   o.precision = PISCO_PREC_FP32;
   o.schedule = PISCO_SCHED_AUTO;
+  o.product = PISCO_PRODUCT_AUTO;
   return o;
 }
 
@@ -131,13 +132,14 @@ struct EstLayout {
   size_t total;
 };
 
-EstLayout est_layout(const Plan& p, int b, void* ws) {
+EstLayout est_layout(const Plan& p, int b, void* ws, bool structured) {
   Carver c(ws);
   EstLayout e{};
   // tables first: their offsets do not depend on the block size
   char* tb = c.take<char>(layout_tables(p, kTabAll, nullptr, nullptr));
   layout_tables(p, kTabAll, tb, &e.tabs);
-  e.gram = c.take<float2>(size_t(p.n) * p.n);
+  // the explicit Gram, or (structured products) only its lags
+  e.gram = c.take<float2>(structured ? size_t(p.P) * p.nlag : size_t(p.n) * p.n);
   e.eigvals = c.take<double>(b);
   e.basis = c.take<double2>(size_t(b) * p.n);
   e.counts = c.take<int32_t>(4);
@@ -146,7 +148,7 @@ EstLayout est_layout(const Plan& p, int b, void* ws) {
   e.lam = c.take<float>(p.Nlr);
   // the nullspace stage has a region of its own: the later stages may be
   // enqueued while its iteration can still go on
-  e.null_ws = c.take<char>(ws_stage_scratch(p, b, 2));
+  e.null_ws = c.take<char>(layout_null(p, b, nullptr, nullptr, structured));
   size_t m = 0;
   for (int st = 1; st <= 5; ++st) {
     const size_t v = st == 2 ? 0 : ws_stage_scratch(p, b, st);
@@ -161,7 +163,17 @@ EstLayout est_layout(const Plan& p, int b, void* ws) {
 
 namespace pisco {
 
-size_t estimate_ws_size(const Plan& p, int b) { return est_layout(p, b, nullptr).total; }
+bool structured_product(const Plan& p, const pisco_opts_t& o) {
+  if (p.rows != PISCO_ROWS_ALL) return false;  // the masked Gram has no lag structure
+  if (o.product == PISCO_PRODUCT_STRUCTURED) return true;
+  if (o.product == PISCO_PRODUCT_DENSE) return false;
+  return p.D == 3 && p.n >= 4096;
+}
+
+
+size_t estimate_ws_size(const Plan& p, int b, bool structured) {
+  return est_layout(p, b, nullptr, structured).total;
+}
 
 pisco_status_t choose_schedule(Handle* h, const pisco_opts_t& o, int* device_products) {
   *device_products = 0;
@@ -187,13 +199,37 @@ pisco_status_t estimate_core(Handle* h, const Plan& p, const pisco_opts_t& o, in
                              const float2* acs, float2* maps_out, float* lam_min, void* ws,
                              int fixed_products, int ax_waves, int32_t** counts_out,
                              bool tables_ready) {
-  EstLayout e = est_layout(p, b, ws);
+  const bool structured = structured_product(p, o);
+  EstLayout e = est_layout(p, b, ws, structured);
   if (counts_out) *counts_out = e.counts;
   pisco_status_t st;
   int device_products = 0;
   if (fixed_products <= 0 && (st = choose_schedule(h, o, &device_products))) return st;
   if (!tables_ready && (st = build_tables(h, p, kTabAll, e.tabs))) return st;
-  if ((st = run_gram(h, p, e.tabs, acs, e.gram, e.stage_ws))) return st;
+  if ((st = run_gram(h, p, e.tabs, acs, e.gram, e.stage_ws, structured ? e.gram : nullptr)))
+    return st;
+  ToeplitzOp tp{};
+  if (structured) {
+    NullWs nw;
+    layout_null(p, b, e.null_ws, &nw, true);
+    tp.lags = e.gram;
+    tp.boxmap = e.tabs.boxmap;
+    tp.sup = e.tabs.sup;
+    tp.Tf = e.tabs.Tf;
+    tp.Ti = e.tabs.Ti;
+    tp.Tr = e.tabs.Tr;
+    tp.rhat = nw.rhat;
+    tp.buf0 = nw.sp0;
+    tp.buf1 = nw.sp1;
+    tp.D = p.D;
+    tp.W = 2 * p.tau + 1;
+    tp.Wz = p.D == 3 ? tp.W : 1;
+    tp.F = p.K[2];
+    tp.Fz = p.K[0];
+    tp.Q = p.Q;
+    tp.L = p.L;
+    tp.P = p.P;
+  }
   float* lam = lam_min ? lam_min : e.lam;
   const std::function<pisco_status_t()> later = [&]() -> pisco_status_t {
     pisco_status_t s2;
@@ -207,7 +243,7 @@ pisco_status_t estimate_core(Handle* h, const Plan& p, const pisco_opts_t& o, in
   bool queued = false;
   if ((st = run_nullspace(h, p, b, o.max_subspace_iters, e.gram, e.eigvals, e.basis, e.counts,
                           e.null_ws, fixed_products, ax_waves, &later, &queued,
-                          device_products)))
+                          device_products, structured ? &tp : nullptr)))
     return st;
   return queued ? PISCO_OK : later();
 }
@@ -338,7 +374,7 @@ pisco_status_t pisco_workspace_size(const pisco_problem_t* prob, const pisco_opt
     if (st) return st;
   }
   if (stage == PISCO_STAGE_ALL) {
-    *bytes = est_layout(p, b, nullptr).total;
+    *bytes = est_layout(p, b, nullptr, structured_product(p, o)).total;
     return PISCO_OK;
   }
   if (stage < 1 || stage > 6) return PISCO_ERR_ARG;
@@ -591,7 +627,9 @@ pisco_status_t pisco_estimate(pisco_handle_t handle, const pisco_problem_t* prob
     return fail(h, PISCO_ERR_ARG, "null or unaligned pointer");
   if (o.precision < PISCO_PREC_FP32 || o.precision > PISCO_PREC_SPLIT_BF16)
     return fail(h, PISCO_ERR_ARG, "unknown precision");
-  if (ws_bytes < estimate_ws_size(p, b))
+  if (o.product < PISCO_PRODUCT_AUTO || o.product > PISCO_PRODUCT_STRUCTURED)
+    return fail(h, PISCO_ERR_ARG, "unknown product");
+  if (ws_bytes < estimate_ws_size(p, b, structured_product(p, o)))
     return fail(h, PISCO_ERR_WORKSPACE, "workspace too small for pisco_estimate");
   return estimate_core(h, p, o, b, static_cast<const float2*>(acs),
                        static_cast<float2*>(maps_out), lam_min, ws, 0, 0);
@@ -662,7 +700,10 @@ pisco_status_t batch_prepare(Handle* h, int32_t B, const pisco_problem_t* probs,
     if (sl.o.precision < PISCO_PREC_FP32 || sl.o.precision > PISCO_PREC_SPLIT_BF16)
       return fail(h, PISCO_ERR_ARG, "unknown precision");
     sl.bmax = sl.o.block > 0 ? sl.b : max_block(sl.p, sl.b);
-    sl.ws_bytes = (estimate_ws_size(sl.p, sl.bmax) + 255) & ~size_t(255);
+    if (sl.o.product < PISCO_PRODUCT_AUTO || sl.o.product > PISCO_PRODUCT_STRUCTURED)
+      return fail(h, PISCO_ERR_ARG, "unknown product");
+    sl.ws_bytes = (estimate_ws_size(sl.p, sl.bmax, structured_product(sl.p, sl.o)) + 255) &
+                  ~size_t(255);
     sum += sl.ws_bytes;
     out->push_back(sl);
   }
@@ -721,7 +762,7 @@ pisco_status_t pisco_batch_create(pisco_handle_t handle, int32_t B, const pisco_
   // every run of a slice checks that its block fits the slice's region
   auto run = [&](const BatchSlice& x, Handle* hh, int bb, int fixed, int waves,
                  int32_t** counts, bool tables_ready = false) -> pisco_status_t {
-    if (bb > x.bmax || estimate_ws_size(x.p, bb) > x.ws_bytes)
+    if (bb > x.bmax || estimate_ws_size(x.p, bb, structured_product(x.p, x.o)) > x.ws_bytes)
       return fail(h, PISCO_ERR_WORKSPACE, "batch: block exceeds the slice's workspace region");
     return estimate_core(hh, x.p, x.o, bb, x.acs, x.out, x.lam, x.ws, fixed, waves, counts,
                          tables_ready);

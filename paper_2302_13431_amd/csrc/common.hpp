@@ -190,8 +190,36 @@ struct NullWs {
   int* ctl;        // [16] control words, then the device-resident schedule
   double* jac;     // Cholesky scratch (global-memory fallback) [b*(b+1)*2]
   double* heev;    // eigen-decomposition scratch [heev_workspace_doubles(b)]
+  // structured products only (null otherwise): per-frequency Gram blocks
+  // [F^D][Q][Q] and two spectrum buffers of toeplitz_spectrum_elems each
+  double2* rhat;
+  double2* sp0;
+  double2* sp1;
 };
-size_t layout_null(const Plan& p, int b, void* ws, NullWs* out);
+size_t layout_null(const Plan& p, int b, void* ws, NullWs* out, bool structured = false);
+
+// Gram products through the correlation structure (toeplitz.hip): the lags
+// R_pq[d] on the (4 tau + 1)^D box stand for the Gram.
+struct ToeplitzOp {
+  const float2* lags;   // [P][Bz][B][B] (Bz = 1 when D = 2), as the Gram stage forms them
+  const int* boxmap;    // [Wz][W][W] box cell -> support index, -1 outside
+  const int4* sup;      // support points (z, y, x, 0)
+  const double2* Tf;    // F x W: box -> frequency
+  const double2* Ti;    // W x F: frequency -> box, 1/F included
+  const double2* Tr;    // F x F: lags -> frequency
+  double2* rhat;        // [Fz F F][Q][Q]
+  double2* buf0;        // spectrum buffers, toeplitz_spectrum_elems(p, b) each
+  double2* buf1;
+  int D, W, Wz, F, Fz, Q, L, P;
+};
+size_t toeplitz_spectrum_elems(const Plan& p, int b);
+// rhat from the lags (once per nullspace call; uses buf0 / buf1).
+pisco_status_t toeplitz_prepare(Handle* h, const ToeplitzOp& op);
+// out = A X (or the Chebyshev step / role of the explicit product) for a
+// column-major n x b block.
+pisco_status_t toeplitz_product(Handle* h, const ToeplitzOp& op, const double2* X,
+                                double2* out, int n, int b, const double* coef,
+                                const double2* prev, const int* role);
 
 struct GxWs {
   float2* Fh;      // [b][Q][nK] filter spectra
@@ -223,10 +251,14 @@ struct Tables {
   double2* Ma[3] = {nullptr, nullptr, nullptr};
   float2* Ms[3] = {nullptr, nullptr, nullptr};
   double2* Ms64[3] = {nullptr, nullptr, nullptr};
+  double2* Tf = nullptr;  // structured products: box -> frequency (F x W)
+  double2* Ti = nullptr;  // frequency -> box (W x F, 1/F included)
+  double2* Tr = nullptr;  // lags -> frequency (F x F)
 };
 // Which tables a call needs (bit mask).
-constexpr unsigned kTabSupport = 1u, kTabGx = 2u, kTabMaps = 4u, kTabMask = 8u;
-constexpr unsigned kTabAll = kTabSupport | kTabGx | kTabMaps;
+constexpr unsigned kTabSupport = 1u, kTabGx = 2u, kTabMaps = 4u, kTabMask = 8u,
+                   kTabToeplitz = 16u;
+constexpr unsigned kTabAll = kTabSupport | kTabGx | kTabMaps | kTabToeplitz;
 // Carves the tables of `which` from `ws` (sizes only when ws is null);
 // returns the bytes used.
 size_t layout_tables(const Plan& p, unsigned which, void* ws, Tables* out);
@@ -249,8 +281,10 @@ size_t layout_maps(const Plan& p, void* ws, MapsWs* out);
 
 // support_ws (nullable): region of L int4 where the support list is built in
 // stream order instead of taken from the handle's table.
+// lags_out (nullable): the lags R_pq go there ([P][nlag]) and the Gram is
+// not gathered (gram unused).
 pisco_status_t run_gram(Handle* h, const Plan& p, const Tables& t, const float2* acs,
-                        float2* gram, void* ws);
+                        float2* gram, void* ws, float2* lags_out = nullptr);
 // The Gram with the library's static per-device scratch (kGramScratchBytes)
 // as workspace: no allocation; calls that overlap on one GPU race.
 constexpr size_t kGramScratchBytes = size_t(64) << 20;
@@ -268,12 +302,15 @@ pisco_status_t gram_scratch_address(Handle* h, void** out);
 // goes on while the host waits), again after a later step when that one was
 // not final, and *downstream_queued tells the caller whether the last call
 // stands.  Its work must not touch `ws`.
+// tp (nullable): products through the correlation structure (gram unused;
+// ws laid out with layout_null(..., structured = true)).
 pisco_status_t run_nullspace(Handle* h, const Plan& p, int b, int max_iters,
                              const float2* gram, double* eigvals, double2* basis,
                              int32_t* counts, void* ws, int fixed_products = 0,
                              int ax_waves = 0,
                              const std::function<pisco_status_t()>* downstream = nullptr,
-                             bool* downstream_queued = nullptr, int device_products = 0);
+                             bool* downstream_queued = nullptr, int device_products = 0,
+                             const ToeplitzOp* tp = nullptr);
 // Products the device-resident schedule enqueues (the cap on the products
 // it can run): at most kDeviceProducts, fewer when max_iters is smaller.
 constexpr int kDeviceProducts = 16;
@@ -320,7 +357,10 @@ pisco_status_t run_espirit_operator(Handle* h, int Q, long long N, float bound,
 // The whole path for one problem on h's stream (pisco_estimate's body);
 // fixed_products / ax_waves as for run_nullspace; counts_out (nullable)
 // receives the device address of the nullspace counts in `ws`.
-size_t estimate_ws_size(const Plan& p, int b);
+// structured: Gram products through the correlation structure (the Gram is
+// not formed; see structured_product).
+size_t estimate_ws_size(const Plan& p, int b, bool structured);
+bool structured_product(const Plan& p, const pisco_opts_t& o);
 // tables_ready: the tables in `ws` were built by an earlier run with the
 // same problem and block (a batch's captured graph skips rebuilding them).
 pisco_status_t estimate_core(Handle* h, const Plan& p, const pisco_opts_t& o, int b,

@@ -418,7 +418,7 @@ static pisco_status_t run_gram_valid(Handle* h, const Plan& p, const Tables& t, 
 }
 
 pisco_status_t run_gram(Handle* h, const Plan& p, const Tables& t, const float2* acs,
-                        float2* gram, void* ws) {
+                        float2* gram, void* ws, float2* lags_out) {
   if (p.rows == PISCO_ROWS_VALID) return run_gram_valid(h, p, t, acs, gram, ws);
   GramWs w;
   layout_gram(p, ws, &w);
@@ -455,7 +455,9 @@ pisco_status_t run_gram(Handle* h, const Plan& p, const Tables& t, const float2*
     PISCO_KERNEL(h, k_inv_first, dim3(blocks_for(iy)), dim3(256), 0, Sfull, w.T2, iy, Q, F1, F2, B1);
   }
   PassGeom ix = geom(F2, 1LL * P * B0 * B1);
-  PISCO_KERNEL(h, k_inv_x, dim3(blocks_for(ix)), dim3(256), 0, w.T2, w.R, ix, F2, B2, scale);
+  float2* R = lags_out ? lags_out : w.R;
+  PISCO_KERNEL(h, k_inv_x, dim3(blocks_for(ix)), dim3(256), 0, w.T2, R, ix, F2, B2, scale);
+  if (lags_out) return PISCO_OK;  // the caller multiplies through the lags
 
   dim3 gg(ceil_div(p.n, 256), p.n);
   PISCO_KERNEL(h, k_gather, gg, dim3(256), 0, w.R, support, gram, Q, p.L, B0, B1, B2, p.nlag);

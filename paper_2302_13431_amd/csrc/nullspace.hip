@@ -1055,7 +1055,8 @@ pisco_status_t run_nullspace(Handle* h, const Plan& p, int b, int max_iters,
                              const float2* gram, double* eigvals, double2* basis,
                              int32_t* counts, void* ws, int fixed_products, int ax_waves,
                              const std::function<pisco_status_t()>* downstream,
-                             bool* downstream_queued, int device_products) {
+                             bool* downstream_queued, int device_products,
+                             const ToeplitzOp* tp) {
   if (downstream_queued) *downstream_queued = false;
   const bool device = device_products > 0 && fixed_products <= 0;
   if (fixed_products <= 0 && !device) {
@@ -1071,7 +1072,7 @@ pisco_status_t run_nullspace(Handle* h, const Plan& p, int b, int max_iters,
     }
   }
   NullCtx c{h, &p, b, {}};
-  layout_null(p, b, ws, &c.w);
+  layout_null(p, b, ws, &c.w, tp != nullptr);
   hipStream_t s = h->stream;
   const int n = p.n;
   const long long nb = 1LL * n * b;
@@ -1083,6 +1084,7 @@ pisco_status_t run_nullspace(Handle* h, const Plan& p, int b, int max_iters,
   // first product is orthonormalised before any Rayleigh-Ritz step
   PISCO_KERNEL(h, k_init_block, dim3(ceil_div(nb, 256)), dim3(256), 0, X, n, b);
   pisco_status_t st = PISCO_OK;
+  if (tp && (st = toeplitz_prepare(h, *tp))) return st;
 
   const double thr2 = double(p.thresh) * double(p.thresh);
   const double tol = 1e-10;
@@ -1105,6 +1107,7 @@ pisco_status_t run_nullspace(Handle* h, const Plan& p, int b, int max_iters,
                      const int* role = nullptr) -> pisco_status_t {
     const dim3 g(ceil_div(n, 32), ceil_div(b, 32));
     const double* coef = role ? c.w.filt : (step ? c.w.filt + 3 * (step - 1) : nullptr);
+    if (tp) return toeplitz_product(h, *tp, in, out, n, b, coef, prev, role);
     switch (ksplit) {
       case 8:
         PISCO_KERNEL(h, k_gemm_ax<8>, g, dim3(512), 0, gram, in, out, n, b, kchunk, coef, prev,

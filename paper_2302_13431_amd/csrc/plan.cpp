@@ -112,7 +112,7 @@ size_t layout_gram(const Plan& p, void* ws, GramWs* o) {
   return c.used + 256;
 }
 
-size_t layout_null(const Plan& p, int b, void* ws, NullWs* o) {
+size_t layout_null(const Plan& p, int b, void* ws, NullWs* o, bool structured) {
   Carver c(ws);
   NullWs w{};
   const size_t nb = size_t(p.n) * b, bb = size_t(b) * b;
@@ -139,6 +139,11 @@ size_t layout_null(const Plan& p, int b, void* ws, NullWs* o) {
   w.ctl = c.take<int>(16 + 128);
   w.jac = c.take<double>((size_t(b) + 1) * b * 2);
   w.heev = c.take<double>(heev_workspace_doubles(b));
+  if (structured) {
+    w.rhat = c.take<double2>(size_t(p.K[0]) * p.K[1] * p.K[2] * p.Q * p.Q);
+    w.sp0 = c.take<double2>(toeplitz_spectrum_elems(p, b));
+    w.sp1 = c.take<double2>(toeplitz_spectrum_elems(p, b));
+  }
   if (o) *o = w;
   return c.used + 256;
 }

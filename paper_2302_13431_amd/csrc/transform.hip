@@ -187,7 +187,7 @@ pisco_status_t axis_transform64(Handle* h, const double2* in, double2* out,
 //          it in the same lexicographic order
 enum TableKind { kTDft32 = 0, kTDft64 = 1, kTSinc32 = 2, kTSupport = 3, kTBoxMap = 4,
                  kTSinc64 = 5 };
-constexpr int kMaxTableJobs = 20;
+constexpr int kMaxTableJobs = 24;
 struct TableJob {
   int kind, nout, nin, co, ci;
   double period, sign, scale, sigma;
@@ -304,9 +304,16 @@ size_t layout_tables(const Plan& p, unsigned which, void* ws, Tables* out) {
   Tables t;
   const int first = p.D == 3 ? 0 : 1;
   const int box = 2 * p.tau + 1;
-  if (which & (kTabSupport | kTabGx)) t.sup = c.take<int4>(p.L);
-  if (which & kTabGx) {
+  if (which & (kTabSupport | kTabGx | kTabToeplitz)) t.sup = c.take<int4>(p.L);
+  if (which & (kTabGx | kTabToeplitz))
     t.boxmap = c.take<int>(size_t(p.D == 3 ? box : 1) * box * box);
+  if (which & kTabToeplitz) {
+    const int F = p.K[2];
+    t.Tf = c.take<double2>(size_t(F) * box);
+    t.Ti = c.take<double2>(size_t(box) * F);
+    t.Tr = c.take<double2>(size_t(F) * F);
+  }
+  if (which & kTabGx) {
     for (int d = first; d < 3; ++d) {
       t.M1[d] = c.take<float2>(size_t(p.K[d]) * box);
       t.M3[d] = c.take<float2>(size_t(p.B[d]) * p.K[d]);
@@ -350,9 +357,20 @@ pisco_status_t build_tables(Handle* h, const Plan& p, unsigned which, const Tabl
   };
   const int first = p.D == 3 ? 0 : 1;
   const int tau = p.tau, box = 2 * tau + 1;
-  if (t.sup && (which & (kTabSupport | kTabGx))) add(kTSupport, t.sup, 1, 1, 0, 0, 1, 0, 0, 0);
-  if (which & kTabGx) {
+  if (t.sup && (which & (kTabSupport | kTabGx | kTabToeplitz)))
+    add(kTSupport, t.sup, 1, 1, 0, 0, 1, 0, 0, 0);
+  if (which & (kTabGx | kTabToeplitz))
     add(kTBoxMap, t.boxmap, (p.D == 3 ? box : 1) * box, box, 0, 0, 1, 0, 0, 0);
+  if (which & kTabToeplitz) {
+    // structured Gram products on F = 4 tau + 1 points per axis: box (m -
+    // tau) -> frequency e^{-i 2 pi f m / F}; back with e^{+i 2 pi f n / F} / F;
+    // lags (d - 2 tau) -> frequency e^{-i 2 pi f d / F}
+    const int F = p.K[2];
+    add(kTDft64, t.Tf, F, box, 0, tau, F, -1.0, 1.0, 0.0);
+    add(kTDft64, t.Ti, box, F, tau, 0, F, +1.0, 1.0 / F, 0.0);
+    add(kTDft64, t.Tr, F, F, 0, 2 * tau, F, -1.0, 1.0, 0.0);
+  }
+  if (which & kTabGx) {
     for (int d = first; d < 3; ++d) {
       const int Lk = p.K[d], Bd = p.B[d], lr = p.lr[d];
       // filter spectra: e^{+i 2 pi n f / Lk}, n = box index - tau

@@ -24,7 +24,8 @@ class Estimator:
                  grid_lr: Sequence[int], grid_out: Sequence[int], thresh: float = 0.05,
                  power_iters: int = 10, tol: float = 0.0, phase_rule: int = 0,
                  block: int = 0, max_subspace_iters: int = 60, precision: int = 0,
-                 schedule: int = 0, shape: int = 0, gram_rows: int = 0, stream=None):
+                 schedule: int = 0, shape: int = 0, gram_rows: int = 0, stream=None,
+                 product: int = 0):
         import torch
         self.torch = torch
         self.D = len(acs_shape)
@@ -36,7 +37,7 @@ class Estimator:
         self.prob = L.make_problem(self.D, Q, acs_shape, radius, grid_lr, grid_out, thresh,
                                    shape, gram_rows)
         self.opts = L.make_opts(power_iters, tol, phase_rule, block, max_subspace_iters,
-                                precision, schedule)
+                                precision, schedule, product)
         self.h = L.Handle(stream)
         self.support = L.pisco_support(self.D, radius, shape)
         self.nsup = len(self.support)

@@ -301,12 +301,19 @@ def test_maps(name, rule):
 # ------------------------------------------------------------------ end to end
 
 
+PRODUCTS = {1: "dense", 2: "structured"}
+
+
 @pytest.mark.parametrize("name", WLALL)
 @pytest.mark.parametrize("prec", list(PRECISIONS))
-def test_end_to_end(name, prec):
+@pytest.mark.parametrize("product", list(PRODUCTS))
+def test_end_to_end(name, prec, product):
+    """The whole path against the oracle, with the nullspace's Gram products
+    either on the explicit Gram or through its correlation structure (the
+    Gram never formed)."""
     ref = oracle_full(name)
     w, acs = scan_inputs(name)
-    est = estimator(name, precision=prec)
+    est = estimator(name, precision=prec, product=product)
     out, lam = est.estimate(cuda(acs))
     out, lam = out.cpu().numpy(), lam.cpu().numpy()
     bound = float(len(ref.lam))
@@ -314,8 +321,9 @@ def test_end_to_end(name, prec):
     mask_lr = lowres_mask(ref.c_lr, ref.rho_lr, None)
     mo = output_mask(mask_lr, w.grid)
     e = map_error(ref.maps, out)
-    report(f"e2e {name} {PRECISIONS[prec]}", err_lam=e_lam, err_map_mask=float(e[mo].max()),
-           err_map_p99=float(np.percentile(e, 99)), err_map_all=float(e.max()))
+    report(f"e2e {name} {PRECISIONS[prec]} {PRODUCTS[product]}", err_lam=e_lam,
+           err_map_mask=float(e[mo].max()), err_map_p99=float(np.percentile(e, 99)),
+           err_map_all=float(e.max()))
     assert est.status() == 0
     assert e_lam <= 1e-5
     assert float(e[mo].max()) <= 1e-4
@@ -339,20 +347,25 @@ def test_end_to_end_ragged():
     assert e_lam <= 1e-5 and float(e[mo].max()) <= 1e-4
 
 
-def test_end_to_end_small_3d():
+@pytest.mark.parametrize("product", list(PRODUCTS))
+def test_end_to_end_small_3d(product):
+    """Odd extents in every dimension, radius 2 (a 5^3 box, 9^3 frequency
+    grid for the structured products)."""
     import paper_2302_13431_amd as P
     from oracle import pipeline as opipe
     sc = generator.make_scan(66, (24, 28, 32), 4, (12, 12, 12), 4, 40.0, keep_kspace=False)
     acs = generator.as_device_input(sc.acs)
     lr, out_grid, radius = (16, 18, 20), (24, 28, 32), 2.0
     ref = opipe.estimate(acs.astype(np.complex128), radius, lr, out_grid)
-    est = P.Estimator(4, (12, 12, 12), radius, lr, out_grid, block=64)
+    est = P.Estimator(4, (12, 12, 12), radius, lr, out_grid, block=64, product=product)
     out, lam = est.estimate(cuda(acs))
     out, lam = out.cpu().numpy(), lam.cpu().numpy()
     mo = output_mask(lowres_mask(ref.c_lr, ref.rho_lr, None), out_grid)
     e = map_error(ref.maps, out)
     e_lam = float(np.abs(lam - ref.lam_min).max() / len(ref.lam))
-    report("e2e small 3d", r_s=ref.split.r_signal, err_lam=e_lam, err_map=float(e[mo].max()))
+    report(f"e2e small 3d {PRODUCTS[product]}", r_s=ref.split.r_signal, err_lam=e_lam,
+           err_map=float(e[mo].max()))
+    assert est.status() == 0
     assert e_lam <= 1e-5 and float(e[mo].max()) <= 1e-4
 
 
