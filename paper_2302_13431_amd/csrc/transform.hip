@@ -89,6 +89,42 @@ __global__ void __launch_bounds__(256) k_axis_mid(const TI* __restrict__ in,
     if (k < cnt) dst[size_t(o0 + k) * inner] = acc[k];
 }
 
+// out[outer][o][inner] = sum_i M[o][i] in[outer][i][inner] for short
+// transforms (nin <= NMAX): one thread per (outer, inner) column holds its
+// nin inputs in registers (all loads in flight at once) and forms the nout
+// outputs one after another; M is the same for every lane, so its entries
+// come through scalar loads and no LDS is used.  FP64 output only.
+template <class TI, int NMAX>
+__global__ void __launch_bounds__(256) k_axis_reg(const TI* __restrict__ in,
+                                                  double2* __restrict__ out,
+                                                  const double2* __restrict__ M,
+                                                  long long outer, int nin, int nout,
+                                                  int inner) {
+  const long long col = blockIdx.x * 256LL + threadIdx.x;
+  if (col >= outer * inner) return;
+  const long long ou = col / inner;
+  const int ii = int(col - ou * inner);
+  const TI* src = in + size_t(ou) * nin * inner + ii;
+  double2* dst = out + size_t(ou) * nout * inner + ii;
+  double2 x[NMAX];
+#pragma unroll
+  for (int i = 0; i < NMAX; ++i)
+    x[i] = i < nin ? widen<double2>(src[size_t(i) * inner]) : make_double2(0.0, 0.0);
+  for (int o = 0; o < nout; ++o) {
+    const double2* m = M + size_t(o) * nin;
+    double ar = 0.0, ai = 0.0;
+#pragma unroll
+    for (int i = 0; i < NMAX; ++i) {
+      if (i < nin) {
+        const double2 mv = m[i];
+        ar = fma(mv.x, x[i].x, fma(-mv.y, x[i].y, ar));
+        ai = fma(mv.x, x[i].y, fma(mv.y, x[i].x, ai));
+      }
+    }
+    dst[size_t(o) * inner] = make_double2(ar, ai);
+  }
+}
+
 // out[line][o] = sum_i M[o][i] in[line][i]   (contiguous lines)
 // One output per thread: a block takes lpb = max(1, 256 / nout) lines,
 // staged in LDS, so that even a long output line spreads over many
@@ -139,6 +175,17 @@ static pisco_status_t axis_impl(Handle* h, const TI* in, TO* out, const int shap
     const long long blocks = per > 1 ? outer * per : ceil_div(outer, lpb);
     PISCO_KERNEL(h, (k_axis_last<TI, TO>), dim3(blocks), dim3(256), lds, in, out, M, outer, nin,
                  nout, lpb);
+  } else if (sizeof(TO) == sizeof(double2) && nin <= 32 && outer * inner >= 256LL * 1024) {
+    // short FP64 transforms over long runs (the structured Gram products)
+    const long long cols = ceil_div(outer * inner, 256);
+    const double2* Md = reinterpret_cast<const double2*>(M);
+    double2* od = reinterpret_cast<double2*>(out);
+    if (nin <= 16)
+      PISCO_KERNEL(h, (k_axis_reg<TI, 16>), dim3(cols), dim3(256), 0, in, od, Md, outer, nin,
+                   nout, int(inner));
+    else
+      PISCO_KERNEL(h, (k_axis_reg<TI, 32>), dim3(cols), dim3(256), 0, in, od, Md, outer, nin,
+                   nout, int(inner));
   } else {
     if (nin > kMidMaxIn) return PISCO_ERR_UNSUPPORTED;
     const long long cols = ceil_div(outer * inner, 256);
