@@ -502,6 +502,13 @@ constexpr int kCholThreads = 1024;
 // right of the diagonal block to LDS for the trailing update.
 // After a barrier the trailing update T_ij -= R_Ji^H R_Jj runs in 2 x 2
 // patches of the upper triangle, one per thread, operands in registers.
+//
+// Blocked use (kLds false, large b): a call eliminates only the panels of
+// rows [kbeg, kend) and applies their trailing updates to those rows alone
+// (every column right of the diagonal); the update of the rows below, with
+// the finished rows R_[kbeg,kend),: as one rank-(kend - kbeg) block, is
+// k_chol_update's, across many workgroups.  The first call (kbeg = 0)
+// also stages T; later calls read the scales back from dsc_out.
 template <bool kLds>
 __global__ void __launch_bounds__(kCholThreads) k_chol(const double2* __restrict__ S, int b,
                                                double shift, double2* __restrict__ R,
@@ -509,7 +516,8 @@ __global__ void __launch_bounds__(kCholThreads) k_chol(const double2* __restrict
                                                double2* __restrict__ gwork,
                                                int* __restrict__ flag,
                                                double* __restrict__ rdiag,
-                                               const int* __restrict__ skip) {
+                                               const int* __restrict__ skip, int kbeg,
+                                               int kend) {
   if (skip && *skip) return;
   constexpr int kNB = 8;                        // panel height (b is a multiple)
   constexpr int kNT = kCholThreads;
@@ -574,7 +582,7 @@ __global__ void __launch_bounds__(kCholThreads) k_chol(const double2* __restrict
         ++j;
       }
     }
-  } else {
+  } else if (kbeg == 0) {
     for (int k = t; k < b; k += kNT) {
       const double d = S[size_t(k) * b + k].x;
       dsc[k] = d > 0.0 ? 1.0 / sqrt(d) : 0.0;
@@ -583,9 +591,11 @@ __global__ void __launch_bounds__(kCholThreads) k_chol(const double2* __restrict
     __syncthreads();
     for (int e = t; e < b * b; e += kNT) stage(e % b, e / b, S[e]);
     for (int e = t; e < b * b; e += kNT) zero_lower(e % b, e / b);
+  } else {
+    for (int k = t; k < b; k += kNT) dsc[k] = dsc_out[k];
   }
   __syncthreads();
-  for (int k0 = 0; k0 < b; k0 += kNB) {
+  for (int k0 = kbeg; k0 < kend; k0 += kNB) {
     const int k1 = k0 + kNB, nc = b - k1;
     const int groups = nc > 0 ? (nc + kCols - 1) / kCols : 1;
     for (int g = wave; g < groups; g += kNT / 64) {
@@ -634,9 +644,11 @@ __global__ void __launch_bounds__(kCholThreads) k_chol(const double2* __restrict
       }
     }
     __syncthreads();
-    // trailing update in 2 x 2 patches (pi <= pj) of the upper triangle
+    // trailing update in 2 x 2 patches (pi <= pj) of the upper triangle,
+    // patch rows below kend left to k_chol_update
     const int m = nc >> 1;
-    const int npatch = m * (m + 1) / 2;
+    const int mr = (kend - k1) >> 1;  // patch rows of this call
+    const int npatch = m * (m + 1) / 2 - (m - mr) * (m - mr + 1) / 2;
     for (int q = t; q < npatch; q += kNT) {
       // row of patches: start(p) = p m - p (p - 1) / 2 <= q < start(p + 1)
       const double tm = 2.0 * m + 1.0;
@@ -667,6 +679,43 @@ __global__ void __launch_bounds__(kCholThreads) k_chol(const double2* __restrict
   }
 }
 
+// Trailing update of the blocked Cholesky: T_ij -= sum_{l in [kbeg, kend)}
+// conj(R_li) R_lj for kend <= i <= j < b, one 32 x 32 tile of the upper
+// triangle per workgroup; the finished rows R_l,: sit in T's rows l (T
+// row-major, ld = b + 1) and are staged in LDS for the tile's rows and
+// columns.
+constexpr int kCholPanel = 32;  // rows per panel of the blocked factorisation
+
+__global__ void __launch_bounds__(256) k_chol_update(double2* __restrict__ T, int b, int kbeg,
+                                                     int kend, const int* __restrict__ skip) {
+  if (skip && *skip) return;
+  __shared__ double2 Ri[kCholPanel][33], Rj[kCholPanel][33];
+  const int ld = b + 1, K = kend - kbeg;
+  const int nt = (b - kend + 31) / 32;
+  // tile (ti, tj), ti <= tj, from the linear index (row-major upper triangle)
+  const int q = blockIdx.x;
+  int ti = 0;
+  while ((ti + 1) * nt - (ti + 1) * ti / 2 <= q) ++ti;
+  const int tj = ti + (q - (ti * nt - ti * (ti - 1) / 2));
+  const int i0 = kend + 32 * ti, j0 = kend + 32 * tj;
+  for (int e = threadIdx.x; e < K * 32; e += 256) {
+    const int kk = e >> 5, c = e & 31;
+    const size_t row = size_t(kbeg + kk) * ld;
+    Ri[kk][c] = i0 + c < b ? T[row + i0 + c] : make_double2(0.0, 0.0);
+    Rj[kk][c] = j0 + c < b ? T[row + j0 + c] : make_double2(0.0, 0.0);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int e = threadIdx.x + 256 * u;
+    const int ii = e >> 5, jj = e & 31;
+    const int i = i0 + ii, j = j0 + jj;
+    if (i >= b || j >= b || j < i) continue;
+    double2 acc = make_double2(0.0, 0.0);
+    for (int kk = 0; kk < K; ++kk) acc = zadd(acc, zmulc(Ri[kk][ii], Rj[kk][jj]));
+    T[size_t(i) * ld + j] = zsub(T[size_t(i) * ld + j], acc);
+  }
+}
 
 // M = D R^{-1}, one column j per wave: back substitution R x = e_j in
 // column (axpy) order, k = j down to 0: x_k = r_k / R_kk, then
@@ -1014,12 +1063,23 @@ pisco_status_t chol_inv(NullCtx& c, const double2* S, double shift, double2* M,
     return PISCO_ERR_UNSUPPORTED;
   }
   int* flag = c.w.ctl + 8;
-  if (b <= kCholLdsMax)
+  double2* T = reinterpret_cast<double2*>(c.w.jac);
+  if (b <= kCholLdsMax) {
     PISCO_KERNEL(c.h, k_chol<true>, dim3(1), dim3(kCholThreads), 0, S, b, shift, c.w.R,
-                 c.w.dsc, reinterpret_cast<double2*>(c.w.jac), flag, rdiag, skip);
-  else
-    PISCO_KERNEL(c.h, k_chol<false>, dim3(1), dim3(kCholThreads), 0, S, b, shift, c.w.R,
-                 c.w.dsc, reinterpret_cast<double2*>(c.w.jac), flag, rdiag, skip);
+                 c.w.dsc, T, flag, rdiag, skip, 0, b);
+  } else {
+    // blocked: one workgroup eliminates a panel of rows, many update the rest
+    for (int kb = 0; kb < b; kb += kCholPanel) {
+      const int ke = kb + kCholPanel < b ? kb + kCholPanel : b;
+      PISCO_KERNEL(c.h, k_chol<false>, dim3(1), dim3(kCholThreads), 0, S, b, shift, c.w.R,
+                   c.w.dsc, T, flag, rdiag, skip, kb, ke);
+      if (ke < b) {
+        const int nt = ceil_div(b - ke, 32);
+        PISCO_KERNEL(c.h, k_chol_update, dim3(nt * (nt + 1) / 2), dim3(256), 0, T, b, kb, ke,
+                     skip);
+      }
+    }
+  }
   const dim3 tg(ceil_div(b, kTriWaves)), tb(64 * kTriWaves);
   if (b <= 64)
     PISCO_KERNEL(c.h, (k_tri_inv<1, true>), tg, tb, 0, c.w.R, c.w.dsc, M, b, skip);

@@ -75,15 +75,22 @@ def test_gram(name):
 # ------------------------------------------------------------------ nullspace
 
 
-@pytest.mark.parametrize("name", WLALL)
-def test_nullspace(name):
+NULL_CASES = [(w, BLOCK[w]) for w in WLALL] + [("2d_256x256_q32_acs32_r5", 128),
+                                               ("2d_256x256_q32_acs32_r5", 160)]
+
+
+@pytest.mark.parametrize("name,block", NULL_CASES)
+def test_nullspace(name, block):
+    """Blocks up to 96 are factored with the matrix in LDS, larger ones by
+    the blocked (panel + multi-workgroup update) Cholesky; 128 and 160 also
+    reach the register and global-memory tridiagonalisations."""
     _, _, _, g32, sp = oracle_gram_split(name)
-    est = estimator(name)
+    est = estimator(name, block=block)
     ev, basis, counts = est.nullspace(cuda(g32))
     ev, basis, counts = ev.cpu().numpy(), basis.cpu().numpy(), counts.cpu().numpy()
     rs = int(counts[0])
-    report("nullspace " + name, r_gpu=rs, r_oracle=sp.r_signal, iters=int(counts[2]),
-           gap=sp.gap)
+    report(f"nullspace {name} b={block}", r_gpu=rs, r_oracle=sp.r_signal,
+           iters=int(counts[2]), gap=sp.gap)
     assert counts[3] == 1, "not converged"
     assert rs == sp.r_signal
     lam = sp.eigvals
