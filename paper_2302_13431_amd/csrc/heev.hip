@@ -1,13 +1,14 @@
 // Eigen-decomposition of the small Hermitian Rayleigh-Ritz matrix H = X^H A X
 // (order b, FP64) used by the signal/null split.
 //
-//   k_hetrd(_reg) one workgroup: Householder reduction H = Q T Q^H with T real
-//                 symmetric tridiagonal (each reflector H_k = I - tau_k v_k v_k^H
-//                 is chosen so that H_k^H maps the column below the diagonal
-//                 onto a real multiple of the first unit vector); the
+//   k_hetrd_reg / k_hetrd_step: Householder reduction H = Q T Q^H with T
+//                 real symmetric tridiagonal (each reflector H_k = I - tau_k
+//                 v_k v_k^H is chosen so that H_k^H maps the column below the
+//                 diagonal onto a real multiple of the first unit vector); the
 //                 reflectors are kept for the back-transformation.  Up to
-//                 order 128 the matrix stays in registers (k_hetrd_reg),
-//                 beyond that in global memory.
+//                 order 128 one workgroup holds the matrix in registers
+//                 (k_hetrd_reg); beyond that one launch per step spreads the
+//                 matrix's columns over many workgroups (k_hetrd_step).
 //   k_tri_eigval  one workgroup per eigenvalue: multisection on Sturm counts
 //                 (256 points per step), to about eps * ||T||.
 //   k_tri_vector  one workgroup per eigenvalue: the eigenvector of T by the
@@ -69,138 +70,158 @@ __device__ inline double wave_min(double v) {
 
 // ------------------------------------------------------------------ reduction
 
-// A (column-major b x b, Hermitian part of H) is reduced in place in `gwork`
-// (global, b*b); orders up to 128 take k_hetrd_reg below, which keeps A in
-// registers.  Step k: wave 0 builds the
-// reflector from column k; the product x = tau A22 v is formed in column
-// slices (partial sums in LDS), wave 0 forms w = x - (tau/2)(x^H v) v, and
-// all threads apply A22 <- A22 - v w^H - w v^H, which equals H_k^H A22 H_k.
-__global__ void __launch_bounds__(1024) k_hetrd(const double2* __restrict__ H, int b,
-                                                double2* __restrict__ gwork,
-                                                double2* __restrict__ refl,
-                                                double2* __restrict__ tau_out,
-                                                double* __restrict__ d_out,
-                                                double* __restrict__ e_out) {
-  constexpr int kVec = kTriMax;      // vector capacity
-  constexpr int kPR = 256;           // product: row stride
-  constexpr int kPS = 1024 / kPR;    // product: column slices
-  constexpr int kUR = 256;           // update: row stride
-  constexpr int kUS = 1024 / kUR;    // update: column slices
-  __shared__ double2 part[kPS][kVec];
-  __shared__ double2 vs[kVec], ws[kVec];
-  __shared__ double2 sh_tau;
-  double2* A = gwork;
-  const int t = threadIdx.x;
-  for (int e = t; e < b * b; e += 1024) {
-    const int i = e % b, j = e / b;
-    const double2 x = H[e], y = H[size_t(i) * b + j];
-    A[e] = make_double2(0.5 * (x.x + y.x), 0.5 * (x.y - y.y));
+// A = (H + H^H) / 2, column-major (the stepped reduction's first buffer).
+__global__ void k_hetrd_sym(const double2* __restrict__ H, int b, double2* __restrict__ A) {
+  const long long e = blockIdx.x * 256LL + threadIdx.x;
+  if (e >= 1LL * b * b) return;
+  const int i = int(e % b), j = int(e / b);
+  const double2 x = H[e], y = H[size_t(i) * b + j];
+  A[e] = make_double2(0.5 * (x.x + y.x), 0.5 * (x.y - y.y));
+}
+
+// Step k of the reduction for orders above 128 (one launch per step, k = 0
+// .. b - 1), on one-wave workgroups that each own every gridDim.x-th column
+// of the trailing block.  With A^(k) the matrix after k reflections and
+// x_{k-1} = tau_{k-1} A^(k-1)_22 v_{k-1} from the previous launch, every
+// workgroup forms the same w_{k-1} = x - (tau/2)(x^H v) v, the updated column
+// k of A^(k) and from it the reflector (v_k, tau_k, beta_k) (workgroup 0
+// stores them, with d_k and e_k = beta_k); then each applies
+// A^(k) = A^(k-1) - v w^H - w v^H to its own columns (rows > k), writes them
+// to the other buffer and forms x_k for them: by Hermitian symmetry
+// (A v)_j = sum_i conj(A_ij) v_i, a dot product down its own column, so no
+// sum crosses workgroups.  x_{k-1} and x_k sit in two vectors (every
+// workgroup reads the one while some write the other); b <= 64 kR.
+template <int kR>
+__global__ void __launch_bounds__(64) k_hetrd_step(const double2* __restrict__ Aold,
+                                                   double2* __restrict__ Anew, int b, int k,
+                                                   const double2* __restrict__ xin,
+                                                   double2* __restrict__ xout,
+                                                   double2* __restrict__ refl,
+                                                   double2* __restrict__ tau_out,
+                                                   double* __restrict__ d_out,
+                                                   double* __restrict__ e_out) {
+  constexpr int kMaxB = 64 * kR;
+  __shared__ double2 vpS[kMaxB], wpS[kMaxB], vS[kMaxB], cS[kMaxB];
+  const int lane = threadIdx.x;
+  // previous reflector and its w on rows k .. b - 1
+  if (k >= 1) {
+    const int kp = k - 1;
+    const double2 tp = tau_out[kp];
+    double2 xr[kR], vr[kR];
+    double dr = 0.0, di = 0.0;
+#pragma unroll
+    for (int s = 0; s < kR; ++s) {
+      const int i = k + lane + 64 * s;
+      xr[s] = make_double2(0.0, 0.0);
+      vr[s] = make_double2(0.0, 0.0);
+      if (i < b) {
+        vr[s] = refl[size_t(kp) * b + i];
+        xr[s] = xin[i];
+        dr += xr[s].x * vr[s].x + xr[s].y * vr[s].y;
+        di += xr[s].x * vr[s].y - xr[s].y * vr[s].x;
+      }
+    }
+    dr = wave_sum(dr);
+    di = wave_sum(di);
+    const double2 ap = zmul(make_double2(-0.5 * tp.x, -0.5 * tp.y), make_double2(dr, di));
+#pragma unroll
+    for (int s = 0; s < kR; ++s) {
+      const int i = k + lane + 64 * s;
+      if (i < b) {
+        vpS[i] = vr[s];
+        wpS[i] = zadd(xr[s], zmul(ap, vr[s]));
+      }
+    }
   }
   __syncthreads();
-  for (int k = 0; k + 1 < b; ++k) {
-    const int m = b - k - 1;
-    const double2* colk = A + size_t(k) * b + (k + 1);
-    if (t < 64) {
-      double s = 0.0;
-      for (int i = 1 + t; i < m; i += 64) s += zabs2(colk[i]);
-      s = wave_sum(s);
-      const double2 al = colk[0];
-      double2 tau = make_double2(0.0, 0.0), scale = make_double2(0.0, 0.0);
-      double beta = al.x;
-      if (s > 0.0 || al.y != 0.0) {
-        const double nrm = sqrt(zabs2(al) + s);
-        beta = al.x >= 0.0 ? -nrm : nrm;
-        tau = make_double2((beta - al.x) / beta, -al.y / beta);
-        const double2 den = make_double2(al.x - beta, al.y);  // |den| >= nrm
-        const double inv = 1.0 / zabs2(den);
-        scale = make_double2(den.x * inv, -den.y * inv);
-      }
-      for (int i = t; i < m; i += 64) {
-        const double2 v = i == 0 ? make_double2(1.0, 0.0) : zmul(colk[i], scale);
-        vs[i] = v;
-        refl[size_t(k) * b + k + 1 + i] = v;
-      }
-      if (t == 0) {
-        sh_tau = tau;
-        tau_out[k] = tau;
-        e_out[k] = beta;
-        d_out[k] = A[size_t(k) * b + k].x;
-      }
-    }
-    __syncthreads();
-    const double2 tau = sh_tau;
-    double2* a22 = A + size_t(k + 1) * b + (k + 1);  // A22(i, j) = a22[j * b + i]
-    {
-      const int i0 = t % kPR, sl = t / kPR;
-      if (sl < kPS) {
-        for (int i = i0; i < m; i += kPR) {
-          double2 acc = make_double2(0.0, 0.0);
-          int j = sl;
-          // four columns per pass with their loads issued together, then
-          // the remaining columns one by one
-          for (; j + 3 * kPS < m; j += 4 * kPS) {
-            double2 a[4], v[4];
+  // column k of A^(k) on rows k .. b - 1
+  const double2 vk = k >= 1 ? vpS[k] : make_double2(0.0, 0.0);
+  const double2 wk = k >= 1 ? wpS[k] : make_double2(0.0, 0.0);
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-              a[u] = a22[size_t(j + u * kPS) * b + i];
-              v[u] = vs[j + u * kPS];
-            }
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-              acc.x += a[u].x * v[u].x - a[u].y * v[u].y;
-              acc.y += a[u].x * v[u].y + a[u].y * v[u].x;
-            }
-          }
-          for (; j < m; j += kPS) {
-            const double2 a = a22[size_t(j) * b + i], v = vs[j];
-            acc.x += a.x * v.x - a.y * v.y;
-            acc.y += a.x * v.y + a.y * v.x;
-          }
-          part[sl][i] = acc;
-        }
+  for (int s = 0; s < kR; ++s) {
+    const int i = k + lane + 64 * s;
+    if (i < b) {
+      double2 a = Aold[size_t(k) * b + i];
+      if (k >= 1) {
+        const double2 vi = vpS[i], wi = wpS[i];
+        a.x -= vi.x * wk.x + vi.y * wk.y + wi.x * vk.x + wi.y * vk.y;
+        a.y -= vi.y * wk.x - vi.x * wk.y + wi.y * vk.x - wi.x * vk.y;
       }
+      cS[i] = a;
     }
-    __syncthreads();
-    if (t < 64) {
-      double dr = 0.0, di = 0.0;  // x^H v
-      for (int i = t; i < m; i += 64) {
-        double2 x = part[0][i];
+  }
+  __syncthreads();
+  const bool lead = blockIdx.x == 0;
+  if (k + 1 >= b) {  // the last diagonal entry only
+    if (lead && lane == 0) {
+      d_out[k] = cS[k].x;
+      e_out[k] = 0.0;
+    }
+    return;
+  }
+  // reflector from rows k + 1 .. b - 1 (the arithmetic of k_hetrd_reg)
+  double sq = 0.0;
 #pragma unroll
-        for (int q = 1; q < kPS; ++q) x = zadd(x, part[q][i]);
-        x = zmul(tau, x);
-        part[0][i] = x;
-        const double2 v = vs[i];
-        dr += x.x * v.x + x.y * v.y;
-        di += x.x * v.y - x.y * v.x;
-      }
-      dr = wave_sum(dr);
-      di = wave_sum(di);
-      const double2 ap = zmul(make_double2(-0.5 * tau.x, -0.5 * tau.y), make_double2(dr, di));
-      for (int i = t; i < m; i += 64) ws[i] = zadd(part[0][i], zmul(ap, vs[i]));
+  for (int s = 0; s < kR; ++s) {
+    const int i = k + 2 + lane + 64 * s;
+    if (i < b) sq += zabs2(cS[i]);
+  }
+  sq = wave_sum(sq);
+  const double2 al = cS[k + 1];
+  double2 tau = make_double2(0.0, 0.0), scale = make_double2(0.0, 0.0);
+  double beta = al.x;
+  if (sq > 0.0 || al.y != 0.0) {
+    const double nrm = sqrt(zabs2(al) + sq);
+    beta = al.x >= 0.0 ? -nrm : nrm;
+    tau = make_double2((beta - al.x) / beta, -al.y / beta);
+    const double2 den = make_double2(al.x - beta, al.y);  // |den| >= nrm
+    const double inv = 1.0 / zabs2(den);
+    scale = make_double2(den.x * inv, -den.y * inv);
+  }
+#pragma unroll
+  for (int s = 0; s < kR; ++s) {
+    const int i = k + 1 + lane + 64 * s;
+    if (i < b) {
+      const double2 v = i == k + 1 ? make_double2(1.0, 0.0) : zmul(cS[i], scale);
+      vS[i] = v;
+      if (lead) refl[size_t(k) * b + i] = v;
     }
-    __syncthreads();
-    {
-      const int i0 = t % kUR, sl = t / kUR;
-      for (int i = i0; i < m; i += kUR) {
-        const double2 vi = vs[i], wi = ws[i];
-        for (int j = sl; j < m; j += kUS) {
-          const double2 vj = vs[j], wj = ws[j];
-          double2 a = a22[size_t(j) * b + i];
+  }
+  if (lead && lane == 0) {
+    tau_out[k] = tau;
+    e_out[k] = beta;
+    d_out[k] = cS[k].x;
+  }
+  __syncthreads();
+  // own columns: update (rows > k), store, and x_k = tau A^(k) v_k there
+  for (int j = k + 1 + blockIdx.x; j < b; j += gridDim.x) {
+    const double2 vj = k >= 1 ? vpS[j] : make_double2(0.0, 0.0);
+    const double2 wj = k >= 1 ? wpS[j] : make_double2(0.0, 0.0);
+    double pr = 0.0, pi = 0.0;
+#pragma unroll
+    for (int s = 0; s < kR; ++s) {
+      const int i = k + 1 + lane + 64 * s;
+      if (i < b) {
+        double2 a = Aold[size_t(j) * b + i];
+        if (k >= 1) {
+          const double2 vi = vpS[i], wi = wpS[i];
           a.x -= vi.x * wj.x + vi.y * wj.y + wi.x * vj.x + wi.y * vj.y;
           a.y -= vi.y * wj.x - vi.x * wj.y + wi.y * vj.x - wi.x * vj.y;
-          a22[size_t(j) * b + i] = a;
+          Anew[size_t(j) * b + i] = a;
         }
+        const double2 v = vS[i];
+        pr += a.x * v.x + a.y * v.y;  // conj(a) v
+        pi += a.x * v.y - a.y * v.x;
       }
     }
-    __syncthreads();
-  }
-  if (t == 0) {
-    d_out[b - 1] = A[size_t(b - 1) * b + (b - 1)].x;
-    if (b >= 1) e_out[b - 1] = 0.0;
+    pr = wave_sum(pr);
+    pi = wave_sum(pi);
+    if (lane == 0) xout[j] = zmul(tau, make_double2(pr, pi));
   }
 }
 
-// The same reduction for b <= 8 kU with A held in registers: thread t owns
+
+// The reduction for b <= 8 kU with A held in registers: thread t owns
 // row i = t % 128 of the columns j = sl + 8 u (sl = t / 128, u < kU; kU = 12
 // for b <= 96, 16 for b <= 128).
 // The product and the rank-2 update then read only v and w (broadcast) from
@@ -734,9 +755,10 @@ __global__ void __launch_bounds__(64) k_tri_vector(const double* __restrict__ d,
 // heev_workspace_doubles(b) doubles.
 size_t heev_workspace_doubles(int b) {
   const size_t bb = size_t(b) * b;
-  // refl (complex b*b), reduction matrix for orders above 128 (complex b*b),
-  // zwork (b*b), tau (complex b), d, e, lam (b each)
-  return 2 * bb + 2 * bb + bb + 2 * size_t(b) + 3 * size_t(b) + 64;
+  // refl (complex b*b), two reduction matrices for orders above 128 (complex
+  // b*b each), zwork (b*b), tau (complex b), d, e, lam (b each), the
+  // product vectors of the stepped reduction (two complex b)
+  return 2 * bb + 4 * bb + bb + 2 * size_t(b) + 3 * size_t(b) + 4 * size_t(b) + 64;
 }
 
 pisco_status_t run_heev(Handle* h, const double2* H, int b, double2* U, double* theta,
@@ -753,12 +775,35 @@ pisco_status_t run_heev(Handle* h, const double2* H, int b, double2* U, double* 
   double* d = reinterpret_cast<double*>(tau + b);
   double* e = d + b;
   double* lam = e + b;
+  double2* gwork2 = reinterpret_cast<double2*>(lam + b);
+  double2* xvec = gwork2 + bb;
   if (b <= kTrdLdsMax)
     PISCO_KERNEL(h, k_hetrd_reg<kTrdLdsMax / 8>, dim3(1), dim3(1024), 0, H, b, refl, tau, d, e);
   else if (b <= 128)
     PISCO_KERNEL(h, k_hetrd_reg<16>, dim3(1), dim3(1024), 0, H, b, refl, tau, d, e);
-  else
-    PISCO_KERNEL(h, k_hetrd, dim3(1), dim3(1024), 0, H, b, gwork, refl, tau, d, e);
+  else {
+    // one launch per step on many one-wave workgroups, the matrix alternating
+    // between two buffers
+    PISCO_KERNEL(h, k_hetrd_sym, dim3(ceil_div(bb, 256)), dim3(256), 0, H, b, gwork);
+    for (int k = 0; k < b; ++k) {
+      const int m = b - 1 - k;
+      const unsigned g = m > 1 ? unsigned((m + 1) / 2) : 1u;
+      const double2* rd = k == 0 ? gwork : ((k - 1) & 1 ? gwork2 : gwork);
+      double2* wr = (k & 1) ? gwork2 : gwork;
+      // x_{k-1} is read by every workgroup while x_k is written: two vectors
+      const double2* xin = (k & 1) ? xvec : xvec + b;
+      double2* xout = (k & 1) ? xvec + b : xvec;
+      if (b <= 256)
+        PISCO_KERNEL(h, k_hetrd_step<4>, dim3(g), dim3(64), 0, rd, wr, b, k, xin, xout, refl,
+                     tau, d, e);
+      else if (b <= 512)
+        PISCO_KERNEL(h, k_hetrd_step<8>, dim3(g), dim3(64), 0, rd, wr, b, k, xin, xout, refl,
+                     tau, d, e);
+      else
+        PISCO_KERNEL(h, k_hetrd_step<16>, dim3(g), dim3(64), 0, rd, wr, b, k, xin, xout, refl,
+                     tau, d, e);
+    }
+  }
   PISCO_KERNEL(h, k_tri_eigval, dim3(b), dim3(kEigThreads), 0, d, e, b, lam);
   if (b <= 128)
     PISCO_KERNEL(h, k_tri_vector<2>, dim3(b), dim3(64), 0, d, e, lam, b, refl, tau, zwork, U, theta);
