@@ -4,9 +4,11 @@
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
 
 One step is one full pass of the hot path on one synthetic scan whose ACS is
-already resident in HBM: calibration Gram by FFT correlation, FP64 signal /
-null split, G(x) on the low-resolution grid, per-voxel power iteration, phase
-reference, sinc interpolation and RSS normalisation (pisco_estimate).  The
+already resident in HBM: calibration correlations by FFT, FP64 signal / null
+split (for 3D problems the Gram products go through the correlation lags on
+the (4 tau + 1)^3 frequency grid instead of an explicit Gram), G(x) on the
+low-resolution grid, per-voxel power iteration, phase reference, sinc
+interpolation and RSS normalisation (pisco_estimate).  The
 default workload is the largest one a single GPU holds: the 3D
 256 x 256 x 128 scan with 32 channels, 32^3 ACS and radius 5 (n = 16480).
 
@@ -59,6 +61,11 @@ def kernel_model(name: str, w, est, rs: int):
     """(bound, algorithmic work per launch, unit) of a kernel, or None.
 
     Work per unit (the method's own need, not what the kernel happens to do):
+      k_tp_pointwise  one Q x Q product per frequency of the structured Gram
+                 product (F = 4 tau + 1 points per axis): read of the block's
+                 spectrum and write of the result, 2 x 16 F^D Q b bytes, plus
+                 the Q x Q matrices, 16 F^D Q^2 bytes (8 F^D Q^2 b flops, an
+                 intensity below the FP64 machine balance: HBM-bound)
       k_gemm_ax  Gram x block, complex FP64 (matrix cores): 8 n^2 b flops
       k_hetrd    Householder tridiagonalisation, order b, complex:
                  16/3 b^3 flops (4/3 b^3 real multiply-adds, x4 for complex)
@@ -68,6 +75,9 @@ def kernel_model(name: str, w, est, rs: int):
       k_rss      read + write of the output maps:     16 Q N_out bytes
     """
     n, b, Q = est.n, est.block, est.Q
+    if name.startswith("k_tp_pointwise"):
+        nf = (4 * int(w.radius) + 1) ** w.D
+        return "hbm", 2.0 * 16 * nf * Q * b + 16.0 * nf * Q * Q, "byte"
     if name.startswith("k_gemm_ax"):
         return "mfma_fp64", 8.0 * n * n * b, "flop"
     if name.startswith("k_hetrd"):
@@ -87,7 +97,7 @@ def kernel_model(name: str, w, est, rs: int):
     return None
 
 
-KERNEL_SOURCES = {"k_gemm_ax": "nullspace.hip", "k_hetrd": "heev.hip", "k_hetrd_reg": "heev.hip",
+KERNEL_SOURCES = {"k_tp_pointwise": "toeplitz.hip", "k_gemm_ax": "nullspace.hip", "k_hetrd": "heev.hip", "k_hetrd_reg": "heev.hip",
                   "k_chol": "nullspace.hip", "k_tri_inv": "nullspace.hip",
                   "k_gemm_tn": "nullspace.hip",
                   "k_gemm_nn": "nullspace.hip", "k_herk": "gx.hip", "k_power": "eig.hip",
@@ -707,6 +717,10 @@ def main():
                                                         "output voxels where the map is "
                                                         "defined)" if golden else None},
                        "nullspace_block": est.block, "signal_rank": rs,
+                       "gram_products": ("structured: A X through the lags on the "
+                                         "(4 tau + 1)^D frequency grid, the Gram not formed"
+                                         if w.D == 3 and est.n >= 4096 else
+                                         "dense: the explicit Gram on FP64 matrix cores"),
                        "nullspace_products": int(counts[2]),
                        "device_status": mixed["status"] | plain["status"],
                        "mixed": form(mixed, tol_mixed, sweep_mixed),
