@@ -43,6 +43,16 @@ __device__ inline void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Workgroup b of nb is dispatched to XCD b % 8 (each XCD has its own L2);
+// the logical index gives each XCD a contiguous range of [0, nb) (a
+// bijection), so that neighbouring logical workgroups share one L2.
+constexpr int kXcds = 8;
+__device__ inline long long xcd_block(unsigned b, unsigned nb) {
+  const unsigned x = b % kXcds, k = b / kXcds, q = nb / kXcds, r = nb % kXcds;
+  const unsigned base = x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q;
+  return (long long)base + k;
+}
+
 __host__ __device__ inline double2 zmul(double2 a, double2 b) {
   return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
@@ -191,7 +201,7 @@ struct NullWs {
   double* jac;     // Cholesky scratch (global-memory fallback) [b*(b+1)*2]
   double* heev;    // eigen-decomposition scratch [heev_workspace_doubles(b)]
   // structured products only (null otherwise): per-frequency Gram blocks
-  // [F^D][Q][Q] and two spectrum buffers of toeplitz_spectrum_elems each
+  // [F^D + 1][kMaxQ][kMaxQ] and two spectrum buffers of toeplitz_spectrum_elems each
   double2* rhat;
   double2* sp0;
   double2* sp1;
@@ -207,12 +217,13 @@ struct ToeplitzOp {
   const double2* Tf;    // F x W: box -> frequency
   const double2* Ti;    // W x F: frequency -> box, 1/F included
   const double2* Tr;    // F x F: lags -> frequency
-  double2* rhat;        // [Fz F F][Q][Q]
+  double2* rhat;        // [Fz F F + 1][kMaxQ][kMaxQ], toeplitz_rhat_elems
   double2* buf0;        // spectrum buffers, toeplitz_spectrum_elems(p, b) each
   double2* buf1;
   int D, W, Wz, F, Fz, Q, L, P;
 };
 size_t toeplitz_spectrum_elems(const Plan& p, int b);
+size_t toeplitz_rhat_elems(const Plan& p);
 // rhat from the lags (once per nullspace call; uses buf0 / buf1).
 pisco_status_t toeplitz_prepare(Handle* h, const ToeplitzOp& op);
 // out = A X (or the Chebyshev step / role of the explicit product) for a

@@ -61,15 +61,6 @@ struct FastDiv {
     return a * fma(r0, e, r0);
   }
 };
-constexpr int kXcds = 8;
-
-// Workgroup b of nb is dispatched to XCD b % 8; the logical index gives each
-// XCD a contiguous range (a bijection on [0, nb)).
-__device__ inline long long xcd_block(unsigned b, unsigned nb) {
-  const unsigned x = b % kXcds, k = b / kXcds, q = nb / kXcds, r = nb % kXcds;
-  const unsigned base = x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q;
-  return (long long)base + k;
-}
 
 // The twisted factorisation of tri::twisted_vector on two lanes: lane 0
 // runs the top-down pivots D+ (kept in z) and multipliers Lp while lane 1

@@ -20,18 +20,6 @@ namespace pisco {
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-constexpr int kXcds = 8;
-
-// Workgroup b of nb is dispatched to XCD b % 8; the logical index gives each
-// XCD a contiguous range of patches (a bijection on [0, nb)), so that the
-// patches whose entries share lines of the entry-major outputs (V) are
-// written through one L2.
-__device__ inline long long llr_block(unsigned b, unsigned nb) {
-  const unsigned x = b % kXcds, k = b / kXcds, q = nb / kXcds, r = nb % kXcds;
-  const unsigned base = x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q;
-  return (long long)base + k;
-}
-
 // -A_b packed upper, voxel-major [B][Q(Q+1)/2] (each patch's entries
 // contiguous, as the Lanczos kernel reads them); X is [B][Q][m].
 // One wave per patch on FP32 matrix cores (v_mfma_f32_16x16x4f32): the
@@ -47,7 +35,7 @@ __global__ void __launch_bounds__(64) k_llr_gram(const float2* __restrict__ X,
                                                  int m, unsigned* status) {
   constexpr int kC = 32;  // pixels per chunk
   __shared__ float2 tile[16 * NQB][kC + 1];
-  const long long b = llr_block(blockIdx.x, gridDim.x);
+  const long long b = xcd_block(blockIdx.x, gridDim.x);
   if (b >= B) return;
   const int l = threadIdx.x, li = l & 15, kg = l >> 4;
   const float2* xb = X + size_t(b) * Q * m;
@@ -123,7 +111,7 @@ __global__ void __launch_bounds__(64) k_llr_project(const float2* __restrict__ X
                                                     float2* __restrict__ Xr, long long B, int Q,
                                                     int m, int r) {
   __shared__ float2 vs[8 * kMaxQ];
-  const long long b = llr_block(blockIdx.x, gridDim.x);
+  const long long b = xcd_block(blockIdx.x, gridDim.x);
   if (b >= B) return;
   const int l = threadIdx.x;
   for (int e = l; e < r * Q; e += 64) vs[e] = V[size_t(e) * B + b];

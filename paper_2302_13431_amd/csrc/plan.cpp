@@ -140,7 +140,7 @@ size_t layout_null(const Plan& p, int b, void* ws, NullWs* o, bool structured) {
   w.jac = c.take<double>((size_t(b) + 1) * b * 2);
   w.heev = c.take<double>(heev_workspace_doubles(b));
   if (structured) {
-    w.rhat = c.take<double2>(size_t(p.K[0]) * p.K[1] * p.K[2] * p.Q * p.Q);
+    w.rhat = c.take<double2>(toeplitz_rhat_elems(p));
     w.sp0 = c.take<double2>(toeplitz_spectrum_elems(p, b));
     w.sp1 = c.take<double2>(toeplitz_spectrum_elems(p, b));
   }

@@ -32,18 +32,23 @@ __device__ inline int tp_pidx(int p, int q, int Q) {  // p <= q
   return p * Q - p * (p - 1) / 2 + (q - p);
 }
 
-// rhat[f][p][q] from the transformed lags lf[pair][f]: conj below the
-// diagonal, real diagonal
+// rhat[f][p][q] (rows of kMaxQ, zero past Q, and a zero matrix at f = nf)
+// from the transformed lags lf[pair][f]: conj below the diagonal, real
+// diagonal
+constexpr int kRQ = kMaxQ * kMaxQ;  // elements per frequency
 __global__ void k_tp_rhat(const double2* __restrict__ lf, double2* __restrict__ rhat, int Q,
                           long long nf) {
   const long long idx = blockIdx.x * 256LL + threadIdx.x;
-  if (idx >= nf * Q * Q) return;
-  const long long f = idx / (Q * Q);
-  const int e = int(idx - f * Q * Q), p = e / Q, q = e - p * Q;
-  const int lo = p < q ? p : q, hi = p < q ? q : p;
-  double2 v = lf[size_t(tp_pidx(lo, hi, Q)) * nf + f];
-  if (p > q) v.y = -v.y;
-  if (p == q) v.y = 0.0;
+  if (idx >= (nf + 1) * kRQ) return;
+  const long long f = idx / kRQ;
+  const int e = int(idx - f * kRQ), p = e / kMaxQ, q = e - p * kMaxQ;
+  double2 v = make_double2(0.0, 0.0);
+  if (f < nf && p < Q && q < Q) {
+    const int lo = p < q ? p : q, hi = p < q ? q : p;
+    v = lf[size_t(tp_pidx(lo, hi, Q)) * nf + f];
+    if (p > q) v.y = -v.y;
+    if (p == q) v.y = 0.0;
+  }
   rhat[idx] = v;
 }
 
@@ -81,7 +86,7 @@ __global__ void __launch_bounds__(256) k_tp_pointwise(const double2* __restrict_
   const int c0 = blockIdx.x * 64 + wv * 16;
   if (c0 >= b) return;  // the whole wave
   const double2* X = Xh + size_t(f) * b * Q;
-  const double2* R = rhat + size_t(f) * Q * Q;
+  const double2* R = rhat + size_t(f) * kRQ;
   const bool crow = c0 + li < b;
   f64x4 t1[2], t2[2], t3[2];
 #pragma unroll
@@ -98,7 +103,7 @@ __global__ void __launch_bounds__(256) k_tp_pointwise(const double2* __restrict_
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
       const int p = 16 * j + li;
-      const double2 r = p < Q && q < Q ? R[p * Q + q] : make_double2(0.0, 0.0);
+      const double2 r = R[p * kMaxQ + q];
       t1[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(x.x, r.x, t1[j], 0, 0, 0);
       t2[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(x.y, r.y, t2[j], 0, 0, 0);
       t3[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(x.x + x.y, r.x + r.y, t3[j], 0, 0, 0);
@@ -113,6 +118,182 @@ __global__ void __launch_bounds__(256) k_tp_pointwise(const double2* __restrict_
       if (c < b && p < Q)
         Y[size_t(c) * Q + p] = make_double2(t1[j][v] - t2[j][v], t3[j][v] - t1[j][v] - t2[j][v]);
     }
+}
+
+// 3D products: the z pass, the per-frequency products and the inverse z pass
+// in one kernel, so that the full spectrum [F^3][b][Q] never reaches memory.
+// in  = [Wz][F F][b][Q] after the x and y passes, out = the same layout
+// after the inverse z pass; rhat frequency f = (fz F + fy) F + fx.
+// Workgroup = one (fy, fx) pair x 16 columns c (XCD-contiguous, so that the
+// tiles of one pair share its matrices in one L2), four waves w; the
+// frequencies go two per step k (fz = 2k + par, par = 0, 1):
+//   forward z: wave w forms X_fz at the MFMA steps s = 2w, 2w + 1 of both
+//     frequencies from the 16 x Q x Wz input tile in LDS (FP64 FMA) and
+//     puts them in LDS (xf);
+//   products: wave (j, par) = (w & 1, w >> 1) takes output channels
+//     p in [16 j, 16 j + 16) of frequency 2k + par, 24 FP64 MFMAs
+//     (three-multiplication complex products, as in k_tp_pointwise), and
+//     puts Y in LDS (yb);
+//   inverse z: wave w accumulates the outputs z = w, w + 4, ... of the
+//     whole 16 x Q tile from both frequencies' Y.
+// Software pipeline, one barrier per step: the MFMAs of k run while the same
+// wave accumulates k - 1 and forms its share of k + 1, and the matrices of
+// k + 1 are loaded during k (two register sets, the loop unrolled by two);
+// no branch inside a step (a frequency past F takes the zero matrix).
+template <int kW>
+__global__ void __launch_bounds__(256) k_tp_zfused(const double2* __restrict__ in,
+                                                   const double2* __restrict__ rhat,
+                                                   const double2* __restrict__ Tf,
+                                                   const double2* __restrict__ Ti,
+                                                   double2* __restrict__ out, int Q, int b, int F,
+                                                   int ctiles, const int* __restrict__ role) {
+  constexpr int QS = kMaxQ + 1;      // padded LDS row
+  constexpr int kS = kMaxQ / 4;      // MFMA steps
+  constexpr int kZ = (kW + 3) / 4;   // output z per wave
+  static_assert(kS == 8, "two MFMA steps per wave in the forward z pass");
+  __shared__ double2 xs[kW * 16 * QS];
+  __shared__ double2 xf[2][2][kS][64];    // [buffer][parity][s][lane]
+  __shared__ double2 yb[2][2][2][4][64];  // [buffer][parity][j][v][lane]
+  if (role && *role == 0) return;
+  const int l = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int j = w & 1, par = w >> 1;
+  const int li = l & 15, lk = l >> 4;
+  const long long tile = xcd_block(blockIdx.x, gridDim.x);
+  const int pair = int(tile / ctiles), c0 = int(tile % ctiles) * 16;
+  const size_t FF = size_t(F) * F;
+  const size_t zstride = FF * b * Q;
+  {
+    // stage x[z][c][q], zeros past b and past Q, all loads first
+    const double2* src = in + (size_t(pair) * b + c0) * Q;
+    constexpr int kIt = (kW * 16 * kMaxQ + 255) / 256;
+    double2 v[kIt];
+#pragma unroll
+    for (int u = 0; u < kIt; ++u) {
+      const int e = threadIdx.x + 256 * u;
+      const int z = e / (16 * kMaxQ), r = e - z * 16 * kMaxQ, c = r / kMaxQ, q = r - c * kMaxQ;
+      v[u] = z < kW && q < Q && c0 + c < b ? src[z * zstride + size_t(c) * Q + q]
+                                            : make_double2(0.0, 0.0);
+    }
+#pragma unroll
+    for (int u = 0; u < kIt; ++u) {
+      const int e = threadIdx.x + 256 * u;
+      const int z = e / (16 * kMaxQ), r = e - z * 16 * kMaxQ, c = r / kMaxQ, q = r - c * kMaxQ;
+      if (z < kW) xs[(z * 16 + c) * QS + q] = v[u];
+    }
+    // the Y of "step -1" is zero
+    double2* y1 = &yb[1][0][0][0][0];
+#pragma unroll
+    for (int u = 0; u < 2 * 2 * 4 * 64 / 256; ++u) y1[threadIdx.x + 256 * u] = make_double2(0.0, 0.0);
+  }
+  const int p = 16 * j + li;
+  const int iters = (F + 1) / 2;
+  // X of frequencies 2k and 2k + 1 at steps 2w, 2w + 1 into xf[buf]
+  auto fwd = [&](int k, int buf) {
+    const int f0 = 2 * k < F ? 2 * k : 0, f1 = 2 * k + 1 < F ? 2 * k + 1 : 0;
+    const double2* t0 = Tf + size_t(f0) * kW;
+    const double2* t1 = Tf + size_t(f1) * kW;
+    double2 a[2][2];
+#pragma unroll
+    for (int f = 0; f < 2; ++f)
+#pragma unroll
+      for (int u = 0; u < 2; ++u) a[f][u] = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int z = 0; z < kW; ++z) {
+      const double2 m0 = t0[z], m1 = t1[z];
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const double2 x = xs[(z * 16 + li) * QS + 4 * (2 * w + u) + lk];
+        a[0][u].x = fma(m0.x, x.x, fma(-m0.y, x.y, a[0][u].x));
+        a[0][u].y = fma(m0.x, x.y, fma(m0.y, x.x, a[0][u].y));
+        a[1][u].x = fma(m1.x, x.x, fma(-m1.y, x.y, a[1][u].x));
+        a[1][u].y = fma(m1.x, x.y, fma(m1.y, x.x, a[1][u].y));
+      }
+    }
+#pragma unroll
+    for (int f = 0; f < 2; ++f)
+#pragma unroll
+      for (int u = 0; u < 2; ++u) xf[buf][f][2 * w + u][l] = a[f][u];
+  };
+  // the matrix operand of frequency fz (the zero matrix past F): loads
+  // without conditions, so that the wait before the MFMAs can leave the
+  // next frequency's loads in flight
+  auto load_r = [&](int fz, double2* r) {
+    const double2* R = rhat + (fz < F ? size_t(fz) * FF + pair : FF * F) * kRQ + p * kMaxQ + lk;
+#pragma unroll
+    for (int s = 0; s < kS; ++s) r[s] = R[4 * s];
+  };
+  // outputs z = w + 4 i (clamped past Wz: computed, never stored), element
+  // e = (jj, v) of lane l at c = lk + 4 v, p = 16 jj + li
+  double2 acc[kZ][8];
+#pragma unroll
+  for (int i = 0; i < kZ; ++i)
+#pragma unroll
+    for (int e = 0; e < 8; ++e) acc[i][e] = make_double2(0.0, 0.0);
+  auto inv = [&](int k, int buf) {
+#pragma unroll
+    for (int f = 0; f < 2; ++f) {
+      const int fz = 2 * k + f < F && k >= 0 ? 2 * k + f : 0;
+      double2 y[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) y[e] = yb[buf][f][e >> 2][e & 3][l];
+#pragma unroll
+      for (int i = 0; i < kZ; ++i) {
+        const int z = w + 4 * i < kW ? w + 4 * i : kW - 1;
+        const double2 m = Ti[size_t(z) * F + fz];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          acc[i][e].x = fma(m.x, y[e].x, fma(-m.y, y[e].y, acc[i][e].x));
+          acc[i][e].y = fma(m.x, y[e].y, fma(m.y, y[e].x, acc[i][e].y));
+        }
+      }
+    }
+  };
+  // step k: MFMAs of frequency 2k + par with its matrix in r, the next
+  // step's matrix into rn
+  auto step = [&](int k, const double2* r, double2* rn) {
+    __syncthreads();  // xf[k & 1] and yb[(k - 1) & 1] complete
+    load_r(2 * k + 2 + par, rn);
+    f64x4 c1 = {0.0, 0.0, 0.0, 0.0}, c2 = c1, c3 = c1;
+#pragma unroll
+    for (int s = 0; s < kS; ++s) {
+      const double2 x = xf[k & 1][par][s][l];
+      c1 = __builtin_amdgcn_mfma_f64_16x16x4f64(x.x, r[s].x, c1, 0, 0, 0);
+      c2 = __builtin_amdgcn_mfma_f64_16x16x4f64(x.y, r[s].y, c2, 0, 0, 0);
+      c3 = __builtin_amdgcn_mfma_f64_16x16x4f64(x.x + x.y, r[s].x + r[s].y, c3, 0, 0, 0);
+    }
+    // independent of the MFMAs above: step k - 1 into the outputs (zero Y
+    // at k = 0), this wave's share of step k + 1 (unused after the last)
+    inv(k - 1, (k - 1) & 1);
+    fwd(k + 1, (k + 1) & 1);
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+      yb[k & 1][par][j][v][l] = make_double2(c1[v] - c2[v], c3[v] - c1[v] - c2[v]);
+  };
+  __syncthreads();  // xs staged
+  double2 ra[kS], rb[kS];
+  load_r(par, ra);
+  fwd(0, 0);
+  int k = 0;
+  for (; k + 2 <= iters; k += 2) {
+    step(k, ra, rb);
+    step(k + 1, rb, ra);
+  }
+  if (k < iters) step(k, ra, rb);
+  __syncthreads();
+  inv(iters - 1, (iters - 1) & 1);
+  double2* dst = out + (size_t(pair) * b + c0) * Q + li;
+#pragma unroll
+  for (int i = 0; i < kZ; ++i) {
+    const int z = w + 4 * i;
+    if (z < kW) {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int c = lk + 4 * (e & 3), pp = 16 * (e >> 2);
+        if (c0 + c < b && pp + li < Q) dst[z * zstride + size_t(c) * Q + pp] = acc[i][e];
+      }
+    }
+  }
 }
 
 // out[c][p L + i] from box[cell(i)][c][p]: S, or a S + bc X + g prev with
@@ -156,6 +337,10 @@ size_t toeplitz_spectrum_elems(const Plan& p, int b) {
   return size_t(p.K[0]) * p.K[1] * p.K[2] * size_t(b) * p.Q;
 }
 
+size_t toeplitz_rhat_elems(const Plan& p) {
+  return (size_t(p.K[0]) * p.K[1] * p.K[2] + 1) * kRQ;
+}
+
 pisco_status_t toeplitz_prepare(Handle* h, const ToeplitzOp& op) {
   // lags [P][Bz][B][B] -> [P][Fz][F][F] (FP64), then the per-frequency
   // Hermitian matrices
@@ -172,7 +357,7 @@ pisco_status_t toeplitz_prepare(Handle* h, const ToeplitzOp& op) {
     lf = op.buf0;
   }
   const long long nf = 1LL * Fz * F * F;
-  PISCO_KERNEL(h, k_tp_rhat, dim3(ceil_div(nf * op.Q * op.Q, 256)), dim3(256), 0, lf, op.rhat,
+  PISCO_KERNEL(h, k_tp_rhat, dim3(ceil_div((nf + 1) * kRQ, 256)), dim3(256), 0, lf, op.rhat,
                op.Q, nf);
   return PISCO_OK;
 }
@@ -191,6 +376,28 @@ pisco_status_t toeplitz_product(Handle* h, const ToeplitzOp& op, const double2* 
   if ((st = axis_transform64(h, op.buf0, op.buf1, fx, 1, F, op.Tf))) return st;
   const int fy[4] = {Wz, W, F * bq, 1};
   if ((st = axis_transform64(h, op.buf1, op.buf0, fy, 1, F, op.Tf))) return st;
+  if (op.D == 3 && (W & 1) && W >= 3 && W <= 11 && Fz == F && Wz == W) {
+    // z pass, per-frequency products and inverse z pass fused: buf0 -> buf1
+    const int ctiles = ceil_div(b, 16);
+    const dim3 grid(unsigned(F * F * ctiles));
+    const dim3 blk(256);
+    switch (W) {
+#define TP_ZF(w)                                                                                 \
+  case w:                                                                                        \
+    PISCO_KERNEL(h, k_tp_zfused<w>, grid, blk, 0, op.buf0, op.rhat, op.Tf, op.Ti, op.buf1, Q, b, \
+                 F, ctiles, role);                                                               \
+    break;
+      TP_ZF(3) TP_ZF(5) TP_ZF(7) TP_ZF(9) TP_ZF(11)
+#undef TP_ZF
+    }
+    const int iy[4] = {Wz, F, F * bq, 1};
+    if ((st = axis_transform64(h, op.buf1, op.buf0, iy, 1, W, op.Ti))) return st;
+    const int ix[4] = {Wz * W, F, bq, 1};
+    if ((st = axis_transform64(h, op.buf0, op.buf1, ix, 1, W, op.Ti))) return st;
+    PISCO_KERNEL(h, k_tp_gather, dim3(ceil_div(1LL * b * n, 256)), dim3(256), 0, op.buf1, op.sup,
+                 X, out, prev, n, op.L, Q, b, W, W / 2, W / 2, coef, role);
+    return PISCO_OK;
+  }
   double2* spec = op.buf0;
   double2* other = op.buf1;
   if (op.D == 3) {
