@@ -124,173 +124,192 @@ __global__ void __launch_bounds__(256) k_tp_pointwise(const double2* __restrict_
 // in one kernel, so that the full spectrum [F^3][b][Q] never reaches memory.
 // in  = [Wz][F F][b][Q] after the x and y passes, out = the same layout
 // after the inverse z pass; rhat frequency f = (fz F + fy) F + fx.
+//
+// The z box is centred (z = tau + d, |d| <= tau), so the z transforms pair
+// the frequencies f and F - f: with u_d = x(tau + d) + x(tau - d) (u_0 =
+// x(tau)), v_d = x(tau + d) - x(tau - d), and Tf[f][tau + d] = cos + i sin,
+//   X_f = C + i S,  X_(F-f) = C - i S,  C = sum_d cos_d u_d,  S = sum_d sin_d v_d,
+// and back, with S' = Y_f + Y_(F-f), D' = Y_f - Y_(F-f), Ti[tau + d][f] =
+// c' + i s' (the 1/F included),
+//   out(tau +- d) += c'_d S' +- i s'_d D'
+// (a quarter of the multiply-adds of the plain transforms).  The FP64 matrix
+// cores and the FP64 vector ALUs do not work at once, so this matters as
+// much as the MFMAs.
+//
 // Workgroup = one (fy, fx) pair x 16 columns c (XCD-contiguous, so that the
-// tiles of one pair share its matrices in one L2), four waves w; the
-// frequencies go two per step k (fz = 2k + par, par = 0, 1):
-//   forward z: wave w forms X_fz at the MFMA steps s = 2w, 2w + 1 of both
-//     frequencies from the 16 x Q x Wz input tile in LDS (FP64 FMA) and
-//     puts them in LDS (xf);
-//   products: wave (j, par) = (w & 1, w >> 1) takes output channels
-//     p in [16 j, 16 j + 16) of frequency 2k + par, 24 FP64 MFMAs
-//     (three-multiplication complex products, as in k_tp_pointwise), and
-//     puts Y in LDS (yb);
-//   inverse z: wave w accumulates the outputs z = w, w + 4, ... of the
-//     whole 16 x Q tile from both frequencies' Y.
-// Software pipeline, one barrier per step: the MFMAs of k run while the same
-// wave accumulates k - 1 and forms its share of k + 1, and the matrices of
-// k + 1 are loaded during k (two register sets, the loop unrolled by two);
-// no branch inside a step (a frequency past F takes the zero matrix).
+// tiles of one pair share its matrices in one L2), eight waves in two roles
+// (one of each per SIMD), steps k = 0 .. 2 tau: frequency 0 alone, then the
+// pairs (k, F - k); one barrier per step:
+//   matrix waves (j, par), w < 4: output channels p in [16 j, 16 j + 16) of
+//     the step's frequency par, 24 FP64 MFMAs (three-multiplication complex
+//     products, as in k_tp_pointwise), Y into LDS (yb); the matrices of
+//     step k + 1 load during step k;
+//   vector waves v = w - 4: X of both frequencies of step k + 1 at the MFMA
+//     steps s = 2v, 2v + 1 (u, v of their inputs held in registers) into LDS
+//     (xf), and two of the eight output elements per lane accumulated from
+//     step k - 1.
 template <int kW>
-__global__ void __launch_bounds__(256) k_tp_zfused(const double2* __restrict__ in,
+__global__ void __launch_bounds__(512) k_tp_zfused(const double2* __restrict__ in,
                                                    const double2* __restrict__ rhat,
                                                    const double2* __restrict__ Tf,
                                                    const double2* __restrict__ Ti,
                                                    double2* __restrict__ out, int Q, int b, int F,
                                                    int ctiles, const int* __restrict__ role) {
-  constexpr int QS = kMaxQ + 1;      // padded LDS row
-  constexpr int kS = kMaxQ / 4;      // MFMA steps
-  constexpr int kZ = (kW + 3) / 4;   // output z per wave
-  static_assert(kS == 8, "two MFMA steps per wave in the forward z pass");
-  __shared__ double2 xs[kW * 16 * QS];
-  __shared__ double2 xf[2][2][kS][64];    // [buffer][parity][s][lane]
-  __shared__ double2 yb[2][2][2][4][64];  // [buffer][parity][j][v][lane]
+  constexpr int kT = kW / 2;     // tau
+  constexpr int kS = kMaxQ / 4;  // MFMA steps
+  static_assert(kS == 8, "two MFMA steps per vector wave");
+  __shared__ double2 xf[2][2][kS][64];    // [buffer][frequency of the step][s][lane]
+  __shared__ double2 yb[2][2][2][4][64];  // [buffer][frequency of the step][j][v][lane]
   if (role && *role == 0) return;
   const int l = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int j = w & 1, par = w >> 1;
   const int li = l & 15, lk = l >> 4;
   const long long tile = xcd_block(blockIdx.x, gridDim.x);
   const int pair = int(tile / ctiles), c0 = int(tile % ctiles) * 16;
   const size_t FF = size_t(F) * F;
   const size_t zstride = FF * b * Q;
-  {
-    // stage x[z][c][q], zeros past b and past Q, all loads first
-    const double2* src = in + (size_t(pair) * b + c0) * Q;
-    constexpr int kIt = (kW * 16 * kMaxQ + 255) / 256;
-    double2 v[kIt];
+  const int iters = 2 * kT + 1;
+  if (w < 4) {
+    // matrix waves; the loads of the matrices go without conditions (the
+    // zero matrix at FF F when a step has no such frequency), so that the
+    // wait before the MFMAs can leave the next step's loads in flight
+    const int j = w & 1, par = w >> 1;
+    const int p = 16 * j + li;
+    auto load_r = [&](int k, double2* r) {
+      const int fz = par == 0 ? k : (k == 0 ? F : F - k);
+      const double2* R =
+          rhat + (k < iters && fz < F ? size_t(fz) * FF + pair : FF * F) * kRQ + p * kMaxQ + lk;
 #pragma unroll
-    for (int u = 0; u < kIt; ++u) {
-      const int e = threadIdx.x + 256 * u;
-      const int z = e / (16 * kMaxQ), r = e - z * 16 * kMaxQ, c = r / kMaxQ, q = r - c * kMaxQ;
-      v[u] = z < kW && q < Q && c0 + c < b ? src[z * zstride + size_t(c) * Q + q]
-                                            : make_double2(0.0, 0.0);
+      for (int s = 0; s < kS; ++s) r[s] = R[4 * s];
+    };
+    auto products = [&](int k, const double2* r) {
+      f64x4 c1 = {0.0, 0.0, 0.0, 0.0}, c2 = c1, c3 = c1;
+#pragma unroll
+      for (int s = 0; s < kS; ++s) {
+        const double2 x = xf[k & 1][par][s][l];
+        c1 = __builtin_amdgcn_mfma_f64_16x16x4f64(x.x, r[s].x, c1, 0, 0, 0);
+        c2 = __builtin_amdgcn_mfma_f64_16x16x4f64(x.y, r[s].y, c2, 0, 0, 0);
+        c3 = __builtin_amdgcn_mfma_f64_16x16x4f64(x.x + x.y, r[s].x + r[s].y, c3, 0, 0, 0);
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        yb[k & 1][par][j][v][l] = make_double2(c1[v] - c2[v], c3[v] - c1[v] - c2[v]);
+    };
+    double2 ra[kS], rb[kS];
+    load_r(0, ra);
+    int k = 0;
+    for (; k + 2 <= iters; k += 2) {
+      __syncthreads();  // xf[k & 1] complete, yb[k & 1] read
+      load_r(k + 1, rb);
+      products(k, ra);
+      __syncthreads();
+      load_r(k + 2, ra);
+      products(k + 1, rb);
     }
-#pragma unroll
-    for (int u = 0; u < kIt; ++u) {
-      const int e = threadIdx.x + 256 * u;
-      const int z = e / (16 * kMaxQ), r = e - z * 16 * kMaxQ, c = r / kMaxQ, q = r - c * kMaxQ;
-      if (z < kW) xs[(z * 16 + c) * QS + q] = v[u];
+    if (k < iters) {
+      __syncthreads();
+      products(k, ra);
     }
-    // the Y of "step -1" is zero
-    double2* y1 = &yb[1][0][0][0][0];
-#pragma unroll
-    for (int u = 0; u < 2 * 2 * 4 * 64 / 256; ++u) y1[threadIdx.x + 256 * u] = make_double2(0.0, 0.0);
+    __syncthreads();
+    return;
   }
-  const int p = 16 * j + li;
-  const int iters = (F + 1) / 2;
-  // X of frequencies 2k and 2k + 1 at steps 2w, 2w + 1 into xf[buf]
-  auto fwd = [&](int k, int buf) {
-    const int f0 = 2 * k < F ? 2 * k : 0, f1 = 2 * k + 1 < F ? 2 * k + 1 : 0;
-    const double2* t0 = Tf + size_t(f0) * kW;
-    const double2* t1 = Tf + size_t(f1) * kW;
-    double2 a[2][2];
+  // vector waves: elements (c = li, q = 4 s + lk), s = 2 vw + u, forward;
+  // output elements e = 2 vw + u at (c = lk + 4 (e & 3), p = 16 (e >> 2) + li)
+  const int vw = w - 4;
+  double2 U[2][kT + 1], V[2][kT + 1];
+  {
+    const bool rowok = c0 + li < b;
+    const double2* src = in + (size_t(pair) * b + c0 + li) * Q;
+    double2 x[2][kW];
 #pragma unroll
-    for (int f = 0; f < 2; ++f)
+    for (int u = 0; u < 2; ++u) {
+      const int q = 4 * (2 * vw + u) + lk;
+      const bool ok = rowok && q < Q;
 #pragma unroll
-      for (int u = 0; u < 2; ++u) a[f][u] = make_double2(0.0, 0.0);
+      for (int z = 0; z < kW; ++z) x[u][z] = ok ? src[z * zstride + q] : make_double2(0.0, 0.0);
+    }
 #pragma unroll
-    for (int z = 0; z < kW; ++z) {
-      const double2 m0 = t0[z], m1 = t1[z];
+    for (int u = 0; u < 2; ++u) {
+      U[u][0] = x[u][kT];
+      V[u][0] = make_double2(0.0, 0.0);
 #pragma unroll
-      for (int u = 0; u < 2; ++u) {
-        const double2 x = xs[(z * 16 + li) * QS + 4 * (2 * w + u) + lk];
-        a[0][u].x = fma(m0.x, x.x, fma(-m0.y, x.y, a[0][u].x));
-        a[0][u].y = fma(m0.x, x.y, fma(m0.y, x.x, a[0][u].y));
-        a[1][u].x = fma(m1.x, x.x, fma(-m1.y, x.y, a[1][u].x));
-        a[1][u].y = fma(m1.x, x.y, fma(m1.y, x.x, a[1][u].y));
+      for (int d = 1; d <= kT; ++d) {
+        U[u][d] = make_double2(x[u][kT + d].x + x[u][kT - d].x, x[u][kT + d].y + x[u][kT - d].y);
+        V[u][d] = make_double2(x[u][kT + d].x - x[u][kT - d].x, x[u][kT + d].y - x[u][kT - d].y);
       }
     }
+  }
+  auto fwd = [&](int k, int buf) {  // frequencies k and F - k of step k
+    const double2* tf = Tf + size_t(k < F ? k : 0) * kW + kT;
 #pragma unroll
-    for (int f = 0; f < 2; ++f)
+    for (int u = 0; u < 2; ++u) {
+      double2 C = make_double2(0.0, 0.0), S = C;
 #pragma unroll
-      for (int u = 0; u < 2; ++u) xf[buf][f][2 * w + u][l] = a[f][u];
+      for (int d = 0; d <= kT; ++d) {
+        const double2 m = tf[d];
+        C.x = fma(m.x, U[u][d].x, C.x);
+        C.y = fma(m.x, U[u][d].y, C.y);
+        if (d > 0) {
+          S.x = fma(m.y, V[u][d].x, S.x);
+          S.y = fma(m.y, V[u][d].y, S.y);
+        }
+      }
+      xf[buf][0][2 * vw + u][l] = make_double2(C.x - S.y, C.y + S.x);
+      xf[buf][1][2 * vw + u][l] = make_double2(C.x + S.y, C.y - S.x);
+    }
   };
-  // the matrix operand of frequency fz (the zero matrix past F): loads
-  // without conditions, so that the wait before the MFMAs can leave the
-  // next frequency's loads in flight
-  auto load_r = [&](int fz, double2* r) {
-    const double2* R = rhat + (fz < F ? size_t(fz) * FF + pair : FF * F) * kRQ + p * kMaxQ + lk;
+  double2 P[2][kT + 1], M[2][kT + 1];
 #pragma unroll
-    for (int s = 0; s < kS; ++s) r[s] = R[4 * s];
-  };
-  // outputs z = w + 4 i (clamped past Wz: computed, never stored), element
-  // e = (jj, v) of lane l at c = lk + 4 v, p = 16 jj + li
-  double2 acc[kZ][8];
+  for (int u = 0; u < 2; ++u)
 #pragma unroll
-  for (int i = 0; i < kZ; ++i)
+    for (int d = 0; d <= kT; ++d) P[u][d] = M[u][d] = make_double2(0.0, 0.0);
+  auto inv = [&](int k, int buf) {  // Y of step k (zero at k = -1)
+    const double2* ti = Ti + size_t(kT) * F + (k > 0 ? k : 0);
 #pragma unroll
-    for (int e = 0; e < 8; ++e) acc[i][e] = make_double2(0.0, 0.0);
-  auto inv = [&](int k, int buf) {
+    for (int u = 0; u < 2; ++u) {
+      const int e = 2 * vw + u;
+      const double2 ya = yb[buf][0][e >> 2][e & 3][l], yc = yb[buf][1][e >> 2][e & 3][l];
+      const double2 Sv = make_double2(ya.x + yc.x, ya.y + yc.y);
+      const double2 Dv = make_double2(ya.x - yc.x, ya.y - yc.y);
 #pragma unroll
-    for (int f = 0; f < 2; ++f) {
-      const int fz = 2 * k + f < F && k >= 0 ? 2 * k + f : 0;
-      double2 y[8];
-#pragma unroll
-      for (int e = 0; e < 8; ++e) y[e] = yb[buf][f][e >> 2][e & 3][l];
-#pragma unroll
-      for (int i = 0; i < kZ; ++i) {
-        const int z = w + 4 * i < kW ? w + 4 * i : kW - 1;
-        const double2 m = Ti[size_t(z) * F + fz];
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          acc[i][e].x = fma(m.x, y[e].x, fma(-m.y, y[e].y, acc[i][e].x));
-          acc[i][e].y = fma(m.x, y[e].y, fma(m.y, y[e].x, acc[i][e].y));
+      for (int d = 0; d <= kT; ++d) {
+        const double2 m = ti[size_t(d) * F];
+        P[u][d].x = fma(m.x, Sv.x, P[u][d].x);
+        P[u][d].y = fma(m.x, Sv.y, P[u][d].y);
+        if (d > 0) {
+          M[u][d].x = fma(m.y, Dv.x, M[u][d].x);
+          M[u][d].y = fma(m.y, Dv.y, M[u][d].y);
         }
       }
     }
   };
-  // step k: MFMAs of frequency 2k + par with its matrix in r, the next
-  // step's matrix into rn
-  auto step = [&](int k, const double2* r, double2* rn) {
-    __syncthreads();  // xf[k & 1] and yb[(k - 1) & 1] complete
-    load_r(2 * k + 2 + par, rn);
-    f64x4 c1 = {0.0, 0.0, 0.0, 0.0}, c2 = c1, c3 = c1;
+  // the Y of step -1 is zero (each lane reads back only what it wrote here)
 #pragma unroll
-    for (int s = 0; s < kS; ++s) {
-      const double2 x = xf[k & 1][par][s][l];
-      c1 = __builtin_amdgcn_mfma_f64_16x16x4f64(x.x, r[s].x, c1, 0, 0, 0);
-      c2 = __builtin_amdgcn_mfma_f64_16x16x4f64(x.y, r[s].y, c2, 0, 0, 0);
-      c3 = __builtin_amdgcn_mfma_f64_16x16x4f64(x.x + x.y, r[s].x + r[s].y, c3, 0, 0, 0);
-    }
-    // independent of the MFMAs above: step k - 1 into the outputs (zero Y
-    // at k = 0), this wave's share of step k + 1 (unused after the last)
-    inv(k - 1, (k - 1) & 1);
-    fwd(k + 1, (k + 1) & 1);
-#pragma unroll
-    for (int v = 0; v < 4; ++v)
-      yb[k & 1][par][j][v][l] = make_double2(c1[v] - c2[v], c3[v] - c1[v] - c2[v]);
-  };
-  __syncthreads();  // xs staged
-  double2 ra[kS], rb[kS];
-  load_r(par, ra);
-  fwd(0, 0);
-  int k = 0;
-  for (; k + 2 <= iters; k += 2) {
-    step(k, ra, rb);
-    step(k + 1, rb, ra);
+  for (int u = 0; u < 2; ++u) {
+    const int e = 2 * vw + u;
+    yb[1][0][e >> 2][e & 3][l] = make_double2(0.0, 0.0);
+    yb[1][1][e >> 2][e & 3][l] = make_double2(0.0, 0.0);
   }
-  if (k < iters) step(k, ra, rb);
+  fwd(0, 0);
+  for (int k = 0; k < iters; ++k) {
+    __syncthreads();            // xf[k & 1] read next, yb[(k - 1) & 1] complete
+    fwd(k + 1, (k + 1) & 1);  // unused after the last step
+    inv(k - 1, (k - 1) & 1);
+  }
   __syncthreads();
   inv(iters - 1, (iters - 1) & 1);
-  double2* dst = out + (size_t(pair) * b + c0) * Q + li;
+  double2* dst = out + (size_t(pair) * b + c0) * Q;
 #pragma unroll
-  for (int i = 0; i < kZ; ++i) {
-    const int z = w + 4 * i;
-    if (z < kW) {
+  for (int u = 0; u < 2; ++u) {
+    const int e = 2 * vw + u;
+    const int c = lk + 4 * (e & 3), pp = 16 * (e >> 2) + li;
+    if (c0 + c < b && pp < Q) {
+      double2* o = dst + size_t(c) * Q + pp;
+      o[kT * zstride] = P[u][0];
 #pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const int c = lk + 4 * (e & 3), pp = 16 * (e >> 2);
-        if (c0 + c < b && pp + li < Q) dst[z * zstride + size_t(c) * Q + pp] = acc[i][e];
+      for (int d = 1; d <= kT; ++d) {
+        o[(kT + d) * zstride] = make_double2(P[u][d].x - M[u][d].y, P[u][d].y + M[u][d].x);
+        o[(kT - d) * zstride] = make_double2(P[u][d].x + M[u][d].y, P[u][d].y - M[u][d].x);
       }
     }
   }
@@ -380,7 +399,7 @@ pisco_status_t toeplitz_product(Handle* h, const ToeplitzOp& op, const double2* 
     // z pass, per-frequency products and inverse z pass fused: buf0 -> buf1
     const int ctiles = ceil_div(b, 16);
     const dim3 grid(unsigned(F * F * ctiles));
-    const dim3 blk(256);
+    const dim3 blk(512);
     switch (W) {
 #define TP_ZF(w)                                                                                 \
   case w:                                                                                        \
