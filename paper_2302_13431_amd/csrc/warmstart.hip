@@ -13,10 +13,15 @@
 // 1 - |c_hat^H c|^2 / ||c_hat||^2 against the method's own eigenvectors c,
 // with Adam on FP32 master weights.
 //
-// Arithmetic: weights and activations FP16, products on the matrix cores
-// (v_mfma_f32_16x16x16f16) with FP32 accumulation; per-voxel gradients FP16
-// (they are O(1): the batch mean is applied to the FP32 weight gradients);
-// loss, weight gradients and optimizer state FP32.
+// Arithmetic: weights FP16, products on the matrix cores
+// (v_mfma_f32_16x16x32_f16) with FP32 accumulation.  Inference carries the
+// activations in FP16.  Training carries features, activations and
+// per-voxel gradients as FP16 pairs hi + lo (FP32 values; products hi hi +
+// hi lo + lo hi), because with one FP16 part the rounding of an activation
+// moves pre-activations near zero across the ReLU and the flipped masks
+// dominate the gradient error (about 1e-2 in the 2-norm); the weight
+// gradients are summed over the voxels by split K in FP32, then the loss,
+// gradients and optimizer state are FP32.
 //
 // Parameter vector (FP32 master and FP16 copy, same layout):
 //   [W1 (H x Din, row-major), b1 (H), W2 (H x H), b2 (H), W3 (Dout x H), b3]
@@ -32,7 +37,6 @@ namespace {
 
 constexpr int kHidden = 256;
 
-typedef _Float16 f16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 struct WsDims {
@@ -62,94 +66,199 @@ __device__ inline int pair_index(int p, int q, int Q) {  // p <= q
 
 // ------------------------------------------------------------------ features
 
-// X[v][j] (FP16, row-major N x Din) from packed G ([pair][N] float2) and the
-// neighbour vectors ([Q][N] float2).
-__global__ void k_ws_features(const float2* __restrict__ G, const float2* __restrict__ nb,
-                              int Q, long long N, float inv_bound, _Float16* __restrict__ X) {
-  const int din = Q * Q + 2 * Q;
-  const long long idx = blockIdx.x * 256LL + threadIdx.x;
-  if (idx >= N * din) return;
-  const long long v = idx / din;
-  const int j = int(idx - v * din);
-  float f;
-  if (j < Q) {
-    f = G[size_t(pair_index(j, j, Q)) * N + v].x * inv_bound;
-  } else if (j < Q * Q) {
-    // off-diagonal entry o in row-major order of p < q, then re / im
-    int o = (j - Q) >> 1, p = 0;
-    while (o >= Q - 1 - p) {
-      o -= Q - 1 - p;
-      ++p;
+// X[j][v] (feature-major Din x N, FP16; with Xlo the FP32 value as hi +
+// lo) from packed G ([pair][N] float2) and the neighbour vectors ([Q][N]
+// float2), one thread per voxel: every read and write is contiguous across
+// the voxels of a wave (the loops over the kMaxQ bound are unrolled and
+// guarded by Q).
+__global__ void __launch_bounds__(256) k_ws_features(const float2* __restrict__ G,
+                                                     const float2* __restrict__ nb, int Q,
+                                                     long long N, float inv_bound,
+                                                     _Float16* __restrict__ X,
+                                                     _Float16* __restrict__ Xlo) {
+  const long long v = blockIdx.x * 256LL + threadIdx.x;
+  if (v >= N) return;
+  auto put = [&](int j, float f) {
+    const _Float16 hi = static_cast<_Float16>(f);
+    X[size_t(j) * N + v] = hi;
+    if (Xlo) Xlo[size_t(j) * N + v] = static_cast<_Float16>(f - static_cast<float>(hi));
+  };
+  // diagonal (real), then the off-diagonal entries p < q in row-major order
+  // (re, im)
+  int k = 0, o = 0;
+#pragma unroll
+  for (int p = 0; p < kMaxQ; ++p) {
+#pragma unroll
+    for (int q = p; q < kMaxQ; ++q) {
+      if (p < Q && q < Q) {
+        const float2 g = G[size_t(k) * N + v];
+        ++k;
+        if (p == q) {
+          put(p, g.x * inv_bound);
+        } else {
+          put(Q + 2 * o, g.x * inv_bound);
+          put(Q + 2 * o + 1, g.y * inv_bound);
+          ++o;
+        }
+      }
     }
-    const float2 g = G[size_t(pair_index(p, p + 1 + o, Q)) * N + v];
-    f = ((j - Q) & 1 ? g.y : g.x) * inv_bound;
-  } else {
-    const int k = j - Q * Q;
-    const float2 n = nb[size_t(k >> 1) * N + v];
-    f = k & 1 ? n.y : n.x;
   }
-  X[idx] = static_cast<_Float16>(f);
+#pragma unroll
+  for (int q = 0; q < kMaxQ; ++q) {
+    if (q >= Q) continue;
+    const float2 n = nb[size_t(q) * N + v];
+    put(Q * Q + 2 * q, n.x);
+    put(Q * Q + 2 * q + 1, n.y);
+  }
 }
 
 // ------------------------------------------------------------------ GEMM
 
-// C (M x N) = op(A) (M x K) op(B) (K x N), FP16 operands, FP32 accumulation
-// on the matrix cores.  op(A)(m, k) = kTA ? A[k lda + m] : A[m lda + k];
-// op(B)(k, n) = kTB ? B[n ldb + k] : B[k ldb + n].  Workgroup tile 64 x 64,
-// four waves of 32 x 32 (2 x 2 blocks of 16 x 16), K in steps of 16.
-// Operand lanes: lane l holds row (column) l % 16 at k = 4 (l / 16) + j;
-// accumulator element v of lane l is row 4 (l / 16) + v, column l % 16.
+// C (M x N) = sum over operand parts of op(A_a) op(B_b), FP16 operands with
+// FP32 accumulation on the matrix cores (v_mfma_f32_16x16x32_f16).  An
+// operand is one FP16 matrix or a pair hi + lo of the same layout (an FP32
+// value carried as two FP16 parts); with pairs the products hi hi, hi lo
+// and lo hi are summed (lo lo, below 2^-22 relative, is dropped).
+// op(A)(m, k) = kTA ? A[k lda + m] : A[m lda + k];
+// op(B)(k, n) = kTB ? B[n ldb + k] : B[k ldb + n].
+// Workgroup tile 64 x 64, four waves of 32 x 32 (2 x 2 blocks of 16 x 16),
+// K in steps of 32 through LDS: each operand tile is staged as 64 rows of
+// 32 k (row stride 40 halves, so that the 16-byte operand reads of eight
+// lanes hit distinct banks), double-buffered, the next step's global loads
+// in flight during the current step's products.  A k-contiguous operand is
+// loaded eight halves per thread along k; an m-contiguous one eight along m
+// and transposed on its way into LDS.  Operand lanes: lane l supplies row l
+// % 16 at k = 8 (l / 16) + j (both operands the same, so any assignment of
+// k to the lanes gives the same sums); accumulator element v of lane l is
+// row 4 (l / 16) + v, column l % 16.  blockIdx.z takes K chunk z of kchunk
+// (split K: the partial products go to C + z M N, summed by k_ws_reduce).
 // Epilogues:
 enum : int {
-  kEpiBiasReluF16 = 0,  // C16 = fp16(max(acc + bias[n], 0)), bias FP16
-  kEpiBiasF32 = 1,      // C32 = acc + bias[n], bias FP16
-  kEpiMaskF16 = 2,      // C16 = fp16(acc) where mask16[m][n] > 0, else 0
-  kEpiF32 = 3,          // C32 = acc
+  kEpiBiasReluF16 = 0,    // C16 = fp16(max(acc + bias[n], 0))
+  kEpiBiasReluSplit = 1,  // (C16, C16lo) = hi / lo parts of max(acc + bias[n], 0)
+  kEpiBiasF32 = 2,        // C32 = acc + bias[n]
+  kEpiMaskSplit = 3,      // (C16, C16lo) = parts of acc where the mask pair is > 0, else 0
+  kEpiPartF32 = 4,        // C32 + z M N = acc (ldc = N)
 };
 
-template <bool kTA, bool kTB, int kEpi>
-__global__ void __launch_bounds__(256) k_hgemm(const _Float16* __restrict__ A, int lda,
-                                               const _Float16* __restrict__ B, int ldb, int M,
-                                               int N, int K, const _Float16* __restrict__ bias,
-                                               const _Float16* __restrict__ mask, int ldm,
-                                               void* __restrict__ C, int ldc) {
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+
+constexpr int kGT = 64;        // tile rows (M) and columns (N)
+constexpr int kGK = 32;        // K step
+constexpr int kGS = kGK + 8;   // LDS row stride, halves
+
+struct HOperand {
+  const _Float16* part[2];  // hi, lo (lo null for a single FP16 operand)
+  int ld;
+  bool vec;  // ld and both parts allow 16-byte loads
+};
+
+struct HOut {
+  void* c;             // FP16 (hi) or FP32 output
+  _Float16* clo;       // lo part for split epilogues
+  int ldc;
+  const _Float16* bias;
+  const _Float16* mask[2];  // mask pair (hi, lo): on where hi > 0 or lo > 0
+  int ldm;
+};
+
+// eight halves of op(X) for this thread's share of the tile (rows r0.., k0..)
+template <bool kKc>
+__device__ inline f16x8 tile_load(const _Float16* base, int ld, bool vec, int R, int K, int r0,
+                                  int k0) {
+  const int t = threadIdx.x;
+  f16x8 v;
+  if (kKc) {  // element (r, k) at base[r ld + k]
+    const int r = r0 + (t >> 2), k = k0 + (t & 3) * 8;
+    if (vec && r < R && k + 8 <= K) return *reinterpret_cast<const f16x8*>(base + size_t(r) * ld + k);
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+      v[i] = r < R && k + i < K ? base[size_t(r) * ld + k + i] : static_cast<_Float16>(0.f);
+  } else {  // element (r, k) at base[k ld + r]
+    const int k = k0 + (t >> 3), r = r0 + (t & 7) * 8;
+    if (vec && k < K && r + 8 <= R) return *reinterpret_cast<const f16x8*>(base + size_t(k) * ld + r);
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+      v[i] = k < K && r + i < R ? base[size_t(k) * ld + r + i] : static_cast<_Float16>(0.f);
+  }
+  return v;
+}
+
+template <bool kKc>
+__device__ inline void tile_store(_Float16* lds, const f16x8& v) {
+  const int t = threadIdx.x;
+  if (kKc) {
+    *reinterpret_cast<f16x8*>(lds + (t >> 2) * kGS + (t & 3) * 8) = v;
+  } else {
+    const int k = t >> 3, r = (t & 7) * 8;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) lds[(r + i) * kGS + k] = v[i];
+  }
+}
+
+template <bool kTA, bool kTB, int kPA, int kPB, int kEpi>
+__global__ void __launch_bounds__(256) k_hgemm(HOperand A, HOperand B, int M, int N, int K,
+                                               int kchunk, HOut o) {
+  __shared__ _Float16 As[2][kPA][kGT * kGS];
+  __shared__ _Float16 Bs[2][kPB][kGT * kGS];
   const int t = threadIdx.x, wv = t >> 6, l = t & 63;
   const int li = l & 15, kg = l >> 4;
-  const int m0 = blockIdx.x * 64 + (wv & 1) * 32, n0 = blockIdx.y * 64 + (wv >> 1) * 32;
+  const int m0 = blockIdx.x * kGT, n0 = blockIdx.y * kGT;
+  const int wm = (wv & 1) * 32, wn = (wv >> 1) * 32;
+  const int kb = blockIdx.z * kchunk, ke = K < kb + kchunk ? K : kb + kchunk;
   f32x4 acc[2][2];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-  for (int k0 = 0; k0 < K; k0 += 16) {
-    f16x4 a[2], b[2];
+  f16x8 ra[kPA], rb[kPB];
+  auto load = [&](int k0) {
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
-      const int m = m0 + 16 * i + li;
+    for (int p = 0; p < kPA; ++p) ra[p] = tile_load<!kTA>(A.part[p], A.ld, A.vec, M, ke, m0, k0);
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int k = k0 + 4 * kg + j;
-        _Float16 v = 0;
-        if (m < M && k < K) v = kTA ? A[size_t(k) * lda + m] : A[size_t(m) * lda + k];
-        a[i][j] = v;
-      }
-    }
+    for (int p = 0; p < kPB; ++p) rb[p] = tile_load<kTB>(B.part[p], B.ld, B.vec, N, ke, n0, k0);
+  };
+  auto store = [&](int buf) {
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
-      const int n = n0 + 16 * i + li;
+    for (int p = 0; p < kPA; ++p) tile_store<!kTA>(As[buf][p], ra[p]);
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int k = k0 + 4 * kg + j;
-        _Float16 v = 0;
-        if (n < N && k < K) v = kTB ? B[size_t(n) * ldb + k] : B[size_t(k) * ldb + n];
-        b[i][j] = v;
-      }
-    }
+    for (int p = 0; p < kPB; ++p) tile_store<kTB>(Bs[buf][p], rb[p]);
+  };
+  int buf = 0;
+  if (kb < ke) {
+    load(kb);
+    store(0);
+  }
+  __syncthreads();
+  for (int k0 = kb; k0 < ke; k0 += kGK) {
+    const bool next = k0 + kGK < ke;
+    if (next) load(k0 + kGK);
+    f16x8 a[kPA][2], b[kPB][2];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int p = 0; p < kPA; ++p)
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+        a[p][i] = *reinterpret_cast<const f16x8*>(&As[buf][p][(wm + 16 * i + li) * kGS + 8 * kg]);
+#pragma unroll
+    for (int p = 0; p < kPB; ++p)
 #pragma unroll
       for (int j = 0; j < 2; ++j)
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16f16(a[i], b[j], acc[i][j], 0, 0, 0);
+        b[p][j] = *reinterpret_cast<const f16x8*>(&Bs[buf][p][(wn + 16 * j + li) * kGS + 8 * kg]);
+#pragma unroll
+    for (int pa = 0; pa < kPA; ++pa)
+#pragma unroll
+      for (int pb = 0; pb < kPB; ++pb) {
+        if (pa + pb > 1) continue;  // lo lo dropped
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a[pa][i], b[pb][j], acc[i][j], 0,
+                                                               0, 0);
+      }
+    if (next) store(buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
   }
 #pragma unroll
   for (int i = 0; i < 2; ++i)
@@ -157,42 +266,112 @@ __global__ void __launch_bounds__(256) k_hgemm(const _Float16* __restrict__ A, i
     for (int j = 0; j < 2; ++j)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int m = m0 + 16 * i + 4 * kg + v, n = n0 + 16 * j + li;
+        const int m = m0 + wm + 16 * i + 4 * kg + v, n = n0 + wn + 16 * j + li;
         if (m >= M || n >= N) continue;
-        const float x = acc[i][j][v];
-        if (kEpi == kEpiBiasReluF16) {
-          static_cast<_Float16*>(C)[size_t(m) * ldc + n] =
-              static_cast<_Float16>(fmaxf(x + static_cast<float>(bias[n]), 0.f));
-        } else if (kEpi == kEpiBiasF32) {
-          static_cast<float*>(C)[size_t(m) * ldc + n] = x + static_cast<float>(bias[n]);
-        } else if (kEpi == kEpiMaskF16) {
-          const bool on = static_cast<float>(mask[size_t(m) * ldm + n]) > 0.f;
-          static_cast<_Float16*>(C)[size_t(m) * ldc + n] = static_cast<_Float16>(on ? x : 0.f);
-        } else {
-          static_cast<float*>(C)[size_t(m) * ldc + n] = x;
+        float x = acc[i][j][v];
+        if (kEpi == kEpiPartF32) {
+          static_cast<float*>(o.c)[(size_t(blockIdx.z) * M + m) * N + n] = x;
+          continue;
         }
+        if (kEpi == kEpiBiasF32) {
+          static_cast<float*>(o.c)[size_t(m) * o.ldc + n] = x + static_cast<float>(o.bias[n]);
+          continue;
+        }
+        if (kEpi == kEpiBiasReluF16 || kEpi == kEpiBiasReluSplit)
+          x = fmaxf(x + static_cast<float>(o.bias[n]), 0.f);
+        if (kEpi == kEpiMaskSplit) {
+          const size_t mi = size_t(m) * o.ldm + n;
+          const bool on = static_cast<float>(o.mask[0][mi]) > 0.f ||
+                          static_cast<float>(o.mask[1][mi]) > 0.f;
+          x = on ? x : 0.f;
+        }
+        const _Float16 hi = static_cast<_Float16>(x);
+        static_cast<_Float16*>(o.c)[size_t(m) * o.ldc + n] = hi;
+        if (kEpi != kEpiBiasReluF16)
+          o.clo[size_t(m) * o.ldc + n] = static_cast<_Float16>(x - static_cast<float>(hi));
       }
 }
 
-template <bool kTA, bool kTB, int kEpi>
-pisco_status_t hgemm(Handle* h, const _Float16* A, int lda, const _Float16* B, int ldb, int M,
-                     int N, int K, const _Float16* bias, const _Float16* mask, int ldm, void* C,
-                     int ldc) {
+// out[i] (+)= sum_z part[z][i], i < n (fixed order)
+__global__ void k_ws_reduce(const float* __restrict__ part, int nsplit, long long n,
+                            float* __restrict__ out) {
+  const long long i = blockIdx.x * 256LL + threadIdx.x;
+  if (i >= n) return;
+  float s = 0.f;
+  for (int z = 0; z < nsplit; ++z) s += part[size_t(z) * n + i];
+  out[i] = s;
+}
+
+HOperand hop(const _Float16* hi, const _Float16* lo, int ld) {
+  HOperand a;
+  a.part[0] = hi;
+  a.part[1] = lo;
+  a.ld = ld;
+  auto al = [](const void* p) { return !p || (reinterpret_cast<uintptr_t>(p) & 15) == 0; };
+  a.vec = ld % 8 == 0 && al(hi) && al(lo);
+  return a;
+}
+
+// Largest partial buffer of the split-K weight gradients, floats.
+constexpr long long kPartFloats = 1LL << 22;
+
+template <bool kTA, bool kTB, int kPA, int kPB, int kEpi>
+pisco_status_t hgemm(Handle* h, const HOperand& A, const HOperand& B, int M, int N, int K,
+                     const HOut& o, float* part = nullptr) {
   if (M <= 0 || N <= 0) return PISCO_OK;
-  dim3 g(ceil_div(M, 64), ceil_div(N, 64));
-  PISCO_KERNEL(h, (k_hgemm<kTA, kTB, kEpi>), g, dim3(256), 0, A, lda, B, ldb, M, N, K, bias,
-               mask, ldm, C, ldc);
+  const int mt = ceil_div(M, kGT), nt = ceil_div(N, kGT);
+  int nsplit = 1, kchunk = K;
+  if (kEpi == kEpiPartF32) {
+    // enough workgroups to fill the chip, chunks of whole K steps, the
+    // partials within the buffer
+    long long want = ceil_div(2048, mt * nt);
+    const long long cap = kPartFloats / (1LL * M * N);
+    if (want > cap) want = cap;
+    if (want < 1) want = 1;
+    kchunk = int(ceil_div(ceil_div(K, int(want)), kGK) * kGK);
+    if (kchunk < kGK) kchunk = kGK;
+    nsplit = ceil_div(K, kchunk);
+    if (nsplit < 1) nsplit = 1;
+  }
+  HOut oo = o;
+  if (kEpi == kEpiPartF32) oo.c = part;
+  PISCO_KERNEL(h, (k_hgemm<kTA, kTB, kPA, kPB, kEpi>), dim3(mt, nt, nsplit), dim3(256), 0, A, B,
+               M, N, K, kchunk, oo);
+  if (kEpi == kEpiPartF32) {
+    const long long n = 1LL * M * N;
+    PISCO_KERNEL(h, k_ws_reduce, dim3(ceil_div(n, 256)), dim3(256), 0, part, nsplit, n,
+                 static_cast<float*>(o.c));
+  }
   return PISCO_OK;
+}
+
+HOut out16(_Float16* c, _Float16* clo, int ldc, const _Float16* bias = nullptr) {
+  HOut o{};
+  o.c = c;
+  o.clo = clo;
+  o.ldc = ldc;
+  o.bias = bias;
+  return o;
+}
+
+HOut out32(float* c, int ldc, const _Float16* bias = nullptr) {
+  HOut o{};
+  o.c = c;
+  o.ldc = ldc;
+  o.bias = bias;
+  return o;
 }
 
 // ------------------------------------------------------------------ loss, sums, optimizer
 
 // Per voxel: c_hat = n + y, loss 1 - |c_hat^H c|^2 / ||c_hat||^2 and its
 // gradient g = -(2 / ||c_hat||^2) (conj(s) c - (|s|^2 / ||c_hat||^2) c_hat),
-// s = c_hat^H c, stored as dY (FP16, N x 2Q, re / im interleaved).
+// s = c_hat^H c, stored as dY (N x 2Q, re / im interleaved) in two FP16
+// parts hi + lo.
 __global__ void k_ws_loss(const float* __restrict__ Y, const float2* __restrict__ nb,
                           const float2* __restrict__ target, int Q, long long N,
-                          float* __restrict__ loss, _Float16* __restrict__ dY) {
+                          float* __restrict__ loss, _Float16* __restrict__ dY,
+                          _Float16* __restrict__ dYlo) {
   const long long v = blockIdx.x * 256LL + threadIdx.x;
   if (v >= N) return;
   // loops over the kMaxQ bound (unrolled, guarded by q < Q) keep ch in
@@ -221,8 +400,11 @@ __global__ void k_ws_loss(const float* __restrict__ Y, const float2* __restrict_
     const float ur = sr * c.x + si * c.y, ui = sr * c.y - si * c.x;
     const float gr = -2.f * inv * (ur - s2 * inv * ch[q].x);
     const float gi = -2.f * inv * (ui - s2 * inv * ch[q].y);
-    dY[size_t(v) * 2 * Q + 2 * q] = static_cast<_Float16>(gr);
-    dY[size_t(v) * 2 * Q + 2 * q + 1] = static_cast<_Float16>(gi);
+    const _Float16 hr = static_cast<_Float16>(gr), hi = static_cast<_Float16>(gi);
+    dY[size_t(v) * 2 * Q + 2 * q] = hr;
+    dY[size_t(v) * 2 * Q + 2 * q + 1] = hi;
+    dYlo[size_t(v) * 2 * Q + 2 * q] = static_cast<_Float16>(gr - static_cast<float>(hr));
+    dYlo[size_t(v) * 2 * Q + 2 * q + 1] = static_cast<_Float16>(gi - static_cast<float>(hi));
   }
 }
 
@@ -241,19 +423,24 @@ __global__ void __launch_bounds__(1024) k_ws_sum(const float* __restrict__ x, lo
   if (threadIdx.x == 0) out[0] = red[0] * scale;
 }
 
-// out[c] = sum_r D[r][c] for an M x N FP16 matrix (bias gradients); block of
-// 256 threads: 64 columns x 4 row groups
-__global__ void __launch_bounds__(256) k_ws_colsum(const _Float16* __restrict__ D, int M,
-                                                   int N, float* __restrict__ out) {
+// part[z][c] = sum over rows r of chunk z of (D[r][c] + Dlo[r][c]), an M x N
+// matrix in two FP16 parts (bias gradients); block of 256 threads: 64
+// columns x 4 row groups, blockIdx.y = chunk of `rows` rows
+__global__ void __launch_bounds__(256) k_ws_colsum(const _Float16* __restrict__ D,
+                                                   const _Float16* __restrict__ Dlo, int M,
+                                                   int N, int rows, float* __restrict__ part) {
   __shared__ float red[4][64];
   const int c = blockIdx.x * 64 + (threadIdx.x & 63), g = threadIdx.x >> 6;
+  const int r0 = blockIdx.y * rows, r1 = M < r0 + rows ? M : r0 + rows;
   float s = 0.f;
   if (c < N)
-    for (int r = g; r < M; r += 4) s += static_cast<float>(D[size_t(r) * N + c]);
+    for (int r = r0 + g; r < r1; r += 4)
+      s += static_cast<float>(D[size_t(r) * N + c]) + static_cast<float>(Dlo[size_t(r) * N + c]);
   red[g][threadIdx.x & 63] = s;
   __syncthreads();
   if (g == 0 && c < N)
-    out[c] = red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] + red[3][threadIdx.x];
+    part[size_t(blockIdx.y) * N + c] =
+        red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] + red[3][threadIdx.x];
 }
 
 // Adam on the mean gradient (grad holds the batch sum): bias-corrected
@@ -357,67 +544,125 @@ __global__ void k_ws_init(float* __restrict__ master, _Float16* __restrict__ w16
   w16[i] = static_cast<_Float16>(w);
 }
 
+// out[c] = column sums of the M x N pair D + Dlo, by row chunks (partials in
+// part, then k_ws_reduce, fixed order)
+pisco_status_t colsum(Handle* h, const _Float16* D, const _Float16* Dlo, int M, int N,
+                      float* part, float* out) {
+  int chunks = ceil_div(M, 512);
+  const int cap = int((1LL << 22) / N);
+  if (chunks > 256) chunks = 256;
+  if (chunks > cap) chunks = cap;
+  if (chunks < 1) chunks = 1;
+  const int rows = ceil_div(M, chunks);
+  chunks = ceil_div(M, rows);
+  if (chunks < 1) chunks = 1;
+  PISCO_KERNEL(h, k_ws_colsum, dim3(ceil_div(N, 64), chunks), dim3(256), 0, D, Dlo, M, N, rows,
+               part);
+  PISCO_KERNEL(h, k_ws_reduce, dim3(ceil_div(N, 256)), dim3(256), 0, part, chunks, (long long)N,
+               out);
+  return PISCO_OK;
+}
+
+// Activations and per-voxel gradients in two FP16 parts each (hi, lo); the
+// forward pass of inference uses the hi parts alone.
 struct WsBuffers {
-  _Float16 *X, *H1, *H2, *dY, *dH2, *dH1;
-  float *Y, *loss, *grad;
+  _Float16 *X[2], *H1[2], *H2[2], *dY[2], *dH2[2], *dH1[2];
+  float *Y, *loss, *grad, *part;
 };
 
 size_t ws_layout(const WsDims& d, long long N, void* base, WsBuffers* o) {
   Carver c(base);
   WsBuffers w{};
-  w.X = c.take<_Float16>(size_t(N) * d.din);
-  w.H1 = c.take<_Float16>(size_t(N) * d.h);
-  w.H2 = c.take<_Float16>(size_t(N) * d.h);
+  for (int p = 0; p < 2; ++p) {
+    w.X[p] = c.take<_Float16>(size_t(N) * d.din);
+    w.H1[p] = c.take<_Float16>(size_t(N) * d.h);
+    w.H2[p] = c.take<_Float16>(size_t(N) * d.h);
+    w.dY[p] = c.take<_Float16>(size_t(N) * d.dout);
+    w.dH2[p] = c.take<_Float16>(size_t(N) * d.h);
+    w.dH1[p] = c.take<_Float16>(size_t(N) * d.h);
+  }
   w.Y = c.take<float>(size_t(N) * d.dout);
-  w.dY = c.take<_Float16>(size_t(N) * d.dout);
-  w.dH2 = c.take<_Float16>(size_t(N) * d.h);
-  w.dH1 = c.take<_Float16>(size_t(N) * d.h);
   w.loss = c.take<float>(size_t(N));
   w.grad = c.take<float>(size_t(d.count));
+  w.part = c.take<float>(size_t(kPartFloats));
   if (o) *o = w;
   return c.used + 256;
 }
 
+// Inference (split = false): FP16 activations.  Training (split = true):
+// features and activations as hi + lo, so that the pre-activations, and
+// with them the ReLU masks of the backward pass, carry FP32 accuracy
+// (weights are FP16 by definition and exact in one part).
 pisco_status_t ws_forward(Handle* h, const WsDims& d, long long N, float bound,
                           const float2* G, const float2* nb, const _Float16* w,
-                          const WsBuffers& b) {
+                          const WsBuffers& b, bool split) {
   const int n = int(N);
-  PISCO_KERNEL(h, k_ws_features, dim3(ceil_div(N * d.din, 256)), dim3(256), 0, G, nb, d.Q, N,
-               1.f / bound, b.X);
+  PISCO_KERNEL(h, k_ws_features, dim3(ceil_div(N, 256)), dim3(256), 0, G, nb, d.Q, N,
+               1.f / bound, b.X[0], split ? b.X[1] : nullptr);
   pisco_status_t st;
-  if ((st = hgemm<false, true, kEpiBiasReluF16>(h, b.X, d.din, w + d.off_w1, d.din, n, d.h,
-                                                d.din, w + d.off_b1, nullptr, 0, b.H1, d.h)))
+  const HOperand W1 = hop(w + d.off_w1, nullptr, d.din), W2 = hop(w + d.off_w2, nullptr, d.h),
+                 W3 = hop(w + d.off_w3, nullptr, d.h);
+  if (split) {
+    if ((st = hgemm<true, true, 2, 1, kEpiBiasReluSplit>(
+             h, hop(b.X[0], b.X[1], n), W1, n, d.h, d.din,
+             out16(b.H1[0], b.H1[1], d.h, w + d.off_b1))))
+      return st;
+    if ((st = hgemm<false, true, 2, 1, kEpiBiasReluSplit>(
+             h, hop(b.H1[0], b.H1[1], d.h), W2, n, d.h, d.h,
+             out16(b.H2[0], b.H2[1], d.h, w + d.off_b2))))
+      return st;
+    return hgemm<false, true, 2, 1, kEpiBiasF32>(h, hop(b.H2[0], b.H2[1], d.h), W3, n, d.dout,
+                                                 d.h, out32(b.Y, d.dout, w + d.off_b3));
+  }
+  if ((st = hgemm<true, true, 1, 1, kEpiBiasReluF16>(h, hop(b.X[0], nullptr, n), W1, n,
+                                                      d.h, d.din,
+                                                      out16(b.H1[0], nullptr, d.h, w + d.off_b1))))
     return st;
-  if ((st = hgemm<false, true, kEpiBiasReluF16>(h, b.H1, d.h, w + d.off_w2, d.h, n, d.h, d.h,
-                                                w + d.off_b2, nullptr, 0, b.H2, d.h)))
+  if ((st = hgemm<false, true, 1, 1, kEpiBiasReluF16>(h, hop(b.H1[0], nullptr, d.h), W2, n, d.h,
+                                                      d.h,
+                                                      out16(b.H2[0], nullptr, d.h, w + d.off_b2))))
     return st;
-  return hgemm<false, true, kEpiBiasF32>(h, b.H2, d.h, w + d.off_w3, d.h, n, d.dout, d.h,
-                                         w + d.off_b3, nullptr, 0, b.Y, d.dout);
+  return hgemm<false, true, 1, 1, kEpiBiasF32>(h, hop(b.H2[0], nullptr, d.h), W3, n, d.dout, d.h,
+                                               out32(b.Y, d.dout, w + d.off_b3));
 }
 
-// Gradient of the summed loss into b.grad (FP32, parameter layout).
+// Gradient of the summed loss into b.grad (FP32, parameter layout), from the
+// split forward pass and dY; weight gradients by split K over the voxels.
 pisco_status_t ws_backward(Handle* h, const WsDims& d, long long N, const _Float16* w,
                            const WsBuffers& b) {
   const int n = int(N);
   pisco_status_t st;
-  if ((st = hgemm<true, false, kEpiF32>(h, b.dY, d.dout, b.H2, d.h, d.dout, d.h, n, nullptr,
-                                        nullptr, 0, b.grad + d.off_w3, d.h)))
+  const HOperand dYk = hop(b.dY[0], b.dY[1], d.dout), H2 = hop(b.H2[0], b.H2[1], d.h),
+                 H1 = hop(b.H1[0], b.H1[1], d.h), X = hop(b.X[0], b.X[1], n),
+                 dH2 = hop(b.dH2[0], b.dH2[1], d.h), dH1 = hop(b.dH1[0], b.dH1[1], d.h);
+  // dW3 = dY^T H2, db3 = column sums of dY
+  if ((st = hgemm<true, false, 2, 2, kEpiPartF32>(h, dYk, H2, d.dout, d.h, n,
+                                                  out32(b.grad + d.off_w3, d.h), b.part)))
     return st;
-  PISCO_KERNEL(h, k_ws_colsum, dim3(ceil_div(d.dout, 64)), dim3(256), 0, b.dY, n, d.dout, b.grad + d.off_b3);
-  if ((st = hgemm<false, false, kEpiMaskF16>(h, b.dY, d.dout, w + d.off_w3, d.h, n, d.h, d.dout,
-                                             nullptr, b.H2, d.h, b.dH2, d.h)))
+  if ((st = colsum(h, b.dY[0], b.dY[1], n, d.dout, b.part, b.grad + d.off_b3))) return st;
+  // dH2 = (dY W3) masked by h2 > 0
+  HOut m2 = out16(b.dH2[0], b.dH2[1], d.h);
+  m2.mask[0] = b.H2[0];
+  m2.mask[1] = b.H2[1];
+  m2.ldm = d.h;
+  if ((st = hgemm<false, false, 2, 1, kEpiMaskSplit>(h, dYk, hop(w + d.off_w3, nullptr, d.h), n,
+                                                     d.h, d.dout, m2)))
     return st;
-  if ((st = hgemm<true, false, kEpiF32>(h, b.dH2, d.h, b.H1, d.h, d.h, d.h, n, nullptr, nullptr,
-                                        0, b.grad + d.off_w2, d.h)))
+  if ((st = hgemm<true, false, 2, 2, kEpiPartF32>(h, dH2, H1, d.h, d.h, n,
+                                                  out32(b.grad + d.off_w2, d.h), b.part)))
     return st;
-  PISCO_KERNEL(h, k_ws_colsum, dim3(ceil_div(d.h, 64)), dim3(256), 0, b.dH2, n, d.h, b.grad + d.off_b2);
-  if ((st = hgemm<false, false, kEpiMaskF16>(h, b.dH2, d.h, w + d.off_w2, d.h, n, d.h, d.h,
-                                             nullptr, b.H1, d.h, b.dH1, d.h)))
+  if ((st = colsum(h, b.dH2[0], b.dH2[1], n, d.h, b.part, b.grad + d.off_b2))) return st;
+  HOut m1 = out16(b.dH1[0], b.dH1[1], d.h);
+  m1.mask[0] = b.H1[0];
+  m1.mask[1] = b.H1[1];
+  m1.ldm = d.h;
+  if ((st = hgemm<false, false, 2, 1, kEpiMaskSplit>(h, dH2, hop(w + d.off_w2, nullptr, d.h), n,
+                                                     d.h, d.h, m1)))
     return st;
-  if ((st = hgemm<true, false, kEpiF32>(h, b.dH1, d.h, b.X, d.din, d.h, d.din, n, nullptr,
-                                        nullptr, 0, b.grad + d.off_w1, d.din)))
+  if ((st = hgemm<true, true, 2, 2, kEpiPartF32>(h, dH1, X, d.h, d.din, n,
+                                                  out32(b.grad + d.off_w1, d.din), b.part)))
     return st;
-  PISCO_KERNEL(h, k_ws_colsum, dim3(ceil_div(d.h, 64)), dim3(256), 0, b.dH1, n, d.h, b.grad + d.off_b1);
+  if ((st = colsum(h, b.dH1[0], b.dH1[1], n, d.h, b.part, b.grad + d.off_b1))) return st;
   return PISCO_OK;
 }
 
@@ -507,7 +752,8 @@ pisco_status_t pisco_ws_forward(pisco_handle_t handle, int32_t Q, int64_t N, flo
   ws_layout(d, N, ws, &b);
   const _Float16* w = static_cast<const _Float16*>(weights16);
   const float2* nb = static_cast<const float2*>(neighbor);
-  if ((st = ws_forward(h, d, N, bound, static_cast<const float2*>(G), nb, w, b))) return st;
+  if ((st = ws_forward(h, d, N, bound, static_cast<const float2*>(G), nb, w, b, false)))
+    return st;
   PISCO_KERNEL(h, k_ws_apply, dim3(ceil_div(N, 256)), dim3(256), 0, b.Y, nb, Q, N,
                static_cast<float2*>(init));
   return PISCO_OK;
@@ -535,9 +781,10 @@ pisco_status_t pisco_ws_train_step(pisco_handle_t handle, int32_t Q, int64_t N, 
   ws_layout(d, N, ws, &b);
   _Float16* w = static_cast<_Float16*>(weights16);
   const float2* nb = static_cast<const float2*>(neighbor);
-  if ((st = ws_forward(h, d, N, bound, static_cast<const float2*>(G), nb, w, b))) return st;
+  if ((st = ws_forward(h, d, N, bound, static_cast<const float2*>(G), nb, w, b, true)))
+    return st;
   PISCO_KERNEL(h, k_ws_loss, dim3(ceil_div(N, 256)), dim3(256), 0, b.Y, nb,
-               static_cast<const float2*>(target), Q, N, b.loss, b.dY);
+               static_cast<const float2*>(target), Q, N, b.loss, b.dY[0], b.dY[1]);
   if (loss_out)
     PISCO_KERNEL(h, k_ws_sum, dim3(1), dim3(1024), 0, b.loss, N, float(1.0 / double(N)), loss_out);
   if ((st = ws_backward(h, d, N, w, b))) return st;
