@@ -95,14 +95,16 @@ __global__ void __launch_bounds__(256) k_herk(const float2* __restrict__ F,
 // x_hi) and a product is x_hi y_hi + x_hi y_lo + x_lo y_hi (three MFMAs; the
 // dropped x_lo y_lo is below 2^-22 relative).  kPrec = PISCO_PREC_SPLIT_BF16:
 // three BF16 parts hi, mid, lo and the six cross products of total order
-// <= 2.  Workgroup: 4 frequencies, one per wave; r runs in chunks of 16
+// <= 2.  Workgroup: 4 frequencies, one per wave; r runs in chunks of 32
 // staged in LDS as [r][q][f] (f padded to 5 against bank conflicts).  For one frequency the Q x Q result is C = A^H A with A the
 // r x Q matrix F[.][.][f]: Re C = Ar^T Ar + Ai^T Ai, Im C = Ar^T Ai - Ai^T Ar,
-// as 16 x 16 x 16 blocks (upper blocks only).  Operand lanes: lane l holds
-// row (column) l % 16 at k = 4 (l / 16) + j, j < 4; accumulator element v of
-// lane l is row 4 (l / 16) + v, column l % 16.
-typedef _Float16 f16x4 __attribute__((ext_vector_type(4)));
-typedef short bf16x4 __attribute__((ext_vector_type(4)));
+// as 16 x 16 x 32 blocks on gfx950's double-K shapes (upper blocks only).
+// Operand lanes: lane l holds row (column) l % 16 at k = 8 (l / 16) + j,
+// j < 8 (the same for both operands); accumulator element v of lane l is
+// row 4 (l / 16) + v, column l % 16.
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef short bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 __device__ inline short bf16_rne(float f) {
@@ -120,10 +122,10 @@ struct SplitOps;
 template <>
 struct SplitOps<PISCO_PREC_SPLIT_F16> {
   static constexpr int kParts = 2;
-  typedef f16x4 vec;
-  __device__ static void split(const float (&x)[4], float s, vec (&out)[kParts]) {
+  typedef f16x8 vec;
+  __device__ static void split(const float (&x)[8], float s, vec (&out)[kParts]) {
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
+    for (int j = 0; j < 8; ++j) {
       const float v = x[j] * s;
       const _Float16 hi = static_cast<_Float16>(v);
       out[0][j] = hi;
@@ -132,7 +134,7 @@ struct SplitOps<PISCO_PREC_SPLIT_F16> {
   }
   __device__ static vec neg(vec a) { return -a; }
   __device__ static f32x4 mma(vec a, vec b, f32x4 c) {
-    return __builtin_amdgcn_mfma_f32_16x16x16f16(a, b, c, 0, 0, 0);
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
   }
   // (part of x, part of y) pairs kept: hi hi, hi lo, lo hi
   static constexpr int kTerms = 3;
@@ -143,10 +145,10 @@ struct SplitOps<PISCO_PREC_SPLIT_F16> {
 template <>
 struct SplitOps<PISCO_PREC_SPLIT_BF16> {
   static constexpr int kParts = 3;
-  typedef bf16x4 vec;
-  __device__ static void split(const float (&x)[4], float, vec (&out)[kParts]) {
+  typedef bf16x8 vec;
+  __device__ static void split(const float (&x)[8], float, vec (&out)[kParts]) {
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
+    for (int j = 0; j < 8; ++j) {
       float v = x[j];
       const short hi = bf16_rne(v);
       v -= bf16_to_f32(hi);
@@ -157,9 +159,10 @@ struct SplitOps<PISCO_PREC_SPLIT_BF16> {
       out[2][j] = bf16_rne(v);
     }
   }
-  __device__ static vec neg(vec a) { return a ^ bf16x4{short(0x8000), short(0x8000), short(0x8000), short(0x8000)}; }
+  __device__ static vec neg(vec a) { return a ^ short(0x8000); }
   __device__ static f32x4 mma(vec a, vec b, f32x4 c) {
-    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8_t, a),
+                                                   __builtin_bit_cast(bf16x8_t, b), c, 0, 0, 0);
   }
   // hi hi, hi mid, mid hi, hi lo, lo hi, mid mid
   static constexpr int kTerms = 6;
@@ -175,7 +178,8 @@ __global__ void __launch_bounds__(256) k_herk_mfma(const float2* __restrict__ F,
   using Ops = SplitOps<kPrec>;
   using vec = typename Ops::vec;
   constexpr int kFB = 4, kFP = 5, kFW = 1;  // frequencies per block / padded / per wave
-  __shared__ float2 tile[16 * kMaxQ * kFP];
+  constexpr int kR = 32;  // r per chunk (the MFMA's K)
+  __shared__ float2 tile[kR * kMaxQ * kFP];
   const int t = threadIdx.x, wv = t >> 6, l = t & 63;
   const int li = l & 15, kg = l >> 4;
   const int f0 = blockIdx.x * kFB;
@@ -189,8 +193,8 @@ __global__ void __launch_bounds__(256) k_herk_mfma(const float2* __restrict__ F,
       cr[fi][bk] = f32x4{0.f, 0.f, 0.f, 0.f};
       ci[fi][bk] = f32x4{0.f, 0.f, 0.f, 0.f};
     }
-  for (int r0 = 0; r0 < rs; r0 += 16) {
-    for (int e = t; e < 16 * Q * kFB; e += 256) {
+  for (int r0 = 0; r0 < rs; r0 += kR) {
+    for (int e = t; e < kR * Q * kFB; e += 256) {
       const int ff = e % kFB, rq = e / kFB, rr = rq / Q;
       const int f = f0 + ff;
       tile[rq * kFP + ff] = (r0 + rr < rs && f < nK) ? F[size_t(r0 * Q + rq) * nK + f]
@@ -204,11 +208,11 @@ __global__ void __launch_bounds__(256) k_herk_mfma(const float2* __restrict__ F,
       vec re[2][Ops::kParts], im[2][Ops::kParts];
 #pragma unroll
       for (int cb = 0; cb < 2; ++cb) {
-        float xr[4], xi[4];
+        float xr[8], xi[8];
         const int q = 16 * cb + li;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const float2 v = q < Q ? tile[((4 * kg + j) * Q + q) * kFP + ff] : make_float2(0.f, 0.f);
+        for (int j = 0; j < 8; ++j) {
+          const float2 v = q < Q ? tile[((8 * kg + j) * Q + q) * kFP + ff] : make_float2(0.f, 0.f);
           xr[j] = v.x;
           xi[j] = v.y;
         }
