@@ -12,6 +12,8 @@
 
 namespace pisco {
 
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
 // Element helpers: loads widen to the accumulation type T of the output.
 template <class T> struct Acc;
 template <> struct Acc<float2> {
@@ -157,6 +159,139 @@ __global__ void __launch_bounds__(256) k_axis_last(const TI* __restrict__ in,
   out[size_t(l0 + ln) * nout + o] = TO{ar, ai};
 }
 
+// FP32 transforms on the matrix cores (v_mfma_f32_16x16x4f32, twice the
+// FP32 vector rate without packed operations), for the passes with many
+// outputs per input (the interpolation to the output grid, G(x) on the
+// low-resolution grid).  A workgroup forms a 64 x 64 tile of the product
+// C = M X over K = nin (rounded up to 4, zeros past nin) staged in LDS, four
+// waves of 16 x 64; complex products in the three-multiplication form (T1
+// = Ar Br, T2 = Ai Bi, T3 = (Ar + Ai)(Br + Bi); Re = T1 - T2, Im = T3 - T1 -
+// T2).  Operand lanes of the 16 x 16 x 4 shape: lane l supplies A row l % 16
+// and B column l % 16 at k = l / 16; accumulator element v of lane l is row
+// 4 (l / 16) + v, column l % 16.
+//   k_axis_mm_cols (inner >= 64): X[k][col] = in[outer][k][inner0 + col],
+//     A = M (64 outputs), B = X; the tile's outputs are written along inner.
+//   k_axis_mm_lines (inner = 1): A = the lines' inputs (64 lines), B = M^T;
+//     each line's 64 outputs are written along the line.
+constexpr int kMmK = 64;  // nin at most (K padded to a multiple of 4)
+
+__device__ inline void mm_tile(const float2* As, int lda, const float2* Bs, int ldb, bool bt,
+                               int K4, f32x4 (&t1)[4], f32x4 (&t2)[4], f32x4 (&t3)[4]) {
+  // As[r][k] (row stride lda); Bs[k][c] (bt == false, stride ldb) or Bs[c][k]
+  const int l = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int li = l & 15, kq = l >> 4;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) t1[j] = t2[j] = t3[j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int k0 = 0; k0 < K4; k0 += 4) {
+    const int k = k0 + kq;
+    const float2 a = As[(16 * wv + li) * lda + k];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const float2 b = bt ? Bs[(16 * j + li) * ldb + k] : Bs[k * ldb + 16 * j + li];
+      t1[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b.x, t1[j], 0, 0, 0);
+      t2[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, b.y, t2[j], 0, 0, 0);
+      t3[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x + a.y, b.x + b.y, t3[j], 0, 0, 0);
+    }
+  }
+}
+
+// Ms[o][k] = M[o0 + o][k] (zeros past nout and nin), row stride kMmK + 1
+__device__ inline void mm_stage_m(float2* Ms, const float2* __restrict__ M, int o0, int nout,
+                                  int nin, int K4) {
+  for (int e = threadIdx.x; e < 64 * K4; e += 256) {
+    const int o = e / K4, k = e - o * K4;
+    Ms[o * (kMmK + 1) + k] =
+        o0 + o < nout && k < nin ? M[size_t(o0 + o) * nin + k] : make_float2(0.f, 0.f);
+  }
+}
+
+// kMmTiles column tiles per workgroup, one after another: M staged once, the
+// next tile's inputs loaded into registers while the current one is
+// multiplied
+constexpr int kMmTiles = 8;
+
+__global__ void __launch_bounds__(256) k_axis_mm_cols(const float2* __restrict__ in,
+                                                      float2* __restrict__ out,
+                                                      const float2* __restrict__ M, int nin,
+                                                      int nout, int inner) {
+  constexpr int XS = 64 + 1;  // Xs row stride
+  constexpr int kPer = kMmK * 64 / 256;  // staged elements per thread
+  __shared__ float2 Ms[64 * (kMmK + 1)];
+  __shared__ float2 Xs[kMmK * XS];
+  const int K4 = (nin + 3) & ~3;
+  const int o0 = blockIdx.y * 64;
+  const long long ou = blockIdx.z;
+  const int tiles = (inner + 63) / 64;
+  const int tb = blockIdx.x * kMmTiles, te = tiles < tb + kMmTiles ? tiles : tb + kMmTiles;
+  mm_stage_m(Ms, M, o0, nout, nin, K4);
+  const float2* src = in + size_t(ou) * nin * inner;
+  float2 x[kPer];
+  auto load = [&](int tile) {
+    const int c0 = tile * 64;
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      const int e = threadIdx.x + 256 * u, k = e >> 6, c = e & 63;
+      x[u] = k < nin && c0 + c < inner ? src[size_t(k) * inner + c0 + c] : make_float2(0.f, 0.f);
+    }
+  };
+  const int l = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  float2* dst = out + size_t(ou) * nout * inner;
+  if (tb < te) load(tb);
+  for (int tile = tb; tile < te; ++tile) {
+    __syncthreads();  // the previous tile's products are done with Xs
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+      const int e = threadIdx.x + 256 * u, k = e >> 6, c = e & 63;
+      if (k < K4) Xs[k * XS + c] = x[u];
+    }
+    __syncthreads();
+    if (tile + 1 < te) load(tile + 1);
+    f32x4 t1[4], t2[4], t3[4];
+    mm_tile(Ms, kMmK + 1, Xs, XS, false, K4, t1, t2, t3);
+    const int c0 = tile * 64;
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int o = o0 + 16 * wv + 4 * (l >> 4) + v, c = c0 + 16 * j + (l & 15);
+        if (o < nout && c < inner)
+          dst[size_t(o) * inner + c] =
+              make_float2(t1[j][v] - t2[j][v], t3[j][v] - t1[j][v] - t2[j][v]);
+      }
+  }
+}
+
+__global__ void __launch_bounds__(256) k_axis_mm_lines(const float2* __restrict__ in,
+                                                       float2* __restrict__ out,
+                                                       const float2* __restrict__ M,
+                                                       long long lines, int nin, int nout) {
+  __shared__ float2 Ms[64 * (kMmK + 1)];
+  __shared__ float2 Xs[64 * (kMmK + 1)];
+  const int K4 = (nin + 3) & ~3;
+  const long long l0 = 1LL * blockIdx.x * 64;
+  const int o0 = blockIdx.y * 64;
+  mm_stage_m(Ms, M, o0, nout, nin, K4);
+  for (int e = threadIdx.x; e < 64 * K4; e += 256) {
+    const int r = e / K4, k = e - r * K4;
+    Xs[r * (kMmK + 1) + k] = k < nin && l0 + r < lines ? in[size_t(l0 + r) * nin + k]
+                                                       : make_float2(0.f, 0.f);
+  }
+  __syncthreads();
+  f32x4 t1[4], t2[4], t3[4];
+  mm_tile(Xs, kMmK + 1, Ms, kMmK + 1, true, K4, t1, t2, t3);
+  const int l = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int j = 0; j < 4; ++j)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const long long r = l0 + 16 * wv + 4 * (l >> 4) + v;
+      const int o = o0 + 16 * j + (l & 15);
+      if (r < lines && o < nout)
+        out[size_t(r) * nout + o] =
+            make_float2(t1[j][v] - t2[j][v], t3[j][v] - t1[j][v] - t2[j][v]);
+    }
+}
+
 template <class TI, class TO>
 static pisco_status_t axis_impl(Handle* h, const TI* in, TO* out, const int shape_in[4],
                                 int axis, int nout, const TO* M) {
@@ -165,6 +300,24 @@ static pisco_status_t axis_impl(Handle* h, const TI* in, TO* out, const int shap
   long long inner = 1;
   for (int d = axis + 1; d < 4; ++d) inner *= shape_in[d];
   const int nin = shape_in[axis];
+  if (sizeof(TI) == sizeof(float2) && sizeof(TO) == sizeof(float2) && nin <= kMmK &&
+      outer * inner * nout >= (1LL << 24) &&
+      (inner == 1 || (inner >= 64 && outer <= 65535))) {
+    // large FP32 passes on the matrix cores
+    const float2* fi = reinterpret_cast<const float2*>(in);
+    float2* fo = reinterpret_cast<float2*>(out);
+    const float2* fm = reinterpret_cast<const float2*>(M);
+    if (inner == 1) {
+      PISCO_KERNEL(h, k_axis_mm_lines, dim3(unsigned(ceil_div(outer, 64)), ceil_div(nout, 64)),
+                   dim3(256), 0, fi, fo, fm, outer, nin, nout);
+    } else {
+      PISCO_KERNEL(h, k_axis_mm_cols,
+                   dim3(unsigned(ceil_div(ceil_div(inner, 64), kMmTiles)), ceil_div(nout, 64),
+                        unsigned(outer)),
+                   dim3(256), 0, fi, fo, fm, nin, nout, int(inner));
+    }
+    return PISCO_OK;
+  }
   if (inner == 1) {
     int lpb = nout >= 256 ? 1 : 256 / nout;
     const int fit = int((64 * 1024) / (size_t(nin) * sizeof(TO)));  // staged lines in 64 KB
