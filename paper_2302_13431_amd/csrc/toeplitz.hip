@@ -13,11 +13,11 @@
 // diagonal is taken real, which is the transform of the Hermitian part of
 // R_pp, so the operator is exactly Hermitian like the explicit Gram.
 //
-// One product (FP64): scatter the block onto the box, three pruned DFT
-// passes (box -> frequency, the separable one-axis transform), one
-// (b x Q)(Q x Q) product per frequency, three passes back (frequency ->
-// box), gather the support points with the Chebyshev-step epilogue of the
-// explicit product.  The spectra are laid out frequency-major with the b Q
+// One product (FP64): the block onto the box and through the x transform
+// (one kernel), the y (and z) transforms, one (b x Q)(Q x Q) product per
+// frequency (in 3D fused with the z transforms), the inverse y transform,
+// and the inverse x transform with the gather of the support points and the
+// Chebyshev-step epilogue of the explicit product (one kernel).  The spectra are laid out frequency-major with the b Q
 // block innermost ([f][c][q]), so that every pass reads and writes whole
 // contiguous runs and each frequency's block is one contiguous matrix.
 // Work per product: 8 F^D Q^2 b flops for the per-frequency products plus
@@ -315,6 +315,141 @@ __global__ void __launch_bounds__(512) k_tp_zfused(const double2* __restrict__ i
   }
 }
 
+// Support block -> x spectrum of the box in one pass (the scatter onto the
+// box and the x transform fused): thread (box row r = (z, y), e = c Q + q)
+// reads x(tau + d) = X[c][q L + boxmap[r][tau + d]] (zero off the support;
+// one contiguous run of the column per thread) and writes out[r][fx][e] for
+// all F frequencies through the pairs (k, F - k) of the centred box, as in
+// k_tp_zfused.  role 0: nothing to do (the gather copies X).
+template <int kW>
+__global__ void __launch_bounds__(256) k_tp_scatter_fx(const double2* __restrict__ X,
+                                                       const int* __restrict__ boxmap,
+                                                       const double2* __restrict__ Tf,
+                                                       double2* __restrict__ out, int n, int L,
+                                                       int Q, int b, int F, int rows,
+                                                       const int* __restrict__ role) {
+  constexpr int kT = kW / 2;
+  if (role && *role == 0) return;
+  const int bq = b * Q;
+  const long long idx = blockIdx.x * 256LL + threadIdx.x;
+  if (idx >= 1LL * rows * bq) return;
+  const int r = int(idx / bq), e = int(idx - 1LL * r * bq);
+  const int c = e / Q, q = e - c * Q;
+  const double2* src = X + size_t(c) * n + size_t(q) * L;
+  double2 x[kW];
+#pragma unroll
+  for (int i = 0; i < kW; ++i) {
+    const int s = boxmap[r * kW + i];
+    x[i] = s >= 0 ? src[s] : make_double2(0.0, 0.0);
+  }
+  double2 U[kT + 1], V[kT + 1];
+  U[0] = x[kT];
+  V[0] = make_double2(0.0, 0.0);
+#pragma unroll
+  for (int d = 1; d <= kT; ++d) {
+    U[d] = make_double2(x[kT + d].x + x[kT - d].x, x[kT + d].y + x[kT - d].y);
+    V[d] = make_double2(x[kT + d].x - x[kT - d].x, x[kT + d].y - x[kT - d].y);
+  }
+  double2* dst = out + size_t(r) * F * bq + e;
+#pragma unroll
+  for (int k = 0; k <= 2 * kT; ++k) {
+    const double2* tf = Tf + size_t(k) * kW + kT;
+    double2 C = make_double2(0.0, 0.0), S = C;
+#pragma unroll
+    for (int d = 0; d <= kT; ++d) {
+      const double2 m = tf[d];
+      C.x = fma(m.x, U[d].x, C.x);
+      C.y = fma(m.x, U[d].y, C.y);
+      if (d > 0) {
+        S.x = fma(m.y, V[d].x, S.x);
+        S.y = fma(m.y, V[d].y, S.y);
+      }
+    }
+    dst[size_t(k) * bq] = make_double2(C.x - S.y, C.y + S.x);
+    if (k > 0) dst[size_t(F - k) * bq] = make_double2(C.x + S.y, C.y - S.x);
+  }
+}
+
+// x spectrum of the box -> support block in one pass (the inverse x
+// transform and the gather fused): thread (r, e) reads in[r][f][e] for the
+// F frequencies, forms the row's box values through the frequency pairs,
+// and writes the support points of the row, out[c][q L + s] = S, or a S +
+// bc X + g prev with (a, bc, g) = coef[0..2] (coef[3..5] for role 2); role
+// 0 copies X.  Every support point lies in exactly one box row.
+template <int kW>
+__global__ void __launch_bounds__(256) k_tp_ix_gather(const double2* __restrict__ in,
+                                                      const int* __restrict__ boxmap,
+                                                      const double2* __restrict__ Ti,
+                                                      const double2* __restrict__ X,
+                                                      double2* out, const double2* prev, int n,
+                                                      int L, int Q, int b, int rows,
+                                                      const double* __restrict__ coef,
+                                                      const int* __restrict__ role) {
+  constexpr int kT = kW / 2, kF = 2 * kW - 1;
+  const int bq = b * Q;
+  const long long idx = blockIdx.x * 256LL + threadIdx.x;
+  if (idx >= 1LL * rows * bq) return;
+  const int r = int(idx / bq), e = int(idx - 1LL * r * bq);
+  const int c = e / Q, q = e - c * Q;
+  const size_t col = size_t(c) * n + size_t(q) * L;
+  int rl = 1;
+  if (role) {
+    rl = *role;
+    if (rl == 2) coef += 3;
+  }
+  if (rl == 0) {
+#pragma unroll
+    for (int i = 0; i < kW; ++i) {
+      const int s = boxmap[r * kW + i];
+      if (s >= 0) out[col + s] = X[col + s];
+    }
+    return;
+  }
+  double2 y[kF];
+  const double2* src = in + size_t(r) * kF * bq + e;
+#pragma unroll
+  for (int f = 0; f < kF; ++f) y[f] = src[size_t(f) * bq];
+  double2 P[kT + 1], M[kT + 1];
+#pragma unroll
+  for (int d = 0; d <= kT; ++d) P[d] = M[d] = make_double2(0.0, 0.0);
+#pragma unroll
+  for (int k = 0; k <= 2 * kT; ++k) {
+    const double2 ya = y[k], yc = k > 0 ? y[kF - k] : make_double2(0.0, 0.0);
+    const double2 Sv = make_double2(ya.x + yc.x, ya.y + yc.y);
+    const double2 Dv = make_double2(ya.x - yc.x, ya.y - yc.y);
+#pragma unroll
+    for (int d = 0; d <= kT; ++d) {
+      const double2 m = Ti[size_t(kT + d) * kF + k];
+      P[d].x = fma(m.x, Sv.x, P[d].x);
+      P[d].y = fma(m.x, Sv.y, P[d].y);
+      if (d > 0) {
+        M[d].x = fma(m.y, Dv.x, M[d].x);
+        M[d].y = fma(m.y, Dv.y, M[d].y);
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < kW; ++i) {
+    const int s = boxmap[r * kW + i];
+    if (s < 0) continue;
+    const int d = i - kT, ad = d < 0 ? -d : d;
+    const double sg = d < 0 ? -1.0 : 1.0;
+    const double2 v = d == 0 ? P[0]
+                             : make_double2(P[ad].x - sg * M[ad].y, P[ad].y + sg * M[ad].x);
+    double2 res = v;
+    if (coef) {
+      const double2 xv = X[col + s];
+      res = make_double2(coef[0] * v.x + coef[1] * xv.x, coef[0] * v.y + coef[1] * xv.y);
+      if (prev) {
+        const double2 pv = prev[col + s];
+        res.x += coef[2] * pv.x;
+        res.y += coef[2] * pv.y;
+      }
+    }
+    out[col + s] = res;
+  }
+}
+
 // out[c][p L + i] from box[cell(i)][c][p]: S, or a S + bc X + g prev with
 // (a, bc, g) = coef[0..2] (coef[3..5] for role 2); role 0 copies X
 __global__ void k_tp_gather(const double2* __restrict__ box, const int4* __restrict__ sup,
@@ -386,15 +521,33 @@ pisco_status_t toeplitz_product(Handle* h, const ToeplitzOp& op, const double2* 
                                 const double2* prev, const int* role) {
   const int Q = op.Q, W = op.W, Wz = op.Wz, F = op.F, Fz = op.Fz;
   const int bq = b * Q;
-  const int cells = Wz * W * W;
+  const int cells = Wz * W * W, rows = Wz * W;
+  const long long rq = 1LL * rows * bq;
+  // the box's x passes fused with the scatter and the gather for the box
+  // widths with a compiled kernel
+  const bool fused_x = (W & 1) && W >= 3 && W <= 13 && F == 2 * W - 1;
   pisco_status_t st;
-  PISCO_KERNEL(h, k_tp_scatter, dim3(ceil_div(1LL * cells * bq, 256)), dim3(256), 0, X,
-               op.boxmap, op.buf0, n, op.L, Q, b, cells, role);
-  // box -> frequency: x, y (, z)
-  const int fx[4] = {Wz * W, W, bq, 1};
-  if ((st = axis_transform64(h, op.buf0, op.buf1, fx, 1, F, op.Tf))) return st;
+  // box -> frequency: x (into buf1), y (, z)
+  if (fused_x) {
+    switch (W) {
+#define TP_SX(w)                                                                                \
+  case w:                                                                                       \
+    PISCO_KERNEL(h, k_tp_scatter_fx<w>, dim3(ceil_div(rq, 256)), dim3(256), 0, X, op.boxmap,    \
+                 op.Tf, op.buf1, n, op.L, Q, b, F, rows, role);                                 \
+    break;
+      TP_SX(3) TP_SX(5) TP_SX(7) TP_SX(9) TP_SX(11) TP_SX(13)
+#undef TP_SX
+    }
+  } else {
+    PISCO_KERNEL(h, k_tp_scatter, dim3(ceil_div(1LL * cells * bq, 256)), dim3(256), 0, X,
+                 op.boxmap, op.buf0, n, op.L, Q, b, cells, role);
+    const int fx[4] = {rows, W, bq, 1};
+    if ((st = axis_transform64(h, op.buf0, op.buf1, fx, 1, F, op.Tf))) return st;
+  }
   const int fy[4] = {Wz, W, F * bq, 1};
   if ((st = axis_transform64(h, op.buf1, op.buf0, fy, 1, F, op.Tf))) return st;
+  // per-frequency products; the y spectrum of the box ends in `ys`
+  double2* ys = op.buf0;
   if (op.D == 3 && (W & 1) && W >= 3 && W <= 11 && Fz == F && Wz == W) {
     // z pass, per-frequency products and inverse z pass fused: buf0 -> buf1
     const int ctiles = ceil_div(b, 16);
@@ -411,38 +564,50 @@ pisco_status_t toeplitz_product(Handle* h, const ToeplitzOp& op, const double2* 
     }
     const int iy[4] = {Wz, F, F * bq, 1};
     if ((st = axis_transform64(h, op.buf1, op.buf0, iy, 1, W, op.Ti))) return st;
-    const int ix[4] = {Wz * W, F, bq, 1};
-    if ((st = axis_transform64(h, op.buf0, op.buf1, ix, 1, W, op.Ti))) return st;
-    PISCO_KERNEL(h, k_tp_gather, dim3(ceil_div(1LL * b * n, 256)), dim3(256), 0, op.buf1, op.sup,
-                 X, out, prev, n, op.L, Q, b, W, W / 2, W / 2, coef, role);
+    ys = op.buf0;
+  } else {
+    double2* spec = op.buf0;
+    double2* other = op.buf1;
+    if (op.D == 3) {
+      const int fz[4] = {1, Wz, F * F * bq, 1};
+      if ((st = axis_transform64(h, op.buf0, op.buf1, fz, 1, Fz, op.Tf))) return st;
+      spec = op.buf1;
+      other = op.buf0;
+    }
+    const int nf = Fz * F * F;
+    PISCO_KERNEL(h, k_tp_pointwise, dim3(ceil_div(b, 64), nf), dim3(256), 0, spec, op.rhat,
+                 other, Q, b, role);
+    // frequency -> box: (z,) y
+    double2* cur = other;
+    double2* nxt = spec;
+    if (op.D == 3) {
+      const int iz[4] = {1, Fz, F * F * bq, 1};
+      if ((st = axis_transform64(h, cur, nxt, iz, 1, Wz, op.Ti))) return st;
+      double2* tmp = cur;
+      cur = nxt;
+      nxt = tmp;
+    }
+    const int iy[4] = {Wz, F, F * bq, 1};
+    if ((st = axis_transform64(h, cur, nxt, iy, 1, W, op.Ti))) return st;
+    ys = nxt;
+  }
+  // x back and the support points, with the epilogue
+  if (fused_x) {
+    switch (W) {
+#define TP_XG(w)                                                                                 \
+  case w:                                                                                        \
+    PISCO_KERNEL(h, k_tp_ix_gather<w>, dim3(ceil_div(rq, 256)), dim3(256), 0, ys, op.boxmap,     \
+                 op.Ti, X, out, prev, n, op.L, Q, b, rows, coef, role);                          \
+    break;
+      TP_XG(3) TP_XG(5) TP_XG(7) TP_XG(9) TP_XG(11) TP_XG(13)
+#undef TP_XG
+    }
     return PISCO_OK;
   }
-  double2* spec = op.buf0;
-  double2* other = op.buf1;
-  if (op.D == 3) {
-    const int fz[4] = {1, Wz, F * F * bq, 1};
-    if ((st = axis_transform64(h, op.buf0, op.buf1, fz, 1, Fz, op.Tf))) return st;
-    spec = op.buf1;
-    other = op.buf0;
-  }
-  const int nf = Fz * F * F;
-  PISCO_KERNEL(h, k_tp_pointwise, dim3(ceil_div(b, 64), nf), dim3(256), 0, spec, op.rhat,
-               other, Q, b, role);
-  // frequency -> box: (z,) y, x
-  double2* cur = other;
-  double2* nxt = spec;
-  if (op.D == 3) {
-    const int iz[4] = {1, Fz, F * F * bq, 1};
-    if ((st = axis_transform64(h, cur, nxt, iz, 1, Wz, op.Ti))) return st;
-    double2* t = cur;
-    cur = nxt;
-    nxt = t;
-  }
-  const int iy[4] = {Wz, F, F * bq, 1};
-  if ((st = axis_transform64(h, cur, nxt, iy, 1, W, op.Ti))) return st;
-  const int ix[4] = {Wz * W, F, bq, 1};
-  if ((st = axis_transform64(h, nxt, cur, ix, 1, W, op.Ti))) return st;
-  PISCO_KERNEL(h, k_tp_gather, dim3(ceil_div(1LL * b * n, 256)), dim3(256), 0, cur, op.sup, X,
+  double2* box = ys == op.buf0 ? op.buf1 : op.buf0;
+  const int ix[4] = {rows, F, bq, 1};
+  if ((st = axis_transform64(h, ys, box, ix, 1, W, op.Ti))) return st;
+  PISCO_KERNEL(h, k_tp_gather, dim3(ceil_div(1LL * b * n, 256)), dim3(256), 0, box, op.sup, X,
                out, prev, n, op.L, Q, b, W, op.D == 3 ? op.W / 2 : 0, op.W / 2, coef, role);
   return PISCO_OK;
 }
