@@ -315,6 +315,91 @@ __global__ void __launch_bounds__(512) k_tp_zfused(const double2* __restrict__ i
   }
 }
 
+// One-axis transforms of the centred box through the frequency pairs (k,
+// F - k) (as in k_tp_zfused), for the y passes: in[outer][W][inner] ->
+// out[outer][F][inner] and back, one thread per (outer, inner) column.
+template <int kW>
+__global__ void __launch_bounds__(256) k_tp_fwd_pair(const double2* __restrict__ in,
+                                                     const double2* __restrict__ Tf,
+                                                     double2* __restrict__ out, long long outer,
+                                                     long long inner) {
+  constexpr int kT = kW / 2, kF = 2 * kW - 1;
+  const long long idx = blockIdx.x * 256LL + threadIdx.x;
+  if (idx >= outer * inner) return;
+  const long long o = idx / inner, j = idx - o * inner;
+  const double2* src = in + size_t(o) * kW * inner + j;
+  double2 x[kW];
+#pragma unroll
+  for (int i = 0; i < kW; ++i) x[i] = src[size_t(i) * inner];
+  double2 U[kT + 1], V[kT + 1];
+  U[0] = x[kT];
+  V[0] = make_double2(0.0, 0.0);
+#pragma unroll
+  for (int d = 1; d <= kT; ++d) {
+    U[d] = make_double2(x[kT + d].x + x[kT - d].x, x[kT + d].y + x[kT - d].y);
+    V[d] = make_double2(x[kT + d].x - x[kT - d].x, x[kT + d].y - x[kT - d].y);
+  }
+  double2* dst = out + size_t(o) * kF * inner + j;
+#pragma unroll
+  for (int k = 0; k <= 2 * kT; ++k) {
+    const double2* tf = Tf + size_t(k) * kW + kT;
+    double2 C = make_double2(0.0, 0.0), S = C;
+#pragma unroll
+    for (int d = 0; d <= kT; ++d) {
+      const double2 m = tf[d];
+      C.x = fma(m.x, U[d].x, C.x);
+      C.y = fma(m.x, U[d].y, C.y);
+      if (d > 0) {
+        S.x = fma(m.y, V[d].x, S.x);
+        S.y = fma(m.y, V[d].y, S.y);
+      }
+    }
+    dst[size_t(k) * inner] = make_double2(C.x - S.y, C.y + S.x);
+    if (k > 0) dst[size_t(kF - k) * inner] = make_double2(C.x + S.y, C.y - S.x);
+  }
+}
+
+template <int kW>
+__global__ void __launch_bounds__(256) k_tp_inv_pair(const double2* __restrict__ in,
+                                                     const double2* __restrict__ Ti,
+                                                     double2* __restrict__ out, long long outer,
+                                                     long long inner) {
+  constexpr int kT = kW / 2, kF = 2 * kW - 1;
+  const long long idx = blockIdx.x * 256LL + threadIdx.x;
+  if (idx >= outer * inner) return;
+  const long long o = idx / inner, j = idx - o * inner;
+  const double2* src = in + size_t(o) * kF * inner + j;
+  double2 y[kF];
+#pragma unroll
+  for (int f = 0; f < kF; ++f) y[f] = src[size_t(f) * inner];
+  double2 P[kT + 1], M[kT + 1];
+#pragma unroll
+  for (int d = 0; d <= kT; ++d) P[d] = M[d] = make_double2(0.0, 0.0);
+#pragma unroll
+  for (int k = 0; k <= 2 * kT; ++k) {
+    const double2 ya = y[k], yc = k > 0 ? y[kF - k] : make_double2(0.0, 0.0);
+    const double2 Sv = make_double2(ya.x + yc.x, ya.y + yc.y);
+    const double2 Dv = make_double2(ya.x - yc.x, ya.y - yc.y);
+#pragma unroll
+    for (int d = 0; d <= kT; ++d) {
+      const double2 m = Ti[size_t(kT + d) * kF + k];
+      P[d].x = fma(m.x, Sv.x, P[d].x);
+      P[d].y = fma(m.x, Sv.y, P[d].y);
+      if (d > 0) {
+        M[d].x = fma(m.y, Dv.x, M[d].x);
+        M[d].y = fma(m.y, Dv.y, M[d].y);
+      }
+    }
+  }
+  double2* dst = out + size_t(o) * kW * inner + j;
+  dst[size_t(kT) * inner] = P[0];
+#pragma unroll
+  for (int d = 1; d <= kT; ++d) {
+    dst[size_t(kT + d) * inner] = make_double2(P[d].x - M[d].y, P[d].y + M[d].x);
+    dst[size_t(kT - d) * inner] = make_double2(P[d].x + M[d].y, P[d].y - M[d].x);
+  }
+}
+
 // Support block -> x spectrum of the box in one pass (the scatter onto the
 // box and the x transform fused): thread (box row r = (z, y), e = c Q + q)
 // reads x(tau + d) = X[c][q L + boxmap[r][tau + d]] (zero off the support;
@@ -544,8 +629,21 @@ pisco_status_t toeplitz_product(Handle* h, const ToeplitzOp& op, const double2* 
     const int fx[4] = {rows, W, bq, 1};
     if ((st = axis_transform64(h, op.buf0, op.buf1, fx, 1, F, op.Tf))) return st;
   }
-  const int fy[4] = {Wz, W, F * bq, 1};
-  if ((st = axis_transform64(h, op.buf1, op.buf0, fy, 1, F, op.Tf))) return st;
+  const long long yin = 1LL * F * bq;  // inner extent of the y passes
+  if (fused_x) {
+    switch (W) {
+#define TP_FY(w)                                                                                \
+  case w:                                                                                       \
+    PISCO_KERNEL(h, k_tp_fwd_pair<w>, dim3(ceil_div(Wz * yin, 256)), dim3(256), 0, op.buf1,     \
+                 op.Tf, op.buf0, (long long)Wz, yin);                                           \
+    break;
+      TP_FY(3) TP_FY(5) TP_FY(7) TP_FY(9) TP_FY(11) TP_FY(13)
+#undef TP_FY
+    }
+  } else {
+    const int fy[4] = {Wz, W, F * bq, 1};
+    if ((st = axis_transform64(h, op.buf1, op.buf0, fy, 1, F, op.Tf))) return st;
+  }
   // per-frequency products; the y spectrum of the box ends in `ys`
   double2* ys = op.buf0;
   if (op.D == 3 && (W & 1) && W >= 3 && W <= 11 && Fz == F && Wz == W) {
@@ -562,8 +660,15 @@ pisco_status_t toeplitz_product(Handle* h, const ToeplitzOp& op, const double2* 
       TP_ZF(3) TP_ZF(5) TP_ZF(7) TP_ZF(9) TP_ZF(11)
 #undef TP_ZF
     }
-    const int iy[4] = {Wz, F, F * bq, 1};
-    if ((st = axis_transform64(h, op.buf1, op.buf0, iy, 1, W, op.Ti))) return st;
+    switch (W) {
+#define TP_IY(w)                                                                                \
+  case w:                                                                                       \
+    PISCO_KERNEL(h, k_tp_inv_pair<w>, dim3(ceil_div(Wz * yin, 256)), dim3(256), 0, op.buf1,     \
+                 op.Ti, op.buf0, (long long)Wz, yin);                                           \
+    break;
+      TP_IY(3) TP_IY(5) TP_IY(7) TP_IY(9) TP_IY(11)
+#undef TP_IY
+    }
     ys = op.buf0;
   } else {
     double2* spec = op.buf0;
@@ -587,8 +692,20 @@ pisco_status_t toeplitz_product(Handle* h, const ToeplitzOp& op, const double2* 
       cur = nxt;
       nxt = tmp;
     }
-    const int iy[4] = {Wz, F, F * bq, 1};
-    if ((st = axis_transform64(h, cur, nxt, iy, 1, W, op.Ti))) return st;
+    if (fused_x) {
+      switch (W) {
+#define TP_IY(w)                                                                                \
+  case w:                                                                                       \
+    PISCO_KERNEL(h, k_tp_inv_pair<w>, dim3(ceil_div(Wz * yin, 256)), dim3(256), 0, cur, op.Ti,  \
+                 nxt, (long long)Wz, yin);                                                      \
+    break;
+        TP_IY(3) TP_IY(5) TP_IY(7) TP_IY(9) TP_IY(11) TP_IY(13)
+#undef TP_IY
+      }
+    } else {
+      const int iy[4] = {Wz, F, F * bq, 1};
+      if ((st = axis_transform64(h, cur, nxt, iy, 1, W, op.Ti))) return st;
+    }
     ys = nxt;
   }
   // x back and the support points, with the epilogue
