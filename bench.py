@@ -61,6 +61,12 @@ def kernel_model(name: str, w, est, rs: int):
     """(bound, algorithmic work per launch, unit) of a kernel, or None.
 
     Work per unit (the method's own need, not what the kernel happens to do):
+      k_tp_zfused  3D structured Gram product past the x and y passes: the z
+                 transforms, one Q x Q complex product per frequency (F = 4 tau
+                 + 1 points per axis) and the inverse z transforms; bound by
+                 FP64 arithmetic (the matrix cores and the vector ALUs do not
+                 co-execute), work = the per-frequency products, 8 F^3 Q^2 b
+                 flops (the three-multiplication form issues 6/8 of them)
       k_tp_pointwise  one Q x Q product per frequency of the structured Gram
                  product (F = 4 tau + 1 points per axis): read of the block's
                  spectrum and write of the result, 2 x 16 F^D Q b bytes, plus
@@ -75,6 +81,9 @@ def kernel_model(name: str, w, est, rs: int):
       k_rss      read + write of the output maps:     16 Q N_out bytes
     """
     n, b, Q = est.n, est.block, est.Q
+    if name.startswith("k_tp_zfused"):
+        nf = (4 * int(w.radius) + 1) ** 3
+        return "mfma_fp64", 8.0 * nf * Q * Q * b, "flop"
     if name.startswith("k_tp_pointwise"):
         nf = (4 * int(w.radius) + 1) ** w.D
         return "hbm", 2.0 * 16 * nf * Q * b + 16.0 * nf * Q * Q, "byte"
@@ -97,7 +106,7 @@ def kernel_model(name: str, w, est, rs: int):
     return None
 
 
-KERNEL_SOURCES = {"k_tp_pointwise": "toeplitz.hip", "k_gemm_ax": "nullspace.hip", "k_hetrd": "heev.hip", "k_hetrd_reg": "heev.hip",
+KERNEL_SOURCES = {"k_tp_zfused": "toeplitz.hip", "k_tp_pointwise": "toeplitz.hip", "k_gemm_ax": "nullspace.hip", "k_hetrd": "heev.hip", "k_hetrd_reg": "heev.hip",
                   "k_chol": "nullspace.hip", "k_tri_inv": "nullspace.hip",
                   "k_gemm_tn": "nullspace.hip",
                   "k_gemm_nn": "nullspace.hip", "k_herk": "gx.hip", "k_power": "eig.hip",
