@@ -67,7 +67,9 @@ __global__ void __launch_bounds__(256, 3) k_power(const float2* __restrict__ G, 
   const int t = threadIdx.x, wv = t >> 6, l = t & 63;
   const int q = l % QG, slot = l / QG;
   const int P = Q * (Q + 1) / 2;
-  const long long v0 = 1LL * blockIdx.x * VB;
+  // XCD-contiguous voxel blocks: a block's plane runs share 128-byte lines
+  // with its neighbours', fetched once into one L2
+  const long long v0 = xcd_block(blockIdx.x, gridDim.x) * VB;
   {
     // eight loads per thread in flight at once
     constexpr int kU = 8;
