@@ -258,6 +258,13 @@ pisco_status_t pisco_create(pisco_handle_t* handle, void* stream) {
   Handle* h = new (std::nothrow) Handle();
   if (!h) return PISCO_ERR_ARG;
   h->stream = static_cast<hipStream_t>(stream);
+  {
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+        cus > 0)
+      h->num_cu = cus;
+  }
   hipError_t e = hipMalloc(reinterpret_cast<void**>(&h->status_dev), 64);
   if (e != hipSuccess) {
     delete h;

@@ -98,6 +98,8 @@ struct Handle {
   std::vector<TraceRec> records;
   // autotuner results per problem shape: nullspace block and product waves
   std::map<std::string, std::pair<int, int>> tuned;
+  // compute units of the device current at creation (persistent grids)
+  int num_cu = 256;
 };
 
 // Brackets one kernel launch with events when tracing is on and the kernel

@@ -136,36 +136,46 @@ __global__ void __launch_bounds__(256) k_tp_pointwise(const double2* __restrict_
 // cores and the FP64 vector ALUs do not work at once, so this matters as
 // much as the MFMAs.
 //
-// Workgroup = one (fy, fx) pair x 16 columns c (XCD-contiguous, so that the
-// tiles of one pair share its matrices in one L2), eight waves in two roles
-// (one of each per SIMD), steps k = 0 .. 2 tau: frequency 0 alone, then the
-// pairs (k, F - k); one barrier per step:
+// Tile = one (fy, fx) pair x 16 columns c.  A workgroup walks every G-th
+// tile (G workgroups, one per CU; the tiles one XCD holds at a time are
+// consecutive, so the tiles of one pair share its matrices in one L2), with
+// eight waves
+// in two roles (one of each per SIMD); per tile the steps k = 0 .. 2 tau
+// take frequency 0 alone, then the pairs (k, F - k); one barrier per step:
 //   matrix waves (j, par), w < 4: output channels p in [16 j, 16 j + 16) of
 //     the step's frequency par, 24 FP64 MFMAs (three-multiplication complex
 //     products, as in k_tp_pointwise), Y into LDS (yb); the matrices of
-//     step k + 1 load during step k;
+//     step k + 1 load during step k; and z-plane k of the next tile's input
+//     goes into LDS (xn), so that the next tile starts without a wait on
+//     HBM;
 //   vector waves v = w - 4: X of both frequencies of step k + 1 at the MFMA
 //     steps s = 2v, 2v + 1 (u, v of their inputs held in registers) into LDS
 //     (xf), and two of the eight output elements per lane accumulated from
-//     step k - 1.
+//     step k - 1, stored at the end of the tile.
 template <int kW>
 __global__ void __launch_bounds__(512) k_tp_zfused(const double2* __restrict__ in,
                                                    const double2* __restrict__ rhat,
                                                    const double2* __restrict__ Tf,
                                                    const double2* __restrict__ Ti,
                                                    double2* __restrict__ out, int Q, int b, int F,
-                                                   int ctiles, const int* __restrict__ role) {
+                                                   int ctiles, int tiles,
+                                                   const int* __restrict__ role) {
   constexpr int kT = kW / 2;     // tau
   constexpr int kS = kMaxQ / 4;  // MFMA steps
+  constexpr int QS = kMaxQ + 1;  // padded LDS row of the next tile's input
   static_assert(kS == 8, "two MFMA steps per vector wave");
   __shared__ double2 xf[2][2][kS][64];    // [buffer][frequency of the step][s][lane]
   __shared__ double2 yb[2][2][2][4][64];  // [buffer][frequency of the step][j][v][lane]
+  __shared__ double2 xn[kW * 16 * QS];    // the next tile's input [z][c][q]
   if (role && *role == 0) return;
   const int l = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int li = l & 15, lk = l >> 4;
-  const long long tile = xcd_block(blockIdx.x, gridDim.x);
-  const int pair = int(tile / ctiles), c0 = int(tile % ctiles) * 16;
+  // this workgroup's tiles: rank, rank + G, ...; the ranks are dealt to the
+  // XCDs in contiguous ranges, so that at any time the workgroups of one XCD
+  // hold consecutive tiles, which share their pair's matrices in its L2
+  const long long G = gridDim.x;
+  const long long t0 = xcd_block(blockIdx.x, gridDim.x);
   const size_t FF = size_t(F) * F;
   const size_t zstride = FF * b * Q;
   const int iters = 2 * kT + 1;
@@ -175,141 +185,185 @@ __global__ void __launch_bounds__(512) k_tp_zfused(const double2* __restrict__ i
     // wait before the MFMAs can leave the next step's loads in flight
     const int j = w & 1, par = w >> 1;
     const int p = 16 * j + li;
-    auto load_r = [&](int k, double2* r) {
-      const int fz = par == 0 ? k : (k == 0 ? F : F - k);
-      const double2* R =
-          rhat + (k < iters && fz < F ? size_t(fz) * FF + pair : FF * F) * kRQ + p * kMaxQ + lk;
+    const int tl = threadIdx.x;  // 0 .. 255 over the matrix waves
+    for (long long tile = t0; tile < tiles; tile += G) {
+      const int pair = int(tile / ctiles);
+      const bool more = tile + G < tiles;
+      const long long tn = more ? tile + G : tile;
+      const int pn = int(tn / ctiles), cn = int(tn % ctiles) * 16;
+      const double2* srcn = in + (size_t(pn) * b + cn) * Q;
+      auto load_r = [&](int k, double2* r) {
+        const int fz = par == 0 ? k : (k == 0 ? F : F - k);
+        const double2* R =
+            rhat + (k < iters && fz < F ? size_t(fz) * FF + pair : FF * F) * kRQ + p * kMaxQ + lk;
 #pragma unroll
-      for (int s = 0; s < kS; ++s) r[s] = R[4 * s];
-    };
-    auto products = [&](int k, const double2* r) {
-      f64x4 c1 = {0.0, 0.0, 0.0, 0.0}, c2 = c1, c3 = c1;
+        for (int s = 0; s < kS; ++s) r[s] = R[4 * s];
+      };
+      auto products = [&](int k, const double2* r) {
+        f64x4 c1 = {0.0, 0.0, 0.0, 0.0}, c2 = c1, c3 = c1;
 #pragma unroll
-      for (int s = 0; s < kS; ++s) {
-        const double2 x = xf[k & 1][par][s][l];
-        c1 = __builtin_amdgcn_mfma_f64_16x16x4f64(x.x, r[s].x, c1, 0, 0, 0);
-        c2 = __builtin_amdgcn_mfma_f64_16x16x4f64(x.y, r[s].y, c2, 0, 0, 0);
-        c3 = __builtin_amdgcn_mfma_f64_16x16x4f64(x.x + x.y, r[s].x + r[s].y, c3, 0, 0, 0);
+        for (int s = 0; s < kS; ++s) {
+          const double2 x = xf[k & 1][par][s][l];
+          c1 = __builtin_amdgcn_mfma_f64_16x16x4f64(x.x, r[s].x, c1, 0, 0, 0);
+          c2 = __builtin_amdgcn_mfma_f64_16x16x4f64(x.y, r[s].y, c2, 0, 0, 0);
+          c3 = __builtin_amdgcn_mfma_f64_16x16x4f64(x.x + x.y, r[s].x + r[s].y, c3, 0, 0, 0);
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          yb[k & 1][par][j][v][l] = make_double2(c1[v] - c2[v], c3[v] - c1[v] - c2[v]);
+      };
+      // z-plane k of the next tile: 16 x kMaxQ elements, two per lane
+      auto next_load = [&](int k, double2* g) {
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+          const int e = tl + 256 * u, c = e / kMaxQ, q = e - c * kMaxQ;
+          g[u] = more && q < Q && cn + c < b ? srcn[k * zstride + size_t(c) * Q + q]
+                                            : make_double2(0.0, 0.0);
+        }
+      };
+      auto next_store = [&](int k, const double2* g) {
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+          const int e = tl + 256 * u, c = e / kMaxQ, q = e - c * kMaxQ;
+          xn[(k * 16 + c) * QS + q] = g[u];
+        }
+      };
+      double2 ra[kS], rb[kS], g[2];
+      load_r(0, ra);
+      int k = 0;
+      for (; k + 2 <= iters; k += 2) {
+        __syncthreads();  // xf[k & 1] complete, yb[k & 1] read
+        next_load(k, g);
+        load_r(k + 1, rb);
+        products(k, ra);
+        next_store(k, g);
+        __syncthreads();
+        next_load(k + 1, g);
+        load_r(k + 2, ra);
+        products(k + 1, rb);
+        next_store(k + 1, g);
       }
-#pragma unroll
-      for (int v = 0; v < 4; ++v)
-        yb[k & 1][par][j][v][l] = make_double2(c1[v] - c2[v], c3[v] - c1[v] - c2[v]);
-    };
-    double2 ra[kS], rb[kS];
-    load_r(0, ra);
-    int k = 0;
-    for (; k + 2 <= iters; k += 2) {
-      __syncthreads();  // xf[k & 1] complete, yb[k & 1] read
-      load_r(k + 1, rb);
-      products(k, ra);
-      __syncthreads();
-      load_r(k + 2, ra);
-      products(k + 1, rb);
+      if (k < iters) {
+        __syncthreads();
+        next_load(k, g);
+        products(k, ra);
+        next_store(k, g);
+      }
+      __syncthreads();  // end of the tile
     }
-    if (k < iters) {
-      __syncthreads();
-      products(k, ra);
-    }
-    __syncthreads();
     return;
   }
   // vector waves: elements (c = li, q = 4 s + lk), s = 2 vw + u, forward;
   // output elements e = 2 vw + u at (c = lk + 4 (e & 3), p = 16 (e >> 2) + li)
   const int vw = w - 4;
-  double2 U[2][kT + 1], V[2][kT + 1];
-  {
-    const bool rowok = c0 + li < b;
-    const double2* src = in + (size_t(pair) * b + c0 + li) * Q;
-    double2 x[2][kW];
+  for (long long tile = t0; tile < tiles; tile += G) {
+    const int pair = int(tile / ctiles), c0 = int(tile % ctiles) * 16;
+    double2 U[2][kT + 1], V[2][kT + 1];
+    {
+      double2 x[2][kW];
+      if (tile == t0) {
+        const bool rowok = c0 + li < b;
+        const double2* src = in + (size_t(pair) * b + c0 + li) * Q;
 #pragma unroll
-    for (int u = 0; u < 2; ++u) {
-      const int q = 4 * (2 * vw + u) + lk;
-      const bool ok = rowok && q < Q;
+        for (int u = 0; u < 2; ++u) {
+          const int q = 4 * (2 * vw + u) + lk;
+          const bool ok = rowok && q < Q;
 #pragma unroll
-      for (int z = 0; z < kW; ++z) x[u][z] = ok ? src[z * zstride + q] : make_double2(0.0, 0.0);
-    }
+          for (int z = 0; z < kW; ++z)
+            x[u][z] = ok ? src[z * zstride + q] : make_double2(0.0, 0.0);
+        }
+      } else {
+        // staged by the matrix waves during the previous tile (zeros past
+        // b and Q)
 #pragma unroll
-    for (int u = 0; u < 2; ++u) {
-      U[u][0] = x[u][kT];
-      V[u][0] = make_double2(0.0, 0.0);
+        for (int u = 0; u < 2; ++u)
 #pragma unroll
-      for (int d = 1; d <= kT; ++d) {
-        U[u][d] = make_double2(x[u][kT + d].x + x[u][kT - d].x, x[u][kT + d].y + x[u][kT - d].y);
-        V[u][d] = make_double2(x[u][kT + d].x - x[u][kT - d].x, x[u][kT + d].y - x[u][kT - d].y);
+          for (int z = 0; z < kW; ++z) x[u][z] = xn[(z * 16 + li) * QS + 4 * (2 * vw + u) + lk];
       }
-    }
-  }
-  auto fwd = [&](int k, int buf) {  // frequencies k and F - k of step k
-    const double2* tf = Tf + size_t(k < F ? k : 0) * kW + kT;
 #pragma unroll
-    for (int u = 0; u < 2; ++u) {
-      double2 C = make_double2(0.0, 0.0), S = C;
+      for (int u = 0; u < 2; ++u) {
+        U[u][0] = x[u][kT];
+        V[u][0] = make_double2(0.0, 0.0);
 #pragma unroll
-      for (int d = 0; d <= kT; ++d) {
-        const double2 m = tf[d];
-        C.x = fma(m.x, U[u][d].x, C.x);
-        C.y = fma(m.x, U[u][d].y, C.y);
-        if (d > 0) {
-          S.x = fma(m.y, V[u][d].x, S.x);
-          S.y = fma(m.y, V[u][d].y, S.y);
+        for (int d = 1; d <= kT; ++d) {
+          U[u][d] = make_double2(x[u][kT + d].x + x[u][kT - d].x, x[u][kT + d].y + x[u][kT - d].y);
+          V[u][d] = make_double2(x[u][kT + d].x - x[u][kT - d].x, x[u][kT + d].y - x[u][kT - d].y);
         }
       }
-      xf[buf][0][2 * vw + u][l] = make_double2(C.x - S.y, C.y + S.x);
-      xf[buf][1][2 * vw + u][l] = make_double2(C.x + S.y, C.y - S.x);
     }
-  };
-  double2 P[2][kT + 1], M[2][kT + 1];
+    auto fwd = [&](int k, int buf) {  // frequencies k and F - k of step k
+      const double2* tf = Tf + size_t(k < F ? k : 0) * kW + kT;
 #pragma unroll
-  for (int u = 0; u < 2; ++u)
+      for (int u = 0; u < 2; ++u) {
+        double2 C = make_double2(0.0, 0.0), S = C;
 #pragma unroll
-    for (int d = 0; d <= kT; ++d) P[u][d] = M[u][d] = make_double2(0.0, 0.0);
-  auto inv = [&](int k, int buf) {  // Y of step k (zero at k = -1)
-    const double2* ti = Ti + size_t(kT) * F + (k > 0 ? k : 0);
+        for (int d = 0; d <= kT; ++d) {
+          const double2 m = tf[d];
+          C.x = fma(m.x, U[u][d].x, C.x);
+          C.y = fma(m.x, U[u][d].y, C.y);
+          if (d > 0) {
+            S.x = fma(m.y, V[u][d].x, S.x);
+            S.y = fma(m.y, V[u][d].y, S.y);
+          }
+        }
+        xf[buf][0][2 * vw + u][l] = make_double2(C.x - S.y, C.y + S.x);
+        xf[buf][1][2 * vw + u][l] = make_double2(C.x + S.y, C.y - S.x);
+      }
+    };
+    double2 P[2][kT + 1], M[2][kT + 1];
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+      for (int d = 0; d <= kT; ++d) P[u][d] = M[u][d] = make_double2(0.0, 0.0);
+    auto inv = [&](int k, int buf) {  // Y of step k (zero at k = -1)
+      const double2* ti = Ti + size_t(kT) * F + (k > 0 ? k : 0);
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int e = 2 * vw + u;
+        const double2 ya = yb[buf][0][e >> 2][e & 3][l], yc = yb[buf][1][e >> 2][e & 3][l];
+        const double2 Sv = make_double2(ya.x + yc.x, ya.y + yc.y);
+        const double2 Dv = make_double2(ya.x - yc.x, ya.y - yc.y);
+#pragma unroll
+        for (int d = 0; d <= kT; ++d) {
+          const double2 m = ti[size_t(d) * F];
+          P[u][d].x = fma(m.x, Sv.x, P[u][d].x);
+          P[u][d].y = fma(m.x, Sv.y, P[u][d].y);
+          if (d > 0) {
+            M[u][d].x = fma(m.y, Dv.x, M[u][d].x);
+            M[u][d].y = fma(m.y, Dv.y, M[u][d].y);
+          }
+        }
+      }
+    };
+    // the Y of step -1 is zero (each lane reads back only what it wrote
+    // here; the matrix waves write yb[1] first at step 1, after a barrier)
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
       const int e = 2 * vw + u;
-      const double2 ya = yb[buf][0][e >> 2][e & 3][l], yc = yb[buf][1][e >> 2][e & 3][l];
-      const double2 Sv = make_double2(ya.x + yc.x, ya.y + yc.y);
-      const double2 Dv = make_double2(ya.x - yc.x, ya.y - yc.y);
-#pragma unroll
-      for (int d = 0; d <= kT; ++d) {
-        const double2 m = ti[size_t(d) * F];
-        P[u][d].x = fma(m.x, Sv.x, P[u][d].x);
-        P[u][d].y = fma(m.x, Sv.y, P[u][d].y);
-        if (d > 0) {
-          M[u][d].x = fma(m.y, Dv.x, M[u][d].x);
-          M[u][d].y = fma(m.y, Dv.y, M[u][d].y);
-        }
-      }
+      yb[1][0][e >> 2][e & 3][l] = make_double2(0.0, 0.0);
+      yb[1][1][e >> 2][e & 3][l] = make_double2(0.0, 0.0);
     }
-  };
-  // the Y of step -1 is zero (each lane reads back only what it wrote here)
+    fwd(0, 0);
+    for (int k = 0; k < iters; ++k) {
+      __syncthreads();            // xf[k & 1] read next, yb[(k - 1) & 1] complete
+      fwd(k + 1, (k + 1) & 1);  // unused after the last step
+      inv(k - 1, (k - 1) & 1);
+    }
+    __syncthreads();  // end of the tile
+    inv(iters - 1, (iters - 1) & 1);
+    double2* dst = out + (size_t(pair) * b + c0) * Q;
 #pragma unroll
-  for (int u = 0; u < 2; ++u) {
-    const int e = 2 * vw + u;
-    yb[1][0][e >> 2][e & 3][l] = make_double2(0.0, 0.0);
-    yb[1][1][e >> 2][e & 3][l] = make_double2(0.0, 0.0);
-  }
-  fwd(0, 0);
-  for (int k = 0; k < iters; ++k) {
-    __syncthreads();            // xf[k & 1] read next, yb[(k - 1) & 1] complete
-    fwd(k + 1, (k + 1) & 1);  // unused after the last step
-    inv(k - 1, (k - 1) & 1);
-  }
-  __syncthreads();
-  inv(iters - 1, (iters - 1) & 1);
-  double2* dst = out + (size_t(pair) * b + c0) * Q;
+    for (int u = 0; u < 2; ++u) {
+      const int e = 2 * vw + u;
+      const int c = lk + 4 * (e & 3), pp = 16 * (e >> 2) + li;
+      if (c0 + c < b && pp < Q) {
+        double2* o = dst + size_t(c) * Q + pp;
+        o[kT * zstride] = P[u][0];
 #pragma unroll
-  for (int u = 0; u < 2; ++u) {
-    const int e = 2 * vw + u;
-    const int c = lk + 4 * (e & 3), pp = 16 * (e >> 2) + li;
-    if (c0 + c < b && pp < Q) {
-      double2* o = dst + size_t(c) * Q + pp;
-      o[kT * zstride] = P[u][0];
-#pragma unroll
-      for (int d = 1; d <= kT; ++d) {
-        o[(kT + d) * zstride] = make_double2(P[u][d].x - M[u][d].y, P[u][d].y + M[u][d].x);
-        o[(kT - d) * zstride] = make_double2(P[u][d].x + M[u][d].y, P[u][d].y - M[u][d].x);
+        for (int d = 1; d <= kT; ++d) {
+          o[(kT + d) * zstride] = make_double2(P[u][d].x - M[u][d].y, P[u][d].y + M[u][d].x);
+          o[(kT - d) * zstride] = make_double2(P[u][d].x + M[u][d].y, P[u][d].y - M[u][d].x);
+        }
       }
     }
   }
@@ -648,14 +702,16 @@ pisco_status_t toeplitz_product(Handle* h, const ToeplitzOp& op, const double2* 
   double2* ys = op.buf0;
   if (op.D == 3 && (W & 1) && W >= 3 && W <= 11 && Fz == F && Wz == W) {
     // z pass, per-frequency products and inverse z pass fused: buf0 -> buf1
+    // a persistent grid: one workgroup per CU, each walking a range of tiles
     const int ctiles = ceil_div(b, 16);
-    const dim3 grid(unsigned(F * F * ctiles));
+    const int tiles = F * F * ctiles;
+    const dim3 grid(unsigned(tiles < h->num_cu ? tiles : h->num_cu));
     const dim3 blk(512);
     switch (W) {
 #define TP_ZF(w)                                                                                 \
   case w:                                                                                        \
     PISCO_KERNEL(h, k_tp_zfused<w>, grid, blk, 0, op.buf0, op.rhat, op.Tf, op.Ti, op.buf1, Q, b, \
-                 F, ctiles, role);                                                               \
+                 F, ctiles, tiles, role);                                                        \
     break;
       TP_ZF(3) TP_ZF(5) TP_ZF(7) TP_ZF(9) TP_ZF(11)
 #undef TP_ZF
