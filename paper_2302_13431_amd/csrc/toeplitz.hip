@@ -454,32 +454,66 @@ __global__ void __launch_bounds__(256) k_tp_inv_pair(const double2* __restrict__
   }
 }
 
+// A box row's support points are one run of consecutive support indices
+// (lexicographic order, x fastest): cells x0 .. x0 + len - 1 <-> s0 ...
+__device__ inline void row_run(const int* __restrict__ boxmap, int r, int W, int* x0, int* len,
+                               int* s0) {
+  int a = -1, n = 0, s = 0;
+  for (int x = 0; x < W; ++x) {
+    const int v = boxmap[r * W + x];
+    if (v >= 0) {
+      if (a < 0) {
+        a = x;
+        s = v;
+      }
+      ++n;
+    }
+  }
+  *x0 = a < 0 ? 0 : a;
+  *len = n;
+  *s0 = s;
+}
+
 // Support block -> x spectrum of the box in one pass (the scatter onto the
-// box and the x transform fused): thread (box row r = (z, y), e = c Q + q)
-// reads x(tau + d) = X[c][q L + boxmap[r][tau + d]] (zero off the support;
-// one contiguous run of the column per thread) and writes out[r][fx][e] for
-// all F frequencies through the pairs (k, F - k) of the centred box, as in
-// k_tp_zfused.  role 0: nothing to do (the gather copies X).
+// box and the x transform fused).  Workgroup = one box row r x 256 block
+// elements e = c Q + q: the row's support run of each element (consecutive
+// support indices, one contiguous run of the block's column) is loaded with
+// consecutive lanes on consecutive points, staged in LDS, and each thread
+// then transforms its element's row through the frequency pairs (k, F - k)
+// of the centred box, as in k_tp_zfused, writing out[r][fx][e] along e.
+// role 0: nothing to do (the gather copies X).
 template <int kW>
 __global__ void __launch_bounds__(256) k_tp_scatter_fx(const double2* __restrict__ X,
                                                        const int* __restrict__ boxmap,
                                                        const double2* __restrict__ Tf,
                                                        double2* __restrict__ out, int n, int L,
-                                                       int Q, int b, int F, int rows,
+                                                       int Q, int b, int F,
                                                        const int* __restrict__ role) {
   constexpr int kT = kW / 2;
+  __shared__ double2 vals[kW][256];
   if (role && *role == 0) return;
   const int bq = b * Q;
-  const long long idx = blockIdx.x * 256LL + threadIdx.x;
-  if (idx >= 1LL * rows * bq) return;
-  const int r = int(idx / bq), e = int(idx - 1LL * r * bq);
-  const int c = e / Q, q = e - c * Q;
-  const double2* src = X + size_t(c) * n + size_t(q) * L;
+  const int r = blockIdx.y, e0 = blockIdx.x * 256;
+  int x0, len, s0;
+  row_run(boxmap, r, kW, &x0, &len, &s0);
+  // vals[i][el] = X[c][q L + s0 + i] for the run, consecutive lanes along i
+  for (int o = threadIdx.x; o < 256 * len; o += 256) {
+    const int el = o / len, i = o - el * len, e = e0 + el;
+    double2 v = make_double2(0.0, 0.0);
+    if (e < bq) {
+      const int c = e / Q, q = e - c * Q;
+      v = X[size_t(c) * n + size_t(q) * L + s0 + i];
+    }
+    vals[i][el] = v;
+  }
+  __syncthreads();
+  const int e = e0 + threadIdx.x;
+  if (e >= bq) return;
   double2 x[kW];
 #pragma unroll
   for (int i = 0; i < kW; ++i) {
-    const int s = boxmap[r * kW + i];
-    x[i] = s >= 0 ? src[s] : make_double2(0.0, 0.0);
+    const int k = i - x0;
+    x[i] = k >= 0 && k < len ? vals[k][threadIdx.x] : make_double2(0.0, 0.0);
   }
   double2 U[kT + 1], V[kT + 1];
   U[0] = x[kT];
@@ -510,82 +544,90 @@ __global__ void __launch_bounds__(256) k_tp_scatter_fx(const double2* __restrict
 }
 
 // x spectrum of the box -> support block in one pass (the inverse x
-// transform and the gather fused): thread (r, e) reads in[r][f][e] for the
-// F frequencies, forms the row's box values through the frequency pairs,
-// and writes the support points of the row, out[c][q L + s] = S, or a S +
-// bc X + g prev with (a, bc, g) = coef[0..2] (coef[3..5] for role 2); role
-// 0 copies X.  Every support point lies in exactly one box row.
+// transform and the gather fused).  Workgroup = one box row r x 256 block
+// elements: each thread reads its element's F frequencies (along e, as
+// written), forms the row's box values through the frequency pairs and puts
+// the row's support run in LDS; then the run of every element is written,
+// consecutive lanes on consecutive support points: out[c][q L + s] = S, or
+// a S + bc X + g prev with (a, bc, g) = coef[0..2] (coef[3..5] for role 2);
+// role 0 copies X.  Every support point lies in exactly one box row.
 template <int kW>
 __global__ void __launch_bounds__(256) k_tp_ix_gather(const double2* __restrict__ in,
                                                       const int* __restrict__ boxmap,
                                                       const double2* __restrict__ Ti,
                                                       const double2* __restrict__ X,
                                                       double2* out, const double2* prev, int n,
-                                                      int L, int Q, int b, int rows,
+                                                      int L, int Q, int b,
                                                       const double* __restrict__ coef,
                                                       const int* __restrict__ role) {
   constexpr int kT = kW / 2, kF = 2 * kW - 1;
+  __shared__ double2 vals[kW][256];
   const int bq = b * Q;
-  const long long idx = blockIdx.x * 256LL + threadIdx.x;
-  if (idx >= 1LL * rows * bq) return;
-  const int r = int(idx / bq), e = int(idx - 1LL * r * bq);
-  const int c = e / Q, q = e - c * Q;
-  const size_t col = size_t(c) * n + size_t(q) * L;
+  const int r = blockIdx.y, e0 = blockIdx.x * 256;
+  int x0, len, s0;
+  row_run(boxmap, r, kW, &x0, &len, &s0);
   int rl = 1;
   if (role) {
     rl = *role;
     if (rl == 2) coef += 3;
   }
-  if (rl == 0) {
+  const int e = e0 + threadIdx.x;
+  if (rl != 0 && e < bq) {
+    double2 y[kF];
+    const double2* src = in + size_t(r) * kF * bq + e;
 #pragma unroll
-    for (int i = 0; i < kW; ++i) {
-      const int s = boxmap[r * kW + i];
-      if (s >= 0) out[col + s] = X[col + s];
-    }
-    return;
-  }
-  double2 y[kF];
-  const double2* src = in + size_t(r) * kF * bq + e;
+    for (int f = 0; f < kF; ++f) y[f] = src[size_t(f) * bq];
+    double2 P[kT + 1], M[kT + 1];
 #pragma unroll
-  for (int f = 0; f < kF; ++f) y[f] = src[size_t(f) * bq];
-  double2 P[kT + 1], M[kT + 1];
+    for (int d = 0; d <= kT; ++d) P[d] = M[d] = make_double2(0.0, 0.0);
 #pragma unroll
-  for (int d = 0; d <= kT; ++d) P[d] = M[d] = make_double2(0.0, 0.0);
+    for (int k = 0; k <= 2 * kT; ++k) {
+      const double2 ya = y[k], yc = k > 0 ? y[kF - k] : make_double2(0.0, 0.0);
+      const double2 Sv = make_double2(ya.x + yc.x, ya.y + yc.y);
+      const double2 Dv = make_double2(ya.x - yc.x, ya.y - yc.y);
 #pragma unroll
-  for (int k = 0; k <= 2 * kT; ++k) {
-    const double2 ya = y[k], yc = k > 0 ? y[kF - k] : make_double2(0.0, 0.0);
-    const double2 Sv = make_double2(ya.x + yc.x, ya.y + yc.y);
-    const double2 Dv = make_double2(ya.x - yc.x, ya.y - yc.y);
-#pragma unroll
-    for (int d = 0; d <= kT; ++d) {
-      const double2 m = Ti[size_t(kT + d) * kF + k];
-      P[d].x = fma(m.x, Sv.x, P[d].x);
-      P[d].y = fma(m.x, Sv.y, P[d].y);
-      if (d > 0) {
-        M[d].x = fma(m.y, Dv.x, M[d].x);
-        M[d].y = fma(m.y, Dv.y, M[d].y);
+      for (int d = 0; d <= kT; ++d) {
+        const double2 m = Ti[size_t(kT + d) * kF + k];
+        P[d].x = fma(m.x, Sv.x, P[d].x);
+        P[d].y = fma(m.x, Sv.y, P[d].y);
+        if (d > 0) {
+          M[d].x = fma(m.y, Dv.x, M[d].x);
+          M[d].y = fma(m.y, Dv.y, M[d].y);
+        }
       }
     }
-  }
 #pragma unroll
-  for (int i = 0; i < kW; ++i) {
-    const int s = boxmap[r * kW + i];
-    if (s < 0) continue;
-    const int d = i - kT, ad = d < 0 ? -d : d;
-    const double sg = d < 0 ? -1.0 : 1.0;
-    const double2 v = d == 0 ? P[0]
-                             : make_double2(P[ad].x - sg * M[ad].y, P[ad].y + sg * M[ad].x);
+    for (int i = 0; i < kW; ++i) {
+      const int k = i - x0;
+      if (k < 0 || k >= len) continue;
+      const int d = i - kT, ad = d < 0 ? -d : d;
+      const double sg = d < 0 ? -1.0 : 1.0;
+      vals[k][threadIdx.x] = d == 0 ? P[0]
+                                    : make_double2(P[ad].x - sg * M[ad].y, P[ad].y + sg * M[ad].x);
+    }
+  }
+  __syncthreads();
+  for (int o = threadIdx.x; o < 256 * len; o += 256) {
+    const int el = o / len, i = o - el * len, ee = e0 + el;
+    if (ee >= bq) continue;
+    const int c = ee / Q, q = ee - c * Q;
+    const size_t idx = size_t(c) * n + size_t(q) * L + s0 + i;
+    if (rl == 0) {
+      out[idx] = X[idx];
+      continue;
+    }
+    const double2 v = vals[i][el];
     double2 res = v;
     if (coef) {
-      const double2 xv = X[col + s];
+      const double2 xv = X[idx];
       res = make_double2(coef[0] * v.x + coef[1] * xv.x, coef[0] * v.y + coef[1] * xv.y);
       if (prev) {
-        const double2 pv = prev[col + s];
+        const double2 pv = prev[idx];
         res.x += coef[2] * pv.x;
         res.y += coef[2] * pv.y;
       }
     }
-    out[col + s] = res;
+    out[idx] = res;
   }
 }
 
@@ -661,7 +703,6 @@ pisco_status_t toeplitz_product(Handle* h, const ToeplitzOp& op, const double2* 
   const int Q = op.Q, W = op.W, Wz = op.Wz, F = op.F, Fz = op.Fz;
   const int bq = b * Q;
   const int cells = Wz * W * W, rows = Wz * W;
-  const long long rq = 1LL * rows * bq;
   // the box's x passes fused with the scatter and the gather for the box
   // widths with a compiled kernel
   const bool fused_x = (W & 1) && W >= 3 && W <= 13 && F == 2 * W - 1;
@@ -671,8 +712,8 @@ pisco_status_t toeplitz_product(Handle* h, const ToeplitzOp& op, const double2* 
     switch (W) {
 #define TP_SX(w)                                                                                \
   case w:                                                                                       \
-    PISCO_KERNEL(h, k_tp_scatter_fx<w>, dim3(ceil_div(rq, 256)), dim3(256), 0, X, op.boxmap,    \
-                 op.Tf, op.buf1, n, op.L, Q, b, F, rows, role);                                 \
+    PISCO_KERNEL(h, k_tp_scatter_fx<w>, dim3(ceil_div(bq, 256), rows), dim3(256), 0, X,         \
+                 op.boxmap, op.Tf, op.buf1, n, op.L, Q, b, F, role);                            \
     break;
       TP_SX(3) TP_SX(5) TP_SX(7) TP_SX(9) TP_SX(11) TP_SX(13)
 #undef TP_SX
@@ -769,8 +810,8 @@ pisco_status_t toeplitz_product(Handle* h, const ToeplitzOp& op, const double2* 
     switch (W) {
 #define TP_XG(w)                                                                                 \
   case w:                                                                                        \
-    PISCO_KERNEL(h, k_tp_ix_gather<w>, dim3(ceil_div(rq, 256)), dim3(256), 0, ys, op.boxmap,     \
-                 op.Ti, X, out, prev, n, op.L, Q, b, rows, coef, role);                          \
+    PISCO_KERNEL(h, k_tp_ix_gather<w>, dim3(ceil_div(bq, 256), rows), dim3(256), 0, ys,          \
+                 op.boxmap, op.Ti, X, out, prev, n, op.L, Q, b, coef, role);                     \
     break;
       TP_XG(3) TP_XG(5) TP_XG(7) TP_XG(9) TP_XG(11) TP_XG(13)
 #undef TP_XG
