@@ -289,6 +289,9 @@ struct MapsWs {
   float2* cref;    // [Q][Nlr] phase-referenced maps
 };
 size_t layout_maps(const Plan& p, void* ws, MapsWs* out);
+// order of the interpolation passes over the used axes (0 = z, 1 = y, 2 = x):
+// x last, z and y ascending in out / lr; returns the number of used axes (D)
+int interp_order(const Plan& p, int ord[3]);
 
 // ------------------------------------------------------------------ stage launchers
 
@@ -391,9 +394,18 @@ pisco_status_t run_heev(Handle* h, const double2* H, int b, double2* U, double* 
 // Separable transform along one axis of a batched 3D array:
 //   out[b][..o..] = sum_i M[o][i] * in[b][..i..]
 // shape_in = {batch, d0, d1, d2}; axis in {1,2,3}; M is [nout][nin] float2.
+// real_m: M's imaginary parts are zero and may be skipped (sinc tables).
 pisco_status_t axis_transform(Handle* h, const float2* in, float2* out,
                               const int shape_in[4], int axis, int nout,
-                              const float2* M);
+                              const float2* M, bool real_m = false);
+
+// Last interpolation pass along x with a real M ([nout][nin], imaginary
+// parts ignored) fused with the per-voxel coil normalisation:
+//   out[q][r][o] = y[q][r][o] / ||y[:, r, o]||_2,  y[q][r][o] = sum_i M[o][i] in[q][r][i]
+// (a zero norm leaves y).  PISCO_ERR_UNSUPPORTED when the shape does not fit
+// (Q > 64 or nin > 64); nothing is launched then.
+pisco_status_t interp_x_rss(Handle* h, const float2* in, float2* out, const float2* M, int Q,
+                            long long rows, int nin, int nout);
 
 // FP64 variants of axis_transform (input FP32 or FP64, output and matrix FP64)
 pisco_status_t axis_transform64(Handle* h, const float2* in, double2* out,

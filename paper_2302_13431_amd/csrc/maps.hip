@@ -150,18 +150,28 @@ pisco_status_t run_maps(Handle* h, const Plan& p, const Tables& t, int phase_rul
   } else {
     PISCO_KERNEL(h, k_phase_coil, dim3(ceil_div(N, 256)), dim3(256), 0, maps_lr, w.cref, Q, N);
   }
-  // interpolation: [Q][lr0][lr1][lr2] -> x -> y -> (z) -> maps_out
+  // interpolation [Q][lr0][lr1][lr2] -> [Q][out0][out1][out2], one axis at a
+  // time in the order interp_order gives (x last); the x pass carries the
+  // coil normalisation
   int sh[4] = {Q, p.lr[0], p.lr[1], p.lr[2]};
-  if ((st = axis_transform(h, w.cref, w.tmpA, sh, 3, p.out[2], Ms[2]))) return st;
-  sh[3] = p.out[2];
-  if (p.D == 3) {
-    if ((st = axis_transform(h, w.tmpA, w.tmpB, sh, 2, p.out[1], Ms[1]))) return st;
-    sh[2] = p.out[1];
-    if ((st = axis_transform(h, w.tmpB, maps_out, sh, 1, p.out[0], Ms[0]))) return st;
-  } else {
-    if ((st = axis_transform(h, w.tmpA, maps_out, sh, 2, p.out[1], Ms[1]))) return st;
+  int ord[3];
+  const int n = interp_order(p, ord);
+  const float2* cur = w.cref;
+  for (int i = 0; i + 1 < n; ++i) {
+    const int d = ord[i];
+    float2* dst = i == 0 ? w.tmpA : w.tmpB;
+    if ((st = axis_transform(h, cur, dst, sh, d + 1, p.out[d], Ms[d], true))) return st;
+    sh[d + 1] = p.out[d];
+    cur = dst;
   }
-  PISCO_KERNEL(h, k_rss, dim3(ceil_div(p.Nout, 256)), dim3(256), 0, maps_out, Q, p.Nout);
+  const long long rows = 1LL * p.out[0] * p.out[1];
+  st = interp_x_rss(h, cur, maps_out, Ms[2], Q, rows, p.lr[2], p.out[2]);
+  if (st == PISCO_ERR_UNSUPPORTED) {
+    if ((st = axis_transform(h, cur, maps_out, sh, 3, p.out[2], Ms[2], true))) return st;
+    PISCO_KERNEL(h, k_rss, dim3(ceil_div(p.Nout, 256)), dim3(256), 0, maps_out, Q, p.Nout);
+  } else if (st) {
+    return st;
+  }
   return PISCO_OK;
 }
 

@@ -166,6 +166,22 @@ size_t layout_gx(const Plan& p, int b, void* ws, GxWs* o) {
   return c.used + 256;
 }
 
+int interp_order(const Plan& p, int ord[3]) {
+  // the passes of a separable interpolation commute.  x comes last (that pass
+  // carries the coil normalisation); of z and y the axis that grows less goes
+  // first, which keeps the intermediates small (ties: z first).
+  int n = 0;
+  if (p.D == 3) {
+    const bool zfirst = 1LL * p.out[0] * p.lr[1] <= 1LL * p.out[1] * p.lr[0];
+    ord[n++] = zfirst ? 0 : 1;
+    ord[n++] = zfirst ? 1 : 0;
+  } else {
+    ord[n++] = 1;
+  }
+  ord[n++] = 2;
+  return n;
+}
+
 size_t layout_maps(const Plan& p, void* ws, MapsWs* o) {
   Carver c(ws);
   MapsWs w{};
@@ -176,11 +192,17 @@ size_t layout_maps(const Plan& p, void* ws, MapsWs* o) {
   w.rtB = c.take<double2>(r1 > r2 ? r1 : r2);
   w.m = c.take<double2>(p.Nlr);
   w.pmax = c.take<double>((p.Nlr + 255) / 256 + 1);
-  // largest intermediate of the interpolation passes (lr -> out in x, y, z order)
-  const size_t a = size_t(p.Q) * p.lr[0] * p.lr[1] * p.out[2];
-  const size_t b = size_t(p.Q) * p.lr[0] * p.out[1] * p.out[2];
-  w.tmpA = c.take<float2>(a > b ? a : b);
-  w.tmpB = c.take<float2>(a > b ? a : b);
+  // intermediates of the interpolation passes, in the order interp_order gives
+  int ord[3];
+  const int n = interp_order(p, ord);
+  size_t ext[3] = {size_t(p.lr[0]), size_t(p.lr[1]), size_t(p.lr[2])};
+  size_t inter[2] = {0, 0};
+  for (int i = 0; i + 1 < n; ++i) {
+    ext[ord[i]] = size_t(p.out[ord[i]]);
+    inter[i] = size_t(p.Q) * ext[0] * ext[1] * ext[2];
+  }
+  w.tmpA = c.take<float2>(inter[0]);
+  w.tmpB = c.take<float2>(inter[1]);
   w.cref = c.take<float2>(size_t(p.Q) * p.Nlr);
   if (o) *o = w;
   return c.used + 256;

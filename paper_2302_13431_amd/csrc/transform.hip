@@ -162,22 +162,25 @@ __global__ void __launch_bounds__(256) k_axis_last(const TI* __restrict__ in,
 // FP32 transforms on the matrix cores (v_mfma_f32_16x16x4f32, twice the
 // FP32 vector rate without packed operations), for the passes with many
 // outputs per input (the interpolation to the output grid, G(x) on the
-// low-resolution grid).  A workgroup forms a 64 x 64 tile of the product
+// low-resolution grid).  A workgroup forms 64 x 64 tiles of the product
 // C = M X over K = nin (rounded up to 4, zeros past nin) staged in LDS, four
-// waves of 16 x 64; complex products in the three-multiplication form (T1
-// = Ar Br, T2 = Ai Bi, T3 = (Ar + Ai)(Br + Bi); Re = T1 - T2, Im = T3 - T1 -
-// T2).  Operand lanes of the 16 x 16 x 4 shape: lane l supplies A row l % 16
-// and B column l % 16 at k = l / 16; accumulator element v of lane l is row
-// 4 (l / 16) + v, column l % 16.
-//   k_axis_mm_cols (inner >= 64): X[k][col] = in[outer][k][inner0 + col],
+// waves of 16 x 64.  A complex M takes the three-multiplication form (T1 =
+// Ar Br, T2 = Ai Bi, T3 = (Ar + Ai)(Br + Bi); Re = T1 - T2, Im = T3 - T1 -
+// T2); a real M (kReal: its imaginary parts are ignored) two products, Re =
+// M Xr and Im = M Xi.  Operand lanes of the 16 x 16 x 4 shape: lane l
+// supplies A row l % 16 and B column l % 16 at k = l / 16; accumulator
+// element v of lane l is row 4 (l / 16) + v, column l % 16.
+//   k_axis_mm_cols (inner > 1): X[k][col] = in[outer][k][inner0 + col],
 //     A = M (64 outputs), B = X; the tile's outputs are written along inner.
 //   k_axis_mm_lines (inner = 1): A = the lines' inputs (64 lines), B = M^T;
 //     each line's 64 outputs are written along the line.
 constexpr int kMmK = 64;  // nin at most (K padded to a multiple of 4)
 
+// As[r][k] (row stride lda); Bs[k][c] (bt == false, stride ldb) or Bs[c][k].
+// With kReal, M is A when bt == false (column tiles) and B when bt == true.
+template <bool kReal>
 __device__ inline void mm_tile(const float2* As, int lda, const float2* Bs, int ldb, bool bt,
                                int K4, f32x4 (&t1)[4], f32x4 (&t2)[4], f32x4 (&t3)[4]) {
-  // As[r][k] (row stride lda); Bs[k][c] (bt == false, stride ldb) or Bs[c][k]
   const int l = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int li = l & 15, kq = l >> 4;
 #pragma unroll
@@ -188,11 +191,24 @@ __device__ inline void mm_tile(const float2* As, int lda, const float2* Bs, int 
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const float2 b = bt ? Bs[(16 * j + li) * ldb + k] : Bs[k * ldb + 16 * j + li];
-      t1[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b.x, t1[j], 0, 0, 0);
-      t2[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, b.y, t2[j], 0, 0, 0);
-      t3[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x + a.y, b.x + b.y, t3[j], 0, 0, 0);
+      if (!kReal) {
+        t1[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b.x, t1[j], 0, 0, 0);
+        t2[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, b.y, t2[j], 0, 0, 0);
+        t3[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x + a.y, b.x + b.y, t3[j], 0, 0, 0);
+      } else if (!bt) {  // A = M real
+        t1[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b.x, t1[j], 0, 0, 0);
+        t2[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b.y, t2[j], 0, 0, 0);
+      } else {  // B = M^T real
+        t1[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b.x, t1[j], 0, 0, 0);
+        t2[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, b.x, t2[j], 0, 0, 0);
+      }
     }
   }
+}
+
+template <bool kReal>
+__device__ inline float2 mm_result(const f32x4& t1, const f32x4& t2, const f32x4& t3, int v) {
+  return kReal ? make_float2(t1[v], t2[v]) : make_float2(t1[v] - t2[v], t3[v] - t1[v] - t2[v]);
 }
 
 // Ms[o][k] = M[o0 + o][k] (zeros past nout and nin), row stride kMmK + 1
@@ -205,29 +221,41 @@ __device__ inline void mm_stage_m(float2* Ms, const float2* __restrict__ M, int 
   }
 }
 
-// kMmTiles column tiles per workgroup, one after another: M staged once, the
+// kMmTiles input tiles per workgroup, one after another: M staged once, the
 // next tile's inputs loaded into registers while the current one is
-// multiplied
+// multiplied.  Both kernels take a 1-D grid whose logical workgroup index
+// (XCD-contiguous) runs fastest over the 64-output tiles: the workgroups that
+// read one input tile run together on one XCD, so the tile is fetched from
+// HBM once.
 constexpr int kMmTiles = 8;
 
+// The input tiles of k_axis_mm_cols run over (outer index, 64 columns of
+// inner) with the column tile fastest, so that a short inner axis still gives
+// a workgroup kMmTiles tiles.
+template <bool kReal>
 __global__ void __launch_bounds__(256) k_axis_mm_cols(const float2* __restrict__ in,
                                                       float2* __restrict__ out,
-                                                      const float2* __restrict__ M, int nin,
-                                                      int nout, int inner) {
+                                                      const float2* __restrict__ M,
+                                                      long long outer, int nin, int nout,
+                                                      int inner) {
   constexpr int XS = 64 + 1;  // Xs row stride
   constexpr int kPer = kMmK * 64 / 256;  // staged elements per thread
   __shared__ float2 Ms[64 * (kMmK + 1)];
   __shared__ float2 Xs[kMmK * XS];
   const int K4 = (nin + 3) & ~3;
-  const int o0 = blockIdx.y * 64;
-  const long long ou = blockIdx.z;
-  const int tiles = (inner + 63) / 64;
-  const int tb = blockIdx.x * kMmTiles, te = tiles < tb + kMmTiles ? tiles : tb + kMmTiles;
+  const int ctiles = (inner + 63) / 64;
+  const long long tiles = outer * ctiles;
+  const int otiles = (nout + 63) / 64;
+  const long long lb = xcd_block(blockIdx.x, gridDim.x);
+  const int o0 = int(lb % otiles) * 64;
+  const long long tb = lb / otiles * kMmTiles;
+  const long long te = tiles < tb + kMmTiles ? tiles : tb + kMmTiles;
   mm_stage_m(Ms, M, o0, nout, nin, K4);
-  const float2* src = in + size_t(ou) * nin * inner;
   float2 x[kPer];
-  auto load = [&](int tile) {
-    const int c0 = tile * 64;
+  auto load = [&](long long tile) {
+    const long long ou = tile / ctiles;
+    const int c0 = int(tile - ou * ctiles) * 64;
+    const float2* src = in + size_t(ou) * nin * inner;
 #pragma unroll
     for (int u = 0; u < kPer; ++u) {
       const int e = threadIdx.x + 256 * u, k = e >> 6, c = e & 63;
@@ -235,9 +263,8 @@ __global__ void __launch_bounds__(256) k_axis_mm_cols(const float2* __restrict__
     }
   };
   const int l = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  float2* dst = out + size_t(ou) * nout * inner;
   if (tb < te) load(tb);
-  for (int tile = tb; tile < te; ++tile) {
+  for (long long tile = tb; tile < te; ++tile) {
     __syncthreads();  // the previous tile's products are done with Xs
 #pragma unroll
     for (int u = 0; u < kPer; ++u) {
@@ -247,74 +274,210 @@ __global__ void __launch_bounds__(256) k_axis_mm_cols(const float2* __restrict__
     __syncthreads();
     if (tile + 1 < te) load(tile + 1);
     f32x4 t1[4], t2[4], t3[4];
-    mm_tile(Ms, kMmK + 1, Xs, XS, false, K4, t1, t2, t3);
-    const int c0 = tile * 64;
+    mm_tile<kReal>(Ms, kMmK + 1, Xs, XS, false, K4, t1, t2, t3);
+    const long long ou = tile / ctiles;
+    const int c0 = int(tile - ou * ctiles) * 64;
+    float2* dst = out + size_t(ou) * nout * inner;
 #pragma unroll
     for (int j = 0; j < 4; ++j)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int o = o0 + 16 * wv + 4 * (l >> 4) + v, c = c0 + 16 * j + (l & 15);
-        if (o < nout && c < inner)
-          dst[size_t(o) * inner + c] =
-              make_float2(t1[j][v] - t2[j][v], t3[j][v] - t1[j][v] - t2[j][v]);
+        if (o < nout && c < inner) dst[size_t(o) * inner + c] = mm_result<kReal>(t1[j], t2[j], t3[j], v);
       }
   }
 }
 
+template <bool kReal>
 __global__ void __launch_bounds__(256) k_axis_mm_lines(const float2* __restrict__ in,
                                                        float2* __restrict__ out,
                                                        const float2* __restrict__ M,
                                                        long long lines, int nin, int nout) {
+  constexpr int kPer = kMmK * 64 / 256;  // staged elements per thread
   __shared__ float2 Ms[64 * (kMmK + 1)];
   __shared__ float2 Xs[64 * (kMmK + 1)];
   const int K4 = (nin + 3) & ~3;
-  const long long l0 = 1LL * blockIdx.x * 64;
-  const int o0 = blockIdx.y * 64;
+  const int otiles = (nout + 63) / 64;
+  const long long tiles = (lines + 63) / 64;
+  const long long lb = xcd_block(blockIdx.x, gridDim.x);
+  const int o0 = int(lb % otiles) * 64;
+  const long long tb = lb / otiles * kMmTiles;
+  const long long te = tiles < tb + kMmTiles ? tiles : tb + kMmTiles;
   mm_stage_m(Ms, M, o0, nout, nin, K4);
-  for (int e = threadIdx.x; e < 64 * K4; e += 256) {
-    const int r = e / K4, k = e - r * K4;
-    Xs[r * (kMmK + 1) + k] = k < nin && l0 + r < lines ? in[size_t(l0 + r) * nin + k]
-                                                       : make_float2(0.f, 0.f);
+  // element u of this thread: line r, input k of a 64-line tile (r < 64 for
+  // e < 64 K4), at offset r nin + k from the tile's first line
+  int off[kPer], lds[kPer];
+#pragma unroll
+  for (int u = 0; u < kPer; ++u) {
+    const int e = threadIdx.x + 256 * u, r = e / K4, k = e - r * K4;
+    const bool use = e < 64 * K4;
+    lds[u] = use ? r * (kMmK + 1) + k : -1;
+    off[u] = use && k < nin ? r * nin + k : -1;
   }
-  __syncthreads();
-  f32x4 t1[4], t2[4], t3[4];
-  mm_tile(Xs, kMmK + 1, Ms, kMmK + 1, true, K4, t1, t2, t3);
+  float2 x[kPer];
+  auto load = [&](long long tile) {
+    const long long l0 = tile * 64;
+    const float2* src = in + size_t(l0) * nin;
+    const long long lim = (lines - l0) * nin;  // elements of this tile in range
+#pragma unroll
+    for (int u = 0; u < kPer; ++u)
+      x[u] = off[u] >= 0 && off[u] < lim ? src[off[u]] : make_float2(0.f, 0.f);
+  };
   const int l = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (tb < te) load(tb);
+  for (long long tile = tb; tile < te; ++tile) {
+    __syncthreads();  // the previous tile's products are done with Xs
 #pragma unroll
-  for (int j = 0; j < 4; ++j)
+    for (int u = 0; u < kPer; ++u)
+      if (lds[u] >= 0) Xs[lds[u]] = x[u];
+    __syncthreads();
+    if (tile + 1 < te) load(tile + 1);
+    f32x4 t1[4], t2[4], t3[4];
+    mm_tile<kReal>(Xs, kMmK + 1, Ms, kMmK + 1, true, K4, t1, t2, t3);
+    const long long l0 = tile * 64;
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const long long r = l0 + 16 * wv + 4 * (l >> 4) + v;
-      const int o = o0 + 16 * j + (l & 15);
-      if (r < lines && o < nout)
-        out[size_t(r) * nout + o] =
-            make_float2(t1[j][v] - t2[j][v], t3[j][v] - t1[j][v] - t2[j][v]);
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const long long r = l0 + 16 * wv + 4 * (l >> 4) + v;
+        const int o = o0 + 16 * j + (l & 15);
+        if (r < lines && o < nout) out[size_t(r) * nout + o] = mm_result<kReal>(t1[j], t2[j], t3[j], v);
+      }
+  }
+}
+
+// The last interpolation pass (along x, real sinc matrix) with the coil
+// normalisation c[:, v] /= ||c[:, v]||_2 fused in: in = [Q][rows][nin], out =
+// [Q][rows][nout].  A 64-line tile holds G = 64 / Q row indices times all Q
+// coils (local line g Q + q), so every output voxel of the tile has its Q
+// coil values in the tile.  After the products the squared magnitudes go
+// through LDS (over Xs, free until the next tile is staged); one thread per
+// (g, column) sums them over q in coil order, as the separate normalisation
+// would, and the lanes scale their values by 1 / sqrt(sum) (a zero sum leaves
+// the values as they are).
+__global__ void __launch_bounds__(256) k_interp_x_rss(const float2* __restrict__ in,
+                                                      float2* __restrict__ out,
+                                                      const float2* __restrict__ M, int Q,
+                                                      long long rows, int nin, int nout) {
+  constexpr int kPer = kMmK * 64 / 256;  // staged elements per thread
+  __shared__ float2 Ms[64 * (kMmK + 1)];
+  __shared__ float2 Xs[64 * (kMmK + 1)];
+  float* ssq = reinterpret_cast<float*>(Xs);  // [64 lines][64 columns]
+  float* inv = ssq + 64 * 64;                 // [G][64 columns]
+  const int K4 = (nin + 3) & ~3;
+  const int G = 64 / Q;
+  const int otiles = (nout + 63) / 64;
+  const long long tiles = (rows + G - 1) / G;
+  const long long lb = xcd_block(blockIdx.x, gridDim.x);
+  const int o0 = int(lb % otiles) * 64;
+  const long long tb = lb / otiles * kMmTiles;
+  const long long te = tiles < tb + kMmTiles ? tiles : tb + kMmTiles;
+  mm_stage_m(Ms, M, o0, nout, nin, K4);
+  // element u of this thread: local line r = g Q + q, input k; its source
+  // is line q rows + (tile G + g), at offset off[u] + tile G nin
+  int lds[kPer], gu[kPer];
+  long long off[kPer];
+#pragma unroll
+  for (int u = 0; u < kPer; ++u) {
+    const int e = threadIdx.x + 256 * u, r = e / K4, k = e - r * K4;
+    const bool use = e < 64 * K4 && r < G * Q;
+    const int g = r / Q, q = r - g * Q;
+    lds[u] = e < 64 * K4 ? r * (kMmK + 1) + k : -1;
+    gu[u] = use && k < nin ? g : -1;
+    off[u] = (1LL * q * rows + g) * nin + k;
+  }
+  float2 x[kPer];
+  auto load = [&](long long tile) {
+    const long long r0 = tile * G;
+#pragma unroll
+    for (int u = 0; u < kPer; ++u)
+      x[u] = gu[u] >= 0 && r0 + gu[u] < rows ? in[off[u] + r0 * nin] : make_float2(0.f, 0.f);
+  };
+  const int l = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (tb < te) load(tb);
+  for (long long tile = tb; tile < te; ++tile) {
+    __syncthreads();  // the previous tile is done with Xs (products and sums)
+#pragma unroll
+    for (int u = 0; u < kPer; ++u)
+      if (lds[u] >= 0) Xs[lds[u]] = x[u];
+    __syncthreads();
+    if (tile + 1 < te) load(tile + 1);
+    f32x4 t1[4], t2[4], t3[4];
+    mm_tile<true>(Xs, kMmK + 1, Ms, kMmK + 1, true, K4, t1, t2, t3);
+    __syncthreads();  // every wave is done reading Xs
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        ssq[(16 * wv + 4 * (l >> 4) + v) * 64 + 16 * j + (l & 15)] =
+            cabs2(mm_result<true>(t1[j], t2[j], t3[j], v));
+    __syncthreads();
+    for (int e = threadIdx.x; e < G * 64; e += 256) {
+      const int g = e >> 6, c = e & 63;
+      float s = 0.f;
+      for (int q = 0; q < Q; ++q) s += ssq[(g * Q + q) * 64 + c];
+      inv[e] = s > 0.f ? 1.f / sqrtf(s) : 1.f;
     }
+    __syncthreads();
+    const long long r0 = tile * G;
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = 16 * wv + 4 * (l >> 4) + v, c = 16 * j + (l & 15);
+        const int g = r / Q, q = r - g * Q;
+        if (r < G * Q && r0 + g < rows && o0 + c < nout)
+          out[(size_t(q) * rows + r0 + g) * nout + o0 + c] =
+              cscale(mm_result<true>(t1[j], t2[j], t3[j], v), inv[g * 64 + c]);
+      }
+  }
+}
+
+pisco_status_t interp_x_rss(Handle* h, const float2* in, float2* out, const float2* M, int Q,
+                            long long rows, int nin, int nout) {
+  if (Q < 1 || Q > 64 || nin < 1 || nin > kMmK || nout < 1 || rows < 1)
+    return PISCO_ERR_UNSUPPORTED;
+  const long long tiles = (rows + 64 / Q - 1) / (64 / Q);
+  const long long blocks = 1LL * ceil_div(nout, 64) * ceil_div(tiles, kMmTiles);
+  if (blocks >= (1LL << 24)) return PISCO_ERR_UNSUPPORTED;
+  PISCO_KERNEL(h, k_interp_x_rss, dim3(unsigned(blocks)), dim3(256), 0, in, out, M, Q, rows, nin,
+               nout);
+  return PISCO_OK;
 }
 
 template <class TI, class TO>
 static pisco_status_t axis_impl(Handle* h, const TI* in, TO* out, const int shape_in[4],
-                                int axis, int nout, const TO* M) {
+                                int axis, int nout, const TO* M, bool real_m) {
   long long outer = shape_in[0];
   for (int d = 1; d < axis; ++d) outer *= shape_in[d];
   long long inner = 1;
   for (int d = axis + 1; d < 4; ++d) inner *= shape_in[d];
   const int nin = shape_in[axis];
+  // the matrix-core kernels: FP32, at most kMmK inputs, enough work to fill
+  // the chip, and column tiles at least half used
+  const long long mm_blocks =
+      ceil_div(nout, 64) * ceil_div(inner == 1 ? ceil_div(outer, 64) : outer * ceil_div(inner, 64),
+                                    kMmTiles);
   if (sizeof(TI) == sizeof(float2) && sizeof(TO) == sizeof(float2) && nin <= kMmK &&
-      outer * inner * nout >= (1LL << 24) &&
-      (inner == 1 || (inner >= 64 && outer <= 65535))) {
-    // large FP32 passes on the matrix cores
+      outer * inner * nout >= (1LL << 22) && (inner == 1 || inner >= 32) &&
+      mm_blocks < (1LL << 24)) {
     const float2* fi = reinterpret_cast<const float2*>(in);
     float2* fo = reinterpret_cast<float2*>(out);
     const float2* fm = reinterpret_cast<const float2*>(M);
     if (inner == 1) {
-      PISCO_KERNEL(h, k_axis_mm_lines, dim3(unsigned(ceil_div(outer, 64)), ceil_div(nout, 64)),
-                   dim3(256), 0, fi, fo, fm, outer, nin, nout);
+      if (real_m)
+        PISCO_KERNEL(h, k_axis_mm_lines<true>, dim3(unsigned(mm_blocks)), dim3(256), 0, fi, fo,
+                     fm, outer, nin, nout);
+      else
+        PISCO_KERNEL(h, k_axis_mm_lines<false>, dim3(unsigned(mm_blocks)), dim3(256), 0, fi, fo,
+                     fm, outer, nin, nout);
     } else {
-      PISCO_KERNEL(h, k_axis_mm_cols,
-                   dim3(unsigned(ceil_div(ceil_div(inner, 64), kMmTiles)), ceil_div(nout, 64),
-                        unsigned(outer)),
-                   dim3(256), 0, fi, fo, fm, nin, nout, int(inner));
+      if (real_m)
+        PISCO_KERNEL(h, k_axis_mm_cols<true>, dim3(unsigned(mm_blocks)), dim3(256), 0, fi, fo, fm,
+                     outer, nin, nout, int(inner));
+      else
+        PISCO_KERNEL(h, k_axis_mm_cols<false>, dim3(unsigned(mm_blocks)), dim3(256), 0, fi, fo,
+                     fm, outer, nin, nout, int(inner));
     }
     return PISCO_OK;
   }
@@ -353,18 +516,18 @@ static pisco_status_t axis_impl(Handle* h, const TI* in, TO* out, const int shap
 }
 
 pisco_status_t axis_transform(Handle* h, const float2* in, float2* out, const int shape_in[4],
-                              int axis, int nout, const float2* M) {
-  return axis_impl<float2, float2>(h, in, out, shape_in, axis, nout, M);
+                              int axis, int nout, const float2* M, bool real_m) {
+  return axis_impl<float2, float2>(h, in, out, shape_in, axis, nout, M, real_m);
 }
 
 pisco_status_t axis_transform64(Handle* h, const float2* in, double2* out,
                                 const int shape_in[4], int axis, int nout, const double2* M) {
-  return axis_impl<float2, double2>(h, in, out, shape_in, axis, nout, M);
+  return axis_impl<float2, double2>(h, in, out, shape_in, axis, nout, M, false);
 }
 
 pisco_status_t axis_transform64(Handle* h, const double2* in, double2* out,
                                 const int shape_in[4], int axis, int nout, const double2* M) {
-  return axis_impl<double2, double2>(h, in, out, shape_in, axis, nout, M);
+  return axis_impl<double2, double2>(h, in, out, shape_in, axis, nout, M, false);
 }
 
 // ------------------------------------------------------------------ plan-constant tables
@@ -435,22 +598,19 @@ __device__ void sinc_entry(const TableJob& j, int idx, double* re, double* im) {
   const bool split = (nin % 2 == 0) && nout > nin;
   const double y = double(o - nout / 2) / double(nout);
   const double x = double(a - nin / 2) / double(nin);
-  double sr = 0.0, si = 0.0;
+  // The frequencies run over a symmetric range (odd nin, or even nin with the
+  // Nyquist term split in halves at -nin/2 and +nin/2), so the sine terms
+  // cancel in pairs; for even nin with nout = nin the grids coincide and the
+  // sum is nin times a Kronecker delta.  The kernel is real: only the cosine
+  // sum is formed, and the interpolation passes take the real-matrix products.
+  double sr = 0.0;
   for (int k = kmin; k <= kmax; ++k) {
-    double sn, cs;
-    sincospi(2.0 * double(k) * (y - x), &sn, &cs);
     const double w = (split && k == kmin) ? 0.5 : 1.0;
-    sr += w * cs;
-    si += w * sn;
+    sr += w * cospi(2.0 * double(k) * (y - x));
   }
-  if (split) {
-    double sn, cs;
-    sincospi(2.0 * double(nin / 2) * (y - x), &sn, &cs);
-    sr += 0.5 * cs;
-    si += 0.5 * sn;
-  }
+  if (split) sr += 0.5 * cospi(2.0 * double(nin / 2) * (y - x));
   *re = sr / nin;
-  *im = si / nin;
+  *im = 0.0;
 }
 
 __global__ void __launch_bounds__(256) k_build_tables(TableJobs jobs) {
