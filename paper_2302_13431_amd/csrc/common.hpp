@@ -407,6 +407,13 @@ pisco_status_t axis_transform(Handle* h, const float2* in, float2* out,
 pisco_status_t interp_x_rss(Handle* h, const float2* in, float2* out, const float2* M, int Q,
                             long long rows, int nin, int nout);
 
+// axis_transform whose outer index is the packed Hermitian pair of a Q x Q
+// matrix, stored as G = bound I - y (diagonal pairs real).  Only on the
+// matrix-core column path; PISCO_ERR_UNSUPPORTED (nothing launched) otherwise.
+pisco_status_t axis_transform_gx(Handle* h, const float2* in, float2* out,
+                                 const int shape_in[4], int axis, int nout, const float2* M,
+                                 int Q, float bound);
+
 // FP64 variants of axis_transform (input FP32 or FP64, output and matrix FP64)
 pisco_status_t axis_transform64(Handle* h, const float2* in, double2* out,
                                 const int shape_in[4], int axis, int nout, const double2* M);

@@ -51,7 +51,10 @@ __global__ void __launch_bounds__(256) k_herk(const float2* __restrict__ F,
   __shared__ float2 tile[8 * 256];
   const int t = threadIdx.x;
   const int fl = t % FT, q = t / FT;
-  const int f = blockIdx.x * FT + fl;
+  // XCD-contiguous frequency blocks: the blocks that share a 128-byte line
+  // of F run on one XCD (one L2)
+  const int fb = int(xcd_block(blockIdx.x, gridDim.x));
+  const int f = fb * FT + fl;
   const bool active = q < Q && f < nK;
   const int rs = counts[0];
   float2 acc[kMaxQ];
@@ -61,7 +64,7 @@ __global__ void __launch_bounds__(256) k_herk(const float2* __restrict__ F,
     const int rc = rs - r0 < 8 ? rs - r0 : 8;
     for (int e = t; e < rc * Q * FT; e += 256) {
       const int rr = e / (Q * FT), rem = e - rr * Q * FT, qq = rem / FT, ff = rem - qq * FT;
-      const int gf = blockIdx.x * FT + ff;
+      const int gf = fb * FT + ff;
       tile[e] = gf < nK ? F[(size_t(r0 + rr) * Q + qq) * nK + gf] : make_float2(0.f, 0.f);
     }
     __syncthreads();
@@ -182,7 +185,9 @@ __global__ void __launch_bounds__(256) k_herk_mfma(const float2* __restrict__ F,
   __shared__ float2 tile[kR * kMaxQ * kFP];
   const int t = threadIdx.x, wv = t >> 6, l = t & 63;
   const int li = l & 15, kg = l >> 4;
-  const int f0 = blockIdx.x * kFB;
+  // XCD-contiguous frequency blocks: the four blocks that share a 128-byte
+  // line of F run on one XCD (one L2), so the line is fetched once
+  const int f0 = int(xcd_block(blockIdx.x, gridDim.x)) * kFB;
   const int rs = counts[0];
   const int nqb = Q > 16 ? 2 : 1;
   f32x4 cr[kFW][3], ci[kFW][3];
@@ -331,16 +336,31 @@ pisco_status_t run_gx(Handle* h, const Plan& p, const Tables& t, int b, int prec
     if ((st = chain(h, bufA, w.Klag, shk, 2, p.B[1], M3[1]))) return st;
   }
   // 4. evaluate on the low-res grid: [P][Bz][By][Bx] -> [P][lr0][lr1][lr2]
+  // (the last pass stores G = |Lambda| I - G^s where it runs on the matrix
+  // cores; otherwise a pass of its own does)
   int shl[4] = {P, p.B[0], p.B[1], p.B[2]};
+  const float bound = float(p.L);
+  const float2* last_in = nullptr;
+  int last_axis = 0;
   if (p.D == 3) {
     if ((st = chain(h, w.Klag, bufA, shl, 3, p.lr[2], M4[2]))) return st;
     if ((st = chain(h, bufA, bufB, shl, 2, p.lr[1], M4[1]))) return st;
-    if ((st = chain(h, bufB, G, shl, 1, p.lr[0], M4[0]))) return st;
+    last_in = bufB;
+    last_axis = 1;
   } else {
     if ((st = chain(h, w.Klag, bufA, shl, 3, p.lr[2], M4[2]))) return st;
-    if ((st = chain(h, bufA, G, shl, 2, p.lr[1], M4[1]))) return st;
+    last_in = bufA;
+    last_axis = 2;
   }
-  PISCO_KERNEL(h, k_gx_finish, dim3(ceil_div(1LL * P * p.Nlr, 256)), dim3(256), 0, G, Q, p.Nlr, float(p.L));
+  const int last = last_axis - 1;  // grid dimension of the last pass
+  st = axis_transform_gx(h, last_in, G, shl, last_axis, p.lr[last], M4[last], Q, bound);
+  if (st == PISCO_ERR_UNSUPPORTED) {
+    if ((st = axis_transform(h, last_in, G, shl, last_axis, p.lr[last], M4[last]))) return st;
+    PISCO_KERNEL(h, k_gx_finish, dim3(ceil_div(1LL * P * p.Nlr, 256)), dim3(256), 0, G, Q, p.Nlr,
+                 bound);
+  } else if (st) {
+    return st;
+  }
   return PISCO_OK;
 }
 

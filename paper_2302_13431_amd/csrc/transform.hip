@@ -232,12 +232,16 @@ constexpr int kMmTiles = 8;
 // The input tiles of k_axis_mm_cols run over (outer index, 64 columns of
 // inner) with the column tile fastest, so that a short inner axis still gives
 // a workgroup kMmTiles tiles.
-template <bool kReal>
+// kEpi = 1: the outer index is a packed Hermitian pair of a Q x Q matrix
+// (row-major upper triangle) and the result y is stored as bound - Re y (a
+// diagonal pair, imaginary part zero) or -y (off-diagonal): G = |Lambda| I -
+// G^s without a pass of its own.
+template <bool kReal, int kEpi>
 __global__ void __launch_bounds__(256) k_axis_mm_cols(const float2* __restrict__ in,
                                                       float2* __restrict__ out,
                                                       const float2* __restrict__ M,
                                                       long long outer, int nin, int nout,
-                                                      int inner) {
+                                                      int inner, int epi_q, float epi_bound) {
   constexpr int XS = 64 + 1;  // Xs row stride
   constexpr int kPer = kMmK * 64 / 256;  // staged elements per thread
   __shared__ float2 Ms[64 * (kMmK + 1)];
@@ -278,12 +282,19 @@ __global__ void __launch_bounds__(256) k_axis_mm_cols(const float2* __restrict__
     const long long ou = tile / ctiles;
     const int c0 = int(tile - ou * ctiles) * 64;
     float2* dst = out + size_t(ou) * nout * inner;
+    bool diag = false;
+    if (kEpi == 1) {  // pair ou is diagonal when it opens its row's block
+      long long base = 0;
+      for (int p = 0; p < epi_q && base <= ou; base += epi_q - p, ++p) diag = diag || base == ou;
+    }
 #pragma unroll
     for (int j = 0; j < 4; ++j)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int o = o0 + 16 * wv + 4 * (l >> 4) + v, c = c0 + 16 * j + (l & 15);
-        if (o < nout && c < inner) dst[size_t(o) * inner + c] = mm_result<kReal>(t1[j], t2[j], t3[j], v);
+        float2 y = mm_result<kReal>(t1[j], t2[j], t3[j], v);
+        if (kEpi == 1) y = diag ? make_float2(epi_bound - y.x, 0.f) : make_float2(-y.x, -y.y);
+        if (o < nout && c < inner) dst[size_t(o) * inner + c] = y;
       }
   }
 }
@@ -447,7 +458,8 @@ pisco_status_t interp_x_rss(Handle* h, const float2* in, float2* out, const floa
 
 template <class TI, class TO>
 static pisco_status_t axis_impl(Handle* h, const TI* in, TO* out, const int shape_in[4],
-                                int axis, int nout, const TO* M, bool real_m) {
+                                int axis, int nout, const TO* M, bool real_m, int epi = 0,
+                                int epi_q = 0, float epi_bound = 0.f) {
   long long outer = shape_in[0];
   for (int d = 1; d < axis; ++d) outer *= shape_in[d];
   long long inner = 1;
@@ -465,6 +477,7 @@ static pisco_status_t axis_impl(Handle* h, const TI* in, TO* out, const int shap
     float2* fo = reinterpret_cast<float2*>(out);
     const float2* fm = reinterpret_cast<const float2*>(M);
     if (inner == 1) {
+      if (epi != 0) return PISCO_ERR_UNSUPPORTED;
       if (real_m)
         PISCO_KERNEL(h, k_axis_mm_lines<true>, dim3(unsigned(mm_blocks)), dim3(256), 0, fi, fo,
                      fm, outer, nin, nout);
@@ -472,15 +485,21 @@ static pisco_status_t axis_impl(Handle* h, const TI* in, TO* out, const int shap
         PISCO_KERNEL(h, k_axis_mm_lines<false>, dim3(unsigned(mm_blocks)), dim3(256), 0, fi, fo,
                      fm, outer, nin, nout);
     } else {
-      if (real_m)
-        PISCO_KERNEL(h, k_axis_mm_cols<true>, dim3(unsigned(mm_blocks)), dim3(256), 0, fi, fo, fm,
-                     outer, nin, nout, int(inner));
+      if (epi == 1 && !real_m)
+        PISCO_KERNEL(h, (k_axis_mm_cols<false, 1>), dim3(unsigned(mm_blocks)), dim3(256), 0, fi,
+                     fo, fm, outer, nin, nout, int(inner), epi_q, epi_bound);
+      else if (epi != 0)
+        return PISCO_ERR_UNSUPPORTED;
+      else if (real_m)
+        PISCO_KERNEL(h, (k_axis_mm_cols<true, 0>), dim3(unsigned(mm_blocks)), dim3(256), 0, fi,
+                     fo, fm, outer, nin, nout, int(inner), 0, 0.f);
       else
-        PISCO_KERNEL(h, k_axis_mm_cols<false>, dim3(unsigned(mm_blocks)), dim3(256), 0, fi, fo,
-                     fm, outer, nin, nout, int(inner));
+        PISCO_KERNEL(h, (k_axis_mm_cols<false, 0>), dim3(unsigned(mm_blocks)), dim3(256), 0, fi,
+                     fo, fm, outer, nin, nout, int(inner), 0, 0.f);
     }
     return PISCO_OK;
   }
+  if (epi != 0) return PISCO_ERR_UNSUPPORTED;
   if (inner == 1) {
     int lpb = nout >= 256 ? 1 : 256 / nout;
     const int fit = int((64 * 1024) / (size_t(nin) * sizeof(TO)));  // staged lines in 64 KB
@@ -518,6 +537,15 @@ static pisco_status_t axis_impl(Handle* h, const TI* in, TO* out, const int shap
 pisco_status_t axis_transform(Handle* h, const float2* in, float2* out, const int shape_in[4],
                               int axis, int nout, const float2* M, bool real_m) {
   return axis_impl<float2, float2>(h, in, out, shape_in, axis, nout, M, real_m);
+}
+
+pisco_status_t axis_transform_gx(Handle* h, const float2* in, float2* out,
+                                 const int shape_in[4], int axis, int nout, const float2* M,
+                                 int Q, float bound) {
+  long long outer = shape_in[0];
+  for (int d = 1; d < axis; ++d) outer *= shape_in[d];
+  if (Q < 1 || outer != 1LL * Q * (Q + 1) / 2) return PISCO_ERR_UNSUPPORTED;
+  return axis_impl<float2, float2>(h, in, out, shape_in, axis, nout, M, false, 1, Q, bound);
 }
 
 pisco_status_t axis_transform64(Handle* h, const float2* in, double2* out,
