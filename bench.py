@@ -110,7 +110,8 @@ KERNEL_SOURCES = {"k_tp_zfused": "toeplitz.hip", "k_tp_pointwise": "toeplitz.hip
                   "k_chol": "nullspace.hip", "k_tri_inv": "nullspace.hip",
                   "k_gemm_tn": "nullspace.hip",
                   "k_gemm_nn": "nullspace.hip", "k_herk": "gx.hip", "k_power": "eig.hip",
-                  "k_gather": "gram.hip", "k_rss": "maps.hip"}
+                  "k_gather": "gram.hip", "k_inv_first": "gram.hip", "k_rss": "maps.hip",
+                  "k_interp_x_rss": "transform.hip", "k_herk_mfma": "gx.hip"}
 
 
 def measured_traffic(kernel: str, workload: str):
