@@ -239,6 +239,109 @@ __global__ void __launch_bounds__(256) k_inv_first(const float2* __restrict__ S,
       out[(size_t(pair) * B + m) * inner + in_i] = r[ln * g.L + lag_position(m, B, F)];
 }
 
+// Value of lane (lane ^ h) of the wave, h a power of two below 64, on the
+// ALU's data-parallel moves where one exists: quad permutations [1,0,3,2]
+// (h = 1) and [2,3,0,1] (h = 2); h = 8 a rotation by 8 within 16-lane rows;
+// h = 4 rotations by 12 and 4 within the row (lane + 4 and lane - 4), taken
+// by lane bit 2; h = 16 a swizzle xor within 32-lane halves; h = 32 through
+// the LDS crossbar.
+template <int kCtrl>
+__device__ inline float dpp_mov(float v) {
+  return __builtin_bit_cast(
+      float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), kCtrl, 0xF, 0xF, false));
+}
+__device__ inline float lane_xor(float v, int h, int lane) {
+  switch (h) {
+    case 1: return dpp_mov<0xB1>(v);
+    case 2: return dpp_mov<0x4E>(v);
+    case 4: {
+      const float up = dpp_mov<0x12C>(v), down = dpp_mov<0x124>(v);
+      return (lane & 4) ? down : up;
+    }
+    case 8: return dpp_mov<0x128>(v);
+    case 16:
+      return __builtin_bit_cast(float,
+                                __builtin_amdgcn_ds_swizzle(__builtin_bit_cast(int, v), 0x401F));
+    default: return __shfl_xor(v, h, 64);
+  }
+}
+
+// First inverse pass in column blocks (F <= 64): a workgroup takes C
+// consecutive columns (inner indices) of every channel's spectrum into LDS,
+// laid out [q][c][j] with the F frequencies contiguous, so that each spectrum
+// is read from HBM once, and forms every channel pair's cross-spectrum from
+// there (the line-per-pair form re-reads two channel planes per pair).  A
+// wave transforms 64 / F lines at a time across its lanes: the input in
+// bit-reversed order, then radix-2 steps h = 1, 2, .., F/2 pairing lane j
+// with lane j ^ h: the lower lane forms a + W b, the upper a - W b (a, b the
+// lower and upper values, W = e^{+i pi (j mod h) / h}); lane j then holds
+// output position j (lag j, or j - F past F/2), and the lanes at the B kept
+// lags store.  A wave takes every nw-th pair and its C columns in turn.
+__global__ void __launch_bounds__(512) k_inv_first_cols(const float2* __restrict__ S,
+                                                        float2* __restrict__ out, int Q, int F,
+                                                        int logF, int inner, int B, int C) {
+  extern __shared__ float2 sl[];  // [Q][C][F]
+  const long long c0 = 1LL * blockIdx.x * C;
+  for (int e = threadIdx.x; e < Q * F * C; e += blockDim.x) {
+    const int c = e % C, j = (e / C) % F, q = e / (C * F);
+    sl[(q * C + c) * F + j] =
+        c0 + c < inner ? S[(size_t(q) * F + j) * inner + c0 + c] : make_float2(0.f, 0.f);
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int per = 64 / F, sub = lane / F, jl = lane % F;
+  const int jr = logF > 0 ? int(__brev(unsigned(jl)) >> (32 - logF)) : 0;
+  float2 tw[6];
+#pragma unroll
+  for (int s = 0; s < 6; ++s) {
+    const int h = 1 << s;
+    float sn = 0.f, cs = 1.f;
+    if (h < F) sincospif(float(jl & (h - 1)) / float(h), &sn, &cs);
+    tw[s] = make_float2(cs, sn);
+  }
+  const int hb = (B - 1) / 2;
+  const int m = jl <= hb ? jl + hb : (jl >= F - hb ? jl - F + hb : -1);
+  const int P = Q * (Q + 1) / 2;
+  // kIlp lines per lane in flight, so that the cross-lane exchanges of one
+  // line overlap those of the others
+  constexpr int kIlp = 4;
+  for (int pair = wv; pair < P; pair += nw) {
+    int p, q;
+    pair_decode(pair, Q, &p, &q);
+    for (int cb = 0; cb < C; cb += per * kIlp) {
+      float2 x[kIlp];
+#pragma unroll
+      for (int u = 0; u < kIlp; ++u) {
+        const int c = cb + sub + per * u;
+        x[u] = c < C ? cmulc(sl[(p * C + c) * F + jr], sl[(q * C + c) * F + jr])
+                     : make_float2(0.f, 0.f);
+      }
+#pragma unroll
+      for (int s = 0; s < 6; ++s) {
+        const int h = 1 << s;
+        if (h < F) {
+          // the upper lane twiddles its own value and sends it, the lower
+          // lane sends its value as is: lower x + W x', upper x - W x'
+          const bool lo = (jl & h) == 0;
+#pragma unroll
+          for (int u = 0; u < kIlp; ++u) {
+            const float2 w = cmul(tw[s], x[u]);
+            const float2 snd = lo ? x[u] : w;
+            const float2 r = make_float2(lane_xor(snd.x, h, lane), lane_xor(snd.y, h, lane));
+            x[u] = lo ? cadd(x[u], r) : csub(r, w);
+          }
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kIlp; ++u) {
+        const int c = cb + sub + per * u;
+        if (c < C && m >= 0 && c0 + c < inner)
+          out[(size_t(pair) * B + m) * inner + c0 + c] = x[u];
+      }
+    }
+  }
+}
+
 // Middle inverse pass: in [outer][F][inner] -> out [outer][B][inner]
 __global__ void __launch_bounds__(256) k_inv_mid(const float2* __restrict__ in,
                                                  float2* __restrict__ out, PassGeom g,
@@ -417,11 +520,32 @@ static pisco_status_t run_gram_valid(Handle* h, const Plan& p, const Tables& t, 
   return PISCO_OK;
 }
 
+// First inverse pass: S [Q][F][inner] -> out [P][B][inner].  The column-block
+// kernel where F <= 64 and C >= 1 columns of all Q spectra fit in 64 KB of
+// LDS (C a power of two up to 8); the line-per-pair kernel otherwise.
+static pisco_status_t inv_first(Handle* h, const float2* S, float2* out, int Q, int F,
+                                int inner, int B) {
+  int logF = 0;
+  while ((1 << logF) < F) ++logF;
+  int C = 8;
+  while (C > 0 && size_t(Q) * F * C * sizeof(float2) > 65536) C >>= 1;
+  if ((1 << logF) == F && F <= 64 && C >= 1) {
+    PISCO_KERNEL(h, k_inv_first_cols, dim3(ceil_div(inner, C)), dim3(512),
+                 size_t(Q) * F * C * sizeof(float2), S, out, Q, F, logF, inner, B, C);
+    return PISCO_OK;
+  }
+  const int P = Q * (Q + 1) / 2;
+  PassGeom g = geom(F, 1LL * P * inner);
+  PISCO_KERNEL(h, k_inv_first, dim3(blocks_for(g)), dim3(256), 0, S, out, g, Q, F, inner, B);
+  return PISCO_OK;
+}
+
 pisco_status_t run_gram(Handle* h, const Plan& p, const Tables& t, const float2* acs,
                         float2* gram, void* ws, float2* lags_out) {
   if (p.rows == PISCO_ROWS_VALID) return run_gram_valid(h, p, t, acs, gram, ws);
   GramWs w;
   layout_gram(p, ws, &w);
+  pisco_status_t st;
   const int Q = p.Q, P = p.P;
   const int A0 = p.acs[0], A1 = p.acs[1], A2 = p.acs[2];
   const int F0 = p.F[0], F1 = p.F[1], F2 = p.F[2];
@@ -446,13 +570,11 @@ pisco_status_t run_gram(Handle* h, const Plan& p, const Tables& t, const float2*
   // inverse per pair: (z), y, x
   const float scale = 1.0f / float(p.nF);
   if (p.D == 3) {
-    PassGeom iz = geom(F0, 1LL * P * F1 * F2);
-    PISCO_KERNEL(h, k_inv_first, dim3(blocks_for(iz)), dim3(256), 0, Sfull, w.T1, iz, Q, F0, F1 * F2, B0);
+    if ((st = inv_first(h, Sfull, w.T1, Q, F0, F1 * F2, B0))) return st;
     PassGeom iy = geom(F1, 1LL * P * B0 * F2);
     PISCO_KERNEL(h, k_inv_mid, dim3(blocks_for(iy)), dim3(256), 0, w.T1, w.T2, iy, F1, F2, B1);
   } else {
-    PassGeom iy = geom(F1, 1LL * P * F2);
-    PISCO_KERNEL(h, k_inv_first, dim3(blocks_for(iy)), dim3(256), 0, Sfull, w.T2, iy, Q, F1, F2, B1);
+    if ((st = inv_first(h, Sfull, w.T2, Q, F1, F2, B1))) return st;
   }
   PassGeom ix = geom(F2, 1LL * P * B0 * B1);
   float2* R = lags_out ? lags_out : w.R;
