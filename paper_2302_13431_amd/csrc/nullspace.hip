@@ -507,8 +507,9 @@ constexpr int kCholThreads = 1024;
 // rows [kbeg, kend) and applies their trailing updates to those rows alone
 // (every column right of the diagonal); the update of the rows below, with
 // the finished rows R_[kbeg,kend),: as one rank-(kend - kbeg) block, is
-// k_chol_update's, across many workgroups.  The first call (kbeg = 0)
-// also stages T; later calls read the scales back from dsc_out.
+// k_chol_update's, across many workgroups.  T, the scales and R's lower
+// part are staged beforehand by k_chol_stage; every call reads the scales
+// back from dsc_out.
 template <bool kLds>
 __global__ void __launch_bounds__(kCholThreads) k_chol(const double2* __restrict__ S, int b,
                                                double shift, double2* __restrict__ R,
@@ -582,16 +583,9 @@ __global__ void __launch_bounds__(kCholThreads) k_chol(const double2* __restrict
         ++j;
       }
     }
-  } else if (kbeg == 0) {
-    for (int k = t; k < b; k += kNT) {
-      const double d = S[size_t(k) * b + k].x;
-      dsc[k] = d > 0.0 ? 1.0 / sqrt(d) : 0.0;
-      dsc_out[k] = dsc[k];
-    }
-    __syncthreads();
-    for (int e = t; e < b * b; e += kNT) stage(e % b, e / b, S[e]);
-    for (int e = t; e < b * b; e += kNT) zero_lower(e % b, e / b);
   } else {
+    // blocked use: T, the scales and R's lower part were staged by
+    // k_chol_stage across many workgroups
     for (int k = t; k < b; k += kNT) dsc[k] = dsc_out[k];
   }
   __syncthreads();
@@ -677,6 +671,34 @@ __global__ void __launch_bounds__(kCholThreads) k_chol(const double2* __restrict
     }
     __syncthreads();
   }
+}
+
+// Staging of the blocked Cholesky over many workgroups, one thread per
+// entry (i, j) of the column-major S: the scale d_i = 1 / sqrt(S_ii) (0
+// where S_ii <= 0) to dsc_out, T_ij = d_i d_j S_ij (+ shift on the diagonal,
+// imaginary part dropped there) for i <= j into T (row-major, ld = b + 1),
+// and zeros into R below the diagonal.
+__global__ void __launch_bounds__(256) k_chol_stage(const double2* __restrict__ S, int b,
+                                                    double shift, double2* __restrict__ T,
+                                                    double2* __restrict__ R,
+                                                    double* __restrict__ dsc_out,
+                                                    const int* __restrict__ skip) {
+  if (skip && *skip) return;
+  const long long e = blockIdx.x * 256LL + threadIdx.x;
+  if (e >= 1LL * b * b) return;
+  const int i = int(e % b), j = int(e / b);
+  if (j < i) {
+    R[e] = make_double2(0.0, 0.0);
+    return;
+  }
+  const double si = S[size_t(i) * b + i].x, sj = S[size_t(j) * b + j].x;
+  const double di = si > 0.0 ? 1.0 / sqrt(si) : 0.0, dj = sj > 0.0 ? 1.0 / sqrt(sj) : 0.0;
+  double2 v = zscale(S[e], di * dj);
+  if (i == j) {
+    v = make_double2(v.x + shift, 0.0);
+    dsc_out[i] = di;
+  }
+  T[size_t(i) * (b + 1) + j] = v;
 }
 
 // Trailing update of the blocked Cholesky: T_ij -= sum_{l in [kbeg, kend)}
@@ -1068,7 +1090,10 @@ pisco_status_t chol_inv(NullCtx& c, const double2* S, double shift, double2* M,
     PISCO_KERNEL(c.h, k_chol<true>, dim3(1), dim3(kCholThreads), 0, S, b, shift, c.w.R,
                  c.w.dsc, T, flag, rdiag, skip, 0, b);
   } else {
-    // blocked: one workgroup eliminates a panel of rows, many update the rest
+    // blocked: staged across many workgroups, then one workgroup eliminates
+    // a panel of rows and many update the rest
+    PISCO_KERNEL(c.h, k_chol_stage, dim3(ceil_div(1LL * b * b, 256)), dim3(256), 0, S, b, shift,
+                 T, c.w.R, c.w.dsc, skip);
     for (int kb = 0; kb < b; kb += kCholPanel) {
       const int ke = kb + kCholPanel < b ? kb + kCholPanel : b;
       PISCO_KERNEL(c.h, k_chol<false>, dim3(1), dim3(kCholThreads), 0, S, b, shift, c.w.R,
