@@ -277,6 +277,41 @@ __device__ inline float lane_xor(float v, int h, int lane) {
 // lower and upper values, W = e^{+i pi (j mod h) / h}); lane j then holds
 // output position j (lag j, or j - F past F/2), and the lanes at the B kept
 // lags store.  A wave takes every nw-th pair and its C columns in turn.
+// Lane-parallel inverse transform of kIlp lines per lane (F <= 64, 64 / F
+// lines per wave, lane = sub-line * F + jl): x holds the input at position
+// bit-reverse(jl) and on return output position jl; tw[s] is the lane's
+// twiddle e^{+i pi (jl mod h) / h} of step h = 2^s.
+template <int kIlp>
+__device__ inline void lane_ifft(float2 (&x)[kIlp], const float2 (&tw)[6], int F, int jl,
+                                 int lane) {
+#pragma unroll
+  for (int s = 0; s < 6; ++s) {
+    const int h = 1 << s;
+    if (h < F) {
+      // the upper lane twiddles its own value and sends it, the lower lane
+      // sends its value as is: lower x + W x', upper x - W x'
+      const bool lo = (jl & h) == 0;
+#pragma unroll
+      for (int u = 0; u < kIlp; ++u) {
+        const float2 w = cmul(tw[s], x[u]);
+        const float2 snd = lo ? x[u] : w;
+        const float2 r = make_float2(lane_xor(snd.x, h, lane), lane_xor(snd.y, h, lane));
+        x[u] = lo ? cadd(x[u], r) : csub(r, w);
+      }
+    }
+  }
+}
+
+__device__ inline void lane_twiddles(float2 (&tw)[6], int F, int jl) {
+#pragma unroll
+  for (int s = 0; s < 6; ++s) {
+    const int h = 1 << s;
+    float sn = 0.f, cs = 1.f;
+    if (h < F) sincospif(float(jl & (h - 1)) / float(h), &sn, &cs);
+    tw[s] = make_float2(cs, sn);
+  }
+}
+
 __global__ void __launch_bounds__(512) k_inv_first_cols(const float2* __restrict__ S,
                                                         float2* __restrict__ out, int Q, int F,
                                                         int logF, int inner, int B, int C) {
@@ -292,13 +327,7 @@ __global__ void __launch_bounds__(512) k_inv_first_cols(const float2* __restrict
   const int per = 64 / F, sub = lane / F, jl = lane % F;
   const int jr = logF > 0 ? int(__brev(unsigned(jl)) >> (32 - logF)) : 0;
   float2 tw[6];
-#pragma unroll
-  for (int s = 0; s < 6; ++s) {
-    const int h = 1 << s;
-    float sn = 0.f, cs = 1.f;
-    if (h < F) sincospif(float(jl & (h - 1)) / float(h), &sn, &cs);
-    tw[s] = make_float2(cs, sn);
-  }
+  lane_twiddles(tw, F, jl);
   const int hb = (B - 1) / 2;
   const int m = jl <= hb ? jl + hb : (jl >= F - hb ? jl - F + hb : -1);
   const int P = Q * (Q + 1) / 2;
@@ -316,22 +345,7 @@ __global__ void __launch_bounds__(512) k_inv_first_cols(const float2* __restrict
         x[u] = c < C ? cmulc(sl[(p * C + c) * F + jr], sl[(q * C + c) * F + jr])
                      : make_float2(0.f, 0.f);
       }
-#pragma unroll
-      for (int s = 0; s < 6; ++s) {
-        const int h = 1 << s;
-        if (h < F) {
-          // the upper lane twiddles its own value and sends it, the lower
-          // lane sends its value as is: lower x + W x', upper x - W x'
-          const bool lo = (jl & h) == 0;
-#pragma unroll
-          for (int u = 0; u < kIlp; ++u) {
-            const float2 w = cmul(tw[s], x[u]);
-            const float2 snd = lo ? x[u] : w;
-            const float2 r = make_float2(lane_xor(snd.x, h, lane), lane_xor(snd.y, h, lane));
-            x[u] = lo ? cadd(x[u], r) : csub(r, w);
-          }
-        }
-      }
+      lane_ifft(x, tw, F, jl, lane);
 #pragma unroll
       for (int u = 0; u < kIlp; ++u) {
         const int c = cb + sub + per * u;
@@ -339,6 +353,56 @@ __global__ void __launch_bounds__(512) k_inv_first_cols(const float2* __restrict
           out[(size_t(pair) * B + m) * inner + c0 + c] = x[u];
       }
     }
+  }
+}
+
+// Middle inverse pass in column blocks (F <= 64): a workgroup takes one outer
+// index and C <= 64 consecutive columns, stages the F x C input tile in LDS
+// by whole rows (transposed to [c][j], rows padded by one), transforms the
+// C lines across lanes as k_inv_first_cols does, and writes the B kept lags
+// back through LDS as whole rows of C columns.
+__global__ void __launch_bounds__(512) k_inv_mid_cols(const float2* __restrict__ in,
+                                                      float2* __restrict__ out, int F, int logF,
+                                                      int inner, int B, int C) {
+  __shared__ float2 xin[64 * 65];  // [c][j], row stride F + 1
+  __shared__ float2 xo[64 * 64];   // [m][c], row stride C
+  const int cblocks = (inner + C - 1) / C;
+  const long long o = blockIdx.x / cblocks;
+  const int c0 = int(blockIdx.x % cblocks) * C;
+  const int FS = F + 1;
+  const float2* src = in + size_t(o) * F * inner;
+  for (int e = threadIdx.x; e < F * C; e += blockDim.x) {
+    const int j = e / C, c = e - j * C;
+    xin[c * FS + j] = c0 + c < inner ? src[size_t(j) * inner + c0 + c] : make_float2(0.f, 0.f);
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int per = 64 / F, sub = lane / F, jl = lane % F;
+  const int jr = logF > 0 ? int(__brev(unsigned(jl)) >> (32 - logF)) : 0;
+  float2 tw[6];
+  lane_twiddles(tw, F, jl);
+  const int hb = (B - 1) / 2;
+  const int m = jl <= hb ? jl + hb : (jl >= F - hb ? jl - F + hb : -1);
+  constexpr int kIlp = 4;
+  for (int cb = wv * per * kIlp; cb < C; cb += nw * per * kIlp) {
+    float2 x[kIlp];
+#pragma unroll
+    for (int u = 0; u < kIlp; ++u) {
+      const int c = cb + sub + per * u;
+      x[u] = c < C ? xin[c * FS + jr] : make_float2(0.f, 0.f);
+    }
+    lane_ifft(x, tw, F, jl, lane);
+#pragma unroll
+    for (int u = 0; u < kIlp; ++u) {
+      const int c = cb + sub + per * u;
+      if (c < C && m >= 0) xo[m * C + c] = x[u];
+    }
+  }
+  __syncthreads();
+  float2* dst = out + size_t(o) * B * inner;
+  for (int e = threadIdx.x; e < B * C; e += blockDim.x) {
+    const int mm = e / C, c = e - mm * C;
+    if (c0 + c < inner) dst[size_t(mm) * inner + c0 + c] = xo[e];
   }
 }
 
@@ -572,7 +636,15 @@ pisco_status_t run_gram(Handle* h, const Plan& p, const Tables& t, const float2*
   if (p.D == 3) {
     if ((st = inv_first(h, Sfull, w.T1, Q, F0, F1 * F2, B0))) return st;
     PassGeom iy = geom(F1, 1LL * P * B0 * F2);
-    PISCO_KERNEL(h, k_inv_mid, dim3(blocks_for(iy)), dim3(256), 0, w.T1, w.T2, iy, F1, F2, B1);
+    if (F1 <= 64 && (F1 & (F1 - 1)) == 0) {
+      int logF = 0;
+      while ((1 << logF) < F1) ++logF;
+      const int C = F2 < 64 ? F2 : 64;
+      PISCO_KERNEL(h, k_inv_mid_cols, dim3(unsigned(1LL * P * B0 * ceil_div(F2, C))), dim3(512),
+                   0, w.T1, w.T2, F1, logF, F2, B1, C);
+    } else {
+      PISCO_KERNEL(h, k_inv_mid, dim3(blocks_for(iy)), dim3(256), 0, w.T1, w.T2, iy, F1, F2, B1);
+    }
   } else {
     if ((st = inv_first(h, Sfull, w.T2, Q, F1, F2, B1))) return st;
   }
