@@ -43,6 +43,130 @@ __global__ void k_scatter_box(const double2* __restrict__ basis,
   box[idx] = v;
 }
 
+// Filter spectra in one pass per (r, q) workgroup: the box of v_r's channel
+// q gathered from the basis (FP64 -> FP32), then the x, y and z DFTs of the
+// separable zero-padded transform (box -> K = 2 box - 1 per axis, M1 tables)
+// in LDS, the spectrum written once: Fh[r][q][fz][fy][fx].  Only rows r < r_s
+// are formed (the contraction reads no others).  Each pass gives a thread one
+// line of the box (its inputs in registers) and a range of frequencies that
+// is the same across the wave, so a table row is one batch of wave-uniform
+// (scalar) loads.  LDS: region A holds the box and later the y result,
+// region B the x result.  kBox is the box edge, k3D whether z is transformed.
+__device__ inline float2 cfma(float2 m, float2 v, float2 acc) {
+  acc.x = fmaf(m.x, v.x, fmaf(-m.y, v.y, acc.x));
+  acc.y = fmaf(m.x, v.y, fmaf(m.y, v.x, acc.y));
+  return acc;
+}
+
+template <int kBox>
+__device__ inline float2 dft_row(const float2* __restrict__ Mrow, const float2 (&v)[kBox]) {
+  float2 acc = make_float2(0.f, 0.f);
+#pragma unroll
+  for (int i = 0; i < kBox; ++i) acc = cfma(Mrow[i], v[i], acc);
+  return acc;
+}
+
+template <int kBox, bool k3D>
+__global__ void __launch_bounds__(256) k_filter_spectra(
+    const double2* __restrict__ basis, const int32_t* __restrict__ counts,
+    const int* __restrict__ map, const float2* __restrict__ Mx, const float2* __restrict__ My,
+    const float2* __restrict__ Mz, float2* __restrict__ Fh, int n, int L, int Q) {
+  constexpr int K = 2 * kBox - 1, Bz = k3D ? kBox : 1, Kz = k3D ? K : 1;
+  constexpr int kCells = Bz * kBox * kBox, kPlane = K * K;
+  constexpr int kRegionA = kCells > Bz * kPlane ? kCells : Bz * kPlane;
+  extern __shared__ float2 sm[];
+  const int rq = blockIdx.x, r = rq / Q, q = rq - r * Q;
+  if (r >= counts[0]) return;
+  const int tid = threadIdx.x;
+  float2* bx = sm;             // [Bz][box][box]
+  float2* t2 = sm;             // [Bz][K][K] (after the x pass)
+  float2* t1 = sm + kRegionA;  // [Bz][box][K]
+  const double2* v_r = basis + size_t(r) * n + size_t(q) * L;
+  for (int cell = tid; cell < kCells; cell += 256) {
+    const int i = map[cell];
+    float2 v = make_float2(0.f, 0.f);
+    if (i >= 0) {
+      const double2 d = v_r[i];
+      v = make_float2(float(d.x), float(d.y));
+    }
+    bx[cell] = v;
+  }
+  __syncthreads();
+  float2 v[kBox];
+  // x: row (cz, cy) of the box; threads 0-127 take the lower frequencies,
+  // 128-255 the upper ones (wave-uniform halves)
+  {
+    constexpr int kRows = Bz * kBox, kHalf = (K + 1) / 2;
+    const int half = tid >> 7, f0 = half ? kHalf : 0, f1 = half ? K : kHalf;
+    for (int row = tid & 127; row < kRows; row += 128) {
+#pragma unroll
+      for (int i = 0; i < kBox; ++i) v[i] = bx[row * kBox + i];
+      for (int f = f0; f < f1; ++f) t1[row * K + f] = dft_row<kBox>(Mx + f * kBox, v);
+    }
+  }
+  __syncthreads();
+  // y: (cz, fx) -> K frequencies
+  for (int e = tid; e < Bz * K; e += 256) {
+    const int cz = e / K, fx = e - cz * K;
+#pragma unroll
+    for (int i = 0; i < kBox; ++i) v[i] = t1[(cz * kBox + i) * K + fx];
+    for (int f = 0; f < K; ++f) t2[(cz * K + f) * K + fx] = dft_row<kBox>(My + f * kBox, v);
+  }
+  __syncthreads();
+  // z: (fy, fx) -> Kz frequencies, straight to the spectrum
+  float2* dst = Fh + size_t(rq) * Kz * kPlane;
+  for (int e = tid; e < kPlane; e += 256) {
+    if (!k3D) {
+      dst[e] = t2[e];
+      continue;
+    }
+#pragma unroll
+    for (int i = 0; i < kBox; ++i) v[i] = t2[i * kPlane + e];
+    for (int f = 0; f < Kz; ++f) dst[size_t(f) * kPlane + e] = dft_row<kBox>(Mz + f * kBox, v);
+  }
+}
+
+template <int kBox>
+static size_t filter_spectra_lds(bool d3) {
+  const size_t K = 2 * kBox - 1, Bz = d3 ? kBox : 1;
+  const size_t cells = Bz * kBox * kBox, a = cells > Bz * K * K ? cells : Bz * K * K;
+  return (a + Bz * kBox * K) * sizeof(float2);
+}
+
+// The one-pass filter spectra where the box edge has an instance and the LDS
+// fits in 64 KB; PISCO_ERR_UNSUPPORTED (nothing launched) otherwise.
+static pisco_status_t filter_spectra(Handle* h, const Plan& p, int b, const double2* basis,
+                                     const int32_t* counts, const int* map, const Tables& t,
+                                     float2* Fh) {
+  const int box = 2 * p.tau + 1;
+  const bool d3 = p.D == 3;
+  if (p.K[2] != 2 * box - 1 || p.K[1] != 2 * box - 1 || (d3 && p.K[0] != 2 * box - 1))
+    return PISCO_ERR_UNSUPPORTED;
+  const float2* Mz = d3 ? t.M1[0] : t.M1[1];
+  const dim3 grid(unsigned(b * p.Q));
+#define PISCO_FS_CASE(B)                                                                     \
+  case B: {                                                                                  \
+    const size_t lds = filter_spectra_lds<B>(d3);                                            \
+    if (lds > 65536) return PISCO_ERR_UNSUPPORTED;                                           \
+    if (d3)                                                                                  \
+      PISCO_KERNEL(h, (k_filter_spectra<B, true>), grid, dim3(256), lds, basis, counts, map, \
+                   t.M1[2], t.M1[1], Mz, Fh, p.n, p.L, p.Q);                                 \
+    else                                                                                     \
+      PISCO_KERNEL(h, (k_filter_spectra<B, false>), grid, dim3(256), lds, basis, counts,    \
+                   map, t.M1[2], t.M1[1], Mz, Fh, p.n, p.L, p.Q);                            \
+    return PISCO_OK;                                                                         \
+  }
+  switch (box) {
+    PISCO_FS_CASE(5)
+    PISCO_FS_CASE(7)
+    PISCO_FS_CASE(9)
+    PISCO_FS_CASE(11)
+    PISCO_FS_CASE(13)
+    default: return PISCO_ERR_UNSUPPORTED;
+  }
+#undef PISCO_FS_CASE
+}
+
 // Kh[pair(p,q)][f] = sum_{r < r_s} conj(F[r][p][f]) F[r][q][f]
 // Block: FT frequencies x Q channels; r staged through LDS in chunks of 8.
 __global__ void __launch_bounds__(256) k_herk(const float2* __restrict__ F,
@@ -301,17 +425,22 @@ pisco_status_t run_gx(Handle* h, const Plan& p, const Tables& t, int b, int prec
   const int* map = t.boxmap;
   float2* bufA = w.Tmp;
   float2* bufB = w.Tmp + w.tmp_half;
-  PISCO_KERNEL(h, k_scatter_box, dim3(ceil_div(1LL * b * Q * ncell, 256)), dim3(256), 0, basis, counts, map, bufA, p.n, p.L, Q, b, ncell);
-
-  // 1. filter spectra: [bQ][Bz][box][box] -> [bQ][Kz][Ky][Kx] (ends in Fh)
-  int shp[4] = {b * Q, Bz, box, box};
-  if (p.D == 3) {
-    if ((st = chain(h, bufA, bufB, shp, 3, p.K[2], M1[2]))) return st;
-    if ((st = chain(h, bufB, bufA, shp, 2, p.K[1], M1[1]))) return st;
-    if ((st = chain(h, bufA, w.Fh, shp, 1, p.K[0], M1[0]))) return st;
-  } else {
-    if ((st = chain(h, bufA, bufB, shp, 3, p.K[2], M1[2]))) return st;
-    if ((st = chain(h, bufB, w.Fh, shp, 2, p.K[1], M1[1]))) return st;
+  // 1. filter spectra: [bQ][Bz][box][box] -> [bQ][Kz][Ky][Kx] (ends in Fh);
+  // one pass per (r, q) where the box edge has an instance and fits
+  st = filter_spectra(h, p, b, basis, counts, map, t, w.Fh);
+  if (st == PISCO_ERR_UNSUPPORTED) {
+    PISCO_KERNEL(h, k_scatter_box, dim3(ceil_div(1LL * b * Q * ncell, 256)), dim3(256), 0, basis, counts, map, bufA, p.n, p.L, Q, b, ncell);
+    int shp[4] = {b * Q, Bz, box, box};
+    if (p.D == 3) {
+      if ((st = chain(h, bufA, bufB, shp, 3, p.K[2], M1[2]))) return st;
+      if ((st = chain(h, bufB, bufA, shp, 2, p.K[1], M1[1]))) return st;
+      if ((st = chain(h, bufA, w.Fh, shp, 1, p.K[0], M1[0]))) return st;
+    } else {
+      if ((st = chain(h, bufA, bufB, shp, 3, p.K[2], M1[2]))) return st;
+      if ((st = chain(h, bufB, w.Fh, shp, 2, p.K[1], M1[1]))) return st;
+    }
+  } else if (st) {
+    return st;
   }
   // 2. contraction over the signal vectors
   if (precision == PISCO_PREC_SPLIT_F16) {
