@@ -276,7 +276,8 @@ __device__ inline float lane_xor(float v, int h, int lane) {
 // with lane j ^ h: the lower lane forms a + W b, the upper a - W b (a, b the
 // lower and upper values, W = e^{+i pi (j mod h) / h}); lane j then holds
 // output position j (lag j, or j - F past F/2), and the lanes at the B kept
-// lags store.  A wave takes every nw-th pair and its C columns in turn.
+// lags store.  A wave takes every nw-th pair of the workgroup's pair range
+// (gridDim.y ranges) and its C columns in turn.
 // Lane-parallel inverse transform of kIlp lines per lane (F <= 64, 64 / F
 // lines per wave, lane = sub-line * F + jl): x holds the input at position
 // bit-reverse(jl) and on return output position jl; tw[s] is the lane's
@@ -330,11 +331,14 @@ __global__ void __launch_bounds__(512) k_inv_first_cols(const float2* __restrict
   lane_twiddles(tw, F, jl);
   const int hb = (B - 1) / 2;
   const int m = jl <= hb ? jl + hb : (jl >= F - hb ? jl - F + hb : -1);
+  // pairs [pb, pe) of this workgroup (blockIdx.y of gridDim.y groups)
   const int P = Q * (Q + 1) / 2;
+  const int per_group = (P + gridDim.y - 1) / gridDim.y;
+  const int pb = blockIdx.y * per_group, pe = pb + per_group < P ? pb + per_group : P;
   // kIlp lines per lane in flight, so that the cross-lane exchanges of one
   // line overlap those of the others
   constexpr int kIlp = 4;
-  for (int pair = wv; pair < P; pair += nw) {
+  for (int pair = pb + wv; pair < pe; pair += nw) {
     int p, q;
     pair_decode(pair, Q, &p, &q);
     for (int cb = 0; cb < C; cb += per * kIlp) {
@@ -594,7 +598,14 @@ static pisco_status_t inv_first(Handle* h, const float2* S, float2* out, int Q, 
   int C = 8;
   while (C > 0 && size_t(Q) * F * C * sizeof(float2) > 65536) C >>= 1;
   if ((1 << logF) == F && F <= 64 && C >= 1) {
-    PISCO_KERNEL(h, k_inv_first_cols, dim3(ceil_div(inner, C)), dim3(512),
+    // few column blocks (2D): the channel pairs split over workgroups too,
+    // about two workgroups per CU, at least eight pairs (one per wave) each
+    const int P = Q * (Q + 1) / 2;
+    const long long cblocks = ceil_div(inner, C);
+    long long groups = (2LL * h->num_cu + cblocks - 1) / cblocks;
+    const long long gmax = (P + 7) / 8;
+    groups = groups < 1 ? 1 : (groups > gmax ? gmax : groups);
+    PISCO_KERNEL(h, k_inv_first_cols, dim3(unsigned(cblocks), unsigned(groups)), dim3(512),
                  size_t(Q) * F * C * sizeof(float2), S, out, Q, F, logF, inner, B, C);
     return PISCO_OK;
   }
