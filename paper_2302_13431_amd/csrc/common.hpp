@@ -239,7 +239,6 @@ struct GxWs {
   float2* Tmp;     // separable-transform scratch, two halves of tmp_half
   size_t tmp_half;
   float2* Kh;      // [P][nK] K^(f)
-  float2* Klag;    // [P][nlag]
 };
 size_t layout_gx(const Plan& p, int b, void* ws, GxWs* out);
 
@@ -249,8 +248,9 @@ size_t layout_gx(const Plan& p, int b, void* ws, GxWs* out);
 //   sup    : int4 [L], support offsets (z, y, x, 0) in the library's order
 //   boxmap : int [box^D], support-box cell -> support index (-1 outside)
 //   M1[d]  : float2 [K_d][2 tau + 1]  filter spectra  e^{+i 2 pi n f / K_d}
-//   M3[d]  : float2 [B_d][K_d]        lags from spectra (1/K_d) e^{+i 2 pi m f / K_d}
-//   M4[d]  : float2 [lr_d][B_d]       low-res evaluation e^{-i 2 pi m x}
+//   M4[d]  : float2 [lr_d][K_d]       low-res evaluation from the spectra: the lags
+//                                     (1/K_d) e^{+i 2 pi m f / K_d}, |m| <= 2 tau,
+//                                     evaluated at e^{-i 2 pi m x} and summed (FP64)
 //   Ma[d]  : double2 [lr_d][A_d]      apodized low-res image (FP64)
 //   Ms[d]  : float2 [out_d][lr_d]     periodic sinc interpolation
 //   Ms64[d]: double2 [out_d][lr_d]    the same in FP64 (support mask)
@@ -259,7 +259,6 @@ struct Tables {
   int4* sup = nullptr;
   int* boxmap = nullptr;
   float2* M1[3] = {nullptr, nullptr, nullptr};
-  float2* M3[3] = {nullptr, nullptr, nullptr};
   float2* M4[3] = {nullptr, nullptr, nullptr};
   double2* Ma[3] = {nullptr, nullptr, nullptr};
   float2* Ms[3] = {nullptr, nullptr, nullptr};

@@ -420,7 +420,6 @@ pisco_status_t run_gx(Handle* h, const Plan& p, const Tables& t, int b, int prec
   const int ncell = Bz * box * box;
   pisco_status_t st;
   const float2* const* M1 = t.M1;
-  const float2* const* M3 = t.M3;
   const float2* const* M4 = t.M4;
   const int* map = t.boxmap;
   float2* bufA = w.Tmp;
@@ -454,30 +453,22 @@ pisco_status_t run_gx(Handle* h, const Plan& p, const Tables& t, int b, int prec
     const int FT = 256 / Q;
     PISCO_KERNEL(h, k_herk, dim3(ceil_div(p.nK, FT)), dim3(256), 0, w.Fh, counts, w.Kh, Q, p.nK, FT);
   }
-  // 3. lags: [P][Kz][Ky][Kx] -> [P][Bz'][By][Bx]
-  int shk[4] = {P, p.K[0], p.K[1], p.K[2]};
-  if (p.D == 3) {
-    if ((st = chain(h, w.Kh, bufA, shk, 3, p.B[2], M3[2]))) return st;
-    if ((st = chain(h, bufA, bufB, shk, 2, p.B[1], M3[1]))) return st;
-    if ((st = chain(h, bufB, w.Klag, shk, 1, p.B[0], M3[0]))) return st;
-  } else {
-    if ((st = chain(h, w.Kh, bufA, shk, 3, p.B[2], M3[2]))) return st;
-    if ((st = chain(h, bufA, w.Klag, shk, 2, p.B[1], M3[1]))) return st;
-  }
-  // 4. evaluate on the low-res grid: [P][Bz][By][Bx] -> [P][lr0][lr1][lr2]
+  // 3. evaluate on the low-res grid straight from the spectra (the lags and
+  // their evaluation composed per axis in the M4 tables):
+  // [P][Kz][Ky][Kx] -> [P][lr0][lr1][lr2]
   // (the last pass stores G = |Lambda| I - G^s where it runs on the matrix
   // cores; otherwise a pass of its own does)
-  int shl[4] = {P, p.B[0], p.B[1], p.B[2]};
+  int shl[4] = {P, p.K[0], p.K[1], p.K[2]};
   const float bound = float(p.L);
   const float2* last_in = nullptr;
   int last_axis = 0;
   if (p.D == 3) {
-    if ((st = chain(h, w.Klag, bufA, shl, 3, p.lr[2], M4[2]))) return st;
+    if ((st = chain(h, w.Kh, bufA, shl, 3, p.lr[2], M4[2]))) return st;
     if ((st = chain(h, bufA, bufB, shl, 2, p.lr[1], M4[1]))) return st;
     last_in = bufB;
     last_axis = 1;
   } else {
-    if ((st = chain(h, w.Klag, bufA, shl, 3, p.lr[2], M4[2]))) return st;
+    if ((st = chain(h, w.Kh, bufA, shl, 3, p.lr[2], M4[2]))) return st;
     last_in = bufA;
     last_axis = 2;
   }

@@ -161,7 +161,6 @@ size_t layout_gx(const Plan& p, int b, void* ws, GxWs* o) {
   w.tmp_half = half;
   w.Tmp = c.take<float2>(2 * half);
   w.Kh = c.take<float2>(size_t(p.P) * p.nK);
-  w.Klag = c.take<float2>(size_t(p.P) * p.nlag);
   if (o) *o = w;
   return c.used + 256;
 }

@@ -577,12 +577,16 @@ pisco_status_t axis_transform64(Handle* h, const double2* in, double2* out,
 //          the index of an inside cell is the number of inside cells before
 //          it in the same lexicographic order
 enum TableKind { kTDft32 = 0, kTDft64 = 1, kTSinc32 = 2, kTSupport = 3, kTBoxMap = 4,
-                 kTSinc64 = 5 };
+                 kTSinc64 = 5, kTDftDft32 = 6 };
 constexpr int kMaxTableJobs = 24;
 struct TableJob {
   int kind, nout, nin, co, ci;
   double period, sign, scale, sigma;
   void* out;
+  // kTDftDft32: the product of two dft matrices, [nout][nmid] (the fields
+  // above, no weight) times [nmid][nin] (these), summed over the middle index
+  int nmid, co2, ci2;
+  double period2, sign2, scale2;
 };
 struct TableJobs {
   TableJob job[kMaxTableJobs];
@@ -595,28 +599,48 @@ __device__ inline bool in_ball(int z, int y, int x, double r2) {
   return r2 < 0.0 || double(z) * z + double(y) * y + double(x) * x <= r2;
 }
 
-__device__ void dft_entry(const TableJob& j, int idx, double* re, double* im) {
-  const int o = idx / j.nin, i = idx - o * j.nin;
-  const long long prod = 1LL * (i - j.ci) * (o - j.co);
+__device__ void dft_value(int o, int i, int co, int ci, double period, double sign,
+                          double scale, double sigma, double* re, double* im) {
+  const long long prod = 1LL * (i - ci) * (o - co);
   // the phase reduced exactly in integers before the trigonometric call
-  const long long per = (long long)llround(j.period);
+  const long long per = (long long)llround(period);
   double frac;
-  if (double(per) == j.period && per > 0) {
+  if (double(per) == period && per > 0) {
     long long r = prod % per;
     if (r < 0) r += per;
-    frac = double(r) / j.period;
+    frac = double(r) / period;
   } else {
-    frac = double(prod) / j.period;
+    frac = double(prod) / period;
   }
   double sn, cs;
-  sincospi(2.0 * j.sign * frac, &sn, &cs);
-  double w = j.scale;
-  if (j.sigma > 0.0) {
-    const double k = double(i - j.ci);
-    w *= exp(-k * k / (2.0 * j.sigma * j.sigma));
+  sincospi(2.0 * sign * frac, &sn, &cs);
+  double w = scale;
+  if (sigma > 0.0) {
+    const double k = double(i - ci);
+    w *= exp(-k * k / (2.0 * sigma * sigma));
   }
   *re = w * cs;
   *im = w * sn;
+}
+
+__device__ void dft_entry(const TableJob& j, int idx, double* re, double* im) {
+  const int o = idx / j.nin, i = idx - o * j.nin;
+  dft_value(o, i, j.co, j.ci, j.period, j.sign, j.scale, j.sigma, re, im);
+}
+
+// entry (o, i) of the product of the two dft matrices of a kTDftDft32 job
+__device__ void dftdft_entry(const TableJob& j, int idx, double* re, double* im) {
+  const int o = idx / j.nin, i = idx - o * j.nin;
+  double sr = 0.0, si = 0.0;
+  for (int m = 0; m < j.nmid; ++m) {
+    double ar, ai, br, bi;
+    dft_value(o, m, j.co, j.ci, j.period, j.sign, j.scale, 0.0, &ar, &ai);
+    dft_value(m, i, j.co2, j.ci2, j.period2, j.sign2, j.scale2, 0.0, &br, &bi);
+    sr += ar * br - ai * bi;
+    si += ar * bi + ai * br;
+  }
+  *re = sr;
+  *im = si;
 }
 
 __device__ void sinc_entry(const TableJob& j, int idx, double* re, double* im) {
@@ -652,10 +676,13 @@ __global__ void __launch_bounds__(256) k_build_tables(TableJobs jobs) {
     default: total = j.nout * j.nin;
   }
   for (int idx = blockIdx.x * 256 + threadIdx.x; idx < total; idx += gridDim.x * 256) {
-    if (j.kind == kTDft32 || j.kind == kTDft64 || j.kind == kTSinc32 || j.kind == kTSinc64) {
+    if (j.kind == kTDft32 || j.kind == kTDft64 || j.kind == kTSinc32 || j.kind == kTSinc64 ||
+        j.kind == kTDftDft32) {
       double re, im;
       if (j.kind == kTSinc32 || j.kind == kTSinc64)
         sinc_entry(j, idx, &re, &im);
+      else if (j.kind == kTDftDft32)
+        dftdft_entry(j, idx, &re, &im);
       else
         dft_entry(j, idx, &re, &im);
       if (j.kind == kTDft64 || j.kind == kTSinc64)
@@ -704,8 +731,7 @@ size_t layout_tables(const Plan& p, unsigned which, void* ws, Tables* out) {
   if (which & kTabGx) {
     for (int d = first; d < 3; ++d) {
       t.M1[d] = c.take<float2>(size_t(p.K[d]) * box);
-      t.M3[d] = c.take<float2>(size_t(p.B[d]) * p.K[d]);
-      t.M4[d] = c.take<float2>(size_t(p.lr[d]) * p.B[d]);
+      t.M4[d] = c.take<float2>(size_t(p.lr[d]) * p.K[d]);
     }
   }
   if (which & kTabMaps) {
@@ -763,10 +789,18 @@ pisco_status_t build_tables(Handle* h, const Plan& p, unsigned which, const Tabl
       const int Lk = p.K[d], Bd = p.B[d], lr = p.lr[d];
       // filter spectra: e^{+i 2 pi n f / Lk}, n = box index - tau
       add(kTDft32, t.M1[d], Lk, box, 0, tau, Lk, +1.0, 1.0, 0.0);
-      // lags from spectra: (1/Lk) e^{+i 2 pi m f / Lk}, m = out index - 2 tau
-      add(kTDft32, t.M3[d], Bd, Lk, 2 * tau, 0, Lk, +1.0, 1.0 / Lk, 0.0);
-      // low-res evaluation: e^{-i 2 pi m x}, x = (a - floor(N/2)) / N
-      add(kTDft32, t.M4[d], lr, Bd, lr / 2, 2 * tau, lr, -1.0, 1.0, 0.0);
+      // low-res evaluation straight from the spectra: the lags (1/Lk) e^{+i 2
+      // pi m f / Lk}, m = lag index - 2 tau, evaluated at e^{-i 2 pi m x}, x =
+      // (a - floor(N/2)) / N, summed over the Bd lags in FP64
+      add(kTDft32, t.M4[d], lr, Lk, lr / 2, 2 * tau, lr, -1.0, 1.0, 0.0);
+      TableJob& j = jobs.job[jobs.count - 1];
+      j.kind = kTDftDft32;
+      j.nmid = Bd;
+      j.co2 = 2 * tau;
+      j.ci2 = 0;
+      j.period2 = Lk;
+      j.sign2 = +1.0;
+      j.scale2 = 1.0 / Lk;
     }
   }
   if (which & kTabMaps) {
