@@ -357,25 +357,42 @@ __global__ void __launch_bounds__(256) k_axis_mm_lines(const float2* __restrict_
   }
 }
 
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+
 // The last interpolation pass (along x, real sinc matrix) with the coil
 // normalisation c[:, v] /= ||c[:, v]||_2 fused in: in = [Q][rows][nin], out =
 // [Q][rows][nout].  A 64-line tile holds G = 64 / Q row indices times all Q
 // coils (local line g Q + q), so every output voxel of the tile has its Q
-// coil values in the tile.  After the products the squared magnitudes go
-// through LDS (over Xs, free until the next tile is staged); one thread per
-// (g, column) sums them over q in coil order, as the separate normalisation
-// would, and the lanes scale their values by 1 / sqrt(sum) (a zero sum leaves
-// the values as they are).
+// coil values in the tile; a zero sum of squares leaves the values as they
+// are.
+// Products on the FP16 matrix cores with split operands: X and M scaled by
+// 2^10 (|X| stays far below the FP16 range: the unit-modulus references
+// interpolated by periodic sinc), each split into an FP16 high part and the
+// FP16 rounding of the rest, and the three products hi hi, hi lo, lo hi
+// accumulated in FP32 on v_mfma_f32_16x16x32_f16 (K = nin padded to 64 with
+// zeros); the dropped lo lo term is below 2^-21 of the product.  M is split
+// once per workgroup into LDS, a line tile per step on the fly from its FP32
+// staging.  Operand lanes of the 16 x 16 x 32 shape: lane l supplies A row
+// l % 16 and B column l % 16 for k = 8 (l / 16) + 0..7.
+// The sums over q: kQW = Q / 16 waves per row index (Q = 16 or 32) reduce in
+// registers and across lanes, and for two waves add the partner wave's
+// partial through LDS; any other Q (kQW = 0) puts the squared magnitudes in
+// LDS over Xs (free until the next tile is staged) and one thread per
+// (g, column) sums them.
+template <int kQW>
 __global__ void __launch_bounds__(256) k_interp_x_rss(const float2* __restrict__ in,
                                                       float2* __restrict__ out,
-                                                      const float2* __restrict__ M, int Q,
+                                                      const float2* __restrict__ M, int Qarg,
                                                       long long rows, int nin, int nout) {
-  constexpr int kPer = kMmK * 64 / 256;  // staged elements per thread
-  __shared__ float2 Ms[64 * (kMmK + 1)];
-  __shared__ float2 Xs[64 * (kMmK + 1)];
-  float* ssq = reinterpret_cast<float*>(Xs);  // [64 lines][64 columns]
-  float* inv = ssq + 64 * 64;                 // [G][64 columns]
-  const int K4 = (nin + 3) & ~3;
+  constexpr int XS = 65;  // Xs row stride (float2)
+  constexpr int MS = 72;  // Mh, Ml row stride (halves; rows 16-byte aligned)
+  __shared__ float2 Xs[64 * XS];
+  __shared__ _Float16 Mh[64 * MS], Ml[64 * MS];
+  __shared__ float psum[4][64];  // kQW = 2: per-wave column sums
+  float* ssq = reinterpret_cast<float*>(Xs);  // kQW = 0: [64 lines][64 columns]
+  float* inv = ssq + 64 * 64;                 // kQW = 0: [G][64 columns]
+  const int Q = kQW > 0 ? 16 * kQW : Qarg;    // a constant for kQW > 0
+  const float scale = 1024.f, unscale = 1.f / (1024.f * 1024.f);
   const int G = 64 / Q;
   const int otiles = (nout + 63) / 64;
   const long long tiles = (rows + G - 1) / G;
@@ -383,63 +400,127 @@ __global__ void __launch_bounds__(256) k_interp_x_rss(const float2* __restrict__
   const int o0 = int(lb % otiles) * 64;
   const long long tb = lb / otiles * kMmTiles;
   const long long te = tiles < tb + kMmTiles ? tiles : tb + kMmTiles;
-  mm_stage_m(Ms, M, o0, nout, nin, K4);
-  // element u of this thread: local line r = g Q + q, input k; its source
-  // is line q rows + (tile G + g), at offset off[u] + tile G nin
-  int lds[kPer], gu[kPer];
-  long long off[kPer];
+  for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+    const int o = e >> 6, k = e & 63;
+    const float v = (o0 + o < nout && k < nin ? M[size_t(o0 + o) * nin + k].x : 0.f) * scale;
+    const _Float16 hi = static_cast<_Float16>(v);
+    Mh[o * MS + k] = hi;
+    Ml[o * MS + k] = static_cast<_Float16>(v - static_cast<float>(hi));
+  }
+  // element u of this thread: local line r = e / 64 (= g Q + q), input
+  // k = e % 64; its source is line q rows + (tile G + g), at offset off[u] +
+  // tile G nin
+  int gu[16];
+  long long off[16];
 #pragma unroll
-  for (int u = 0; u < kPer; ++u) {
-    const int e = threadIdx.x + 256 * u, r = e / K4, k = e - r * K4;
-    const bool use = e < 64 * K4 && r < G * Q;
+  for (int u = 0; u < 16; ++u) {
+    const int e = threadIdx.x + 256 * u, r = e >> 6, k = e & 63;
     const int g = r / Q, q = r - g * Q;
-    lds[u] = e < 64 * K4 ? r * (kMmK + 1) + k : -1;
-    gu[u] = use && k < nin ? g : -1;
+    gu[u] = r < G * Q && k < nin ? g : -1;
     off[u] = (1LL * q * rows + g) * nin + k;
   }
-  float2 x[kPer];
+  float2 x[16];
   auto load = [&](long long tile) {
     const long long r0 = tile * G;
 #pragma unroll
-    for (int u = 0; u < kPer; ++u)
+    for (int u = 0; u < 16; ++u)
       x[u] = gu[u] >= 0 && r0 + gu[u] < rows ? in[off[u] + r0 * nin] : make_float2(0.f, 0.f);
   };
-  const int l = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int l = threadIdx.x & 63, wv = threadIdx.x >> 6, li = l & 15, kg = l >> 4;
   if (tb < te) load(tb);
   for (long long tile = tb; tile < te; ++tile) {
-    __syncthreads();  // the previous tile is done with Xs (products and sums)
+    __syncthreads();  // the previous tile is done with Xs and psum
 #pragma unroll
-    for (int u = 0; u < kPer; ++u)
-      if (lds[u] >= 0) Xs[lds[u]] = x[u];
-    __syncthreads();
-    if (tile + 1 < te) load(tile + 1);
-    f32x4 t1[4], t2[4], t3[4];
-    mm_tile<true>(Xs, kMmK + 1, Ms, kMmK + 1, true, K4, t1, t2, t3);
-    __syncthreads();  // every wave is done reading Xs
-#pragma unroll
-    for (int j = 0; j < 4; ++j)
-#pragma unroll
-      for (int v = 0; v < 4; ++v)
-        ssq[(16 * wv + 4 * (l >> 4) + v) * 64 + 16 * j + (l & 15)] =
-            cabs2(mm_result<true>(t1[j], t2[j], t3[j], v));
-    __syncthreads();
-    for (int e = threadIdx.x; e < G * 64; e += 256) {
-      const int g = e >> 6, c = e & 63;
-      float s = 0.f;
-      for (int q = 0; q < Q; ++q) s += ssq[(g * Q + q) * 64 + c];
-      inv[e] = s > 0.f ? 1.f / sqrtf(s) : 1.f;
+    for (int u = 0; u < 16; ++u) {
+      const int e = threadIdx.x + 256 * u;
+      Xs[(e >> 6) * XS + (e & 63)] = x[u];
     }
     __syncthreads();
+    if (tile + 1 < te) load(tile + 1);
+    f32x4 t1[4], t2[4];  // Re and Im: rows 4 kg + v of the wave's 16 lines
+#pragma unroll
+    for (int j = 0; j < 4; ++j) t1[j] = t2[j] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int ks = 0; ks < 2; ++ks) {
+      const int k0 = 32 * ks + 8 * kg;
+      f16x8 rh, rl, ih, il;
+      const float2* xr = Xs + (16 * wv + li) * XS + k0;
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const float2 v = xr[i];
+        const float a = v.x * scale, b = v.y * scale;
+        const _Float16 ah = static_cast<_Float16>(a), bh = static_cast<_Float16>(b);
+        rh[i] = ah;
+        rl[i] = static_cast<_Float16>(a - static_cast<float>(ah));
+        ih[i] = bh;
+        il[i] = static_cast<_Float16>(b - static_cast<float>(bh));
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int o = 16 * j + li;
+        const f16x8 mh = *reinterpret_cast<const f16x8*>(Mh + o * MS + k0);
+        const f16x8 ml = *reinterpret_cast<const f16x8*>(Ml + o * MS + k0);
+        t1[j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(rh, mh, t1[j], 0, 0, 0);
+        t1[j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(rh, ml, t1[j], 0, 0, 0);
+        t1[j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(rl, mh, t1[j], 0, 0, 0);
+        t2[j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ih, mh, t2[j], 0, 0, 0);
+        t2[j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ih, ml, t2[j], 0, 0, 0);
+        t2[j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(il, mh, t2[j], 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      t1[j] = t1[j] * unscale;
+      t2[j] = t2[j] * unscale;
+    }
+    float sc[4];  // 1 / norm for the lane's columns 16 j + l % 16
+    if (kQW > 0) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        float s = 0.f;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) s += t1[j][v] * t1[j][v] + t2[j][v] * t2[j][v];
+        s += __shfl_xor(s, 16, 64);
+        s += __shfl_xor(s, 32, 64);
+        sc[j] = s;
+      }
+      if (kQW == 2) {
+        if (l < 16)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) psum[wv][16 * j + l] = sc[j];
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < 4; ++j) sc[j] += psum[wv ^ 1][16 * j + li];
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) sc[j] = sc[j] > 0.f ? 1.f / sqrtf(sc[j]) : 1.f;
+    } else {
+      __syncthreads();  // every wave is done reading Xs
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+          ssq[(16 * wv + 4 * kg + v) * 64 + 16 * j + li] =
+              t1[j][v] * t1[j][v] + t2[j][v] * t2[j][v];
+      __syncthreads();
+      for (int e = threadIdx.x; e < G * 64; e += 256) {
+        const int g = e >> 6, c = e & 63;
+        float s = 0.f;
+        for (int q = 0; q < Q; ++q) s += ssq[(g * Q + q) * 64 + c];
+        inv[e] = s > 0.f ? 1.f / sqrtf(s) : 1.f;
+      }
+      __syncthreads();
+    }
     const long long r0 = tile * G;
 #pragma unroll
     for (int j = 0; j < 4; ++j)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int r = 16 * wv + 4 * (l >> 4) + v, c = 16 * j + (l & 15);
+        const int r = 16 * wv + 4 * kg + v, c = 16 * j + li;
         const int g = r / Q, q = r - g * Q;
         if (r < G * Q && r0 + g < rows && o0 + c < nout)
           out[(size_t(q) * rows + r0 + g) * nout + o0 + c] =
-              cscale(mm_result<true>(t1[j], t2[j], t3[j], v), inv[g * 64 + c]);
+              cscale(make_float2(t1[j][v], t2[j][v]), kQW > 0 ? sc[j] : inv[g * 64 + c]);
       }
   }
 }
@@ -451,8 +532,15 @@ pisco_status_t interp_x_rss(Handle* h, const float2* in, float2* out, const floa
   const long long tiles = (rows + 64 / Q - 1) / (64 / Q);
   const long long blocks = 1LL * ceil_div(nout, 64) * ceil_div(tiles, kMmTiles);
   if (blocks >= (1LL << 24)) return PISCO_ERR_UNSUPPORTED;
-  PISCO_KERNEL(h, k_interp_x_rss, dim3(unsigned(blocks)), dim3(256), 0, in, out, M, Q, rows, nin,
-               nout);
+  if (Q == 16)
+    PISCO_KERNEL(h, k_interp_x_rss<1>, dim3(unsigned(blocks)), dim3(256), 0, in, out, M, Q, rows,
+                 nin, nout);
+  else if (Q == 32)
+    PISCO_KERNEL(h, k_interp_x_rss<2>, dim3(unsigned(blocks)), dim3(256), 0, in, out, M, Q, rows,
+                 nin, nout);
+  else
+    PISCO_KERNEL(h, k_interp_x_rss<0>, dim3(unsigned(blocks)), dim3(256), 0, in, out, M, Q, rows,
+                 nin, nout);
   return PISCO_OK;
 }
 
