@@ -72,6 +72,33 @@ def test_gram(name):
     assert est.status() == 0
 
 
+@pytest.mark.parametrize("acs_n", [40, 64])
+def test_gram_fft_lengths(acs_n):
+    """The correlation's inverse passes at F = 64 (column blocks, pairs split
+    over workgroups) and F = 128 (the line-per-pair passes that take F above
+    64): ACS 40 and 64 with radius 3 give F = next_pow2(A + 6) = 64 and 128.
+    Random channels (the Gram is defined for any data), oracle Gram from the
+    correlation lags."""
+    import paper_2302_13431_amd as P
+    from oracle import calib, support
+    Q, radius = 8, 3.0
+    rng = np.random.default_rng(1000 + acs_n)
+    acs = (rng.standard_normal((Q, acs_n, acs_n))
+           + 1j * rng.standard_normal((Q, acs_n, acs_n))).astype(np.complex64)
+    lam = support.kernel_support(2, radius, "ellipsoid")
+    lags = support.difference_set(lam)
+    ref = calib.gram_from_lags(calib.correlation_lags(acs.astype(np.complex128), lags), lam,
+                               lags)
+    est = P.Estimator(Q, (acs_n, acs_n), radius, (32, 32), (64, 64), block=64)
+    g = est.gram(cuda(acs)).cpu().numpy().astype(np.complex128)
+    e_max = float(np.abs(g - ref).max() / np.abs(ref).max())
+    e_fro = float(np.linalg.norm(g - ref) / np.linalg.norm(ref))
+    report(f"gram fft lengths acs={acs_n}", err_max=e_max, err_fro=e_fro)
+    assert np.array_equal(g, g.conj().T)
+    assert e_max <= 1e-5 and e_fro <= 1e-5
+    assert est.status() == 0
+
+
 # ------------------------------------------------------------------ nullspace
 
 
