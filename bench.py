@@ -578,8 +578,8 @@ def main():
         print(json.dumps({"copy_bytes": src.numel(), "copies": 5}))
         return
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (asked for {args.gpus}); the path does not run "
-              "across GPUs in this build.", file=sys.stderr)
+        print(f"bench.py measures one GPU only (asked for {args.gpus}): the map estimate runs "
+              "on a single GPU; sharding across GPUs is not implemented.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
