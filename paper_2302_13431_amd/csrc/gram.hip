@@ -266,18 +266,6 @@ __device__ inline float lane_xor(float v, int h, int lane) {
   }
 }
 
-// First inverse pass in column blocks (F <= 64): a workgroup takes C
-// consecutive columns (inner indices) of every channel's spectrum into LDS,
-// laid out [q][c][j] with the F frequencies contiguous, so that each spectrum
-// is read from HBM once, and forms every channel pair's cross-spectrum from
-// there (the line-per-pair form re-reads two channel planes per pair).  A
-// wave transforms 64 / F lines at a time across its lanes: the input in
-// bit-reversed order, then radix-2 steps h = 1, 2, .., F/2 pairing lane j
-// with lane j ^ h: the lower lane forms a + W b, the upper a - W b (a, b the
-// lower and upper values, W = e^{+i pi (j mod h) / h}); lane j then holds
-// output position j (lag j, or j - F past F/2), and the lanes at the B kept
-// lags store.  A wave takes every nw-th pair of the workgroup's pair range
-// (gridDim.y ranges) and its C columns in turn.
 // Lane-parallel inverse transform of kIlp lines per lane (F <= 64, 64 / F
 // lines per wave, lane = sub-line * F + jl): x holds the input at position
 // bit-reverse(jl) and on return output position jl; tw[s] is the lane's
@@ -313,6 +301,18 @@ __device__ inline void lane_twiddles(float2 (&tw)[6], int F, int jl) {
   }
 }
 
+// First inverse pass in column blocks (F <= 64): a workgroup takes C
+// consecutive columns (inner indices) of every channel's spectrum into LDS,
+// laid out [q][c][j] with the F frequencies contiguous, so that each spectrum
+// is read from HBM once, and forms every channel pair's cross-spectrum from
+// there (the line-per-pair form re-reads two channel planes per pair).  A
+// wave transforms 64 / F lines at a time across its lanes: the input in
+// bit-reversed order, then radix-2 steps h = 1, 2, .., F/2 pairing lane j
+// with lane j ^ h: the lower lane forms a + W b, the upper a - W b (a, b the
+// lower and upper values, W = e^{+i pi (j mod h) / h}); lane j then holds
+// output position j (lag j, or j - F past F/2), and the lanes at the B kept
+// lags store.  A wave takes every nw-th pair of the workgroup's pair range
+// (gridDim.y ranges) and its C columns in turn.
 __global__ void __launch_bounds__(512) k_inv_first_cols(const float2* __restrict__ S,
                                                         float2* __restrict__ out, int Q, int F,
                                                         int logF, int inner, int B, int C) {
