@@ -787,7 +787,7 @@ pisco_status_t run_heev(Handle* h, const double2* H, int b, double2* U, double* 
     PISCO_KERNEL(h, k_hetrd_sym, dim3(ceil_div(bb, 256)), dim3(256), 0, H, b, gwork);
     for (int k = 0; k < b; ++k) {
       const int m = b - 1 - k;
-      const unsigned g = m > 1 ? unsigned((m + 1) / 2) : 1u;
+      const unsigned g = m > 1 ? unsigned(m) : 1u;
       const double2* rd = k == 0 ? gwork : ((k - 1) & 1 ? gwork2 : gwork);
       double2* wr = (k & 1) ? gwork2 : gwork;
       // x_{k-1} is read by every workgroup while x_k is written: two vectors
