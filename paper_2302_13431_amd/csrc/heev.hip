@@ -796,6 +796,9 @@ pisco_status_t run_heev(Handle* h, const double2* H, int b, double2* U, double* 
       if (b <= 256)
         PISCO_KERNEL(h, k_hetrd_step<4>, dim3(g), dim3(64), 0, rd, wr, b, k, xin, xout, refl,
                      tau, d, e);
+      else if (b <= 384)
+        PISCO_KERNEL(h, k_hetrd_step<6>, dim3(g), dim3(64), 0, rd, wr, b, k, xin, xout, refl,
+                     tau, d, e);
       else if (b <= 512)
         PISCO_KERNEL(h, k_hetrd_step<8>, dim3(g), dim3(64), 0, rd, wr, b, k, xin, xout, refl,
                      tau, d, e);
