@@ -1112,6 +1112,8 @@ pisco_status_t chol_inv(NullCtx& c, const double2* S, double shift, double2* M,
     PISCO_KERNEL(c.h, (k_tri_inv<2, true>), tg, tb, 0, c.w.R, c.w.dsc, M, b, skip);
   else if (b <= 256)
     PISCO_KERNEL(c.h, (k_tri_inv<4, false>), tg, tb, 0, c.w.R, c.w.dsc, M, b, skip);
+  else if (b <= 384)
+    PISCO_KERNEL(c.h, (k_tri_inv<6, false>), tg, tb, 0, c.w.R, c.w.dsc, M, b, skip);
   else if (b <= 512)
     PISCO_KERNEL(c.h, (k_tri_inv<8, false>), tg, tb, 0, c.w.R, c.w.dsc, M, b, skip);
   else
